@@ -1,0 +1,234 @@
+/*
+ * flow.h -- C ABI of the MI355X (gfx950) TV-L1 optical-flow library built on the preconditioned
+ * dual solvers of Sun, Tai and Yuan, "Variational Image Motion Estimation by Accelerated Dual
+ * Optimization" (arXiv 2011.10979).
+ *
+ * Problem (Sec. 1, eq:l1:optical:flow and eq:l1:optical:flow:no:w): given two grayscale frames
+ * I0 = I(t) and I1 = I(t+1), find a per-pixel displacement d = (u, v), u along columns (x) and v
+ * along rows (y), with I1(x + d) ~= I0(x), by minimising the isotropic TV-L1 energy
+ *     |grad w|_1 + |grad d|_1 + lambda | grad I^T d + beta w + I_t |_1          (beta >= 0)
+ * (the w / illumination block is present only for beta > 0).  The energy is linearised around the
+ * current flow and solved on its dual by one of the paper's schemes inside a coarse-to-fine
+ * warping pyramid (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *   - Images and flow fields are row-major FP32 planes of H rows by W columns.  `ld` / `ld_*` is the
+ *     row pitch in ELEMENTS (>= W).  Pointers tagged "device" must be device memory of the
+ *     context's GPU (e.g. torch.cuda tensors); nothing is ever copied from host memory unless a
+ *     pointer is tagged "host".
+ *   - Input frames hold intensities in [0, 1]; the solver multiplies them by
+ *     params.intensity_scale (kappa, default 255: the 8-bit scale of the paper's data) before
+ *     forming the data term.
+ *   - Every call returns a flow_status; none throws or aborts.  flow_last_error() gives a
+ *     thread-local message for the last failing call on the calling thread.
+ *   - The caller owns every buffer it passes.  The library never retains a caller pointer after a
+ *     call returns (serving tickets: until the ticket is done), never frees it and never writes
+ *     to an input.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is stream-ordered on it;
+ *     entry points documented as blocking synchronise that stream before returning.
+ */
+#ifndef FLOWMI_FLOW_H
+#define FLOWMI_FLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum flow_status {
+    FLOW_OK = 0,
+    FLOW_E_INVAL = -1,      /* invalid argument (NULL pointer, bad size, parameter out of range) */
+    FLOW_E_NOMEM = -2,      /* request exceeds the context's HBM budget, or device allocation failed */
+    FLOW_E_HIP = -3,        /* a HIP runtime call failed (message in flow_last_error) */
+    FLOW_E_NONFINITE = -4,  /* energy or gap is not finite (outputs are still written) */
+    FLOW_E_BUSY = -5,       /* serving queue full / context busy */
+    FLOW_E_NOTFOUND = -6    /* unknown ticket */
+} flow_status;
+
+/* Solver scheme (Sec. 3.1).
+ *   FLOW_PADMM   rpADMMI (tag rpADMMI): dual steps with the proximal weights a c I - c grad grad^* and
+ *                a~ c I - c M_s, multipliers relaxed by r = relax in (0, (1+sqrt 5)/2); relax = 1 is
+ *                pADMM; beta = 0 with relax = 1 is Zach-pADMM (tag Zach-pADMM).
+ *   FLOW_RPADMM2 rpADMMII (tag rpADMMII): relaxation rho = relax in (0, 2) of [SUN].
+ *   FLOW_PDR     preconditioned Douglas-Rachford on the saddle-point form (tag pDR) with
+ *                gs_sweeps symmetric red-black Gauss-Seidel sweeps as the preconditioner. */
+typedef enum flow_scheme { FLOW_PADMM = 0, FLOW_RPADMM2 = 1, FLOW_PDR = 2 } flow_scheme;
+
+/* Storage of the image / derivative pyramids: FP32, or FP16 with FP32 arithmetic. */
+typedef enum flow_storage { FLOW_STORE_F32 = 0, FLOW_STORE_F16 = 1 } flow_storage;
+
+typedef struct flow_params {
+    uint32_t struct_size;     /* sizeof(flow_params); set by flow_params_default */
+    int32_t scheme;           /* flow_scheme, default FLOW_PADMM */
+    double lambda;            /* data weight > 0, default 0.05 */
+    double beta;              /* illumination weight >= 0, default 0 (no w block) */
+    double c;                 /* ADMM step > 0, default 0.05 (Sec. 4) */
+    double relax;             /* r (PADMM) in (0, 1.618...) or rho (RPADMM2) in (0, 2); default 1 */
+    double sigma, tau;        /* pDR steps > 0, defaults 2 and 0.4 (Sec. 4) */
+    int32_t gs_sweeps;        /* pDR symmetric sweeps >= 1, default 1 */
+    double intensity_scale;   /* kappa > 0, default 255 */
+    int32_t levels;           /* pyramid levels >= 1 (factor 1/2, ceil sizes); default 5 */
+    int32_t warps;            /* re-linearisations per level >= 1; default 5 */
+    int32_t iters;            /* inner iterations per warp >= 0; default 50 */
+    int32_t storage;          /* flow_storage, default FLOW_STORE_F32 */
+    int32_t use_graph;        /* 1: capture the whole solve in a hipGraph once per shape and replay */
+    double tol;               /* > 0: stop a warp's iterations once |gap| / energy <= tol (checked
+                                 every check_every iterations; disables graph replay); 0: fixed count */
+    int32_t check_every;      /* >= 1 when tol > 0 */
+} flow_params;
+
+/* FP64 scalars of the last warp of the finest level (linearised energy of that warp):
+ *   energy   = sum |grad d| (+ sum |grad w|) + lambda sum |rho|     (eq:l1:finite / eq:l1:finite:no:w)
+ *   dual     = sum I_t s                                             (eq:dual:l1:flow:cons)
+ *   gap      = energy - dual
+ *   residual = |A s + B y|_2, the violation of eq:dual:l1:flow:constaint
+ *   tv, data = the two parts of energy.
+ * For pDR the dual pair is (q, s) = (P(y_bar + 2 tau grad X), Theta) of the last iteration. */
+typedef struct flow_result {
+    double energy, dual, gap, residual, tv, data;
+} flow_result;
+
+/* Per-solve timing, filled when the context's stats are enabled (flow_set_stats).  Times come
+ * from hipEvents recorded around each level's block of iteration kernels on the solve stream. */
+#define FLOW_MAX_LEVELS 16
+typedef struct flow_stats {
+    int32_t levels;
+    int32_t H[FLOW_MAX_LEVELS], W[FLOW_MAX_LEVELS];
+    int64_t iter_launches[FLOW_MAX_LEVELS];   /* iteration kernel launches at this level */
+    double iter_ms[FLOW_MAX_LEVELS];          /* event time of those launches (includes gaps) */
+    double total_ms;                          /* event time of the whole solve on the device */
+    int64_t px_iter;                          /* pixel-iterations of the solve */
+    int32_t graph_replayed;                   /* 1 if the solve ran as a graph replay */
+} flow_stats;
+
+typedef struct flow_ctx flow_ctx;
+
+/* Fill *p with the defaults listed above.  FLOW_E_INVAL if p is NULL. */
+flow_status flow_params_default(flow_params* p);
+
+/* Create a context on HIP device `device` whose device allocations never exceed
+ * hbm_budget_bytes (0 = no limit).  *out receives the context.  FLOW_E_INVAL on a bad device,
+ * FLOW_E_HIP on a runtime error. */
+flow_status flow_create(flow_ctx** out, int device, size_t hbm_budget_bytes);
+
+/* Release the context and all its device memory, graphs and streams (NULL is a no-op). */
+flow_status flow_destroy(flow_ctx* ctx);
+
+/* Plain solve of one pair (the whole coarse-to-fine pipeline of Sec. 4).
+ *   I0, I1   device, H x W, pitch ld (elements), intensities in [0, 1]
+ *   u, v     device outputs, H x W, pitch ld_uv: the flow in pixels of the finest level
+ *   res      host, may be NULL: energy / dual / gap of the final warp
+ *   stream   hipStream_t; the call is stream-ordered and blocks until the results are written
+ * Errors: FLOW_E_INVAL for NULL device pointers, H or W < 2, ld or ld_uv < W, levels < 1,
+ * warps < 1, iters < 0, lambda <= 0, beta < 0, c <= 0, relax outside the Prop. 3.1 range of the
+ * scheme, sigma or tau <= 0, gs_sweeps < 1, intensity_scale <= 0, tol < 0, or a coarsest level
+ * with a side < 2; FLOW_E_NOMEM if the pair's working set exceeds the budget; FLOW_E_NONFINITE
+ * if energy or gap is not finite. */
+flow_status flow_solve(flow_ctx* ctx, const float* I0, const float* I1, int32_t H, int32_t W, int64_t ld,
+                       const flow_params* p, float* u, float* v, int64_t ld_uv, flow_result* res,
+                       void* stream);
+
+/* One pair of a batch: device frames and outputs as in flow_solve, res is host (may be NULL). */
+typedef struct flow_pair {
+    const float* I0;
+    const float* I1;
+    int32_t H, W;
+    int64_t ld;
+    float* u;
+    float* v;
+    int64_t ld_uv;
+    flow_result* res;
+} flow_pair;
+
+/* Solve n pairs of uneven sizes together: every iteration step advances all pairs that are at
+ * that step with one launch of a persistent kernel that pulls (pair, tile) items from a work
+ * queue (Sec. 4 pipeline per pair; levels per pair = params.levels, reduced where a pair is too
+ * small).  Results equal n plain solves bitwise.  Blocks until all results are written. */
+flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                               void* stream);
+
+/* Enable (1) or disable (0) per-solve event timing; flow_get_stats returns the last solve's. */
+flow_status flow_set_stats(flow_ctx* ctx, int32_t enable);
+flow_status flow_get_stats(const flow_ctx* ctx, flow_stats* out);
+
+/* Bytes of device memory the context currently holds. */
+flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
+
+/* Process-wide kernel tuning knobs (set by the autotuner; 0 restores the built-in heuristic):
+ *   "admm_rows"   rows per wavefront strip of the fused ADMM iteration kernel: 2, 4 or 8.
+ * FLOW_E_INVAL for an unknown key or value.  Not thread-safe against concurrent solves. */
+flow_status flow_tune_set(const char* key, int64_t value);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* flow_last_error(void);
+
+/* ------------------------------------------------------------------------------------------------
+ * Operator-level entry points: one step of the pipeline on caller-provided device planes, for
+ * testing each stage in isolation.  All planes of one call share H, W and the pitch ld.  They are
+ * stream-ordered and do not synchronise; errors are reported before any launch.
+ * ----------------------------------------------------------------------------------------------*/
+
+/* Next pyramid level: dst (ceil(H/2) x ceil(W/2), pitch ldd) = mean of 2x2 blocks of src with
+ * rows / columns past the edge replicated. */
+flow_status flow_op_downsample(const float* src, int32_t H, int32_t W, int64_t ld, float* dst, int64_t ldd,
+                               void* stream);
+
+/* Central differences of I with replicated neighbours: Dx = (I[j+1] - I[j-1]) / 2, Dy likewise. */
+flow_status flow_op_derivatives(const float* I, int32_t H, int32_t W, int64_t ld, float* Dx, float* Dy,
+                                void* stream);
+
+/* Warp and linearise (Sec. 1: rho(d) = grad I^T d + I_t) around (u0, v0):
+ *   I_x = kappa B(DxI1)(x + d0), I_y = kappa B(DyI1)(x + d0),
+ *   I_t = kappa (B(I1)(x + d0) - I0) - I_x u0 - I_y v0,
+ * with B bilinear sampling at clamped coordinates, and at_out (device, one float) receives
+ * a~ = max(max_ij(beta^2 + I_x^2 + I_y^2), 1e-12) (Prop. 3.1). */
+flow_status flow_op_linearize(const float* I0, const float* I1, const float* DxI1, const float* DyI1,
+                              const float* u0, const float* v0, int32_t H, int32_t W, int64_t ld,
+                              double kappa, double beta, float* Ix, float* Iy, float* It, float* at_out,
+                              void* stream);
+
+/* fine (Hf x Wf, pitch ldf) = scale * B(coarse)(i/2 - 1/4, j/2 - 1/4); the coarse plane is
+ * ceil(Hf/2) x ceil(Wf/2) with pitch ldc.  Flow components use scale 2, illumination scale 1. */
+flow_status flow_op_upsample(const float* coarse, int64_t ldc, float* fine, int32_t Hf, int32_t Wf, int64_t ldf,
+                             double scale, void* stream);
+
+/* State planes of the ADMM family (device, H x W, pitch ld).  w, px, py are only read / written
+ * when beta > 0 (they may be NULL otherwise).  u0, v0 (read only, may be NULL) select the
+ * increment form the solver uses: the multipliers are u0 + u, v0 + v, and I_t passed with them is
+ * relative to (u0, v0), i.e. kappa (I1(x + d0) - I0); with u0 = v0 = NULL, u and v are the flow
+ * and I_t is absolute.  flow_op_energy ignores u0, v0. */
+typedef struct flow_admm_state {
+    float *w, *u, *v, *px, *py, *q1x, *q1y, *q2x, *q2y, *s;
+    const float *u0, *v0;
+} flow_admm_state;
+
+/* One iteration of the scheme in p->scheme (FLOW_PADMM or FLOW_RPADMM2) from `in` to `out`
+ * (distinct planes).  Ix, Iy, It are the linearisation and at (device, one float) is a~. */
+flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* out, const float* Ix,
+                              const float* Iy, const float* It, const float* at, int32_t H, int32_t W,
+                              int64_t ld, const flow_params* p, void* stream);
+
+/* State planes of pDR: X = (w, u, v), X bar = (wb, ub, vb), y bar = (pbx, pby, qb1x, qb1y, qb2x,
+ * qb2y); w, wb, pbx, pby only when beta > 0.  Updated in place.  work: 3 scratch planes (device,
+ * same shape and pitch).  s_out (may be NULL) receives Theta, the data dual of the resolvent. */
+typedef struct flow_pdr_state {
+    float *w, *u, *v, *wb, *ub, *vb, *pbx, *pby, *qb1x, *qb1y, *qb2x, *qb2y;
+} flow_pdr_state;
+
+/* One pDR iteration in place (Sec. 3.1.2, eq:resolvent, eq. neumann:boudary). */
+flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work1, float* work2,
+                             float* s_out, const float* Ix, const float* Iy, const float* It, int32_t H,
+                             int32_t W, int64_t ld, const flow_params* p, void* stream);
+
+/* FP64 energy / dual / gap / residual of an ADMM-family state (see flow_result), blocking:
+ * res is host memory and the stream is synchronised. */
+flow_status flow_op_energy(const flow_admm_state* st, const float* Ix, const float* Iy, const float* It,
+                           int32_t H, int32_t W, int64_t ld, double lambda, double beta, flow_result* res,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLOWMI_FLOW_H */

@@ -1,0 +1,658 @@
+// Host runtime behind the C ABI of include/flow.h: parameter checks, the device arena of one
+// solve, the coarse-to-fine launch sequence (Sec. 4), hipGraph capture / replay of that sequence,
+// and the operator-level entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/flow.h"
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace flowmi {
+
+thread_local std::string g_last_error;
+
+flow_status fail(flow_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+flow_status hip_fail(hipError_t e, const char* what) {
+    return fail(FLOW_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+    } while (0)
+
+int64_t pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
+
+// A caller plane of H rows, W used columns and pitch ld elements must lie inside the device
+// allocation that contains its first element; a plane that runs past it would make the kernels
+// write outside the caller's memory, so it is rejected before anything is launched.
+flow_status check_extent(const void* ptr, int H, int W, int64_t ld, size_t elem, const char* name) {
+    if (!ptr) return fail(FLOW_E_INVAL, std::string(name) + " is NULL");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        return fail(FLOW_E_INVAL, std::string(name) + " is not device memory of this GPU");
+    }
+    const uintptr_t lo = (uintptr_t)ptr, b = (uintptr_t)base;
+    const uintptr_t need = lo + ((size_t)(H - 1) * (size_t)ld + (size_t)W) * elem;
+    if (lo < b || need > b + size)
+        return fail(FLOW_E_INVAL, std::string(name) + ": H x W plane with this pitch runs past its allocation");
+    return FLOW_OK;
+}
+
+std::vector<std::pair<int, int>> level_shapes(int H, int W, int levels) {
+    std::vector<std::pair<int, int>> s;
+    s.emplace_back(H, W);
+    for (int l = 1; l < levels; ++l) s.emplace_back((s.back().first + 1) / 2, (s.back().second + 1) / 2);
+    return s;
+}
+
+flow_status validate(const flow_params* p) {
+    if (!p) return fail(FLOW_E_INVAL, "params is NULL");
+    if (p->struct_size != sizeof(flow_params)) return fail(FLOW_E_INVAL, "params.struct_size mismatch");
+    if (p->scheme < FLOW_PADMM || p->scheme > FLOW_PDR) return fail(FLOW_E_INVAL, "unknown scheme");
+    if (!(p->lambda > 0)) return fail(FLOW_E_INVAL, "lambda must be > 0");
+    if (!(p->beta >= 0)) return fail(FLOW_E_INVAL, "beta must be >= 0");
+    if (!(p->c > 0)) return fail(FLOW_E_INVAL, "c must be > 0");
+    if (p->scheme == FLOW_PADMM && !(p->relax > 0 && p->relax < (1.0 + std::sqrt(5.0)) / 2.0))
+        return fail(FLOW_E_INVAL, "rpADMMI relaxation r must lie in (0, (1+sqrt 5)/2)");
+    if (p->scheme == FLOW_RPADMM2 && !(p->relax > 0 && p->relax < 2.0))
+        return fail(FLOW_E_INVAL, "rpADMMII relaxation rho must lie in (0, 2)");
+    if (!(p->sigma > 0) || !(p->tau > 0)) return fail(FLOW_E_INVAL, "sigma and tau must be > 0");
+    if (p->gs_sweeps < 1) return fail(FLOW_E_INVAL, "gs_sweeps must be >= 1");
+    if (!(p->intensity_scale > 0)) return fail(FLOW_E_INVAL, "intensity_scale must be > 0");
+    if (p->levels < 1 || p->levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "levels out of range");
+    if (p->warps < 1) return fail(FLOW_E_INVAL, "warps must be >= 1");
+    if (p->iters < 0) return fail(FLOW_E_INVAL, "iters must be >= 0");
+    if (p->storage != FLOW_STORE_F32 && p->storage != FLOW_STORE_F16) return fail(FLOW_E_INVAL, "bad storage");
+    if (!(p->tol >= 0)) return fail(FLOW_E_INVAL, "tol must be >= 0");
+    if (p->tol > 0 && p->check_every < 1) return fail(FLOW_E_INVAL, "check_every must be >= 1");
+    return FLOW_OK;
+}
+
+flow_status validate_shape(int H, int W, int64_t ld, int levels) {
+    if (H < 2 || W < 2) return fail(FLOW_E_INVAL, "H and W must be >= 2");
+    if (ld < W) return fail(FLOW_E_INVAL, "pitch smaller than W");
+    auto s = level_shapes(H, W, levels).back();
+    if (s.first < 2 || s.second < 2) return fail(FLOW_E_INVAL, "coarsest level has a side < 2");
+    return FLOW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Layout of one pair's working set: pyramid, linearisation and scheme state per level.
+// ---------------------------------------------------------------------------------------------
+size_t layout_bytes(int H, int W, const flow_params& p) {
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    const bool pdr = p.scheme == FLOW_PDR;
+    const bool hw = p.beta > 0;
+    size_t total = 0;
+    for (auto [h, w] : level_shapes(H, W, p.levels)) {
+        const size_t plane = (size_t)h * pitch_of(w) * 4;
+        const size_t pyr = (size_t)h * pitch_of(w) * (f16 ? 2 : 4);
+        total += 4 * pyr + 5 * plane;   // pyramid, linearisation, linearisation point
+        if (pdr) total += (size_t)(hw ? 3 + 3 + 6 + 3 + 1 : 2 + 2 + 4 + 2 + 1) * plane;
+        else total += (size_t)2 * (hw ? 10 : 7) * plane;
+        total += 48 * 256;  // alignment slack: every plane starts on a 256-byte boundary
+    }
+    return total;
+}
+
+flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, std::vector<LevelPlanes>& out) {
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    const bool pdr = p.scheme == FLOW_PDR;
+    const bool hw = p.beta > 0;
+    out.clear();
+    char* cur = (char*)arena.base;
+    char* end = cur + arena.bytes;
+    bool short_of_space = false;
+    auto take = [&](size_t n) -> void* {
+        char* q = (char*)(((uintptr_t)cur + 255) & ~(uintptr_t)255);
+        if (q + n > end) {
+            short_of_space = true;
+            return nullptr;
+        }
+        cur = q + n;
+        return q;
+    };
+    for (auto [h, w] : level_shapes(H, W, p.levels)) {
+        LevelPlanes L{};
+        L.H = h;
+        L.W = w;
+        L.ld = pitch_of(w);
+        const size_t plane = (size_t)h * L.ld * 4;
+        const size_t pyr = (size_t)h * L.ld * (f16 ? 2 : 4);
+        L.I0 = take(pyr);
+        L.I1 = take(pyr);
+        L.Dx = take(pyr);
+        L.Dy = take(pyr);
+        L.Ix = (float*)take(plane);
+        L.Iy = (float*)take(plane);
+        L.It = (float*)take(plane);
+        L.U0[0] = (float*)take(plane);
+        L.U0[1] = (float*)take(plane);
+        if (!pdr) {
+            for (int b = 0; b < 2; ++b)
+                for (int k = 0; k < 10; ++k) {
+                    const bool wk = k == 0 || k == 3 || k == 4;   // w, px, py
+                    L.st[b][k] = (!wk || hw) ? (float*)take(plane) : nullptr;
+                }
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                const bool need = k > 0 || hw;
+                L.X[k] = need ? (float*)take(plane) : nullptr;
+                L.Xb[k] = need ? (float*)take(plane) : nullptr;
+                L.b[k] = need ? (float*)take(plane) : nullptr;
+            }
+            for (int k = 0; k < 6; ++k) L.yb[k] = (k >= 2 || hw) ? (float*)take(plane) : nullptr;
+            L.s_out = (float*)take(plane);
+        }
+        if (short_of_space) return fail(FLOW_E_NOMEM, "arena too small for layout");
+        out.push_back(L);
+    }
+    return FLOW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launch sequence
+// ---------------------------------------------------------------------------------------------
+AdmmIterArgs admm_args(const LevelPlanes& L, int from, const flow_params& p, const float* at) {
+    AdmmIterArgs a{};
+    const float* const* in = L.st[from];
+    float* const* out = L.st[from ^ 1];
+    a.w = in[0]; a.u = in[1]; a.v = in[2]; a.px = in[3]; a.py = in[4];
+    a.q1x = in[5]; a.q1y = in[6]; a.q2x = in[7]; a.q2y = in[8]; a.s = in[9];
+    a.wo = out[0]; a.uo = out[1]; a.vo = out[2]; a.pxo = out[3]; a.pyo = out[4];
+    a.q1xo = out[5]; a.q1yo = out[6]; a.q2xo = out[7]; a.q2yo = out[8]; a.so = out[9];
+    a.Ix = L.Ix; a.Iy = L.Iy; a.It = L.It; a.at = at;
+    a.u0 = L.U0[0]; a.v0 = L.U0[1];
+    a.H = L.H; a.W = L.W; a.ld = L.ld;
+    fill_admm_coeffs(a, p);
+    return a;
+}
+
+void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p) {
+    const double c = p.c;
+    a.c = (float)c;
+    a.lam = (float)p.lambda;
+    a.beta = (float)p.beta;
+    a.inv_ac = (float)(1.0 / (8.0 * c));
+    if (p.scheme == FLOW_RPADMM2) {
+        a.c_rho_s = (float)(c * p.relax);
+        a.cA = (float)(c * p.relax);
+        a.cB = (float)c;
+        a.cC = (float)(c * (1.0 - p.relax));
+    } else {
+        a.c_rho_s = (float)c;
+        a.cA = (float)(c * p.relax);
+        a.cB = (float)(c * p.relax);
+        a.cC = 0.f;
+    }
+}
+
+PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p) {
+    PdrArgs a{};
+    a.w = L.X[0]; a.u = L.X[1]; a.v = L.X[2];
+    a.wb = L.Xb[0]; a.ub = L.Xb[1]; a.vb = L.Xb[2];
+    a.pbx = L.yb[0]; a.pby = L.yb[1]; a.qb1x = L.yb[2]; a.qb1y = L.yb[3]; a.qb2x = L.yb[4]; a.qb2y = L.yb[5];
+    a.bw = L.b[0]; a.bu = L.b[1]; a.bv = L.b[2];
+    a.s_out = L.s_out;
+    a.Ix = L.Ix; a.Iy = L.Iy; a.It = L.It;
+    a.u0 = L.U0[0]; a.v0 = L.U0[1];
+    a.H = L.H; a.W = L.W; a.ld = L.ld;
+    a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    a.lam = (float)p.lambda; a.beta = (float)p.beta;
+    return a;
+}
+
+void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s) {
+    launch_pdr_rhs_red(a, hw, s);
+    PdrArgs c = a;
+    for (int k = 0; k < sweeps; ++k) {
+        c.colour = 1;
+        launch_pdr_colour(c, hw, s);                 // black
+        if (k < sweeps - 1) {
+            c.colour = 0;
+            launch_pdr_colour(c, hw, s);             // red (the last red is fused into the final pass)
+        }
+    }
+    launch_pdr_final(a, hw, s);
+}
+
+// Final ADMM state index of a level after `n` iterations starting from buffer 0.
+int admm_final_buf(int64_t n) { return (int)(n & 1); }
+
+// Flow component k (0 = w, 1 = u, 2 = v) of a level after its warps: pDR keeps X; the ADMM family
+// keeps the committed flow in U0 and w in its state.
+const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int64_t iters_done) {
+    if (p.scheme == FLOW_PDR) return L.X[k];
+    if (k > 0) return L.U0[k - 1];
+    return L.st[admm_final_buf(iters_done)][0];
+}
+
+EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int64_t iters_done, Scratch& sc) {
+    EnergyArgs e{};
+    if (p.scheme == FLOW_PDR) {
+        e.w = L.X[0]; e.u = L.X[1]; e.v = L.X[2];
+        e.px = L.yb[0]; e.py = L.yb[1]; e.q1x = L.yb[2]; e.q1y = L.yb[3]; e.q2x = L.yb[4]; e.q2y = L.yb[5];
+        e.s = L.s_out;
+        e.pdr_tau = (float)p.tau;
+        e.lu0 = L.U0[0]; e.lv0 = L.U0[1];
+    } else {
+        // before the warp's commit: flow = U0 + increment
+        float* const* st = L.st[admm_final_buf(iters_done)];
+        e.w = st[0]; e.u = L.U0[0]; e.v = L.U0[1]; e.du = st[1]; e.dv = st[2];
+        e.px = st[3]; e.py = st[4]; e.q1x = st[5]; e.q1y = st[6]; e.q2x = st[7]; e.q2y = st[8]; e.s = st[9];
+        e.pdr_tau = 0.f;
+    }
+    e.Ix = L.Ix; e.Iy = L.Iy; e.It = L.It;
+    e.H = L.H; e.W = L.W; e.ld = L.ld;
+    e.lam = (float)p.lambda; e.beta = (float)p.beta;
+    e.partial = sc.e_partial; e.counter = sc.e_counter; e.out = sc.e_out;
+    return e;
+}
+
+// Everything after the level-0 frames are in the pyramid: pyramid, levels, warps, iterations,
+// final energy.  `timers` (may be null) receives events around each warp's iteration block.
+flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
+                         WarpTimers* timers, StopTest* stop) {
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    const bool pdr = p.scheme == FLOW_PDR;
+    const bool hw = p.beta > 0;
+    const int nl = (int)Ls.size();
+    for (int l = 0; l < nl; ++l) {
+        LevelPlanes& L = Ls[l];
+        if (l > 0) {
+            const LevelPlanes& F = Ls[l - 1];
+            launch_downsample(F.I0, F.H, F.W, F.ld, L.I0, L.ld, f16, s);
+            launch_downsample(F.I1, F.H, F.W, F.ld, L.I1, L.ld, f16, s);
+        }
+        launch_derivatives(L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, f16, s);
+    }
+    int64_t done_coarse = 0;
+    for (int l = nl - 1; l >= 0; --l) {
+        LevelPlanes& L = Ls[l];
+        // level start: upsample flow from level l+1 (or zero), clear duals
+        LevelInitArgs ia{};
+        ia.H = L.H; ia.W = L.W; ia.ld = L.ld;
+        if (l < nl - 1) {
+            const LevelPlanes& C = Ls[l + 1];
+            ia.uc = level_flow(C, p, 1, done_coarse);
+            ia.vc = level_flow(C, p, 2, done_coarse);
+            ia.wc = hw ? level_flow(C, p, 0, done_coarse) : nullptr;
+            ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
+        }
+        if (!pdr) {
+            ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
+            ia.set_flow[1] = L.U0[0];
+            ia.set_flow[2] = L.U0[1];
+            int nz = 0;
+            for (int k = 3; k < 10; ++k)
+                if (L.st[0][k]) ia.zero[nz++] = L.st[0][k];
+            ia.nzero = nz;
+        } else {
+            ia.set_flow[0] = hw ? L.X[0] : nullptr;
+            ia.set_flow[1] = L.X[1];
+            ia.set_flow[2] = L.X[2];
+            ia.copy_flow[0] = hw ? L.Xb[0] : nullptr;
+            ia.copy_flow[1] = L.Xb[1];
+            ia.copy_flow[2] = L.Xb[2];
+            int nz = 0;
+            for (int k = 0; k < 6; ++k)
+                if (L.yb[k]) ia.zero[nz++] = L.yb[k];
+            ia.zero[nz++] = L.s_out;
+            ia.nzero = nz;
+        }
+        launch_level_init(ia, s);
+
+        int64_t done = 0;
+        for (int wp = 0; wp < p.warps; ++wp) {
+            // warp start: linearise around the current flow with I_t relative to it; the ADMM
+            // increment (du, dv) restarts at zero, pDR keeps a copy of the linearisation point
+            LinArgs la{};
+            la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+            la.u0 = level_flow(L, p, 1, done);
+            la.v0 = level_flow(L, p, 2, done);
+            la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
+            la.at = sc.at; la.partial = sc.lin_partial; la.counter = sc.lin_counter;
+            la.H = L.H; la.W = L.W; la.ld = L.ld;
+            la.kappa = (float)p.intensity_scale; la.beta = (float)p.beta;
+            la.rel = 1;
+            if (!pdr) {
+                la.zero_u = L.st[admm_final_buf(done)][1];
+                la.zero_v = L.st[admm_final_buf(done)][2];
+            } else {
+                la.keep_u = L.U0[0];
+                la.keep_v = L.U0[1];
+            }
+            launch_linearize(la, f16, s);
+            if (timers) timers->begin(l, s);
+            int64_t k = 0;
+            while (k < p.iters) {
+                int64_t chunk = p.iters - k;
+                if (stop && p.tol > 0) chunk = std::min<int64_t>(chunk, p.check_every);
+                for (int64_t t = 0; t < chunk; ++t) {
+                    if (!pdr) launch_admm_iter(admm_args(L, admm_final_buf(done), p, sc.at), hw, s);
+                    else enqueue_pdr_iter(pdr_args(L, p), p.gs_sweeps, hw, s);
+                    ++done;
+                }
+                k += chunk;
+                if (timers) timers->count(l, chunk);
+                if (stop && p.tol > 0 && k < p.iters) {
+                    launch_energy(energy_args(L, p, done, sc), s);
+                    bool converged = false;
+                    flow_status st = stop->check(sc, s, &converged);
+                    if (st != FLOW_OK) return st;
+                    if (converged) break;
+                }
+            }
+            if (timers) timers->end(l, s);
+            const bool last = l == 0 && wp == p.warps - 1;
+            if (last) launch_energy(energy_args(L, p, done, sc), s);
+            if (!pdr) {
+                const int f = admm_final_buf(done);
+                launch_commit(L.U0[0], L.U0[1], L.st[f][1], L.st[f][2], L.H, L.W, L.ld, s);
+            }
+        }
+        done_coarse = done;
+        if (l == 0) sc.final_iters = done;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return FLOW_OK;
+}
+
+}  // namespace flowmi
+
+using namespace flowmi;
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+flow_status flow_params_default(flow_params* p) {
+    if (!p) return fail(FLOW_E_INVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(flow_params);
+    p->scheme = FLOW_PADMM;
+    p->lambda = 0.05;
+    p->beta = 0.0;
+    p->c = 0.05;
+    p->relax = 1.0;
+    p->sigma = 2.0;
+    p->tau = 0.4;
+    p->gs_sweeps = 1;
+    p->intensity_scale = 255.0;
+    p->levels = 5;
+    p->warps = 5;
+    p->iters = 50;
+    p->storage = FLOW_STORE_F32;
+    p->use_graph = 1;
+    p->tol = 0.0;
+    p->check_every = 10;
+    return FLOW_OK;
+}
+
+const char* flow_last_error(void) { return g_last_error.c_str(); }
+
+flow_status flow_tune_set(const char* key, int64_t value) {
+    if (!key) return fail(FLOW_E_INVAL, "key is NULL");
+    if (std::strcmp(key, "admm_rows") == 0) {
+        if (value != 0 && value != 2 && value != 4 && value != 8) return fail(FLOW_E_INVAL, "admm_rows: 0, 2, 4 or 8");
+        g_admm_rows_override = (int)value;
+        return FLOW_OK;
+    }
+    return fail(FLOW_E_INVAL, std::string("unknown tuning key ") + key);
+}
+
+flow_status flow_create(flow_ctx** out, int device, size_t budget) {
+    if (!out) return fail(FLOW_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(FLOW_E_INVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<flow_ctx> c(new flow_ctx());
+    c->device = device;
+    c->budget = budget;
+    flow_status st = c->init_scratch();
+    if (st != FLOW_OK) return st;
+    *out = c.release();
+    return FLOW_OK;
+}
+
+flow_status flow_destroy(flow_ctx* ctx) {
+    if (!ctx) return FLOW_OK;
+    hipSetDevice(ctx->device);
+    delete ctx;
+    return FLOW_OK;
+}
+
+flow_status flow_set_stats(flow_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    ctx->stats_enabled = enable != 0;
+    return FLOW_OK;
+}
+
+flow_status flow_get_stats(const flow_ctx* ctx, flow_stats* out) {
+    if (!ctx || !out) return fail(FLOW_E_INVAL, "NULL argument");
+    *out = ctx->last_stats;
+    return FLOW_OK;
+}
+
+flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return fail(FLOW_E_INVAL, "NULL argument");
+    *bytes = ctx->bytes_in_use();
+    return FLOW_OK;
+}
+
+flow_status flow_solve(flow_ctx* ctx, const float* I0, const float* I1, int32_t H, int32_t W, int64_t ld,
+                       const flow_params* p, float* u, float* v, int64_t ld_uv, flow_result* res, void* stream) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    if (!I0 || !I1 || !u || !v) return fail(FLOW_E_INVAL, "NULL device pointer");
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    st = validate_shape(H, W, ld, p->levels);
+    if (st != FLOW_OK) return st;
+    if (ld_uv < W) return fail(FLOW_E_INVAL, "ld_uv smaller than W");
+    HIP_TRY(hipSetDevice(ctx->device));
+    for (auto [ptr, l, name] : {std::make_tuple((const void*)I0, ld, "I0"), std::make_tuple((const void*)I1, ld, "I1"),
+                                std::make_tuple((const void*)u, ld_uv, "u"), std::make_tuple((const void*)v, ld_uv, "v")}) {
+        st = check_extent(ptr, H, W, l, sizeof(float), name);
+        if (st != FLOW_OK) return st;
+    }
+    return ctx->solve(I0, I1, H, W, ld, *p, u, v, ld_uv, res, (hipStream_t)stream);
+}
+
+// ------------------------------- operator-level entry points ---------------------------------
+#define EXTENT(ptr, h, w, ld, name)                                                   \
+    do {                                                                              \
+        flow_status _s = check_extent((ptr), (h), (w), (ld), sizeof(float), (name));  \
+        if (_s != FLOW_OK) return _s;                                                 \
+    } while (0)
+
+flow_status flow_op_downsample(const float* src, int32_t H, int32_t W, int64_t ld, float* dst, int64_t ldd,
+                               void* stream) {
+    if (!src || !dst) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (H < 1 || W < 1 || ld < W || ldd < (W + 1) / 2) return fail(FLOW_E_INVAL, "bad shape");
+    EXTENT(src, H, W, ld, "src");
+    EXTENT(dst, (H + 1) / 2, (W + 1) / 2, ldd, "dst");
+    launch_downsample(src, H, W, ld, dst, ldd, false, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_derivatives(const float* I, int32_t H, int32_t W, int64_t ld, float* Dx, float* Dy,
+                                void* stream) {
+    if (!I || !Dx || !Dy) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (H < 1 || W < 1 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    EXTENT(I, H, W, ld, "I");
+    EXTENT(Dx, H, W, ld, "Dx");
+    EXTENT(Dy, H, W, ld, "Dy");
+    launch_derivatives(I, H, W, ld, Dx, Dy, ld, false, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_linearize(const float* I0, const float* I1, const float* DxI1, const float* DyI1,
+                              const float* u0, const float* v0, int32_t H, int32_t W, int64_t ld, double kappa,
+                              double beta, float* Ix, float* Iy, float* It, float* at_out, void* stream) {
+    if (!I0 || !I1 || !DxI1 || !DyI1 || !u0 || !v0 || !Ix || !Iy || !It || !at_out)
+        return fail(FLOW_E_INVAL, "NULL pointer");
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    EXTENT(I0, H, W, ld, "I0"); EXTENT(I1, H, W, ld, "I1"); EXTENT(DxI1, H, W, ld, "DxI1");
+    EXTENT(DyI1, H, W, ld, "DyI1"); EXTENT(u0, H, W, ld, "u0"); EXTENT(v0, H, W, ld, "v0");
+    EXTENT(Ix, H, W, ld, "Ix"); EXTENT(Iy, H, W, ld, "Iy"); EXTENT(It, H, W, ld, "It");
+    EXTENT(at_out, 1, 1, 1, "at_out");
+    OpScratch& os = op_scratch();
+    flow_status st = os.ensure_lin(linearize_blocks(H, W));
+    if (st != FLOW_OK) return st;
+    LinArgs a{};
+    a.I0 = I0; a.I1 = I1; a.Dx = DxI1; a.Dy = DyI1; a.u0 = u0; a.v0 = v0;
+    a.Ix = Ix; a.Iy = Iy; a.It = It; a.at = at_out; a.partial = os.lin_partial; a.counter = os.lin_counter;
+    a.H = H; a.W = W; a.ld = ld; a.kappa = (float)kappa; a.beta = (float)beta;
+    launch_linearize(a, false, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_upsample(const float* coarse, int64_t ldc, float* fine, int32_t Hf, int32_t Wf, int64_t ldf,
+                             double scale, void* stream) {
+    if (!coarse || !fine) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (Hf < 3 || Wf < 3 || ldf < Wf || ldc < (Wf + 1) / 2) return fail(FLOW_E_INVAL, "bad shape");
+    EXTENT(coarse, (Hf + 1) / 2, (Wf + 1) / 2, ldc, "coarse");
+    EXTENT(fine, Hf, Wf, ldf, "fine");
+    launch_upsample(coarse, ldc, fine, Hf, Wf, ldf, (float)scale, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* out, const float* Ix,
+                              const float* Iy, const float* It, const float* at, int32_t H, int32_t W, int64_t ld,
+                              const flow_params* p, void* stream) {
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    if (p->scheme == FLOW_PDR) return fail(FLOW_E_INVAL, "flow_op_admm_iter needs an ADMM scheme");
+    if (!in || !out || !Ix || !Iy || !It || !at) return fail(FLOW_E_INVAL, "NULL pointer");
+    const bool hw = p->beta > 0;
+    const float* ins[10] = {in->w, in->u, in->v, in->px, in->py, in->q1x, in->q1y, in->q2x, in->q2y, in->s};
+    float* outs[10] = {out->w, out->u, out->v, out->px, out->py, out->q1x, out->q1y, out->q2x, out->q2y, out->s};
+    for (int k = 0; k < 10; ++k) {
+        const bool wk = k == 0 || k == 3 || k == 4;
+        if ((!wk || hw) && (!ins[k] || !outs[k])) return fail(FLOW_E_INVAL, "NULL state plane");
+        if ((!wk || hw) && ins[k] == outs[k]) return fail(FLOW_E_INVAL, "in and out planes must differ");
+    }
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    for (int k = 0; k < 10; ++k) {
+        const bool wk = k == 0 || k == 3 || k == 4;
+        if (wk && !hw) continue;
+        EXTENT(ins[k], H, W, ld, "state in");
+        EXTENT(outs[k], H, W, ld, "state out");
+    }
+    EXTENT(Ix, H, W, ld, "Ix"); EXTENT(Iy, H, W, ld, "Iy"); EXTENT(It, H, W, ld, "It");
+    EXTENT(at, 1, 1, 1, "at");
+    AdmmIterArgs a{};
+    a.w = ins[0]; a.u = ins[1]; a.v = ins[2]; a.px = ins[3]; a.py = ins[4];
+    a.q1x = ins[5]; a.q1y = ins[6]; a.q2x = ins[7]; a.q2y = ins[8]; a.s = ins[9];
+    a.wo = outs[0]; a.uo = outs[1]; a.vo = outs[2]; a.pxo = outs[3]; a.pyo = outs[4];
+    a.q1xo = outs[5]; a.q1yo = outs[6]; a.q2xo = outs[7]; a.q2yo = outs[8]; a.so = outs[9];
+    a.Ix = Ix; a.Iy = Iy; a.It = It; a.at = at; a.H = H; a.W = W; a.ld = ld;
+    if ((in->u0 == nullptr) != (in->v0 == nullptr)) return fail(FLOW_E_INVAL, "u0 and v0 go together");
+    if (in->u0) {
+        EXTENT(in->u0, H, W, ld, "u0");
+        EXTENT(in->v0, H, W, ld, "v0");
+        a.u0 = in->u0;
+        a.v0 = in->v0;
+    }
+    fill_admm_coeffs(a, *p);
+    launch_admm_iter(a, hw, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work1, float* work2, float* s_out,
+                             const float* Ix, const float* Iy, const float* It, int32_t H, int32_t W, int64_t ld,
+                             const flow_params* p, void* stream) {
+    flow_status v = validate(p);
+    if (v != FLOW_OK) return v;
+    if (!st || !work1 || !work2 || !Ix || !Iy || !It) return fail(FLOW_E_INVAL, "NULL pointer");
+    const bool hw = p->beta > 0;
+    if (!st->u || !st->v || !st->ub || !st->vb || !st->qb1x || !st->qb1y || !st->qb2x || !st->qb2y)
+        return fail(FLOW_E_INVAL, "NULL state plane");
+    if (hw && (!st->w || !st->wb || !st->pbx || !st->pby || !work0)) return fail(FLOW_E_INVAL, "NULL w-block plane");
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    {
+        const float* planes[] = {st->u, st->v, st->ub, st->vb, st->qb1x, st->qb1y, st->qb2x, st->qb2y, work1, work2,
+                                 Ix, Iy, It};
+        for (const float* q : planes) EXTENT(q, H, W, ld, "pDR plane");
+        if (hw) {
+            const float* wp[] = {st->w, st->wb, st->pbx, st->pby, work0};
+            for (const float* q : wp) EXTENT(q, H, W, ld, "pDR w-block plane");
+        }
+        if (s_out) EXTENT(s_out, H, W, ld, "s_out");
+    }
+    PdrArgs a{};
+    a.w = st->w; a.u = st->u; a.v = st->v; a.wb = st->wb; a.ub = st->ub; a.vb = st->vb;
+    a.pbx = st->pbx; a.pby = st->pby; a.qb1x = st->qb1x; a.qb1y = st->qb1y; a.qb2x = st->qb2x; a.qb2y = st->qb2y;
+    a.bw = work0; a.bu = work1; a.bv = work2; a.s_out = s_out;
+    a.Ix = Ix; a.Iy = Iy; a.It = It; a.H = H; a.W = W; a.ld = ld;
+    a.sigma = (float)p->sigma; a.tau = (float)p->tau; a.stt = (float)(p->sigma * p->tau);
+    a.lam = (float)p->lambda; a.beta = (float)p->beta;
+    enqueue_pdr_iter(a, p->gs_sweeps, hw, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_energy(const flow_admm_state* st, const float* Ix, const float* Iy, const float* It,
+                           int32_t H, int32_t W, int64_t ld, double lambda, double beta, flow_result* res,
+                           void* stream) {
+    if (!st || !Ix || !Iy || !It || !res) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (!st->u || !st->v || !st->q1x || !st->q1y || !st->q2x || !st->q2y || !st->s)
+        return fail(FLOW_E_INVAL, "NULL state plane");
+    if (beta > 0 && (!st->w || !st->px || !st->py)) return fail(FLOW_E_INVAL, "NULL w-block plane");
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    {
+        const float* planes[] = {st->u, st->v, st->q1x, st->q1y, st->q2x, st->q2y, st->s, Ix, Iy, It};
+        for (const float* q : planes) EXTENT(q, H, W, ld, "energy plane");
+        if (beta > 0) {
+            const float* wp[] = {st->w, st->px, st->py};
+            for (const float* q : wp) EXTENT(q, H, W, ld, "energy w-block plane");
+        }
+    }
+    OpScratch& os = op_scratch();
+    flow_status s2 = os.ensure_lin(1);
+    if (s2 != FLOW_OK) return s2;
+    EnergyArgs e{};
+    e.w = st->w; e.u = st->u; e.v = st->v; e.px = st->px; e.py = st->py;
+    e.q1x = st->q1x; e.q1y = st->q1y; e.q2x = st->q2x; e.q2y = st->q2y; e.s = st->s;
+    e.Ix = Ix; e.Iy = Iy; e.It = It; e.H = H; e.W = W; e.ld = ld;
+    e.lam = (float)lambda; e.beta = (float)beta; e.pdr_tau = 0.f;
+    e.partial = os.e_partial; e.counter = os.e_counter; e.out = os.e_out;
+    hipStream_t s = (hipStream_t)stream;
+    launch_energy(e, s);
+    HIP_TRY(hipGetLastError());
+    double h[kEnergyTerms];
+    HIP_TRY(hipMemcpyAsync(h, os.e_out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    fill_result(h, res);
+    return FLOW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Host-side structures of the runtime: arena layout of one pair, small per-context device
+// buffers, event timers, the stopping test and the context itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/flow.h"
+#include "kernels.hpp"
+
+namespace flowmi {
+
+flow_status fail(flow_status st, const std::string& msg);
+flow_status hip_fail(hipError_t e, const char* what);
+int64_t pitch_of(int W);
+flow_status check_extent(const void* ptr, int H, int W, int64_t ld, size_t elem, const char* name);
+std::vector<std::pair<int, int>> level_shapes(int H, int W, int levels);
+flow_status validate(const flow_params* p);
+flow_status validate_shape(int H, int W, int64_t ld, int levels);
+
+struct DevArena {
+    void* base = nullptr;
+    size_t bytes = 0;
+};
+
+// Planes of one pyramid level (pitch ld elements; pyramid planes are FP32 or FP16).
+struct LevelPlanes {
+    int H = 0, W = 0;
+    int64_t ld = 0;
+    void *I0 = nullptr, *I1 = nullptr, *Dx = nullptr, *Dy = nullptr;
+    float *Ix = nullptr, *Iy = nullptr, *It = nullptr;
+    float* st[2][10] = {};                // ADMM ping-pong: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
+    float* U0[2] = {};                    // linearisation point (u0, v0); ADMM: the committed flow
+    float *X[3] = {}, *Xb[3] = {}, *b[3] = {}, *yb[6] = {}, *s_out = nullptr;   // pDR
+};
+
+// Small device buffers used by the reductions of one solve stream.
+struct Scratch {
+    float* at = nullptr;
+    float* lin_partial = nullptr;
+    unsigned* lin_counter = nullptr;
+    int lin_cap = 0;
+    double* e_partial = nullptr;
+    unsigned* e_counter = nullptr;
+    double* e_out = nullptr;
+    int64_t final_iters = 0;
+    flow_status alloc(int lin_blocks);
+    void release();
+    size_t bytes() const;
+};
+
+// Events around each warp's block of iteration kernels, summed per level.
+struct WarpTimers {
+    struct Pair { hipEvent_t a, b; int level; };
+    std::vector<Pair> pairs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int64_t launches[FLOW_MAX_LEVELS] = {};
+    int cur_level = 0;
+    hipEvent_t get();
+    void reset();
+    void begin(int level, hipStream_t s);
+    void end(int level, hipStream_t s);
+    void count(int level, int64_t n) { launches[level] += n; }
+    ~WarpTimers();
+};
+
+struct StopTest {
+    double tol = 0.0;
+    double* host = nullptr;   // pinned, kEnergyTerms doubles
+    flow_status check(Scratch& sc, hipStream_t s, bool* converged);
+};
+
+size_t layout_bytes(int H, int W, const flow_params& p);
+flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, std::vector<LevelPlanes>& out);
+void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p);
+flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
+                         WarpTimers* timers, StopTest* stop);
+const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int64_t iters_done);
+void fill_result(const double* h, flow_result* r);
+std::string graph_key(int H, int W, const flow_params& p, const void* arena);
+
+// Lazily allocated buffers for the operator-level entry points (per device, process lifetime).
+struct OpScratch {
+    float* lin_partial = nullptr;
+    unsigned* lin_counter = nullptr;
+    int lin_cap = 0;
+    double* e_partial = nullptr;
+    unsigned* e_counter = nullptr;
+    double* e_out = nullptr;
+    flow_status ensure_lin(int blocks);
+};
+OpScratch& op_scratch();
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t final_iters = 0;
+};
+
+struct BatchState;   // batch.cpp
+void destroy_batch(BatchState* b);
+
+}  // namespace flowmi
+
+struct flow_ctx {
+    int device = 0;
+    size_t budget = 0;
+    flowmi::DevArena arena;
+    flowmi::Scratch scratch;
+    double* host_out = nullptr;           // pinned
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, flowmi::GraphEntry> graphs;
+    bool stats_enabled = false;
+    flow_stats last_stats{};
+    flowmi::WarpTimers timers;
+    hipEvent_t ev_total[2] = {nullptr, nullptr};
+    flowmi::BatchState* batch = nullptr;
+
+    flow_status init_scratch();
+    size_t bytes_in_use() const;
+    flow_status ensure_arena(size_t need);
+    void drop_graphs();
+    flow_status solve(const float* I0, const float* I1, int H, int W, int64_t ld, const flow_params& p, float* u,
+                      float* v, int64_t ld_uv, flow_result* res, hipStream_t s);
+    ~flow_ctx();
+};

