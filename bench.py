@@ -7,11 +7,11 @@ whole solve (pyramid, warps, iterations, energy / gap) with the frames already r
 the solve is replayed from a hipGraph.  value = pixel-iterations of a step / step time.
 
 Also reported on the same JSON line:
-  roofline      the fused ADMM iteration kernel (the dominant kernel) at the finest level:
-                68 algorithmic bytes per pixel-iteration (7 state planes read + 3 linearisation
-                planes read + 7 state planes written, FP32) x pixels per launch / average launch
-                duration, timed with HIP events around that level's iteration blocks during
-                instrumented solves, against the 8 TB/s HBM peak
+  roofline      the ADMM iteration kernels (the dominant kernels; the autotuner picks one-pass or
+                K-iteration tiles per level): 76 algorithmic bytes per pixel per launch (12 FP32
+                planes read, 7 written) x pixels x launches / their time, timed with HIP events
+                around each warp's iteration block during instrumented solves, against the 8 TB/s
+                HBM peak; one_pass_equivalent_GBs counts 76 B per pixel-iteration instead
   cpu_baseline  the FP64 NumPy oracle on a bounded sample of the same workload, one core
   per_level     Gpixel-iter/s of each level's iteration blocks
 """
@@ -26,12 +26,15 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PX_ITER = {("padmm", False): 68, ("rpadmm2", False): 68, ("padmm", True): 92, ("rpadmm2", True): 92}
+# FP32 planes read + written per pixel by one launch of an iteration kernel (increment form):
+# reads du, dv, s, q1x, q1y, q2x, q2y, I_x, I_y, I_t, u0, v0 (+ w, px, py); writes the 7 (10) state planes
+BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
+BYTES_PER_PX_ITER_ONEPASS = BYTES_PER_PX_LAUNCH   # one launch = one iteration for the one-pass kernel
 
 
 def kernel_sha():
     h = hashlib.sha256()
-    for f in ("admm.hip", "kernels.hpp"):
+    for f in ("admm.hip", "admm_tb.hip", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -85,6 +88,7 @@ def main():
     ap.add_argument("--W", type=int, default=640)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -106,6 +110,11 @@ def main():
                        iters=args.iters, use_graph=1)
     u = torch.empty_like(I0)
     v = torch.empty_like(I0)
+    tuning = None
+    if not args.no_autotune:
+        # one-time choice of the iteration kernel per level shape (outside the timed region)
+        tuning = {k: v_["choice"] for k, v_ in ctx.autotune(args.H, args.W, params).items()}
+        print(f"[bench] autotuned: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ctx.solve(I0, I1, params, u=u, v=v)
     torch.cuda.synchronize()
@@ -155,15 +164,38 @@ def main():
     has_w = params.beta > 0
     roof = None
     if args.scheme in ("padmm", "rpadmm2"):
-        bpp = BYTES_PER_PX_ITER[(args.scheme, has_w)]
-        a, b = shapes[0]
-        launch_s = lvl_ms[0] * 1e-3 / max(1, lvl_launch[0])
-        achieved = bpp * a * b / launch_s / 1e9
+        # Dominant kernel = the iteration kernel (one-pass or K-iteration tiles, per the tuning).
+        # Algorithmic bytes of one launch: the 12 (15 with the w / p block) FP32 planes it reads
+        # and the 7 (10) it writes, once per pixel of the level, whatever K the launch advances.
+        per_px = BYTES_PER_PX_LAUNCH[has_w]
+        tot_bytes = 0.0
+        tot_ms = 0.0
+        tot_launches = 0
+        tot_pxiter = 0.0
+        for l, (a, b) in enumerate(shapes):
+            key = f"{a}x{b}{'w' if has_w else ''}i{args.iters}"
+            ch = (tuning or {}).get(key, {"mode": 1, "K": 1})
+            if ch["mode"] == 1:
+                per_warp = args.iters
+            elif ch["K"] == 0:
+                per_warp = 1                                   # resident: a warp in one launch
+            else:
+                per_warp = -(-args.iters // ch["K"])
+            n = per_warp * args.warps * reps
+            tot_launches += n
+            tot_bytes += per_px * a * b * n
+            tot_ms += lvl_ms[l]
+            tot_pxiter += a * b * lvl_launch[l]
+        launch_s = tot_ms * 1e-3 / max(1, tot_launches)
+        achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
         traffic = measured_traffic(f"{args.W}x{args.H}")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "admm_iter_kernel", "launch": f"{b}x{a} px, {bpp} B/px-iter",
-                "avg_launch_us": round(launch_s * 1e6, 3)}
+                "kernel": "admm iteration kernels (tuned per level)",
+                "per_unit": f"{per_px} B per pixel per launch",
+                "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step": tot_launches // reps,
+                "one_pass_equivalent_GBs": round(BYTES_PER_PX_ITER_ONEPASS[has_w] * tot_pxiter
+                                                 / (tot_ms * 1e-3) / 1e9, 1)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -180,7 +212,7 @@ def main():
                                f"{args.iters} iterations, {args.scheme}",
                    "H": args.H, "W": args.W, "levels": args.levels, "warps": args.warps, "iters": args.iters,
                    "scheme": args.scheme, "storage": args.storage, "px_iter_per_step": px_iter,
-                   "graph": True},
+                   "graph": True, "autotuned": tuning},
         "energy": res["energy"], "gap": res["gap"],
         "per_level": per_level,
         "roofline": roof,

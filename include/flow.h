@@ -149,6 +149,18 @@ typedef struct flow_pair {
 flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
                                void* stream);
 
+/* Autotuner: for every pyramid level of an H x W pair under params p, time each iteration-kernel
+ * choice (one-pass kernel with 2 / 4 / 8-row strips; K-iteration tiles of 256, 1024 and small
+ * 1024-thread work-groups for K = 2, 4, 8, 16; a resident tile where the level fits) over one
+ * warp's iterations with HIP events on `stream`, and keep the fastest per level shape for this
+ * context's later solves.  Every choice computes the same iteration (results agree to rounding).
+ * Blocking; uses the context's arena (contents are overwritten).  No effect for pDR. */
+flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
+
+/* JSON report of the last flow_autotune (choice and all measured candidates per level shape) into
+ * buf (host, cap bytes including the terminating NUL); FLOW_E_INVAL if it does not fit. */
+flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
+
 /* Enable (1) or disable (0) per-solve event timing; flow_get_stats returns the last solve's. */
 flow_status flow_set_stats(flow_ctx* ctx, int32_t enable);
 flow_status flow_get_stats(const flow_ctx* ctx, flow_stats* out);
@@ -157,7 +169,12 @@ flow_status flow_get_stats(const flow_ctx* ctx, flow_stats* out);
 flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
 
 /* Process-wide kernel tuning knobs (set by the autotuner; 0 restores the built-in heuristic):
- *   "admm_rows"   rows per wavefront strip of the fused ADMM iteration kernel: 2, 4 or 8.
+ *   "admm_rows"   rows per wavefront strip of the fused one-pass ADMM iteration kernel: 2, 4 or 8.
+ *   "tb_mode"     iteration kernel per level: 0 built-in choice (levels that fit one 1024-thread tile
+ *                 stay resident for a whole warp, larger ones use the one-pass kernel), 1 one-pass
+ *                 kernel only, 2 K-iteration tiles of 256 threads, 3 of 1024 threads, 4 small tiles
+ *                 of 1024 threads.
+ *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
  * FLOW_E_INVAL for an unknown key or value.  Not thread-safe against concurrent solves. */
 flow_status flow_tune_set(const char* key, int64_t value);
 
@@ -183,7 +200,7 @@ flow_status flow_op_derivatives(const float* I, int32_t H, int32_t W, int64_t ld
  *   I_x = kappa B(DxI1)(x + d0), I_y = kappa B(DyI1)(x + d0),
  *   I_t = kappa (B(I1)(x + d0) - I0) - I_x u0 - I_y v0,
  * with B bilinear sampling at clamped coordinates, and at_out (device, one float) receives
- * a~ = max(max_ij(beta^2 + I_x^2 + I_y^2), 1e-12) (Prop. 3.1). */
+ * max_ij(beta^2 + I_x^2 + I_y^2) = ||M_s||, the a~ of Prop. 3.1 (the iteration floors it at 1e-12). */
 flow_status flow_op_linearize(const float* I0, const float* I1, const float* DxI1, const float* DyI1,
                               const float* u0, const float* v0, int32_t H, int32_t W, int64_t ld,
                               double kappa, double beta, float* Ix, float* Iy, float* It, float* at_out,
@@ -209,6 +226,18 @@ typedef struct flow_admm_state {
 flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* out, const float* Ix,
                               const float* Iy, const float* It, const float* at, int32_t H, int32_t W,
                               int64_t ld, const flow_params* p, void* stream);
+
+/* `iters` iterations in ONE launch of the temporally blocked tile kernel (the solver's path for
+ * levels that do not need the one-pass kernel), increment form only (in->u0, in->v0 set).
+ * threads: 256 or 1024 (6 pixels per thread, 4 with beta > 0) or 1025 (1024 threads, 2 pixels per
+ * thread); tile_h x tile_w: output tile; each tile's extended region
+ * min(H, tile_h + 3 iters) x min(W, tile_w + 3 iters) must fit that capacity, else FLOW_E_INVAL.
+ * use_queue: 0 = one work-group per tile, 1 = persistent work-groups pulling tiles from a counter
+ * (the batched path).  Blocking (synchronises the stream). */
+flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* out, const float* Ix, const float* Iy,
+                            const float* It, const float* at, int32_t H, int32_t W, int64_t ld,
+                            const flow_params* p, int32_t iters, int32_t threads, int32_t tile_h, int32_t tile_w,
+                            int32_t use_queue, void* stream);
 
 /* State planes of pDR: X = (w, u, v), X bar = (wb, ub, vb), y bar = (pbx, pby, qb1x, qb1y, qb2x,
  * qb2y); w, wb, pbx, pby only when beta > 0.  Updated in place.  work: 3 scratch planes (device,

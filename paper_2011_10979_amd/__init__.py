@@ -67,7 +67,7 @@ _lib = None
 EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "flow_solve_batched",
            "flow_set_stats", "flow_get_stats", "flow_memory_in_use", "flow_last_error", "flow_op_downsample",
            "flow_op_derivatives", "flow_op_linearize", "flow_op_upsample", "flow_op_admm_iter", "flow_op_pdr_iter",
-           "flow_op_energy", "flow_tune_set"]
+           "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning"]
 
 
 def lib():
@@ -85,6 +85,8 @@ def lib():
             "flow_solve": [vp, vp, vp, i32, i32, i64, ctypes.POINTER(_Params), vp, vp, i64, ctypes.POINTER(_Result), vp],
             "flow_solve_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
             "flow_set_stats": [vp, i32],
+            "flow_autotune": [vp, i32, i32, ctypes.POINTER(_Params), vp],
+            "flow_get_tuning": [vp, ctypes.c_char_p, ctypes.c_size_t],
             "flow_get_stats": [vp, ctypes.POINTER(_Stats)],
             "flow_memory_in_use": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "flow_op_downsample": [vp, i32, i32, i64, vp, i64, vp],
@@ -93,6 +95,8 @@ def lib():
             "flow_op_upsample": [vp, i64, vp, i32, i32, i64, dbl, vp],
             "flow_op_admm_iter": [ctypes.POINTER(_AdmmState), ctypes.POINTER(_AdmmState), vp, vp, vp, vp, i32, i32,
                                   i64, ctypes.POINTER(_Params), vp],
+            "flow_op_admm_tb": [ctypes.POINTER(_AdmmState), ctypes.POINTER(_AdmmState), vp, vp, vp, vp, i32, i32, i64,
+                                ctypes.POINTER(_Params), i32, i32, i32, i32, i32, vp],
             "flow_op_pdr_iter": [ctypes.POINTER(_PdrState), vp, vp, vp, vp, vp, vp, vp, i32, i32, i64,
                                  ctypes.POINTER(_Params), vp],
             "flow_op_energy": [ctypes.POINTER(_AdmmState), vp, vp, vp, i32, i32, i64, dbl, dbl, ctypes.POINTER(_Result),
@@ -219,6 +223,16 @@ class Context:
                     iter_ms=list(s.iter_ms[:n]), total_ms=s.total_ms, px_iter=s.px_iter,
                     graph_replayed=bool(s.graph_replayed))
 
+    def autotune(self, H, W, params: Params | None = None, **kw):
+        """Time every iteration-kernel choice on the level shapes of an H x W pair; later solves of
+        this context use the fastest per level.  Returns the JSON report as a dict."""
+        import json
+        params = params or Params(**kw)
+        _check(lib().flow_autotune(self._h, H, W, ctypes.byref(params.c_struct()), _stream()))
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().flow_get_tuning(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode() or "{}")
+
     def memory_in_use(self):
         b = ctypes.c_size_t()
         _check(lib().flow_memory_in_use(self._h, ctypes.byref(b)))
@@ -325,6 +339,20 @@ def admm_iter(state, Ix, Iy, It, at, params: Params):
     _check(lib().flow_op_admm_iter(ctypes.byref(_admm_struct(state)), ctypes.byref(_admm_struct(out)), _ptr(Ix),
                                    _ptr(Iy), _ptr(It), _ptr(at), H, W, state["u"].stride(0),
                                    ctypes.byref(params.c_struct()), _stream()))
+    return out
+
+
+def admm_tb(state, Ix, Iy, It, at, params: Params, iters, threads=256, tile_h=16, tile_w=32, use_queue=False):
+    """`iters` iterations in one launch of the K-iteration tile kernel (increment form: the state
+    must hold "u0", "v0"); returns the new state dict."""
+    ref = _plane(state["u"], "u")
+    out = {k: (_like(t) if t is not None else None) for k, t in state.items() if k not in ("u0", "v0")}
+    _same_layout(ref, list(state.items()) + [(k + "_out", t) for k, t in out.items()]
+                 + [("Ix", Ix), ("Iy", Iy), ("It", It)], "admm_tb")
+    H, W = ref.shape
+    _check(lib().flow_op_admm_tb(ctypes.byref(_admm_struct(state)), ctypes.byref(_admm_struct(out)), _ptr(Ix),
+                                 _ptr(Iy), _ptr(It), _ptr(at), H, W, ref.stride(0), ctypes.byref(params.c_struct()),
+                                 iters, threads, tile_h, tile_w, 1 if use_queue else 0, _stream()))
     return out
 
 

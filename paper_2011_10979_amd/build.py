@@ -17,8 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflowmi.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["admm.hip", "pyramid.hip", "pdr.hip", "energy.hip", "batch_kernels.hip",
-           "runtime.cpp", "context.cpp", "batch.cpp"]
+SOURCES = ["admm.hip", "admm_tb.hip", "pyramid.hip", "pdr.hip", "energy.hip", "batch_kernels.hip",
+           "runtime.cpp", "context.cpp", "tb_plan.cpp", "autotune.cpp", "batch.cpp"]
 
 ARCH = os.environ.get("FLOWMI_ARCH", "gfx950")
 

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void admm_iter_kernel(AdmmIterArgs a) {
     const bool store_col = cv && lane >= 2 && lane <= 62;
     const int y0 = seg * R;
     const int y1 = min(y0 + R, a.H);
-    const float inv_atc = 1.f / ((*a.at) * a.c);
+    const float inv_atc = 1.f / (fmaxf(*a.at, 1e-12f) * a.c);   // a~ >= ||M_s|| (Prop. 3.1), floored
     const float c = a.c, inv_ac = a.inv_ac, beta = a.beta;
 
     // values of row r - 1 (and y+ of row r - 2) carried between steps
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void admm_iter_kernel(AdmmIterArgs a) {
 
 int g_admm_rows_override = 0;
 
-AdmmGeometry admm_geometry(int H, int W) {
+AdmmGeometry admm_geometry(int H, int W, int rows_hint) {
     AdmmGeometry g;
     g.strips = (W + kStrip - 1) / kStrip;
     auto waves = [&](int r) { return (long long)g.strips * ((H + r - 1) / r); };
@@ -218,6 +218,8 @@ AdmmGeometry admm_geometry(int H, int W) {
     else if (waves(4) >= 1024) rows = 4;
     if (g_admm_rows_override == 2 || g_admm_rows_override == 4 || g_admm_rows_override == 8)
         rows = g_admm_rows_override;
+    else if (rows_hint == 2 || rows_hint == 4 || rows_hint == 8)
+        rows = rows_hint;
     g.rows = rows;
     g.segs = (H + g.rows - 1) / g.rows;
     long long blocks = (waves(rows) + 3) / 4;
@@ -235,7 +237,7 @@ static void launch_rows(const AdmmIterArgs& b, const AdmmGeometry& g, bool has_w
 }
 
 void launch_admm_iter(const AdmmIterArgs& a, bool has_w, hipStream_t s) {
-    const AdmmGeometry g = admm_geometry(a.H, a.W);
+    const AdmmGeometry g = admm_geometry(a.H, a.W, a.rows);
     AdmmIterArgs b = a;
     b.rows = g.rows;
     b.strips = g.strips;

@@ -1,0 +1,269 @@
+// Temporally blocked iterations of the preconditioned dual ADMM family (Sec. 3.1.1) on gfx950.
+//
+// One work-group owns an output tile of one pyramid level (of one pair) and advances it by K
+// iterations in a single launch.  One iteration makes every value depend on the previous
+// iterate within 2 rows / columns above and to the left and 1 below and to the right (g needs q
+// to the left and above, y+ needs g to the right and below, the output needs y+ to the left and
+// above), so the tile is loaded with a halo of 2K (top, left) and K (bottom, right) and the valid
+// region shrinks by that much over the K iterations; on sides where the tile meets the image
+// border there is no halo and the discrete boundary rules of Sec. 2.2 apply exactly.  Halo
+// pixels are recomputed by the neighbouring tiles; their values here only feed other halo pixels.
+//
+// Placement: q (and p), whose neighbours the divergence reads, and g, whose neighbours the
+// gradient reads, live in LDS; everything only read at its own pixel (the increment du, dv, s,
+// w and the linearisation I_x, I_y, I_t, u0, v0) lives in registers of the thread that owns the
+// pixel for the whole launch.  Per iteration:  A: g from q (LDS) -> LDS;  barrier;  B: y+ from
+// g (LDS), written over q;  barrier;  C: div y+, s+, multipliers (registers), then A of the next
+// iteration (C only reads y+, A only writes g, so they need no barrier between them).
+//
+// Work distribution: a persistent grid pulls tile indices from a device counter; tiles of one
+// launch read one state buffer and write the other, so they never depend on each other and every
+// work-group exits once the counter passes the tile count.  Levels of different pairs can share a
+// launch (batched solves): each tile names its level descriptor.
+#include "kernels.hpp"
+
+namespace flowmi {
+
+namespace {
+
+template <bool HAS_W, int NT, int PPT>
+struct TileLds {
+    static constexpr int CAP = NT * PPT;
+    float sq1x[CAP], sq1y[CAP], sq2x[CAP], sq2y[CAP], sgu[CAP], sgv[CAP];
+    float spx[HAS_W ? CAP : 1], spy[HAS_W ? CAP : 1], sgw[HAS_W ? CAP : 1];
+};
+
+// K iterations of output tile T of level L by the calling work-group.
+template <bool HAS_W, int NT, int PPT>
+__device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, const TbLevel& L,
+                                             TileLds<HAS_W, NT, PPT>& S) {
+    float* sq1x = S.sq1x; float* sq1y = S.sq1y; float* sq2x = S.sq2x; float* sq2y = S.sq2y;
+    float* sgu = S.sgu; float* sgv = S.sgv; float* spx = S.spx; float* spy = S.spy; float* sgw = S.sgw;
+    const int tid = threadIdx.x;
+    const float c = a.c, inv_ac = a.inv_ac, beta = a.beta, crs = a.c_rho_s;
+    {
+        const int H = L.H, W = L.W;
+        const int64_t ld = L.ld;
+        const int K = a.K;
+        // extended region: output tile plus halo, clipped to the image
+        const int ey0 = max(T.y0 - 2 * K, 0), ex0 = max(T.x0 - 2 * K, 0);
+        const int ey1 = min(T.y0 + T.th + K, H), ex1 = min(T.x0 + T.tw + K, W);
+        const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;
+        const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);   // a~ >= ||M_s||, floored
+
+        float du[PPT], dv[PPT], ss[PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], ww[PPT];
+        int ei[PPT], ej[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = tid + k * NT;
+            ei[k] = e / EW;
+            ej[k] = e - ei[k] * EW;
+            du[k] = dv[k] = ss[k] = Ix[k] = Iy[k] = It[k] = u0[k] = v0[k] = ww[k] = 0.f;
+            if (e < EN) {
+                const int64_t o = (int64_t)(ey0 + ei[k]) * ld + (ex0 + ej[k]);
+                sq1x[e] = L.in[5][o];
+                sq1y[e] = L.in[6][o];
+                sq2x[e] = L.in[7][o];
+                sq2y[e] = L.in[8][o];
+                du[k] = L.in[1][o];
+                dv[k] = L.in[2][o];
+                ss[k] = L.in[9][o];
+                Ix[k] = L.Ix[o];
+                Iy[k] = L.Iy[o];
+                It[k] = L.It[o];
+                u0[k] = L.u0[o];
+                v0[k] = L.v0[o];
+                if constexpr (HAS_W) {
+                    spx[e] = L.in[3][o];
+                    spy[e] = L.in[4][o];
+                    ww[k] = L.in[0][o];
+                }
+            }
+        }
+        __syncthreads();
+
+        // phase A (g) for the thread's pixels
+        auto phase_a = [&]() {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e = tid + k * NT;
+                if (e >= EN) continue;
+                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+                const bool l = ej[k] > 0 && gj > 0, u = ei[k] > 0 && gi > 0;
+                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
+                const float dq1 = mx * sq1x[e] - (l ? sq1x[e - 1] : 0.f) + my * sq1y[e] - (u ? sq1y[e - EW] : 0.f);
+                const float dq2 = mx * sq2x[e] - (l ? sq2x[e - 1] : 0.f) + my * sq2y[e] - (u ? sq2y[e - EW] : 0.f);
+                sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
+                sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
+                if constexpr (HAS_W) {
+                    const float dp = mx * spx[e] - (l ? spx[e - 1] : 0.f) + my * spy[e] - (u ? spy[e - EW] : 0.f);
+                    sgw[e] = ww[k] + c * (dp - beta * ss[k]);
+                }
+            }
+        };
+
+        phase_a();
+        for (int it = 0; it < K; ++it) {
+            __syncthreads();
+            // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own pixel)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e = tid + k * NT;
+                if (e >= EN) continue;
+                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+                const bool r = ej[k] < EW - 1, d = e + EW < EN;
+                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
+                const float gu = sgu[e], gv = sgv[e];
+                const float t1x = sq1x[e] + mx * ((r ? sgu[e + 1] : gu) - gu) * inv_ac;
+                const float t1y = sq1y[e] + my * ((d ? sgu[e + EW] : gu) - gu) * inv_ac;
+                const float t2x = sq2x[e] + mx * ((r ? sgv[e + 1] : gv) - gv) * inv_ac;
+                const float t2y = sq2y[e] + my * ((d ? sgv[e + EW] : gv) - gv) * inv_ac;
+                const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
+                const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
+                sq1x[e] = t1x * sc;
+                sq1y[e] = t1y * sc;
+                sq2x[e] = t2x * sc;
+                sq2y[e] = t2y * sc;
+                if constexpr (HAS_W) {
+                    const float gw = sgw[e];
+                    const float tpx = spx[e] + mx * ((r ? sgw[e + 1] : gw) - gw) * inv_ac;
+                    const float tpy = spy[e] + my * ((d ? sgw[e + EW] : gw) - gw) * inv_ac;
+                    const float np2 = tpx * tpx + tpy * tpy;
+                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                    spx[e] = tpx * sp;
+                    spy[e] = tpy * sp;
+                }
+            }
+            __syncthreads();
+            // phase C: div y+, s+, multipliers (own pixels, registers)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int e = tid + k * NT;
+                if (e >= EN) continue;
+                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+                const bool l = ej[k] > 0 && gj > 0, u = ei[k] > 0 && gi > 0;
+                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
+                const float dn1 = mx * sq1x[e] - (l ? sq1x[e - 1] : 0.f) + my * sq1y[e] - (u ? sq1y[e - EW] : 0.f);
+                const float dn2 = mx * sq2x[e] - (l ? sq2x[e - 1] : 0.f) + my * sq2y[e] - (u ? sq2y[e - EW] : 0.f);
+                const float hu = du[k] + crs * (dn1 - Ix[k] * ss[k]);
+                const float hv = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
+                float acc = It[k] + Ix[k] * hu + Iy[k] * hv;
+                float dnp = 0.f;
+                if constexpr (HAS_W) {
+                    dnp = mx * spx[e] - (l ? spx[e - 1] : 0.f) + my * spy[e] - (u ? spy[e - EW] : 0.f);
+                    acc += beta * (ww[k] + crs * (dnp - beta * ss[k]));
+                }
+                float sn = ss[k] + acc * inv_atc;
+                sn = fminf(fmaxf(sn, -a.lam), a.lam);
+                const float ms = a.cB * sn - a.cC * ss[k];
+                du[k] = du[k] + a.cA * dn1 - Ix[k] * ms;
+                dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;
+                if constexpr (HAS_W) ww[k] = ww[k] + a.cA * dnp - beta * ms;
+                ss[k] = sn;
+            }
+            if (it + 1 < K) phase_a();
+        }
+
+        // write the output tile
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = tid + k * NT;
+            if (e >= EN) continue;
+            const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+            if (gi < T.y0 || gi >= T.y0 + T.th || gj < T.x0 || gj >= T.x0 + T.tw) continue;
+            const int64_t o = (int64_t)gi * ld + gj;
+            L.out[1][o] = du[k];
+            L.out[2][o] = dv[k];
+            L.out[9][o] = ss[k];
+            L.out[5][o] = sq1x[e];
+            L.out[6][o] = sq1y[e];
+            L.out[7][o] = sq2x[e];
+            L.out[8][o] = sq2y[e];
+            if constexpr (HAS_W) {
+                L.out[0][o] = ww[k];
+                L.out[3][o] = spx[e];
+                L.out[4][o] = spy[e];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    // work-groups are dealt round-robin to the 8 XCDs; neighbouring tiles (which re-read each
+    // other's halo) go to the same XCD's L2
+    const int per = nb >> 3;   // host pads the grid to a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+// One level, regular tiling: the tile comes from the work-group index, the level descriptor from
+// the kernel arguments (no table reads, no counter).
+template <bool HAS_W, int NT, int PPT>
+__global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
+    __shared__ TileLds<HAS_W, NT, PPT> S;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= a.ntiles) return;
+    TbTile T;
+    T.level = 0;
+    const int ty = t / a.ntx, tx = t - ty * a.ntx;
+    T.y0 = ty * a.th;
+    T.x0 = tx * a.tw;
+    T.th = min(a.th, a.lvl.H - T.y0);
+    T.tw = min(a.tw, a.lvl.W - T.x0);
+    process_tile<HAS_W, NT, PPT>(a, T, a.lvl, S);
+}
+
+// Many levels (batched pairs): a persistent grid pulls (level, tile) items from a counter.
+template <bool HAS_W, int NT, int PPT>
+__global__ __launch_bounds__(NT) void admm_tb_queue_kernel(TbArgs a) {
+    __shared__ TileLds<HAS_W, NT, PPT> S;
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)(atomicAdd(a.queue, 1u) - a.queue_base);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();                  // everyone has read s_tile before it is overwritten
+        if (t >= a.ntiles) break;         // uniform: the whole work-group leaves together
+        const TbTile T = a.tiles[t];
+        process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
+        __syncthreads();                  // LDS is reused by the next tile
+    }
+}
+
+__global__ void reset_u32_kernel(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+void launch_reset_u32(unsigned* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(reset_u32_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+}
+
+int tb_capacity(bool has_w, int nt) {
+    if (nt == 1024) return 1024 * (has_w ? kTbPptW : kTbPpt);
+    if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
+    return 256 * (has_w ? kTbPptW : kTbPpt);
+}
+
+template <bool HAS_W, int NT, int PPT>
+static void launch_one(const TbArgs& a, int grid, hipStream_t s) {
+    if (a.queue) hipLaunchKernelGGL((admm_tb_queue_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((admm_tb_direct_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+}
+
+void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s) {
+    if (!a.queue) grid = (grid + 7) / 8 * 8;     // direct mode: XCD remap wants a multiple of 8
+    if (nt == 1024) {
+        if (has_w) launch_one<true, 1024, kTbPptW>(a, grid, s);
+        else launch_one<false, 1024, kTbPpt>(a, grid, s);
+    } else if (nt == 1025) {
+        if (has_w) launch_one<true, 1024, kTbPptSmall>(a, grid, s);
+        else launch_one<false, 1024, kTbPptSmall>(a, grid, s);
+    } else {
+        if (has_w) launch_one<true, 256, kTbPptW>(a, grid, s);
+        else launch_one<false, 256, kTbPpt>(a, grid, s);
+    }
+}
+
+}  // namespace flowmi

@@ -1,0 +1,134 @@
+// Autotuner: for every level shape of a pair, time each iteration-kernel choice (one-pass kernel
+// with strip heights 2 / 4 / 8; K-iteration tiles of 256, 1024 and small 1024-thread work-groups
+// with K = 2, 4, 8, 16; a resident tile where the level fits) over one warp's worth of iterations
+// with HIP events, and keep the fastest.  Every choice computes the same iteration, so the choice
+// changes speed only (results agree to rounding); later solves of the context use the table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "runtime.hpp"
+
+namespace flowmi {
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+    } while (0)
+
+static flow_status clear_level(const LevelPlanes& L, hipStream_t s) {
+    const size_t plane = (size_t)L.H * L.ld * sizeof(float);
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 10; ++k)
+            if (L.st[b][k]) HIP_TRY(hipMemsetAsync(L.st[b][k], 0, plane, s));
+    for (float* q : {L.Ix, L.Iy, L.It, L.U0[0], L.U0[1]}) HIP_TRY(hipMemsetAsync(q, 0, plane, s));
+    return FLOW_OK;
+}
+
+}  // namespace flowmi
+
+using namespace flowmi;
+
+extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    st = validate_shape(H, W, W, p->levels);
+    if (st != FLOW_OK) return st;
+    if (p->scheme == FLOW_PDR || p->iters < 1) return FLOW_OK;     // nothing to choose
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    st = ctx->ensure_arena(layout_bytes(H, W, *p));
+    if (st != FLOW_OK) return st;
+    std::vector<LevelPlanes> Ls;
+    st = build_layout(ctx->arena, H, W, *p, Ls);
+    if (st != FLOW_OK) return st;
+    const bool hw = p->beta > 0;
+    const float ones[2] = {1.f, 1.f};
+    HIP_TRY(hipMemcpyAsync(ctx->scratch.at, ones, sizeof(ones), hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::ostringstream rep;
+    rep << "{";
+    bool first_level = true;
+    for (const LevelPlanes& L : Ls) {
+        st = clear_level(L, s);
+        if (st != FLOW_OK) break;
+        struct Cand { TunedChoice c; LevelTbPlan P; bool tb; };
+        std::vector<Cand> cands;
+        for (int rows : {0, 2, 4, 8}) {
+            Cand c{};
+            c.c.mode = 1;
+            c.c.rows = rows;
+            c.tb = false;
+            cands.push_back(c);
+        }
+        for (int mode : {2, 4, 3})
+            for (int K : {2, 4, 8, 16}) {
+                LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K);
+                if (!P.tb) continue;
+                if (P.resident && K != 2) continue;             // one resident candidate per size
+                if (!P.resident && P.K != K) continue;          // capacity lowered K: a duplicate
+                std::vector<TbTile> tiles;
+                append_tiles(P, 0, L.H, L.W, tiles);
+                P.ntiles = (int)tiles.size();
+                Cand c{};
+                c.c.mode = mode;
+                c.c.K = P.resident ? 0 : K;
+                c.P = P;
+                c.tb = true;
+                cands.push_back(c);
+            }
+        double best = 1e30;
+        TunedChoice bestc;
+        std::ostringstream lv;
+        for (Cand& c : cands) {
+            const LevelTbPlan* P = c.tb ? &c.P : nullptr;
+            enqueue_admm_iters(L, *p, P, c.c.rows, 0, p->iters, 0, ctx->scratch.at, s);    // warm-up
+            float ms_best = 1e30f;
+            for (int rep_i = 0; rep_i < 3; ++rep_i) {
+                HIP_TRY(hipEventRecord(e0, s));
+                enqueue_admm_iters(L, *p, P, c.c.rows, 0, p->iters, 0, ctx->scratch.at, s);
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                ms_best = std::min(ms_best, ms);
+            }
+            HIP_TRY(hipGetLastError());
+            c.c.us_per_iter = 1e3 * ms_best / p->iters;
+            lv << (lv.tellp() > 0 ? ", " : "") << "\"m" << c.c.mode << "k" << c.c.K << "r" << c.c.rows
+               << "\": " << c.c.us_per_iter;
+            if (c.c.us_per_iter < best) {
+                best = c.c.us_per_iter;
+                bestc = c.c;
+            }
+        }
+        ctx->tuned[tune_key(L.H, L.W, hw, p->iters)] = bestc;
+        rep << (first_level ? "" : ", ") << "\"" << tune_key(L.H, L.W, hw, p->iters) << "\": {\"choice\": {\"mode\": "
+            << bestc.mode << ", \"K\": " << bestc.K << ", \"rows\": " << bestc.rows << ", \"us_per_iter\": "
+            << bestc.us_per_iter << "}, \"candidates\": {" << lv.str() << "}}";
+        first_level = false;
+    }
+    rep << "}";
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != FLOW_OK) return st;
+    ctx->tune_report = rep.str();
+    ctx->tune_epoch++;
+    ctx->drop_graphs();
+    return FLOW_OK;
+}
+
+extern "C" flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap) {
+    if (!ctx || !buf || cap == 0) return fail(FLOW_E_INVAL, "NULL argument");
+    const std::string& r = ctx->tune_report;
+    if (r.size() + 1 > cap) return fail(FLOW_E_INVAL, "buffer too small for the tuning report");
+    std::memcpy(buf, r.c_str(), r.size() + 1);
+    return FLOW_OK;
+}

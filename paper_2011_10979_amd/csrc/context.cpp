@@ -15,33 +15,29 @@ namespace flowmi {
         if (_e != hipSuccess) return hip_fail(_e, #expr);       \
     } while (0)
 
-flow_status Scratch::alloc(int lin_blocks) {
+flow_status Scratch::alloc() {
     release();
-    lin_cap = lin_blocks;
     HIP_TRY(hipMalloc(&at, 256));
-    HIP_TRY(hipMalloc(&lin_partial, sizeof(float) * (size_t)lin_blocks));
-    HIP_TRY(hipMalloc(&lin_counter, 256));
+    HIP_TRY(hipMalloc(&queue, 256));
+    HIP_TRY(hipMemset(queue, 0, 256));
     HIP_TRY(hipMalloc(&e_partial, sizeof(double) * kEnergyTerms * kEnergyBlocks));
-    HIP_TRY(hipMalloc(&e_counter, 256));
     HIP_TRY(hipMalloc(&e_out, sizeof(double) * kEnergyTerms));
-    HIP_TRY(hipMemset(lin_counter, 0, 256));
-    HIP_TRY(hipMemset(e_counter, 0, 256));
     HIP_TRY(hipMemset(at, 0, 256));
     return FLOW_OK;
 }
 
 void Scratch::release() {
-    for (void* p : {(void*)at, (void*)lin_partial, (void*)lin_counter, (void*)e_partial, (void*)e_counter,
-                    (void*)e_out})
+    for (void* p : {(void*)at, (void*)queue, (void*)e_partial, (void*)e_out})
         if (p) hipFree(p);
-    at = nullptr; lin_partial = nullptr; lin_counter = nullptr; e_partial = nullptr; e_counter = nullptr;
+    at = nullptr;
+    queue = nullptr;
+    e_partial = nullptr;
     e_out = nullptr;
-    lin_cap = 0;
 }
 
 size_t Scratch::bytes() const {
     if (!at) return 0;
-    return 4 * 256 + sizeof(float) * (size_t)lin_cap + sizeof(double) * kEnergyTerms * (kEnergyBlocks + 1);
+    return 512 + sizeof(double) * kEnergyTerms * (kEnergyBlocks + 1);
 }
 
 hipEvent_t WarpTimers::get() {
@@ -93,28 +89,20 @@ flow_status StopTest::check(Scratch& sc, hipStream_t s, bool* converged) {
     return FLOW_OK;
 }
 
-std::string graph_key(int H, int W, const flow_params& p, const void* arena) {
+std::string graph_key(int H, int W, const flow_params& p, const void* arena, int tune_epoch) {
     std::ostringstream o;
     o.precision(17);
     o << H << ',' << W << ',' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
       << p.sigma << ',' << p.tau << ',' << p.gs_sweeps << ',' << p.intensity_scale << ',' << p.levels << ','
-      << p.warps << ',' << p.iters << ',' << p.storage << ',' << arena;
+      << p.warps << ',' << p.iters << ',' << p.storage << ',' << arena << ",tb" << g_tb_mode << ',' << g_tb_k
+      << ",rows" << g_admm_rows_override << ",te" << tune_epoch;
     return o.str();
 }
 
-flow_status OpScratch::ensure_lin(int blocks) {
-    if (!lin_counter) {
-        HIP_TRY(hipMalloc(&lin_counter, 256));
-        HIP_TRY(hipMemset(lin_counter, 0, 256));
-        HIP_TRY(hipMalloc(&e_counter, 256));
-        HIP_TRY(hipMemset(e_counter, 0, 256));
+flow_status OpScratch::ensure() {
+    if (!e_partial) {
         HIP_TRY(hipMalloc(&e_partial, sizeof(double) * kEnergyTerms * kEnergyBlocks));
         HIP_TRY(hipMalloc(&e_out, sizeof(double) * kEnergyTerms));
-    }
-    if (blocks > lin_cap) {
-        if (lin_partial) HIP_TRY(hipFree(lin_partial));
-        HIP_TRY(hipMalloc(&lin_partial, sizeof(float) * (size_t)blocks));
-        lin_cap = blocks;
     }
     return FLOW_OK;
 }
@@ -135,7 +123,7 @@ flow_status flow_ctx::init_scratch() {
     HIP_TRY(hipHostMalloc((void**)&host_out, sizeof(double) * kEnergyTerms * 2, hipHostMallocDefault));
     HIP_TRY(hipEventCreate(&ev_total[0]));
     HIP_TRY(hipEventCreate(&ev_total[1]));
-    return scratch.alloc(1024);
+    return scratch.alloc();
 }
 
 size_t flow_ctx::bytes_in_use() const { return arena.bytes + scratch.bytes(); }
@@ -146,6 +134,7 @@ void flow_ctx::drop_graphs() {
         if (kv.second.graph) hipGraphDestroy(kv.second.graph);
     }
     graphs.clear();
+    plans.clear();
 }
 
 flow_status flow_ctx::ensure_arena(size_t need) {
@@ -172,13 +161,6 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
     const bool f16 = p.storage == FLOW_STORE_F16;
     flow_status st = ensure_arena(layout_bytes(H, W, p));
     if (st != FLOW_OK) return st;
-    const int lb = linearize_blocks(H, W);
-    if (lb > scratch.lin_cap) {
-        HIP_TRY(hipDeviceSynchronize());
-        drop_graphs();
-        st = scratch.alloc(lb);
-        if (st != FLOW_OK) return st;
-    }
     std::vector<LevelPlanes> Ls;
     st = build_layout(arena, H, W, p, Ls);
     if (st != FLOW_OK) return st;
@@ -187,17 +169,25 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
     launch_import(I1, H, W, ld, Ls[0].I1, Ls[0].ld, f16, s);
     if (stats_enabled) HIP_TRY(hipEventRecord(ev_total[0], s));
 
-    const bool use_graph = p.use_graph && p.tol == 0.0 && !(stats_enabled && p.use_graph == 2);
-    int64_t final_iters = 0;
+    const bool use_graph = p.use_graph && p.tol == 0.0;
+    const std::string key = graph_key(H, W, p, arena.base, tune_epoch);
+    auto pit = plans.find(key);
+    if (pit == plans.end()) {
+        std::unique_ptr<SolvePlan> plan(new SolvePlan());
+        st = make_plan(Ls, p, scratch, *plan, &tuned);
+        if (st != FLOW_OK) return st;
+        pit = plans.emplace(key, std::move(plan)).first;
+    }
+    const SolvePlan* plan = pit->second.get();
+    int final_buf = 0;
     bool replayed = false;
     timers.reset();
     if (use_graph) {
-        const std::string key = graph_key(H, W, p, arena.base);
         auto it = graphs.find(key);
         if (it == graphs.end()) {
             GraphEntry g;
             HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-            flow_status cst = enqueue_core(Ls, p, scratch, cap_stream, nullptr, nullptr);
+            flow_status cst = enqueue_core(Ls, p, scratch, cap_stream, nullptr, nullptr, plan);
             hipGraph_t graph = nullptr;
             hipError_t ee = hipStreamEndCapture(cap_stream, &graph);
             if (cst != FLOW_OK) {
@@ -207,24 +197,24 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
             if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
             g.graph = graph;
             HIP_TRY(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
-            g.final_iters = scratch.final_iters;
+            g.final_buf = scratch.final_buf;
             it = graphs.emplace(key, g).first;
         }
         HIP_TRY(hipGraphLaunch(it->second.exec, s));
-        final_iters = it->second.final_iters;
+        final_buf = it->second.final_buf;
         replayed = true;
     } else {
         StopTest stop;
         stop.tol = p.tol;
         stop.host = host_out + kEnergyTerms;
-        st = enqueue_core(Ls, p, scratch, s, stats_enabled ? &timers : nullptr, p.tol > 0 ? &stop : nullptr);
+        st = enqueue_core(Ls, p, scratch, s, stats_enabled ? &timers : nullptr, p.tol > 0 ? &stop : nullptr, plan);
         if (st != FLOW_OK) return st;
-        final_iters = scratch.final_iters;
+        final_buf = scratch.final_buf;
     }
     if (stats_enabled) HIP_TRY(hipEventRecord(ev_total[1], s));
 
-    launch_copy2d(level_flow(Ls[0], p, 1, final_iters), H, W, Ls[0].ld, u, ld_uv, s);
-    launch_copy2d(level_flow(Ls[0], p, 2, final_iters), H, W, Ls[0].ld, v, ld_uv, s);
+    launch_copy2d(level_flow(Ls[0], p, 1, final_buf), H, W, Ls[0].ld, u, ld_uv, s);
+    launch_copy2d(level_flow(Ls[0], p, 2, final_buf), H, W, Ls[0].ld, v, ld_uv, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(host_out, scratch.e_out, sizeof(double) * kEnergyTerms, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -6,7 +6,7 @@
 // plus G_TV = sum(|grad d| - <grad d, q>), G_data = sum(lambda |rho| - rho s) and <Lambda, r>, whose
 // sum equals E - D.  Per-pixel terms are formed in FP32 and accumulated in FP64: per thread over a
 // fixed grid-stride set of pixels, across the wavefront with lane shuffles, across the block in
-// LDS, and over blocks by the last block to finish, in block order, so the result is bitwise
+// LDS, and over blocks by a second one-block kernel in a fixed order, so the result is bitwise
 // reproducible for a given shape.
 #include "kernels.hpp"
 
@@ -96,7 +96,6 @@ __global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) {
         if (!isfinite(chk)) acc[7] += 1.0;
     }
     __shared__ double sm[4][kEnergyTerms];
-    __shared__ int is_last;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kEnergyTerms; ++k) {
@@ -108,24 +107,25 @@ __global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) {
         const int k = threadIdx.x;
         a.partial[blockIdx.x * kEnergyTerms + k] = ((sm[0][k] + sm[1][k]) + sm[2][k]) + sm[3][k];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(a.counter, 1u);
-        is_last = (prev == gridDim.x - 1u);
-    }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        if (threadIdx.x < kEnergyTerms) {
-            const int k = threadIdx.x;
-            double t = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b)
-                t += __hip_atomic_load(&a.partial[b * kEnergyTerms + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            a.out[k] = t;
-        }
+}
+
+// Sum of the per-block partials (a separate launch: the kernel boundary makes the partials
+// visible without any fence).  Thread t adds partials t, t + 256, ... in order, then a fixed
+// pairwise tree in LDS combines the 256 sums, so the result is reproducible bit for bit.
+__global__ __launch_bounds__(256) void energy_final_kernel(const double* __restrict__ partial, int nblocks,
+                                                          double* __restrict__ out) {
+    __shared__ double sm[256];
+    for (int k = 0; k < kEnergyTerms; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) t += partial[b * kEnergyTerms + k];
+        sm[threadIdx.x] = t;
         __syncthreads();
-        if (threadIdx.x == 0) *a.counter = 0u;
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sm[0];
+        __syncthreads();
     }
 }
 
@@ -137,6 +137,7 @@ void launch_energy(const EnergyArgs& a, hipStream_t s) {
     if (blocks > kEnergyBlocks) blocks = kEnergyBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(energy_kernel, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(256), 0, s, (const double*)a.partial, blocks, a.out);
 }
 
 }  // namespace flowmi

@@ -24,23 +24,56 @@ struct AdmmIterArgs {
     float inv_ac;           // 1 / (a c), a = 8
     float c_rho_s;          // c * rho_s (rho_s = 1 for rpADMMI, rho for rpADMMII)
     float cA, cB, cC;       // Lambda+ = Lambda + cA div y+ - A (cB s+ - cC s)
-    int rows;               // output rows per wavefront
+    int rows;               // output rows per wavefront (caller: 0 = built-in choice, or 2 / 4 / 8)
     int strips, segs;       // wavefront grid: strips along x, segments along y
 };
 
 struct AdmmGeometry { int rows, strips, segs, blocks; };
-AdmmGeometry admm_geometry(int H, int W);
+AdmmGeometry admm_geometry(int H, int W, int rows_hint);
 extern int g_admm_rows_override;   // 0 = heuristic; 2, 4 or 8 force the strip height
 void launch_admm_iter(const AdmmIterArgs& a, bool has_w, hipStream_t s);
+
+// Temporally blocked iterations: K iterations of one output tile per work-group launch.
+constexpr int kTbPpt = 6;            // pixels per thread (beta = 0): LDS q1x..q2y, gu, gv
+constexpr int kTbPptW = 4;           // with the w / p block
+constexpr int kTbPptSmall = 2;       // 1024 threads on small tiles (work-group size code 1025)
+struct TbTile {
+    int level;                       // index of the (pair, level) descriptor
+    int y0, x0, th, tw;              // output tile
+};
+struct TbLevel {
+    const float* in[10];             // iterate k: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
+    float* out[10];                  // iterate k + K
+    const float *Ix, *Iy, *It, *u0, *v0;
+    const float* at;                 // the pair's two a~ slots
+    int H, W;
+    int64_t ld;
+};
+struct TbArgs {
+    const TbTile* tiles;
+    int ntiles;
+    const TbLevel* levels;           // two descriptors per (pair, level): [2 * id + dir]
+    int dir;                         // which ping-pong direction this launch uses
+    int K;                           // iterations of this launch (halo = 2K top/left, K bottom/right)
+    int at_slot;                     // a~ slot of the current warp
+    unsigned* queue;                 // work counter, monotone within a solve (nullptr: direct mode)
+    unsigned queue_base;             // counter value at the start of this launch
+    float c, lam, beta, inv_ac, c_rho_s, cA, cB, cC;
+    // direct mode (one level, regular tiles): descriptor of this launch's direction and tiling
+    TbLevel lvl;
+    int th, tw, ntx;
+};
+int tb_capacity(bool has_w, int nt);   // nt: 256, 1024, or 1025 (1024 threads, small tiles)
+void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s);
+void launch_reset_u32(unsigned* p, int n, hipStream_t s);
 
 // Warp + linearise + a~ (max of M_s) with a last-block finalisation.
 struct LinArgs {
     const void *I0, *I1, *Dx, *Dy;   // float or __half, pitch ld
     const float *u0, *v0;            // pitch ld
     float *Ix, *Iy, *It;             // pitch ld
-    float* at;                       // device scalar out
-    float* partial;                  // >= gridDim.x*gridDim.y floats
-    unsigned* counter;               // zero on entry, zero again on exit
+    float* at;                       // device scalar: max of M_s accumulated here (zero on entry)
+    float* at_clear;                 // optional scalar cleared for the next warp (the other slot)
     int H, W;
     int64_t ld;
     float kappa, beta;
@@ -49,7 +82,6 @@ struct LinArgs {
     float *keep_u, *keep_v;          // optional planes receiving a copy of (u0, v0)
 };
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s);
-int linearize_blocks(int H, int W);
 
 // Pyramid: 2x2 box average with edge replication, central differences, format conversion.
 void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s);
@@ -65,8 +97,9 @@ struct LevelInitArgs {
     int64_t ldc;
     float* set_flow[3];              // w, u, v targets (w may be nullptr)
     float* copy_flow[3];             // pDR X bar: copies of w, u, v (may be nullptr)
-    float* zero[8];                  // planes to clear (nullptr-terminated use of count)
+    float* zero[8];                  // planes to clear (first nzero entries)
     int nzero;
+    float* clear_scalar;             // optional device scalar set to 0 (the first warp's a~ slot)
     int H, W;
     int64_t ld;
 };
@@ -105,7 +138,6 @@ struct EnergyArgs {
     const float *du, *dv;            // increment form: flow = u + du, rho uses du (It relative)
     const float *lu0, *lv0;          // or: rho uses u - lu0, v - lv0 (It relative)
     double* partial;                 // kEnergyTerms doubles per block
-    unsigned* counter;
     double* out;                     // kEnergyTerms doubles
 };
 constexpr int kEnergyTerms = 8;      // tv, data, dual, residual^2, g_tv, g_data, lam_r, nonfinite

@@ -108,35 +108,16 @@ __global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
         if (a.keep_u) { a.keep_u[off] = u0; a.keep_v[off] = v0; }
         ms = a.beta * a.beta + Ix * Ix + Iy * Iy;
     }
-    // a~ = max M_s: wave -> block -> per-block partial; the last block to finish reduces the
-    // partials (max is exact, so the result does not depend on the order).
+    // a~ = max M_s: wave -> block -> one atomic max per block on the float's bit pattern (exact
+    // and order-independent for non-negative values); the consumer applies the 1e-12 floor.
     __shared__ float smax[4];
-    __shared__ int is_last;
     ms = wave_max(ms);
     if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = ms;
     __syncthreads();
-    const int nblk = gridDim.x * gridDim.y;
     if (threadIdx.x == 0) {
         const float bm = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
-        a.partial[blockIdx.y * gridDim.x + blockIdx.x] = bm;
-        __threadfence();
-        const unsigned prev = atomicAdd(a.counter, 1u);
-        is_last = (prev == (unsigned)nblk - 1u);
-    }
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        float m = 0.f;
-        for (int k = threadIdx.x; k < nblk; k += 256)
-            m = fmaxf(m, __hip_atomic_load(&a.partial[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        m = wave_max(m);
-        if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const float bm = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
-            *a.at = fmaxf(bm, 1e-12f);
-            *a.counter = 0u;
-        }
+        atomicMax((unsigned int*)a.at, __float_as_uint(bm));
+        if (a.at_clear && blockIdx.x == 0 && blockIdx.y == 0) *a.at_clear = 0.f;
     }
 }
 
@@ -171,6 +152,7 @@ __global__ __launch_bounds__(256) void level_init_kernel(LevelInitArgs a) {
 #pragma unroll
     for (int k = 0; k < 8; ++k)   // constant indices keep the argument block out of scratch
         if (k < a.nzero) a.zero[k][off] = 0.f;
+    if (a.clear_scalar && i == 0 && j == 0) *a.clear_scalar = 0.f;
 }
 
 __global__ __launch_bounds__(256) void upsample_kernel(const float* __restrict__ F, int Hc, int Wc, int64_t ldc,
@@ -202,8 +184,6 @@ __global__ __launch_bounds__(256) void copy2d_kernel(const float* __restrict__ s
 }
 
 }  // namespace
-
-int linearize_blocks(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
 
 void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s) {
     const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;

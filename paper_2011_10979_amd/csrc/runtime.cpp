@@ -235,18 +235,15 @@ void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s) {
     launch_pdr_final(a, hw, s);
 }
 
-// Final ADMM state index of a level after `n` iterations starting from buffer 0.
-int admm_final_buf(int64_t n) { return (int)(n & 1); }
-
-// Flow component k (0 = w, 1 = u, 2 = v) of a level after its warps: pDR keeps X; the ADMM family
-// keeps the committed flow in U0 and w in its state.
-const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int64_t iters_done) {
+// Flow component k (0 = w, 1 = u, 2 = v) of a level: pDR keeps X; the ADMM family keeps the
+// committed flow in U0 and w in its current state buffer `cur`.
+const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur) {
     if (p.scheme == FLOW_PDR) return L.X[k];
     if (k > 0) return L.U0[k - 1];
-    return L.st[admm_final_buf(iters_done)][0];
+    return L.st[cur][0];
 }
 
-EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int64_t iters_done, Scratch& sc) {
+EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc) {
     EnergyArgs e{};
     if (p.scheme == FLOW_PDR) {
         e.w = L.X[0]; e.u = L.X[1]; e.v = L.X[2];
@@ -256,7 +253,7 @@ EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int64_t iters
         e.lu0 = L.U0[0]; e.lv0 = L.U0[1];
     } else {
         // before the warp's commit: flow = U0 + increment
-        float* const* st = L.st[admm_final_buf(iters_done)];
+        float* const* st = L.st[cur];
         e.w = st[0]; e.u = L.U0[0]; e.v = L.U0[1]; e.du = st[1]; e.dv = st[2];
         e.px = st[3]; e.py = st[4]; e.q1x = st[5]; e.q1y = st[6]; e.q2x = st[7]; e.q2y = st[8]; e.s = st[9];
         e.pdr_tau = 0.f;
@@ -264,14 +261,80 @@ EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int64_t iters
     e.Ix = L.Ix; e.Iy = L.Iy; e.It = L.It;
     e.H = L.H; e.W = L.W; e.ld = L.ld;
     e.lam = (float)p.lambda; e.beta = (float)p.beta;
-    e.partial = sc.e_partial; e.counter = sc.e_counter; e.out = sc.e_out;
+    e.partial = sc.e_partial; e.out = sc.e_out;
     return e;
+}
+
+// Tile plan of every level plus the device tables the tile kernel reads (ADMM family only).
+flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
+                      const std::map<std::string, TunedChoice>* tuned) {
+    out.levels.clear();
+    if (p.scheme == FLOW_PDR) return FLOW_OK;
+    const bool hw = p.beta > 0;
+    std::vector<TbTile> tiles;
+    std::vector<TbLevel> descs(2 * Ls.size());
+    for (size_t l = 0; l < Ls.size(); ++l) {
+        LevelTbPlan P = plan_level_tuned(Ls[l].H, Ls[l].W, hw, p.iters, tuned);
+        if (P.tb) {
+            P.tile_off = (int)tiles.size();
+            append_tiles(P, (int)l, Ls[l].H, Ls[l].W, tiles);
+            P.ntiles = (int)tiles.size() - P.tile_off;
+        }
+        fill_tb_level(&descs[2 * l], Ls[l], sc.at);
+        out.levels.push_back(P);
+    }
+    out.tables.reset(new TbTables());
+    return out.tables->upload(tiles, descs);
+}
+
+TbArgs tb_args(const SolvePlan& plan, const LevelTbPlan& P, const LevelPlanes& L, const flow_params& p, int cur,
+               int K, int at_slot, const float* at2) {
+    AdmmIterArgs co{};
+    fill_admm_coeffs(co, p);
+    TbArgs a{};
+    (void)plan;
+    a.ntiles = P.ntiles;
+    a.dir = cur;
+    a.K = K;
+    a.at_slot = at_slot;
+    a.queue = nullptr;                 // one level per launch: direct mode
+    a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
+    a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
+    TbLevel d[2];
+    fill_tb_level(d, L, at2);
+    a.lvl = d[cur];
+    a.th = P.th;
+    a.tw = P.tw;
+    a.ntx = (L.W + P.tw - 1) / P.tw;
+    return a;
+}
+
+// `n` ADMM-family iterations of level L starting from state buffer `cur`, with the kernel choice
+// of plan P (nullptr: one-pass kernel, strip height rows_hint); returns the buffer holding the result.
+int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
+                       int64_t n, int at_slot, const float* at2, hipStream_t s) {
+    const bool hw = p.beta > 0;
+    int64_t t = 0;
+    while (t < n) {
+        if (P) {
+            const int kk = (int)std::min<int64_t>(P->resident ? n - t : P->K, n - t);
+            launch_admm_tb(tb_args(SolvePlan(), *P, L, p, cur, kk, at_slot, at2), hw, P->nt, P->ntiles, s);
+            t += kk;
+        } else {
+            AdmmIterArgs ai = admm_args(L, cur, p, at2 + at_slot);
+            ai.rows = rows_hint;
+            launch_admm_iter(ai, hw, s);
+            t += 1;
+        }
+        cur ^= 1;
+    }
+    return cur;
 }
 
 // Everything after the level-0 frames are in the pyramid: pyramid, levels, warps, iterations,
 // final energy.  `timers` (may be null) receives events around each warp's iteration block.
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
-                         WarpTimers* timers, StopTest* stop) {
+                         WarpTimers* timers, StopTest* stop, const SolvePlan* plan) {
     const bool f16 = p.storage == FLOW_STORE_F16;
     const bool pdr = p.scheme == FLOW_PDR;
     const bool hw = p.beta > 0;
@@ -285,17 +348,20 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
         }
         launch_derivatives(L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, f16, s);
     }
-    int64_t done_coarse = 0;
+    int cur_coarse = 0;
     for (int l = nl - 1; l >= 0; --l) {
         LevelPlanes& L = Ls[l];
+        const LevelTbPlan* P = (plan && !pdr && l < (int)plan->levels.size() && plan->levels[l].tb)
+                                   ? &plan->levels[l] : nullptr;
+        const int rows_hint = (plan && !pdr && l < (int)plan->levels.size()) ? plan->levels[l].rows : 0;
         // level start: upsample flow from level l+1 (or zero), clear duals
         LevelInitArgs ia{};
         ia.H = L.H; ia.W = L.W; ia.ld = L.ld;
         if (l < nl - 1) {
             const LevelPlanes& C = Ls[l + 1];
-            ia.uc = level_flow(C, p, 1, done_coarse);
-            ia.vc = level_flow(C, p, 2, done_coarse);
-            ia.wc = hw ? level_flow(C, p, 0, done_coarse) : nullptr;
+            ia.uc = level_flow(C, p, 1, cur_coarse);
+            ia.vc = level_flow(C, p, 2, cur_coarse);
+            ia.wc = hw ? level_flow(C, p, 0, cur_coarse) : nullptr;
             ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
         }
         if (!pdr) {
@@ -319,24 +385,26 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             ia.zero[nz++] = L.s_out;
             ia.nzero = nz;
         }
+        ia.clear_scalar = sc.at;     // a~ slot of the level's first warp
         launch_level_init(ia, s);
 
-        int64_t done = 0;
+        int cur = 0;                 // ADMM: state buffer holding the current iterate
         for (int wp = 0; wp < p.warps; ++wp) {
             // warp start: linearise around the current flow with I_t relative to it; the ADMM
             // increment (du, dv) restarts at zero, pDR keeps a copy of the linearisation point
             LinArgs la{};
             la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
-            la.u0 = level_flow(L, p, 1, done);
-            la.v0 = level_flow(L, p, 2, done);
+            la.u0 = level_flow(L, p, 1, cur);
+            la.v0 = level_flow(L, p, 2, cur);
             la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
-            la.at = sc.at; la.partial = sc.lin_partial; la.counter = sc.lin_counter;
+            la.at = sc.at + (wp & 1);
+            la.at_clear = sc.at + ((wp + 1) & 1);
             la.H = L.H; la.W = L.W; la.ld = L.ld;
             la.kappa = (float)p.intensity_scale; la.beta = (float)p.beta;
             la.rel = 1;
             if (!pdr) {
-                la.zero_u = L.st[admm_final_buf(done)][1];
-                la.zero_v = L.st[admm_final_buf(done)][2];
+                la.zero_u = L.st[cur][1];
+                la.zero_v = L.st[cur][2];
             } else {
                 la.keep_u = L.U0[0];
                 la.keep_v = L.U0[1];
@@ -347,15 +415,15 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             while (k < p.iters) {
                 int64_t chunk = p.iters - k;
                 if (stop && p.tol > 0) chunk = std::min<int64_t>(chunk, p.check_every);
-                for (int64_t t = 0; t < chunk; ++t) {
-                    if (!pdr) launch_admm_iter(admm_args(L, admm_final_buf(done), p, sc.at), hw, s);
-                    else enqueue_pdr_iter(pdr_args(L, p), p.gs_sweeps, hw, s);
-                    ++done;
+                if (pdr) {
+                    for (int64_t t = 0; t < chunk; ++t) enqueue_pdr_iter(pdr_args(L, p), p.gs_sweeps, hw, s);
+                } else {
+                    cur = enqueue_admm_iters(L, p, P, rows_hint, cur, chunk, wp & 1, sc.at, s);
                 }
                 k += chunk;
                 if (timers) timers->count(l, chunk);
                 if (stop && p.tol > 0 && k < p.iters) {
-                    launch_energy(energy_args(L, p, done, sc), s);
+                    launch_energy(energy_args(L, p, cur, sc), s);
                     bool converged = false;
                     flow_status st = stop->check(sc, s, &converged);
                     if (st != FLOW_OK) return st;
@@ -364,14 +432,11 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             }
             if (timers) timers->end(l, s);
             const bool last = l == 0 && wp == p.warps - 1;
-            if (last) launch_energy(energy_args(L, p, done, sc), s);
-            if (!pdr) {
-                const int f = admm_final_buf(done);
-                launch_commit(L.U0[0], L.U0[1], L.st[f][1], L.st[f][2], L.H, L.W, L.ld, s);
-            }
+            if (last) launch_energy(energy_args(L, p, cur, sc), s);
+            if (!pdr) launch_commit(L.U0[0], L.U0[1], L.st[cur][1], L.st[cur][2], L.H, L.W, L.ld, s);
         }
-        done_coarse = done;
-        if (l == 0) sc.final_iters = done;
+        cur_coarse = cur;
+        if (l == 0) sc.final_buf = cur;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -417,6 +482,17 @@ flow_status flow_tune_set(const char* key, int64_t value) {
     if (std::strcmp(key, "admm_rows") == 0) {
         if (value != 0 && value != 2 && value != 4 && value != 8) return fail(FLOW_E_INVAL, "admm_rows: 0, 2, 4 or 8");
         g_admm_rows_override = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "tb_mode") == 0) {
+        if (value < 0 || value > 4)
+            return fail(FLOW_E_INVAL, "tb_mode: 0 built-in, 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 small tiles/1024");
+        g_tb_mode = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "tb_k") == 0) {
+        if (value < 0 || value > 64) return fail(FLOW_E_INVAL, "tb_k: 0 (default) .. 64");
+        g_tb_k = (int)value;
         return FLOW_OK;
     }
     return fail(FLOW_E_INVAL, std::string("unknown tuning key ") + key);
@@ -521,12 +597,10 @@ flow_status flow_op_linearize(const float* I0, const float* I1, const float* DxI
     EXTENT(DyI1, H, W, ld, "DyI1"); EXTENT(u0, H, W, ld, "u0"); EXTENT(v0, H, W, ld, "v0");
     EXTENT(Ix, H, W, ld, "Ix"); EXTENT(Iy, H, W, ld, "Iy"); EXTENT(It, H, W, ld, "It");
     EXTENT(at_out, 1, 1, 1, "at_out");
-    OpScratch& os = op_scratch();
-    flow_status st = os.ensure_lin(linearize_blocks(H, W));
-    if (st != FLOW_OK) return st;
+    HIP_TRY(hipMemsetAsync(at_out, 0, sizeof(float), (hipStream_t)stream));
     LinArgs a{};
     a.I0 = I0; a.I1 = I1; a.Dx = DxI1; a.Dy = DyI1; a.u0 = u0; a.v0 = v0;
-    a.Ix = Ix; a.Iy = Iy; a.It = It; a.at = at_out; a.partial = os.lin_partial; a.counter = os.lin_counter;
+    a.Ix = Ix; a.Iy = Iy; a.It = It; a.at = at_out;
     a.H = H; a.W = W; a.ld = ld; a.kappa = (float)kappa; a.beta = (float)beta;
     launch_linearize(a, false, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
@@ -587,6 +661,78 @@ flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* 
     return FLOW_OK;
 }
 
+flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* out, const float* Ix, const float* Iy,
+                            const float* It, const float* at, int32_t H, int32_t W, int64_t ld, const flow_params* p,
+                            int32_t iters, int32_t threads, int32_t tile_h, int32_t tile_w, int32_t use_queue,
+                            void* stream) {
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    if (p->scheme == FLOW_PDR) return fail(FLOW_E_INVAL, "flow_op_admm_tb needs an ADMM scheme");
+    if (!in || !out || !Ix || !Iy || !It || !at) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (!in->u0 || !in->v0) return fail(FLOW_E_INVAL, "the tile kernel runs the increment form: u0, v0 required");
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    if (threads != 256 && threads != 1024 && threads != 1025)
+        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or 1025 (1024 threads, small tiles)");
+    if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
+    const bool hw = p->beta > 0;
+    const int cap = tb_capacity(hw, threads);
+    if ((int64_t)std::min<int64_t>(H, (int64_t)tile_h + 3 * iters) * std::min<int64_t>(W, (int64_t)tile_w + 3 * iters) > cap)
+        return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
+    const float* ins[10] = {in->w, in->u, in->v, in->px, in->py, in->q1x, in->q1y, in->q2x, in->q2y, in->s};
+    float* outs[10] = {out->w, out->u, out->v, out->px, out->py, out->q1x, out->q1y, out->q2x, out->q2y, out->s};
+    for (int k = 0; k < 10; ++k) {
+        const bool wk = k == 0 || k == 3 || k == 4;
+        if (wk && !hw) continue;
+        if (!ins[k] || !outs[k] || ins[k] == outs[k]) return fail(FLOW_E_INVAL, "bad state plane");
+        EXTENT(ins[k], H, W, ld, "state in");
+        EXTENT(outs[k], H, W, ld, "state out");
+    }
+    EXTENT(Ix, H, W, ld, "Ix"); EXTENT(Iy, H, W, ld, "Iy"); EXTENT(It, H, W, ld, "It");
+    EXTENT(in->u0, H, W, ld, "u0"); EXTENT(in->v0, H, W, ld, "v0"); EXTENT(at, 1, 1, 1, "at");
+    LevelTbPlan P;
+    P.tb = true;
+    P.nt = threads;
+    P.K = iters;
+    P.th = tile_h;
+    P.tw = tile_w;
+    std::vector<TbTile> tiles;
+    append_tiles(P, 0, H, W, tiles);
+    P.ntiles = (int)tiles.size();
+    std::vector<TbLevel> descs(2);
+    for (int k = 0; k < 10; ++k) {
+        descs[0].in[k] = ins[k];
+        descs[0].out[k] = outs[k];
+    }
+    descs[0].Ix = Ix; descs[0].Iy = Iy; descs[0].It = It; descs[0].u0 = in->u0; descs[0].v0 = in->v0;
+    descs[0].at = at; descs[0].H = H; descs[0].W = W; descs[0].ld = ld;
+    descs[1] = descs[0];
+    TbTables tab;
+    st = tab.upload(tiles, descs);
+    if (st != FLOW_OK) return st;
+    unsigned* q = nullptr;
+    HIP_TRY(hipMalloc(&q, 256));
+    hipStream_t s = (hipStream_t)stream;
+    launch_reset_u32(q, 1, s);
+    AdmmIterArgs co{};
+    fill_admm_coeffs(co, *p);
+    TbArgs a{};
+    a.tiles = tab.d_tiles; a.ntiles = P.ntiles; a.levels = tab.d_levels; a.dir = 0; a.K = iters; a.at_slot = 0;
+    a.queue = use_queue ? q : nullptr; a.queue_base = 0;
+    a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
+    a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
+    a.lvl = descs[0];
+    a.th = tile_h;
+    a.tw = tile_w;
+    a.ntx = (W + tile_w - 1) / tile_w;
+    launch_admm_tb(a, hw, threads, use_queue ? tb_grid(P, P.ntiles) : P.ntiles, s);
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(q);
+    if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "tile kernel");
+    return FLOW_OK;
+}
+
 flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work1, float* work2, float* s_out,
                              const float* Ix, const float* Iy, const float* It, int32_t H, int32_t W, int64_t ld,
                              const flow_params* p, void* stream) {
@@ -637,14 +783,14 @@ flow_status flow_op_energy(const flow_admm_state* st, const float* Ix, const flo
         }
     }
     OpScratch& os = op_scratch();
-    flow_status s2 = os.ensure_lin(1);
+    flow_status s2 = os.ensure();
     if (s2 != FLOW_OK) return s2;
     EnergyArgs e{};
     e.w = st->w; e.u = st->u; e.v = st->v; e.px = st->px; e.py = st->py;
     e.q1x = st->q1x; e.q1y = st->q1y; e.q2x = st->q2x; e.q2y = st->q2y; e.s = st->s;
     e.Ix = Ix; e.Iy = Iy; e.It = It; e.H = H; e.W = W; e.ld = ld;
     e.lam = (float)lambda; e.beta = (float)beta; e.pdr_tau = 0.f;
-    e.partial = os.e_partial; e.counter = os.e_counter; e.out = os.e_out;
+    e.partial = os.e_partial; e.out = os.e_out;
     hipStream_t s = (hipStream_t)stream;
     launch_energy(e, s);
     HIP_TRY(hipGetLastError());

@@ -40,15 +40,12 @@ struct LevelPlanes {
 
 // Small device buffers used by the reductions of one solve stream.
 struct Scratch {
-    float* at = nullptr;
-    float* lin_partial = nullptr;
-    unsigned* lin_counter = nullptr;
-    int lin_cap = 0;
+    float* at = nullptr;              // two a~ slots: warp w of a level uses slot w % 2
     double* e_partial = nullptr;
-    unsigned* e_counter = nullptr;
     double* e_out = nullptr;
-    int64_t final_iters = 0;
-    flow_status alloc(int lin_blocks);
+    unsigned* queue = nullptr;        // work counter of the tile kernel (reset at the start of a solve)
+    int final_buf = 0;
+    flow_status alloc();
     void release();
     size_t bytes() const;
 };
@@ -75,31 +72,75 @@ struct StopTest {
     flow_status check(Scratch& sc, hipStream_t s, bool* converged);
 };
 
+struct SolvePlan;
 size_t layout_bytes(int H, int W, const flow_params& p);
 flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, std::vector<LevelPlanes>& out);
 void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p);
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
-                         WarpTimers* timers, StopTest* stop);
-const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int64_t iters_done);
+                         WarpTimers* timers, StopTest* stop, const SolvePlan* plan);
+const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur);
 void fill_result(const double* h, flow_result* r);
-std::string graph_key(int H, int W, const flow_params& p, const void* arena);
+std::string graph_key(int H, int W, const flow_params& p, const void* arena, int tune_epoch);
 
 // Lazily allocated buffers for the operator-level entry points (per device, process lifetime).
 struct OpScratch {
-    float* lin_partial = nullptr;
-    unsigned* lin_counter = nullptr;
-    int lin_cap = 0;
     double* e_partial = nullptr;
-    unsigned* e_counter = nullptr;
     double* e_out = nullptr;
-    flow_status ensure_lin(int blocks);
+    flow_status ensure();
 };
 OpScratch& op_scratch();
+
+// Per-level choice between the one-pass kernel and K-iteration tiles.
+struct LevelTbPlan {
+    bool tb = false;           // false: one launch of the one-pass kernel per iteration
+    bool resident = false;     // one tile covers the level: all iterations of a warp in one launch
+    int nt = 256;              // work-group size of the tile kernel
+    int K = 1;                 // iterations per launch
+    int th = 0, tw = 0;        // output tile
+    int tile_off = 0, ntiles = 0;
+    int rows = 0;              // one-pass kernel strip height (0 = built-in)
+};
+// Autotuned kernel choice of one level shape (see flow_autotune).
+struct TunedChoice {
+    int mode = 0;              // 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 small tiles/1024
+    int K = 0, rows = 0;
+    double us_per_iter = 0;
+};
+std::string tune_key(int H, int W, bool hw, int iters);
+extern int g_tb_mode;
+extern int g_tb_k;
+LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq);
+LevelTbPlan plan_level_tuned(int H, int W, bool hw, int iters, const std::map<std::string, TunedChoice>* tuned);
+void append_tiles(const LevelTbPlan& P, int level_id, int H, int W, std::vector<TbTile>& out);
+void fill_tb_level(TbLevel* d, const LevelPlanes& L, const float* at2);
+int tb_grid(const LevelTbPlan& P, int ntiles);
+
+struct TbTables {
+    TbTile* d_tiles = nullptr;
+    TbLevel* d_levels = nullptr;
+    size_t bytes = 0;
+    flow_status upload(const std::vector<TbTile>& tiles, const std::vector<TbLevel>& levels);
+    void release();
+    ~TbTables() { release(); }
+};
+
+// Iteration plan of one solve shape: a plan per level and the device tables of the tile kernel.
+struct SolvePlan {
+    std::vector<LevelTbPlan> levels;
+    std::unique_ptr<TbTables> tables;
+};
+
+flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
+                      const std::map<std::string, TunedChoice>* tuned);
+int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
+                       int64_t n, int at_slot, const float* at2, hipStream_t s);
+TbArgs tb_args(const SolvePlan& plan, const LevelTbPlan& P, const LevelPlanes& L, const flow_params& p, int cur,
+               int K, int at_slot, const float* at2);
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int64_t final_iters = 0;
+    int final_buf = 0;
 };
 
 struct BatchState;   // batch.cpp
@@ -115,6 +156,10 @@ struct flow_ctx {
     double* host_out = nullptr;           // pinned
     hipStream_t cap_stream = nullptr;
     std::map<std::string, flowmi::GraphEntry> graphs;
+    std::map<std::string, std::unique_ptr<flowmi::SolvePlan>> plans;
+    std::map<std::string, flowmi::TunedChoice> tuned;     // per level shape, from flow_autotune
+    int tune_epoch = 0;
+    std::string tune_report;                             // JSON of the last flow_autotune
     bool stats_enabled = false;
     flow_stats last_stats{};
     flowmi::WarpTimers timers;

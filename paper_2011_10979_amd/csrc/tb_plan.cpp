@@ -1,0 +1,147 @@
+// Planning of temporally blocked iterations: per level, whether the fused one-pass kernel or the
+// K-iteration tile kernel runs, with which work-group size, K and output tile; and the device
+// tables (tiles, level descriptors) the tile kernel reads.
+#include <algorithm>
+#include <cstring>
+
+#include "runtime.hpp"
+
+namespace flowmi {
+
+int g_tb_mode = 0;   // 0 built-in, 1 one-pass only, 2 tiles of 256 threads, 3 of 1024, 4 of 1024 (small)
+int g_tb_k = 0;      // iterations per launch of tiled levels (0 = default)
+
+constexpr int kDefaultK = 4;
+
+static bool fit_tile(int H, int W, int cap, int K, int ew_target, int& th, int& tw) {
+    // output tile th x tw whose extended region (halo 2K + K per axis, clipped to the image) fits
+    const int ew = std::min(W, ew_target);
+    tw = (ew >= W) ? W : ew - 3 * K;
+    const int ext_w = std::min(W, tw + 3 * K);
+    int eh = cap / ext_w;
+    th = (eh >= H) ? H : eh - 3 * K;
+    return tw >= 8 && th >= 2 && (int64_t)std::min(W, tw + 3 * K) * std::min(H, th + 3 * K) <= cap;
+}
+
+LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
+    LevelTbPlan P;
+    if (mode == 1 || iters < 2) return P;                    // one-pass kernel
+    if (mode == 0) {
+        // built-in choice: a level that fits one 1024-thread tile stays resident for a whole warp
+        // (one launch instead of `iters`); larger levels use the one-pass kernel
+        if ((int64_t)H * W <= tb_capacity(hw, 1024)) {
+            P.tb = P.resident = true;
+            P.nt = 1024;
+            P.K = iters;
+            P.th = H;
+            P.tw = W;
+        }
+        return P;
+    }
+    const int nt = (mode == 3) ? 1024 : (mode == 4 ? 1025 : 256);
+    const int cap = tb_capacity(hw, nt);
+    if ((int64_t)H * W <= cap) {                             // the whole level stays resident
+        P.tb = true;
+        P.nt = nt;
+        P.resident = true;
+        P.K = iters;
+        P.th = H;
+        P.tw = W;
+        return P;
+    }
+    int K = kreq > 0 ? kreq : kDefaultK;
+    const int ew_target = nt == 1024 ? (hw ? 80 : 96) : (nt == 1025 ? 64 : (hw ? 32 : 48));
+    int th = 0, tw = 0;
+    while (K > 0 && !fit_tile(H, W, cap, K, ew_target, th, tw)) --K;
+    if (K < 1) return P;
+    P.tb = true;
+    P.nt = nt;
+    P.K = K;
+    P.th = th;
+    P.tw = tw;
+    return P;
+}
+
+std::string tune_key(int H, int W, bool hw, int iters) {
+    return std::to_string(H) + "x" + std::to_string(W) + (hw ? "w" : "") + "i" + std::to_string(iters);
+}
+
+LevelTbPlan plan_level_tuned(int H, int W, bool hw, int iters, const std::map<std::string, TunedChoice>* tuned) {
+    if (g_tb_mode == 0 && tuned) {
+        auto it = tuned->find(tune_key(H, W, hw, iters));
+        if (it != tuned->end()) {
+            LevelTbPlan P = plan_level(H, W, hw, iters, it->second.mode, it->second.K);
+            P.rows = it->second.rows;
+            return P;
+        }
+    }
+    return plan_level(H, W, hw, iters, g_tb_mode, g_tb_k);
+}
+
+void append_tiles(const LevelTbPlan& P, int level_id, int H, int W, std::vector<TbTile>& out) {
+    for (int y = 0; y < H; y += P.th)
+        for (int x = 0; x < W; x += P.tw) {
+            TbTile t;
+            t.level = level_id;
+            t.y0 = y;
+            t.x0 = x;
+            t.th = std::min(P.th, H - y);
+            t.tw = std::min(P.tw, W - x);
+            out.push_back(t);
+        }
+}
+
+void fill_tb_level(TbLevel* d, const LevelPlanes& L, const float* at2) {
+    for (int dir = 0; dir < 2; ++dir) {
+        TbLevel& x = d[dir];
+        std::memset(&x, 0, sizeof(x));
+        for (int k = 0; k < 10; ++k) {
+            x.in[k] = L.st[dir][k];
+            x.out[k] = L.st[dir ^ 1][k];
+        }
+        x.Ix = L.Ix;
+        x.Iy = L.Iy;
+        x.It = L.It;
+        x.u0 = L.U0[0];
+        x.v0 = L.U0[1];
+        x.at = at2;
+        x.H = L.H;
+        x.W = L.W;
+        x.ld = L.ld;
+    }
+}
+
+int tb_grid(const LevelTbPlan& P, int ntiles) {
+    const int per_cu = P.nt == 1024 ? 1 : (P.nt == 1025 ? 2 : 4);   // LDS / thread-limited residency
+    return std::max(1, std::min(ntiles, 256 * per_cu));
+}
+
+flow_status TbTables::upload(const std::vector<TbTile>& tiles, const std::vector<TbLevel>& levels) {
+    release();
+    const size_t bt = sizeof(TbTile) * std::max<size_t>(1, tiles.size());
+    const size_t bl = sizeof(TbLevel) * std::max<size_t>(1, levels.size());
+    hipError_t e = hipMalloc(&d_tiles, bt);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(tiles)");
+    e = hipMalloc(&d_levels, bl);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(levels)");
+    if (!tiles.empty()) {
+        e = hipMemcpy(d_tiles, tiles.data(), sizeof(TbTile) * tiles.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(tiles)");
+    }
+    if (!levels.empty()) {
+        e = hipMemcpy(d_levels, levels.data(), sizeof(TbLevel) * levels.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(levels)");
+    }
+    bytes = bt + bl;
+    return FLOW_OK;
+}
+
+void TbTables::release() {
+    if (d_tiles) hipFree(d_tiles);
+    if (d_levels) hipFree(d_levels);
+    d_tiles = nullptr;
+    d_levels = nullptr;
+    bytes = 0;
+}
+
+}  // namespace flowmi

@@ -188,3 +188,34 @@ def test_error_paths(ctx):
     with pytest.raises(fm.FlowError) as e:
         ctx.solve(bad, I1, fm.Params(levels=1, warps=1, iters=5, use_graph=0))
     assert e.value.status == fm.FLOW_E_NONFINITE
+
+
+def test_autotuned_solve_keeps_parity():
+    """The autotuner only changes which kernel runs each level (speed); the tuned solve still meets
+    the oracle bar, and the report names one choice per level shape."""
+    print("[case] autotuned multilevel", flush=True)
+    c = fm.Context(0)
+    try:
+        rep = c.autotune(96, 128, fm.Params(levels=3, warps=3, iters=40))
+        assert len(rep) == 3
+        for key, entry in rep.items():
+            assert entry["choice"]["mode"] in (1, 2, 3, 4) and entry["choice"]["us_per_iter"] > 0
+            assert len(entry["candidates"]) >= 4
+        pair = synth.vga_pair(seed=5, H=96, W=128)
+        conditioned_check(c, pair, "autotuned 96x128", levels=3, warps=3, iters=40)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8)])
+def test_every_kernel_mode_keeps_parity(ctx, mode, k):
+    """Each forced kernel choice (one-pass; tiles of 256 / 1024 / small 1024 threads) meets the bar."""
+    print(f"[case] forced mode {mode} K {k}", flush=True)
+    fm.set_tuning("tb_mode", mode)
+    fm.set_tuning("tb_k", k)
+    try:
+        pair = synth.vga_pair(seed=6, H=120, W=150)
+        conditioned_check(ctx, pair, f"mode {mode} K {k}", levels=3, warps=2, iters=30)
+    finally:
+        fm.set_tuning("tb_mode", 0)
+        fm.set_tuning("tb_k", 0)
