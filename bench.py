@@ -7,13 +7,22 @@ whole solve (pyramid, warps, iterations, energy / gap) with the frames already r
 the solve is replayed from a hipGraph.  value = pixel-iterations of a step / step time.
 
 Also reported on the same JSON line:
-  roofline      the ADMM iteration kernels (the dominant kernels; the autotuner picks one-pass or
-                K-iteration tiles per level): 76 algorithmic bytes per pixel per launch (12 FP32
-                planes read, 7 written) x pixels x launches / their time, timed with HIP events
-                around each warp's iteration block during instrumented solves, against the 8 TB/s
-                HBM peak; one_pass_equivalent_GBs counts 76 B per pixel-iteration instead
-  cpu_baseline  the FP64 NumPy oracle on a bounded sample of the same workload, one core
+  roofline      the dominant kernel: the ADMM iteration kernel of the finest level (about three
+                quarters of all pixel-iterations; the autotuner picks one-pass or K-iteration tiles
+                per level).  Algorithmic bytes of one launch = 76 B per pixel (12 FP32 planes read,
+                7 written, once per launch whatever K it advances) x the level's pixels; launch
+                duration from HIP events on the solve stream around each warp's block of iteration
+                launches, averaged over instrumented solves; peak = 8 TB/s HBM.  traffic = HBM bytes
+                per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated against a
+                plain copy), when they were taken on the current kernel source, else null.
+  cpu_baseline  the FP64 NumPy oracle on the same workload (solved twice, about 10-15 s), one core
   per_level     Gpixel-iter/s of each level's iteration blocks
+
+Other modes:
+  --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
+                                      them from F instead of tuning (for profiler runs)
+  --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
+                                      kernel for the HBM counter calibration) and exit
 """
 from __future__ import annotations
 
@@ -29,12 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # FP32 planes read + written per pixel by one launch of an iteration kernel (increment form):
 # reads du, dv, s, q1x, q1y, q2x, q2y, I_x, I_y, I_t, u0, v0 (+ w, px, py); writes the 7 (10) state planes
 BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
-BYTES_PER_PX_ITER_ONEPASS = BYTES_PER_PX_LAUNCH   # one launch = one iteration for the one-pass kernel
 
 
 def kernel_sha():
     h = hashlib.sha256()
-    for f in ("admm.hip", "admm_tb.hip", "kernels.hpp"):
+    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp"):
         with open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -56,22 +64,43 @@ def measured_traffic(workload):
 
 def cpu_baseline(pair, args):
     """Time the oracle on a bounded sample of the workload: the full pyramid and warps with
-    `cpu_iters` iterations per warp instead of 50."""
+    `cpu_iters` iterations per warp (default: all of them), solved `cpu_reps` times."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import numpy as np
     from oracle import Params, solve_pair
     from oracle.pyramid import level_shapes
     I0 = pair.I0.astype(np.float32).astype(np.float64)
     I1 = pair.I1.astype(np.float32).astype(np.float64)
-    p = Params(scheme=args.scheme, levels=args.levels, warps=args.warps, iters=args.cpu_iters)
+    iters = args.cpu_iters or args.iters
+    p = Params(scheme=args.scheme, levels=args.levels, warps=args.warps, iters=iters)
     t0 = time.perf_counter()
-    solve_pair(I0, I1, p)
+    for _ in range(args.cpu_reps):
+        solve_pair(I0, I1, p)
     dt = time.perf_counter() - t0
     px = sum(h * w for h, w in level_shapes(I0.shape[0], I0.shape[1], args.levels))
-    pxi = px * args.warps * args.cpu_iters
+    pxi = px * args.warps * iters * args.cpu_reps
     return {"value": pxi / dt / 1e9, "unit": "Gpixel-iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"{I0.shape[1]}x{I0.shape[0]}, {args.levels} levels x {args.warps} warps x "
-                      f"{args.cpu_iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
+            "sample": f"{args.cpu_reps} x the {I0.shape[1]}x{I0.shape[0]} solve, {args.levels} levels x {args.warps} "
+                      f"warps x {iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
+
+
+def calibrate_copy(mb, steps):
+    """Plain device-to-device copies of `mb` MiB: the kernel of known traffic (mb MiB read and mb
+    MiB written per launch) that scales the HBM counters."""
+    import torch
+    n = mb * (1 << 20) // 4
+    x = torch.ones(n, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps)):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(1, steps)
+    print(json.dumps({"copy_MiB": mb, "ms": round(dt * 1e3, 4), "GBs": round(2 * mb * (1 << 20) / dt / 1e9, 1)}),
+          flush=True)
 
 
 def main():
@@ -86,9 +115,13 @@ def main():
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--H", type=int, default=480)
     ap.add_argument("--W", type=int, default=640)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=0, help="iterations per warp of the oracle sample (0: all)")
+    ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--save-tuning", default=None)
+    ap.add_argument("--load-tuning", default=None)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -101,6 +134,10 @@ def main():
     import synth
     import paper_2011_10979_amd as fm
 
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy, args.steps)
+        return
+
     dev = torch.device("cuda:0")
     pair = synth.vga_pair(seed=1, H=args.H, W=args.W)
     I0 = torch.from_numpy(pair.I0.astype(np.float32)).to(dev)
@@ -111,10 +148,19 @@ def main():
     u = torch.empty_like(I0)
     v = torch.empty_like(I0)
     tuning = None
-    if not args.no_autotune:
+    if args.load_tuning:
+        with open(args.load_tuning) as fh:
+            tuning = json.load(fh)
+        for key, ch in tuning.items():
+            ctx.set_choice(key, ch["mode"], ch["K"], ch["rows"])
+        print(f"[bench] loaded tuning: {tuning}", file=sys.stderr, flush=True)
+    elif not args.no_autotune:
         # one-time choice of the iteration kernel per level shape (outside the timed region)
         tuning = {k: v_["choice"] for k, v_ in ctx.autotune(args.H, args.W, params).items()}
         print(f"[bench] autotuned: {tuning}", file=sys.stderr, flush=True)
+    if args.save_tuning and tuning is not None:
+        with open(args.save_tuning, "w") as fh:
+            json.dump(tuning, fh)
     for _ in range(args.warmup):
         ctx.solve(I0, I1, params, u=u, v=v)
     torch.cuda.synchronize()
@@ -146,56 +192,53 @@ def main():
     ctx.set_stats(True)
     p_inst = fm.Params(**{**params.__dict__, "use_graph": 0})
     lvl_ms = [0.0] * args.levels
-    lvl_launch = [0] * args.levels
+    lvl_iters = [0] * args.levels
     reps = 3
     for _ in range(reps):
         ctx.solve(I0, I1, p_inst, u=u, v=v)
         s = ctx.stats()
         for l in range(args.levels):
             lvl_ms[l] += s["iter_ms"][l]
-            lvl_launch[l] += s["iter_launches"][l]
+            lvl_iters[l] += s["iterations"][l]
     ctx.set_stats(False)
     per_level = []
     for l, (a, b) in enumerate(shapes):
-        gpx = a * b * lvl_launch[l] / (lvl_ms[l] * 1e-3) / 1e9 if lvl_ms[l] > 0 else None
+        gpx = a * b * lvl_iters[l] / (lvl_ms[l] * 1e-3) / 1e9 if lvl_ms[l] > 0 else None
         per_level.append({"level": l, "H": a, "W": b, "Gpx_iter_s": gpx,
-                          "us_per_iter": 1e3 * lvl_ms[l] / max(1, lvl_launch[l])})
+                          "us_per_iter": 1e3 * lvl_ms[l] / max(1, lvl_iters[l])})
 
     has_w = params.beta > 0
     roof = None
     if args.scheme in ("padmm", "rpadmm2"):
-        # Dominant kernel = the iteration kernel (one-pass or K-iteration tiles, per the tuning).
-        # Algorithmic bytes of one launch: the 12 (15 with the w / p block) FP32 planes it reads
-        # and the 7 (10) it writes, once per pixel of the level, whatever K the launch advances.
-        per_px = BYTES_PER_PX_LAUNCH[has_w]
-        tot_bytes = 0.0
-        tot_ms = 0.0
-        tot_launches = 0
-        tot_pxiter = 0.0
-        for l, (a, b) in enumerate(shapes):
+        # Dominant kernel: the iteration kernel of level 0.  Kernel launches per warp follow the
+        # level's choice: `iters` for the one-pass kernel, ceil(iters / K) for K-iteration tiles,
+        # one for a resident tile.
+        def launches_per_warp(l):
+            a, b = shapes[l]
             key = f"{a}x{b}{'w' if has_w else ''}i{args.iters}"
             ch = (tuning or {}).get(key, {"mode": 1, "K": 1})
             if ch["mode"] == 1:
-                per_warp = args.iters
-            elif ch["K"] == 0:
-                per_warp = 1                                   # resident: a warp in one launch
-            else:
-                per_warp = -(-args.iters // ch["K"])
-            n = per_warp * args.warps * reps
-            tot_launches += n
-            tot_bytes += per_px * a * b * n
-            tot_ms += lvl_ms[l]
-            tot_pxiter += a * b * lvl_launch[l]
-        launch_s = tot_ms * 1e-3 / max(1, tot_launches)
-        achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+                return args.iters, ch
+            if ch["K"] == 0:
+                return 1, ch
+            return -(-args.iters // ch["K"]), ch
+        per_px = BYTES_PER_PX_LAUNCH[has_w]
+        n0, ch0 = launches_per_warp(0)
+        n0 *= args.warps * reps
+        launch_s = lvl_ms[0] * 1e-3 / n0
+        bytes_launch = per_px * shapes[0][0] * shapes[0][1]
+        achieved = bytes_launch / launch_s / 1e9
         traffic = measured_traffic(f"{args.W}x{args.H}")
+        all_launches = sum(launches_per_warp(l)[0] for l in range(args.levels)) * args.warps
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "admm iteration kernels (tuned per level)",
-                "per_unit": f"{per_px} B per pixel per launch",
-                "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step": tot_launches // reps,
-                "one_pass_equivalent_GBs": round(BYTES_PER_PX_ITER_ONEPASS[has_w] * tot_pxiter
-                                                 / (tot_ms * 1e-3) / 1e9, 1)}
+                "kernel": f"ADMM iteration kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
+                "per_unit": f"{per_px} B per pixel per launch", "bytes_per_launch": bytes_launch,
+                "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step_level0": n0 // reps,
+                "iteration_launches_per_step": all_launches,
+                # the same pixel-iterations priced at one HBM pass per iteration (76 B per pixel-iteration)
+                "one_pass_equivalent_GBs": round(per_px * shapes[0][0] * shapes[0][1] * lvl_iters[0]
+                                                 / (lvl_ms[0] * 1e-3) / 1e9, 1)}
 
     cpu = None
     if not args.no_cpu_baseline:

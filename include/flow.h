@@ -96,8 +96,8 @@ typedef struct flow_result {
 typedef struct flow_stats {
     int32_t levels;
     int32_t H[FLOW_MAX_LEVELS], W[FLOW_MAX_LEVELS];
-    int64_t iter_launches[FLOW_MAX_LEVELS];   /* iteration kernel launches at this level */
-    double iter_ms[FLOW_MAX_LEVELS];          /* event time of those launches (includes gaps) */
+    int64_t iterations[FLOW_MAX_LEVELS];      /* inner iterations run at this level (all warps) */
+    double iter_ms[FLOW_MAX_LEVELS];          /* event time of their kernel launches (includes gaps) */
     double total_ms;                          /* event time of the whole solve on the device */
     int64_t px_iter;                          /* pixel-iterations of the solve */
     int32_t graph_replayed;                   /* 1 if the solve ran as a graph replay */
@@ -160,6 +160,14 @@ flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params
 /* JSON report of the last flow_autotune (choice and all measured candidates per level shape) into
  * buf (host, cap bytes including the terminating NUL); FLOW_E_INVAL if it does not fit. */
 flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
+
+/* Set the iteration-kernel choice of one level shape (H x W, with or without the w / p block, iters
+ * per warp) by hand, as flow_autotune would: mode 1 = one-pass kernel with `rows` rows per strip
+ * (0 = built-in), 2 / 3 / 4 = K-iteration tiles of 256 / 1024 / small 1024-thread work-groups with K
+ * iterations per launch (K = 0: resident if the level fits one tile, else the built-in K).  Lets a
+ * caller reuse a tuning measured in another process.  Drops the context's captured graphs. */
+flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t mode,
+                             int32_t K, int32_t rows);
 
 /* Enable (1) or disable (0) per-solve event timing; flow_get_stats returns the last solve's. */
 flow_status flow_set_stats(flow_ctx* ctx, int32_t enable);

@@ -43,7 +43,7 @@ class _Result(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("H", ctypes.c_int32 * MAX_LEVELS), ("W", ctypes.c_int32 * MAX_LEVELS),
-                ("iter_launches", ctypes.c_int64 * MAX_LEVELS), ("iter_ms", ctypes.c_double * MAX_LEVELS),
+                ("iterations", ctypes.c_int64 * MAX_LEVELS), ("iter_ms", ctypes.c_double * MAX_LEVELS),
                 ("total_ms", ctypes.c_double), ("px_iter", ctypes.c_int64), ("graph_replayed", ctypes.c_int32)]
 
 
@@ -67,7 +67,8 @@ _lib = None
 EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "flow_solve_batched",
            "flow_set_stats", "flow_get_stats", "flow_memory_in_use", "flow_last_error", "flow_op_downsample",
            "flow_op_derivatives", "flow_op_linearize", "flow_op_upsample", "flow_op_admm_iter", "flow_op_pdr_iter",
-           "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning"]
+           "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
+           "flow_tune_choice"]
 
 
 def lib():
@@ -87,6 +88,7 @@ def lib():
             "flow_set_stats": [vp, i32],
             "flow_autotune": [vp, i32, i32, ctypes.POINTER(_Params), vp],
             "flow_get_tuning": [vp, ctypes.c_char_p, ctypes.c_size_t],
+            "flow_tune_choice": [vp, i32, i32, i32, i32, i32, i32, i32],
             "flow_get_stats": [vp, ctypes.POINTER(_Stats)],
             "flow_memory_in_use": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "flow_op_downsample": [vp, i32, i32, i64, vp, i64, vp],
@@ -219,7 +221,7 @@ class Context:
         s = _Stats()
         _check(lib().flow_get_stats(self._h, ctypes.byref(s)))
         n = s.levels
-        return dict(levels=n, H=list(s.H[:n]), W=list(s.W[:n]), iter_launches=list(s.iter_launches[:n]),
+        return dict(levels=n, H=list(s.H[:n]), W=list(s.W[:n]), iterations=list(s.iterations[:n]),
                     iter_ms=list(s.iter_ms[:n]), total_ms=s.total_ms, px_iter=s.px_iter,
                     graph_replayed=bool(s.graph_replayed))
 
@@ -232,6 +234,15 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().flow_get_tuning(self._h, buf, len(buf)))
         return json.loads(buf.value.decode() or "{}")
+
+    def set_choice(self, key: str, mode: int, K: int = 0, rows: int = 0):
+        """Apply one level-shape choice of an autotune report (key "<H>x<W>[w]i<iters>") by hand."""
+        import re
+        m = re.fullmatch(r"(\d+)x(\d+)(w?)i(\d+)", key)
+        if not m:
+            raise ValueError(f"bad tuning key {key!r}")
+        H, W, hw, it = int(m.group(1)), int(m.group(2)), m.group(3) == "w", int(m.group(4))
+        _check(lib().flow_tune_choice(self._h, H, W, int(hw), it, int(mode), int(K), int(rows)))
 
     def memory_in_use(self):
         b = ctypes.c_size_t()

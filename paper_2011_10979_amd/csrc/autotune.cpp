@@ -132,3 +132,20 @@ extern "C" flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t ca
     std::memcpy(buf, r.c_str(), r.size() + 1);
     return FLOW_OK;
 }
+
+extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters,
+                                        int32_t mode, int32_t K, int32_t rows) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
+    if (mode < 1 || mode > 4) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass) or 2..4 (tiles)");
+    if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
+    if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
+    TunedChoice c;
+    c.mode = mode;
+    c.K = K;
+    c.rows = rows;
+    ctx->tuned[tune_key(H, W, has_w != 0, iters)] = c;
+    ctx->tune_epoch++;
+    ctx->drop_graphs();
+    return FLOW_OK;
+}

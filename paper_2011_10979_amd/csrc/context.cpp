@@ -226,8 +226,8 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
         for (int l = 0; l < S.levels; ++l) {
             S.H[l] = Ls[l].H;
             S.W[l] = Ls[l].W;
-            S.iter_launches[l] = replayed ? (int64_t)p.warps * p.iters : timers.launches[l];
-            pxi += (int64_t)Ls[l].H * Ls[l].W * S.iter_launches[l];
+            S.iterations[l] = replayed ? (int64_t)p.warps * p.iters : timers.launches[l];
+            pxi += (int64_t)Ls[l].H * Ls[l].W * S.iterations[l];
         }
         for (auto& pr : timers.pairs) {
             float ms = 0.f;

@@ -20,15 +20,15 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-__global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) {
+// Partial sums of work-group `blk` of `nblk` (grid-stride over the pixels) into a.partial[blk].
+__device__ __forceinline__ void energy_body(const EnergyArgs& a, int blk, int nblk) {
     double acc[kEnergyTerms];
 #pragma unroll
     for (int k = 0; k < kEnergyTerms; ++k) acc[k] = 0.0;
     const bool has_w = a.beta != 0.f;
     const int64_t npix = (int64_t)a.H * a.W;
     const float tau = a.pdr_tau;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < npix;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t idx = (int64_t)blk * 256 + threadIdx.x; idx < npix; idx += (int64_t)nblk * 256) {
         const int i = (int)(idx / a.W), j = (int)(idx % a.W);
         const int64_t o = (int64_t)i * a.ld + j;
         const bool hr = j < a.W - 1, hd = i < a.H - 1, hl = j > 0, hu = i > 0;
@@ -105,15 +105,17 @@ __global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) {
     __syncthreads();
     if (threadIdx.x < kEnergyTerms) {
         const int k = threadIdx.x;
-        a.partial[blockIdx.x * kEnergyTerms + k] = ((sm[0][k] + sm[1][k]) + sm[2][k]) + sm[3][k];
+        a.partial[blk * kEnergyTerms + k] = ((sm[0][k] + sm[1][k]) + sm[2][k]) + sm[3][k];
     }
 }
+
+__global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) { energy_body(a, blockIdx.x, gridDim.x); }
 
 // Sum of the per-block partials (a separate launch: the kernel boundary makes the partials
 // visible without any fence).  Thread t adds partials t, t + 256, ... in order, then a fixed
 // pairwise tree in LDS combines the 256 sums, so the result is reproducible bit for bit.
-__global__ __launch_bounds__(256) void energy_final_kernel(const double* __restrict__ partial, int nblocks,
-                                                          double* __restrict__ out) {
+__device__ __forceinline__ void energy_final_body(const double* __restrict__ partial, int nblocks,
+                                                  double* __restrict__ out) {
     __shared__ double sm[256];
     for (int k = 0; k < kEnergyTerms; ++k) {
         double t = 0.0;
@@ -129,15 +131,57 @@ __global__ __launch_bounds__(256) void energy_final_kernel(const double* __restr
     }
 }
 
+__global__ __launch_bounds__(256) void energy_final_kernel(const double* __restrict__ partial, int nblocks,
+                                                          double* __restrict__ out) {
+    energy_final_body(partial, nblocks, out);
+}
+
+// Batched: item k owns work-groups [off[k], off[k+1]) of the first kernel (as many as its own
+// single launch would use, so each pair's sums are formed in the same order as in a plain solve)
+// and work-group k of the second.
+__device__ __forceinline__ int find_item_e(const int* __restrict__ off, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void energy_batched_kernel(const EnergyArgs* __restrict__ items,
+                                                            const int* __restrict__ off, int n) {
+    const int k = find_item_e(off, n, blockIdx.x);
+    const EnergyArgs a = items[k];
+    energy_body(a, blockIdx.x - off[k], off[k + 1] - off[k]);
+}
+
+__global__ __launch_bounds__(256) void energy_final_batched_kernel(const EnergyArgs* __restrict__ items,
+                                                                  const int* __restrict__ off) {
+    const int k = blockIdx.x;
+    energy_final_body(items[k].partial, off[k + 1] - off[k], items[k].out);
+}
+
 }  // namespace
 
-void launch_energy(const EnergyArgs& a, hipStream_t s) {
-    const int64_t npix = (int64_t)a.H * a.W;
+int energy_blocks(int H, int W) {
+    const int64_t npix = (int64_t)H * W;
     int blocks = (int)((npix + 255) / 256);
     if (blocks > kEnergyBlocks) blocks = kEnergyBlocks;
     if (blocks < 1) blocks = 1;
+    return blocks;
+}
+
+void launch_energy(const EnergyArgs& a, hipStream_t s) {
+    const int blocks = energy_blocks(a.H, a.W);
     hipLaunchKernelGGL(energy_kernel, dim3(blocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(256), 0, s, (const double*)a.partial, blocks, a.out);
+}
+
+void launch_energy_batched(const EnergyArgs* items, const int* off, int n, int total_blocks, hipStream_t s) {
+    if (n <= 0 || total_blocks <= 0) return;
+    hipLaunchKernelGGL(energy_batched_kernel, dim3(total_blocks), dim3(256), 0, s, items, off, n);
+    hipLaunchKernelGGL(energy_final_batched_kernel, dim3(n), dim3(256), 0, s, items, off);
 }
 
 }  // namespace flowmi

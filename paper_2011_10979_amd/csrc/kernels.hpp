@@ -6,68 +6,11 @@
 #include <hip/hip_fp16.h>
 #include <cstdint>
 
+#include "admm_args.hpp"
+
 namespace flowmi {
 
-constexpr int kWave = 64;
-constexpr int kStrip = kWave - 3;   // output columns per wavefront in the streaming iteration kernels
-
-// One iteration of the ADMM family (rpADMMI / rpADMMII), fused into one pass.
-struct AdmmIterArgs {
-    const float *w, *u, *v, *px, *py, *q1x, *q1y, *q2x, *q2y, *s;   // iterate k
-    float *wo, *uo, *vo, *pxo, *pyo, *q1xo, *q1yo, *q2xo, *q2yo, *so; // iterate k + 1
-    const float *Ix, *Iy, *It;
-    const float *u0, *v0;   // linearisation point (increment form: u, v hold u - u0, It is relative)
-    const float* at;        // device scalar a~
-    int H, W;
-    int64_t ld;
-    float c, lam, beta;
-    float inv_ac;           // 1 / (a c), a = 8
-    float c_rho_s;          // c * rho_s (rho_s = 1 for rpADMMI, rho for rpADMMII)
-    float cA, cB, cC;       // Lambda+ = Lambda + cA div y+ - A (cB s+ - cC s)
-    int rows;               // output rows per wavefront (caller: 0 = built-in choice, or 2 / 4 / 8)
-    int strips, segs;       // wavefront grid: strips along x, segments along y
-};
-
-struct AdmmGeometry { int rows, strips, segs, blocks; };
-AdmmGeometry admm_geometry(int H, int W, int rows_hint);
-extern int g_admm_rows_override;   // 0 = heuristic; 2, 4 or 8 force the strip height
-void launch_admm_iter(const AdmmIterArgs& a, bool has_w, hipStream_t s);
-
-// Temporally blocked iterations: K iterations of one output tile per work-group launch.
-constexpr int kTbPpt = 6;            // pixels per thread (beta = 0): LDS q1x..q2y, gu, gv
-constexpr int kTbPptW = 4;           // with the w / p block
-constexpr int kTbPptSmall = 2;       // 1024 threads on small tiles (work-group size code 1025)
-struct TbTile {
-    int level;                       // index of the (pair, level) descriptor
-    int y0, x0, th, tw;              // output tile
-};
-struct TbLevel {
-    const float* in[10];             // iterate k: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
-    float* out[10];                  // iterate k + K
-    const float *Ix, *Iy, *It, *u0, *v0;
-    const float* at;                 // the pair's two a~ slots
-    int H, W;
-    int64_t ld;
-};
-struct TbArgs {
-    const TbTile* tiles;
-    int ntiles;
-    const TbLevel* levels;           // two descriptors per (pair, level): [2 * id + dir]
-    int dir;                         // which ping-pong direction this launch uses
-    int K;                           // iterations of this launch (halo = 2K top/left, K bottom/right)
-    int at_slot;                     // a~ slot of the current warp
-    unsigned* queue;                 // work counter, monotone within a solve (nullptr: direct mode)
-    unsigned queue_base;             // counter value at the start of this launch
-    float c, lam, beta, inv_ac, c_rho_s, cA, cB, cC;
-    // direct mode (one level, regular tiles): descriptor of this launch's direction and tiling
-    TbLevel lvl;
-    int th, tw, ntx;
-};
-int tb_capacity(bool has_w, int nt);   // nt: 256, 1024, or 1025 (1024 threads, small tiles)
-void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s);
-void launch_reset_u32(unsigned* p, int n, hipStream_t s);
-
-// Warp + linearise + a~ (max of M_s) with a last-block finalisation.
+// Warp + linearise + a~ (max of M_s, one atomic max per work-group on the float bits).
 struct LinArgs {
     const void *I0, *I1, *Dx, *Dy;   // float or __half, pitch ld
     const float *u0, *v0;            // pitch ld
@@ -82,6 +25,17 @@ struct LinArgs {
     float *keep_u, *keep_v;          // optional planes receiving a copy of (u0, v0)
 };
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s);
+
+// Argument blocks of the elementwise pyramid / bookkeeping kernels (also the items of batched launches).
+struct DownArgs { const void* src; int H, W; int64_t ld; void* dst; int64_t ldd; };     // output ceil(H/2) x ceil(W/2)
+struct DerivArgs { const void* I; int H, W; int64_t ld; void* Dx; void* Dy; int64_t ldd; };
+struct CopyArgs { const float* src; int H, W; int64_t lds; void* dst; int64_t ldd; };    // FP32 -> FP32 or FP16
+struct CommitArgs { float* u0; float* v0; const float* du; const float* dv; int H, W; int64_t ld; };
+
+// Batched launches of one body over many items (one work-group grid per item, prefix offsets).
+enum class BatchOp { Downsample, Derivatives, Copy, Commit, Linearize, LevelInit };
+int blocks_of(int H, int W);   // 64 x 4 blocks covering an H x W plane
+void launch_batched(BatchOp op, const void* items, const int* off, int n, int total_blocks, bool f16, hipStream_t s);
 
 // Pyramid: 2x2 box average with edge replication, central differences, format conversion.
 void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s);
@@ -143,5 +97,9 @@ struct EnergyArgs {
 constexpr int kEnergyTerms = 8;      // tv, data, dual, residual^2, g_tv, g_data, lam_r, nonfinite
 constexpr int kEnergyBlocks = 512;
 void launch_energy(const EnergyArgs& a, hipStream_t s);
+int energy_blocks(int H, int W);     // work-groups of the first energy kernel for an H x W level
+// items[k] owns work-groups [off[k], off[k+1]) (off[k+1] - off[k] = energy_blocks of its level);
+// each item has its own partial (that many x kEnergyTerms doubles) and out buffers
+void launch_energy_batched(const EnergyArgs* items, const int* off, int n, int total_blocks, hipStream_t s);
 
 }  // namespace flowmi

@@ -5,8 +5,12 @@
 //   linearize    bilinear warp of I1, D_x I1, D_y I1 at x + d0 and the linearisation
 //                rho(d) = I_x u + I_y v + I_t (Sec. 1), plus a~ = max M_s (Prop. 3.1)
 //   level_init   centre-aligned bilinear x2 upsampling of the flow, dual reset
+//   commit       end of a warp in increment form (u0 += du)
+//   copy         plane copies with format conversion (frame import, flow export)
 // All are elementwise or gather kernels: one thread per output pixel, 64-wide rows per wavefront
-// so that every plane access is a coalesced row segment.
+// so that every plane access is a coalesced row segment.  Each body is written once and launched
+// either for one plane set (grid = the plane's blocks) or batched over many plane sets in one launch,
+// where a block-offset prefix maps each work-group to its item (no work-group is wasted).
 #include "kernels.hpp"
 
 namespace flowmi {
@@ -22,39 +26,52 @@ template <> __device__ __forceinline__ void stv<__half>(__half* p, int64_t i, fl
 
 dim3 grid2d(int H, int W) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
+// ---------------------------------------------------------------------------------------------
+// bodies: (bx, by) is the work-group's position in the item's grid of 64 x 4 blocks
+// ---------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void downsample_kernel(const T* __restrict__ src, int H, int W, int64_t ld,
-                                                         T* __restrict__ dst, int Hc, int Wc, int64_t ldd) {
-    const int b = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int a = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (a >= Hc || b >= Wc) return;
-    const int r0 = 2 * a, r1 = min(2 * a + 1, H - 1);
-    const int c0 = 2 * b, c1 = min(2 * b + 1, W - 1);
-    const float s = ldv(src, (int64_t)r0 * ld + c0) + ldv(src, (int64_t)r0 * ld + c1) +
-                    ldv(src, (int64_t)r1 * ld + c0) + ldv(src, (int64_t)r1 * ld + c1);
-    stv(dst, (int64_t)a * ldd + b, 0.25f * s);
+__device__ __forceinline__ void downsample_body(const DownArgs& a, int bx, int by) {
+    const int Hc = (a.H + 1) / 2, Wc = (a.W + 1) / 2;
+    const int b = bx * 64 + (threadIdx.x & 63);
+    const int r = by * 4 + (threadIdx.x >> 6);
+    if (r >= Hc || b >= Wc) return;
+    const T* src = (const T*)a.src;
+    const int r0 = 2 * r, r1 = min(2 * r + 1, a.H - 1);
+    const int c0 = 2 * b, c1 = min(2 * b + 1, a.W - 1);
+    const float s = ldv(src, (int64_t)r0 * a.ld + c0) + ldv(src, (int64_t)r0 * a.ld + c1) +
+                    ldv(src, (int64_t)r1 * a.ld + c0) + ldv(src, (int64_t)r1 * a.ld + c1);
+    stv((T*)a.dst, (int64_t)r * a.ldd + b, 0.25f * s);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void derivatives_kernel(const T* __restrict__ I, int H, int W, int64_t ld,
-                                                          T* __restrict__ Dx, T* __restrict__ Dy, int64_t ldd) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= H || j >= W) return;
-    const int64_t row = (int64_t)i * ld;
+__device__ __forceinline__ void derivatives_body(const DerivArgs& a, int bx, int by) {
+    const int j = bx * 64 + (threadIdx.x & 63);
+    const int i = by * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    const T* I = (const T*)a.I;
+    const int64_t row = (int64_t)i * a.ld;
+    const int W = a.W, H = a.H;
     const float dx = 0.5f * (ldv(I, row + min(j + 1, W - 1)) - ldv(I, row + max(j - 1, 0)));
-    const float dy = 0.5f * (ldv(I, (int64_t)min(i + 1, H - 1) * ld + j) - ldv(I, (int64_t)max(i - 1, 0) * ld + j));
-    stv(Dx, (int64_t)i * ldd + j, dx);
-    stv(Dy, (int64_t)i * ldd + j, dy);
+    const float dy = 0.5f * (ldv(I, (int64_t)min(i + 1, H - 1) * a.ld + j) - ldv(I, (int64_t)max(i - 1, 0) * a.ld + j));
+    stv((T*)a.Dx, (int64_t)i * a.ldd + j, dx);
+    stv((T*)a.Dy, (int64_t)i * a.ldd + j, dy);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void import_kernel(const float* __restrict__ src, int H, int W, int64_t lds,
-                                                     T* __restrict__ dst, int64_t ldd) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= H || j >= W) return;
-    stv(dst, (int64_t)i * ldd + j, src[(int64_t)i * lds + j]);
+__device__ __forceinline__ void copy_body(const CopyArgs& a, int bx, int by) {
+    const int j = bx * 64 + (threadIdx.x & 63);
+    const int i = by * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    stv((T*)a.dst, (int64_t)i * a.ldd + j, a.src[(int64_t)i * a.lds + j]);
+}
+
+__device__ __forceinline__ void commit_body(const CommitArgs& a, int bx, int by) {
+    const int j = bx * 64 + (threadIdx.x & 63);
+    const int i = by * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    const int64_t o = (int64_t)i * a.ld + j;
+    a.u0[o] += a.du[o];
+    a.v0[o] += a.dv[o];
 }
 
 // Integer / fraction split of the sample position p + d clamped into [0, n-1]; keeps the
@@ -81,9 +98,9 @@ __device__ __forceinline__ float wave_max(float x) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by) {
+    const int j = bx * 64 + (threadIdx.x & 63);
+    const int i = by * 4 + (threadIdx.x >> 6);
     const T* I0 = (const T*)a.I0;
     const T* I1 = (const T*)a.I1;
     const T* Dx = (const T*)a.Dx;
@@ -117,7 +134,7 @@ __global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
     if (threadIdx.x == 0) {
         const float bm = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
         atomicMax((unsigned int*)a.at, __float_as_uint(bm));
-        if (a.at_clear && blockIdx.x == 0 && blockIdx.y == 0) *a.at_clear = 0.f;
+        if (a.at_clear && bx == 0 && by == 0) *a.at_clear = 0.f;
     }
 }
 
@@ -134,9 +151,9 @@ __device__ __forceinline__ float up_sample(const float* F, int Hc, int Wc, int64
     return (1.f - ty) * ((1.f - tx) * F[o] + tx * F[o + 1]) + ty * ((1.f - tx) * F[o + ldc] + tx * F[o + ldc + 1]);
 }
 
-__global__ __launch_bounds__(256) void level_init_kernel(LevelInitArgs a) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void level_init_body(const LevelInitArgs& a, int bx, int by) {
+    const int j = bx * 64 + (threadIdx.x & 63);
+    const int i = by * 4 + (threadIdx.x >> 6);
     if (i >= a.H || j >= a.W) return;
     const int64_t off = (int64_t)i * a.ld + j;
     // target order (w, u, v): illumination keeps its scale, flow components double
@@ -155,6 +172,26 @@ __global__ __launch_bounds__(256) void level_init_kernel(LevelInitArgs a) {
     if (a.clear_scalar && i == 0 && j == 0) *a.clear_scalar = 0.f;
 }
 
+// ---------------------------------------------------------------------------------------------
+// single launches: the grid is the item's own block grid
+// ---------------------------------------------------------------------------------------------
+template <typename T> __global__ __launch_bounds__(256) void downsample_kernel(DownArgs a) {
+    downsample_body<T>(a, blockIdx.x, blockIdx.y);
+}
+template <typename T> __global__ __launch_bounds__(256) void derivatives_kernel(DerivArgs a) {
+    derivatives_body<T>(a, blockIdx.x, blockIdx.y);
+}
+template <typename T> __global__ __launch_bounds__(256) void copy_kernel(CopyArgs a) {
+    copy_body<T>(a, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(256) void commit_kernel(CommitArgs a) { commit_body(a, blockIdx.x, blockIdx.y); }
+template <typename T> __global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
+    linearize_body<T>(a, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(256) void level_init_kernel(LevelInitArgs a) {
+    level_init_body(a, blockIdx.x, blockIdx.y);
+}
+
 __global__ __launch_bounds__(256) void upsample_kernel(const float* __restrict__ F, int Hc, int Wc, int64_t ldc,
                                                        float* __restrict__ out, int Hf, int Wf, int64_t ldf,
                                                        float scale) {
@@ -164,67 +201,72 @@ __global__ __launch_bounds__(256) void upsample_kernel(const float* __restrict__
     out[(int64_t)i * ldf + j] = scale * up_sample(F, Hc, Wc, ldc, i, j);
 }
 
-__global__ __launch_bounds__(256) void commit_kernel(float* __restrict__ u0, float* __restrict__ v0,
-                                                     const float* __restrict__ du, const float* __restrict__ dv,
-                                                     int H, int W, int64_t ld) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= H || j >= W) return;
-    const int64_t o = (int64_t)i * ld + j;
-    u0[o] += du[o];
-    v0[o] += dv[o];
+// ---------------------------------------------------------------------------------------------
+// batched launches: item k owns work-groups [off[k], off[k+1]), row-major over its block grid
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int find_item(const int* __restrict__ off, int n, int b) {
+    int lo = 0, hi = n;   // invariant off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
-__global__ __launch_bounds__(256) void copy2d_kernel(const float* __restrict__ src, int H, int W, int64_t lds,
-                                                     float* __restrict__ dst, int64_t ldd) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= H || j >= W) return;
-    dst[(int64_t)i * ldd + j] = src[(int64_t)i * lds + j];
+template <typename A> __device__ __forceinline__ int grid_w(const A& a) { return (a.W + 63) / 64; }
+template <> __device__ __forceinline__ int grid_w<DownArgs>(const DownArgs& a) { return ((a.W + 1) / 2 + 63) / 64; }
+
+template <typename A, void (*BODY)(const A&, int, int)>
+__global__ __launch_bounds__(256) void batched_kernel(const A* __restrict__ items, const int* __restrict__ off, int n) {
+    const int k = find_item(off, n, blockIdx.x);
+    const A a = items[k];
+    const int local = blockIdx.x - off[k];
+    const int gx = grid_w(a);
+    BODY(a, local % gx, local / gx);
+}
+
+template <typename A, void (*BODY)(const A&, int, int)>
+void launch_b(const void* items, const int* off, int n, int total, hipStream_t s) {
+    hipLaunchKernelGGL((batched_kernel<A, BODY>), dim3(total), dim3(256), 0, s, (const A*)items, off, n);
 }
 
 }  // namespace
 
+// ----------------------------------- host launchers --------------------------------------------
 void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s) {
-    const int Hc = (H + 1) / 2, Wc = (W + 1) / 2;
-    if (f16)
-        hipLaunchKernelGGL(downsample_kernel<__half>, grid2d(Hc, Wc), dim3(256), 0, s, (const __half*)src, H, W,
-                           ld, (__half*)dst, Hc, Wc, ldd);
-    else
-        hipLaunchKernelGGL(downsample_kernel<float>, grid2d(Hc, Wc), dim3(256), 0, s, (const float*)src, H, W,
-                           ld, (float*)dst, Hc, Wc, ldd);
+    const DownArgs a{src, H, W, ld, dst, ldd};
+    const dim3 g = grid2d((H + 1) / 2, (W + 1) / 2);
+    if (f16) hipLaunchKernelGGL(downsample_kernel<__half>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(downsample_kernel<float>, g, dim3(256), 0, s, a);
 }
 
 void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void* Dy, int64_t ldd, bool f16,
                         hipStream_t s) {
-    if (f16)
-        hipLaunchKernelGGL(derivatives_kernel<__half>, grid2d(H, W), dim3(256), 0, s, (const __half*)I, H, W, ld,
-                           (__half*)Dx, (__half*)Dy, ldd);
-    else
-        hipLaunchKernelGGL(derivatives_kernel<float>, grid2d(H, W), dim3(256), 0, s, (const float*)I, H, W, ld,
-                           (float*)Dx, (float*)Dy, ldd);
+    const DerivArgs a{I, H, W, ld, Dx, Dy, ldd};
+    if (f16) hipLaunchKernelGGL(derivatives_kernel<__half>, grid2d(H, W), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(derivatives_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }
 
 void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64_t ldd, bool f16, hipStream_t s) {
-    if (f16)
-        hipLaunchKernelGGL(import_kernel<__half>, grid2d(H, W), dim3(256), 0, s, src, H, W, lds, (__half*)dst, ldd);
-    else
-        hipLaunchKernelGGL(import_kernel<float>, grid2d(H, W), dim3(256), 0, s, src, H, W, lds, (float*)dst, ldd);
-}
-
-void launch_commit(float* u0, float* v0, const float* du, const float* dv, int H, int W, int64_t ld, hipStream_t s) {
-    hipLaunchKernelGGL(commit_kernel, grid2d(H, W), dim3(256), 0, s, u0, v0, du, dv, H, W, ld);
+    const CopyArgs a{src, H, W, lds, dst, ldd};
+    if (f16) hipLaunchKernelGGL(copy_kernel<__half>, grid2d(H, W), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }
 
 void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s) {
-    hipLaunchKernelGGL(copy2d_kernel, grid2d(H, W), dim3(256), 0, s, src, H, W, lds, dst, ldd);
+    const CopyArgs a{src, H, W, lds, dst, ldd};
+    hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
+}
+
+void launch_commit(float* u0, float* v0, const float* du, const float* dv, int H, int W, int64_t ld, hipStream_t s) {
+    const CommitArgs a{u0, v0, du, dv, H, W, ld};
+    hipLaunchKernelGGL(commit_kernel, grid2d(H, W), dim3(256), 0, s, a);
 }
 
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s) {
-    if (f16)
-        hipLaunchKernelGGL(linearize_kernel<__half>, grid2d(a.H, a.W), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(linearize_kernel<float>, grid2d(a.H, a.W), dim3(256), 0, s, a);
+    if (f16) hipLaunchKernelGGL(linearize_kernel<__half>, grid2d(a.H, a.W), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(linearize_kernel<float>, grid2d(a.H, a.W), dim3(256), 0, s, a);
 }
 
 void launch_level_init(const LevelInitArgs& a, hipStream_t s) {
@@ -235,6 +277,32 @@ void launch_upsample(const float* coarse, int64_t ldc, float* fine, int Hf, int 
                      hipStream_t s) {
     hipLaunchKernelGGL(upsample_kernel, grid2d(Hf, Wf), dim3(256), 0, s, coarse, (Hf + 1) / 2, (Wf + 1) / 2, ldc,
                        fine, Hf, Wf, ldf, scale);
+}
+
+int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
+
+void launch_batched(BatchOp op, const void* items, const int* off, int n, int total, bool f16, hipStream_t s) {
+    if (n <= 0 || total <= 0) return;
+    switch (op) {
+        case BatchOp::Downsample:
+            if (f16) launch_b<DownArgs, downsample_body<__half>>(items, off, n, total, s);
+            else launch_b<DownArgs, downsample_body<float>>(items, off, n, total, s);
+            break;
+        case BatchOp::Derivatives:
+            if (f16) launch_b<DerivArgs, derivatives_body<__half>>(items, off, n, total, s);
+            else launch_b<DerivArgs, derivatives_body<float>>(items, off, n, total, s);
+            break;
+        case BatchOp::Copy:
+            if (f16) launch_b<CopyArgs, copy_body<__half>>(items, off, n, total, s);
+            else launch_b<CopyArgs, copy_body<float>>(items, off, n, total, s);
+            break;
+        case BatchOp::Commit: launch_b<CommitArgs, commit_body>(items, off, n, total, s); break;
+        case BatchOp::Linearize:
+            if (f16) launch_b<LinArgs, linearize_body<__half>>(items, off, n, total, s);
+            else launch_b<LinArgs, linearize_body<float>>(items, off, n, total, s);
+            break;
+        case BatchOp::LevelInit: launch_b<LevelInitArgs, level_init_body>(items, off, n, total, s); break;
+    }
 }
 
 }  // namespace flowmi

@@ -161,9 +161,9 @@ def test_stopping_tolerance_stops_early(ctx):
     I0, I1 = to_dev(pair.I0), to_dev(pair.I1)
     ctx.set_stats(True)
     _, _, r_fixed = ctx.solve(I0, I1, fm.Params(levels=1, warps=1, iters=2000, use_graph=0))
-    n_fixed = ctx.stats()["iter_launches"][0]
+    n_fixed = ctx.stats()["iterations"][0]
     _, _, r_tol = ctx.solve(I0, I1, fm.Params(levels=1, warps=1, iters=2000, tol=2e-3, check_every=50))
-    n_tol = ctx.stats()["iter_launches"][0]
+    n_tol = ctx.stats()["iterations"][0]
     ctx.set_stats(False)
     assert n_fixed == 2000 and n_tol < 2000
     assert abs(r_tol["gap"]) <= 2e-3 * r_tol["energy"]
