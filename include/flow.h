@@ -101,6 +101,7 @@ typedef struct flow_stats {
     double total_ms;                          /* event time of the whole solve on the device */
     int64_t px_iter;                          /* pixel-iterations of the solve */
     int32_t graph_replayed;                   /* 1 if the solve ran as a graph replay */
+    int64_t level_px[FLOW_MAX_LEVELS];        /* pixels of the level (a batch: summed over its pairs) */
 } flow_stats;
 
 typedef struct flow_ctx flow_ctx;
@@ -130,7 +131,10 @@ flow_status flow_solve(flow_ctx* ctx, const float* I0, const float* I1, int32_t 
                        const flow_params* p, float* u, float* v, int64_t ld_uv, flow_result* res,
                        void* stream);
 
-/* One pair of a batch: device frames and outputs as in flow_solve, res is host (may be NULL). */
+/* One pair of a batch: device frames and outputs as in flow_solve (caller-owned, FP32, pitches ld
+ * and ld_uv in elements); res is host memory (may be NULL); levels > 0 sets this pair's pyramid
+ * depth (0: params->levels), so pairs of very different sizes can each keep coarsest levels of a
+ * useful size. */
 typedef struct flow_pair {
     const float* I0;
     const float* I1;
@@ -140,14 +144,33 @@ typedef struct flow_pair {
     float* v;
     int64_t ld_uv;
     flow_result* res;
+    int32_t levels;
 } flow_pair;
 
-/* Solve n pairs of uneven sizes together: every iteration step advances all pairs that are at
- * that step with one launch of a persistent kernel that pulls (pair, tile) items from a work
- * queue (Sec. 4 pipeline per pair; levels per pair = params.levels, reduced where a pair is too
- * small).  Results equal n plain solves bitwise.  Blocks until all results are written. */
+/* Solve n pairs of uneven sizes together (the coarse-to-fine solve of Sec. 4 for every pair).
+ * Stage s works on pyramid level Lmax-1-s of every pair that has it (all pairs reach level 0 in
+ * the last stage); each step of a stage (level start, warp, K iterations, commit, energy) is ONE
+ * launch over all pairs, the iterations a launch of the K-iteration tile kernel over the tiles of
+ * every pair's level, in XCD order or from per-XCD work queues (choice, K and tile width per stage
+ * from flow_autotune_batched, else built in).  ADMM family only with tol = 0 (pDR pairs and
+ * stopping tests run as plain solves in turn).  Every pair's arithmetic is independent of the rest
+ * of the batch and of the stage choices, so a pair's results are bitwise the same alone or in any
+ * batch, and equal to a plain solve that uses small 1024-thread tiles (tb_mode 4) at every level.
+ * The context keeps the working set of the last batch (arena, tables, captured graph) for reuse.
+ * Errors: FLOW_E_INVAL (any pair invalid: nothing runs), FLOW_E_NOMEM (working set of all pairs
+ * above the budget), FLOW_E_NONFINITE (outputs written, some pair's energy not finite).  Blocks
+ * until all results are written. */
 flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
                                void* stream);
+
+/* Batched autotuner: for each stage of this batch, time every tile-launch choice (table order or
+ * per-XCD work queues; K = 2, 4, 8 iterations per launch, or the whole warp where every level of the
+ * stage fits one tile; extended tile width 64 or 128) over one warp's iterations, and keep the
+ * fastest for later flow_solve_batched calls on batches whose stage has the same level shapes.
+ * The choice changes speed only (results are bitwise the same).  Runs the pipeline on the pairs'
+ * frames; blocking. */
+flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                                  void* stream);
 
 /* Autotuner: for every pyramid level of an H x W pair under params p, time each iteration-kernel
  * choice (one-pass kernel with 2 / 4 / 8-row strips; K-iteration tiles of 256, 1024 and small
@@ -183,6 +206,11 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 kernel only, 2 K-iteration tiles of 256 threads, 3 of 1024 threads, 4 small tiles
  *                 of 1024 threads.
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
+ *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
+ *                 work queues.
+ *   "batch_k"     iterations per batched tile launch (0 = tuned / built-in; lowered where a level's
+ *                 tiles cannot hold the halo).
+ *   "batch_ew"    extended tile width target of batched tiles (0 = tuned / built-in, else 16..512).
  * FLOW_E_INVAL for an unknown key or value.  Not thread-safe against concurrent solves. */
 flow_status flow_tune_set(const char* key, int64_t value);
 
@@ -240,8 +268,10 @@ flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* 
  * threads: 256 or 1024 (6 pixels per thread, 4 with beta > 0) or 1025 (1024 threads, 2 pixels per
  * thread); tile_h x tile_w: output tile; each tile's extended region
  * min(H, tile_h + 3 iters) x min(W, tile_w + 3 iters) must fit that capacity, else FLOW_E_INVAL.
- * use_queue: 0 = one work-group per tile, 1 = persistent work-groups pulling tiles from a counter
- * (the batched path).  Blocking (synchronises the stream). */
+ * order: 0 = one work-group per tile (tile from the work-group index), 1 = persistent work-groups
+ * pulling tiles from one counter, 2 = the same with 8 per-XCD sub-queues (the batched path's work
+ * queue), 3 = one work-group per entry of a tile table in XCD order (the batched path's table
+ * order).  Every order computes the same values.  Blocking (synchronises the stream). */
 flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* out, const float* Ix, const float* Iy,
                             const float* It, const float* at, int32_t H, int32_t W, int64_t ld,
                             const flow_params* p, int32_t iters, int32_t threads, int32_t tile_h, int32_t tile_w,

@@ -44,7 +44,8 @@ class _Result(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("H", ctypes.c_int32 * MAX_LEVELS), ("W", ctypes.c_int32 * MAX_LEVELS),
                 ("iterations", ctypes.c_int64 * MAX_LEVELS), ("iter_ms", ctypes.c_double * MAX_LEVELS),
-                ("total_ms", ctypes.c_double), ("px_iter", ctypes.c_int64), ("graph_replayed", ctypes.c_int32)]
+                ("total_ms", ctypes.c_double), ("px_iter", ctypes.c_int64), ("graph_replayed", ctypes.c_int32),
+                ("level_px", ctypes.c_int64 * MAX_LEVELS)]
 
 
 class _AdmmState(ctypes.Structure):
@@ -59,7 +60,7 @@ class _PdrState(ctypes.Structure):
 class _Pair(ctypes.Structure):
     _fields_ = [("I0", ctypes.c_void_p), ("I1", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("ld", ctypes.c_int64), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("ld_uv", ctypes.c_int64),
-                ("res", ctypes.c_void_p)]
+                ("res", ctypes.c_void_p), ("levels", ctypes.c_int32)]
 
 
 _lib = None
@@ -68,7 +69,7 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_set_stats", "flow_get_stats", "flow_memory_in_use", "flow_last_error", "flow_op_downsample",
            "flow_op_derivatives", "flow_op_linearize", "flow_op_upsample", "flow_op_admm_iter", "flow_op_pdr_iter",
            "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
-           "flow_tune_choice"]
+           "flow_tune_choice", "flow_autotune_batched"]
 
 
 def lib():
@@ -85,6 +86,7 @@ def lib():
             "flow_destroy": [vp],
             "flow_solve": [vp, vp, vp, i32, i32, i64, ctypes.POINTER(_Params), vp, vp, i64, ctypes.POINTER(_Result), vp],
             "flow_solve_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
+            "flow_autotune_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
             "flow_set_stats": [vp, i32],
             "flow_autotune": [vp, i32, i32, ctypes.POINTER(_Params), vp],
             "flow_get_tuning": [vp, ctypes.c_char_p, ctypes.c_size_t],
@@ -223,7 +225,7 @@ class Context:
         n = s.levels
         return dict(levels=n, H=list(s.H[:n]), W=list(s.W[:n]), iterations=list(s.iterations[:n]),
                     iter_ms=list(s.iter_ms[:n]), total_ms=s.total_ms, px_iter=s.px_iter,
-                    graph_replayed=bool(s.graph_replayed))
+                    graph_replayed=bool(s.graph_replayed), level_px=list(s.level_px[:n]))
 
     def autotune(self, H, W, params: Params | None = None, **kw):
         """Time every iteration-kernel choice on the level shapes of an H x W pair; later solves of
@@ -270,24 +272,40 @@ class Context:
                                 _ptr(u), _ptr(v), u.stride(0), ctypes.byref(res), _stream()))
         return u, v, _result_dict(res)
 
-    def solve_batched(self, pairs, params: Params | None = None, **kw):
-        """pairs: list of (I0, I1); returns a list of (u, v, result)."""
-        params = params or Params(**kw)
+    def _pairs(self, pairs):
         n = len(pairs)
         arr = (_Pair * n)()
         results = [_Result() for _ in range(n)]
         outs = []
-        for k, (I0, I1) in enumerate(pairs):
+        for k, pr in enumerate(pairs):
+            I0, I1 = pr[0], pr[1]
+            levels = int(pr[2]) if len(pr) > 2 else 0
             _plane(I0, "I0")
             _plane(I1, "I1")
+            if I0.shape != I1.shape or I0.stride() != I1.stride():
+                raise ValueError(f"pair {k}: I0 and I1 must have the same shape and layout")
             H, W = I0.shape
             u = torch.empty((H, W), device=I0.device, dtype=torch.float32)
             v = torch.empty((H, W), device=I0.device, dtype=torch.float32)
             arr[k] = _Pair(I0.data_ptr(), I1.data_ptr(), H, W, I0.stride(0), u.data_ptr(), v.data_ptr(), W,
-                           ctypes.cast(ctypes.byref(results[k]), ctypes.c_void_p))
+                           ctypes.cast(ctypes.byref(results[k]), ctypes.c_void_p), levels)
             outs.append((u, v))
-        _check(lib().flow_solve_batched(self._h, n, arr, ctypes.byref(params.c_struct()), _stream()))
+        return arr, results, outs
+
+    def solve_batched(self, pairs, params: Params | None = None, **kw):
+        """pairs: list of (I0, I1) or (I0, I1, levels); all pairs advance together (one launch per
+        step over all pairs).  Returns a list of (u, v, result)."""
+        params = params or Params(**kw)
+        arr, results, outs = self._pairs(pairs)
+        _check(lib().flow_solve_batched(self._h, len(pairs), arr, ctypes.byref(params.c_struct()), _stream()))
         return [(u, v, _result_dict(r)) for (u, v), r in zip(outs, results)]
+
+    def autotune_batched(self, pairs, params: Params | None = None, **kw):
+        """Time the batched tile-launch choices per stage of this batch; later solve_batched calls
+        on batches with the same stage shapes use the fastest."""
+        params = params or Params(**kw)
+        arr, _, _ = self._pairs(pairs)
+        _check(lib().flow_autotune_batched(self._h, len(pairs), arr, ctypes.byref(params.c_struct()), _stream()))
 
 
 # ------------------------------------ operator-level calls -----------------------------------
@@ -353,7 +371,7 @@ def admm_iter(state, Ix, Iy, It, at, params: Params):
     return out
 
 
-def admm_tb(state, Ix, Iy, It, at, params: Params, iters, threads=256, tile_h=16, tile_w=32, use_queue=False):
+def admm_tb(state, Ix, Iy, It, at, params: Params, iters, threads=256, tile_h=16, tile_w=32, order=0):
     """`iters` iterations in one launch of the K-iteration tile kernel (increment form: the state
     must hold "u0", "v0"); returns the new state dict."""
     ref = _plane(state["u"], "u")
@@ -363,7 +381,7 @@ def admm_tb(state, Ix, Iy, It, at, params: Params, iters, threads=256, tile_h=16
     H, W = ref.shape
     _check(lib().flow_op_admm_tb(ctypes.byref(_admm_struct(state)), ctypes.byref(_admm_struct(out)), _ptr(Ix),
                                  _ptr(Iy), _ptr(It), _ptr(at), H, W, ref.stride(0), ctypes.byref(params.c_struct()),
-                                 iters, threads, tile_h, tile_w, 1 if use_queue else 0, _stream()))
+                                 iters, threads, tile_h, tile_w, int(order), _stream()))
     return out
 
 

@@ -55,10 +55,13 @@ struct TbArgs {
     int dir;                         // which ping-pong direction this launch uses
     int K;                           // iterations of this launch (halo = 2K top/left, K bottom/right)
     int at_slot;                     // a~ slot of the current warp
-    unsigned* queue;                 // work counter, monotone within a solve (nullptr: direct mode)
+    unsigned* queue;                 // work counters (nullptr: tiles from the work-group index)
     unsigned queue_base;             // counter value at the start of this launch
+    int nq;                          // sub-queues: work-group b drains tiles [ntiles*x/nq, ntiles*(x+1)/nq)
+                                     // of sub-queue x = b % nq with counter queue[x] (nq <= grid)
     float c, lam, beta, inv_ac, c_rho_s, cA, cB, cC;
-    // direct mode (one level, regular tiles): descriptor of this launch's direction and tiling
+    // tiles == nullptr: direct mode (one level, regular tiles): descriptor of this launch's
+    // direction and tiling; tiles != nullptr and queue == nullptr: tile k of the table per work-group
     TbLevel lvl;
     int th, tw, ntx;
 };

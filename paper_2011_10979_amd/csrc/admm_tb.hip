@@ -16,10 +16,11 @@
 // g (LDS), written over q;  barrier;  C: div y+, s+, multipliers (registers), then A of the next
 // iteration (C only reads y+, A only writes g, so they need no barrier between them).
 //
-// Work distribution: a persistent grid pulls tile indices from a device counter; tiles of one
-// launch read one state buffer and write the other, so they never depend on each other and every
-// work-group exits once the counter passes the tile count.  Levels of different pairs can share a
-// launch (batched solves): each tile names its level descriptor.
+// Work distribution: one work-group per tile of one level (direct), per entry of a tile table
+// (batched pairs: each tile names its pair-level descriptor), or a persistent grid that pulls
+// tile indices from device counters.  Tiles of one launch read one state buffer and write the
+// other, so they never depend on each other, and every work-group of the persistent grid exits
+// once its counter passes the end of its run of tiles.
 #include "kernels.hpp"
 
 namespace flowmi {
@@ -212,17 +213,33 @@ __global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
     process_tile<HAS_W, NT, PPT>(a, T, a.lvl, S);
 }
 
-// Many levels (batched pairs): a persistent grid pulls (level, tile) items from a counter.
+// Many levels (batched pairs), table order: work-group b takes tile xcd_tile(b) of the table, so
+// each XCD works through a contiguous run of tiles (neighbours share its L2).
+template <bool HAS_W, int NT, int PPT>
+__global__ __launch_bounds__(NT) void admm_tb_table_kernel(TbArgs a) {
+    __shared__ TileLds<HAS_W, NT, PPT> S;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= a.ntiles) return;
+    const TbTile T = a.tiles[t];
+    process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
+}
+
+// Many levels (batched pairs), work queue: a persistent grid pulls (level, tile) items from nq
+// counters; sub-queue x owns a contiguous run of the table and is drained by the work-groups
+// b = x (mod nq), which the dispatcher places on one XCD when nq = 8.
 template <bool HAS_W, int NT, int PPT>
 __global__ __launch_bounds__(NT) void admm_tb_queue_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
     __shared__ int s_tile;
+    const int x = blockIdx.x % a.nq;
+    const int lo = (int)((int64_t)a.ntiles * x / a.nq);
+    const int hi = (int)((int64_t)a.ntiles * (x + 1) / a.nq);
     for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)(atomicAdd(a.queue, 1u) - a.queue_base);
+        if (threadIdx.x == 0) s_tile = lo + (int)(atomicAdd(a.queue + x, 1u) - a.queue_base);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();                  // everyone has read s_tile before it is overwritten
-        if (t >= a.ntiles) break;         // uniform: the whole work-group leaves together
+        if (t >= hi) break;               // uniform: the whole work-group leaves together
         const TbTile T = a.tiles[t];
         process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
         __syncthreads();                  // LDS is reused by the next tile
@@ -249,11 +266,12 @@ int tb_capacity(bool has_w, int nt) {
 template <bool HAS_W, int NT, int PPT>
 static void launch_one(const TbArgs& a, int grid, hipStream_t s) {
     if (a.queue) hipLaunchKernelGGL((admm_tb_queue_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+    else if (a.tiles) hipLaunchKernelGGL((admm_tb_table_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
     else hipLaunchKernelGGL((admm_tb_direct_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
 }
 
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s) {
-    if (!a.queue) grid = (grid + 7) / 8 * 8;     // direct mode: XCD remap wants a multiple of 8
+    if (!a.queue) grid = (grid + 7) / 8 * 8;     // direct / table order: the XCD remap wants a multiple of 8
     if (nt == 1024) {
         if (has_w) launch_one<true, 1024, kTbPptW>(a, grid, s);
         else launch_one<false, 1024, kTbPpt>(a, grid, s);

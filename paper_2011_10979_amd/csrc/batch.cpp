@@ -1,20 +1,844 @@
-// Batched solve of many pairs (placeholder until the work-queue path lands: plain solves in turn).
+// Batched solve of many pairs of uneven sizes on one GPU: the coarse-to-fine solve of Sec. 4 for
+// every pair, advanced together.  Stage s works on pyramid level l = Lmax-1-s of every pair that has
+// it, so all pairs reach level 0 in the last stage.  Every step of a stage is ONE launch over all
+// its pairs: the elementwise steps (import, downsample, derivatives, level start, linearisation,
+// commit, energy, export) through item tables in which a block-offset prefix maps each work-group
+// to its pair, and each block of K iterations through the K-iteration tile kernel over a table of
+// (pair-level, tile) entries, taken in XCD order or drained from per-XCD work queues.
+//
+// Determinism: a pair's arithmetic never depends on the other pairs of the batch (each pair has
+// its own a~ slots and energy partials, every tile is computed by the same kernel instantiation, and
+// the K of a launch only decides how far a tile's halo is recomputed), so a pair's results are
+// bitwise the same alone or in any batch, for any stage choice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "runtime.hpp"
 
 namespace flowmi {
-struct BatchState {};
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+    } while (0)
+
+namespace {
+
+constexpr int kBatchNt = 1025;   // tile kernel instantiation of every batched level (1024 threads, small tiles)
+constexpr int kNq = 8;           // per-XCD sub-queues of the work-queue order
+
+enum { ORDER_TABLE = 0, ORDER_QUEUE = 1 };
+
+struct StageChoice {
+    int K = 0;                   // iterations per tile launch (>= iters: the whole warp in one launch)
+    int ew = 64;                 // extended tile width target
+    int order = ORDER_TABLE;
+};
+
+// One batched launch of an elementwise body: items and block offsets at byte offsets of a table.
+struct BLaunch {
+    size_t items = 0, off = 0;
+    int n = 0, total = 0;
+};
+
+struct BStage {
+    int l = 0;                          // pyramid level (0 = finest)
+    std::vector<int> pairs;             // pairs that have level l
+    std::string key;                    // level shapes of the stage (tuning key)
+    StageChoice ch;
+    int lpw = 0;                        // tile launches per warp
+    int tile_off = 0, ntiles = 0, grid = 0;
+    int counter_off = 0;                // first counter of the stage's queue launches
+    BLaunch init;
+    std::vector<BLaunch> lin, commit;   // per warp
+};
+
+// Host-side builder of a device table: typed arrays at 256-byte aligned offsets.
+struct TableBuilder {
+    std::vector<char> h;
+    template <typename T> size_t put(const std::vector<T>& v) {
+        const size_t o = (h.size() + 255) & ~(size_t)255;
+        h.resize(o + std::max<size_t>(1, v.size() * sizeof(T)), 0);
+        if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size() * sizeof(T));
+        return o;
+    }
+    // items plus their block-offset prefix (blocks[k] work-groups for item k)
+    template <typename T> BLaunch launch(const std::vector<T>& items, const std::vector<int>& blocks) {
+        BLaunch L;
+        std::vector<int> off(items.size() + 1, 0);
+        for (size_t k = 0; k < items.size(); ++k) off[k + 1] = off[k] + blocks[k];
+        L.items = put(items);
+        L.off = put(off);
+        L.n = (int)items.size();
+        L.total = off.back();
+        return L;
+    }
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+    char* d = nullptr;
+    size_t bytes = 0;
+    flow_status ensure(size_t need, const char* what) {
+        if (need <= bytes) return FLOW_OK;
+        if (d) {
+            hipDeviceSynchronize();
+            hipFree(d);
+            d = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc((void**)&d, need);
+        if (e != hipSuccess) return fail(FLOW_E_NOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+        bytes = need;
+        return FLOW_OK;
+    }
+    void release() {
+        if (d) hipFree(d);
+        d = nullptr;
+        bytes = 0;
+    }
+};
+
+struct PinnedBuf {
+    char* h = nullptr;
+    size_t bytes = 0;
+    flow_status ensure(size_t need) {
+        if (need <= bytes) return FLOW_OK;
+        if (h) hipHostFree(h);
+        h = nullptr;
+        bytes = 0;
+        HIP_TRY(hipHostMalloc((void**)&h, need, hipHostMallocDefault));
+        bytes = need;
+        return FLOW_OK;
+    }
+    void release() {
+        if (h) hipHostFree(h);
+        h = nullptr;
+        bytes = 0;
+    }
+};
+
+}  // namespace
+
+// Working set and launch plan of one batch composition.
+struct BatchPlan {
+    std::string key;
+    int n = 0, lmax = 0;
+    std::vector<int> H, W, levels;
+    std::vector<std::vector<LevelPlanes>> L;   // [pair][level]
+    std::vector<BStage> stages;                // coarsest first
+    std::vector<BLaunch> down;                 // [level], level >= 1
+    BLaunch deriv, energy;
+    int ncounters = 0;
+    int final_cur = 0;                         // state buffer of the level-0 result
+    // device scalars (in BatchState::dyn): a~ slots, energy partials and sums, queue counters
+    size_t at_off = 0, epart_off = 0, eout_off = 0, cnt_off = 0, dyn_bytes = 0;
+    size_t descs_off = 0, tiles_off = 0;       // tile-kernel tables in BatchState::tab
+    BLaunch imp, exp;                          // import / export launches in BatchState::io
+    size_t io_bytes = 0;
+};
+
+struct BatchState {
+    DevArena arena;
+    DevBuf dyn, tab, io;
+    PinnedBuf h_io, h_e;
+    std::unique_ptr<BatchPlan> plan;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string graph_key;
+    std::map<std::string, StageChoice> tuned;  // per stage key
+    int tune_epoch = 0;
+    std::vector<hipEvent_t> ev;                // stage timers of instrumented solves
+
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_key.clear();
+    }
+    size_t bytes() const { return arena.bytes + dyn.bytes + tab.bytes + io.bytes; }
+    ~BatchState() {
+        hipDeviceSynchronize();
+        drop_graph();
+        if (arena.base) hipFree(arena.base);
+        dyn.release();
+        tab.release();
+        io.release();
+        h_io.release();
+        h_e.release();
+        for (auto e : ev) hipEventDestroy(e);
+    }
+};
+
 void destroy_batch(BatchState* b) { delete b; }
+size_t batch_bytes(const BatchState* b) { return b ? b->bytes() : 0; }
+
+int g_batch_order = -1;
+int g_batch_k = 0;
+int g_batch_ew = 0;
+
+namespace {
+
+std::string stage_key(const std::vector<std::pair<int, int>>& shapes, bool hw, int iters) {
+    std::vector<std::pair<int, int>> s = shapes;
+    std::sort(s.begin(), s.end());
+    std::ostringstream o;
+    o << (hw ? "w" : "") << "i" << iters << ":";
+    for (auto& x : s) o << x.first << "x" << x.second << ",";
+    return o.str();
+}
+
+// Whether every level of the stage takes tiles for exactly K iterations with this width target.
+bool stage_fits(const BatchPlan& P, const BStage& S, bool hw, int K, int ew) {
+    for (int k : S.pairs) {
+        const LevelPlanes& L = P.L[k][S.l];
+        const LevelTbPlan T = plan_tiles(L.H, L.W, hw, kBatchNt, K, ew);
+        if (!T.tb) return false;
+        if (!T.resident && T.K != K) return false;
+    }
+    return true;
+}
+
+bool stage_all_resident(const BatchPlan& P, const BStage& S, bool hw) {
+    for (int k : S.pairs) {
+        const LevelPlanes& L = P.L[k][S.l];
+        if ((int64_t)L.H * L.W > tb_capacity(hw, kBatchNt)) return false;
+    }
+    return true;
+}
+
+// Built-in stage choice: the whole warp in one launch where every level fits one tile; else
+// 4 iterations per launch on stages large enough to fill the chip with tiles, 8 on smaller ones.
+StageChoice default_choice(const BatchPlan& P, const BStage& S, bool hw, int iters) {
+    StageChoice c;
+    c.order = ORDER_TABLE;
+    c.ew = 64;
+    if (stage_all_resident(P, S, hw)) {
+        c.K = std::max(1, iters);
+        return c;
+    }
+    int64_t px = 0;
+    for (int k : S.pairs) px += (int64_t)P.L[k][S.l].H * P.L[k][S.l].W;
+    c.K = px >= 300000 ? 4 : 8;
+    while (c.K > 1 && !stage_fits(P, S, hw, c.K, c.ew)) --c.K;
+    return c;
+}
+
+void stage_tiles(const BatchPlan& P, const BStage& S, bool hw, const StageChoice& ch,
+                 const std::vector<int>& desc_id, std::vector<TbTile>& out) {
+    for (int k : S.pairs) {
+        const LevelPlanes& L = P.L[k][S.l];
+        LevelTbPlan T = plan_tiles(L.H, L.W, hw, kBatchNt, std::min(ch.K, 64), ch.ew);
+        append_tiles(T, desc_id[k * FLOW_MAX_LEVELS + S.l], L.H, L.W, out);
+    }
+}
+
+int launches_per_warp(int iters, int K) { return iters <= 0 ? 0 : (iters + K - 1) / K; }
+
+}  // namespace
+
 }  // namespace flowmi
 
 using namespace flowmi;
 
-extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
-                                          void* stream) {
-    if (!ctx || !pairs || n < 0) return fail(FLOW_E_INVAL, "bad batch arguments");
-    for (int32_t k = 0; k < n; ++k) {
+namespace {
+
+flow_status validate_pairs(int n, const flow_pair* pairs, const flow_params& p) {
+    for (int k = 0; k < n; ++k) {
         const flow_pair& q = pairs[k];
-        flow_status st = flow_solve(ctx, q.I0, q.I1, q.H, q.W, q.ld, p, q.u, q.v, q.ld_uv, q.res, stream);
+        const std::string who = "pair " + std::to_string(k) + ": ";
+        if (q.levels < 0 || q.levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, who + "levels out of range");
+        const int lv = q.levels > 0 ? q.levels : p.levels;
+        flow_status st = validate_shape(q.H, q.W, q.ld, lv);
+        if (st != FLOW_OK) return fail(st, who + flow_last_error());
+        if (q.ld_uv < q.W) return fail(FLOW_E_INVAL, who + "ld_uv smaller than W");
+        if (!q.I0 || !q.I1 || !q.u || !q.v) return fail(FLOW_E_INVAL, who + "NULL device pointer");
+        const struct { const void* ptr; int64_t ld; const char* name; } planes[4] = {
+            {q.I0, q.ld, "I0"}, {q.I1, q.ld, "I1"}, {q.u, q.ld_uv, "u"}, {q.v, q.ld_uv, "v"}};
+        for (auto& pl : planes) {
+            st = check_extent(pl.ptr, q.H, q.W, pl.ld, sizeof(float), pl.name);
+            if (st != FLOW_OK) return fail(st, who + flow_last_error());
+        }
+    }
+    return FLOW_OK;
+}
+
+std::string batch_key(int n, const flow_pair* pairs, const flow_params& p) {
+    std::ostringstream o;
+    o.precision(17);
+    o << n << ";bo" << g_batch_order << ",bk" << g_batch_k << ",be" << g_batch_ew << ';' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
+      << p.intensity_scale << ',' << p.levels << ',' << p.warps << ',' << p.iters << ',' << p.storage << ';';
+    for (int k = 0; k < n; ++k) o << pairs[k].H << 'x' << pairs[k].W << 'l' << pairs[k].levels << ',';
+    return o.str();
+}
+
+// Lays the pairs out in the batch arena and builds every table of the launch sequence.
+flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pairs, const flow_params& p) {
+    const bool hw = p.beta > 0;
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    std::unique_ptr<BatchPlan> P(new BatchPlan());
+    P->key = batch_key(n, pairs, p);
+    P->n = n;
+    // arena: the pairs' working sets back to back
+    std::vector<size_t> off(n + 1, 0);
+    for (int k = 0; k < n; ++k) {
+        flow_params pk = p;
+        pk.levels = pairs[k].levels > 0 ? pairs[k].levels : p.levels;
+        P->H.push_back(pairs[k].H);
+        P->W.push_back(pairs[k].W);
+        P->levels.push_back(pk.levels);
+        off[k + 1] = off[k] + ((layout_bytes(pairs[k].H, pairs[k].W, pk) + 255) & ~(size_t)255);
+    }
+    const size_t need = off[n];
+    if (B.arena.bytes < need) {
+        if (ctx->budget && need + ctx->bytes_in_use() - B.arena.bytes > ctx->budget)
+            return fail(FLOW_E_NOMEM, "batch working set of " + std::to_string(need) + " bytes exceeds the HBM budget");
+        B.drop_graph();
+        if (B.arena.base) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(B.arena.base));
+            B.arena.base = nullptr;
+            B.arena.bytes = 0;
+        }
+        void* a = nullptr;
+        hipError_t e = hipMalloc(&a, need);
+        if (e != hipSuccess) return fail(FLOW_E_NOMEM, std::string("hipMalloc(batch arena): ") + hipGetErrorString(e));
+        B.arena.base = a;
+        B.arena.bytes = need;
+    }
+    P->L.resize(n);
+    for (int k = 0; k < n; ++k) {
+        flow_params pk = p;
+        pk.levels = P->levels[k];
+        DevArena sub{(char*)B.arena.base + off[k], off[k + 1] - off[k]};
+        flow_status st = build_layout(sub, pairs[k].H, pairs[k].W, pk, P->L[k]);
+        if (st != FLOW_OK) return st;
+        P->lmax = std::max(P->lmax, P->levels[k]);
+    }
+
+    // stages, their choices and tile counts
+    std::vector<int> desc_id(n * FLOW_MAX_LEVELS, -1);
+    int ndesc = 0;
+    for (int k = 0; k < n; ++k)
+        for (int l = 0; l < P->levels[k]; ++l) desc_id[k * FLOW_MAX_LEVELS + l] = ndesc++;
+    std::vector<TbTile> tiles;
+    int ncounters = 0;
+    for (int l = P->lmax - 1; l >= 0; --l) {
+        BStage S;
+        S.l = l;
+        std::vector<std::pair<int, int>> shapes;
+        for (int k = 0; k < n; ++k)
+            if (P->levels[k] > l) {
+                S.pairs.push_back(k);
+                shapes.emplace_back(P->L[k][l].H, P->L[k][l].W);
+            }
+        S.key = stage_key(shapes, hw, p.iters);
+        auto it = B.tuned.find(S.key);
+        S.ch = (it != B.tuned.end() && stage_fits(*P, S, hw, it->second.K, it->second.ew))
+                   ? it->second : default_choice(*P, S, hw, p.iters);
+        // process-wide overrides (tests and experiments); K is lowered until every level fits
+        if (g_batch_order >= 0) S.ch.order = g_batch_order;
+        if (g_batch_ew > 0) S.ch.ew = g_batch_ew;
+        if (g_batch_k > 0) S.ch.K = g_batch_k;
+        if (g_batch_k > 0 || g_batch_ew > 0)
+            while (S.ch.K > 1 && !stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) --S.ch.K;
+        if (!stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) {
+            S.ch.ew = 64;
+            while (S.ch.K > 1 && !stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) --S.ch.K;
+        }
+        S.lpw = launches_per_warp(p.iters, S.ch.K);
+        S.tile_off = (int)tiles.size();
+        stage_tiles(*P, S, hw, S.ch, desc_id, tiles);
+        S.ntiles = (int)tiles.size() - S.tile_off;
+        if (S.ch.order == ORDER_QUEUE) {
+            S.grid = std::max(1, std::min(S.ntiles, 256 * 2));     // 2 work-groups of 1024 threads per CU
+            S.counter_off = ncounters;
+            ncounters += p.warps * S.lpw * kNq;
+        } else {
+            S.grid = S.ntiles;
+        }
+        P->stages.push_back(S);
+    }
+    P->ncounters = ncounters;
+
+    // device scalars
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t r = o; o = (o + b + 255) & ~(size_t)255; return r; };
+    P->at_off = take(sizeof(float) * 2 * n);
+    P->epart_off = take(sizeof(double) * kEnergyTerms * kEnergyBlocks * n);
+    P->eout_off = take(sizeof(double) * kEnergyTerms * n);
+    P->cnt_off = take(sizeof(unsigned) * std::max(1, ncounters));
+    P->dyn_bytes = o;
+    {
+        flow_status st = B.dyn.ensure(P->dyn_bytes, "batch scalars");
         if (st != FLOW_OK) return st;
     }
+    float* d_at = (float*)(B.dyn.d + P->at_off);
+    double* d_epart = (double*)(B.dyn.d + P->epart_off);
+    double* d_eout = (double*)(B.dyn.d + P->eout_off);
+
+    // tables
+    TableBuilder T;
+    std::vector<TbLevel> descs(2 * std::max(1, ndesc));
+    for (int k = 0; k < n; ++k)
+        for (int l = 0; l < P->levels[k]; ++l)
+            fill_tb_level(&descs[2 * desc_id[k * FLOW_MAX_LEVELS + l]], P->L[k][l], d_at + 2 * k);
+    P->descs_off = T.put(descs);
+    P->tiles_off = T.put(tiles);
+    // pyramid
+    P->down.resize(P->lmax);
+    for (int l = 1; l < P->lmax; ++l) {
+        std::vector<DownArgs> it;
+        std::vector<int> bl;
+        for (int k = 0; k < n; ++k) {
+            if (P->levels[k] <= l) continue;
+            const LevelPlanes& F = P->L[k][l - 1];
+            const LevelPlanes& C = P->L[k][l];
+            it.push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
+            it.push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
+            bl.push_back(blocks_of(C.H, C.W));
+            bl.push_back(blocks_of(C.H, C.W));
+        }
+        P->down[l] = T.launch(it, bl);
+    }
+    {
+        std::vector<DerivArgs> it;
+        std::vector<int> bl;
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < P->levels[k]; ++l) {
+                const LevelPlanes& L = P->L[k][l];
+                it.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld});
+                bl.push_back(blocks_of(L.H, L.W));
+            }
+        P->deriv = T.launch(it, bl);
+    }
+    // stages: level start, per-warp linearisation and commit; the state buffer after each warp
+    // follows from the number of tile launches (every pair of a stage has the same schedule)
+    std::vector<int> final_cur_of_stage(P->lmax, 0);
+    for (BStage& S : P->stages) {
+        const int l = S.l;
+        std::vector<LevelInitArgs> init;
+        std::vector<int> bl;
+        for (int k : S.pairs) {
+            const LevelPlanes& L = P->L[k][l];
+            LevelInitArgs ia{};
+            ia.H = L.H; ia.W = L.W; ia.ld = L.ld;
+            if (l < P->levels[k] - 1) {
+                const LevelPlanes& C = P->L[k][l + 1];
+                const int cc = final_cur_of_stage[l + 1];
+                ia.uc = level_flow(C, p, 1, cc);
+                ia.vc = level_flow(C, p, 2, cc);
+                ia.wc = hw ? level_flow(C, p, 0, cc) : nullptr;
+                ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
+            }
+            ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
+            ia.set_flow[1] = L.U0[0];
+            ia.set_flow[2] = L.U0[1];
+            int nz = 0;
+            for (int q = 3; q < 10; ++q)
+                if (L.st[0][q]) ia.zero[nz++] = L.st[0][q];
+            ia.nzero = nz;
+            ia.clear_scalar = d_at + 2 * k;
+            init.push_back(ia);
+            bl.push_back(blocks_of(L.H, L.W));
+        }
+        S.init = T.launch(init, bl);
+        int cur = 0;
+        for (int w = 0; w < p.warps; ++w) {
+            std::vector<LinArgs> lin;
+            for (int k : S.pairs) {
+                const LevelPlanes& L = P->L[k][l];
+                LinArgs la{};
+                la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+                la.u0 = L.U0[0];
+                la.v0 = L.U0[1];
+                la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
+                la.at = d_at + 2 * k + (w & 1);
+                la.at_clear = d_at + 2 * k + ((w + 1) & 1);
+                la.H = L.H; la.W = L.W; la.ld = L.ld;
+                la.kappa = (float)p.intensity_scale;
+                la.beta = (float)p.beta;
+                la.rel = 1;
+                la.zero_u = L.st[cur][1];
+                la.zero_v = L.st[cur][2];
+                lin.push_back(la);
+            }
+            S.lin.push_back(T.launch(lin, bl));
+            cur ^= S.lpw & 1;
+            std::vector<CommitArgs> cm;
+            for (int k : S.pairs) {
+                const LevelPlanes& L = P->L[k][l];
+                cm.push_back(CommitArgs{L.U0[0], L.U0[1], L.st[cur][1], L.st[cur][2], L.H, L.W, L.ld});
+            }
+            S.commit.push_back(T.launch(cm, bl));
+        }
+        final_cur_of_stage[l] = cur;
+    }
+    P->final_cur = final_cur_of_stage[0];
+    {
+        // energy of every pair at the end of level 0, before the last commit
+        Scratch dummy;
+        std::vector<EnergyArgs> it;
+        std::vector<int> bl;
+        for (int k = 0; k < n; ++k) {
+            const LevelPlanes& L = P->L[k][0];
+            EnergyArgs e = energy_args(L, p, P->final_cur, dummy);
+            e.partial = d_epart + (size_t)k * kEnergyTerms * kEnergyBlocks;
+            e.out = d_eout + (size_t)k * kEnergyTerms;
+            it.push_back(e);
+            bl.push_back(energy_blocks(L.H, L.W));
+        }
+        P->energy = T.launch(it, bl);
+    }
+    {
+        flow_status st = B.tab.ensure(T.h.size(), "batch tables");
+        if (st != FLOW_OK) return st;
+        HIP_TRY(hipMemcpy(B.tab.d, T.h.data(), T.h.size(), hipMemcpyHostToDevice));
+    }
+    // io table: import (I0, I1 -> level 0) and export (U0 -> u, v) items, rewritten per call; the
+    // block offsets depend on the composition only and are written once into the staging copy
+    {
+        std::vector<int> bl;
+        for (int k = 0; k < n; ++k) {
+            bl.push_back(blocks_of(pairs[k].H, pairs[k].W));
+            bl.push_back(blocks_of(pairs[k].H, pairs[k].W));
+        }
+        std::vector<CopyArgs> blank(2 * n);
+        TableBuilder io;
+        P->imp = io.launch(blank, bl);
+        P->exp = io.launch(blank, bl);
+        P->io_bytes = io.h.size();
+        flow_status st = B.io.ensure(P->io_bytes, "batch io table");
+        if (st != FLOW_OK) return st;
+        st = B.h_io.ensure(P->io_bytes);
+        if (st != FLOW_OK) return st;
+        std::memcpy(B.h_io.h, io.h.data(), io.h.size());
+    }
+    B.plan = std::move(P);
+    return FLOW_OK;
+}
+
+// Fills the per-call import / export items (caller pointers) into the pinned staging table.
+void fill_io(BatchState& B, int n, const flow_pair* pairs, const flow_params& p) {
+    const BatchPlan& P = *B.plan;
+    CopyArgs* ci = (CopyArgs*)(B.h_io.h + P.imp.items);
+    CopyArgs* ce = (CopyArgs*)(B.h_io.h + P.exp.items);
+    (void)p;
+    for (int k = 0; k < n; ++k) {
+        const LevelPlanes& L = P.L[k][0];
+        const flow_pair& q = pairs[k];
+        ci[2 * k] = CopyArgs{q.I0, q.H, q.W, q.ld, L.I0, L.ld};
+        ci[2 * k + 1] = CopyArgs{q.I1, q.H, q.W, q.ld, L.I1, L.ld};
+        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv};
+        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv};
+    }
+}
+
+void run_b(BatchOp op, const char* base, const BLaunch& L, bool f16, hipStream_t s) {
+    launch_batched(op, base + L.items, (const int*)(base + L.off), L.n, L.total, f16, s);
+}
+
+// The tile launches of one warp of stage S (returns the state buffer after them).
+int enqueue_stage_iters(const BatchState& B, const BStage& S, const flow_params& p, int w, int cur, hipStream_t s) {
+    const BatchPlan& P = *B.plan;
+    const bool hw = p.beta > 0;
+    AdmmIterArgs co{};
+    fill_admm_coeffs(co, p);
+    TbArgs a{};
+    a.tiles = (const TbTile*)(B.tab.d + P.tiles_off) + S.tile_off;
+    a.ntiles = S.ntiles;
+    a.levels = (const TbLevel*)(B.tab.d + P.descs_off);
+    a.at_slot = w & 1;
+    a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
+    a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
+    unsigned* counters = (unsigned*)(B.dyn.d + P.cnt_off);
+    int k = 0, li = 0;
+    while (k < p.iters) {
+        const int kk = std::min(S.ch.K, p.iters - k);
+        a.dir = cur;
+        a.K = kk;
+        if (S.ch.order == ORDER_QUEUE) {
+            a.queue = counters + S.counter_off + (w * S.lpw + li) * kNq;
+            a.queue_base = 0;
+            a.nq = std::min(kNq, S.grid);
+        } else {
+            a.queue = nullptr;
+            a.nq = 1;
+        }
+        launch_admm_tb(a, hw, kBatchNt, S.grid, s);
+        cur ^= 1;
+        k += kk;
+        ++li;
+    }
+    return cur;
+}
+
+void enqueue_batch(const BatchState& B, const flow_params& p, hipStream_t s, hipEvent_t* ev) {
+    const BatchPlan& P = *B.plan;
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    const char* tab = B.tab.d;
+    run_b(BatchOp::Copy, B.io.d, P.imp, f16, s);                         // import
+    if (P.ncounters > 0) launch_reset_u32((unsigned*)(B.dyn.d + P.cnt_off), P.ncounters, s);
+    for (int l = 1; l < P.lmax; ++l) run_b(BatchOp::Downsample, tab, P.down[l], f16, s);
+    run_b(BatchOp::Derivatives, tab, P.deriv, f16, s);
+    int si = 0;
+    for (const BStage& S : P.stages) {
+        run_b(BatchOp::LevelInit, tab, S.init, false, s);
+        int cur = 0;
+        if (ev) hipEventRecord(ev[2 * si], s);
+        for (int w = 0; w < p.warps; ++w) {
+            run_b(BatchOp::Linearize, tab, S.lin[w], f16, s);
+            cur = enqueue_stage_iters(B, S, p, w, cur, s);
+            if (S.l == 0 && w == p.warps - 1)
+                launch_energy_batched((const EnergyArgs*)(tab + P.energy.items), (const int*)(tab + P.energy.off),
+                                      P.energy.n, P.energy.total, s);
+            run_b(BatchOp::Commit, tab, S.commit[w], false, s);
+        }
+        if (ev) hipEventRecord(ev[2 * si + 1], s);
+        ++si;
+    }
+    run_b(BatchOp::Copy, B.io.d, P.exp, false, s);                       // export
+}
+
+BatchState& batch_of(flow_ctx* ctx) {
+    if (!ctx->batch) ctx->batch = new BatchState();
+    return *ctx->batch;
+}
+
+flow_status prepare(flow_ctx* ctx, int n, const flow_pair* pairs, const flow_params& p) {
+    BatchState& B = batch_of(ctx);
+    const std::string key = batch_key(n, pairs, p) + "|te" + std::to_string(B.tune_epoch);
+    if (B.plan && B.plan->key == key) return FLOW_OK;
+    B.drop_graph();
+    B.plan.reset();
+    flow_status st = build_plan(ctx, B, n, pairs, p);
+    if (st != FLOW_OK) return st;
+    B.plan->key = key;
+    return FLOW_OK;
+}
+
+}  // namespace
+
+extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                                          void* stream) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && !pairs)) return fail(FLOW_E_INVAL, "bad batch arguments");
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    st = validate_pairs(n, pairs, *p);
+    if (st != FLOW_OK) return st;
+    if (n == 0) return FLOW_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (p->scheme == FLOW_PDR || p->tol > 0) {
+        // pDR and stopping tests: plain solves in turn
+        for (int32_t k = 0; k < n; ++k) {
+            flow_params pk = *p;
+            if (pairs[k].levels > 0) pk.levels = pairs[k].levels;
+            const flow_pair& q = pairs[k];
+            st = flow_solve(ctx, q.I0, q.I1, q.H, q.W, q.ld, &pk, q.u, q.v, q.ld_uv, q.res, stream);
+            if (st != FLOW_OK) return st;
+        }
+        return FLOW_OK;
+    }
+    st = prepare(ctx, n, pairs, *p);
+    if (st != FLOW_OK) return st;
+    BatchState& B = *ctx->batch;
+    const BatchPlan& P = *B.plan;
+    fill_io(B, n, pairs, *p);
+    HIP_TRY(hipMemcpyAsync(B.io.d, B.h_io.h, P.io_bytes, hipMemcpyHostToDevice, s));
+    const bool timed = ctx->stats_enabled;
+    if (timed) HIP_TRY(hipEventRecord(ctx->ev_total[0], s));
+    const bool use_graph = p->use_graph && !timed;
+    if (use_graph) {
+        if (!B.exec) {
+            HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            enqueue_batch(B, *p, ctx->cap_stream, nullptr);
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamEndCapture(ctx->cap_stream, &g));
+            B.graph = g;
+            HIP_TRY(hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0));
+        }
+        HIP_TRY(hipGraphLaunch(B.exec, s));
+    } else {
+        while (B.ev.size() < 2 * P.stages.size()) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            B.ev.push_back(e);
+        }
+        enqueue_batch(B, *p, s, timed ? B.ev.data() : nullptr);
+    }
+    HIP_TRY(hipGetLastError());
+    if (timed) HIP_TRY(hipEventRecord(ctx->ev_total[1], s));
+    st = B.h_e.ensure(sizeof(double) * kEnergyTerms * n);
+    if (st != FLOW_OK) return st;
+    HIP_TRY(hipMemcpyAsync(B.h_e.h, B.dyn.d + P.eout_off, sizeof(double) * kEnergyTerms * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (timed) {
+        flow_stats S{};
+        S.levels = P.lmax;
+        int64_t pxi = 0;
+        for (size_t si = 0; si < P.stages.size(); ++si) {
+            const BStage& G = P.stages[si];
+            int64_t px = 0;
+            for (int k : G.pairs) px += (int64_t)P.L[k][G.l].H * P.L[k][G.l].W;
+            S.level_px[G.l] = px;
+            S.H[G.l] = 0;
+            S.W[G.l] = 0;
+            S.iterations[G.l] = (int64_t)p->warps * p->iters;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, B.ev[2 * si], B.ev[2 * si + 1]);
+            S.iter_ms[G.l] = ms;
+            pxi += px * S.iterations[G.l];
+        }
+        float tot = 0.f;
+        hipEventElapsedTime(&tot, ctx->ev_total[0], ctx->ev_total[1]);
+        S.total_ms = tot;
+        S.px_iter = pxi;
+        S.graph_replayed = 0;
+        ctx->last_stats = S;
+    }
+    bool finite = true;
+    const double* h = (const double*)B.h_e.h;
+    for (int k = 0; k < n; ++k) {
+        const double* e = h + (size_t)k * kEnergyTerms;
+        fill_result(e, pairs[k].res);
+        if (!std::isfinite(e[0] + e[1]) || !std::isfinite(e[2]) || e[7] != 0.0) finite = false;
+    }
+    if (!finite) return fail(FLOW_E_NONFINITE, "non-finite energy or gap in a batched pair");
+    return FLOW_OK;
+}
+
+extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                                             void* stream) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && !pairs)) return fail(FLOW_E_INVAL, "bad batch arguments");
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    st = validate_pairs(n, pairs, *p);
+    if (st != FLOW_OK) return st;
+    if (n == 0 || p->scheme == FLOW_PDR || p->iters < 1) return FLOW_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    st = prepare(ctx, n, pairs, *p);
+    if (st != FLOW_OK) return st;
+    BatchState& B = *ctx->batch;
+    BatchPlan& P = *B.plan;
+    const bool hw = p->beta > 0;
+    const bool f16 = p->storage == FLOW_STORE_F16;
+    fill_io(B, n, pairs, *p);
+    HIP_TRY(hipMemcpyAsync(B.io.d, B.h_io.h, P.io_bytes, hipMemcpyHostToDevice, s));
+    const char* tab = B.tab.d;
+    run_b(BatchOp::Copy, B.io.d, P.imp, f16, s);
+    for (int l = 1; l < P.lmax; ++l) run_b(BatchOp::Downsample, tab, P.down[l], f16, s);
+    run_b(BatchOp::Derivatives, tab, P.deriv, f16, s);
+    std::vector<int> desc_id(n * FLOW_MAX_LEVELS, -1);
+    int ndesc = 0;
+    for (int k = 0; k < n; ++k)
+        for (int l = 0; l < P.levels[k]; ++l) desc_id[k * FLOW_MAX_LEVELS + l] = ndesc++;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // candidate tables live in a temporary buffer; the plan's own tables stay as they are
+    DevBuf tmp_tiles, tmp_cnt;
+    st = tmp_cnt.ensure(256, "tuning counters");
+    std::map<std::string, StageChoice> chosen;
+    for (BStage& S : P.stages) {
+        if (st != FLOW_OK) break;
+        run_b(BatchOp::LevelInit, tab, S.init, false, s);
+        run_b(BatchOp::Linearize, tab, S.lin[0], f16, s);
+        std::vector<StageChoice> cands;
+        const bool all_res = stage_all_resident(P, S, hw);
+        for (int order : {ORDER_TABLE, ORDER_QUEUE}) {
+            if (all_res) {
+                StageChoice c;
+                c.order = order;
+                c.K = p->iters;
+                cands.push_back(c);
+            }
+            for (int K : {2, 4, 8})
+                for (int ew : {64, 128})
+                    if (stage_fits(P, S, hw, K, ew)) {
+                        StageChoice c;
+                        c.order = order;
+                        c.K = K;
+                        c.ew = ew;
+                        cands.push_back(c);
+                    }
+        }
+        double best = 1e30;
+        StageChoice bestc = S.ch;
+        for (const StageChoice& c : cands) {
+            std::vector<TbTile> tl;
+            stage_tiles(P, S, hw, c, desc_id, tl);
+            st = tmp_tiles.ensure(sizeof(TbTile) * tl.size(), "tuning tiles");
+            if (st != FLOW_OK) break;
+            HIP_TRY(hipMemcpy(tmp_tiles.d, tl.data(), sizeof(TbTile) * tl.size(), hipMemcpyHostToDevice));
+            BStage T = S;
+            T.ch = c;
+            T.lpw = launches_per_warp(p->iters, c.K);
+            T.ntiles = (int)tl.size();
+            T.grid = c.order == ORDER_QUEUE ? std::max(1, std::min(T.ntiles, 512)) : T.ntiles;
+            AdmmIterArgs co{};
+            fill_admm_coeffs(co, *p);
+            float best_ms = 1e30f;
+            for (int rep = 0; rep < 4; ++rep) {               // the first run is a warm-up
+                HIP_TRY(hipEventRecord(e0, s));
+                int cur = 0, k = 0;
+                while (k < p->iters) {
+                    const int kk = std::min(c.K, p->iters - k);
+                    TbArgs a{};
+                    a.tiles = (const TbTile*)tmp_tiles.d;
+                    a.ntiles = T.ntiles;
+                    a.levels = (const TbLevel*)(tab + P.descs_off);
+                    a.at_slot = 0;
+                    a.dir = cur;
+                    a.K = kk;
+                    a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
+                    a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
+                    if (c.order == ORDER_QUEUE) {
+                        launch_reset_u32((unsigned*)tmp_cnt.d, kNq, s);
+                        a.queue = (unsigned*)tmp_cnt.d;
+                        a.nq = std::min(kNq, T.grid);
+                    } else {
+                        a.nq = 1;
+                    }
+                    launch_admm_tb(a, hw, kBatchNt, T.grid, s);
+                    cur ^= 1;
+                    k += kk;
+                }
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) best_ms = std::min(best_ms, ms);
+            }
+            HIP_TRY(hipGetLastError());
+            if (best_ms < best) {
+                best = best_ms;
+                bestc = c;
+            }
+        }
+        chosen[S.key] = bestc;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    tmp_tiles.release();
+    tmp_cnt.release();
+    if (st != FLOW_OK) return st;
+    for (auto& kv : chosen) B.tuned[kv.first] = kv.second;
+    B.tune_epoch++;
+    B.drop_graph();
+    B.plan.reset();
     return FLOW_OK;
 }

@@ -126,7 +126,7 @@ flow_status flow_ctx::init_scratch() {
     return scratch.alloc();
 }
 
-size_t flow_ctx::bytes_in_use() const { return arena.bytes + scratch.bytes(); }
+size_t flow_ctx::bytes_in_use() const { return arena.bytes + scratch.bytes() + flowmi::batch_bytes(batch); }
 
 void flow_ctx::drop_graphs() {
     for (auto& kv : graphs) {
@@ -139,7 +139,7 @@ void flow_ctx::drop_graphs() {
 
 flow_status flow_ctx::ensure_arena(size_t need) {
     if (arena.bytes >= need) return FLOW_OK;
-    if (budget && need + scratch.bytes() > budget)
+    if (budget && need + scratch.bytes() + batch_bytes(batch) > budget)
         return fail(FLOW_E_NOMEM, "working set of " + std::to_string(need) + " bytes exceeds the HBM budget");
     drop_graphs();
     if (arena.base) {
@@ -225,6 +225,7 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
         int64_t pxi = 0;
         for (int l = 0; l < S.levels; ++l) {
             S.H[l] = Ls[l].H;
+            S.level_px[l] = (int64_t)Ls[l].H * Ls[l].W;
             S.W[l] = Ls[l].W;
             S.iterations[l] = replayed ? (int64_t)p.warps * p.iters : timers.launches[l];
             pxi += (int64_t)Ls[l].H * Ls[l].W * S.iterations[l];

@@ -495,6 +495,21 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         g_tb_k = (int)value;
         return FLOW_OK;
     }
+    if (std::strcmp(key, "batch_order") == 0) {
+        if (value < -1 || value > 1) return fail(FLOW_E_INVAL, "batch_order: -1 tuned / built-in, 0 table, 1 queue");
+        g_batch_order = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "batch_k") == 0) {
+        if (value < 0 || value > 64) return fail(FLOW_E_INVAL, "batch_k: 0 (tuned / built-in) .. 64");
+        g_batch_k = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "batch_ew") == 0) {
+        if (value != 0 && (value < 16 || value > 512)) return fail(FLOW_E_INVAL, "batch_ew: 0 (tuned / built-in) or 16 .. 512");
+        g_batch_ew = (int)value;
+        return FLOW_OK;
+    }
     return fail(FLOW_E_INVAL, std::string("unknown tuning key ") + key);
 }
 
@@ -663,7 +678,7 @@ flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* 
 
 flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* out, const float* Ix, const float* Iy,
                             const float* It, const float* at, int32_t H, int32_t W, int64_t ld, const flow_params* p,
-                            int32_t iters, int32_t threads, int32_t tile_h, int32_t tile_w, int32_t use_queue,
+                            int32_t iters, int32_t threads, int32_t tile_h, int32_t tile_w, int32_t order,
                             void* stream) {
     flow_status st = validate(p);
     if (st != FLOW_OK) return st;
@@ -674,6 +689,7 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
     if (threads != 256 && threads != 1024 && threads != 1025)
         return fail(FLOW_E_INVAL, "threads must be 256, 1024 or 1025 (1024 threads, small tiles)");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
+    if (order < 0 || order > 3) return fail(FLOW_E_INVAL, "order must be 0, 1, 2 or 3");
     const bool hw = p->beta > 0;
     const int cap = tb_capacity(hw, threads);
     if ((int64_t)std::min<int64_t>(H, (int64_t)tile_h + 3 * iters) * std::min<int64_t>(W, (int64_t)tile_w + 3 * iters) > cap)
@@ -712,19 +728,23 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
     unsigned* q = nullptr;
     HIP_TRY(hipMalloc(&q, 256));
     hipStream_t s = (hipStream_t)stream;
-    launch_reset_u32(q, 1, s);
+    launch_reset_u32(q, 8, s);
+    const bool use_queue = order == 1 || order == 2;
+    const int grid = use_queue ? tb_grid(P, P.ntiles) : P.ntiles;
     AdmmIterArgs co{};
     fill_admm_coeffs(co, *p);
     TbArgs a{};
-    a.tiles = tab.d_tiles; a.ntiles = P.ntiles; a.levels = tab.d_levels; a.dir = 0; a.K = iters; a.at_slot = 0;
+    a.tiles = order == 0 ? nullptr : tab.d_tiles;
+    a.ntiles = P.ntiles; a.levels = tab.d_levels; a.dir = 0; a.K = iters; a.at_slot = 0;
     a.queue = use_queue ? q : nullptr; a.queue_base = 0;
+    a.nq = order == 2 ? std::min(8, grid) : 1;
     a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
     a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
     a.lvl = descs[0];
     a.th = tile_h;
     a.tw = tile_w;
     a.ntx = (W + tile_w - 1) / tile_w;
-    launch_admm_tb(a, hw, threads, use_queue ? tb_grid(P, P.ntiles) : P.ntiles, s);
+    launch_admm_tb(a, hw, threads, grid, s);
     hipError_t e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(s);
     hipFree(q);

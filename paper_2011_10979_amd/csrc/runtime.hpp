@@ -79,6 +79,7 @@ void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p);
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
                          WarpTimers* timers, StopTest* stop, const SolvePlan* plan);
 const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur);
+EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc);
 void fill_result(const double* h, flow_result* r);
 std::string graph_key(int H, int W, const flow_params& p, const void* arena, int tune_epoch);
 
@@ -109,7 +110,13 @@ struct TunedChoice {
 std::string tune_key(int H, int W, bool hw, int iters);
 extern int g_tb_mode;
 extern int g_tb_k;
+extern int g_batch_order;   // batched tile launches: -1 tuned / built-in, 0 table order, 1 work queue
+extern int g_batch_k;       // 0 tuned / built-in, else iterations per batched tile launch
+extern int g_batch_ew;      // 0 tuned / built-in, else extended tile width target
 LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq);
+// Tiles of work-group size nt (256, 1024, 1025) for K iterations per launch with extended tiles about
+// ew_target wide (0: built-in); K is lowered until the tile fits; resident if the level fits one tile.
+LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target);
 LevelTbPlan plan_level_tuned(int H, int W, bool hw, int iters, const std::map<std::string, TunedChoice>* tuned);
 void append_tiles(const LevelTbPlan& P, int level_id, int H, int W, std::vector<TbTile>& out);
 void fill_tb_level(TbLevel* d, const LevelPlanes& L, const float* at2);
@@ -145,6 +152,7 @@ struct GraphEntry {
 
 struct BatchState;   // batch.cpp
 void destroy_batch(BatchState* b);
+size_t batch_bytes(const BatchState* b);
 
 }  // namespace flowmi
 

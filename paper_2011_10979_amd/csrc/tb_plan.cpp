@@ -23,6 +23,29 @@ static bool fit_tile(int H, int W, int cap, int K, int ew_target, int& th, int& 
     return tw >= 8 && th >= 2 && (int64_t)std::min(W, tw + 3 * K) * std::min(H, th + 3 * K) <= cap;
 }
 
+LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
+    LevelTbPlan P;
+    const int cap = tb_capacity(hw, nt);
+    P.nt = nt;
+    if ((int64_t)H * W <= cap) {                             // one tile covers the level, no halo
+        P.tb = true;
+        P.resident = true;
+        P.K = K;
+        P.th = H;
+        P.tw = W;
+        return P;
+    }
+    if (ew_target <= 0) ew_target = nt == 1024 ? (hw ? 80 : 96) : (nt == 1025 ? 64 : (hw ? 32 : 48));
+    int th = 0, tw = 0;
+    while (K > 0 && !fit_tile(H, W, cap, K, ew_target, th, tw)) --K;
+    if (K < 1) return P;
+    P.tb = true;
+    P.K = K;
+    P.th = th;
+    P.tw = tw;
+    return P;
+}
+
 LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
     LevelTbPlan P;
     if (mode == 1 || iters < 2) return P;                    // one-pass kernel
@@ -39,26 +62,8 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
         return P;
     }
     const int nt = (mode == 3) ? 1024 : (mode == 4 ? 1025 : 256);
-    const int cap = tb_capacity(hw, nt);
-    if ((int64_t)H * W <= cap) {                             // the whole level stays resident
-        P.tb = true;
-        P.nt = nt;
-        P.resident = true;
-        P.K = iters;
-        P.th = H;
-        P.tw = W;
-        return P;
-    }
-    int K = kreq > 0 ? kreq : kDefaultK;
-    const int ew_target = nt == 1024 ? (hw ? 80 : 96) : (nt == 1025 ? 64 : (hw ? 32 : 48));
-    int th = 0, tw = 0;
-    while (K > 0 && !fit_tile(H, W, cap, K, ew_target, th, tw)) --K;
-    if (K < 1) return P;
-    P.tb = true;
-    P.nt = nt;
-    P.K = K;
-    P.th = th;
-    P.tw = tw;
+    P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, 0);
+    if (P.resident) P.K = iters;                             // the whole warp in one launch
     return P;
 }
 

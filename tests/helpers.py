@@ -56,3 +56,37 @@ def random_lin(rng, shape, beta):
 
 def max_abs(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(a) else 0.0
+
+
+def _oracle_job(args):
+    from oracle import Params as OParams, solve_pair
+    I0, I1, kw = args
+    r = solve_pair(I0, I1, OParams(**kw))
+    return r["u"], r["v"], (r["energy"], r["gap"])
+
+
+def oracle_with_sensitivity(jobs, pool):
+    """Start the FP64 oracle on every (I0, I1, kwargs) job and on a copy of its frames perturbed by
+    1e-7 relative (seeded), in `pool`; returns an AsyncResult of [(ref, perturbed), ...]."""
+    rng = np.random.default_rng(123)
+    work = []
+    for I0, I1, kw in jobs:
+        P0 = I0 * (1 + 1e-7 * rng.standard_normal(I0.shape))
+        P1 = I1 * (1 + 1e-7 * rng.standard_normal(I1.shape))
+        work += [(I0, I1, kw), (P0, P1, kw)]
+    return pool.map_async(_oracle_job, work)
+
+
+def assert_conditioned(name, u, v, res, ref, pert):
+    """Per-pixel bar 1e-4 px + 10 x the oracle's own response to the input perturbation (max over a
+    5 x 5 neighbourhood); energy / gap within 1e-6 / 1e-5 of the energy, widened likewise."""
+    import scipy.ndimage
+    ru, rv, (re, rgap) = ref
+    pu, pv, (pe, pgap) = pert
+    d = np.maximum(np.abs(u - ru), np.abs(v - rv))
+    sens = scipy.ndimage.maximum_filter(np.maximum(np.abs(pu - ru), np.abs(pv - rv)), size=5, mode="nearest")
+    print(f"[parity] {name}: max {d.max():.3e} p99.9 {np.quantile(d, 0.999):.3e} mean {d.mean():.3e}; "
+          f"sensitivity max {sens.max():.2e}; energy {res['energy']:.4f} vs {re:.4f}", flush=True)
+    assert np.all(d <= 1e-4 + 10.0 * sens), float((d - 1e-4 - 10.0 * sens).max())
+    assert abs(res["energy"] - re) <= 1e-6 * re + 10.0 * abs(pe - re), (res["energy"], re, pe)
+    assert abs(res["gap"] - rgap) <= 1e-5 * re + 10.0 * abs(pgap - rgap), (res["gap"], rgap, pgap)

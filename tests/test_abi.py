@@ -97,3 +97,26 @@ def test_binding_allocates_outputs_with_the_input_pitch():
         fm._same_layout(t, [("out", o)], "op")
     finally:
         fm._plane = monkey
+
+
+@pytest.mark.parametrize("cname,pyname", [("flow_params", "_Params"), ("flow_result", "_Result"),
+                                          ("flow_stats", "_Stats"), ("flow_pair", "_Pair"),
+                                          ("flow_admm_state", "_AdmmState"), ("flow_pdr_state", "_PdrState")])
+def test_struct_layouts_match_the_header(tmp_path, cname, pyname):
+    """Size and every field offset of the ctypes mirror equal what a C compiler makes of flow.h."""
+    import paper_2011_10979_amd as fm
+    py = getattr(fm, pyname)
+    fields = [f[0] for f in py._fields_]
+    cfields = {"lam": "lambda"}
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {",
+           f'  printf("%zu\\n", sizeof({cname}));']
+    for f in fields:
+        src.append(f'  printf("%zu\\n", offsetof({cname}, {cfields.get(f, f)}));')
+    src.append("  return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(c)], check=True, capture_output=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(py)
+    assert got[1:] == [getattr(py, f).offset for f in fields]

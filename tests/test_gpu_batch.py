@@ -1,0 +1,154 @@
+"""Batched solves: many pairs of uneven sizes advanced together, one launch per pipeline step over
+all pairs (tile table in XCD order or per-XCD work queues).
+
+Checks: parity of every batched pair with the FP64 oracle (same per-pixel bar as plain solves);
+a pair's results are bitwise the same alone, in a mix, under every stage choice (order, K, tile
+width, autotuned), and equal to a plain solve that uses the same tile kernel at every level;
+graph replays pick up new frames; invalid pairs are rejected before anything runs.
+"""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2011_10979_amd as fm  # noqa: E402
+import synth  # noqa: E402
+from helpers import to_dev, to_np, f32, oracle_with_sensitivity, assert_conditioned  # noqa: E402
+
+KW = dict(levels=3, warps=2, iters=30)
+# (H, W, seed, levels): uneven sides, ragged tiles, a pair with fewer levels, a tiny one
+MIX = [(70, 90, 31, 0), (45, 130, 32, 0), (33, 35, 33, 2), (96, 128, 34, 0), (20, 300, 35, 2)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(autouse=True)
+def reset_knobs():
+    yield
+    for k, v in (("tb_mode", 0), ("tb_k", 0), ("batch_order", -1), ("batch_k", 0), ("batch_ew", 0)):
+        fm.set_tuning(k, v)
+
+
+def frames(spec, pad=0):
+    out = []
+    for H, W, seed, lv in spec:
+        p = synth.vga_pair(seed=seed, H=H, W=W)
+        out.append((f32(p.I0), f32(p.I1), lv, to_dev(f32(p.I0), pad), to_dev(f32(p.I1), pad)))
+    return out
+
+
+def batched(ctx, fr, **kw):
+    return ctx.solve_batched([(d0, d1, lv) for _, _, lv, d0, d1 in fr], fm.Params(**kw))
+
+
+def same(a, b):
+    return all(torch.equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2]["energy"] == b[2]["energy"] \
+        and a[2]["gap"] == b[2]["gap"]
+
+
+@pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
+def test_batched_pairs_match_the_oracle(ctx, scheme, relax, beta):
+    print(f"[case] batched parity {scheme} {beta}", flush=True)
+    fr = frames(MIX[:4], pad=3)
+    kw = dict(KW, scheme=scheme, relax=relax, beta=beta)
+    okw = dict(KW, scheme=scheme, relax=relax, beta=beta)
+    jobs = []
+    for I0, I1, lv, _, _ in fr:
+        jobs.append((I0, I1, dict(okw, levels=lv or KW["levels"])))
+    with mp.get_context("fork").Pool(4) as pool:
+        fut = oracle_with_sensitivity(jobs, pool)
+        out = batched(ctx, fr, **kw)
+        refs = fut.get(timeout=900)
+    for k, (u, v, res) in enumerate(out):
+        assert_conditioned(f"batched pair {k} {MIX[k][:2]}", to_np(u), to_np(v), res, refs[2 * k], refs[2 * k + 1])
+
+
+def test_batched_equals_plain_tile_solves_bitwise(ctx):
+    print("[case] batched vs plain mode-4 solves", flush=True)
+    fr = frames(MIX, pad=2)
+    out = batched(ctx, fr, **KW)
+    fm.set_tuning("tb_mode", 4)        # plain solves on small 1024-thread tiles at every level
+    for k, (I0, I1, lv, d0, d1) in enumerate(fr):
+        u, v, res = ctx.solve(d0, d1, fm.Params(**dict(KW, levels=lv or KW["levels"])))
+        assert same(out[k], (u, v, res)), f"pair {k}"
+
+
+@pytest.mark.parametrize("order,K,ew", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 8, 128), (0, 5, 96), (1, 3, 64)])
+def test_pair_alone_equals_pair_in_mix_under_every_choice(ctx, order, K, ew):
+    print(f"[case] alone vs mix order={order} K={K} ew={ew}", flush=True)
+    fr = frames(MIX)
+    alone = batched(ctx, [fr[3]], **KW)[0]
+    fm.set_tuning("batch_order", order)
+    fm.set_tuning("batch_k", K)
+    fm.set_tuning("batch_ew", ew)
+    mix = batched(ctx, [fr[1], fr[3], fr[0], fr[4]], **KW)
+    assert same(alone, mix[1])
+    mix2 = batched(ctx, fr, **KW)
+    assert same(mix[0], mix2[1]) and same(mix[2], mix2[0]) and same(mix[3], mix2[4])
+
+
+def test_autotuned_batch_keeps_results(ctx):
+    print("[case] batched autotune", flush=True)
+    fr = frames(MIX)
+    before = batched(ctx, fr, **KW)
+    ctx.autotune_batched([(d0, d1, lv) for _, _, lv, d0, d1 in fr], fm.Params(**KW))
+    after = batched(ctx, fr, **KW)
+    for a, b in zip(before, after):
+        assert same(a, b)
+
+
+def test_graph_replay_reads_new_frames(ctx):
+    print("[case] batched graph replay", flush=True)
+    fa = frames(MIX[:3])
+    fb = frames([(H, W, seed + 100, lv) for H, W, seed, lv in MIX[:3]])
+    g = dict(KW, use_graph=1)
+    batched(ctx, fa, **g)
+    rep = [batched(ctx, fb, **g) for _ in range(3)]        # replays with other frames
+    direct = batched(ctx, fb, **dict(KW, use_graph=0))
+    for r in rep:
+        for x, y in zip(r, direct):
+            assert same(x, y)
+
+
+def test_f16_storage_batch_matches_plain(ctx):
+    print("[case] batched f16", flush=True)
+    fr = frames(MIX[:3])
+    out = batched(ctx, fr, **KW, storage="f16")
+    fm.set_tuning("tb_mode", 4)
+    for k, (I0, I1, lv, d0, d1) in enumerate(fr):
+        u, v, res = ctx.solve(d0, d1, fm.Params(**dict(KW, levels=lv or KW["levels"], storage="f16")))
+        assert same(out[k], (u, v, res)), f"pair {k}"
+
+
+def test_pdr_batch_runs_plain_solves(ctx):
+    print("[case] batched pdr", flush=True)
+    fr = frames(MIX[:2])
+    out = batched(ctx, fr, **KW, scheme="pdr")
+    for k, (I0, I1, lv, d0, d1) in enumerate(fr):
+        u, v, res = ctx.solve(d0, d1, fm.Params(**dict(KW, levels=lv or KW["levels"], scheme="pdr")))
+        assert same(out[k], (u, v, res))
+
+
+def test_invalid_pairs_are_rejected_before_anything_runs(ctx):
+    print("[case] batched errors", flush=True)
+    fr = frames(MIX[:2])
+    good = (fr[0][3], fr[0][4])
+    tiny = torch.zeros((1, 40), device="cuda")
+    with pytest.raises(fm.FlowError, match="pair 1"):
+        ctx.solve_batched([good, (tiny, tiny)], fm.Params(**KW))
+    with pytest.raises(fm.FlowError, match="pair 0"):
+        ctx.solve_batched([(fr[0][3], fr[0][4], 9)], fm.Params(**KW))   # 70x90 has no 9-level pyramid
+    assert ctx.solve_batched([], fm.Params(**KW)) == []
+    # the context still works afterwards
+    out = batched(ctx, fr, **KW)
+    assert all(np.isfinite(r["energy"]) for _, _, r in out)

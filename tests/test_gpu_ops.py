@@ -220,13 +220,13 @@ def test_admm_iteration_every_strip_height(rows, shape, beta):
 
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 6), ((37, 130), (8, 30), 3), ((101, 250), (12, 20), 4),
                                           ((60, 80), (60, 80), 9), ((64, 64), (10, 18), 1), ((33, 47), (33, 47), 20)])
-@pytest.mark.parametrize("threads,use_queue", [(256, False), (1024, False), (1025, False), (256, True),
-                                               (1024, True)])
+@pytest.mark.parametrize("threads,order", [(256, 0), (1024, 0), (1025, 0), (256, 1), (1024, 1), (1025, 2),
+                                           (1025, 3), (256, 2)])
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
-def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, use_queue, scheme, relax, beta):
+def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme, relax, beta):
     """K iterations of the temporally blocked tile kernel (halo 2K / K, ragged tiles, resident
     levels) against K steps of the oracle on the same increment-form state."""
-    print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, queue=use_queue, scheme=scheme, beta=beta)
+    print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
     cap = 2048 if threads == 1025 else threads * (4 if beta > 0 else 6)
     if min(shape[0], tile[0] + 3 * K) * min(shape[1], tile[1] + 3 * K) > cap:
         pytest.skip("tile plus halo exceeds the kernel capacity")
@@ -246,7 +246,7 @@ def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, use_queue, sch
     at_t = torch.tensor([at, 0.0], dtype=torch.float32, device="cuda")
     out = fm.admm_tb(g, to_dev(Ix, 2), to_dev(Iy, 2), to_dev(Itr, 2), at_t,
                      fm.Params(scheme=scheme, relax=relax, beta=beta), iters=K, threads=threads,
-                     tile_h=tile[0], tile_w=tile[1], use_queue=use_queue)
+                     tile_h=tile[0], tile_w=tile[1], order=order)
     tol = 1e-4 * max(1, K)
     assert max_abs(to_np(out["u"]), full["u"] - u0) < tol
     assert max_abs(to_np(out["v"]), full["v"] - v0) < tol
