@@ -19,6 +19,11 @@ Also reported on the same JSON line:
   per_level     Gpixel-iter/s of each level's iteration blocks
 
 Other modes:
+  --mode batch      64 synthetic pairs of uneven sizes (W ~ U[128, 1280], H ~ U[96, 720], seeds
+                    1000 + k, pyramid depth by size) solved together by the batched path (autotuned
+                    stages, graph replay); value = pixel-iterations of all pairs / step time; reported
+                    beside 64 sequential plain solves of the same pairs (pairs/s, both plain
+                    kernel plans) and a bitwise comparison of every pair with its plain tile solve
   --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
                                       them from F instead of tuning (for profiler runs)
   --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
@@ -84,6 +89,163 @@ def cpu_baseline(pair, args):
                       f"warps x {iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
 
 
+def roofline(ms, launches, iters, px, has_w, kernel, traffic, reps):
+    """HBM roofline of an iteration kernel from event-timed blocks of its launches: algorithmic
+    bytes per launch (BYTES_PER_PX_LAUNCH x pixels) / average launch duration, against 8 TB/s."""
+    per_px = BYTES_PER_PX_LAUNCH[has_w]
+    launch_s = ms * 1e-3 / max(1, launches)
+    bytes_launch = per_px * px
+    achieved = bytes_launch / launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "per_unit": f"{per_px} B per pixel per launch", "bytes_per_launch": bytes_launch,
+            "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step_level0": launches // reps,
+            # the same pixel-iterations priced at one HBM pass per iteration
+            "one_pass_equivalent_GBs": round(per_px * px * iters / (ms * 1e-3) / 1e9, 1)}
+
+
+def _gen_batch_pair(k):
+    import synth
+    p = synth.batch_pair(k)
+    return p.I0.astype("float32"), p.I1.astype("float32")
+
+
+def _oracle_pair(job):
+    from oracle import Params, solve_pair
+    I0, I1, kw = job
+    t0 = time.perf_counter()
+    r = solve_pair(I0.astype("float64"), I1.astype("float64"), Params(**kw))
+    return r["u"], r["v"], time.perf_counter() - t0
+
+
+def run_batch(args):
+    """The batched configuration: 64 uneven pairs in one batched solve vs 64 plain solves."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    import synth
+    import paper_2011_10979_amd as fm
+    n = args.pairs
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        host = pool.map(_gen_batch_pair, range(n))
+    print(f"[bench] generated {n} pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    frames = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev),
+               synth.levels_by_size(*a.shape)) for a, b in host]
+    shapes = [a.shape for a, _ in host]
+    params = fm.Params(scheme=args.scheme, storage=args.storage, warps=args.warps, iters=args.iters, use_graph=1)
+    px_all = 0
+    for (H, W), (_, _, lv) in zip(shapes, frames):
+        h, w = H, W
+        for _ in range(lv):
+            px_all += h * w
+            h, w = (h + 1) // 2, (w + 1) // 2
+    px_iter = px_all * args.warps * args.iters
+    ctx = fm.Context(0)
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        ctx.autotune_batched(frames, params)
+        print(f"[bench] batched autotune {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        out = ctx.solve_batched(frames, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.solve_batched(frames, params)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = px_iter / (ms_step * 1e-3) / 1e9
+    print(f"[bench] batched: {ms_step:.2f} ms per batch, {value:.2f} Gpx-iter/s", file=sys.stderr, flush=True)
+
+    # per-stage timing (direct launches, events around each stage's iterations)
+    ctx.set_stats(True)
+    p_inst = fm.Params(**{**params.__dict__, "use_graph": 0})
+    reps = 2
+    nl = max(lv for _, _, lv in frames)
+    ms = [0.0] * nl
+    launches = [0] * nl
+    iters = [0] * nl
+    for _ in range(reps):
+        ctx.solve_batched(frames, p_inst)
+        s = ctx.stats()
+        for l in range(nl):
+            ms[l] += s["iter_ms"][l]
+            launches[l] += s["launches"][l]
+            iters[l] += s["iterations"][l]
+        level_px = s["level_px"]
+    ctx.set_stats(False)
+    per_level = [{"level": l, "pixels": level_px[l], "Gpx_iter_s": level_px[l] * iters[l] / (ms[l] * 1e-3) / 1e9,
+                  "us_per_launch": 1e3 * ms[l] / max(1, launches[l])} for l in range(nl)]
+    roof = roofline(ms[0], launches[0], iters[0], level_px[0], params.beta > 0,
+                    f"batched tile kernel, level-0 stage ({level_px[0]} px over {n} pairs)", None, reps)
+
+    # 64 sequential plain solves of the same pairs: built-in kernel plan, then tiles at every level
+    plain = {}
+    for label, mode in (("builtin", 0), ("tiles", 4)):
+        fm.set_tuning("tb_mode", mode)
+        outs = []
+        for rep in range(2):                        # the first pass captures each shape's graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs = [ctx.solve(I0, I1, fm.Params(**{**params.__dict__, "levels": lv}))
+                    for I0, I1, lv in frames]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        plain[label] = {"ms": round(dt * 1e3, 3), "pairs_per_s": round(n / dt, 2),
+                        "Gpx_iter_s": round(px_iter / dt / 1e9, 3)}
+        if mode == 4:
+            same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(out, outs))
+            plain[label]["batched_bitwise_equal"] = bool(same)
+    fm.set_tuning("tb_mode", 0)
+    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+
+    # oracle on the smallest pairs: EPE of the batched flow against the FP64 oracle, and the
+    # oracle's own rate on all host cores
+    order = sorted(range(n), key=lambda k: shapes[k][0] * shapes[k][1])[:args.oracle_pairs]
+    jobs = [(host[k][0], host[k][1], dict(scheme=args.scheme, levels=frames[k][2], warps=args.warps,
+                                           iters=args.iters)) for k in order]
+    cpu = None
+    epe = None
+    if jobs and not args.no_cpu_baseline:
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            refs = pool.map(_oracle_pair, jobs)
+        dt = time.perf_counter() - t0
+        epes = []
+        for k, (ru, rv, _) in zip(order, refs):
+            u, v = out[k][0].cpu().numpy(), out[k][1].cpu().numpy()
+            epes.append(float(np.sqrt((u - ru) ** 2 + (v - rv) ** 2).mean()))
+        epe = {"pairs": [list(shapes[k]) for k in order], "mean_epe_vs_oracle": epes, "max": max(epes)}
+        pxi = 0
+        for k in order:
+            h, w = shapes[k]
+            for _ in range(frames[k][2]):
+                pxi += h * w * args.warps * args.iters
+                h, w = (h + 1) // 2, (w + 1) // 2
+        cpu = {"value": round(len(jobs) / dt, 3), "unit": "pairs/s", "cores": min(workers, len(jobs)),
+               "kind": "oracle", "Gpx_iter_s": pxi / dt / 1e9,
+               "sample": f"the {len(jobs)} smallest pairs of the batch, one process per pair "
+                         f"({pxi / 1e6:.0f} M px-iter, {dt:.1f} s, FP64 NumPy)"}
+    line = {
+        "metric": "Gpixel-iter/s (batched coarse-to-fine TV-L1 flow solves, pixel-iterations over all pairs "
+                  "and levels); pairs/s",
+        "value": round(value, 3), "unit": "Gpixel-iter/s", "pairs_per_s": round(n / (ms_step * 1e-3), 2),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n} pairs of uneven sizes (128x96 .. 1280x720, seeds 1000+k), pyramid depth "
+                               f"by size x {args.warps} warps x {args.iters} iterations, {args.scheme}, batched",
+                   "pairs": n, "px_iter_per_step": px_iter, "graph": True, "autotuned": not args.no_autotune},
+        "plain_sequential": plain,
+        "speedup_vs_best_plain": round(min(p_["ms"] for p_ in plain.values()) / ms_step, 3),
+        "per_level": per_level, "roofline": roof, "oracle_check": epe, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def calibrate_copy(mb, steps):
     """Plain device-to-device copies of `mb` MiB: the kernel of known traffic (mb MiB read and mb
     MiB written per launch) that scales the HBM counters."""
@@ -122,6 +284,9 @@ def main():
     ap.add_argument("--save-tuning", default=None)
     ap.add_argument("--load-tuning", default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
+    ap.add_argument("--mode", default="single", choices=["single", "batch"])
+    ap.add_argument("--pairs", type=int, default=64)
+    ap.add_argument("--oracle-pairs", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -136,6 +301,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, args.steps)
+        return
+    if args.mode == "batch":
+        run_batch(args)
         return
 
     dev = torch.device("cuda:0")
@@ -193,6 +361,7 @@ def main():
     p_inst = fm.Params(**{**params.__dict__, "use_graph": 0})
     lvl_ms = [0.0] * args.levels
     lvl_iters = [0] * args.levels
+    lvl_launch = [0] * args.levels
     reps = 3
     for _ in range(reps):
         ctx.solve(I0, I1, p_inst, u=u, v=v)
@@ -200,6 +369,7 @@ def main():
         for l in range(args.levels):
             lvl_ms[l] += s["iter_ms"][l]
             lvl_iters[l] += s["iterations"][l]
+            lvl_launch[l] += s["launches"][l]
     ctx.set_stats(False)
     per_level = []
     for l, (a, b) in enumerate(shapes):
@@ -210,35 +380,11 @@ def main():
     has_w = params.beta > 0
     roof = None
     if args.scheme in ("padmm", "rpadmm2"):
-        # Dominant kernel: the iteration kernel of level 0.  Kernel launches per warp follow the
-        # level's choice: `iters` for the one-pass kernel, ceil(iters / K) for K-iteration tiles,
-        # one for a resident tile.
-        def launches_per_warp(l):
-            a, b = shapes[l]
-            key = f"{a}x{b}{'w' if has_w else ''}i{args.iters}"
-            ch = (tuning or {}).get(key, {"mode": 1, "K": 1})
-            if ch["mode"] == 1:
-                return args.iters, ch
-            if ch["K"] == 0:
-                return 1, ch
-            return -(-args.iters // ch["K"]), ch
-        per_px = BYTES_PER_PX_LAUNCH[has_w]
-        n0, ch0 = launches_per_warp(0)
-        n0 *= args.warps * reps
-        launch_s = lvl_ms[0] * 1e-3 / n0
-        bytes_launch = per_px * shapes[0][0] * shapes[0][1]
-        achieved = bytes_launch / launch_s / 1e9
-        traffic = measured_traffic(f"{args.W}x{args.H}")
-        all_launches = sum(launches_per_warp(l)[0] for l in range(args.levels)) * args.warps
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"ADMM iteration kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
-                "per_unit": f"{per_px} B per pixel per launch", "bytes_per_launch": bytes_launch,
-                "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step_level0": n0 // reps,
-                "iteration_launches_per_step": all_launches,
-                # the same pixel-iterations priced at one HBM pass per iteration (76 B per pixel-iteration)
-                "one_pass_equivalent_GBs": round(per_px * shapes[0][0] * shapes[0][1] * lvl_iters[0]
-                                                 / (lvl_ms[0] * 1e-3) / 1e9, 1)}
+        roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
+                        f"ADMM iteration kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice "
+                        f"{(tuning or {}).get(f'{shapes[0][0]}x{shapes[0][1]}i{args.iters}')}",
+                        measured_traffic(f"{args.W}x{args.H}"), reps)
+        roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
 
     cpu = None
     if not args.no_cpu_baseline:

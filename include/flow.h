@@ -102,6 +102,7 @@ typedef struct flow_stats {
     int64_t px_iter;                          /* pixel-iterations of the solve */
     int32_t graph_replayed;                   /* 1 if the solve ran as a graph replay */
     int64_t level_px[FLOW_MAX_LEVELS];        /* pixels of the level (a batch: summed over its pairs) */
+    int64_t launches[FLOW_MAX_LEVELS];        /* iteration-kernel launches at this level (all warps) */
 } flow_stats;
 
 typedef struct flow_ctx flow_ctx;

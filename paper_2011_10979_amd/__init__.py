@@ -45,7 +45,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("H", ctypes.c_int32 * MAX_LEVELS), ("W", ctypes.c_int32 * MAX_LEVELS),
                 ("iterations", ctypes.c_int64 * MAX_LEVELS), ("iter_ms", ctypes.c_double * MAX_LEVELS),
                 ("total_ms", ctypes.c_double), ("px_iter", ctypes.c_int64), ("graph_replayed", ctypes.c_int32),
-                ("level_px", ctypes.c_int64 * MAX_LEVELS)]
+                ("level_px", ctypes.c_int64 * MAX_LEVELS), ("launches", ctypes.c_int64 * MAX_LEVELS)]
 
 
 class _AdmmState(ctypes.Structure):
@@ -225,7 +225,8 @@ class Context:
         n = s.levels
         return dict(levels=n, H=list(s.H[:n]), W=list(s.W[:n]), iterations=list(s.iterations[:n]),
                     iter_ms=list(s.iter_ms[:n]), total_ms=s.total_ms, px_iter=s.px_iter,
-                    graph_replayed=bool(s.graph_replayed), level_px=list(s.level_px[:n]))
+                    graph_replayed=bool(s.graph_replayed), level_px=list(s.level_px[:n]),
+                    launches=list(s.launches[:n]))
 
     def autotune(self, H, W, params: Params | None = None, **kw):
         """Time every iteration-kernel choice on the level shapes of an H x W pair; later solves of

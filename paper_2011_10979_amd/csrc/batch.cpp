@@ -696,6 +696,7 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
             S.H[G.l] = 0;
             S.W[G.l] = 0;
             S.iterations[G.l] = (int64_t)p->warps * p->iters;
+            S.launches[G.l] = (int64_t)p->warps * G.lpw;
             float ms = 0.f;
             hipEventElapsedTime(&ms, B.ev[2 * si], B.ev[2 * si + 1]);
             S.iter_ms[G.l] = ms;

@@ -52,7 +52,8 @@ hipEvent_t WarpTimers::get() {
 void WarpTimers::reset() {
     pairs.clear();
     used = 0;
-    for (auto& l : launches) l = 0;
+    for (auto& l : iters) l = 0;
+    for (auto& l : kernels) l = 0;
 }
 
 void WarpTimers::begin(int level, hipStream_t s) {
@@ -227,7 +228,8 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
             S.H[l] = Ls[l].H;
             S.level_px[l] = (int64_t)Ls[l].H * Ls[l].W;
             S.W[l] = Ls[l].W;
-            S.iterations[l] = replayed ? (int64_t)p.warps * p.iters : timers.launches[l];
+            S.iterations[l] = replayed ? (int64_t)p.warps * p.iters : timers.iters[l];
+            S.launches[l] = replayed ? 0 : timers.kernels[l];
             pxi += (int64_t)Ls[l].H * Ls[l].W * S.iterations[l];
         }
         for (auto& pr : timers.pairs) {

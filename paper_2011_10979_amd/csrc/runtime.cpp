@@ -312,7 +312,7 @@ TbArgs tb_args(const SolvePlan& plan, const LevelTbPlan& P, const LevelPlanes& L
 // `n` ADMM-family iterations of level L starting from state buffer `cur`, with the kernel choice
 // of plan P (nullptr: one-pass kernel, strip height rows_hint); returns the buffer holding the result.
 int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
-                       int64_t n, int at_slot, const float* at2, hipStream_t s) {
+                       int64_t n, int at_slot, const float* at2, hipStream_t s, int64_t* launches) {
     const bool hw = p.beta > 0;
     int64_t t = 0;
     while (t < n) {
@@ -326,6 +326,7 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
             launch_admm_iter(ai, hw, s);
             t += 1;
         }
+        if (launches) ++*launches;
         cur ^= 1;
     }
     return cur;
@@ -415,13 +416,15 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             while (k < p.iters) {
                 int64_t chunk = p.iters - k;
                 if (stop && p.tol > 0) chunk = std::min<int64_t>(chunk, p.check_every);
+                int64_t nk = 0;
                 if (pdr) {
                     for (int64_t t = 0; t < chunk; ++t) enqueue_pdr_iter(pdr_args(L, p), p.gs_sweeps, hw, s);
+                    nk = chunk * (2 * p.gs_sweeps + 1);
                 } else {
-                    cur = enqueue_admm_iters(L, p, P, rows_hint, cur, chunk, wp & 1, sc.at, s);
+                    cur = enqueue_admm_iters(L, p, P, rows_hint, cur, chunk, wp & 1, sc.at, s, &nk);
                 }
                 k += chunk;
-                if (timers) timers->count(l, chunk);
+                if (timers) timers->count(l, chunk, nk);
                 if (stop && p.tol > 0 && k < p.iters) {
                     launch_energy(energy_args(L, p, cur, sc), s);
                     bool converged = false;

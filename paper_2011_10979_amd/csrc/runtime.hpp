@@ -56,13 +56,14 @@ struct WarpTimers {
     std::vector<Pair> pairs;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    int64_t launches[FLOW_MAX_LEVELS] = {};
+    int64_t iters[FLOW_MAX_LEVELS] = {};      // inner iterations per level
+    int64_t kernels[FLOW_MAX_LEVELS] = {};    // iteration-kernel launches per level
     int cur_level = 0;
     hipEvent_t get();
     void reset();
     void begin(int level, hipStream_t s);
     void end(int level, hipStream_t s);
-    void count(int level, int64_t n) { launches[level] += n; }
+    void count(int level, int64_t n, int64_t k) { iters[level] += n; kernels[level] += k; }
     ~WarpTimers();
 };
 
@@ -140,7 +141,7 @@ struct SolvePlan {
 flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
                       const std::map<std::string, TunedChoice>* tuned);
 int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
-                       int64_t n, int at_slot, const float* at2, hipStream_t s);
+                       int64_t n, int at_slot, const float* at2, hipStream_t s, int64_t* launches = nullptr);
 TbArgs tb_args(const SolvePlan& plan, const LevelTbPlan& P, const LevelPlanes& L, const flow_params& p, int cur,
                int K, int at_slot, const float* at2);
 

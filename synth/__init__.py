@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "Texture", "Pair", "make_pair", "texture_blobs", "texture_rich", "flow_constant",
     "flow_piecewise", "flow_affine_occluded", "translation_pair", "vga_pair", "hd_pair",
-    "batch_pairs", "serving_trace", "SERVING_SIZES", "SERVING_PROBS",
+    "batch_pair", "batch_pairs", "levels_by_size", "serving_trace", "SERVING_SIZES", "SERVING_PROBS",
 ]
 
 
@@ -181,25 +181,29 @@ def hd_pair(seed: int = 2, H: int = 1080, W: int = 1920, noise_std: float = 0.01
     return make_pair(tex, u, v, rng, noise_std, dict(recipe="affine", seed=seed, H=H, W=W))
 
 
-def batch_pairs(n: int = 64, seed0: int = 1000, size_scale: float = 1.0):
-    """n pairs of uneven sizes: W ~ U_int[128, 1280], H ~ U_int[96, 720], pair k seeded seed0 + k.
+def batch_pair(k: int, seed0: int = 1000, size_scale: float = 1.0) -> Pair:
+    """Pair k of `batch_pairs` (seeded seed0 + k): W ~ U_int[128, 1280], H ~ U_int[96, 720]; even k
+    use the piecewise-motion recipe, odd k the rotation + zoom recipe.  `size_scale` shrinks both
+    sides (for quick tests) without changing the draws."""
+    rng = np.random.default_rng(seed0 + k)
+    W = int(rng.integers(128, 1281))
+    H = int(rng.integers(96, 721))
+    W = max(16, int(W * size_scale))
+    H = max(16, int(H * size_scale))
+    if k % 2 == 0:
+        return vga_pair(seed0 + k, H, W)
+    return hd_pair(seed0 + k, H, W)
 
-    Even k use the piecewise-motion recipe, odd k the rotation + zoom recipe.  `size_scale` shrinks
-    both sides (for quick tests) without changing the draws.
-    """
-    out = []
-    for k in range(n):
-        rng = np.random.default_rng(seed0 + k)
-        W = int(rng.integers(128, 1281))
-        H = int(rng.integers(96, 721))
-        W = max(16, int(W * size_scale))
-        H = max(16, int(H * size_scale))
-        if k % 2 == 0:
-            out.append(vga_pair(seed0 + k, H, W))
-        else:
-            p = hd_pair(seed0 + k, H, W)
-            out.append(p)
-    return out
+
+def batch_pairs(n: int = 64, seed0: int = 1000, size_scale: float = 1.0):
+    """n pairs of uneven sizes (see batch_pair)."""
+    return [batch_pair(k, seed0, size_scale) for k in range(n)]
+
+
+def levels_by_size(H: int, W: int) -> int:
+    """Pyramid depth for mixed-size workloads: 1 + floor(log2(min(H, W) / 16)), clamped to [1, 6]
+    (5 levels at 640 x 480, 6 at 1920 x 1080, coarsest side about 16 to 30 pixels)."""
+    return int(min(6, max(1, 1 + math.floor(math.log2(min(H, W) / 16.0)))))
 
 
 SERVING_SIZES = [(240, 320), (480, 640), (436, 1024), (720, 1280), (1080, 1920)]
