@@ -164,6 +164,59 @@ typedef struct flow_pair {
 flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
                                void* stream);
 
+/* ------------------------------------------------------------------------------------------------
+ * Serving: continuous batching of pairs that arrive over time.
+ * ----------------------------------------------------------------------------------------------*/
+typedef struct flow_server flow_server;
+
+typedef struct flow_server_stats {
+    int64_t submitted, admitted, completed;
+    int64_t epochs;                 /* flow_server_step calls that launched work */
+    int32_t active, queued;         /* pairs in flight / waiting for admission now */
+    int32_t peak_active;
+    uint64_t arena_bytes;           /* the serving budget (pairs' working sets) */
+    uint64_t bytes_in_use, peak_bytes_in_use;
+} flow_server_stats;
+
+/* Device bytes of one pair's working set (pyramids, linearisation, scheme state of every level) for
+ * an H x W pair under p with `levels` levels (0: p->levels): what flow_solve, a batch and the
+ * serving budget hold per pair.  Host-only. */
+flow_status flow_working_set_bytes(int32_t H, int32_t W, const flow_params* p, int32_t levels, uint64_t* bytes);
+
+/* Create a serving engine on ctx's GPU for solves with parameters p (ADMM family, tol = 0; per-pair
+ * pyramid depth from flow_pair.levels, else p->levels).  hbm_budget: bytes of device memory for
+ * the working sets of the pairs in flight (0: 8 GiB), allocated once here; a few MB of tables come
+ * on top.  max_active: most pairs in flight at once.  Every epoch runs on `stream` (hipStream_t).
+ * ctx must outlive the engine.  FLOW_E_NOMEM if the budget cannot be allocated. */
+flow_status flow_server_create(flow_ctx* ctx, const flow_params* p, size_t hbm_budget, int32_t max_active,
+                               void* stream, flow_server** out);
+flow_status flow_server_destroy(flow_server* srv);
+
+/* Queue one pair (device frames and outputs as in flow_solve; res host, may be NULL).  The caller
+ * keeps I0, I1, u, v and res valid and untouched until flow_server_poll reports the ticket done,
+ * and the frames must be complete on `stream`'s device before the next flow_server_step.
+ * FLOW_E_INVAL for a bad pair, FLOW_E_NOMEM if its working set can never fit the budget. */
+flow_status flow_server_submit(flow_server* srv, const flow_pair* pair, uint64_t* ticket);
+
+/* Run one epoch (asynchronous on the engine's stream): admit queued pairs, in arrival order, while
+ * a slot and room in the budget are free (first-fit; a pair that does not fit holds the queue);
+ * advance every admitted pair by one warp of its coarse-to-fine solve (Sec. 4) -- level start where
+ * due, linearisation, `iters` iterations, commit -- with one launch per step over all of them
+ * (tile launches cover the current level of every pair; pairs at different levels and warps share
+ * them); finish the pairs that completed level 0 (energy, flow export).  Released memory and slots
+ * return when the epoch's work has completed on the device.  Blocks only when the buffers of the
+ * epoch before last are still in use.  A pair's results are bitwise the same alone or in any mix,
+ * and equal to flow_solve_batched.  active / queued (may be NULL) receive the counts after it. */
+flow_status flow_server_step(flow_server* srv, int32_t* active, int32_t* queued);
+
+/* done = 1 once the ticket's u, v and res are written (the ticket is then collected and later
+ * polls return FLOW_E_NOTFOUND); FLOW_E_NONFINITE with done = 1 if its energy is not finite. */
+flow_status flow_server_poll(flow_server* srv, uint64_t ticket, int32_t* done);
+
+/* Step until nothing is active or queued, then wait for the device (blocking). */
+flow_status flow_server_drain(flow_server* srv);
+flow_status flow_server_get_stats(const flow_server* srv, flow_server_stats* out);
+
 /* Batched autotuner: for each stage of this batch, time every tile-launch choice (table order or
  * per-XCD work queues; K = 2, 4, 8 iterations per launch, or the whole warp where every level of the
  * stage fits one tile; extended tile width 64 or 128) over one warp's iterations, and keep the

@@ -57,6 +57,13 @@ class _PdrState(ctypes.Structure):
                                                 "qb2x", "qb2y")]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("epochs", ctypes.c_int64), ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("peak_active", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes_in_use", ctypes.c_uint64)]
+
+
 class _Pair(ctypes.Structure):
     _fields_ = [("I0", ctypes.c_void_p), ("I1", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("ld", ctypes.c_int64), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("ld_uv", ctypes.c_int64),
@@ -69,7 +76,9 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_set_stats", "flow_get_stats", "flow_memory_in_use", "flow_last_error", "flow_op_downsample",
            "flow_op_derivatives", "flow_op_linearize", "flow_op_upsample", "flow_op_admm_iter", "flow_op_pdr_iter",
            "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
-           "flow_tune_choice", "flow_autotune_batched"]
+           "flow_tune_choice", "flow_autotune_batched", "flow_server_create", "flow_server_destroy",
+           "flow_server_submit", "flow_server_step", "flow_server_poll", "flow_server_drain",
+           "flow_server_get_stats", "flow_working_set_bytes"]
 
 
 def lib():
@@ -87,6 +96,14 @@ def lib():
             "flow_solve": [vp, vp, vp, i32, i32, i64, ctypes.POINTER(_Params), vp, vp, i64, ctypes.POINTER(_Result), vp],
             "flow_solve_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
             "flow_autotune_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
+            "flow_server_create": [vp, ctypes.POINTER(_Params), ctypes.c_size_t, i32, vp, ctypes.POINTER(vp)],
+            "flow_server_destroy": [vp],
+            "flow_working_set_bytes": [i32, i32, ctypes.POINTER(_Params), i32, ctypes.POINTER(ctypes.c_uint64)],
+            "flow_server_submit": [vp, ctypes.POINTER(_Pair), ctypes.POINTER(ctypes.c_uint64)],
+            "flow_server_step": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+            "flow_server_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32)],
+            "flow_server_drain": [vp],
+            "flow_server_get_stats": [vp, ctypes.POINTER(_ServerStats)],
             "flow_set_stats": [vp, i32],
             "flow_autotune": [vp, i32, i32, ctypes.POINTER(_Params), vp],
             "flow_get_tuning": [vp, ctypes.c_char_p, ctypes.c_size_t],
@@ -307,6 +324,80 @@ class Context:
         params = params or Params(**kw)
         arr, _, _ = self._pairs(pairs)
         _check(lib().flow_autotune_batched(self._h, len(pairs), arr, ctypes.byref(params.c_struct()), _stream()))
+
+
+def working_set_bytes(H, W, params: Params | None = None, levels: int = 0, **kw):
+    """Device bytes of one pair's working set (see flow_working_set_bytes)."""
+    params = params or Params(**kw)
+    b = ctypes.c_uint64()
+    _check(lib().flow_working_set_bytes(int(H), int(W), ctypes.byref(params.c_struct()), int(levels), ctypes.byref(b)))
+    return b.value
+
+
+class Server:
+    """Continuous-batching serving engine (flow_server_*): submit pairs as they arrive, call step()
+    to run one epoch (every admitted pair advances one warp; queued pairs are admitted as slots and
+    budget free up), poll tickets for completion."""
+
+    def __init__(self, ctx: Context, params: Params | None = None, budget_bytes: int = 0, max_active: int = 64,
+                 **kw):
+        self.params = params or Params(**kw)
+        self._stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().flow_server_create(ctx._h, ctypes.byref(self.params.c_struct()), int(budget_bytes),
+                                        int(max_active), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._live = {}
+
+    def submit(self, I0, I1, levels: int = 0):
+        _plane(I0, "I0")
+        _plane(I1, "I1")
+        if I0.shape != I1.shape or I0.stride() != I1.stride():
+            raise ValueError("I0 and I1 must have the same shape and layout")
+        H, W = I0.shape
+        u = torch.empty((H, W), device=I0.device, dtype=torch.float32)
+        v = torch.empty((H, W), device=I0.device, dtype=torch.float32)
+        res = _Result()
+        pr = _Pair(I0.data_ptr(), I1.data_ptr(), H, W, I0.stride(0), u.data_ptr(), v.data_ptr(), W,
+                   ctypes.cast(ctypes.byref(res), ctypes.c_void_p), int(levels))
+        t = ctypes.c_uint64()
+        _check(lib().flow_server_submit(self._h, ctypes.byref(pr), ctypes.byref(t)))
+        self._live[t.value] = (I0, I1, u, v, res)       # keeps the buffers alive until done
+        return t.value
+
+    def step(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().flow_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, ticket):
+        """None while running; (u, v, result) once done."""
+        d = ctypes.c_int32()
+        _check(lib().flow_server_poll(self._h, ticket, ctypes.byref(d)))
+        if not d.value:
+            return None
+        _, _, u, v, res = self._live.pop(ticket)
+        return u, v, _result_dict(res)
+
+    def drain(self):
+        _check(lib().flow_server_drain(self._h))
+
+    def stats(self):
+        s = _ServerStats()
+        _check(lib().flow_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().flow_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------ operator-level calls -----------------------------------

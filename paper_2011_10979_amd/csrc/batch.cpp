@@ -21,6 +21,7 @@
 #include <string>
 #include <vector>
 
+#include "multi.hpp"
 #include "runtime.hpp"
 
 namespace flowmi {
@@ -31,25 +32,7 @@ namespace flowmi {
         if (_e != hipSuccess) return hip_fail(_e, #expr);       \
     } while (0)
 
-namespace {
-
-constexpr int kBatchNt = 1025;   // tile kernel instantiation of every batched level (1024 threads, small tiles)
-constexpr int kNq = 8;           // per-XCD sub-queues of the work-queue order
-
-enum { ORDER_TABLE = 0, ORDER_QUEUE = 1 };
-
-struct StageChoice {
-    int K = 0;                   // iterations per tile launch (>= iters: the whole warp in one launch)
-    int ew = 64;                 // extended tile width target
-    int order = ORDER_TABLE;
-};
-
-// One batched launch of an elementwise body: items and block offsets at byte offsets of a table.
-struct BLaunch {
-    size_t items = 0, off = 0;
-    int n = 0, total = 0;
-};
-
+// One stage: pyramid level l of every pair that has it.
 struct BStage {
     int l = 0;                          // pyramid level (0 = finest)
     std::vector<int> pairs;             // pairs that have level l
@@ -61,73 +44,6 @@ struct BStage {
     BLaunch init;
     std::vector<BLaunch> lin, commit;   // per warp
 };
-
-// Host-side builder of a device table: typed arrays at 256-byte aligned offsets.
-struct TableBuilder {
-    std::vector<char> h;
-    template <typename T> size_t put(const std::vector<T>& v) {
-        const size_t o = (h.size() + 255) & ~(size_t)255;
-        h.resize(o + std::max<size_t>(1, v.size() * sizeof(T)), 0);
-        if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size() * sizeof(T));
-        return o;
-    }
-    // items plus their block-offset prefix (blocks[k] work-groups for item k)
-    template <typename T> BLaunch launch(const std::vector<T>& items, const std::vector<int>& blocks) {
-        BLaunch L;
-        std::vector<int> off(items.size() + 1, 0);
-        for (size_t k = 0; k < items.size(); ++k) off[k + 1] = off[k] + blocks[k];
-        L.items = put(items);
-        L.off = put(off);
-        L.n = (int)items.size();
-        L.total = off.back();
-        return L;
-    }
-};
-
-// Grow-only device buffer.
-struct DevBuf {
-    char* d = nullptr;
-    size_t bytes = 0;
-    flow_status ensure(size_t need, const char* what) {
-        if (need <= bytes) return FLOW_OK;
-        if (d) {
-            hipDeviceSynchronize();
-            hipFree(d);
-            d = nullptr;
-            bytes = 0;
-        }
-        hipError_t e = hipMalloc((void**)&d, need);
-        if (e != hipSuccess) return fail(FLOW_E_NOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
-        bytes = need;
-        return FLOW_OK;
-    }
-    void release() {
-        if (d) hipFree(d);
-        d = nullptr;
-        bytes = 0;
-    }
-};
-
-struct PinnedBuf {
-    char* h = nullptr;
-    size_t bytes = 0;
-    flow_status ensure(size_t need) {
-        if (need <= bytes) return FLOW_OK;
-        if (h) hipHostFree(h);
-        h = nullptr;
-        bytes = 0;
-        HIP_TRY(hipHostMalloc((void**)&h, need, hipHostMallocDefault));
-        bytes = need;
-        return FLOW_OK;
-    }
-    void release() {
-        if (h) hipHostFree(h);
-        h = nullptr;
-        bytes = 0;
-    }
-};
-
-}  // namespace
 
 // Working set and launch plan of one batch composition.
 struct BatchPlan {
@@ -198,52 +114,21 @@ std::string stage_key(const std::vector<std::pair<int, int>>& shapes, bool hw, i
     return o.str();
 }
 
-// Whether every level of the stage takes tiles for exactly K iterations with this width target.
+Shapes stage_shapes(const BatchPlan& P, const BStage& S) {
+    Shapes s;
+    for (int k : S.pairs) s.emplace_back(P.L[k][S.l].H, P.L[k][S.l].W);
+    return s;
+}
+
 bool stage_fits(const BatchPlan& P, const BStage& S, bool hw, int K, int ew) {
-    for (int k : S.pairs) {
-        const LevelPlanes& L = P.L[k][S.l];
-        const LevelTbPlan T = plan_tiles(L.H, L.W, hw, kBatchNt, K, ew);
-        if (!T.tb) return false;
-        if (!T.resident && T.K != K) return false;
-    }
-    return true;
-}
-
-bool stage_all_resident(const BatchPlan& P, const BStage& S, bool hw) {
-    for (int k : S.pairs) {
-        const LevelPlanes& L = P.L[k][S.l];
-        if ((int64_t)L.H * L.W > tb_capacity(hw, kBatchNt)) return false;
-    }
-    return true;
-}
-
-// Built-in stage choice: the whole warp in one launch where every level fits one tile; else
-// 4 iterations per launch on stages large enough to fill the chip with tiles, 8 on smaller ones.
-StageChoice default_choice(const BatchPlan& P, const BStage& S, bool hw, int iters) {
-    StageChoice c;
-    c.order = ORDER_TABLE;
-    c.ew = 64;
-    if (stage_all_resident(P, S, hw)) {
-        c.K = std::max(1, iters);
-        return c;
-    }
-    int64_t px = 0;
-    for (int k : S.pairs) px += (int64_t)P.L[k][S.l].H * P.L[k][S.l].W;
-    c.K = px >= 300000 ? 4 : 8;
-    while (c.K > 1 && !stage_fits(P, S, hw, c.K, c.ew)) --c.K;
-    return c;
+    return shapes_fit(stage_shapes(P, S), hw, K, ew);
 }
 
 void stage_tiles(const BatchPlan& P, const BStage& S, bool hw, const StageChoice& ch,
                  const std::vector<int>& desc_id, std::vector<TbTile>& out) {
-    for (int k : S.pairs) {
-        const LevelPlanes& L = P.L[k][S.l];
-        LevelTbPlan T = plan_tiles(L.H, L.W, hw, kBatchNt, std::min(ch.K, 64), ch.ew);
-        append_tiles(T, desc_id[k * FLOW_MAX_LEVELS + S.l], L.H, L.W, out);
-    }
+    for (int k : S.pairs)
+        level_tiles(P.L[k][S.l].H, P.L[k][S.l].W, hw, ch, desc_id[k * FLOW_MAX_LEVELS + S.l], out);
 }
-
-int launches_per_warp(int iters, int K) { return iters <= 0 ? 0 : (iters + K - 1) / K; }
 
 }  // namespace
 
@@ -255,20 +140,8 @@ namespace {
 
 flow_status validate_pairs(int n, const flow_pair* pairs, const flow_params& p) {
     for (int k = 0; k < n; ++k) {
-        const flow_pair& q = pairs[k];
-        const std::string who = "pair " + std::to_string(k) + ": ";
-        if (q.levels < 0 || q.levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, who + "levels out of range");
-        const int lv = q.levels > 0 ? q.levels : p.levels;
-        flow_status st = validate_shape(q.H, q.W, q.ld, lv);
-        if (st != FLOW_OK) return fail(st, who + flow_last_error());
-        if (q.ld_uv < q.W) return fail(FLOW_E_INVAL, who + "ld_uv smaller than W");
-        if (!q.I0 || !q.I1 || !q.u || !q.v) return fail(FLOW_E_INVAL, who + "NULL device pointer");
-        const struct { const void* ptr; int64_t ld; const char* name; } planes[4] = {
-            {q.I0, q.ld, "I0"}, {q.I1, q.ld, "I1"}, {q.u, q.ld_uv, "u"}, {q.v, q.ld_uv, "v"}};
-        for (auto& pl : planes) {
-            st = check_extent(pl.ptr, q.H, q.W, pl.ld, sizeof(float), pl.name);
-            if (st != FLOW_OK) return fail(st, who + flow_last_error());
-        }
+        flow_status st = validate_pair(pairs[k], p, "pair " + std::to_string(k) + ": ");
+        if (st != FLOW_OK) return st;
     }
     return FLOW_OK;
 }
@@ -344,28 +217,21 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
             }
         S.key = stage_key(shapes, hw, p.iters);
         auto it = B.tuned.find(S.key);
-        S.ch = (it != B.tuned.end() && stage_fits(*P, S, hw, it->second.K, it->second.ew))
-                   ? it->second : default_choice(*P, S, hw, p.iters);
+        S.ch = (it != B.tuned.end() && shapes_fit(shapes, hw, it->second.K, it->second.ew))
+                   ? it->second : default_stage_choice(shapes, hw, p.iters);
         // process-wide overrides (tests and experiments); K is lowered until every level fits
         if (g_batch_order >= 0) S.ch.order = g_batch_order;
         if (g_batch_ew > 0) S.ch.ew = g_batch_ew;
         if (g_batch_k > 0) S.ch.K = g_batch_k;
-        if (g_batch_k > 0 || g_batch_ew > 0)
-            while (S.ch.K > 1 && !stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) --S.ch.K;
-        if (!stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) {
-            S.ch.ew = 64;
-            while (S.ch.K > 1 && !stage_fits(*P, S, hw, S.ch.K, S.ch.ew)) --S.ch.K;
-        }
+        S.ch = fit_stage_choice(S.ch, shapes, hw);
         S.lpw = launches_per_warp(p.iters, S.ch.K);
         S.tile_off = (int)tiles.size();
         stage_tiles(*P, S, hw, S.ch, desc_id, tiles);
         S.ntiles = (int)tiles.size() - S.tile_off;
+        S.grid = tile_grid(S.ch, S.ntiles);
         if (S.ch.order == ORDER_QUEUE) {
-            S.grid = std::max(1, std::min(S.ntiles, 256 * 2));     // 2 work-groups of 1024 threads per CU
             S.counter_off = ncounters;
             ncounters += p.warps * S.lpw * kNq;
-        } else {
-            S.grid = S.ntiles;
         }
         P->stages.push_back(S);
     }
@@ -551,36 +417,9 @@ void run_b(BatchOp op, const char* base, const BLaunch& L, bool f16, hipStream_t
 // The tile launches of one warp of stage S (returns the state buffer after them).
 int enqueue_stage_iters(const BatchState& B, const BStage& S, const flow_params& p, int w, int cur, hipStream_t s) {
     const BatchPlan& P = *B.plan;
-    const bool hw = p.beta > 0;
-    AdmmIterArgs co{};
-    fill_admm_coeffs(co, p);
-    TbArgs a{};
-    a.tiles = (const TbTile*)(B.tab.d + P.tiles_off) + S.tile_off;
-    a.ntiles = S.ntiles;
-    a.levels = (const TbLevel*)(B.tab.d + P.descs_off);
-    a.at_slot = w & 1;
-    a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
-    a.cA = co.cA; a.cB = co.cB; a.cC = co.cC;
-    unsigned* counters = (unsigned*)(B.dyn.d + P.cnt_off);
-    int k = 0, li = 0;
-    while (k < p.iters) {
-        const int kk = std::min(S.ch.K, p.iters - k);
-        a.dir = cur;
-        a.K = kk;
-        if (S.ch.order == ORDER_QUEUE) {
-            a.queue = counters + S.counter_off + (w * S.lpw + li) * kNq;
-            a.queue_base = 0;
-            a.nq = std::min(kNq, S.grid);
-        } else {
-            a.queue = nullptr;
-            a.nq = 1;
-        }
-        launch_admm_tb(a, hw, kBatchNt, S.grid, s);
-        cur ^= 1;
-        k += kk;
-        ++li;
-    }
-    return cur;
+    unsigned* counters = (unsigned*)(B.dyn.d + P.cnt_off) + S.counter_off + w * S.lpw * kNq;
+    return enqueue_tile_warp((const TbTile*)(B.tab.d + P.tiles_off) + S.tile_off, S.ntiles, S.grid,
+                             (const TbLevel*)(B.tab.d + P.descs_off), S.ch, p, w & 1, cur, counters, s);
 }
 
 void enqueue_batch(const BatchState& B, const flow_params& p, hipStream_t s, hipEvent_t* ev) {
@@ -759,7 +598,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
         run_b(BatchOp::LevelInit, tab, S.init, false, s);
         run_b(BatchOp::Linearize, tab, S.lin[0], f16, s);
         std::vector<StageChoice> cands;
-        const bool all_res = stage_all_resident(P, S, hw);
+        const bool all_res = shapes_all_resident(stage_shapes(P, S), hw);
         for (int order : {ORDER_TABLE, ORDER_QUEUE}) {
             if (all_res) {
                 StageChoice c;

@@ -1,0 +1,556 @@
+// Serving engine: continuous batching of frame pairs that arrive over time.
+//
+// Requests are queued on submit and admitted, in arrival order, when a slot (at most max_active
+// pairs in flight) and room in the engine's HBM arena (first-fit, the pair's whole working set)
+// are free.  Each call to flow_server_step runs one epoch: every admitted pair advances by one warp
+// of its coarse-to-fine solve (Sec. 4) -- level start where due, linearisation, the warp's
+// iterations, commit -- and all pairs share each launch: item tables map work-groups to pairs for
+// the elementwise steps, and one K-iteration tile launch covers the tiles of every pair's current
+// level.  Newly admitted pairs are imported and get their pyramids in the same epoch.  A pair that
+// finishes level 0 has its energy computed and its flow exported in that epoch; its memory and slot
+// are released once the epoch's event has completed.  Pairs at different levels and warps share
+// launches, so a pair's arithmetic is the same as alone (each pair has its own a~ slots, energy
+// partials and state direction; the K of a launch only decides how far tile halos are recomputed):
+// a served result is bitwise the same alone or in any mix.
+//
+// Epochs are double-buffered: the host builds epoch e + 1's tables while the device runs epoch e,
+// and blocks only when it needs epoch e - 1's buffers again.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "multi.hpp"
+#include "runtime.hpp"
+
+namespace flowmi {
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+    } while (0)
+
+namespace {
+
+// First-fit allocator over [0, cap) with 256-byte granules.
+struct RangeAlloc {
+    size_t cap = 0;
+    std::map<size_t, size_t> free_;   // offset -> size
+    void reset(size_t c) {
+        cap = c;
+        free_.clear();
+        if (c) free_[0] = c;
+    }
+    bool alloc(size_t n, size_t& off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            off = it->first;
+            const size_t rest = it->second - n;
+            free_.erase(it);
+            if (rest) free_[off + n] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Req {
+    flow_pair q{};
+    int levels = 0;
+    size_t bytes = 0;
+    size_t off = 0;
+    int slot = -1;
+    std::vector<LevelPlanes> L;
+    int l = 0, w = 0;          // cursor: next warp w of level l
+    int cur = 0;               // state buffer holding the current iterate
+    int cur_coarse = 0;        // state buffer of the finished coarser level
+    bool imported = false;
+    bool done = false;
+    flow_status status = FLOW_OK;
+};
+
+struct Epoch {
+    hipEvent_t ev = nullptr;
+    bool in_flight = false;
+    std::vector<uint64_t> finishing;
+};
+
+}  // namespace
+
+}  // namespace flowmi
+
+using namespace flowmi;
+
+struct flow_server {
+    int device = 0;
+    flow_params p{};
+    hipStream_t s = nullptr;
+    int max_active = 0;
+    DevArena arena;
+    RangeAlloc ralloc;
+    size_t bytes_in_use = 0;
+    DevBuf dyn;                    // a~ slots, energy partials and sums per slot, queue counters
+    size_t at_off = 0, epart_off = 0, eout_off = 0, cnt_off = 0;
+    DevBuf tab[2];
+    PinnedBuf htab[2], he[2];
+    Epoch ep[2];
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, Req> reqs;
+    std::vector<uint64_t> active;
+    std::vector<int> free_slots;
+    uint64_t next_ticket = 1;
+    flow_server_stats st{};
+
+    flow_status init(const flow_params& prm, size_t budget, int maxa, hipStream_t stream);
+    flow_status retire(int b);
+    flow_status admit();
+    flow_status step(int32_t* n_active, int32_t* n_queued);
+    ~flow_server();
+};
+
+flow_status flow_server::init(const flow_params& prm, size_t budget, int maxa, hipStream_t stream) {
+    p = prm;
+    s = stream;
+    max_active = maxa;
+    void* a = nullptr;
+    hipError_t e = hipMalloc(&a, budget);
+    if (e != hipSuccess) return fail(FLOW_E_NOMEM, std::string("hipMalloc(serving arena): ") + hipGetErrorString(e));
+    arena.base = a;
+    arena.bytes = budget;
+    ralloc.reset(budget);
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t r = o; o = (o + b + 255) & ~(size_t)255; return r; };
+    at_off = take(sizeof(float) * 2 * maxa);
+    epart_off = take(sizeof(double) * kEnergyTerms * kEnergyBlocks * maxa);
+    eout_off = take(sizeof(double) * kEnergyTerms * maxa);
+    cnt_off = take(sizeof(unsigned) * 2 * std::max(1, p.iters) * kNq);
+    flow_status r = dyn.ensure(o, "serving scalars");
+    if (r != FLOW_OK) return r;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipEventCreateWithFlags(&ep[b].ev, hipEventDisableTiming));
+        r = he[b].ensure(sizeof(double) * kEnergyTerms * maxa);
+        if (r != FLOW_OK) return r;
+    }
+    for (int k = maxa - 1; k >= 0; --k) free_slots.push_back(k);
+    st.arena_bytes = budget;
+    return FLOW_OK;
+}
+
+flow_server::~flow_server() {
+    if (s) hipStreamSynchronize(s);
+    for (auto& x : ep)
+        if (x.ev) hipEventDestroy(x.ev);
+    if (arena.base) hipFree(arena.base);
+    dyn.release();
+    for (int b = 0; b < 2; ++b) {
+        tab[b].release();
+        htab[b].release();
+        he[b].release();
+    }
+}
+
+// Epoch b has completed on the device: results of its finishing pairs, memory and slots back.
+flow_status flow_server::retire(int b) {
+    Epoch& E = ep[b];
+    if (!E.in_flight) return FLOW_OK;
+    HIP_TRY(hipEventSynchronize(E.ev));
+    const double* h = (const double*)he[b].h;
+    for (uint64_t t : E.finishing) {
+        Req& r = reqs[t];
+        const double* e = h + (size_t)r.slot * kEnergyTerms;
+        fill_result(e, r.q.res);
+        if (!std::isfinite(e[0] + e[1]) || !std::isfinite(e[2]) || e[7] != 0.0) r.status = FLOW_E_NONFINITE;
+        r.done = true;
+        ralloc.release(r.off, r.bytes);
+        bytes_in_use -= r.bytes;
+        free_slots.push_back(r.slot);
+        r.L.clear();
+        st.completed++;
+    }
+    E.finishing.clear();
+    E.in_flight = false;
+    return FLOW_OK;
+}
+
+flow_status flow_server::admit() {
+    while (!queue.empty() && (int)active.size() < max_active && !free_slots.empty()) {
+        Req& r = reqs[queue.front()];
+        size_t off = 0;
+        if (!ralloc.alloc(r.bytes, off)) break;   // arrival order: later requests wait behind this one
+        flow_params pk = p;
+        pk.levels = r.levels;
+        DevArena sub{(char*)arena.base + off, r.bytes};
+        flow_status rs = build_layout(sub, r.q.H, r.q.W, pk, r.L);
+        if (rs != FLOW_OK) {
+            ralloc.release(off, r.bytes);
+            return rs;
+        }
+        r.off = off;
+        r.slot = free_slots.back();
+        free_slots.pop_back();
+        r.l = r.levels - 1;
+        r.w = 0;
+        r.cur = 0;
+        r.imported = false;
+        bytes_in_use += r.bytes;
+        st.peak_bytes_in_use = std::max(st.peak_bytes_in_use, bytes_in_use);
+        active.push_back(queue.front());
+        queue.pop_front();
+        st.admitted++;
+    }
+    st.peak_active = std::max<int32_t>(st.peak_active, (int32_t)active.size());
+    return FLOW_OK;
+}
+
+static void run_items(BatchOp op, const char* base, const BLaunch& L, bool f16, hipStream_t s) {
+    if (L.n > 0) launch_batched(op, base + L.items, (const int*)(base + L.off), L.n, L.total, f16, s);
+}
+
+flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
+    const int b = (int)(st.epochs & 1);
+    flow_status r = retire(b);                                   // the epoch that used these buffers
+    if (r != FLOW_OK) return r;
+    if (ep[b ^ 1].in_flight && hipEventQuery(ep[b ^ 1].ev) == hipSuccess) {
+        r = retire(b ^ 1);
+        if (r != FLOW_OK) return r;
+    }
+    r = admit();
+    if (r != FLOW_OK) return r;
+    if (active.empty() && !queue.empty() && ep[b ^ 1].in_flight) {
+        r = retire(b ^ 1);                                       // memory held by finishing pairs
+        if (r == FLOW_OK) r = admit();
+        if (r != FLOW_OK) return r;
+    }
+    if (active.empty()) {
+        if (n_active) *n_active = 0;
+        if (n_queued) *n_queued = (int32_t)queue.size();
+        return FLOW_OK;
+    }
+    const bool hw = p.beta > 0;
+    const bool f16 = p.storage == FLOW_STORE_F16;
+    float* d_at = (float*)(dyn.d + at_off);
+    double* d_epart = (double*)(dyn.d + epart_off);
+    double* d_eout = (double*)(dyn.d + eout_off);
+    unsigned* d_cnt = (unsigned*)(dyn.d + cnt_off) + (size_t)b * std::max(1, p.iters) * kNq;
+
+    // ---- tables of this epoch
+    TableBuilder T;
+    std::vector<CopyArgs> imp;
+    std::vector<int> imp_bl;
+    std::vector<DerivArgs> der;
+    std::vector<int> der_bl;
+    int lmax_new = 0;
+    for (uint64_t t : active) {
+        Req& q = reqs[t];
+        if (q.imported) continue;
+        const LevelPlanes& L0 = q.L[0];
+        imp.push_back(CopyArgs{q.q.I0, q.q.H, q.q.W, q.q.ld, L0.I0, L0.ld});
+        imp.push_back(CopyArgs{q.q.I1, q.q.H, q.q.W, q.q.ld, L0.I1, L0.ld});
+        imp_bl.push_back(blocks_of(q.q.H, q.q.W));
+        imp_bl.push_back(blocks_of(q.q.H, q.q.W));
+        lmax_new = std::max(lmax_new, q.levels);
+        for (const LevelPlanes& L : q.L) {
+            der.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld});
+            der_bl.push_back(blocks_of(L.H, L.W));
+        }
+    }
+    const BLaunch l_imp = T.launch(imp, imp_bl);
+    std::vector<BLaunch> l_down(std::max(1, lmax_new));
+    for (int l = 1; l < lmax_new; ++l) {
+        std::vector<DownArgs> it;
+        std::vector<int> bl;
+        for (uint64_t t : active) {
+            Req& q = reqs[t];
+            if (q.imported || q.levels <= l) continue;
+            const LevelPlanes& F = q.L[l - 1];
+            const LevelPlanes& C = q.L[l];
+            it.push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
+            it.push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
+            bl.push_back(blocks_of(C.H, C.W));
+            bl.push_back(blocks_of(C.H, C.W));
+        }
+        l_down[l] = T.launch(it, bl);
+    }
+    const BLaunch l_der = T.launch(der, der_bl);
+
+    Shapes shapes;
+    for (uint64_t t : active) {
+        const LevelPlanes& L = reqs[t].L[reqs[t].l];
+        shapes.emplace_back(L.H, L.W);
+    }
+    StageChoice ch = default_stage_choice(shapes, hw, p.iters);
+    if (g_batch_order >= 0) ch.order = g_batch_order;
+    if (g_batch_ew > 0) ch.ew = g_batch_ew;
+    if (g_batch_k > 0) ch.K = g_batch_k;
+    ch = fit_stage_choice(ch, shapes, hw);
+    const int lpw = launches_per_warp(p.iters, ch.K);
+
+    std::vector<LevelInitArgs> init;
+    std::vector<int> init_bl;
+    std::vector<LinArgs> lin;
+    std::vector<CommitArgs> com;
+    std::vector<int> bl;
+    std::vector<TbLevel> descs(2 * active.size());
+    std::vector<TbTile> tiles;
+    std::vector<EnergyArgs> en;
+    std::vector<int> en_bl;
+    std::vector<CopyArgs> exp;
+    std::vector<int> exp_bl;
+    std::vector<uint64_t> finishing;
+    Scratch none;
+    for (size_t i = 0; i < active.size(); ++i) {
+        Req& q = reqs[active[i]];
+        const int l = q.l;
+        const LevelPlanes& L = q.L[l];
+        float* at2 = d_at + 2 * q.slot;
+        if (q.w == 0) {
+            LevelInitArgs ia{};
+            ia.H = L.H; ia.W = L.W; ia.ld = L.ld;
+            if (l < q.levels - 1) {
+                const LevelPlanes& C = q.L[l + 1];
+                ia.uc = level_flow(C, p, 1, q.cur_coarse);
+                ia.vc = level_flow(C, p, 2, q.cur_coarse);
+                ia.wc = hw ? level_flow(C, p, 0, q.cur_coarse) : nullptr;
+                ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
+            }
+            ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
+            ia.set_flow[1] = L.U0[0];
+            ia.set_flow[2] = L.U0[1];
+            int nz = 0;
+            for (int k = 3; k < 10; ++k)
+                if (L.st[0][k]) ia.zero[nz++] = L.st[0][k];
+            ia.nzero = nz;
+            ia.clear_scalar = at2;
+            init.push_back(ia);
+            init_bl.push_back(blocks_of(L.H, L.W));
+        }
+        LinArgs la{};
+        la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+        la.u0 = L.U0[0];
+        la.v0 = L.U0[1];
+        la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
+        la.at = at2 + (q.w & 1);
+        la.at_clear = at2 + ((q.w + 1) & 1);
+        la.H = L.H; la.W = L.W; la.ld = L.ld;
+        la.kappa = (float)p.intensity_scale;
+        la.beta = (float)p.beta;
+        la.rel = 1;
+        la.zero_u = L.st[q.cur][1];
+        la.zero_v = L.st[q.cur][2];
+        lin.push_back(la);
+        bl.push_back(blocks_of(L.H, L.W));
+        // descriptors in the pair's own direction: launch direction 0 reads state buffer q.cur
+        TbLevel d[2];
+        fill_tb_level(d, L, at2 + (q.w & 1));
+        descs[2 * i] = d[q.cur];
+        descs[2 * i + 1] = d[q.cur ^ 1];
+        level_tiles(L.H, L.W, hw, ch, (int)i, tiles);
+        const int after = q.cur ^ (lpw & 1);
+        if (l == 0 && q.w == p.warps - 1) {
+            EnergyArgs e = energy_args(L, p, after, none);
+            e.partial = d_epart + (size_t)q.slot * kEnergyTerms * kEnergyBlocks;
+            e.out = d_eout + (size_t)q.slot * kEnergyTerms;
+            en.push_back(e);
+            en_bl.push_back(energy_blocks(L.H, L.W));
+            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv});
+            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv});
+            exp_bl.push_back(blocks_of(L.H, L.W));
+            exp_bl.push_back(blocks_of(L.H, L.W));
+            finishing.push_back(active[i]);
+        }
+        com.push_back(CommitArgs{L.U0[0], L.U0[1], L.st[after][1], L.st[after][2], L.H, L.W, L.ld});
+    }
+    const BLaunch l_init = T.launch(init, init_bl);
+    const BLaunch l_lin = T.launch(lin, bl);
+    const BLaunch l_com = T.launch(com, bl);
+    const BLaunch l_en = T.launch(en, en_bl);
+    const BLaunch l_exp = T.launch(exp, exp_bl);
+    const size_t descs_off = T.put(descs);
+    const size_t tiles_off = T.put(tiles);
+
+    r = htab[b].ensure(T.h.size());
+    if (r != FLOW_OK) return r;
+    r = tab[b].ensure(T.h.size(), "serving tables");
+    if (r != FLOW_OK) return r;
+    std::memcpy(htab[b].h, T.h.data(), T.h.size());
+    HIP_TRY(hipSetDevice(device));
+    HIP_TRY(hipMemcpyAsync(tab[b].d, htab[b].h, T.h.size(), hipMemcpyHostToDevice, s));
+
+    // ---- launches
+    const char* tb = tab[b].d;
+    if (ch.order == ORDER_QUEUE) launch_reset_u32(d_cnt, lpw * kNq, s);
+    run_items(BatchOp::Copy, tb, l_imp, f16, s);
+    for (int l = 1; l < lmax_new; ++l) run_items(BatchOp::Downsample, tb, l_down[l], f16, s);
+    run_items(BatchOp::Derivatives, tb, l_der, f16, s);
+    run_items(BatchOp::LevelInit, tb, l_init, false, s);
+    run_items(BatchOp::Linearize, tb, l_lin, f16, s);
+    const int ntiles = (int)tiles.size();
+    enqueue_tile_warp((const TbTile*)(tb + tiles_off), ntiles, tile_grid(ch, ntiles), (const TbLevel*)(tb + descs_off),
+                      ch, p, 0, 0, d_cnt, s);
+    if (l_en.n > 0)
+        launch_energy_batched((const EnergyArgs*)(tb + l_en.items), (const int*)(tb + l_en.off), l_en.n, l_en.total, s);
+    run_items(BatchOp::Commit, tb, l_com, false, s);
+    run_items(BatchOp::Copy, tb, l_exp, false, s);
+    if (!finishing.empty())
+        HIP_TRY(hipMemcpyAsync(he[b].h, d_eout, sizeof(double) * kEnergyTerms * max_active, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ep[b].ev, s));
+    ep[b].in_flight = true;
+    ep[b].finishing = finishing;
+
+    // ---- cursors
+    std::vector<uint64_t> still;
+    for (uint64_t t : active) {
+        Req& q = reqs[t];
+        q.imported = true;
+        q.cur ^= lpw & 1;
+        if (++q.w == p.warps) {
+            q.w = 0;
+            if (q.l == 0) continue;            // finished: results once this epoch completes
+            q.cur_coarse = q.cur;
+            q.cur = 0;
+            --q.l;
+        }
+        still.push_back(t);
+    }
+    active.swap(still);
+    st.epochs++;
+    if (n_active) *n_active = (int32_t)active.size();
+    if (n_queued) *n_queued = (int32_t)queue.size();
+    return FLOW_OK;
+}
+
+extern "C" {
+
+flow_status flow_server_create(flow_ctx* ctx, const flow_params* p, size_t hbm_budget, int32_t max_active,
+                               void* stream, flow_server** out) {
+    if (!ctx || !out) return fail(FLOW_E_INVAL, "NULL argument");
+    *out = nullptr;
+    flow_status r = validate(p);
+    if (r != FLOW_OK) return r;
+    if (p->scheme == FLOW_PDR) return fail(FLOW_E_INVAL, "the serving engine runs the ADMM family (pADMM, rpADMMII)");
+    if (p->tol > 0) return fail(FLOW_E_INVAL, "the serving engine runs a fixed iteration count (tol = 0)");
+    if (max_active < 1 || max_active > 4096) return fail(FLOW_E_INVAL, "max_active must be in [1, 4096]");
+    if (hbm_budget == 0) hbm_budget = (size_t)8 << 30;
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<flow_server> srv(new flow_server());
+    srv->device = ctx->device;
+    r = srv->init(*p, hbm_budget, max_active, (hipStream_t)stream);
+    if (r != FLOW_OK) return r;
+    *out = srv.release();
+    return FLOW_OK;
+}
+
+flow_status flow_working_set_bytes(int32_t H, int32_t W, const flow_params* p, int32_t levels, uint64_t* bytes) {
+    if (!bytes) return fail(FLOW_E_INVAL, "bytes is NULL");
+    flow_status r = validate(p);
+    if (r != FLOW_OK) return r;
+    if (levels < 0 || levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "levels out of range");
+    flow_params pk = *p;
+    if (levels > 0) pk.levels = levels;
+    r = validate_shape(H, W, W, pk.levels);
+    if (r != FLOW_OK) return r;
+    *bytes = (layout_bytes(H, W, pk) + 255) & ~(size_t)255;
+    return FLOW_OK;
+}
+
+flow_status flow_server_destroy(flow_server* srv) {
+    if (!srv) return FLOW_OK;
+    hipSetDevice(srv->device);
+    delete srv;
+    return FLOW_OK;
+}
+
+flow_status flow_server_submit(flow_server* srv, const flow_pair* pair, uint64_t* ticket) {
+    if (!srv || !pair || !ticket) return fail(FLOW_E_INVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(srv->device));
+    flow_status r = validate_pair(*pair, srv->p, "");
+    if (r != FLOW_OK) return r;
+    Req q;
+    q.q = *pair;
+    q.levels = pair->levels > 0 ? pair->levels : srv->p.levels;
+    flow_params pk = srv->p;
+    pk.levels = q.levels;
+    q.bytes = (layout_bytes(pair->H, pair->W, pk) + 255) & ~(size_t)255;
+    if (q.bytes > srv->arena.bytes)
+        return fail(FLOW_E_NOMEM, "pair working set of " + std::to_string(q.bytes) + " bytes exceeds the serving budget");
+    const uint64_t t = srv->next_ticket++;
+    srv->reqs.emplace(t, std::move(q));
+    srv->queue.push_back(t);
+    srv->st.submitted++;
+    *ticket = t;
+    return FLOW_OK;
+}
+
+flow_status flow_server_step(flow_server* srv, int32_t* active, int32_t* queued) {
+    if (!srv) return fail(FLOW_E_INVAL, "server is NULL");
+    HIP_TRY(hipSetDevice(srv->device));
+    return srv->step(active, queued);
+}
+
+flow_status flow_server_poll(flow_server* srv, uint64_t ticket, int32_t* done) {
+    if (!srv || !done) return fail(FLOW_E_INVAL, "NULL argument");
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(FLOW_E_NOTFOUND, "unknown or already collected ticket");
+    for (int b = 0; b < 2 && !it->second.done; ++b) {
+        // a finishing epoch that has completed on the device hands its results over now
+        Epoch& E = srv->ep[b];
+        if (E.in_flight && hipEventQuery(E.ev) == hipSuccess) {
+            flow_status r = srv->retire(b);
+            if (r != FLOW_OK) return r;
+        }
+    }
+    *done = it->second.done ? 1 : 0;
+    if (!it->second.done) return FLOW_OK;
+    const flow_status st = it->second.status;
+    srv->reqs.erase(it);
+    if (st != FLOW_OK) return fail(st, "non-finite energy or gap");
+    return FLOW_OK;
+}
+
+flow_status flow_server_drain(flow_server* srv) {
+    if (!srv) return fail(FLOW_E_INVAL, "server is NULL");
+    HIP_TRY(hipSetDevice(srv->device));
+    int32_t a = 0, q = 0;
+    do {
+        flow_status r = srv->step(&a, &q);
+        if (r != FLOW_OK) return r;
+    } while (a > 0 || q > 0);
+    for (int b = 0; b < 2; ++b) {
+        flow_status r = srv->retire(b);
+        if (r != FLOW_OK) return r;
+    }
+    return FLOW_OK;
+}
+
+flow_status flow_server_get_stats(const flow_server* srv, flow_server_stats* out) {
+    if (!srv || !out) return fail(FLOW_E_INVAL, "NULL argument");
+    *out = srv->st;
+    out->active = (int32_t)srv->active.size();
+    out->queued = (int32_t)srv->queue.size();
+    out->bytes_in_use = srv->bytes_in_use;
+    return FLOW_OK;
+}
+
+}  // extern "C"

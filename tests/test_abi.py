@@ -101,7 +101,8 @@ def test_binding_allocates_outputs_with_the_input_pitch():
 
 @pytest.mark.parametrize("cname,pyname", [("flow_params", "_Params"), ("flow_result", "_Result"),
                                           ("flow_stats", "_Stats"), ("flow_pair", "_Pair"),
-                                          ("flow_admm_state", "_AdmmState"), ("flow_pdr_state", "_PdrState")])
+                                          ("flow_admm_state", "_AdmmState"), ("flow_pdr_state", "_PdrState"),
+                                          ("flow_server_stats", "_ServerStats")])
 def test_struct_layouts_match_the_header(tmp_path, cname, pyname):
     """Size and every field offset of the ctypes mirror equal what a C compiler makes of flow.h."""
     import paper_2011_10979_amd as fm
@@ -120,3 +121,17 @@ def test_struct_layouts_match_the_header(tmp_path, cname, pyname):
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got[0] == ctypes.sizeof(py)
     assert got[1:] == [getattr(py, f).offset for f in fields]
+
+
+def test_working_set_bytes_is_host_only_and_checked(flowlib):
+    import paper_2011_10979_amd as fm
+    vga = fm.working_set_bytes(480, 640)
+    assert vga % 256 == 0
+    # 9 pyramid / linearisation planes + 14 state planes per level (pitch 640), over 5 levels
+    assert 23 * 4 * 480 * 640 < vga < 23 * 4 * 480 * 640 * 1.45
+    assert fm.working_set_bytes(480, 640, levels=3) < vga
+    assert fm.working_set_bytes(480, 640, storage="f16") < vga
+    assert fm.working_set_bytes(480, 640, beta=0.05) > vga
+    for bad in ((1, 64, {}), (480, 640, {"levels": 17}), (40, 40, {"levels": 7})):
+        with pytest.raises(fm.FlowError):
+            fm.working_set_bytes(bad[0], bad[1], **bad[2])
