@@ -24,6 +24,11 @@ Other modes:
                     stages, graph replay); value = pixel-iterations of all pairs / step time; reported
                     beside 64 sequential plain solves of the same pairs (pairs/s, both plain
                     kernel plans) and a bitwise comparison of every pair with its plain tile solve
+  --mode serve      Poisson arrivals (mean 200 pairs/s, seed 7) of pairs drawn from a pool of 10
+                    pre-generated pairs per size (320x240, 640x480, 1024x436, 1280x720, 1920x1080 with
+                    probabilities 0.3, 0.3, 0.2, 0.1, 0.1), 2000 requests after 200 warm-up ones, served
+                    by the continuous-batching engine (8 GiB budget); value = completed pairs/s, with
+                    p50 / p99 latency; the same trace through a one-at-a-time plain-solve server beside it
   --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
                                       them from F instead of tuning (for profiler runs)
   --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
@@ -246,6 +251,187 @@ def run_batch(args):
     ctx.close()
 
 
+def _gen_serving_pair(job):
+    import synth
+    si, j = job
+    H, W = synth.SERVING_SIZES[si]
+    p = synth.vga_pair(5000 + 100 * si + j, H, W) if j % 2 == 0 else synth.hd_pair(5000 + 100 * si + j, H, W)
+    return p.I0.astype("float32"), p.I1.astype("float32")
+
+
+def _percentiles(lat):
+    import numpy as np
+    a = np.asarray(lat) * 1e3
+    return {"n": int(a.size), "p50_ms": round(float(np.percentile(a, 50)), 3), "p99_ms": round(float(np.percentile(a, 99)), 3),
+            "mean_ms": round(float(a.mean()), 3), "max_ms": round(float(a.max()), 3)}
+
+
+def run_serve(args):
+    """The serving configuration: a Poisson request trace through the continuous-batching engine and
+    through a one-at-a-time plain-solve server."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    import synth
+    import paper_2011_10979_amd as fm
+    workers = max(1, min(16, os.cpu_count() or 1))
+    per = args.pool
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        host = pool.map(_gen_serving_pair, [(si, j) for si in range(len(synth.SERVING_SIZES)) for j in range(per)])
+    print(f"[bench] generated {len(host)} pool pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    pool_dev = [[None] * per for _ in synth.SERVING_SIZES]
+    for si in range(len(synth.SERVING_SIZES)):
+        for j in range(per):
+            a, b = host[si * per + j]
+            pool_dev[si][j] = (torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+    levels = [synth.levels_by_size(H, W) for H, W in synth.SERVING_SIZES]
+    n_warm, n_meas = args.serve_warmup, args.requests
+    t_arr, size_idx = synth.serving_trace(n_warm + n_meas, args.rate, seed=7)
+    pick = np.random.default_rng(8).integers(0, per, size=n_warm + n_meas)
+    params = fm.Params(scheme=args.scheme, storage=args.storage, warps=args.warps, iters=args.iters)
+    px_iter = []
+    for si in size_idx:
+        H, W = synth.SERVING_SIZES[si]
+        tot = 0
+        for _ in range(levels[si]):
+            tot += H * W
+            H, W = (H + 1) // 2, (W + 1) // 2
+        px_iter.append(tot * args.warps * args.iters)
+    ctx = fm.Context(0)
+    torch.cuda.synchronize()
+
+    def replay(label, submit, advance, poll, t_arr=t_arr, n_warm=n_warm, n_meas=n_meas):
+        lat = [None] * len(t_arr)
+        done_t = [None] * len(t_arr)
+        pending = {}
+        i = 0
+        start = time.perf_counter()
+        last_print = start
+        while i < len(t_arr) or pending:
+            now = time.perf_counter() - start
+            while i < len(t_arr) and t_arr[i] <= now:
+                pending[submit(i)] = i
+                i += 1
+            if pending:
+                advance()
+                now = time.perf_counter() - start
+                for t in list(pending):
+                    if poll(t):
+                        k = pending.pop(t)
+                        lat[k] = now - t_arr[k]
+                        done_t[k] = now
+            elif i < len(t_arr):
+                time.sleep(max(0.0, t_arr[i] - now))
+            if time.perf_counter() - last_print > 5:
+                last_print = time.perf_counter()
+                print(f"[bench] {label}: {i} submitted, {len(pending)} pending", file=sys.stderr, flush=True)
+        meas = lat[n_warm:]
+        t_first = t_arr[n_warm] if n_warm else 0.0
+        t_last = max(done_t[n_warm:])
+        pxi = sum(px_iter[k % len(px_iter)] for k in range(n_warm, n_warm + n_meas))
+        out = {"pairs_per_s": round(float(n_meas / (t_last - t_first)), 2),
+               "Gpx_iter_s": round(float(pxi / (t_last - t_first) / 1e9), 3)}
+        out.update(_percentiles(meas))
+        per_size = {}
+        for si, (H, W) in enumerate(synth.SERVING_SIZES):
+            sel = [meas[k] for k in range(n_meas) if size_idx[(n_warm + k) % len(size_idx)] == si]
+            if sel:
+                per_size[f"{W}x{H}"] = _percentiles(sel)
+        out["per_size"] = per_size
+        return out
+
+    # continuous batching
+    srv = fm.Server(ctx, params, budget_bytes=args.budget_gib << 30, max_active=args.max_active)
+
+    def s_submit(i):
+        I0, I1 = pool_dev[size_idx[i]][pick[i]]
+        return srv.submit(I0, I1, levels[size_idx[i]])
+
+    def s_poll(t):
+        return srv.poll(t) is not None
+
+    served = replay("engine", s_submit, srv.step, s_poll)
+    sst = srv.stats()
+    served["engine"] = {k: sst[k] for k in ("epochs", "peak_active", "peak_bytes_in_use", "arena_bytes")}
+    # capacity: the first `capacity` requests of the trace all arriving at once
+    n_cap = min(args.capacity, len(t_arr))
+    cap_arr = np.zeros(n_cap)
+    cap_served = replay("engine capacity", s_submit, srv.step, s_poll, cap_arr, 0, n_cap) if n_cap else None
+    srv.close()
+    print(f"[bench] engine: {served}", file=sys.stderr, flush=True)
+
+    # one at a time: a FIFO of plain solves (graph replay per size, tiles at every level)
+    fm.set_tuning("tb_mode", 4)
+    gp = fm.Params(**{**params.__dict__, "use_graph": 1})
+    for si in range(len(synth.SERVING_SIZES)):                     # capture each size's graph
+        ctx.solve(*pool_dev[si][0], fm.Params(**{**gp.__dict__, "levels": levels[si]}))
+    queue = []
+    finished = set()
+    tick = [0]
+
+    def p_submit(i):
+        tick[0] += 1
+        queue.append((tick[0], i))
+        return tick[0]
+
+    def p_advance():
+        if queue:
+            t, i = queue.pop(0)
+            I0, I1 = pool_dev[size_idx[i]][pick[i]]
+            ctx.solve(I0, I1, fm.Params(**{**gp.__dict__, "levels": levels[size_idx[i]]}))
+            finished.add(t)
+
+    plain = replay("plain", p_submit, p_advance, lambda t: t in finished)
+    cap_plain = replay("plain capacity", p_submit, p_advance, lambda t: t in finished, cap_arr, 0, n_cap) \
+        if n_cap else None
+    fm.set_tuning("tb_mode", 0)
+    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+
+    # accuracy: served flows of the smallest size against the FP64 oracle
+    check = None
+    if not args.no_cpu_baseline:
+        jobs = []
+        seen = list(range(min(per, args.oracle_pairs)))
+        for j in seen:
+            a, b = host[j]
+            jobs.append((a, b, dict(scheme=args.scheme, levels=levels[0], warps=args.warps, iters=args.iters)))
+        # served results of those pool pairs: any request that used them (results are the same per pair)
+        srv = fm.Server(ctx, params, budget_bytes=1 << 30, max_active=8)
+        tk = {j: srv.submit(*pool_dev[0][j], levels[0]) for j in seen}
+        srv.drain()
+        got = {j: srv.poll(t) for j, t in tk.items()}
+        srv.close()
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(min(workers, max(1, len(jobs)))) as pool:
+            refs = pool.map(_oracle_pair, jobs)
+        dt = time.perf_counter() - t0
+        epes = []
+        for j, (ru, rv, _) in zip(seen, refs):
+            u, v = got[j][0].cpu().numpy(), got[j][1].cpu().numpy()
+            epes.append(float(np.sqrt((u - ru) ** 2 + (v - rv) ** 2).mean()))
+        check = {"size": "320x240", "pairs": len(jobs), "mean_epe_vs_oracle": epes, "max": max(epes),
+                 "oracle_pairs_per_s": round(len(jobs) / dt, 3), "oracle_cores": min(workers, len(jobs))}
+    line = {
+        "metric": "pairs/s with p50 / p99 latency (served coarse-to-fine TV-L1 flow solves, Poisson arrivals)",
+        "value": served["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals {args.rate}/s, {n_meas} requests after {n_warm}, sizes "
+                               f"320x240/640x480/1024x436/1280x720/1920x1080 (p .3/.3/.2/.1/.1), pool of {per} "
+                               f"pairs per size, pyramid depth by size x {args.warps} warps x {args.iters} "
+                               f"iterations, {args.scheme}",
+                   "budget_GiB": args.budget_gib, "max_active": args.max_active},
+        "served": served, "plain_one_at_a_time": plain,
+        "capacity": {"requests": n_cap, "note": "the first requests of the trace, all arriving at once",
+                     "engine": cap_served, "plain_one_at_a_time": cap_plain},
+        "oracle_check": check,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def calibrate_copy(mb, steps):
     """Plain device-to-device copies of `mb` MiB: the kernel of known traffic (mb MiB read and mb
     MiB written per launch) that scales the HBM counters."""
@@ -284,7 +470,14 @@ def main():
     ap.add_argument("--save-tuning", default=None)
     ap.add_argument("--load-tuning", default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
-    ap.add_argument("--mode", default="single", choices=["single", "batch"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--pool", type=int, default=10)
+    ap.add_argument("--budget-gib", type=int, default=8)
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--capacity", type=int, default=600, help="requests of the saturation run (0: none)")
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--oracle-pairs", type=int, default=4)
     args = ap.parse_args()
@@ -304,6 +497,9 @@ def main():
         return
     if args.mode == "batch":
         run_batch(args)
+        return
+    if args.mode == "serve":
+        run_serve(args)
         return
 
     dev = torch.device("cuda:0")
