@@ -399,14 +399,14 @@ void fill_io(BatchState& B, int n, const flow_pair* pairs, const flow_params& p)
     const BatchPlan& P = *B.plan;
     CopyArgs* ci = (CopyArgs*)(B.h_io.h + P.imp.items);
     CopyArgs* ce = (CopyArgs*)(B.h_io.h + P.exp.items);
-    (void)p;
     for (int k = 0; k < n; ++k) {
         const LevelPlanes& L = P.L[k][0];
         const flow_pair& q = pairs[k];
-        ci[2 * k] = CopyArgs{q.I0, q.H, q.W, q.ld, L.I0, L.ld};
-        ci[2 * k + 1] = CopyArgs{q.I1, q.H, q.W, q.ld, L.I1, L.ld};
-        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv};
-        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv};
+        const float off = p.storage == FLOW_STORE_F16 ? kFrameOffsetF16 : 0.f;
+        ci[2 * k] = CopyArgs{q.I0, q.H, q.W, q.ld, L.I0, L.ld, off};
+        ci[2 * k + 1] = CopyArgs{q.I1, q.H, q.W, q.ld, L.I1, L.ld, off};
+        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv, 0.f};
+        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv, 0.f};
     }
 }
 

@@ -29,7 +29,11 @@ void launch_linearize(const LinArgs& a, bool f16, hipStream_t s);
 // Argument blocks of the elementwise pyramid / bookkeeping kernels (also the items of batched launches).
 struct DownArgs { const void* src; int H, W; int64_t ld; void* dst; int64_t ldd; };     // output ceil(H/2) x ceil(W/2)
 struct DerivArgs { const void* I; int H, W; int64_t ld; void* Dx; void* Dy; int64_t ldd; };
-struct CopyArgs { const float* src; int H, W; int64_t lds; void* dst; int64_t ldd; };    // FP32 -> FP32 or FP16
+// FP32 -> FP32 or FP16 plane copy, dst = src - offset.  Frames imported into FP16 pyramids are
+// stored centred (offset kFrameOffsetF16): every pyramid step is linear and I_t is a difference, so
+// the offset cancels, while FP16 spacing over [-1/2, 1/2] is half of that over [1/2, 1].
+struct CopyArgs { const float* src; int H, W; int64_t lds; void* dst; int64_t ldd; float offset; };
+constexpr float kFrameOffsetF16 = 0.5f;
 struct CommitArgs { float* u0; float* v0; const float* du; const float* dv; int H, W; int64_t ld; };
 
 // Batched launches of one body over many items (one work-group grid per item, prefix offsets).

@@ -62,7 +62,7 @@ __device__ __forceinline__ void copy_body(const CopyArgs& a, int bx, int by) {
     const int j = bx * 64 + (threadIdx.x & 63);
     const int i = by * 4 + (threadIdx.x >> 6);
     if (i >= a.H || j >= a.W) return;
-    stv((T*)a.dst, (int64_t)i * a.ldd + j, a.src[(int64_t)i * a.lds + j]);
+    stv((T*)a.dst, (int64_t)i * a.ldd + j, a.src[(int64_t)i * a.lds + j] - a.offset);
 }
 
 __device__ __forceinline__ void commit_body(const CommitArgs& a, int bx, int by) {
@@ -249,13 +249,13 @@ void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void*
 }
 
 void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64_t ldd, bool f16, hipStream_t s) {
-    const CopyArgs a{src, H, W, lds, dst, ldd};
+    const CopyArgs a{src, H, W, lds, dst, ldd, f16 ? kFrameOffsetF16 : 0.f};
     if (f16) hipLaunchKernelGGL(copy_kernel<__half>, grid2d(H, W), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }
 
 void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s) {
-    const CopyArgs a{src, H, W, lds, dst, ldd};
+    const CopyArgs a{src, H, W, lds, dst, ldd, 0.f};
     hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }
 

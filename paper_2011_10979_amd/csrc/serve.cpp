@@ -265,8 +265,9 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         Req& q = reqs[t];
         if (q.imported) continue;
         const LevelPlanes& L0 = q.L[0];
-        imp.push_back(CopyArgs{q.q.I0, q.q.H, q.q.W, q.q.ld, L0.I0, L0.ld});
-        imp.push_back(CopyArgs{q.q.I1, q.q.H, q.q.W, q.q.ld, L0.I1, L0.ld});
+        const float off = f16 ? kFrameOffsetF16 : 0.f;
+        imp.push_back(CopyArgs{q.q.I0, q.q.H, q.q.W, q.q.ld, L0.I0, L0.ld, off});
+        imp.push_back(CopyArgs{q.q.I1, q.q.H, q.q.W, q.q.ld, L0.I1, L0.ld, off});
         imp_bl.push_back(blocks_of(q.q.H, q.q.W));
         imp_bl.push_back(blocks_of(q.q.H, q.q.W));
         lmax_new = std::max(lmax_new, q.levels);
@@ -373,8 +374,8 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             e.out = d_eout + (size_t)q.slot * kEnergyTerms;
             en.push_back(e);
             en_bl.push_back(energy_blocks(L.H, L.W));
-            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv});
-            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv});
+            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv, 0.f});
+            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv, 0.f});
             exp_bl.push_back(blocks_of(L.H, L.W));
             exp_bl.push_back(blocks_of(L.H, L.W));
             finishing.push_back(active[i]);

@@ -68,9 +68,9 @@ def test_batched_pairs_match_the_oracle(ctx, scheme, relax, beta):
     with mp.get_context("fork").Pool(4) as pool:
         fut = oracle_with_sensitivity(jobs, pool)
         out = batched(ctx, fr, **kw)
-        refs = fut.get(timeout=900)
+        refs = fut(900)
     for k, (u, v, res) in enumerate(out):
-        assert_conditioned(f"batched pair {k} {MIX[k][:2]}", to_np(u), to_np(v), res, refs[2 * k], refs[2 * k + 1])
+        assert_conditioned(f"batched pair {k} {MIX[k][:2]}", to_np(u), to_np(v), res, refs[k][0], refs[k][1:])
 
 
 def test_batched_equals_plain_tile_solves_bitwise(ctx):

@@ -1,0 +1,100 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configurations the benchmark
+times.
+
+  1920x1080, 6 levels x 5 warps x 50 iterations (rotation + zoom up to 20 px with occluding
+  boxes), FP32 storage and FP16-stored pyramids, against the full FP64 oracle solve;
+  the 64-pair batch of uneven sizes: every batched pair bitwise equal to its plain tile solve, and
+  the smallest pairs against the oracle;
+  one pair of every serving size through the serving engine, bitwise equal to the batched solve.
+"""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2011_10979_amd as fm  # noqa: E402
+import synth  # noqa: E402
+from helpers import to_dev, to_np, f32, oracle_with_sensitivity, assert_conditioned  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fm.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(autouse=True)
+def reset_knobs():
+    yield
+    fm.set_tuning("tb_mode", 0)
+
+
+def _gen(k):
+    p = synth.batch_pair(k)
+    return f32(p.I0), f32(p.I1)
+
+
+def test_hd_1080p_fp32_and_fp16_against_the_oracle(ctx):
+    print("[case] 1920x1080 6x5x50 fp32 + fp16", flush=True)
+    pair = synth.hd_pair(seed=2)
+    I0, I1 = f32(pair.I0), f32(pair.I1)
+    kw = dict(levels=6, warps=5, iters=50)
+    with mp.get_context("fork").Pool(4) as pool:
+        fut = oracle_with_sensitivity([(I0, I1, kw)], pool, probes=3)
+        u, v, res = ctx.solve(to_dev(I0), to_dev(I1), fm.Params(**kw, use_graph=1))
+        u16, v16, _ = ctx.solve(to_dev(I0), to_dev(I1), fm.Params(**kw, storage="f16"))
+        ref, *perts = fut(1200)[0]
+    assert_conditioned("1080p fp32", to_np(u), to_np(v), res, ref, perts)
+    d = np.maximum(np.abs(to_np(u) - ref[0]), np.abs(to_np(v) - ref[1]))
+    assert np.quantile(d, 0.999) <= 1e-4 and d.mean() <= 1e-5
+    epe16 = np.hypot(to_np(u16) - ref[0], to_np(v16) - ref[1])
+    print(f"[parity] 1080p fp16 storage: EPE vs oracle mean {epe16.mean():.3e} p99.9 {np.quantile(epe16, 0.999):.3e} "
+          f"max {epe16.max():.3e}", flush=True)
+    assert epe16.mean() <= 1e-2
+
+
+def test_batch_of_64_uneven_pairs(ctx):
+    print("[case] batch of 64", flush=True)
+    with mp.get_context("fork").Pool(16) as pool:
+        host = pool.map(_gen, range(64))
+    frames = [(to_dev(a), to_dev(b), synth.levels_by_size(*a.shape)) for a, b in host]
+    kw = dict(warps=5, iters=50)
+    out = ctx.solve_batched(frames, fm.Params(**kw, use_graph=1))
+    fm.set_tuning("tb_mode", 4)
+    for k, (I0, I1, lv) in enumerate(frames):
+        u, v, res = ctx.solve(I0, I1, fm.Params(**kw, levels=lv))
+        assert torch.equal(u, out[k][0]) and torch.equal(v, out[k][1]) and res["energy"] == out[k][2]["energy"], k
+    small = sorted(range(64), key=lambda k: host[k][0].size)[:2]
+    jobs = [(host[k][0], host[k][1], dict(kw, levels=frames[k][2])) for k in small]
+    with mp.get_context("fork").Pool(4) as pool:
+        refs = oracle_with_sensitivity(jobs, pool, probes=2)(900)
+    for i, k in enumerate(small):
+        assert_conditioned(f"batch pair {k} {host[k][0].shape}", to_np(out[k][0]), to_np(out[k][1]), out[k][2],
+                           refs[i][0], refs[i][1:])
+
+
+def test_serving_sizes_through_the_engine(ctx):
+    print("[case] serving sizes", flush=True)
+    frames = []
+    for si, (H, W) in enumerate(synth.SERVING_SIZES):
+        p = synth.vga_pair(7000 + si, H, W)
+        frames.append((to_dev(f32(p.I0)), to_dev(f32(p.I1)), synth.levels_by_size(H, W)))
+    kw = dict(warps=5, iters=50)
+    srv = fm.Server(ctx, fm.Params(**kw), budget_bytes=2 << 30, max_active=16)
+    tick = []
+    for f in frames:
+        tick.append(srv.submit(*f))
+        srv.step()
+    srv.drain()
+    served = [srv.poll(t) for t in tick]
+    srv.close()
+    batched = ctx.solve_batched(frames, fm.Params(**kw))
+    for k in range(len(frames)):
+        assert torch.equal(served[k][0], batched[k][0]) and torch.equal(served[k][1], batched[k][1]), k
+        assert served[k][2]["energy"] == batched[k][2]["energy"]
