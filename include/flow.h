@@ -150,7 +150,7 @@ typedef struct flow_pair {
 
 /* Solve n pairs of uneven sizes together (the coarse-to-fine solve of Sec. 4 for every pair).
  * Stage s works on pyramid level Lmax-1-s of every pair that has it (all pairs reach level 0 in
- * the last stage); each step of a stage (level start, warp, K iterations, commit, energy) is ONE
+ * the last stage); each step of a stage (level start, linearisation, K iterations, energy) is ONE
  * launch over all pairs, the iterations a launch of the K-iteration tile kernel over the tiles of
  * every pair's level, in XCD order or from per-XCD work queues (choice, K and tile width per stage
  * from flow_autotune_batched, else built in).  ADMM family only with tol = 0 (pDR pairs and
@@ -201,7 +201,7 @@ flow_status flow_server_submit(flow_server* srv, const flow_pair* pair, uint64_t
 /* Run one epoch (asynchronous on the engine's stream): admit queued pairs, in arrival order, while
  * a slot and room in the budget are free (first-fit; a pair that does not fit holds the queue);
  * advance every admitted pair by one warp of its coarse-to-fine solve (Sec. 4) -- level start where
- * due, linearisation, `iters` iterations, commit -- with one launch per step over all of them
+ * due, linearisation, `iters` iterations -- with one launch per step over all of them
  * (tile launches cover the current level of every pair; pairs at different levels and warps share
  * them); finish the pairs that completed level 0 (energy, flow export).  Released memory and slots
  * return when the epoch's work has completed on the device.  Blocks only when the buffers of the
@@ -319,8 +319,8 @@ flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* 
 
 /* `iters` iterations in ONE launch of the temporally blocked tile kernel (the solver's path for
  * levels that do not need the one-pass kernel), increment form only (in->u0, in->v0 set).
- * threads: 256 or 1024 (6 pixels per thread, 4 with beta > 0) or 1025 (1024 threads, 2 pixels per
- * thread); tile_h x tile_w: output tile; each tile's extended region
+ * threads: 256 (6 pixels per thread, 4 with beta > 0), 1024 (4, 3 with beta > 0) or 1025 (1024
+ * threads, 2 pixels per thread); tile_h x tile_w: output tile; each tile's extended region
  * min(H, tile_h + 3 iters) x min(W, tile_w + 3 iters) must fit that capacity, else FLOW_E_INVAL.
  * order: 0 = one work-group per tile (tile from the work-group index), 1 = persistent work-groups
  * pulling tiles from one counter, 2 = the same with 8 per-XCD sub-queues (the batched path's work

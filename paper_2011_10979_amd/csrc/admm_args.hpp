@@ -33,8 +33,10 @@ extern int g_admm_rows_override;   // 0 = heuristic; 2, 4 or 8 force the strip h
 void launch_admm_iter(const AdmmIterArgs& a, bool has_w, hipStream_t s);
 
 // Temporally blocked iterations: K iterations of one output tile per work-group launch.
-constexpr int kTbPpt = 6;            // pixels per thread (beta = 0): LDS q1x..q2y, gu, gv
+constexpr int kTbPpt = 6;            // pixels per thread, 256 threads (beta = 0): LDS q1x..q2y, gu, gv
 constexpr int kTbPptW = 4;           // with the w / p block
+constexpr int kTbPptL = 4;           // 1024 threads (at most 128 VGPRs per thread)
+constexpr int kTbPptLW = 3;
 constexpr int kTbPptSmall = 2;       // 1024 threads on small tiles (work-group size code 1025)
 struct TbTile {
     int level;                       // index of the (pair, level) descriptor

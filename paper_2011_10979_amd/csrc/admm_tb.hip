@@ -35,9 +35,16 @@ struct TileLds {
 };
 
 // K iterations of output tile T of level L by the calling work-group.
+//
+// Control flow is wavefront-uniform: a wavefront skips a slot only when none of its lanes holds a
+// pixel of the extended region; otherwise every lane runs it (lanes past the region hold zeros and
+// compute values nobody uses).  Neighbour values are read from LDS at indices clamped into the
+// array and then selected, so no read sits behind a divergent branch and the reads of a phase
+// issue together.
 template <bool HAS_W, int NT, int PPT>
 __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, const TbLevel& L,
                                              TileLds<HAS_W, NT, PPT>& S) {
+    constexpr int CAP = NT * PPT;
     float* sq1x = S.sq1x; float* sq1y = S.sq1y; float* sq2x = S.sq2x; float* sq2y = S.sq2y;
     float* sgu = S.sgu; float* sgv = S.sgv; float* spx = S.spx; float* spy = S.spy; float* sgw = S.sgw;
     const int tid = threadIdx.x;
@@ -53,19 +60,37 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);   // a~ >= ||M_s||, floored
 
         float du[PPT], dv[PPT], ss[PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], ww[PPT];
+        // per-slot neighbour structure: in-array neighbour indices (clamped into the array) and the
+        // masks of the discrete operators (Sec. 2.2) -- the neighbour lies inside the extended region
+        // (hl, hu, hr, hd), the forward difference / the dual field's own term exists in the image (mx, my)
         int ei[PPT], ej[PPT];
+        // slot k of this wavefront holds any pixel of the extended region (wave-uniform, scalar branch)
+        const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+        auto live = [&](int k) { return wave0 + k * NT < EN; };
+        auto eL = [&](int k) { return max(tid + k * NT - 1, 0); };
+        auto eU = [&](int k) { return max(tid + k * NT - EW, 0); };
+        auto eR = [&](int k) { return min(tid + k * NT + 1, CAP - 1); };
+        auto eD = [&](int k) { return min(tid + k * NT + EW, CAP - 1); };
+        auto hl = [&](int k) { return ej[k] > 0 && ex0 + ej[k] > 0; };
+        auto hu = [&](int k) { return ei[k] > 0 && ey0 + ei[k] > 0; };
+        auto hr = [&](int k) { return ej[k] < EW - 1; };
+        auto hd = [&](int k) { return tid + k * NT + EW < EN; };
+        auto mx = [&](int k) { return ex0 + ej[k] < W - 1 ? 1.f : 0.f; };
+        auto my = [&](int k) { return ey0 + ei[k] < H - 1 ? 1.f : 0.f; };
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int e = tid + k * NT;
             ei[k] = e / EW;
             ej[k] = e - ei[k] * EW;
+            const int gi = ey0 + ei[k], gj = ex0 + ej[k];
             du[k] = dv[k] = ss[k] = Ix[k] = Iy[k] = It[k] = u0[k] = v0[k] = ww[k] = 0.f;
+            float q1x = 0.f, q1y = 0.f, q2x = 0.f, q2y = 0.f, px = 0.f, py = 0.f;
             if (e < EN) {
-                const int64_t o = (int64_t)(ey0 + ei[k]) * ld + (ex0 + ej[k]);
-                sq1x[e] = L.in[5][o];
-                sq1y[e] = L.in[6][o];
-                sq2x[e] = L.in[7][o];
-                sq2y[e] = L.in[8][o];
+                const int64_t o = (int64_t)gi * ld + gj;
+                q1x = L.in[5][o];
+                q1y = L.in[6][o];
+                q2x = L.in[7][o];
+                q2y = L.in[8][o];
                 du[k] = L.in[1][o];
                 dv[k] = L.in[2][o];
                 ss[k] = L.in[9][o];
@@ -75,29 +100,40 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 u0[k] = L.u0[o];
                 v0[k] = L.v0[o];
                 if constexpr (HAS_W) {
-                    spx[e] = L.in[3][o];
-                    spy[e] = L.in[4][o];
+                    px = L.in[3][o];
+                    py = L.in[4][o];
                     ww[k] = L.in[0][o];
                 }
+            }
+            sq1x[e] = q1x;
+            sq1y[e] = q1y;
+            sq2x[e] = q2x;
+            sq2y[e] = q2y;
+            if constexpr (HAS_W) {
+                spx[e] = px;
+                spy[e] = py;
             }
         }
         __syncthreads();
 
-        // phase A (g) for the thread's pixels
+        // divergence of a dual field at slot k: [j < W-1] fx(i,j) - [j > 0] fx(i,j-1) + [i < H-1] fy(i,j) - [i > 0] fy(i-1,j)
+        auto divk = [&](const float* fx, const float* fy, int k, int e) {
+            const float l = fx[eL(k)], u = fy[eU(k)];
+            return mx(k) * fx[e] - (hl(k) ? l : 0.f) + my(k) * fy[e] - (hu(k) ? u : 0.f);
+        };
+
+        // phase A (g) for the thread's slots
         auto phase_a = [&]() {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
+                if (!live(k)) continue;
                 const int e = tid + k * NT;
-                if (e >= EN) continue;
-                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-                const bool l = ej[k] > 0 && gj > 0, u = ei[k] > 0 && gi > 0;
-                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
-                const float dq1 = mx * sq1x[e] - (l ? sq1x[e - 1] : 0.f) + my * sq1y[e] - (u ? sq1y[e - EW] : 0.f);
-                const float dq2 = mx * sq2x[e] - (l ? sq2x[e - 1] : 0.f) + my * sq2y[e] - (u ? sq2y[e - EW] : 0.f);
+                const float dq1 = divk(sq1x, sq1y, k, e);
+                const float dq2 = divk(sq2x, sq2y, k, e);
                 sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
                 sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
                 if constexpr (HAS_W) {
-                    const float dp = mx * spx[e] - (l ? spx[e - 1] : 0.f) + my * spy[e] - (u ? spy[e - EW] : 0.f);
+                    const float dp = divk(spx, spy, k, e);
                     sgw[e] = ww[k] + c * (dp - beta * ss[k]);
                 }
             }
@@ -106,19 +142,17 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         phase_a();
         for (int it = 0; it < K; ++it) {
             __syncthreads();
-            // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own pixel)
+            // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own slot)
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
+                if (!live(k)) continue;
                 const int e = tid + k * NT;
-                if (e >= EN) continue;
-                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-                const bool r = ej[k] < EW - 1, d = e + EW < EN;
-                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
                 const float gu = sgu[e], gv = sgv[e];
-                const float t1x = sq1x[e] + mx * ((r ? sgu[e + 1] : gu) - gu) * inv_ac;
-                const float t1y = sq1y[e] + my * ((d ? sgu[e + EW] : gu) - gu) * inv_ac;
-                const float t2x = sq2x[e] + mx * ((r ? sgv[e + 1] : gv) - gv) * inv_ac;
-                const float t2y = sq2y[e] + my * ((d ? sgv[e + EW] : gv) - gv) * inv_ac;
+                const float gur = sgu[eR(k)], gud = sgu[eD(k)], gvr = sgv[eR(k)], gvd = sgv[eD(k)];
+                const float t1x = sq1x[e] + mx(k) * ((hr(k) ? gur : gu) - gu) * inv_ac;
+                const float t1y = sq1y[e] + my(k) * ((hd(k) ? gud : gu) - gu) * inv_ac;
+                const float t2x = sq2x[e] + mx(k) * ((hr(k) ? gvr : gv) - gv) * inv_ac;
+                const float t2y = sq2y[e] + my(k) * ((hd(k) ? gvd : gv) - gv) * inv_ac;
                 const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
                 const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
                 sq1x[e] = t1x * sc;
@@ -126,9 +160,9 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 sq2x[e] = t2x * sc;
                 sq2y[e] = t2y * sc;
                 if constexpr (HAS_W) {
-                    const float gw = sgw[e];
-                    const float tpx = spx[e] + mx * ((r ? sgw[e + 1] : gw) - gw) * inv_ac;
-                    const float tpy = spy[e] + my * ((d ? sgw[e + EW] : gw) - gw) * inv_ac;
+                    const float gw = sgw[e], gwr = sgw[eR(k)], gwd = sgw[eD(k)];
+                    const float tpx = spx[e] + mx(k) * ((hr(k) ? gwr : gw) - gw) * inv_ac;
+                    const float tpy = spy[e] + my(k) * ((hd(k) ? gwd : gw) - gw) * inv_ac;
                     const float np2 = tpx * tpx + tpy * tpy;
                     const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
                     spx[e] = tpx * sp;
@@ -136,22 +170,19 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 }
             }
             __syncthreads();
-            // phase C: div y+, s+, multipliers (own pixels, registers)
+            // phase C: div y+, s+, multipliers (own slots, registers)
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
+                if (!live(k)) continue;
                 const int e = tid + k * NT;
-                if (e >= EN) continue;
-                const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-                const bool l = ej[k] > 0 && gj > 0, u = ei[k] > 0 && gi > 0;
-                const float mx = gj < W - 1 ? 1.f : 0.f, my = gi < H - 1 ? 1.f : 0.f;
-                const float dn1 = mx * sq1x[e] - (l ? sq1x[e - 1] : 0.f) + my * sq1y[e] - (u ? sq1y[e - EW] : 0.f);
-                const float dn2 = mx * sq2x[e] - (l ? sq2x[e - 1] : 0.f) + my * sq2y[e] - (u ? sq2y[e - EW] : 0.f);
-                const float hu = du[k] + crs * (dn1 - Ix[k] * ss[k]);
-                const float hv = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
-                float acc = It[k] + Ix[k] * hu + Iy[k] * hv;
+                const float dn1 = divk(sq1x, sq1y, k, e);
+                const float dn2 = divk(sq2x, sq2y, k, e);
+                const float hu_ = du[k] + crs * (dn1 - Ix[k] * ss[k]);
+                const float hv_ = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
+                float acc = It[k] + Ix[k] * hu_ + Iy[k] * hv_;
                 float dnp = 0.f;
                 if constexpr (HAS_W) {
-                    dnp = mx * spx[e] - (l ? spx[e - 1] : 0.f) + my * spy[e] - (u ? spy[e - EW] : 0.f);
+                    dnp = divk(spx, spy, k, e);
                     acc += beta * (ww[k] + crs * (dnp - beta * ss[k]));
                 }
                 float sn = ss[k] + acc * inv_atc;
@@ -170,7 +201,8 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         for (int k = 0; k < PPT; ++k) {
             const int e = tid + k * NT;
             if (e >= EN) continue;
-            const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+            const int ei = e / EW, ej = e - ei * EW;
+            const int gi = ey0 + ei, gj = ex0 + ej;
             if (gi < T.y0 || gi >= T.y0 + T.th || gj < T.x0 || gj >= T.x0 + T.tw) continue;
             const int64_t o = (int64_t)gi * ld + gj;
             L.out[1][o] = du[k];
@@ -258,7 +290,7 @@ void launch_reset_u32(unsigned* p, int n, hipStream_t s) {
 }
 
 int tb_capacity(bool has_w, int nt) {
-    if (nt == 1024) return 1024 * (has_w ? kTbPptW : kTbPpt);
+    if (nt == 1024) return 1024 * (has_w ? kTbPptLW : kTbPptL);
     if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
     return 256 * (has_w ? kTbPptW : kTbPpt);
 }
@@ -273,8 +305,8 @@ static void launch_one(const TbArgs& a, int grid, hipStream_t s) {
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s) {
     if (!a.queue) grid = (grid + 7) / 8 * 8;     // direct / table order: the XCD remap wants a multiple of 8
     if (nt == 1024) {
-        if (has_w) launch_one<true, 1024, kTbPptW>(a, grid, s);
-        else launch_one<false, 1024, kTbPpt>(a, grid, s);
+        if (has_w) launch_one<true, 1024, kTbPptLW>(a, grid, s);
+        else launch_one<false, 1024, kTbPptL>(a, grid, s);
     } else if (nt == 1025) {
         if (has_w) launch_one<true, 1024, kTbPptSmall>(a, grid, s);
         else launch_one<false, 1024, kTbPptSmall>(a, grid, s);

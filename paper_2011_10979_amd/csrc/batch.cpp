@@ -2,7 +2,7 @@
 // every pair, advanced together.  Stage s works on pyramid level l = Lmax-1-s of every pair that has
 // it, so all pairs reach level 0 in the last stage.  Every step of a stage is ONE launch over all
 // its pairs: the elementwise steps (import, downsample, derivatives, level start, linearisation,
-// commit, energy, export) through item tables in which a block-offset prefix maps each work-group
+// energy, export) through item tables in which a block-offset prefix maps each work-group
 // to its pair, and each block of K iterations through the K-iteration tile kernel over a table of
 // (pair-level, tile) entries, taken in XCD order or drained from per-XCD work queues.
 //
@@ -42,7 +42,7 @@ struct BStage {
     int tile_off = 0, ntiles = 0, grid = 0;
     int counter_off = 0;                // first counter of the stage's queue launches
     BLaunch init;
-    std::vector<BLaunch> lin, commit;   // per warp
+    std::vector<BLaunch> lin;           // per warp
 };
 
 // Working set and launch plan of one batch composition.
@@ -288,7 +288,7 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
             }
         P->deriv = T.launch(it, bl);
     }
-    // stages: level start, per-warp linearisation and commit; the state buffer after each warp
+    // stages: level start, per-warp linearisation (committing the previous warp); the state buffer after each warp
     // follows from the number of tile launches (every pair of a stage has the same schedule)
     std::vector<int> final_cur_of_stage(P->lmax, 0);
     for (BStage& S : P->stages) {
@@ -304,6 +304,8 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 const int cc = final_cur_of_stage[l + 1];
                 ia.uc = level_flow(C, p, 1, cc);
                 ia.vc = level_flow(C, p, 2, cc);
+                ia.ucd = level_inc(C, p, 1, cc);
+                ia.vcd = level_inc(C, p, 2, cc);
                 ia.wc = hw ? level_flow(C, p, 0, cc) : nullptr;
                 ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
             }
@@ -328,6 +330,10 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
                 la.u0 = L.U0[0];
                 la.v0 = L.U0[1];
+                if (w > 0) {             // commit the previous warp's increment on the way
+                    la.pend_u = L.st[cur][1];
+                    la.pend_v = L.st[cur][2];
+                }
                 la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
                 la.at = d_at + 2 * k + (w & 1);
                 la.at_clear = d_at + 2 * k + ((w + 1) & 1);
@@ -341,18 +347,12 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
             }
             S.lin.push_back(T.launch(lin, bl));
             cur ^= S.lpw & 1;
-            std::vector<CommitArgs> cm;
-            for (int k : S.pairs) {
-                const LevelPlanes& L = P->L[k][l];
-                cm.push_back(CommitArgs{L.U0[0], L.U0[1], L.st[cur][1], L.st[cur][2], L.H, L.W, L.ld});
-            }
-            S.commit.push_back(T.launch(cm, bl));
         }
         final_cur_of_stage[l] = cur;
     }
     P->final_cur = final_cur_of_stage[0];
     {
-        // energy of every pair at the end of level 0, before the last commit
+        // energy of every pair at the end of level 0 (flow = U0 + the last warp's increment)
         Scratch dummy;
         std::vector<EnergyArgs> it;
         std::vector<int> bl;
@@ -405,8 +405,9 @@ void fill_io(BatchState& B, int n, const flow_pair* pairs, const flow_params& p)
         const float off = p.storage == FLOW_STORE_F16 ? kFrameOffsetF16 : 0.f;
         ci[2 * k] = CopyArgs{q.I0, q.H, q.W, q.ld, L.I0, L.ld, off};
         ci[2 * k + 1] = CopyArgs{q.I1, q.H, q.W, q.ld, L.I1, L.ld, off};
-        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv, 0.f};
-        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv, 0.f};
+        // the flow is U0 plus the last warp's pending increment
+        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv, 0.f, L.st[P.final_cur][1]};
+        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv, 0.f, L.st[P.final_cur][2]};
     }
 }
 
@@ -441,7 +442,6 @@ void enqueue_batch(const BatchState& B, const flow_params& p, hipStream_t s, hip
             if (S.l == 0 && w == p.warps - 1)
                 launch_energy_batched((const EnergyArgs*)(tab + P.energy.items), (const int*)(tab + P.energy.off),
                                       P.energy.n, P.energy.total, s);
-            run_b(BatchOp::Commit, tab, S.commit[w], false, s);
         }
         if (ev) hipEventRecord(ev[2 * si + 1], s);
         ++si;

@@ -214,8 +214,8 @@ flow_status flow_ctx::solve(const float* I0, const float* I1, int H, int W, int6
     }
     if (stats_enabled) HIP_TRY(hipEventRecord(ev_total[1], s));
 
-    launch_copy2d(level_flow(Ls[0], p, 1, final_buf), H, W, Ls[0].ld, u, ld_uv, s);
-    launch_copy2d(level_flow(Ls[0], p, 2, final_buf), H, W, Ls[0].ld, v, ld_uv, s);
+    launch_copy2d(level_flow(Ls[0], p, 1, final_buf), H, W, Ls[0].ld, u, ld_uv, s, level_inc(Ls[0], p, 1, final_buf));
+    launch_copy2d(level_flow(Ls[0], p, 2, final_buf), H, W, Ls[0].ld, v, ld_uv, s, level_inc(Ls[0], p, 2, final_buf));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(host_out, scratch.e_out, sizeof(double) * kEnergyTerms, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -13,7 +13,9 @@ namespace flowmi {
 // Warp + linearise + a~ (max of M_s, one atomic max per work-group on the float bits).
 struct LinArgs {
     const void *I0, *I1, *Dx, *Dy;   // float or __half, pitch ld
-    const float *u0, *v0;            // pitch ld
+    float *u0, *v0;                  // pitch ld: the linearisation point (written when pend_u is set)
+    const float *pend_u, *pend_v;    // optional pending increment of the previous warp: the point is
+                                     // u0 + pend_u, committed into u0 here (in place, own pixel only)
     float *Ix, *Iy, *It;             // pitch ld
     float* at;                       // device scalar: max of M_s accumulated here (zero on entry)
     float* at_clear;                 // optional scalar cleared for the next warp (the other slot)
@@ -29,15 +31,17 @@ void launch_linearize(const LinArgs& a, bool f16, hipStream_t s);
 // Argument blocks of the elementwise pyramid / bookkeeping kernels (also the items of batched launches).
 struct DownArgs { const void* src; int H, W; int64_t ld; void* dst; int64_t ldd; };     // output ceil(H/2) x ceil(W/2)
 struct DerivArgs { const void* I; int H, W; int64_t ld; void* Dx; void* Dy; int64_t ldd; };
-// FP32 -> FP32 or FP16 plane copy, dst = src - offset.  Frames imported into FP16 pyramids are
+// FP32 -> FP32 or FP16 plane copy, dst = src (+ add) - offset.  Frames imported into FP16 pyramids are
 // stored centred (offset kFrameOffsetF16): every pyramid step is linear and I_t is a difference, so
 // the offset cancels, while FP16 spacing over [-1/2, 1/2] is half of that over [1/2, 1].
-struct CopyArgs { const float* src; int H, W; int64_t lds; void* dst; int64_t ldd; float offset; };
+struct CopyArgs {
+    const float* src; int H, W; int64_t lds; void* dst; int64_t ldd; float offset;
+    const float* add;                // optional plane (pitch lds) added to src: dst = src + add - offset
+};
 constexpr float kFrameOffsetF16 = 0.5f;
-struct CommitArgs { float* u0; float* v0; const float* du; const float* dv; int H, W; int64_t ld; };
 
 // Batched launches of one body over many items (one work-group grid per item, prefix offsets).
-enum class BatchOp { Downsample, Derivatives, Copy, Commit, Linearize, LevelInit };
+enum class BatchOp { Downsample, Derivatives, Copy, Linearize, LevelInit };
 int blocks_of(int H, int W);   // 64 x 4 blocks covering an H x W plane
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total_blocks, bool f16, hipStream_t s);
 
@@ -46,11 +50,13 @@ void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int
 void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void* Dy, int64_t ldd, bool f16,
                         hipStream_t s);
 void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64_t ldd, bool f16, hipStream_t s);
-void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s);
+void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s,
+                   const float* add = nullptr);
 
 // Level start: upsample (or zero) the flow and clear / set the scheme's auxiliary planes.
 struct LevelInitArgs {
     const float *uc, *vc, *wc;       // coarse flow (nullptr at the coarsest level -> zeros)
+    const float *ucd, *vcd;          // optional pending increment of the coarse flow (sampled as uc + ucd)
     int Hc, Wc;
     int64_t ldc;
     float* set_flow[3];              // w, u, v targets (w may be nullptr)
@@ -65,7 +71,6 @@ void launch_level_init(const LevelInitArgs& a, hipStream_t s);
 void launch_upsample(const float* coarse, int64_t ldc, float* fine, int Hf, int Wf, int64_t ldf, float scale,
                      hipStream_t s);
 // End of a warp in increment form: u0 += du, v0 += dv.
-void launch_commit(float* u0, float* v0, const float* du, const float* dv, int H, int W, int64_t ld, hipStream_t s);
 
 // pDR: three passes per symmetric sweep set (b + red, black, [red, black]*, final red + prox + dual).
 struct PdrArgs {

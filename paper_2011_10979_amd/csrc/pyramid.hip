@@ -3,9 +3,9 @@
 //   downsample   2x2 box mean with edge replication, ceil sizes (factor 1/2)
 //   derivatives  central differences with replicated neighbours
 //   linearize    bilinear warp of I1, D_x I1, D_y I1 at x + d0 and the linearisation
-//                rho(d) = I_x u + I_y v + I_t (Sec. 1), plus a~ = max M_s (Prop. 3.1)
+//                rho(d) = I_x u + I_y v + I_t (Sec. 1), plus a~ = max M_s (Prop. 3.1); it first
+//                commits the previous warp's flow increment (u0 += du) at its own pixel
 //   level_init   centre-aligned bilinear x2 upsampling of the flow, dual reset
-//   commit       end of a warp in increment form (u0 += du)
 //   copy         plane copies with format conversion (frame import, flow export)
 // All are elementwise or gather kernels: one thread per output pixel, 64-wide rows per wavefront
 // so that every plane access is a coalesced row segment.  Each body is written once and launched
@@ -62,16 +62,9 @@ __device__ __forceinline__ void copy_body(const CopyArgs& a, int bx, int by) {
     const int j = bx * 64 + (threadIdx.x & 63);
     const int i = by * 4 + (threadIdx.x >> 6);
     if (i >= a.H || j >= a.W) return;
-    stv((T*)a.dst, (int64_t)i * a.ldd + j, a.src[(int64_t)i * a.lds + j] - a.offset);
-}
-
-__device__ __forceinline__ void commit_body(const CommitArgs& a, int bx, int by) {
-    const int j = bx * 64 + (threadIdx.x & 63);
-    const int i = by * 4 + (threadIdx.x >> 6);
-    if (i >= a.H || j >= a.W) return;
-    const int64_t o = (int64_t)i * a.ld + j;
-    a.u0[o] += a.du[o];
-    a.v0[o] += a.dv[o];
+    const int64_t o = (int64_t)i * a.lds + j;
+    const float x = a.add ? a.src[o] + a.add[o] : a.src[o];
+    stv((T*)a.dst, (int64_t)i * a.ldd + j, x - a.offset);
 }
 
 // Integer / fraction split of the sample position p + d clamped into [0, n-1]; keeps the
@@ -108,7 +101,13 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
     float ms = 0.f;
     if (i < a.H && j < a.W) {
         const int64_t off = (int64_t)i * a.ld + j;
-        const float u0 = a.u0[off], v0 = a.v0[off];
+        float u0 = a.u0[off], v0 = a.v0[off];
+        if (a.pend_u) {                       // commit the previous warp's increment
+            u0 += a.pend_u[off];
+            v0 += a.pend_v[off];
+            a.u0[off] = u0;
+            a.v0[off] = v0;
+        }
         int iy, jx;
         float ty, tx;
         split_pos(i, v0, a.H, iy, ty);
@@ -138,8 +137,10 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
     }
 }
 
-// centre-aligned bilinear sample of a coarse plane at fine pixel (i, j): coarse coordinate i/2 - 1/4
-__device__ __forceinline__ float up_sample(const float* F, int Hc, int Wc, int64_t ldc, int i, int j) {
+// centre-aligned bilinear sample of a coarse plane (plus an optional increment plane D, added at
+// each tap) at fine pixel (i, j): coarse coordinate i/2 - 1/4
+__device__ __forceinline__ float up_sample(const float* F, int Hc, int Wc, int64_t ldc, int i, int j,
+                                           const float* D = nullptr) {
     float y = 0.5f * (float)i - 0.25f;
     float x = 0.5f * (float)j - 0.25f;
     y = fminf(fmaxf(y, 0.f), (float)(Hc - 1));
@@ -148,7 +149,14 @@ __device__ __forceinline__ float up_sample(const float* F, int Hc, int Wc, int64
     const int j0 = min((int)floorf(x), Wc - 2);
     const float ty = y - (float)i0, tx = x - (float)j0;
     const int64_t o = (int64_t)i0 * ldc + j0;
-    return (1.f - ty) * ((1.f - tx) * F[o] + tx * F[o + 1]) + ty * ((1.f - tx) * F[o + ldc] + tx * F[o + ldc + 1]);
+    float f00 = F[o], f01 = F[o + 1], f10 = F[o + ldc], f11 = F[o + ldc + 1];
+    if (D) {
+        f00 += D[o];
+        f01 += D[o + 1];
+        f10 += D[o + ldc];
+        f11 += D[o + ldc + 1];
+    }
+    return (1.f - ty) * ((1.f - tx) * f00 + tx * f01) + ty * ((1.f - tx) * f10 + tx * f11);
 }
 
 __device__ __forceinline__ void level_init_body(const LevelInitArgs& a, int bx, int by) {
@@ -158,11 +166,12 @@ __device__ __forceinline__ void level_init_body(const LevelInitArgs& a, int bx, 
     const int64_t off = (int64_t)i * a.ld + j;
     // target order (w, u, v): illumination keeps its scale, flow components double
     const float* src[3] = {a.wc, a.uc, a.vc};
+    const float* inc[3] = {nullptr, a.ucd, a.vcd};
     const float scale[3] = {1.f, 2.f, 2.f};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (!a.set_flow[k]) continue;
-        const float val = src[k] ? scale[k] * up_sample(src[k], a.Hc, a.Wc, a.ldc, i, j) : 0.f;
+        const float val = src[k] ? scale[k] * up_sample(src[k], a.Hc, a.Wc, a.ldc, i, j, inc[k]) : 0.f;
         a.set_flow[k][off] = val;
         if (a.copy_flow[k]) a.copy_flow[k][off] = val;
     }
@@ -184,7 +193,6 @@ template <typename T> __global__ __launch_bounds__(256) void derivatives_kernel(
 template <typename T> __global__ __launch_bounds__(256) void copy_kernel(CopyArgs a) {
     copy_body<T>(a, blockIdx.x, blockIdx.y);
 }
-__global__ __launch_bounds__(256) void commit_kernel(CommitArgs a) { commit_body(a, blockIdx.x, blockIdx.y); }
 template <typename T> __global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
     linearize_body<T>(a, blockIdx.x, blockIdx.y);
 }
@@ -254,14 +262,10 @@ void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64
     else hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }
 
-void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s) {
-    const CopyArgs a{src, H, W, lds, dst, ldd, 0.f};
+void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s,
+                   const float* add) {
+    const CopyArgs a{src, H, W, lds, dst, ldd, 0.f, add};
     hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
-}
-
-void launch_commit(float* u0, float* v0, const float* du, const float* dv, int H, int W, int64_t ld, hipStream_t s) {
-    const CommitArgs a{u0, v0, du, dv, H, W, ld};
-    hipLaunchKernelGGL(commit_kernel, grid2d(H, W), dim3(256), 0, s, a);
 }
 
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s) {
@@ -296,7 +300,6 @@ void launch_batched(BatchOp op, const void* items, const int* off, int n, int to
             if (f16) launch_b<CopyArgs, copy_body<__half>>(items, off, n, total, s);
             else launch_b<CopyArgs, copy_body<float>>(items, off, n, total, s);
             break;
-        case BatchOp::Commit: launch_b<CommitArgs, commit_body>(items, off, n, total, s); break;
         case BatchOp::Linearize:
             if (f16) launch_b<LinArgs, linearize_body<__half>>(items, off, n, total, s);
             else launch_b<LinArgs, linearize_body<float>>(items, off, n, total, s);

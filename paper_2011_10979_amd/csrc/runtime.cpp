@@ -236,11 +236,18 @@ void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s) {
 }
 
 // Flow component k (0 = w, 1 = u, 2 = v) of a level: pDR keeps X; the ADMM family keeps the
-// committed flow in U0 and w in its current state buffer `cur`.
+// flow in U0 (plus the pending increment, see level_inc) and w in its current state buffer `cur`.
 const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur) {
     if (p.scheme == FLOW_PDR) return L.X[k];
     if (k > 0) return L.U0[k - 1];
     return L.st[cur][0];
+}
+
+// Pending increment of flow component k (ADMM family, u and v: the last warp's du, dv in state
+// buffer `cur`, not yet added to U0); nullptr where the flow is stored whole.
+const float* level_inc(const LevelPlanes& L, const flow_params& p, int k, int cur) {
+    if (p.scheme == FLOW_PDR || k == 0) return nullptr;
+    return L.st[cur][k];
 }
 
 EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc) {
@@ -252,7 +259,7 @@ EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scra
         e.pdr_tau = (float)p.tau;
         e.lu0 = L.U0[0]; e.lv0 = L.U0[1];
     } else {
-        // before the warp's commit: flow = U0 + increment
+        // flow = U0 + the warp's increment (not yet committed)
         float* const* st = L.st[cur];
         e.w = st[0]; e.u = L.U0[0]; e.v = L.U0[1]; e.du = st[1]; e.dv = st[2];
         e.px = st[3]; e.py = st[4]; e.q1x = st[5]; e.q1y = st[6]; e.q2x = st[7]; e.q2y = st[8]; e.s = st[9];
@@ -362,6 +369,8 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             const LevelPlanes& C = Ls[l + 1];
             ia.uc = level_flow(C, p, 1, cur_coarse);
             ia.vc = level_flow(C, p, 2, cur_coarse);
+            ia.ucd = level_inc(C, p, 1, cur_coarse);
+            ia.vcd = level_inc(C, p, 2, cur_coarse);
             ia.wc = hw ? level_flow(C, p, 0, cur_coarse) : nullptr;
             ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
         }
@@ -395,8 +404,12 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             // increment (du, dv) restarts at zero, pDR keeps a copy of the linearisation point
             LinArgs la{};
             la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
-            la.u0 = level_flow(L, p, 1, cur);
-            la.v0 = level_flow(L, p, 2, cur);
+            la.u0 = const_cast<float*>(level_flow(L, p, 1, cur));
+            la.v0 = const_cast<float*>(level_flow(L, p, 2, cur));
+            if (wp > 0) {                // commit the previous warp's increment on the way
+                la.pend_u = level_inc(L, p, 1, cur);
+                la.pend_v = level_inc(L, p, 2, cur);
+            }
             la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
             la.at = sc.at + (wp & 1);
             la.at_clear = sc.at + ((wp + 1) & 1);
@@ -436,7 +449,8 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             if (timers) timers->end(l, s);
             const bool last = l == 0 && wp == p.warps - 1;
             if (last) launch_energy(energy_args(L, p, cur, sc), s);
-            if (!pdr) launch_commit(L.U0[0], L.U0[1], L.st[cur][1], L.st[cur][2], L.H, L.W, L.ld, s);
+            // the warp's increment stays pending in st[cur]: the next linearisation, the next level's
+            // upsampling or the export adds it (ADMM family)
         }
         cur_coarse = cur;
         if (l == 0) sc.final_buf = cur;
@@ -617,7 +631,7 @@ flow_status flow_op_linearize(const float* I0, const float* I1, const float* DxI
     EXTENT(at_out, 1, 1, 1, "at_out");
     HIP_TRY(hipMemsetAsync(at_out, 0, sizeof(float), (hipStream_t)stream));
     LinArgs a{};
-    a.I0 = I0; a.I1 = I1; a.Dx = DxI1; a.Dy = DyI1; a.u0 = u0; a.v0 = v0;
+    a.I0 = I0; a.I1 = I1; a.Dx = DxI1; a.Dy = DyI1; a.u0 = const_cast<float*>(u0); a.v0 = const_cast<float*>(v0);   // read only: no pending increment
     a.Ix = Ix; a.Iy = Iy; a.It = It; a.at = at_out;
     a.H = H; a.W = W; a.ld = ld; a.kappa = (float)kappa; a.beta = (float)beta;
     launch_linearize(a, false, (hipStream_t)stream);

@@ -34,7 +34,7 @@ struct LevelPlanes {
     void *I0 = nullptr, *I1 = nullptr, *Dx = nullptr, *Dy = nullptr;
     float *Ix = nullptr, *Iy = nullptr, *It = nullptr;
     float* st[2][10] = {};                // ADMM ping-pong: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
-    float* U0[2] = {};                    // linearisation point (u0, v0); ADMM: the committed flow
+    float* U0[2] = {};                    // linearisation point (u0, v0); ADMM: the flow without the pending increment
     float *X[3] = {}, *Xb[3] = {}, *b[3] = {}, *yb[6] = {}, *s_out = nullptr;   // pDR
 };
 
@@ -80,6 +80,7 @@ void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p);
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
                          WarpTimers* timers, StopTest* stop, const SolvePlan* plan);
 const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur);
+const float* level_inc(const LevelPlanes& L, const flow_params& p, int k, int cur);
 EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc);
 void fill_result(const double* h, flow_result* r);
 std::string graph_key(int H, int W, const flow_params& p, const void* arena, int tune_epoch);

@@ -3,8 +3,8 @@
 // Requests are queued on submit and admitted, in arrival order, when a slot (at most max_active
 // pairs in flight) and room in the engine's HBM arena (first-fit, the pair's whole working set)
 // are free.  Each call to flow_server_step runs one epoch: every admitted pair advances by one warp
-// of its coarse-to-fine solve (Sec. 4) -- level start where due, linearisation, the warp's
-// iterations, commit -- and all pairs share each launch: item tables map work-groups to pairs for
+// of its coarse-to-fine solve (Sec. 4) -- level start where due, linearisation (which commits the
+// previous warp's increment), the warp's iterations -- and all pairs share each launch: item tables map work-groups to pairs for
 // the elementwise steps, and one K-iteration tile launch covers the tiles of every pair's current
 // level.  Newly admitted pairs are imported and get their pyramids in the same epoch.  A pair that
 // finishes level 0 has its energy computed and its flow exported in that epoch; its memory and slot
@@ -310,7 +310,6 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
     std::vector<LevelInitArgs> init;
     std::vector<int> init_bl;
     std::vector<LinArgs> lin;
-    std::vector<CommitArgs> com;
     std::vector<int> bl;
     std::vector<TbLevel> descs(2 * active.size());
     std::vector<TbTile> tiles;
@@ -332,6 +331,8 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
                 const LevelPlanes& C = q.L[l + 1];
                 ia.uc = level_flow(C, p, 1, q.cur_coarse);
                 ia.vc = level_flow(C, p, 2, q.cur_coarse);
+                ia.ucd = level_inc(C, p, 1, q.cur_coarse);
+                ia.vcd = level_inc(C, p, 2, q.cur_coarse);
                 ia.wc = hw ? level_flow(C, p, 0, q.cur_coarse) : nullptr;
                 ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
             }
@@ -350,6 +351,10 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
         la.u0 = L.U0[0];
         la.v0 = L.U0[1];
+        if (q.w > 0) {                          // commit the previous warp's increment on the way
+            la.pend_u = L.st[q.cur][1];
+            la.pend_v = L.st[q.cur][2];
+        }
         la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
         la.at = at2 + (q.w & 1);
         la.at_clear = at2 + ((q.w + 1) & 1);
@@ -374,17 +379,15 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             e.out = d_eout + (size_t)q.slot * kEnergyTerms;
             en.push_back(e);
             en_bl.push_back(energy_blocks(L.H, L.W));
-            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv, 0.f});
-            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv, 0.f});
+            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv, 0.f, L.st[after][1]});
+            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv, 0.f, L.st[after][2]});
             exp_bl.push_back(blocks_of(L.H, L.W));
             exp_bl.push_back(blocks_of(L.H, L.W));
             finishing.push_back(active[i]);
         }
-        com.push_back(CommitArgs{L.U0[0], L.U0[1], L.st[after][1], L.st[after][2], L.H, L.W, L.ld});
     }
     const BLaunch l_init = T.launch(init, init_bl);
     const BLaunch l_lin = T.launch(lin, bl);
-    const BLaunch l_com = T.launch(com, bl);
     const BLaunch l_en = T.launch(en, en_bl);
     const BLaunch l_exp = T.launch(exp, exp_bl);
     const size_t descs_off = T.put(descs);
@@ -411,7 +414,6 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
                       ch, p, 0, 0, d_cnt, s);
     if (l_en.n > 0)
         launch_energy_batched((const EnergyArgs*)(tb + l_en.items), (const int*)(tb + l_en.off), l_en.n, l_en.total, s);
-    run_items(BatchOp::Commit, tb, l_com, false, s);
     run_items(BatchOp::Copy, tb, l_exp, false, s);
     if (!finishing.empty())
         HIP_TRY(hipMemcpyAsync(he[b].h, d_eout, sizeof(double) * kEnergyTerms * max_active, hipMemcpyDeviceToHost, s));

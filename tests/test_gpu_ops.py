@@ -227,7 +227,8 @@ def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme,
     """K iterations of the temporally blocked tile kernel (halo 2K / K, ragged tiles, resident
     levels) against K steps of the oracle on the same increment-form state."""
     print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
-    cap = 2048 if threads == 1025 else threads * (4 if beta > 0 else 6)
+    cap = 2048 if threads == 1025 else (1024 * (3 if beta > 0 else 4) if threads == 1024 else
+                                        256 * (4 if beta > 0 else 6))
     if min(shape[0], tile[0] + 3 * K) * min(shape[1], tile[1] + 3 * K) > cap:
         pytest.skip("tile plus halo exceeds the kernel capacity")
     rng = np.random.default_rng(zlib.crc32(repr(("tb", shape, tile, K, threads, scheme)).encode()))
