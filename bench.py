@@ -50,6 +50,17 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
 
 
+def pdr_bytes_per_px_iter(has_w, sweeps):
+    """FP32 planes one pDR iteration reads and writes per pixel over its 2n + 1 passes (n sweeps):
+    rhs + first red half sweep, n - 1 (black, red) pairs plus the last black half sweep, and the
+    final pass (last red half sweep, resolvent, dual update)."""
+    if has_w:
+        rhs, colour, final = 12 + 4.5, 6 + 1.5, 20 + 11.5
+    else:
+        rhs, colour, final = 8 + 3, 4 + 1, 15 + 8
+    return 4 * (rhs + (2 * sweeps - 1) * colour + final)
+
+
 def kernel_sha():
     h = hashlib.sha256()
     for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp"):
@@ -94,16 +105,16 @@ def cpu_baseline(pair, args):
                       f"warps x {iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
 
 
-def roofline(ms, launches, iters, px, has_w, kernel, traffic, reps):
+def roofline(ms, launches, iters, px, has_w, kernel, traffic, reps, per_px=None, unit="launch"):
     """HBM roofline of an iteration kernel from event-timed blocks of its launches: algorithmic
     bytes per launch (BYTES_PER_PX_LAUNCH x pixels) / average launch duration, against 8 TB/s."""
-    per_px = BYTES_PER_PX_LAUNCH[has_w]
+    per_px = per_px or BYTES_PER_PX_LAUNCH[has_w]
     launch_s = ms * 1e-3 / max(1, launches)
     bytes_launch = per_px * px
     achieved = bytes_launch / launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-            "per_unit": f"{per_px} B per pixel per launch", "bytes_per_launch": bytes_launch,
+            "per_unit": f"{per_px} B per pixel per {unit}", "bytes_per_launch": bytes_launch,
             "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step_level0": launches // reps,
             # the same pixel-iterations priced at one HBM pass per iteration
             "one_pass_equivalent_GBs": round(per_px * px * iters / (ms * 1e-3) / 1e9, 1)}
@@ -580,6 +591,12 @@ def main():
                         f"ADMM iteration kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice "
                         f"{(tuning or {}).get(f'{shapes[0][0]}x{shapes[0][1]}i{args.iters}')}",
                         measured_traffic(f"{args.W}x{args.H}"), reps)
+        roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
+    elif args.scheme == "pdr":
+        # pDR: the unit is one iteration (2n + 1 passes over the level), timed as a block
+        roof = roofline(lvl_ms[0], lvl_iters[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
+                        f"pDR iteration, level 0 ({shapes[0][1]}x{shapes[0][0]}): {2 * params.gs_sweeps + 1} passes",
+                        None, reps, per_px=pdr_bytes_per_px_iter(has_w, params.gs_sweeps), unit="iteration")
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
 
     cpu = None
