@@ -50,6 +50,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
 
 
+# pDR tile kernel, per launch: reads X, X bar, y bar, I_x, I_y, I_t, u0, v0; writes X, X bar, y bar, Theta
+PDR_TB_BYTES_PER_PX_LAUNCH = {False: 4 * ((2 + 2 + 4 + 5) + (2 + 2 + 4 + 1)), True: 4 * ((3 + 3 + 6 + 5) + (3 + 3 + 6 + 1))}
+
+
 def pdr_bytes_per_px_iter(has_w, sweeps):
     """FP32 planes one pDR iteration reads and writes per pixel over its 2n + 1 passes (n sweeps):
     rhs + first red half sweep, n - 1 (black, red) pairs plus the last black half sweep, and the
@@ -593,10 +597,21 @@ def main():
                         measured_traffic(f"{args.W}x{args.H}"), reps)
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
     elif args.scheme == "pdr":
-        # pDR: the unit is one iteration (2n + 1 passes over the level), timed as a block
-        roof = roofline(lvl_ms[0], lvl_iters[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
-                        f"pDR iteration, level 0 ({shapes[0][1]}x{shapes[0][0]}): {2 * params.gs_sweeps + 1} passes",
-                        None, reps, per_px=pdr_bytes_per_px_iter(has_w, params.gs_sweeps), unit="iteration")
+        key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}p{params.gs_sweeps}"
+        ch0 = (tuning or {}).get(key0, {"mode": 5})
+        if ch0["mode"] == 5:
+            # K-iteration pDR tiles: per launch the kernel reads X, X bar, y bar and the
+            # linearisation once and writes X, X bar, y bar and Theta once
+            roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
+                            f"pDR tile kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
+                            None, reps, per_px=PDR_TB_BYTES_PER_PX_LAUNCH[has_w])
+            roof["one_pass_equivalent_GBs"] = round(pdr_bytes_per_px_iter(has_w, params.gs_sweeps) * shapes[0][0]
+                                                    * shapes[0][1] * lvl_iters[0] / (lvl_ms[0] * 1e-3) / 1e9, 1)
+        else:
+            # three-pass pDR: the unit is one iteration (2n + 1 passes over the level)
+            roof = roofline(lvl_ms[0], lvl_iters[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
+                            f"pDR iteration, level 0 ({shapes[0][1]}x{shapes[0][0]}): {2 * params.gs_sweeps + 1} passes",
+                            None, reps, per_px=pdr_bytes_per_px_iter(has_w, params.gs_sweeps), unit="iteration")
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
 
     cpu = None

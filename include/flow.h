@@ -227,11 +227,12 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
                                   void* stream);
 
 /* Autotuner: for every pyramid level of an H x W pair under params p, time each iteration-kernel
- * choice (one-pass kernel with 2 / 4 / 8-row strips; K-iteration tiles of 256, 1024 and small
- * 1024-thread work-groups for K = 2, 4, 8, 16; a resident tile where the level fits) over one
- * warp's iterations with HIP events on `stream`, and keep the fastest per level shape for this
- * context's later solves.  Every choice computes the same iteration (results agree to rounding).
- * Blocking; uses the context's arena (contents are overwritten).  No effect for pDR. */
+ * choice over one warp's iterations with HIP events on `stream`, and keep the fastest per level
+ * shape for this context's later solves.  ADMM family: one-pass kernel with 2 / 4 / 8-row strips;
+ * K-iteration tiles of 256, 1024 and small 1024-thread work-groups for K = 2, 4, 8, 16; a resident
+ * tile where the level fits.  pDR: the three-pass iteration, K-iteration tiles for K = 1, 2, 3, a
+ * resident tile.  Every choice computes the same iteration (results agree to rounding).  Blocking;
+ * uses the context's arena (contents are overwritten). */
 flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
 
 /* JSON report of the last flow_autotune (choice and all measured candidates per level shape) into
@@ -239,12 +240,14 @@ flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params
 flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
 
 /* Set the iteration-kernel choice of one level shape (H x W, with or without the w / p block, iters
- * per warp) by hand, as flow_autotune would: mode 1 = one-pass kernel with `rows` rows per strip
- * (0 = built-in), 2 / 3 / 4 = K-iteration tiles of 256 / 1024 / small 1024-thread work-groups with K
- * iterations per launch (K = 0: resident if the level fits one tile, else the built-in K).  Lets a
- * caller reuse a tuning measured in another process.  Drops the context's captured graphs. */
-flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t mode,
-                             int32_t K, int32_t rows);
+ * per warp) by hand, as flow_autotune would.  pdr_sweeps = 0: the ADMM family, mode 1 = one-pass
+ * kernel with `rows` rows per strip (0 = built-in), 2 / 3 / 4 = K-iteration tiles of 256 / 1024 /
+ * small 1024-thread work-groups with K iterations per launch (K = 0: resident if the level fits one
+ * tile, else the built-in K).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
+ * iteration, 5 = K-iteration tiles (K = 0: resident).  Lets a caller reuse a tuning measured in
+ * another process.  Drops the context's captured graphs. */
+flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t pdr_sweeps,
+                             int32_t mode, int32_t K, int32_t rows);
 
 /* Enable (1) or disable (0) per-solve event timing; flow_get_stats returns the last solve's. */
 flow_status flow_set_stats(flow_ctx* ctx, int32_t enable);
@@ -260,6 +263,9 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 kernel only, 2 K-iteration tiles of 256 threads, 3 of 1024 threads, 4 small tiles
  *                 of 1024 threads.
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
+ *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
+ *                 warp resident), 1 three-pass iteration, 5 tiles.
+ *   "pdr_k"       iterations per pDR tile launch (0 = built-in 2).
  *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
  *                 work queues.
  *   "batch_k"     iterations per batched tile launch (0 = tuned / built-in; lowered where a level's
@@ -342,6 +348,17 @@ typedef struct flow_pdr_state {
 flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work1, float* work2,
                              float* s_out, const float* Ix, const float* Iy, const float* It, int32_t H,
                              int32_t W, int64_t ld, const flow_params* p, void* stream);
+
+/* `iters` pDR iterations in ONE launch of the temporally blocked pDR tile kernel (the solver's path
+ * for pDR levels), from `in` to `out` (distinct planes; in is not modified), with I_t relative to
+ * the linearisation point (u0, v0) as in the solver: rho = I_t + beta w + I_x (u - u0) + I_y (v - v0).
+ * tile_h x tile_w: output tile; each tile's extended region
+ * min(H, tile_h + (4 gs_sweeps + 3) iters) x min(W, tile_w + (4 gs_sweeps + 3) iters) must hold at
+ * most 2048 pixels, else FLOW_E_INVAL.  s_out receives Theta of the last iteration.  Blocking. */
+flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                           const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                           int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                           void* stream);
 
 /* FP64 energy / dual / gap / residual of an ADMM-family state (see flow_result), blocking:
  * res is host memory and the stream is synchronised. */

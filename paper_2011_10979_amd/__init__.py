@@ -78,7 +78,7 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
            "flow_tune_choice", "flow_autotune_batched", "flow_server_create", "flow_server_destroy",
            "flow_server_submit", "flow_server_step", "flow_server_poll", "flow_server_drain",
-           "flow_server_get_stats", "flow_working_set_bytes"]
+           "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb"]
 
 
 def lib():
@@ -107,7 +107,7 @@ def lib():
             "flow_set_stats": [vp, i32],
             "flow_autotune": [vp, i32, i32, ctypes.POINTER(_Params), vp],
             "flow_get_tuning": [vp, ctypes.c_char_p, ctypes.c_size_t],
-            "flow_tune_choice": [vp, i32, i32, i32, i32, i32, i32, i32],
+            "flow_tune_choice": [vp, i32, i32, i32, i32, i32, i32, i32, i32],
             "flow_get_stats": [vp, ctypes.POINTER(_Stats)],
             "flow_memory_in_use": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "flow_op_downsample": [vp, i32, i32, i64, vp, i64, vp],
@@ -120,6 +120,8 @@ def lib():
                                 ctypes.POINTER(_Params), i32, i32, i32, i32, i32, vp],
             "flow_op_pdr_iter": [ctypes.POINTER(_PdrState), vp, vp, vp, vp, vp, vp, vp, i32, i32, i64,
                                  ctypes.POINTER(_Params), vp],
+            "flow_op_pdr_tb": [ctypes.POINTER(_PdrState), ctypes.POINTER(_PdrState), vp, vp, vp, vp, vp, vp, i32, i32,
+                               i64, ctypes.POINTER(_Params), i32, i32, i32, vp],
             "flow_op_energy": [ctypes.POINTER(_AdmmState), vp, vp, vp, i32, i32, i64, dbl, dbl, ctypes.POINTER(_Result),
                                vp],
         }
@@ -256,13 +258,14 @@ class Context:
         return json.loads(buf.value.decode() or "{}")
 
     def set_choice(self, key: str, mode: int, K: int = 0, rows: int = 0):
-        """Apply one level-shape choice of an autotune report (key "<H>x<W>[w]i<iters>") by hand."""
+        """Apply one level-shape choice of an autotune report (key "<H>x<W>[w]i<iters>[p<sweeps>]") by hand."""
         import re
-        m = re.fullmatch(r"(\d+)x(\d+)(w?)i(\d+)", key)
+        m = re.fullmatch(r"(\d+)x(\d+)(w?)i(\d+)(?:p(\d+))?", key)
         if not m:
             raise ValueError(f"bad tuning key {key!r}")
         H, W, hw, it = int(m.group(1)), int(m.group(2)), m.group(3) == "w", int(m.group(4))
-        _check(lib().flow_tune_choice(self._h, H, W, int(hw), it, int(mode), int(K), int(rows)))
+        sweeps = int(m.group(5)) if m.group(5) else 0
+        _check(lib().flow_tune_choice(self._h, H, W, int(hw), it, sweeps, int(mode), int(K), int(rows)))
 
     def memory_in_use(self):
         b = ctypes.c_size_t()
@@ -489,6 +492,24 @@ def pdr_iter(state, Ix, Iy, It, params: Params, s_out=None):
                                   _ptr(Ix), _ptr(Iy), _ptr(It), H, W, state["u"].stride(0),
                                   ctypes.byref(params.c_struct()), _stream()))
     return state
+
+
+def pdr_tb(state, Ix, Iy, It, u0, v0, params: Params, iters, tile_h=16, tile_w=32):
+    """`iters` pDR iterations in one launch of the tile kernel; returns (new state dict, s_out).
+    I_t is relative to (u0, v0)."""
+    ref = _plane(state["u"], "u")
+    H, W = ref.shape
+    out = {k: (_like(ref) if state.get(k) is not None else None) for k in PDR_KEYS}
+    s_out = _like(ref)
+    _same_layout(ref, [(k, v) for k, v in state.items() if v is not None] +
+                 [(k, v) for k, v in out.items() if v is not None] +
+                 [("Ix", Ix), ("Iy", Iy), ("It", It), ("u0", u0), ("v0", v0), ("s_out", s_out)], "pdr_tb")
+    st_in = _PdrState(*[state[k].data_ptr() if state.get(k) is not None else None for k in PDR_KEYS])
+    st_out = _PdrState(*[out[k].data_ptr() if out.get(k) is not None else None for k in PDR_KEYS])
+    _check(lib().flow_op_pdr_tb(ctypes.byref(st_in), ctypes.byref(st_out), _ptr(s_out), _ptr(Ix), _ptr(Iy), _ptr(It),
+                                _ptr(u0), _ptr(v0), H, W, ref.stride(0), ctypes.byref(params.c_struct()), int(iters),
+                                int(tile_h), int(tile_w), _stream()))
+    return out, s_out
 
 
 def energy(state, Ix, Iy, It, lam=0.05, beta=0.0):

@@ -22,9 +22,19 @@ namespace flowmi {
 
 static flow_status clear_level(const LevelPlanes& L, hipStream_t s) {
     const size_t plane = (size_t)L.H * L.ld * sizeof(float);
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
         for (int k = 0; k < 10; ++k)
             if (L.st[b][k]) HIP_TRY(hipMemsetAsync(L.st[b][k], 0, plane, s));
+        for (int k = 0; k < 3; ++k) {
+            if (L.Xs[b][k]) HIP_TRY(hipMemsetAsync(L.Xs[b][k], 0, plane, s));
+            if (L.Xbs[b][k]) HIP_TRY(hipMemsetAsync(L.Xbs[b][k], 0, plane, s));
+        }
+        for (int k = 0; k < 6; ++k)
+            if (L.ybs[b][k]) HIP_TRY(hipMemsetAsync(L.ybs[b][k], 0, plane, s));
+    }
+    if (L.s_out) HIP_TRY(hipMemsetAsync(L.s_out, 0, plane, s));
+    for (float* q : L.b)
+        if (q) HIP_TRY(hipMemsetAsync(q, 0, plane, s));
     for (float* q : {L.Ix, L.Iy, L.It, L.U0[0], L.U0[1]}) HIP_TRY(hipMemsetAsync(q, 0, plane, s));
     return FLOW_OK;
 }
@@ -39,7 +49,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
     if (st != FLOW_OK) return st;
     st = validate_shape(H, W, W, p->levels);
     if (st != FLOW_OK) return st;
-    if (p->scheme == FLOW_PDR || p->iters < 1) return FLOW_OK;     // nothing to choose
+    if (p->iters < 1) return FLOW_OK;     // nothing to choose
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     st = ctx->ensure_arena(layout_bytes(H, W, *p));
@@ -59,6 +69,62 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
     for (const LevelPlanes& L : Ls) {
         st = clear_level(L, s);
         if (st != FLOW_OK) break;
+        if (p->scheme == FLOW_PDR) {
+            // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, or a resident level
+            struct PCand { TunedChoice c; PdrTbPlan T; };
+            std::vector<PCand> cands;
+            PCand three{};
+            three.c.mode = 1;
+            cands.push_back(three);
+            bool resident_done = false;
+            for (int K : {1, 2, 3}) {
+                PdrTbPlan T = plan_pdr_tiles(L.H, L.W, hw, p->gs_sweeps, K, 0);
+                if (!T.tb) continue;
+                if (T.resident) {
+                    if (resident_done) continue;
+                    resident_done = true;
+                    T.K = p->iters;
+                }
+                PCand c{};
+                c.c.mode = 5;
+                c.c.K = T.resident ? 0 : K;
+                c.T = T;
+                cands.push_back(c);
+            }
+            double best = 1e30;
+            TunedChoice bestc;
+            std::ostringstream lv;
+            for (PCand& c : cands) {
+                float ms_best = 1e30f;
+                for (int rep_i = 0; rep_i < 4; ++rep_i) {      // the first run is a warm-up
+                    HIP_TRY(hipEventRecord(e0, s));
+                    if (c.c.mode == 1) {
+                        for (int t = 0; t < p->iters; ++t) enqueue_pdr_iter(pdr_args(L, *p, 0), p->gs_sweeps, hw, s);
+                    } else {
+                        enqueue_pdr_tiles(L, *p, c.T, 0, p->iters, s, nullptr);
+                    }
+                    HIP_TRY(hipEventRecord(e1, s));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep_i > 0) ms_best = std::min(ms_best, ms);
+                }
+                HIP_TRY(hipGetLastError());
+                c.c.us_per_iter = 1e3 * ms_best / p->iters;
+                lv << (lv.tellp() > 0 ? ", " : "") << "\"m" << c.c.mode << "k" << c.c.K << "\": " << c.c.us_per_iter;
+                if (c.c.us_per_iter < best) {
+                    best = c.c.us_per_iter;
+                    bestc = c.c;
+                }
+            }
+            const std::string key = tune_key(L.H, L.W, hw, p->iters) + "p" + std::to_string(p->gs_sweeps);
+            ctx->tuned[key] = bestc;
+            rep << (first_level ? "" : ", ") << "\"" << key << "\": {\"choice\": {\"mode\": " << bestc.mode
+                << ", \"K\": " << bestc.K << ", \"rows\": 0, \"us_per_iter\": " << bestc.us_per_iter
+                << "}, \"candidates\": {" << lv.str() << "}}";
+            first_level = false;
+            continue;
+        }
         struct Cand { TunedChoice c; LevelTbPlan P; bool tb; };
         std::vector<Cand> cands;
         for (int rows : {0, 2, 4, 8}) {
@@ -134,17 +200,22 @@ extern "C" flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t ca
 }
 
 extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters,
-                                        int32_t mode, int32_t K, int32_t rows) {
+                                        int32_t pdr_sweeps, int32_t mode, int32_t K, int32_t rows) {
     if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
-    if (mode < 1 || mode > 4) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass) or 2..4 (tiles)");
+    if (mode < 1 || mode > 5) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4 (tiles) or 5 (pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
+    if (pdr_sweeps < 0) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= 0");
+    if (pdr_sweeps > 0 && mode != 1 && mode != 5) return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass) or 5 (tiles)");
+    if (pdr_sweeps == 0 && mode == 5) return fail(FLOW_E_INVAL, "mode 5 is a pDR mode");
     TunedChoice c;
     c.mode = mode;
     c.K = K;
     c.rows = rows;
-    ctx->tuned[tune_key(H, W, has_w != 0, iters)] = c;
+    std::string key = tune_key(H, W, has_w != 0, iters);
+    if (pdr_sweeps > 0) key += "p" + std::to_string(pdr_sweeps);
+    ctx->tuned[key] = c;
     ctx->tune_epoch++;
     ctx->drop_graphs();
     return FLOW_OK;

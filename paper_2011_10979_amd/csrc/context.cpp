@@ -96,7 +96,7 @@ std::string graph_key(int H, int W, const flow_params& p, const void* arena, int
     o << H << ',' << W << ',' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
       << p.sigma << ',' << p.tau << ',' << p.gs_sweeps << ',' << p.intensity_scale << ',' << p.levels << ','
       << p.warps << ',' << p.iters << ',' << p.storage << ',' << arena << ",tb" << g_tb_mode << ',' << g_tb_k
-      << ",rows" << g_admm_rows_override << ",te" << tune_epoch;
+      << ",rows" << g_admm_rows_override << ",pdr" << g_pdr_mode << ',' << g_pdr_k << ",te" << tune_epoch;
     return o.str();
 }
 

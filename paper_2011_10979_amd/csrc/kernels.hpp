@@ -86,6 +86,27 @@ struct PdrArgs {
     float sigma, tau, stt, lam, beta;
     int colour;                      // for the plain colour sweep: 0 red, 1 black
 };
+// Temporally blocked pDR: K iterations of one tile per work-group launch (direct tiling of one
+// level).  Component order: x / x bar (u, v, w), y (q1x, q1y, q2x, q2y, p_x, p_y).
+constexpr int kPdrPpt = 2;           // pixels per thread (1024 threads)
+constexpr int kPdrPptW = 2;
+struct PdrTbLevel {
+    const float* x_in[3]; const float* xb_in[3]; const float* y_in[6];
+    float* x_out[3]; float* xb_out[3]; float* y_out[6];
+    const float *Ix, *Iy, *It, *u0, *v0;
+    float* s_out;
+    int H, W;
+    int64_t ld;
+};
+struct PdrTbArgs {
+    PdrTbLevel lvl;
+    int K, sweeps;                   // iterations of this launch; symmetric sweeps per iteration
+    int th, tw, ntx, ntiles;         // output tiling
+    float sigma, tau, stt, lam, beta;
+};
+int pdr_tb_capacity(bool has_w);
+void launch_pdr_tb(const PdrTbArgs& a, bool has_w, hipStream_t s);
+
 void launch_pdr_rhs_red(const PdrArgs& a, bool has_w, hipStream_t s);
 void launch_pdr_colour(const PdrArgs& a, bool has_w, hipStream_t s);
 void launch_pdr_final(const PdrArgs& a, bool has_w, hipStream_t s);

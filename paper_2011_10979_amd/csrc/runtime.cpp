@@ -107,7 +107,7 @@ size_t layout_bytes(int H, int W, const flow_params& p) {
         const size_t plane = (size_t)h * pitch_of(w) * 4;
         const size_t pyr = (size_t)h * pitch_of(w) * (f16 ? 2 : 4);
         total += 4 * pyr + 5 * plane;   // pyramid, linearisation, linearisation point
-        if (pdr) total += (size_t)(hw ? 3 + 3 + 6 + 3 + 1 : 2 + 2 + 4 + 2 + 1) * plane;
+        if (pdr) total += (size_t)(hw ? 2 * (3 + 3 + 6) + 3 + 1 : 2 * (2 + 2 + 4) + 2 + 1) * plane;
         else total += (size_t)2 * (hw ? 10 : 7) * plane;
         total += 48 * 256;  // alignment slack: every plane starts on a 256-byte boundary
     }
@@ -156,11 +156,14 @@ flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, st
         } else {
             for (int k = 0; k < 3; ++k) {
                 const bool need = k > 0 || hw;
-                L.X[k] = need ? (float*)take(plane) : nullptr;
-                L.Xb[k] = need ? (float*)take(plane) : nullptr;
+                for (int c = 0; c < 2; ++c) {
+                    L.Xs[c][k] = need ? (float*)take(plane) : nullptr;
+                    L.Xbs[c][k] = need ? (float*)take(plane) : nullptr;
+                }
                 L.b[k] = need ? (float*)take(plane) : nullptr;
             }
-            for (int k = 0; k < 6; ++k) L.yb[k] = (k >= 2 || hw) ? (float*)take(plane) : nullptr;
+            for (int c = 0; c < 2; ++c)
+                for (int k = 0; k < 6; ++k) L.ybs[c][k] = (k >= 2 || hw) ? (float*)take(plane) : nullptr;
             L.s_out = (float*)take(plane);
         }
         if (short_of_space) return fail(FLOW_E_NOMEM, "arena too small for layout");
@@ -206,11 +209,14 @@ void fill_admm_coeffs(AdmmIterArgs& a, const flow_params& p) {
     }
 }
 
-PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p) {
+PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p, int cur) {
     PdrArgs a{};
-    a.w = L.X[0]; a.u = L.X[1]; a.v = L.X[2];
-    a.wb = L.Xb[0]; a.ub = L.Xb[1]; a.vb = L.Xb[2];
-    a.pbx = L.yb[0]; a.pby = L.yb[1]; a.qb1x = L.yb[2]; a.qb1y = L.yb[3]; a.qb2x = L.yb[4]; a.qb2y = L.yb[5];
+    float* const* X = L.Xs[cur];
+    float* const* Xb = L.Xbs[cur];
+    float* const* yb = L.ybs[cur];
+    a.w = X[0]; a.u = X[1]; a.v = X[2];
+    a.wb = Xb[0]; a.ub = Xb[1]; a.vb = Xb[2];
+    a.pbx = yb[0]; a.pby = yb[1]; a.qb1x = yb[2]; a.qb1y = yb[3]; a.qb2x = yb[4]; a.qb2y = yb[5];
     a.bw = L.b[0]; a.bu = L.b[1]; a.bv = L.b[2];
     a.s_out = L.s_out;
     a.Ix = L.Ix; a.Iy = L.Iy; a.It = L.It;
@@ -238,7 +244,7 @@ void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s) {
 // Flow component k (0 = w, 1 = u, 2 = v) of a level: pDR keeps X; the ADMM family keeps the
 // flow in U0 (plus the pending increment, see level_inc) and w in its current state buffer `cur`.
 const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur) {
-    if (p.scheme == FLOW_PDR) return L.X[k];
+    if (p.scheme == FLOW_PDR) return L.Xs[cur][k];
     if (k > 0) return L.U0[k - 1];
     return L.st[cur][0];
 }
@@ -253,8 +259,10 @@ const float* level_inc(const LevelPlanes& L, const flow_params& p, int k, int cu
 EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc) {
     EnergyArgs e{};
     if (p.scheme == FLOW_PDR) {
-        e.w = L.X[0]; e.u = L.X[1]; e.v = L.X[2];
-        e.px = L.yb[0]; e.py = L.yb[1]; e.q1x = L.yb[2]; e.q1y = L.yb[3]; e.q2x = L.yb[4]; e.q2y = L.yb[5];
+        float* const* X = L.Xs[cur];
+        float* const* yb = L.ybs[cur];
+        e.w = X[0]; e.u = X[1]; e.v = X[2];
+        e.px = yb[0]; e.py = yb[1]; e.q1x = yb[2]; e.q1y = yb[3]; e.q2x = yb[4]; e.q2y = yb[5];
         e.s = L.s_out;
         e.pdr_tau = (float)p.tau;
         e.lu0 = L.U0[0]; e.lv0 = L.U0[1];
@@ -276,7 +284,11 @@ EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scra
 flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
                       const std::map<std::string, TunedChoice>* tuned) {
     out.levels.clear();
-    if (p.scheme == FLOW_PDR) return FLOW_OK;
+    out.pdr.clear();
+    if (p.scheme == FLOW_PDR) {
+        for (const LevelPlanes& L : Ls) out.pdr.push_back(plan_pdr_level(L.H, L.W, p, tuned));
+        return FLOW_OK;
+    }
     const bool hw = p.beta > 0;
     std::vector<TbTile> tiles;
     std::vector<TbLevel> descs(2 * Ls.size());
@@ -339,6 +351,72 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
     return cur;
 }
 
+int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles
+int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
+constexpr int kPdrDefaultK = 2;
+
+PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std::string, TunedChoice>* tuned) {
+    const bool hw = p.beta > 0;
+    int mode = g_pdr_mode, K = g_pdr_k;
+    if (mode == 0 && tuned) {
+        auto it = tuned->find(tune_key(H, W, hw, p.iters) + "p" + std::to_string(p.gs_sweeps));
+        if (it != tuned->end()) {
+            mode = it->second.mode;
+            K = it->second.K;
+        }
+    }
+    if (mode == 1 || p.iters < 1) return PdrTbPlan();
+    PdrTbPlan T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, K > 0 ? K : kPdrDefaultK, 0);
+    if (T.resident && K == 0) T.K = p.iters;        // the whole warp in one launch
+    if (!T.tb) {                                     // the halo does not fit: fewer iterations per launch
+        for (int k = (K > 0 ? K : kPdrDefaultK) - 1; k >= 1 && !T.tb; --k) T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, k, 0);
+    }
+    return T;
+}
+
+PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int K) {
+    PdrTbArgs a{};
+    const int xs[3] = {1, 2, 0};                    // kernel order u, v, w <- layout order w, u, v
+    const int ys[6] = {2, 3, 4, 5, 0, 1};           // q1x q1y q2x q2y p_x p_y <- p_x p_y q1x q1y q2x q2y
+    for (int c = 0; c < 3; ++c) {
+        a.lvl.x_in[c] = L.Xs[cur][xs[c]];
+        a.lvl.xb_in[c] = L.Xbs[cur][xs[c]];
+        a.lvl.x_out[c] = L.Xs[cur ^ 1][xs[c]];
+        a.lvl.xb_out[c] = L.Xbs[cur ^ 1][xs[c]];
+    }
+    for (int c = 0; c < 6; ++c) {
+        a.lvl.y_in[c] = L.ybs[cur][ys[c]];
+        a.lvl.y_out[c] = L.ybs[cur ^ 1][ys[c]];
+    }
+    a.lvl.Ix = L.Ix; a.lvl.Iy = L.Iy; a.lvl.It = L.It;
+    a.lvl.u0 = L.U0[0]; a.lvl.v0 = L.U0[1];
+    a.lvl.s_out = L.s_out;
+    a.lvl.H = L.H; a.lvl.W = L.W; a.lvl.ld = L.ld;
+    a.K = K;
+    a.sweeps = p.gs_sweeps;
+    a.th = T.th; a.tw = T.tw;
+    a.ntx = (L.W + T.tw - 1) / T.tw;
+    a.ntiles = a.ntx * ((L.H + T.th - 1) / T.th);
+    a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    a.lam = (float)p.lambda; a.beta = (float)p.beta;
+    return a;
+}
+
+// `n` pDR iterations of level L on K-iteration tiles starting from state set `cur`; returns the
+// set holding the result.
+int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int64_t n,
+                      hipStream_t s, int64_t* launches) {
+    int64_t t = 0;
+    while (t < n) {
+        const int kk = (int)std::min<int64_t>(T.resident ? n - t : T.K, n - t);
+        launch_pdr_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, s);
+        if (launches) ++*launches;
+        cur ^= 1;
+        t += kk;
+    }
+    return cur;
+}
+
 // Everything after the level-0 frames are in the pyramid: pyramid, levels, warps, iterations,
 // final energy.  `timers` (may be null) receives events around each warp's iteration block.
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
@@ -383,15 +461,15 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
                 if (L.st[0][k]) ia.zero[nz++] = L.st[0][k];
             ia.nzero = nz;
         } else {
-            ia.set_flow[0] = hw ? L.X[0] : nullptr;
-            ia.set_flow[1] = L.X[1];
-            ia.set_flow[2] = L.X[2];
-            ia.copy_flow[0] = hw ? L.Xb[0] : nullptr;
-            ia.copy_flow[1] = L.Xb[1];
-            ia.copy_flow[2] = L.Xb[2];
+            ia.set_flow[0] = hw ? L.Xs[0][0] : nullptr;
+            ia.set_flow[1] = L.Xs[0][1];
+            ia.set_flow[2] = L.Xs[0][2];
+            ia.copy_flow[0] = hw ? L.Xbs[0][0] : nullptr;
+            ia.copy_flow[1] = L.Xbs[0][1];
+            ia.copy_flow[2] = L.Xbs[0][2];
             int nz = 0;
             for (int k = 0; k < 6; ++k)
-                if (L.yb[k]) ia.zero[nz++] = L.yb[k];
+                if (L.ybs[0][k]) ia.zero[nz++] = L.ybs[0][k];
             ia.zero[nz++] = L.s_out;
             ia.nzero = nz;
         }
@@ -431,8 +509,14 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
                 if (stop && p.tol > 0) chunk = std::min<int64_t>(chunk, p.check_every);
                 int64_t nk = 0;
                 if (pdr) {
-                    for (int64_t t = 0; t < chunk; ++t) enqueue_pdr_iter(pdr_args(L, p), p.gs_sweeps, hw, s);
-                    nk = chunk * (2 * p.gs_sweeps + 1);
+                    const PdrTbPlan* T = (plan && l < (int)plan->pdr.size() && plan->pdr[l].tb) ? &plan->pdr[l]
+                                                                                                  : nullptr;
+                    if (T) {
+                        cur = enqueue_pdr_tiles(L, p, *T, cur, chunk, s, &nk);
+                    } else {
+                        for (int64_t t = 0; t < chunk; ++t) enqueue_pdr_iter(pdr_args(L, p, cur), p.gs_sweeps, hw, s);
+                        nk = chunk * (2 * p.gs_sweeps + 1);
+                    }
                 } else {
                     cur = enqueue_admm_iters(L, p, P, rows_hint, cur, chunk, wp & 1, sc.at, s, &nk);
                 }
@@ -510,6 +594,16 @@ flow_status flow_tune_set(const char* key, int64_t value) {
     if (std::strcmp(key, "tb_k") == 0) {
         if (value < 0 || value > 64) return fail(FLOW_E_INVAL, "tb_k: 0 (default) .. 64");
         g_tb_k = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "pdr_mode") == 0) {
+        if (value != 0 && value != 1 && value != 5) return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles");
+        g_pdr_mode = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "pdr_k") == 0) {
+        if (value < 0 || value > 64) return fail(FLOW_E_INVAL, "pdr_k: 0 (built-in) .. 64");
+        g_pdr_k = (int)value;
         return FLOW_OK;
     }
     if (std::strcmp(key, "batch_order") == 0) {
@@ -800,6 +894,59 @@ flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work
     a.lam = (float)p->lambda; a.beta = (float)p->beta;
     enqueue_pdr_iter(a, p->gs_sweeps, hw, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
+    return FLOW_OK;
+}
+
+flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                           const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                           int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                           void* stream) {
+    flow_status v = validate(p);
+    if (v != FLOW_OK) return v;
+    if (!in || !out || !s_out || !Ix || !Iy || !It || !u0 || !v0) return fail(FLOW_E_INVAL, "NULL pointer");
+    if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
+    if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
+    const bool hw = p->beta > 0;
+    const int64_t halo = (int64_t)(4 * p->gs_sweeps + 3) * iters;
+    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw))
+        return fail(FLOW_E_INVAL, "tile plus halo exceeds the pDR tile kernel's capacity");
+    const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,
+                            in->qb1x, in->qb1y, in->qb2x, in->qb2y};
+    const float* outs[12] = {out->w, out->u, out->v, out->wb, out->ub, out->vb, out->pbx, out->pby,
+                             out->qb1x, out->qb1y, out->qb2x, out->qb2y};
+    for (int k = 0; k < 12; ++k) {
+        const bool wk = k == 0 || k == 3 || k == 6 || k == 7;
+        if (wk && !hw) continue;
+        if (!ins[k] || !outs[k] || ins[k] == outs[k]) return fail(FLOW_E_INVAL, "bad pDR state plane");
+        EXTENT(ins[k], H, W, ld, "pDR state in");
+        EXTENT(outs[k], H, W, ld, "pDR state out");
+    }
+    EXTENT(Ix, H, W, ld, "Ix"); EXTENT(Iy, H, W, ld, "Iy"); EXTENT(It, H, W, ld, "It");
+    EXTENT(u0, H, W, ld, "u0"); EXTENT(v0, H, W, ld, "v0"); EXTENT(s_out, H, W, ld, "s_out");
+    LevelPlanes L{};
+    L.H = H; L.W = W; L.ld = ld;
+    for (int c = 0; c < 3; ++c) {
+        L.Xs[0][c] = const_cast<float*>(ins[c]);
+        L.Xbs[0][c] = const_cast<float*>(ins[3 + c]);
+        L.Xs[1][c] = const_cast<float*>(outs[c]);
+        L.Xbs[1][c] = const_cast<float*>(outs[3 + c]);
+    }
+    for (int c = 0; c < 6; ++c) {
+        L.ybs[0][c] = const_cast<float*>(ins[6 + c]);
+        L.ybs[1][c] = const_cast<float*>(outs[6 + c]);
+    }
+    L.Ix = const_cast<float*>(Ix); L.Iy = const_cast<float*>(Iy); L.It = const_cast<float*>(It);
+    L.U0[0] = const_cast<float*>(u0); L.U0[1] = const_cast<float*>(v0);
+    L.s_out = s_out;
+    PdrTbPlan T;
+    T.tb = true;
+    T.K = iters;
+    T.th = tile_h;
+    T.tw = tile_w;
+    hipStream_t s = (hipStream_t)stream;
+    launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, s);   // reads set 0 (in), writes set 1 (out)
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
     return FLOW_OK;
 }
 

@@ -35,7 +35,9 @@ struct LevelPlanes {
     float *Ix = nullptr, *Iy = nullptr, *It = nullptr;
     float* st[2][10] = {};                // ADMM ping-pong: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
     float* U0[2] = {};                    // linearisation point (u0, v0); ADMM: the flow without the pending increment
-    float *X[3] = {}, *Xb[3] = {}, *b[3] = {}, *yb[6] = {}, *s_out = nullptr;   // pDR
+    // pDR, two state sets (the tile kernel reads one and writes the other): X = (w, u, v),
+    // X bar, y bar = (p_x, p_y, q1x, q1y, q2x, q2y); b is the three-pass kernels' work plane
+    float *Xs[2][3] = {}, *Xbs[2][3] = {}, *ybs[2][6] = {}, *b[3] = {}, *s_out = nullptr;
 };
 
 // Small device buffers used by the reductions of one solve stream.
@@ -93,6 +95,17 @@ struct OpScratch {
 };
 OpScratch& op_scratch();
 
+// pDR: the three-pass iteration (nullptr plan) or K-iteration tiles of one level (direct tiling).
+struct PdrTbPlan {
+    bool tb = false;
+    bool resident = false;     // one tile covers the level: a whole warp per launch
+    int K = 1;                 // iterations per launch
+    int th = 0, tw = 0;
+};
+PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target);
+extern int g_pdr_mode;
+extern int g_pdr_k;
+
 // Per-level choice between the one-pass kernel and K-iteration tiles.
 struct LevelTbPlan {
     bool tb = false;           // false: one launch of the one-pass kernel per iteration
@@ -105,7 +118,8 @@ struct LevelTbPlan {
 };
 // Autotuned kernel choice of one level shape (see flow_autotune).
 struct TunedChoice {
-    int mode = 0;              // 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 small tiles/1024
+    int mode = 0;              // ADMM: 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 small tiles/1024;
+                               // pDR: 1 three-pass, 5 tiles (K = 0: resident)
     int K = 0, rows = 0;
     double us_per_iter = 0;
 };
@@ -136,11 +150,18 @@ struct TbTables {
 // Iteration plan of one solve shape: a plan per level and the device tables of the tile kernel.
 struct SolvePlan {
     std::vector<LevelTbPlan> levels;
+    std::vector<PdrTbPlan> pdr;    // per level (pDR)
     std::unique_ptr<TbTables> tables;
 };
 
 flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
                       const std::map<std::string, TunedChoice>* tuned);
+PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std::string, TunedChoice>* tuned);
+int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int64_t n,
+                      hipStream_t s, int64_t* launches);
+PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p, int cur);
+PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int K);
+void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s);
 int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
                        int64_t n, int at_slot, const float* at2, hipStream_t s, int64_t* launches = nullptr);
 TbArgs tb_args(const SolvePlan& plan, const LevelTbPlan& P, const LevelPlanes& L, const flow_params& p, int cur,

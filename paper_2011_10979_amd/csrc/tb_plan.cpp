@@ -67,6 +67,33 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
     return P;
 }
 
+PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target) {
+    // output tile th x tw whose extended region (halo (2n+1)K top / left, (2n+2)K bottom / right,
+    // clipped to the image) fits the kernel's capacity; the whole level if it fits
+    PdrTbPlan P;
+    const int cap = pdr_tb_capacity(hw);
+    if ((int64_t)H * W <= cap) {
+        P.tb = P.resident = true;
+        P.K = K;
+        P.th = H;
+        P.tw = W;
+        return P;
+    }
+    const int halo = (4 * sweeps + 3) * K;
+    if (ew_target <= 0) ew_target = 64;
+    const int ew = std::min(W, std::max(ew_target, halo + 8));
+    const int tw = (ew >= W) ? W : ew - halo;
+    const int ext_w = std::min(W, tw + halo);
+    const int eh = cap / ext_w;
+    const int th = (eh >= H) ? H : eh - halo;
+    if (tw < 8 || th < 2 || (int64_t)ext_w * std::min(H, th + halo) > cap) return P;
+    P.tb = true;
+    P.K = K;
+    P.th = th;
+    P.tw = tw;
+    return P;
+}
+
 std::string tune_key(int H, int W, bool hw, int iters) {
     return std::to_string(H) + "x" + std::to_string(W) + (hw ? "w" : "") + "i" + std::to_string(iters);
 }

@@ -152,6 +152,37 @@ def test_pdr_iteration(shape, sweeps, beta):
     assert max_abs(to_np(s_out), duals["s"]) < 1e-5
 
 
+@pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 6), ((37, 130), (8, 30), 2), ((101, 250), (12, 20), 1),
+                                          ((40, 45), (40, 45), 9), ((64, 64), (10, 18), 2), ((33, 47), (5, 9), 3)])
+@pytest.mark.parametrize("sweeps,beta", [(1, 0.0), (1, 0.05), (2, 0.0)])
+def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
+    """K pDR iterations of the tile kernel (halo (2n+1)K / (2n+2)K, ragged tiles, a resident level)
+    against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
+    print_case("pdr_tb", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta)
+    halo = (4 * sweeps + 3) * K
+    if min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > 2048:
+        pytest.skip("tile plus halo exceeds the kernel capacity")
+    rng = np.random.default_rng(zlib.crc32(repr(("pdrtb", shape, tile, K, sweeps, beta)).encode()))
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0)
+    ref = dict(st)
+    for _ in range(K):
+        ref, duals = schemes.pdr_step(ref, L, beta, 0.05, 2.0, 0.4, sweeps)
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    out, s_out = fm.pdr_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
+                           fm.Params(scheme="pdr", gs_sweeps=sweeps, beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    tol = 1e-4 * max(1, K)
+    for k in keys:
+        assert max_abs(to_np(out[k]), ref[k]) < tol, (k, max_abs(to_np(out[k]), ref[k]))
+    assert max_abs(to_np(s_out), duals["s"]) < tol
+    for k in keys:                                   # the input state is left as it was
+        assert np.array_equal(to_np(g[k]), f32(st[k]))
+
+
 @pytest.mark.parametrize("shape", [(2, 2), (70, 130), (240, 320)])
 @pytest.mark.parametrize("beta", [0.0, 0.05])
 def test_energy_terms(shape, beta):

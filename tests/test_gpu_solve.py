@@ -219,3 +219,18 @@ def test_every_kernel_mode_keeps_parity(ctx, mode, k):
     finally:
         fm.set_tuning("tb_mode", 0)
         fm.set_tuning("tb_k", 0)
+
+
+@pytest.mark.parametrize("mode,k,beta", [(1, 0, 0.0), (5, 1, 0.0), (5, 2, 0.0), (5, 3, 0.05), (5, 2, 0.05)])
+def test_every_pdr_kernel_mode_keeps_parity(ctx, mode, k, beta):
+    """pDR with the three-pass iteration and with K-iteration tiles (K = 1, 2, 3; the coarsest
+    levels resident) meets the bar."""
+    print(f"[case] forced pDR mode {mode} K {k} beta {beta}", flush=True)
+    fm.set_tuning("pdr_mode", mode)
+    fm.set_tuning("pdr_k", k)
+    try:
+        pair = synth.vga_pair(seed=6, H=120, W=150)
+        conditioned_check(ctx, pair, f"pdr mode {mode} K {k}", scheme="pdr", beta=beta, levels=3, warps=2, iters=30)
+    finally:
+        fm.set_tuning("pdr_mode", 0)
+        fm.set_tuning("pdr_k", 0)
