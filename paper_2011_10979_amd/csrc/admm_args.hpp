@@ -67,7 +67,9 @@ struct TbArgs {
     TbLevel lvl;
     int th, tw, ntx;
 };
-int tb_capacity(bool has_w, int nt);   // nt: 256, 1024, or 1025 (1024 threads, small tiles)
+// nt: 256, 1024, or the small-tile codes 1025 / 513 / 257 (1024 / 512 / 256 threads, 2 pixels each;
+// 513 and 257 only with direct tiling)
+int tb_capacity(bool has_w, int nt);
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s);
 void launch_reset_u32(unsigned* p, int n, hipStream_t s);
 

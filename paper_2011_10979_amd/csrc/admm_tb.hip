@@ -292,6 +292,8 @@ void launch_reset_u32(unsigned* p, int n, hipStream_t s) {
 int tb_capacity(bool has_w, int nt) {
     if (nt == 1024) return 1024 * (has_w ? kTbPptLW : kTbPptL);
     if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
+    if (nt == 513) return 512 * kTbPptSmall;     // 512 threads, small tiles
+    if (nt == 257) return 256 * kTbPptSmall;     // 256 threads, small tiles
     return 256 * (has_w ? kTbPptW : kTbPpt);
 }
 
@@ -310,6 +312,15 @@ void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s
     } else if (nt == 1025) {
         if (has_w) launch_one<true, 1024, kTbPptSmall>(a, grid, s);
         else launch_one<false, 1024, kTbPptSmall>(a, grid, s);
+    } else if (nt == 513 || nt == 257) {
+        // small work-groups for latency-bound levels: direct tiling only
+        if (nt == 513) {
+            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 512, kTbPptSmall>), dim3(grid), dim3(512), 0, s, a);
+            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 512, kTbPptSmall>), dim3(grid), dim3(512), 0, s, a);
+        } else {
+            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 256, kTbPptSmall>), dim3(grid), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 256, kTbPptSmall>), dim3(grid), dim3(256), 0, s, a);
+        }
     } else {
         if (has_w) launch_one<true, 256, kTbPptW>(a, grid, s);
         else launch_one<false, 256, kTbPpt>(a, grid, s);

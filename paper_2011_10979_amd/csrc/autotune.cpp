@@ -134,7 +134,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             c.tb = false;
             cands.push_back(c);
         }
-        for (int mode : {2, 4, 3})
+        for (int mode : {2, 4, 3, 7, 6})
             for (int K : {2, 4, 8, 16}) {
                 LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K);
                 if (!P.tb) continue;
@@ -203,12 +203,13 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
                                         int32_t pdr_sweeps, int32_t mode, int32_t K, int32_t rows) {
     if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
-    if (mode < 1 || mode > 5) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4 (tiles) or 5 (pDR tiles)");
+    if (mode < 1 || mode > 7) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6, 7 (tiles) or 5 (pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
     if (pdr_sweeps < 0) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= 0");
     if (pdr_sweeps > 0 && mode != 1 && mode != 5) return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass) or 5 (tiles)");
     if (pdr_sweeps == 0 && mode == 5) return fail(FLOW_E_INVAL, "mode 5 is a pDR mode");
+    if (mode > 7) return fail(FLOW_E_INVAL, "unknown mode");
     TunedChoice c;
     c.mode = mode;
     c.K = K;

@@ -586,8 +586,9 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "tb_mode") == 0) {
-        if (value < 0 || value > 4)
-            return fail(FLOW_E_INVAL, "tb_mode: 0 built-in, 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 small tiles/1024");
+        if (value < 0 || value > 7 || value == 5)
+            return fail(FLOW_E_INVAL, "tb_mode: 0 built-in, 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 / 7 / 6 small "
+                                      "tiles of 1024 / 512 / 256 threads");
         g_tb_mode = (int)value;
         return FLOW_OK;
     }
@@ -797,10 +798,12 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
     if (!in || !out || !Ix || !Iy || !It || !at) return fail(FLOW_E_INVAL, "NULL pointer");
     if (!in->u0 || !in->v0) return fail(FLOW_E_INVAL, "the tile kernel runs the increment form: u0, v0 required");
     if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
-    if (threads != 256 && threads != 1024 && threads != 1025)
-        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or 1025 (1024 threads, small tiles)");
+    if (threads != 256 && threads != 1024 && threads != 1025 && threads != 513 && threads != 257)
+        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or a small-tile code 1025 / 513 / 257");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     if (order < 0 || order > 3) return fail(FLOW_E_INVAL, "order must be 0, 1, 2 or 3");
+    if ((threads == 513 || threads == 257) && order != 0)
+        return fail(FLOW_E_INVAL, "the 512- and 256-thread small tiles run with direct tiling (order 0) only");
     const bool hw = p->beta > 0;
     const int cap = tb_capacity(hw, threads);
     if ((int64_t)std::min<int64_t>(H, (int64_t)tile_h + 3 * iters) * std::min<int64_t>(W, (int64_t)tile_w + 3 * iters) > cap)
