@@ -599,7 +599,7 @@ def main():
     elif args.scheme == "pdr":
         key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}p{params.gs_sweeps}"
         ch0 = (tuning or {}).get(key0, {"mode": 5})
-        if ch0["mode"] == 5:
+        if ch0["mode"] in (5, 6):
             # K-iteration pDR tiles: per launch the kernel reads X, X bar, y bar and the
             # linearisation once and writes X, X bar, y bar and Theta once
             roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,

@@ -244,7 +244,7 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
  * kernel with `rows` rows per strip (0 = built-in), 2 / 3 / 4 / 7 / 6 = K-iteration tiles of 256 /
  * 1024 threads / small tiles of 1024 / 512 / 256 threads with K iterations per launch (K = 0: resident if the level fits one
  * tile, else the built-in K).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
- * iteration, 5 = K-iteration tiles (K = 0: resident).  Lets a caller reuse a tuning measured in
+ * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident).  Lets a caller reuse a tuning measured in
  * another process.  Drops the context's captured graphs. */
 flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t pdr_sweeps,
                              int32_t mode, int32_t K, int32_t rows);
@@ -264,7 +264,7 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 small tiles (2 pixels per thread) of 1024 / 512 / 256 threads.
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
  *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
- *                 warp resident), 1 three-pass iteration, 5 tiles.
+ *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads.
  *   "pdr_k"       iterations per pDR tile launch (0 = built-in 2).
  *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
  *                 work queues.

@@ -77,8 +77,9 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             three.c.mode = 1;
             cands.push_back(three);
             bool resident_done = false;
+            for (int nt : {1024, 512})
             for (int K : {1, 2, 3}) {
-                PdrTbPlan T = plan_pdr_tiles(L.H, L.W, hw, p->gs_sweeps, K, 0);
+                PdrTbPlan T = plan_pdr_tiles(L.H, L.W, hw, p->gs_sweeps, K, 0, nt);
                 if (!T.tb) continue;
                 if (T.resident) {
                     if (resident_done) continue;
@@ -86,7 +87,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
                     T.K = p->iters;
                 }
                 PCand c{};
-                c.c.mode = 5;
+                c.c.mode = nt == 512 ? 6 : 5;
                 c.c.K = T.resident ? 0 : K;
                 c.T = T;
                 cands.push_back(c);
@@ -207,7 +208,8 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
     if (pdr_sweeps < 0) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= 0");
-    if (pdr_sweeps > 0 && mode != 1 && mode != 5) return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass) or 5 (tiles)");
+    if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6)
+        return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads)");
     if (pdr_sweeps == 0 && mode == 5) return fail(FLOW_E_INVAL, "mode 5 is a pDR mode");
     if (mode > 7) return fail(FLOW_E_INVAL, "unknown mode");
     TunedChoice c;

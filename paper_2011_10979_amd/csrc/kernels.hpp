@@ -88,7 +88,7 @@ struct PdrArgs {
 };
 // Temporally blocked pDR: K iterations of one tile per work-group launch (direct tiling of one
 // level).  Component order: x / x bar (u, v, w), y (q1x, q1y, q2x, q2y, p_x, p_y).
-constexpr int kPdrPpt = 2;           // pixels per thread (1024 threads)
+constexpr int kPdrPpt = 2;           // pixels per thread (1024 or 512 threads)
 constexpr int kPdrPptW = 2;
 struct PdrTbLevel {
     const float* x_in[3]; const float* xb_in[3]; const float* y_in[6];
@@ -104,8 +104,8 @@ struct PdrTbArgs {
     int th, tw, ntx, ntiles;         // output tiling
     float sigma, tau, stt, lam, beta;
 };
-int pdr_tb_capacity(bool has_w);
-void launch_pdr_tb(const PdrTbArgs& a, bool has_w, hipStream_t s);
+int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads
+void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 
 void launch_pdr_rhs_red(const PdrArgs& a, bool has_w, hipStream_t s);
 void launch_pdr_colour(const PdrArgs& a, bool has_w, hipStream_t s);

@@ -241,12 +241,17 @@ __global__ __launch_bounds__(NT) void pdr_tb_kernel(PdrTbArgs a) {
 
 }  // namespace
 
-int pdr_tb_capacity(bool has_w) { return 1024 * (has_w ? kPdrPptW : kPdrPpt); }
+int pdr_tb_capacity(bool has_w, int nt) { return nt * (has_w ? kPdrPptW : kPdrPpt); }
 
-void launch_pdr_tb(const PdrTbArgs& a, bool has_w, hipStream_t s) {
+void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
-    if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 1024, kPdrPptW>), dim3(grid), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL((pdr_tb_kernel<false, 1024, kPdrPpt>), dim3(grid), dim3(1024), 0, s, a);
+    if (nt == 512) {
+        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 512, kPdrPptW>), dim3(grid), dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((pdr_tb_kernel<false, 512, kPdrPpt>), dim3(grid), dim3(512), 0, s, a);
+    } else {
+        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 1024, kPdrPptW>), dim3(grid), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((pdr_tb_kernel<false, 1024, kPdrPpt>), dim3(grid), dim3(1024), 0, s, a);
+    }
 }
 
 }  // namespace flowmi

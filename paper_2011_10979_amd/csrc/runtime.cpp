@@ -351,7 +351,7 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
     return cur;
 }
 
-int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles
+int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512
 int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
 constexpr int kPdrDefaultK = 2;
 
@@ -366,10 +366,12 @@ PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std:
         }
     }
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
-    PdrTbPlan T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, K > 0 ? K : kPdrDefaultK, 0);
+    const int nt = mode == 6 ? 512 : 1024;
+    PdrTbPlan T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, K > 0 ? K : kPdrDefaultK, 0, nt);
     if (T.resident && K == 0) T.K = p.iters;        // the whole warp in one launch
     if (!T.tb) {                                     // the halo does not fit: fewer iterations per launch
-        for (int k = (K > 0 ? K : kPdrDefaultK) - 1; k >= 1 && !T.tb; --k) T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, k, 0);
+        for (int k = (K > 0 ? K : kPdrDefaultK) - 1; k >= 1 && !T.tb; --k)
+            T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, k, 0, nt);
     }
     return T;
 }
@@ -409,7 +411,7 @@ int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPla
     int64_t t = 0;
     while (t < n) {
         const int kk = (int)std::min<int64_t>(T.resident ? n - t : T.K, n - t);
-        launch_pdr_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, s);
+        launch_pdr_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, T.nt, s);
         if (launches) ++*launches;
         cur ^= 1;
         t += kk;
@@ -598,7 +600,8 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "pdr_mode") == 0) {
-        if (value != 0 && value != 1 && value != 5) return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles");
+        if (value != 0 && value != 1 && value != 5 && value != 6)
+            return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles of 1024 threads, 6 of 512");
         g_pdr_mode = (int)value;
         return FLOW_OK;
     }
@@ -911,7 +914,7 @@ flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, 
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     const bool hw = p->beta > 0;
     const int64_t halo = (int64_t)(4 * p->gs_sweeps + 3) * iters;
-    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw))
+    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw, 1024))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the pDR tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,
                             in->qb1x, in->qb1y, in->qb2x, in->qb2y};
@@ -947,7 +950,7 @@ flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, 
     T.th = tile_h;
     T.tw = tile_w;
     hipStream_t s = (hipStream_t)stream;
-    launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, s);   // reads set 0 (in), writes set 1 (out)
+    launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);   // reads set 0 (in), writes set 1 (out)
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return FLOW_OK;

@@ -99,10 +99,11 @@ OpScratch& op_scratch();
 struct PdrTbPlan {
     bool tb = false;
     bool resident = false;     // one tile covers the level: a whole warp per launch
+    int nt = 1024;             // work-group size: 1024 or 512 threads
     int K = 1;                 // iterations per launch
     int th = 0, tw = 0;
 };
-PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target);
+PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target, int nt = 1024);
 extern int g_pdr_mode;
 extern int g_pdr_k;
 

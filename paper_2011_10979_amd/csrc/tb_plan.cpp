@@ -69,11 +69,12 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
     return P;
 }
 
-PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target) {
+PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target, int nt) {
     // output tile th x tw whose extended region (halo (2n+1)K top / left, (2n+2)K bottom / right,
     // clipped to the image) fits the kernel's capacity; the whole level if it fits
     PdrTbPlan P;
-    const int cap = pdr_tb_capacity(hw);
+    P.nt = nt;
+    const int cap = pdr_tb_capacity(hw, nt);
     if ((int64_t)H * W <= cap) {
         P.tb = P.resident = true;
         P.K = K;

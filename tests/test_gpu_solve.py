@@ -221,10 +221,11 @@ def test_every_kernel_mode_keeps_parity(ctx, mode, k):
         fm.set_tuning("tb_k", 0)
 
 
-@pytest.mark.parametrize("mode,k,beta", [(1, 0, 0.0), (5, 1, 0.0), (5, 2, 0.0), (5, 3, 0.05), (5, 2, 0.05)])
+@pytest.mark.parametrize("mode,k,beta", [(1, 0, 0.0), (5, 1, 0.0), (5, 2, 0.0), (5, 3, 0.05), (5, 2, 0.05),
+                                         (6, 1, 0.0), (6, 2, 0.05)])
 def test_every_pdr_kernel_mode_keeps_parity(ctx, mode, k, beta):
-    """pDR with the three-pass iteration and with K-iteration tiles (K = 1, 2, 3; the coarsest
-    levels resident) meets the bar."""
+    """pDR with the three-pass iteration and with K-iteration tiles of 1024 and 512 threads (K = 1, 2,
+    3; the coarsest levels resident) meets the bar."""
     print(f"[case] forced pDR mode {mode} K {k} beta {beta}", flush=True)
     fm.set_tuning("pdr_mode", mode)
     fm.set_tuning("pdr_k", k)
