@@ -4,6 +4,8 @@ State dictionaries hold full-size float64 arrays:
   ADMM family:  w, u, v (multipliers = primal flow and illumination), px, py (p), q1x, q1y, q2x,
                 q2y (q), s (data dual).
   pDR:          w, u, v (X), wb, ub, vb (X bar), pbx, pby, qb1x, qb1y, qb2x, qb2y (y bar).
+  ALG1:         the pDR layout: X, X bar (the extrapolated primal point) and y = (p, q) in the y bar
+                slots.
 Linearisation L holds Ix, Iy, It and at (a~).  With beta = 0 the (w, p) block never leaves zero.
 """
 from __future__ import annotations
@@ -196,3 +198,36 @@ def pdr_step(st, L, beta, lam, sigma, tau, sweeps):
 def pdr_T(x, st):
     """T x = x - st Delta x (the operator the SRBGS sweeps precondition)."""
     return x - st * laplacian(x)
+
+
+def alg1_step(st, L, beta, lam, tau, sigma):
+    """One iteration of ALG1, the first-order primal-dual method of Chambolle and Pock that Sec. 4
+    compares against, on the saddle form eq:primal-dual:optical:o (K = diag(grad, grad), F the data
+    term, the dual sets the unit balls of p and of the coupled q), extrapolation weight 1:
+      y+     = P(y + tau K X bar)                       (P_p on p, joint P_q on q)
+      X+     = (I + sigma dF)^{-1}(X - sigma K^* y+)    with K^* y = -div y   (eq:resolvent)
+      X bar+ = 2 X+ - X
+    tau is the dual and sigma the primal step (tau sigma |K|^2 <= 1 with |K|^2 <= 8).  Returns the
+    new state and the dual pair of the gap: q = y+ and s = Theta of the resolvent.
+    """
+    Ix, Iy, It = L["Ix"], L["Iy"], L["It"]
+    has_w = beta != 0.0
+    gwx, gwy = grad(st["wb"])
+    gux, guy = grad(st["ub"])
+    gvx, gvy = grad(st["vb"])
+    if has_w:
+        px, py = proj_p(st["pbx"] + tau * gwx, st["pby"] + tau * gwy)
+    else:
+        px, py = st["pbx"], st["pby"]
+    q1x, q1y, q2x, q2y = proj_q(st["qb1x"] + tau * gux, st["qb1y"] + tau * guy,
+                                st["qb2x"] + tau * gvx, st["qb2y"] + tau * gvy)
+    wt = st["w"] + sigma * div(px, py) if has_w else st["w"]
+    ut = st["u"] + sigma * div(q1x, q1y)
+    vt = st["v"] + sigma * div(q2x, q2y)
+    w, u, v, theta = resolvent(wt, ut, vt, Ix, Iy, It, beta, lam, sigma)
+    if not has_w:
+        w = st["w"]
+    new = dict(w=w, u=u, v=v, wb=2 * w - st["w"] if has_w else st["wb"], ub=2 * u - st["u"], vb=2 * v - st["v"],
+               pbx=px, pby=py, qb1x=q1x, qb1y=q1y, qb2x=q2x, qb2y=q2y)
+    gap_duals = dict(px=px, py=py, q1x=q1x, q1y=q1y, q2x=q2x, q2y=q2y, s=theta)
+    return new, gap_duals

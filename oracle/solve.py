@@ -4,8 +4,9 @@ For level l = L-1 (coarsest) .. 0: bring the flow up from the coarser level (zer
 reset the dual variables, then `warps` times re-linearise around the current flow and run `iters`
 iterations of the chosen scheme.  Dual variables (and pDR's X bar, y bar) carry over between warps
 of one level.  Sec. 4 fixes the solver parameters used here as defaults (c = 0.05; r = 1.618 for
-rpADMMI; rho = 1.9 for rpADMMII; sigma = 2, tau = 0.4 for pDR); the outer-loop choices are this
-library's reading of the unspecified "standard coarse-to-fine framework".
+rpADMMI; rho = 1.9 for rpADMMII; sigma = 2, tau = 0.4 for pDR; ALG1 dual step 0.1 and primal step
+1 / (8 x 0.1)); the outer-loop choices are this library's reading of the unspecified "standard
+coarse-to-fine framework".
 """
 from __future__ import annotations
 
@@ -17,7 +18,8 @@ from . import schemes
 from .energy import terms
 from .pyramid import build_pyramid, linearize, upsample
 
-SCHEMES = ("padmm", "rpadmm2", "zach", "pdr")
+SCHEMES = ("padmm", "rpadmm2", "zach", "pdr", "alg1")
+PDR_STATE = ("pdr", "alg1")     # schemes whose state is (X, X bar, y)
 
 
 @dataclass
@@ -30,6 +32,8 @@ class Params:
     sigma: float = 2.0
     tau: float = 0.4
     gs_sweeps: int = 1
+    alg1_tau: float = 0.1      # ALG1: dual step (Sec. 4); the primal step is 1 / (L^2 tau), L^2 = 8
+    alg1_sigma: float = 1.25
     kappa: float = 255.0       # intensity scale applied to frames given in [0, 1]
     levels: int = 1
     warps: int = 1
@@ -63,6 +67,8 @@ def step(scheme, st, L, p: Params):
         return new, new
     if scheme == "pdr":
         return schemes.pdr_step(st, L, p.beta, p.lam, p.sigma, p.tau, p.gs_sweeps)
+    if scheme == "alg1":
+        return schemes.alg1_step(st, L, p.beta, p.lam, p.alg1_tau, p.alg1_sigma)
     raise ValueError(scheme)
 
 
@@ -89,12 +95,12 @@ def solve_pair(I0, I1, p: Params, trace: bool = False):
             u, v, w = np.zeros(shape), np.zeros(shape), np.zeros(shape)
         else:
             u, v, w = upsample(u, shape, 2.0), upsample(v, shape, 2.0), upsample(w, shape, 1.0)
-        st = zeros_pdr(shape, u, v, w) if p.scheme == "pdr" else zeros_admm(shape, u, v, w)
+        st = zeros_pdr(shape, u, v, w) if p.scheme in PDR_STATE else zeros_admm(shape, u, v, w)
         duals = zeros_admm(shape, u, v, w)
         for wp in range(p.warps):
             Ix, Iy, It, at = linearize(a, b, dx, dy, st["u"], st["v"], p.kappa, p.beta)
             L = dict(Ix=Ix, Iy=Iy, It=It, at=at)
-            if p.scheme != "pdr":
+            if p.scheme not in PDR_STATE:
                 duals = st
             for _ in range(p.iters):
                 st, duals = step(p.scheme, st, L, p)

@@ -150,3 +150,32 @@ def test_linearisation_without_flow_term_is_caught(monkeypatch):
         return Ix, Iy, It + Ix * u0 + Iy * v0, at
     monkeypatch.setattr(pyramid, "linearize", bad)
     _fails(T_pyr.test_linearize_is_exact_first_order_model_on_a_ramp)
+
+
+def test_alg1_primal_step_with_the_wrong_adjoint_sign_is_caught(monkeypatch):
+    good = schemes.div
+
+    def flipped(px, py):
+        return -good(px, py)
+    # only ALG1's primal step sees the flipped divergence: its pin checks the prox of the primal step
+    orig = schemes.alg1_step
+
+    def bad(st, L, beta, lam, tau, sigma):
+        monkeypatch.setattr(schemes, "div", flipped)
+        try:
+            return orig(st, L, beta, lam, tau, sigma)
+        finally:
+            monkeypatch.setattr(schemes, "div", good)
+    monkeypatch.setattr(schemes, "alg1_step", bad)
+    _fails(T_sch.test_alg1_primal_step_is_the_proximal_descent, 0.3)
+
+
+def test_alg1_without_extrapolation_is_caught(monkeypatch):
+    orig = schemes.alg1_step
+
+    def bad(st, L, beta, lam, tau, sigma):
+        new, duals = orig(st, L, beta, lam, tau, sigma)
+        new = dict(new, ub=new["u"], vb=new["v"], wb=new["w"])
+        return new, duals
+    monkeypatch.setattr(schemes, "alg1_step", bad)
+    _fails(T_sch.test_alg1_primal_step_is_the_proximal_descent, 0.0)

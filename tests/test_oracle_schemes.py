@@ -240,7 +240,7 @@ def run(scheme, relax, beta, iters, checkpoints):
     shape, L = small_problem(beta)
     p = Params(scheme=scheme, relax=relax, beta=beta)
     z = np.zeros(shape)
-    st = zeros_pdr(shape, z, z, z) if scheme == "pdr" else zeros_admm(shape, z.copy(), z.copy(), z.copy())
+    st = zeros_pdr(shape, z, z, z) if scheme in ("pdr", "alg1") else zeros_admm(shape, z.copy(), z.copy(), z.copy())
     out = []
     for k in range(1, iters + 1):
         st, duals = step(scheme, st, L, p)
@@ -269,3 +269,82 @@ def test_all_schemes_reach_the_same_minimum(beta):
         finals[(scheme, relax)] = last["energy"]
     e = np.array(list(finals.values()))
     assert np.ptp(e) / e.mean() < 2e-3, finals
+
+
+# --- ALG1 (the primal-dual comparison algorithm of Sec. 4) --------------------------------------
+def random_pd_state(rng, shape, beta):
+    st = {k: rng.normal(scale=0.5, size=shape) for k in ("w", "u", "v", "wb", "ub", "vb")}
+    for k in ("pbx", "pby", "qb1x", "qb1y", "qb2x", "qb2y"):
+        st[k] = rng.uniform(-0.5, 0.5, size=shape)
+    if beta == 0.0:
+        for k in ("w", "wb", "pbx", "pby"):
+            st[k][:] = 0.0
+    return st
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3])
+def test_alg1_dual_step_is_the_projected_ascent(beta):
+    """y+ is the nearest point of the dual set to y + tau K X bar: feasible, and the variational
+    inequality <z - y+, (y + tau K X bar) - y+> <= 0 holds for feasible z."""
+    rng = np.random.default_rng(31)
+    shape = (6, 7)
+    st = random_pd_state(rng, shape, beta)
+    L = random_lin(rng, shape, beta)
+    new, _ = schemes.alg1_step(st, L, beta, 0.05, 0.1, 1.25)
+    tau = 0.1
+    g = [ops.grad(st["ub"]), ops.grad(st["vb"])]
+    a = [st["qb1x"] + tau * g[0][0], st["qb1y"] + tau * g[0][1], st["qb2x"] + tau * g[1][0], st["qb2y"] + tau * g[1][1]]
+    y = [new["qb1x"], new["qb1y"], new["qb2x"], new["qb2y"]]
+    assert np.all(ops.norm_q(*y) <= 1 + 1e-12)
+    for _ in range(20):
+        z = [rng.normal(size=shape) for _ in range(4)]
+        z = list(ops.proj_q(*z))
+        vi = sum(((zi - yi) * (ai - yi)).sum() for zi, yi, ai in zip(z, y, a))
+        assert vi <= 1e-10
+    if beta > 0:
+        gw = ops.grad(st["wb"])
+        assert np.all(ops.norm_p(new["pbx"], new["pby"]) <= 1 + 1e-12)
+        assert np.allclose(np.hypot(*ops.proj_p(st["pbx"] + tau * gw[0], st["pby"] + tau * gw[1])),
+                           np.hypot(new["pbx"], new["pby"]))
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3])
+def test_alg1_primal_step_is_the_proximal_descent(beta):
+    """X+ minimises lambda |rho(X)| + <K X, y+> + |X - X^k|^2 / (2 sigma) (numerically, per pixel:
+    <K X, y> = -<X, div y> is separable), i.e. the primal step uses K^* = -div."""
+    rng = np.random.default_rng(32)
+    shape = (3, 4)
+    st = random_pd_state(rng, shape, beta)
+    L = random_lin(rng, shape, beta)
+    lam, tau, sigma = 0.05, 0.1, 1.25
+    new, _ = schemes.alg1_step(st, L, beta, lam, tau, sigma)
+    dq1 = ops.div(new["qb1x"], new["qb1y"])
+    dq2 = ops.div(new["qb2x"], new["qb2y"])
+    dp = ops.div(new["pbx"], new["pby"])
+    for i in range(shape[0]):
+        for j in range(shape[1]):
+            x0 = np.array([st["w"][i, j], st["u"][i, j], st["v"][i, j]])
+            lin = np.array([dp[i, j], dq1[i, j], dq2[i, j]])
+            e = np.array([beta, L["Ix"][i, j], L["Iy"][i, j]])
+
+            def f(x):
+                xx = x if beta > 0 else np.array([0.0, x[1], x[2]])
+                return (lam * abs(L["It"][i, j] + e @ xx) - lin @ xx + ((xx - x0) ** 2).sum() / (2 * sigma))
+            best = min((scipy.optimize.minimize(f, x0 + rng.normal(scale=0.3, size=3), method="Nelder-Mead",
+                                                options=dict(xatol=1e-11, fatol=1e-14, maxiter=20000)) for _ in range(3)),
+                       key=lambda r: r.fun)
+            got = np.array([new["w"][i, j], new["u"][i, j], new["v"][i, j]])
+            assert f(got) <= best.fun + 1e-9
+            assert np.allclose(got[1:], best.x[1:], atol=2e-4)
+    # extrapolation: X bar+ = 2 X+ - X
+    assert np.allclose(new["ub"], 2 * new["u"] - st["u"]) and np.allclose(new["vb"], 2 * new["v"] - st["v"])
+
+
+def test_alg1_reaches_the_minimum_of_the_preconditioned_schemes():
+    """ALG1 converges (O(1/k)) to the same minimum energy as pADMM on the same linearised problem."""
+    ref = run("padmm", 1.0, 0.05, 3000, (3000,))[-1]
+    tr = run("alg1", 1.0, 0.05, 6000, (200, 6000))
+    first, last = tr
+    assert abs(last["gap"]) < 0.25 * abs(first["gap"])
+    assert abs(last["gap"]) / last["energy"] < 5e-3, last
+    assert abs(last["energy"] - ref["energy"]) / ref["energy"] < 5e-3, (last["energy"], ref["energy"])
