@@ -50,7 +50,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
 
 
-# pDR tile kernel, per launch: reads X, X bar, y bar, I_x, I_y, I_t, u0, v0; writes X, X bar, y bar, Theta
+# pDR / ALG1 tile kernels, per launch: reads X, X bar, y, I_x, I_y, I_t, u0, v0; writes X, X bar, y, Theta
+# (for ALG1 this is also one iteration done in one pass)
 PDR_TB_BYTES_PER_PX_LAUNCH = {False: 4 * ((2 + 2 + 4 + 5) + (2 + 2 + 4 + 1)), True: 4 * ((3 + 3 + 6 + 5) + (3 + 3 + 6 + 1))}
 
 
@@ -596,17 +597,21 @@ def main():
                         f"{(tuning or {}).get(f'{shapes[0][0]}x{shapes[0][1]}i{args.iters}')}",
                         measured_traffic(f"{args.W}x{args.H}"), reps)
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
-    elif args.scheme == "pdr":
-        key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}p{params.gs_sweeps}"
+    elif args.scheme in ("pdr", "alg1"):
+        suffix = "a" if args.scheme == "alg1" else f"p{params.gs_sweeps}"
+        key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}{suffix}"
         ch0 = (tuning or {}).get(key0, {"mode": 5})
         if ch0["mode"] in (5, 6):
-            # K-iteration pDR tiles: per launch the kernel reads X, X bar, y bar and the
-            # linearisation once and writes X, X bar, y bar and Theta once
+            # K-iteration pDR / ALG1 tiles: per launch the kernel reads X, X bar, y and the
+            # linearisation once and writes X, X bar, y and Theta once
+            name = "ALG1" if args.scheme == "alg1" else "pDR"
             roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
-                            f"pDR tile kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
+                            f"{name} tile kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
                             None, reps, per_px=PDR_TB_BYTES_PER_PX_LAUNCH[has_w])
-            roof["one_pass_equivalent_GBs"] = round(pdr_bytes_per_px_iter(has_w, params.gs_sweeps) * shapes[0][0]
-                                                    * shapes[0][1] * lvl_iters[0] / (lvl_ms[0] * 1e-3) / 1e9, 1)
+            one_iter = (PDR_TB_BYTES_PER_PX_LAUNCH[has_w] if args.scheme == "alg1"
+                        else pdr_bytes_per_px_iter(has_w, params.gs_sweeps))
+            roof["one_pass_equivalent_GBs"] = round(one_iter * shapes[0][0] * shapes[0][1] * lvl_iters[0]
+                                                    / (lvl_ms[0] * 1e-3) / 1e9, 1)
         else:
             # three-pass pDR: the unit is one iteration (2n + 1 passes over the level)
             roof = roofline(lvl_ms[0], lvl_iters[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,

@@ -53,8 +53,11 @@ typedef enum flow_status {
  *                pADMM; beta = 0 with relax = 1 is Zach-pADMM (tag Zach-pADMM).
  *   FLOW_RPADMM2 rpADMMII (tag rpADMMII): relaxation rho = relax in (0, 2) of [SUN].
  *   FLOW_PDR     preconditioned Douglas-Rachford on the saddle-point form (tag pDR) with
- *                gs_sweeps symmetric red-black Gauss-Seidel sweeps as the preconditioner. */
-typedef enum flow_scheme { FLOW_PADMM = 0, FLOW_RPADMM2 = 1, FLOW_PDR = 2 } flow_scheme;
+ *                gs_sweeps symmetric red-black Gauss-Seidel sweeps as the preconditioner.
+ *   FLOW_ALG1    ALG1 of Sec. 4, the first-order primal-dual method the paper compares against, on
+ *                the same saddle form: y+ = P(y + alg1_tau grad X bar), X+ = J(X + alg1_sigma div y+)
+ *                (eq:resolvent), X bar+ = 2 X+ - X; alg1_tau alg1_sigma 8 <= 1. */
+typedef enum flow_scheme { FLOW_PADMM = 0, FLOW_RPADMM2 = 1, FLOW_PDR = 2, FLOW_ALG1 = 3 } flow_scheme;
 
 /* Storage of the image / derivative pyramids: FP32, or FP16 with FP32 arithmetic. */
 typedef enum flow_storage { FLOW_STORE_F32 = 0, FLOW_STORE_F16 = 1 } flow_storage;
@@ -77,6 +80,8 @@ typedef struct flow_params {
     double tol;               /* > 0: stop a warp's iterations once |gap| / energy <= tol (checked
                                  every check_every iterations; disables graph replay); 0: fixed count */
     int32_t check_every;      /* >= 1 when tol > 0 */
+    double alg1_tau;          /* ALG1 dual step > 0, default 0.1 (Sec. 4) */
+    double alg1_sigma;        /* ALG1 primal step > 0, default 1 / (8 alg1_tau) = 1.25 */
 } flow_params;
 
 /* FP64 scalars of the last warp of the finest level (linearised energy of that warp):
@@ -85,7 +90,8 @@ typedef struct flow_params {
  *   gap      = energy - dual
  *   residual = |A s + B y|_2, the violation of eq:dual:l1:flow:constaint
  *   tv, data = the two parts of energy.
- * For pDR the dual pair is (q, s) = (P(y_bar + 2 tau grad X), Theta) of the last iteration. */
+ * For pDR the dual pair is (q, s) = (P(y_bar + 2 tau grad X), Theta) of the last iteration; for ALG1
+ * it is (y, Theta) of the last iteration. */
 typedef struct flow_result {
     double energy, dual, gap, residual, tv, data;
 } flow_result;
@@ -244,7 +250,8 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
  * kernel with `rows` rows per strip (0 = built-in), 2 / 3 / 4 / 7 / 6 = K-iteration tiles of 256 /
  * 1024 threads / small tiles of 1024 / 512 / 256 threads with K iterations per launch (K = 0: resident if the level fits one
  * tile, else the built-in K).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
- * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident).  Lets a caller reuse a tuning measured in
+ * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident); pdr_sweeps = -1:
+ * ALG1, modes 5 / 6 as for pDR.  Lets a caller reuse a tuning measured in
  * another process.  Drops the context's captured graphs. */
 flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t pdr_sweeps,
                              int32_t mode, int32_t K, int32_t rows);
@@ -360,6 +367,15 @@ flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, 
                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
                            int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
                            void* stream);
+
+/* `iters` ALG1 iterations in ONE launch of its tile kernel, as flow_op_pdr_tb (same state planes:
+ * X, X bar = the extrapolated point, y in the y bar slots; steps p->alg1_tau, p->alg1_sigma); each
+ * tile's extended region min(H, tile_h + 2 iters) x min(W, tile_w + 2 iters) must hold at most 2048
+ * pixels.  Blocking. */
+flow_status flow_op_alg1_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                            int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                            void* stream);
 
 /* FP64 energy / dual / gap / residual of an ADMM-family state (see flow_result), blocking:
  * res is host memory and the stream is synchronised. */

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflowmi.so")
 
 FLOW_OK, FLOW_E_INVAL, FLOW_E_NOMEM, FLOW_E_HIP, FLOW_E_NONFINITE, FLOW_E_BUSY, FLOW_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
-SCHEMES = {"padmm": 0, "rpadmm2": 1, "pdr": 2}
+SCHEMES = {"padmm": 0, "rpadmm2": 1, "pdr": 2, "alg1": 3}
 STORAGE = {"f32": 0, "f16": 1}
 MAX_LEVELS = 16
 
@@ -34,7 +34,8 @@ class _Params(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("tau", ctypes.c_double), ("gs_sweeps", ctypes.c_int32),
                 ("intensity_scale", ctypes.c_double), ("levels", ctypes.c_int32), ("warps", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("storage", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("alg1_tau", ctypes.c_double),
+                ("alg1_sigma", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -78,7 +79,7 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
            "flow_tune_choice", "flow_autotune_batched", "flow_server_create", "flow_server_destroy",
            "flow_server_submit", "flow_server_step", "flow_server_poll", "flow_server_drain",
-           "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb"]
+           "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb", "flow_op_alg1_tb"]
 
 
 def lib():
@@ -122,6 +123,8 @@ def lib():
                                  ctypes.POINTER(_Params), vp],
             "flow_op_pdr_tb": [ctypes.POINTER(_PdrState), ctypes.POINTER(_PdrState), vp, vp, vp, vp, vp, vp, i32, i32,
                                i64, ctypes.POINTER(_Params), i32, i32, i32, vp],
+            "flow_op_alg1_tb": [ctypes.POINTER(_PdrState), ctypes.POINTER(_PdrState), vp, vp, vp, vp, vp, vp, i32, i32,
+                                i64, ctypes.POINTER(_Params), i32, i32, i32, vp],
             "flow_op_energy": [ctypes.POINTER(_AdmmState), vp, vp, vp, i32, i32, i64, dbl, dbl, ctypes.POINTER(_Result),
                                vp],
         }
@@ -199,6 +202,8 @@ class Params:
     use_graph: int = 1
     tol: float = 0.0
     check_every: int = 10
+    alg1_tau: float = 0.1
+    alg1_sigma: float = 1.25
 
     def c_struct(self) -> _Params:
         p = _Params()
@@ -260,11 +265,11 @@ class Context:
     def set_choice(self, key: str, mode: int, K: int = 0, rows: int = 0):
         """Apply one level-shape choice of an autotune report (key "<H>x<W>[w]i<iters>[p<sweeps>]") by hand."""
         import re
-        m = re.fullmatch(r"(\d+)x(\d+)(w?)i(\d+)(?:p(\d+))?", key)
+        m = re.fullmatch(r"(\d+)x(\d+)(w?)i(\d+)(?:p(\d+)|(a))?", key)
         if not m:
             raise ValueError(f"bad tuning key {key!r}")
         H, W, hw, it = int(m.group(1)), int(m.group(2)), m.group(3) == "w", int(m.group(4))
-        sweeps = int(m.group(5)) if m.group(5) else 0
+        sweeps = int(m.group(5)) if m.group(5) else (-1 if m.group(6) else 0)
         _check(lib().flow_tune_choice(self._h, H, W, int(hw), it, sweeps, int(mode), int(K), int(rows)))
 
     def memory_in_use(self):
@@ -494,7 +499,13 @@ def pdr_iter(state, Ix, Iy, It, params: Params, s_out=None):
     return state
 
 
-def pdr_tb(state, Ix, Iy, It, u0, v0, params: Params, iters, tile_h=16, tile_w=32):
+def alg1_tb(state, Ix, Iy, It, u0, v0, params: Params, iters, tile_h=16, tile_w=32):
+    """`iters` ALG1 iterations in one launch of its tile kernel (state planes as for pDR; y in the
+    y bar slots); returns (new state dict, s_out).  I_t is relative to (u0, v0)."""
+    return pdr_tb(state, Ix, Iy, It, u0, v0, params, iters, tile_h, tile_w, _entry="flow_op_alg1_tb")
+
+
+def pdr_tb(state, Ix, Iy, It, u0, v0, params: Params, iters, tile_h=16, tile_w=32, _entry="flow_op_pdr_tb"):
     """`iters` pDR iterations in one launch of the tile kernel; returns (new state dict, s_out).
     I_t is relative to (u0, v0)."""
     ref = _plane(state["u"], "u")
@@ -506,7 +517,7 @@ def pdr_tb(state, Ix, Iy, It, u0, v0, params: Params, iters, tile_h=16, tile_w=3
                  [("Ix", Ix), ("Iy", Iy), ("It", It), ("u0", u0), ("v0", v0), ("s_out", s_out)], "pdr_tb")
     st_in = _PdrState(*[state[k].data_ptr() if state.get(k) is not None else None for k in PDR_KEYS])
     st_out = _PdrState(*[out[k].data_ptr() if out.get(k) is not None else None for k in PDR_KEYS])
-    _check(lib().flow_op_pdr_tb(ctypes.byref(st_in), ctypes.byref(st_out), _ptr(s_out), _ptr(Ix), _ptr(Iy), _ptr(It),
+    _check(getattr(lib(), _entry)(ctypes.byref(st_in), ctypes.byref(st_out), _ptr(s_out), _ptr(Ix), _ptr(Iy), _ptr(It),
                                 _ptr(u0), _ptr(v0), H, W, ref.stride(0), ctypes.byref(params.c_struct()), int(iters),
                                 int(tile_h), int(tile_w), _stream()))
     return out, s_out

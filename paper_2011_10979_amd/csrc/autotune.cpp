@@ -69,17 +69,22 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
     for (const LevelPlanes& L : Ls) {
         st = clear_level(L, s);
         if (st != FLOW_OK) break;
-        if (p->scheme == FLOW_PDR) {
-            // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, or a resident level
+        if (pd_state(*p)) {
+            // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, or a resident level;
+            // ALG1: tiles with K = 1, 2, 4, 8, or a resident level
+            const bool alg1 = p->scheme == FLOW_ALG1;
             struct PCand { TunedChoice c; PdrTbPlan T; };
             std::vector<PCand> cands;
-            PCand three{};
-            three.c.mode = 1;
-            cands.push_back(three);
+            if (!alg1) {
+                PCand three{};
+                three.c.mode = 1;
+                cands.push_back(three);
+            }
             bool resident_done = false;
+            const std::vector<int> ks = alg1 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 3};
             for (int nt : {1024, 512})
-            for (int K : {1, 2, 3}) {
-                PdrTbPlan T = plan_pdr_tiles(L.H, L.W, hw, p->gs_sweeps, K, 0, nt);
+            for (int K : ks) {
+                PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo_per_iter(*p), K, 0, nt);
                 if (!T.tb) continue;
                 if (T.resident) {
                     if (resident_done) continue;
@@ -118,7 +123,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
                     bestc = c.c;
                 }
             }
-            const std::string key = tune_key(L.H, L.W, hw, p->iters) + "p" + std::to_string(p->gs_sweeps);
+            const std::string key = pd_tune_key(L.H, L.W, *p);
             ctx->tuned[key] = bestc;
             rep << (first_level ? "" : ", ") << "\"" << key << "\": {\"choice\": {\"mode\": " << bestc.mode
                 << ", \"K\": " << bestc.K << ", \"rows\": 0, \"us_per_iter\": " << bestc.us_per_iter
@@ -207,7 +212,8 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     if (mode < 1 || mode > 7) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6, 7 (tiles) or 5 (pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
-    if (pdr_sweeps < 0) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= 0");
+    if (pdr_sweeps < -1) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= -1 (-1: ALG1)");
+    if (pdr_sweeps == -1 && mode != 5 && mode != 6) return fail(FLOW_E_INVAL, "ALG1 modes: 5 / 6 (tiles of 1024 / 512 threads)");
     if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6)
         return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads)");
     if (pdr_sweeps == 0 && mode == 5) return fail(FLOW_E_INVAL, "mode 5 is a pDR mode");
@@ -218,6 +224,7 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     c.rows = rows;
     std::string key = tune_key(H, W, has_w != 0, iters);
     if (pdr_sweeps > 0) key += "p" + std::to_string(pdr_sweeps);
+    if (pdr_sweeps < 0) key += "a";
     ctx->tuned[key] = c;
     ctx->tune_epoch++;
     ctx->drop_graphs();

@@ -479,8 +479,8 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
     if (n == 0) return FLOW_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    if (p->scheme == FLOW_PDR || p->tol > 0) {
-        // pDR and stopping tests: plain solves in turn
+    if (pd_state(*p) || p->tol > 0) {
+        // pDR, ALG1 and stopping tests: plain solves in turn
         for (int32_t k = 0; k < n; ++k) {
             flow_params pk = *p;
             if (pairs[k].levels > 0) pk.levels = pairs[k].levels;
@@ -567,7 +567,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
     if (st != FLOW_OK) return st;
     st = validate_pairs(n, pairs, *p);
     if (st != FLOW_OK) return st;
-    if (n == 0 || p->scheme == FLOW_PDR || p->iters < 1) return FLOW_OK;
+    if (n == 0 || pd_state(*p) || p->iters < 1) return FLOW_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     st = prepare(ctx, n, pairs, *p);

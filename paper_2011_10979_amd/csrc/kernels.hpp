@@ -106,6 +106,8 @@ struct PdrTbArgs {
 };
 int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
+// ALG1 (primal-dual) tiles on the same argument block: sigma / tau are its primal / dual steps
+void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 
 void launch_pdr_rhs_red(const PdrArgs& a, bool has_w, hipStream_t s);
 void launch_pdr_colour(const PdrArgs& a, bool has_w, hipStream_t s);

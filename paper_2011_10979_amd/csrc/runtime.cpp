@@ -67,7 +67,7 @@ std::vector<std::pair<int, int>> level_shapes(int H, int W, int levels) {
 flow_status validate(const flow_params* p) {
     if (!p) return fail(FLOW_E_INVAL, "params is NULL");
     if (p->struct_size != sizeof(flow_params)) return fail(FLOW_E_INVAL, "params.struct_size mismatch");
-    if (p->scheme < FLOW_PADMM || p->scheme > FLOW_PDR) return fail(FLOW_E_INVAL, "unknown scheme");
+    if (p->scheme < FLOW_PADMM || p->scheme > FLOW_ALG1) return fail(FLOW_E_INVAL, "unknown scheme");
     if (!(p->lambda > 0)) return fail(FLOW_E_INVAL, "lambda must be > 0");
     if (!(p->beta >= 0)) return fail(FLOW_E_INVAL, "beta must be >= 0");
     if (!(p->c > 0)) return fail(FLOW_E_INVAL, "c must be > 0");
@@ -76,6 +76,8 @@ flow_status validate(const flow_params* p) {
     if (p->scheme == FLOW_RPADMM2 && !(p->relax > 0 && p->relax < 2.0))
         return fail(FLOW_E_INVAL, "rpADMMII relaxation rho must lie in (0, 2)");
     if (!(p->sigma > 0) || !(p->tau > 0)) return fail(FLOW_E_INVAL, "sigma and tau must be > 0");
+    if (p->scheme == FLOW_ALG1 && !(p->alg1_tau > 0 && p->alg1_sigma > 0 && 8.0 * p->alg1_tau * p->alg1_sigma <= 1.0 + 1e-9))
+        return fail(FLOW_E_INVAL, "ALG1 steps must be > 0 with 8 alg1_tau alg1_sigma <= 1");
     if (p->gs_sweeps < 1) return fail(FLOW_E_INVAL, "gs_sweeps must be >= 1");
     if (!(p->intensity_scale > 0)) return fail(FLOW_E_INVAL, "intensity_scale must be > 0");
     if (p->levels < 1 || p->levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "levels out of range");
@@ -100,7 +102,7 @@ flow_status validate_shape(int H, int W, int64_t ld, int levels) {
 // ---------------------------------------------------------------------------------------------
 size_t layout_bytes(int H, int W, const flow_params& p) {
     const bool f16 = p.storage == FLOW_STORE_F16;
-    const bool pdr = p.scheme == FLOW_PDR;
+    const bool pdr = pd_state(p);
     const bool hw = p.beta > 0;
     size_t total = 0;
     for (auto [h, w] : level_shapes(H, W, p.levels)) {
@@ -116,7 +118,7 @@ size_t layout_bytes(int H, int W, const flow_params& p) {
 
 flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, std::vector<LevelPlanes>& out) {
     const bool f16 = p.storage == FLOW_STORE_F16;
-    const bool pdr = p.scheme == FLOW_PDR;
+    const bool pdr = pd_state(p);
     const bool hw = p.beta > 0;
     out.clear();
     char* cur = (char*)arena.base;
@@ -222,7 +224,13 @@ PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p, int cur) {
     a.Ix = L.Ix; a.Iy = L.Iy; a.It = L.It;
     a.u0 = L.U0[0]; a.v0 = L.U0[1];
     a.H = L.H; a.W = L.W; a.ld = L.ld;
-    a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    if (p.scheme == FLOW_ALG1) {
+        a.sigma = (float)p.alg1_sigma;
+        a.tau = (float)p.alg1_tau;
+        a.stt = 0.f;
+    } else {
+        a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    }
     a.lam = (float)p.lambda; a.beta = (float)p.beta;
     return a;
 }
@@ -244,7 +252,7 @@ void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s) {
 // Flow component k (0 = w, 1 = u, 2 = v) of a level: pDR keeps X; the ADMM family keeps the
 // flow in U0 (plus the pending increment, see level_inc) and w in its current state buffer `cur`.
 const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int cur) {
-    if (p.scheme == FLOW_PDR) return L.Xs[cur][k];
+    if (pd_state(p)) return L.Xs[cur][k];
     if (k > 0) return L.U0[k - 1];
     return L.st[cur][0];
 }
@@ -252,19 +260,19 @@ const float* level_flow(const LevelPlanes& L, const flow_params& p, int k, int c
 // Pending increment of flow component k (ADMM family, u and v: the last warp's du, dv in state
 // buffer `cur`, not yet added to U0); nullptr where the flow is stored whole.
 const float* level_inc(const LevelPlanes& L, const flow_params& p, int k, int cur) {
-    if (p.scheme == FLOW_PDR || k == 0) return nullptr;
+    if (pd_state(p) || k == 0) return nullptr;
     return L.st[cur][k];
 }
 
 EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scratch& sc) {
     EnergyArgs e{};
-    if (p.scheme == FLOW_PDR) {
+    if (pd_state(p)) {
         float* const* X = L.Xs[cur];
         float* const* yb = L.ybs[cur];
         e.w = X[0]; e.u = X[1]; e.v = X[2];
         e.px = yb[0]; e.py = yb[1]; e.q1x = yb[2]; e.q1y = yb[3]; e.q2x = yb[4]; e.q2y = yb[5];
         e.s = L.s_out;
-        e.pdr_tau = (float)p.tau;
+        e.pdr_tau = p.scheme == FLOW_PDR ? (float)p.tau : 0.f;   // ALG1 keeps y itself
         e.lu0 = L.U0[0]; e.lv0 = L.U0[1];
     } else {
         // flow = U0 + the warp's increment (not yet committed)
@@ -285,7 +293,7 @@ flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratc
                       const std::map<std::string, TunedChoice>* tuned) {
     out.levels.clear();
     out.pdr.clear();
-    if (p.scheme == FLOW_PDR) {
+    if (pd_state(p)) {
         for (const LevelPlanes& L : Ls) out.pdr.push_back(plan_pdr_level(L.H, L.W, p, tuned));
         return FLOW_OK;
     }
@@ -354,24 +362,36 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
 int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512
 int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
 constexpr int kPdrDefaultK = 2;
+constexpr int kAlg1DefaultK = 4;
+
+std::string pd_tune_key(int H, int W, const flow_params& p) {
+    const std::string k = tune_key(H, W, p.beta > 0, p.iters);
+    return p.scheme == FLOW_ALG1 ? k + "a" : k + "p" + std::to_string(p.gs_sweeps);
+}
+
+// Halo per iteration of the tile kernels with (X, X bar, y) state, summed over both sides of an axis.
+int pd_halo_per_iter(const flow_params& p) { return p.scheme == FLOW_ALG1 ? 2 : 4 * p.gs_sweeps + 3; }
 
 PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std::string, TunedChoice>* tuned) {
     const bool hw = p.beta > 0;
-    int mode = g_pdr_mode, K = g_pdr_k;
+    const bool alg1 = p.scheme == FLOW_ALG1;
+    int mode = alg1 ? 0 : g_pdr_mode, K = alg1 ? 0 : g_pdr_k;
     if (mode == 0 && tuned) {
-        auto it = tuned->find(tune_key(H, W, hw, p.iters) + "p" + std::to_string(p.gs_sweeps));
+        auto it = tuned->find(pd_tune_key(H, W, p));
         if (it != tuned->end()) {
             mode = it->second.mode;
             K = it->second.K;
         }
     }
+    if (alg1 && mode == 1) mode = 5;                 // ALG1 has no three-pass form
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
     const int nt = mode == 6 ? 512 : 1024;
-    PdrTbPlan T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, K > 0 ? K : kPdrDefaultK, 0, nt);
+    const int kdef = alg1 ? kAlg1DefaultK : kPdrDefaultK;
+    const int hk = pd_halo_per_iter(p);
+    PdrTbPlan T = plan_pd_tiles(H, W, hw, hk, K > 0 ? K : kdef, 0, nt);
     if (T.resident && K == 0) T.K = p.iters;        // the whole warp in one launch
     if (!T.tb) {                                     // the halo does not fit: fewer iterations per launch
-        for (int k = (K > 0 ? K : kPdrDefaultK) - 1; k >= 1 && !T.tb; --k)
-            T = plan_pdr_tiles(H, W, hw, p.gs_sweeps, k, 0, nt);
+        for (int k = (K > 0 ? K : kdef) - 1; k >= 1 && !T.tb; --k) T = plan_pd_tiles(H, W, hw, hk, k, 0, nt);
     }
     return T;
 }
@@ -399,19 +419,26 @@ PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPla
     a.th = T.th; a.tw = T.tw;
     a.ntx = (L.W + T.tw - 1) / T.tw;
     a.ntiles = a.ntx * ((L.H + T.th - 1) / T.th);
-    a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    if (p.scheme == FLOW_ALG1) {
+        a.sigma = (float)p.alg1_sigma;
+        a.tau = (float)p.alg1_tau;
+        a.stt = 0.f;
+    } else {
+        a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
+    }
     a.lam = (float)p.lambda; a.beta = (float)p.beta;
     return a;
 }
 
-// `n` pDR iterations of level L on K-iteration tiles starting from state set `cur`; returns the
-// set holding the result.
+// `n` pDR or ALG1 iterations of level L on K-iteration tiles starting from state set `cur`; returns
+// the set holding the result.
 int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int64_t n,
                       hipStream_t s, int64_t* launches) {
     int64_t t = 0;
     while (t < n) {
         const int kk = (int)std::min<int64_t>(T.resident ? n - t : T.K, n - t);
-        launch_pdr_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, T.nt, s);
+        if (p.scheme == FLOW_ALG1) launch_alg1_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, T.nt, s);
+        else launch_pdr_tb(pdr_tb_args(L, p, T, cur, kk), p.beta > 0, T.nt, s);
         if (launches) ++*launches;
         cur ^= 1;
         t += kk;
@@ -424,7 +451,7 @@ int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPla
 flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, hipStream_t s,
                          WarpTimers* timers, StopTest* stop, const SolvePlan* plan) {
     const bool f16 = p.storage == FLOW_STORE_F16;
-    const bool pdr = p.scheme == FLOW_PDR;
+    const bool pdr = pd_state(p);      // pDR or ALG1: state (X, X bar, y)
     const bool hw = p.beta > 0;
     const int nl = (int)Ls.size();
     for (int l = 0; l < nl; ++l) {
@@ -515,6 +542,8 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
                                                                                                   : nullptr;
                     if (T) {
                         cur = enqueue_pdr_tiles(L, p, *T, cur, chunk, s, &nk);
+                    } else if (p.scheme == FLOW_ALG1) {
+                        return fail(FLOW_E_INVAL, "no ALG1 tile plan for this level");
                     } else {
                         for (int64_t t = 0; t < chunk; ++t) enqueue_pdr_iter(pdr_args(L, p, cur), p.gs_sweeps, hw, s);
                         nk = chunk * (2 * p.gs_sweeps + 1);
@@ -571,6 +600,8 @@ flow_status flow_params_default(flow_params* p) {
     p->levels = 5;
     p->warps = 5;
     p->iters = 50;
+    p->alg1_tau = 0.1;
+    p->alg1_sigma = 1.25;
     p->storage = FLOW_STORE_F32;
     p->use_graph = 1;
     p->tol = 0.0;
@@ -903,19 +934,22 @@ flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work
     return FLOW_OK;
 }
 
-flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
-                           const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
-                           int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
-                           void* stream) {
+}  // extern "C"
+
+// K iterations of the pDR or ALG1 tile kernel (per pp.scheme) from `in` to `out` for the operator entries.
+static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                            int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                            void* stream) {
     flow_status v = validate(p);
     if (v != FLOW_OK) return v;
     if (!in || !out || !s_out || !Ix || !Iy || !It || !u0 || !v0) return fail(FLOW_E_INVAL, "NULL pointer");
     if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     const bool hw = p->beta > 0;
-    const int64_t halo = (int64_t)(4 * p->gs_sweeps + 3) * iters;
+    const int64_t halo = (int64_t)pd_halo_per_iter(*p) * iters;
     if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw, 1024))
-        return fail(FLOW_E_INVAL, "tile plus halo exceeds the pDR tile kernel's capacity");
+        return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,
                             in->qb1x, in->qb1y, in->qb2x, in->qb2y};
     const float* outs[12] = {out->w, out->u, out->v, out->wb, out->ub, out->vb, out->pbx, out->pby,
@@ -950,10 +984,34 @@ flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, 
     T.th = tile_h;
     T.tw = tile_w;
     hipStream_t s = (hipStream_t)stream;
-    launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);   // reads set 0 (in), writes set 1 (out)
+    // reads set 0 (in), writes set 1 (out)
+    if (p->scheme == FLOW_ALG1) launch_alg1_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);
+    else launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return FLOW_OK;
+}
+
+extern "C" {
+
+flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                           const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                           int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                           void* stream) {
+    if (!p) return fail(FLOW_E_INVAL, "params is NULL");
+    flow_params q = *p;
+    q.scheme = FLOW_PDR;
+    return op_pd_tb(in, out, s_out, Ix, Iy, It, u0, v0, H, W, ld, &q, iters, tile_h, tile_w, stream);
+}
+
+flow_status flow_op_alg1_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
+                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
+                            int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
+                            void* stream) {
+    if (!p) return fail(FLOW_E_INVAL, "params is NULL");
+    flow_params q = *p;
+    q.scheme = FLOW_ALG1;
+    return op_pd_tb(in, out, s_out, Ix, Iy, It, u0, v0, H, W, ld, &q, iters, tile_h, tile_w, stream);
 }
 
 flow_status flow_op_energy(const flow_admm_state* st, const float* Ix, const float* Iy, const float* It,

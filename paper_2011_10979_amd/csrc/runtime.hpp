@@ -15,6 +15,8 @@
 namespace flowmi {
 
 flow_status fail(flow_status st, const std::string& msg);
+// Schemes whose state is (X, X bar, y) in the pDR planes: pDR and ALG1.
+inline bool pd_state(const flow_params& p) { return p.scheme == FLOW_PDR || p.scheme == FLOW_ALG1; }
 flow_status hip_fail(hipError_t e, const char* what);
 int64_t pitch_of(int W);
 flow_status check_extent(const void* ptr, int H, int W, int64_t ld, size_t elem, const char* name);
@@ -103,7 +105,9 @@ struct PdrTbPlan {
     int K = 1;                 // iterations per launch
     int th = 0, tw = 0;
 };
-PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target, int nt = 1024);
+PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo_per_iter, int K, int ew_target, int nt = 1024);
+std::string pd_tune_key(int H, int W, const flow_params& p);
+int pd_halo_per_iter(const flow_params& p);
 extern int g_pdr_mode;
 extern int g_pdr_k;
 

@@ -452,7 +452,7 @@ flow_status flow_server_create(flow_ctx* ctx, const flow_params* p, size_t hbm_b
     *out = nullptr;
     flow_status r = validate(p);
     if (r != FLOW_OK) return r;
-    if (p->scheme == FLOW_PDR) return fail(FLOW_E_INVAL, "the serving engine runs the ADMM family (pADMM, rpADMMII)");
+    if (pd_state(*p)) return fail(FLOW_E_INVAL, "the serving engine runs the ADMM family (pADMM, rpADMMII)");
     if (p->tol > 0) return fail(FLOW_E_INVAL, "the serving engine runs a fixed iteration count (tol = 0)");
     if (max_active < 1 || max_active > 4096) return fail(FLOW_E_INVAL, "max_active must be in [1, 4096]");
     if (hbm_budget == 0) hbm_budget = (size_t)8 << 30;

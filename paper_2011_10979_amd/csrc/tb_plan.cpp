@@ -69,9 +69,10 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
     return P;
 }
 
-PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target, int nt) {
-    // output tile th x tw whose extended region (halo (2n+1)K top / left, (2n+2)K bottom / right,
-    // clipped to the image) fits the kernel's capacity; the whole level if it fits
+PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo_per_iter, int K, int ew_target, int nt) {
+    // output tile th x tw whose extended region (halo_per_iter x K per axis over both sides, e.g.
+    // pDR (2n+1)K + (2n+2)K, ALG1 K + K; clipped to the image) fits the kernel's capacity; the whole
+    // level if it fits
     PdrTbPlan P;
     P.nt = nt;
     const int cap = pdr_tb_capacity(hw, nt);
@@ -82,8 +83,8 @@ PdrTbPlan plan_pdr_tiles(int H, int W, bool hw, int sweeps, int K, int ew_target
         P.tw = W;
         return P;
     }
-    const int halo = (4 * sweeps + 3) * K;
-    if (ew_target <= 0) ew_target = 64;
+    const int halo = halo_per_iter * K;
+    if (ew_target <= 0) ew_target = nt == 512 ? 32 : 64;
     const int ew = std::min(W, std::max(ew_target, halo + 8));
     const int tw = (ew >= W) ? W : ew - halo;
     const int ext_w = std::min(W, tw + halo);

@@ -183,6 +183,34 @@ def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
         assert np.array_equal(to_np(g[k]), f32(st[k]))
 
 
+@pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 9), ((37, 130), (8, 30), 4), ((101, 250), (12, 20), 1),
+                                          ((40, 45), (40, 45), 20), ((64, 64), (10, 18), 6), ((33, 47), (5, 9), 3)])
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_alg1_tiles_match_k_oracle_steps(shape, tile, K, beta):
+    """K ALG1 iterations of its tile kernel (halo K on each side, ragged tiles, a resident level)
+    against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
+    print_case("alg1_tb", shape=shape, tile=tile, K=K, beta=beta)
+    if min(shape[0], tile[0] + 2 * K) * min(shape[1], tile[1] + 2 * K) > 2048:
+        pytest.skip("tile plus halo exceeds the kernel capacity")
+    rng = np.random.default_rng(zlib.crc32(repr(("alg1tb", shape, tile, K, beta)).encode()))
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0)
+    ref = dict(st)
+    for _ in range(K):
+        ref, duals = schemes.alg1_step(ref, L, beta, 0.05, 0.1, 1.25)
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    out, s_out = fm.alg1_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
+                            fm.Params(scheme="alg1", beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    tol = 1e-4 * max(1, K)
+    for k in keys:
+        assert max_abs(to_np(out[k]), ref[k]) < tol, (k, max_abs(to_np(out[k]), ref[k]))
+    assert max_abs(to_np(s_out), duals["s"]) < tol
+
+
 @pytest.mark.parametrize("shape", [(2, 2), (70, 130), (240, 320)])
 @pytest.mark.parametrize("beta", [0.0, 0.05])
 def test_energy_terms(shape, beta):

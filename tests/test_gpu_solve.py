@@ -89,7 +89,8 @@ def report(name, du, dv):
 
 
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("padmm", 1.618, 0.0), ("rpadmm2", 1.9, 0.0),
-                                               ("padmm", 1.0, 0.05), ("pdr", 1.0, 0.0), ("pdr", 1.0, 0.05)])
+                                               ("padmm", 1.0, 0.05), ("pdr", 1.0, 0.0), ("pdr", 1.0, 0.05),
+                                               ("alg1", 1.0, 0.0), ("alg1", 1.0, 0.05)])
 def test_translation_single_scale(ctx, scheme, relax, beta):
     """64x64 translation pair, one level, one warp, 200 iterations (the single-scale workload)."""
     print(f"[case] translation {scheme} {relax} {beta}", flush=True)
@@ -100,12 +101,12 @@ def test_translation_single_scale(ctx, scheme, relax, beta):
     assert abs(res["energy"] - ref["energy"]) <= 1e-5 * ref["energy"]
     assert abs(res["gap"] - ref["gap"]) <= 1e-5 * ref["energy"] + 1e-3
     # sanity on the motion itself (pDR moves more slowly per iteration than the ADMM family)
-    slack = 0.06 if scheme == "pdr" else 0.03
+    slack = 0.06 if scheme in ("pdr", "alg1") else 0.03
     assert abs(u.mean() - 0.3) < slack and abs(v.mean() + 0.2) < slack
 
 
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05), ("pdr", 1.0, 0.0),
-                                               ("pdr", 1.0, 0.05)])
+                                               ("pdr", 1.0, 0.05), ("alg1", 1.0, 0.0), ("alg1", 1.0, 0.05)])
 def test_multilevel_small(ctx, scheme, relax, beta):
     print(f"[case] multilevel 96x128 {scheme} {beta}", flush=True)
     pair = synth.vga_pair(seed=5, H=96, W=128)
@@ -235,3 +236,19 @@ def test_every_pdr_kernel_mode_keeps_parity(ctx, mode, k, beta):
     finally:
         fm.set_tuning("pdr_mode", 0)
         fm.set_tuning("pdr_k", 0)
+
+
+@pytest.mark.parametrize("mode,k,beta", [(5, 1, 0.0), (5, 4, 0.0), (6, 2, 0.05), (6, 8, 0.0)])
+def test_every_alg1_kernel_mode_keeps_parity(ctx, mode, k, beta):
+    """ALG1 with tiles of 1024 and 512 threads and several K (coarse levels resident) meets the bar."""
+    print(f"[case] forced ALG1 mode {mode} K {k} beta {beta}", flush=True)
+    c = fm.Context(0)
+    try:
+        pair = synth.vga_pair(seed=6, H=120, W=150)
+        p = fm.Params(scheme="alg1", beta=beta, levels=3, warps=2, iters=30)
+        shapes = [(120, 150), (60, 75), (30, 38)]
+        for H, W in shapes:
+            c.set_choice(f"{H}x{W}{'w' if beta > 0 else ''}i30a", mode, k)
+        conditioned_check(c, pair, f"alg1 mode {mode} K {k}", scheme="alg1", beta=beta, levels=3, warps=2, iters=30)
+    finally:
+        c.close()
