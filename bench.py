@@ -29,6 +29,9 @@ Other modes:
                     probabilities 0.3, 0.3, 0.2, 0.1, 0.1), 2000 requests after 200 warm-up ones, served
                     by the continuous-batching engine (8 GiB budget); value = completed pairs/s, with
                     p50 / p99 latency; the same trace through a one-at-a-time plain-solve server beside it
+  --mode compare    every scheme of Sec. 4 (pADMM, rpADMMI, rpADMMII, Zach-pADMM, pDR, ALG1) on the
+                    same synthetic pair (--pair vga or hd): time per solve, endpoint / angular error
+                    against the ground-truth motion, energy and gap at equal iteration counts
   --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
                                       them from F instead of tuning (for profiler runs)
   --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
@@ -448,6 +451,67 @@ def run_serve(args):
     ctx.close()
 
 
+COMPARE = [  # (label, scheme, relax, beta): the schemes and parameters of Sec. 4 / Table 1
+    ("pADMM", "padmm", 1.0, 0.05), ("rpADMMI r=1.618", "padmm", 1.618, 0.05), ("rpADMMII rho=1.9", "rpadmm2", 1.9, 0.05),
+    ("Zach-pADMM (beta=0)", "padmm", 1.0, 0.0), ("pDR", "pdr", 1.0, 0.05), ("ALG1", "alg1", 1.0, 0.05)]
+
+
+def run_compare(args):
+    """Every scheme of Sec. 4 on the same synthetic pair at the same iteration counts: time per solve
+    on the GPU (autotuned, graph replay) and the accuracy against the ground-truth motion (mean
+    endpoint and angular error), with the final warp's energy and gap."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2011_10979_amd as fm
+    if args.pair == "hd":
+        pair = synth.hd_pair(seed=2)
+        levels = 6
+    else:
+        pair = synth.vga_pair(seed=1, H=args.H, W=args.W)
+        levels = args.levels
+    H, W = pair.I0.shape
+    dev = torch.device("cuda:0")
+    I0 = torch.from_numpy(pair.I0.astype(np.float32)).to(dev)
+    I1 = torch.from_numpy(pair.I1.astype(np.float32)).to(dev)
+    px = 0
+    h, w = H, W
+    for _ in range(levels):
+        px += h * w
+        h, w = (h + 1) // 2, (w + 1) // 2
+    rows = []
+    for label, scheme, relax, beta in COMPARE:
+        ctx = fm.Context(0)
+        p = fm.Params(scheme=scheme, relax=relax, beta=beta, levels=levels, warps=args.warps, iters=args.iters,
+                      use_graph=1)
+        ctx.autotune(H, W, p)
+        for _ in range(2):
+            u, v, res = ctx.solve(I0, I1, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u, v, res = ctx.solve(I0, I1, p)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        un, vn = u.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+        epe = float(np.hypot(un - pair.u, vn - pair.v).mean())
+        cosang = (un * pair.u + vn * pair.v + 1.0) / (np.sqrt(un ** 2 + vn ** 2 + 1.0) * np.sqrt(pair.u ** 2 + pair.v ** 2 + 1.0))
+        aae = float(np.degrees(np.arccos(np.clip(cosang, -1.0, 1.0))).mean())
+        rows.append({"scheme": label, "beta": beta, "ms_per_solve": round(ms, 3),
+                     "Gpx_iter_s": round(px * args.warps * args.iters / (ms * 1e-3) / 1e9, 2),
+                     "epe_px": round(epe, 4), "aae_deg": round(aae, 3), "energy": res["energy"], "gap": res["gap"]})
+        print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+        ctx.close()
+    ref = next(r for r in rows if r["scheme"] == "pADMM")
+    for r in rows:
+        r["time_vs_pADMM"] = round(r["ms_per_solve"] / ref["ms_per_solve"], 3)
+    line = {"metric": "scheme comparison (time per solve, accuracy against the synthetic ground truth)",
+            "config": {"workload": f"{W}x{H} pair ({args.pair}), {levels} levels x {args.warps} warps x {args.iters} "
+                                   f"iterations, every scheme of Sec. 4", "data": "synthetic"},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def calibrate_copy(mb, steps):
     """Plain device-to-device copies of `mb` MiB: the kernel of known traffic (mb MiB read and mb
     MiB written per launch) that scales the HBM counters."""
@@ -486,7 +550,8 @@ def main():
     ap.add_argument("--save-tuning", default=None)
     ap.add_argument("--load-tuning", default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "compare"])
+    ap.add_argument("--pair", default="vga", choices=["vga", "hd"])
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -516,6 +581,9 @@ def main():
         return
     if args.mode == "serve":
         run_serve(args)
+        return
+    if args.mode == "compare":
+        run_compare(args)
         return
 
     dev = torch.device("cuda:0")
