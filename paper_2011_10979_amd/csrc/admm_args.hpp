@@ -38,6 +38,12 @@ constexpr int kTbPptW = 4;           // with the w / p block
 constexpr int kTbPptL = 4;           // 1024 threads (at most 128 VGPRs per thread)
 constexpr int kTbPptLW = 3;
 constexpr int kTbPptSmall = 2;       // 1024 threads on small tiles (work-group size code 1025)
+// Halo of a K-iteration tile: per iteration the dual field q reaches one cell further in every
+// direction and the multipliers follow q's divergence (left / above) at the end of the iteration,
+// so after K iterations the iterate of an output pixel depends on the launch's input within K + 1
+// rows / columns above and to the left and K below and to the right.
+constexpr int tb_halo_lo(int K) { return K + 1; }
+constexpr int tb_halo_hi(int K) { return K; }
 struct TbTile {
     int level;                       // index of the (pair, level) descriptor
     int y0, x0, th, tw;              // output tile
@@ -55,7 +61,7 @@ struct TbArgs {
     int ntiles;
     const TbLevel* levels;           // two descriptors per (pair, level): [2 * id + dir]
     int dir;                         // which ping-pong direction this launch uses
-    int K;                           // iterations of this launch (halo = 2K top/left, K bottom/right)
+    int K;                           // iterations of this launch (halo K + 1 top/left, K bottom/right)
     int at_slot;                     // a~ slot of the current warp
     unsigned* queue;                 // work counters (nullptr: tiles from the work-group index)
     unsigned queue_base;             // counter value at the start of this launch

@@ -1,20 +1,22 @@
 // Temporally blocked iterations of the preconditioned dual ADMM family (Sec. 3.1.1) on gfx950.
 //
 // One work-group owns an output tile of one pyramid level (of one pair) and advances it by K
-// iterations in a single launch.  One iteration makes every value depend on the previous
-// iterate within 2 rows / columns above and to the left and 1 below and to the right (g needs q
-// to the left and above, y+ needs g to the right and below, the output needs y+ to the left and
-// above), so the tile is loaded with a halo of 2K (top, left) and K (bottom, right) and the valid
-// region shrinks by that much over the K iterations; on sides where the tile meets the image
-// border there is no halo and the discrete boundary rules of Sec. 2.2 apply exactly.  Halo
-// pixels are recomputed by the neighbouring tiles; their values here only feed other halo pixels.
+// iterations in a single launch.  g needs q to the left and above, y+ needs g to the right and
+// below, and the multipliers need div y+ (left and above), which is also the divergence the next
+// g takes.  So the new q depends on the previous iterate within one cell in every direction, and
+// the multipliers one cell further to the left and above: after K iterations the valid region has
+// shrunk by K + 1 rows / columns at the top and left and K at the bottom and right, and the tile
+// is loaded with that halo; on sides where the tile meets the image border there is no halo and
+// the discrete boundary rules of Sec. 2.2 apply exactly.  Halo pixels are recomputed by the
+// neighbouring tiles; their values here only feed other halo pixels.
 //
 // Placement: q (and p), whose neighbours the divergence reads, and g, whose neighbours the
 // gradient reads, live in LDS; everything only read at its own pixel (the increment du, dv, s,
 // w and the linearisation I_x, I_y, I_t, u0, v0) lives in registers of the thread that owns the
 // pixel for the whole launch.  Per iteration:  A: g from q (LDS) -> LDS;  barrier;  B: y+ from
 // g (LDS), written over q;  barrier;  C: div y+, s+, multipliers (registers), then A of the next
-// iteration (C only reads y+, A only writes g, so they need no barrier between them).
+// iteration from the divergence C has just taken (C only reads y+, A only writes g, so they need
+// no barrier between them).
 //
 // Work distribution: one work-group per tile of one level (direct), per entry of a tile table
 // (batched pairs: each tile names its pair-level descriptor), or a persistent grid that pulls
@@ -54,7 +56,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         const int64_t ld = L.ld;
         const int K = a.K;
         // extended region: output tile plus halo, clipped to the image
-        const int ey0 = max(T.y0 - 2 * K, 0), ex0 = max(T.x0 - 2 * K, 0);
+        const int ey0 = max(T.y0 - tb_halo_lo(K), 0), ex0 = max(T.x0 - tb_halo_lo(K), 0);
         const int ey1 = min(T.y0 + T.th + K, H), ex1 = min(T.x0 + T.tw + K, W);
         const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;
         const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);   // a~ >= ||M_s||, floored
@@ -122,24 +124,21 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
             return mx(k) * fx[e] - (hl(k) ? l : 0.f) + my(k) * fy[e] - (hu(k) ? u : 0.f);
         };
 
-        // phase A (g) for the thread's slots
-        auto phase_a = [&]() {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!live(k)) continue;
-                const int e = tid + k * NT;
-                const float dq1 = divk(sq1x, sq1y, k, e);
-                const float dq2 = divk(sq2x, sq2y, k, e);
-                sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
-                sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
-                if constexpr (HAS_W) {
-                    const float dp = divk(spx, spy, k, e);
-                    sgw[e] = ww[k] + c * (dp - beta * ss[k]);
-                }
-            }
+        // phase A (g) for slot k from the divergences of the current dual field
+        auto g_out = [&](int k, int e, float dq1, float dq2, float dp) {
+            sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
+            sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
+            if constexpr (HAS_W) sgw[e] = ww[k] + c * (dp - beta * ss[k]);
         };
 
-        phase_a();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!live(k)) continue;
+            const int e = tid + k * NT;
+            float dp = 0.f;
+            if constexpr (HAS_W) dp = divk(spx, spy, k, e);
+            g_out(k, e, divk(sq1x, sq1y, k, e), divk(sq2x, sq2y, k, e), dp);
+        }
         for (int it = 0; it < K; ++it) {
             __syncthreads();
             // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own slot)
@@ -192,8 +191,8 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;
                 if constexpr (HAS_W) ww[k] = ww[k] + a.cA * dnp - beta * ms;
                 ss[k] = sn;
+                if (it + 1 < K) g_out(k, e, dn1, dn2, dnp);   // phase A of the next iteration
             }
-            if (it + 1 < K) phase_a();
         }
 
         // write the output tile

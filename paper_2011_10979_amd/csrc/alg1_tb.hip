@@ -36,8 +36,9 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
     const int H = L.H, W = L.W;
     const int64_t ld = L.ld;
     const int K = a.K;
-    const int ey0 = max(y0 - K, 0), ex0 = max(x0 - K, 0);
-    const int ey1 = min(y0 + th + K, H), ex1 = min(x0 + tw + K, W);
+    const int hk = alg1_halo(K);
+    const int ey0 = max(y0 - hk, 0), ex0 = max(x0 - hk, 0);
+    const int ey1 = min(y0 + th + hk, H), ex1 = min(x0 + tw + hk, W);
     const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;
     const float sigma = a.sigma, tau = a.tau, lam = a.lam, beta = a.beta;
     const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);

@@ -84,7 +84,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             const std::vector<int> ks = alg1 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 3};
             for (int nt : {1024, 512})
             for (int K : ks) {
-                PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo_per_iter(*p), K, 0, nt);
+                PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(*p, K), K, 0, nt);
                 if (!T.tb) continue;
                 if (T.resident) {
                     if (resident_done) continue;

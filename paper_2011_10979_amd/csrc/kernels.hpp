@@ -90,6 +90,14 @@ struct PdrArgs {
 // level).  Component order: x / x bar (u, v, w), y (q1x, q1y, q2x, q2y, p_x, p_y).
 constexpr int kPdrPpt = 2;           // pixels per thread (1024 or 512 threads)
 constexpr int kPdrPptW = 2;
+// Halo of a K-iteration pDR tile with n symmetric sweeps: each of the 2n + 1 half sweeps reaches one
+// cell in every direction, b takes div y bar (left / above) before them and the dual update grad X+
+// (right / below) after them, so X and X bar depend on the launch's input within (2n + 1) K cells
+// on every side and y bar one cell further below and to the right.
+constexpr int pdr_halo_lo(int n, int K) { return (2 * n + 1) * K; }
+constexpr int pdr_halo_hi(int n, int K) { return (2 * n + 1) * K + 1; }
+// ALG1: y+ reads X bar to the right / below, X+ reads y+ to the left / above: K cells on every side.
+constexpr int alg1_halo(int K) { return K; }
 struct PdrTbLevel {
     const float* x_in[3]; const float* xb_in[3]; const float* y_in[6];
     float* x_out[3]; float* xb_out[3]; float* y_out[6];

@@ -7,10 +7,11 @@
 //   [B] [R]   n black / red half sweep pairs (x = (b + st sum_nb x) / (1 + st #nb), st = sigma tau)
 //   [D]       X+ = x; X bar+ = X bar + J(2 X+ - X bar) - X+ (eq:resolvent);
 //             y bar+ = P(y bar + 2 tau grad X+) - tau grad X+
-// with a barrier between phases.  A cell's new value reaches (2n + 1) cells up / left and
-// (2n + 2) cells down / right of the previous iterate, so the tile is loaded with that halo per
-// iteration; where the tile meets the image border there is no halo and the boundary rules of
-// Sec. 2.2 apply exactly.  X and y bar, whose neighbours are read, live in LDS; X bar, b and the
+// with a barrier between phases.  Each half sweep reaches one cell further in every direction; b
+// takes div y bar (left / up) and the dual update grad X+ (right / down), so after K iterations
+// X and X bar depend on the launch's input within (2n + 1) K cells on every side and y bar one
+// more below and to the right.  The tile is loaded with that halo; where it meets the image border
+// there is no halo and the boundary rules of Sec. 2.2 apply exactly.  X and y bar, whose neighbours are read, live in LDS; X bar, b and the
 // linearisation are read at their own cell only and live in registers.  Reads and writes go to
 // different state buffers, so tiles of one launch are independent.  Every neighbour read is an
 // unconditional LDS read at an index clamped into the array followed by a select, in the same
@@ -41,7 +42,7 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
     const int H = L.H, W = L.W;
     const int64_t ld = L.ld;
     const int K = a.K, n = a.sweeps;
-    const int hlu = (2 * n + 1) * K, hrd = (2 * n + 2) * K;
+    const int hlu = pdr_halo_lo(n, K), hrd = pdr_halo_hi(n, K);
     const int ey0 = max(y0 - hlu, 0), ex0 = max(x0 - hlu, 0);
     const int ey1 = min(y0 + th + hrd, H), ex1 = min(x0 + tw + hrd, W);
     const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;

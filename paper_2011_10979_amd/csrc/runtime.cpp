@@ -369,8 +369,10 @@ std::string pd_tune_key(int H, int W, const flow_params& p) {
     return p.scheme == FLOW_ALG1 ? k + "a" : k + "p" + std::to_string(p.gs_sweeps);
 }
 
-// Halo per iteration of the tile kernels with (X, X bar, y) state, summed over both sides of an axis.
-int pd_halo_per_iter(const flow_params& p) { return p.scheme == FLOW_ALG1 ? 2 : 4 * p.gs_sweeps + 3; }
+// Halo of a K-iteration tile with (X, X bar, y) state, summed over both sides of an axis.
+int pd_halo(const flow_params& p, int K) {
+    return p.scheme == FLOW_ALG1 ? 2 * alg1_halo(K) : pdr_halo_lo(p.gs_sweeps, K) + pdr_halo_hi(p.gs_sweeps, K);
+}
 
 PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std::string, TunedChoice>* tuned) {
     const bool hw = p.beta > 0;
@@ -387,11 +389,11 @@ PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std:
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
     const int nt = mode == 6 ? 512 : 1024;
     const int kdef = alg1 ? kAlg1DefaultK : kPdrDefaultK;
-    const int hk = pd_halo_per_iter(p);
-    PdrTbPlan T = plan_pd_tiles(H, W, hw, hk, K > 0 ? K : kdef, 0, nt);
+    const int k0 = K > 0 ? K : kdef;
+    PdrTbPlan T = plan_pd_tiles(H, W, hw, pd_halo(p, k0), k0, 0, nt);
     if (T.resident && K == 0) T.K = p.iters;        // the whole warp in one launch
     if (!T.tb) {                                     // the halo does not fit: fewer iterations per launch
-        for (int k = (K > 0 ? K : kdef) - 1; k >= 1 && !T.tb; --k) T = plan_pd_tiles(H, W, hw, hk, k, 0, nt);
+        for (int k = k0 - 1; k >= 1 && !T.tb; --k) T = plan_pd_tiles(H, W, hw, pd_halo(p, k), k, 0, nt);
     }
     return T;
 }
@@ -840,7 +842,8 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
         return fail(FLOW_E_INVAL, "the 512- and 256-thread small tiles run with direct tiling (order 0) only");
     const bool hw = p->beta > 0;
     const int cap = tb_capacity(hw, threads);
-    if ((int64_t)std::min<int64_t>(H, (int64_t)tile_h + 3 * iters) * std::min<int64_t>(W, (int64_t)tile_w + 3 * iters) > cap)
+    const int64_t halo = (int64_t)tb_halo_lo(iters) + tb_halo_hi(iters);
+    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > cap)
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[10] = {in->w, in->u, in->v, in->px, in->py, in->q1x, in->q1y, in->q2x, in->q2y, in->s};
     float* outs[10] = {out->w, out->u, out->v, out->px, out->py, out->q1x, out->q1y, out->q2x, out->q2y, out->s};
@@ -947,7 +950,7 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     const bool hw = p->beta > 0;
-    const int64_t halo = (int64_t)pd_halo_per_iter(*p) * iters;
+    const int64_t halo = pd_halo(*p, iters);
     if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw, 1024))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,

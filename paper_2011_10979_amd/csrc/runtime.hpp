@@ -105,9 +105,9 @@ struct PdrTbPlan {
     int K = 1;                 // iterations per launch
     int th = 0, tw = 0;
 };
-PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo_per_iter, int K, int ew_target, int nt = 1024);
+PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, int nt = 1024);
 std::string pd_tune_key(int H, int W, const flow_params& p);
-int pd_halo_per_iter(const flow_params& p);
+int pd_halo(const flow_params& p, int K);
 extern int g_pdr_mode;
 extern int g_pdr_k;
 

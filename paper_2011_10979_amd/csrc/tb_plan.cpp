@@ -15,13 +15,14 @@ int g_tb_k = 0;      // iterations per launch of tiled levels (0 = default)
 constexpr int kDefaultK = 4;
 
 static bool fit_tile(int H, int W, int cap, int K, int ew_target, int& th, int& tw) {
-    // output tile th x tw whose extended region (halo 2K + K per axis, clipped to the image) fits
+    // output tile th x tw whose extended region (halo K + 1 and K per axis, clipped to the image) fits
+    const int halo = tb_halo_lo(K) + tb_halo_hi(K);
     const int ew = std::min(W, ew_target);
-    tw = (ew >= W) ? W : ew - 3 * K;
-    const int ext_w = std::min(W, tw + 3 * K);
+    tw = (ew >= W) ? W : ew - halo;
+    const int ext_w = std::min(W, tw + halo);
     int eh = cap / ext_w;
-    th = (eh >= H) ? H : eh - 3 * K;
-    return tw >= 8 && th >= 2 && (int64_t)std::min(W, tw + 3 * K) * std::min(H, th + 3 * K) <= cap;
+    th = (eh >= H) ? H : eh - halo;
+    return tw >= 8 && th >= 2 && (int64_t)std::min(W, tw + halo) * std::min(H, th + halo) <= cap;
 }
 
 LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
@@ -69,10 +70,9 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
     return P;
 }
 
-PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo_per_iter, int K, int ew_target, int nt) {
-    // output tile th x tw whose extended region (halo_per_iter x K per axis over both sides, e.g.
-    // pDR (2n+1)K + (2n+2)K, ALG1 K + K; clipped to the image) fits the kernel's capacity; the whole
-    // level if it fits
+PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, int nt) {
+    // output tile th x tw whose extended region (`halo` = both sides of an axis at K iterations per
+    // launch, clipped to the image) fits the kernel's capacity; the whole level if it fits
     PdrTbPlan P;
     P.nt = nt;
     const int cap = pdr_tb_capacity(hw, nt);
@@ -83,7 +83,6 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo_per_iter, int K, int ew_
         P.tw = W;
         return P;
     }
-    const int halo = halo_per_iter * K;
     if (ew_target <= 0) ew_target = nt == 512 ? 32 : 64;
     const int ew = std::min(W, std::max(ew_target, halo + 8));
     const int tw = (ew >= W) ? W : ew - halo;

@@ -156,10 +156,10 @@ def test_pdr_iteration(shape, sweeps, beta):
                                           ((40, 45), (40, 45), 9), ((64, 64), (10, 18), 2), ((33, 47), (5, 9), 3)])
 @pytest.mark.parametrize("sweeps,beta", [(1, 0.0), (1, 0.05), (2, 0.0)])
 def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
-    """K pDR iterations of the tile kernel (halo (2n+1)K / (2n+2)K, ragged tiles, a resident level)
+    """K pDR iterations of the tile kernel (halo (2n+1)K / (2n+1)K + 1, ragged tiles, a resident level)
     against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
     print_case("pdr_tb", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta)
-    halo = (4 * sweeps + 3) * K
+    halo = (4 * sweeps + 2) * K + 1
     if min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > 2048:
         pytest.skip("tile plus halo exceeds the kernel capacity")
     rng = np.random.default_rng(zlib.crc32(repr(("pdrtb", shape, tile, K, sweeps, beta)).encode()))
@@ -283,12 +283,12 @@ def test_admm_iteration_every_strip_height(rows, shape, beta):
                                            (1025, 3), (256, 2), (513, 0), (257, 0)])
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
 def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme, relax, beta):
-    """K iterations of the temporally blocked tile kernel (halo 2K / K, ragged tiles, resident
+    """K iterations of the temporally blocked tile kernel (halo K + 1 / K, ragged tiles, resident
     levels) against K steps of the oracle on the same increment-form state."""
     print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
     cap = {1025: 2048, 513: 1024, 257: 512}.get(threads) or (1024 * (3 if beta > 0 else 4) if threads == 1024 else
                                                               256 * (4 if beta > 0 else 6))
-    if min(shape[0], tile[0] + 3 * K) * min(shape[1], tile[1] + 3 * K) > cap:
+    if min(shape[0], tile[0] + 2 * K + 1) * min(shape[1], tile[1] + 2 * K + 1) > cap:
         pytest.skip("tile plus halo exceeds the kernel capacity")
     rng = np.random.default_rng(zlib.crc32(repr(("tb", shape, tile, K, threads, scheme)).encode()))
     st = random_admm_state(rng, shape, beta)

@@ -1,0 +1,129 @@
+"""The halo of the K-iteration tile kernels is sufficient and tight, checked on the CPU with the oracle.
+
+A tile kernel loads an output tile plus a halo and advances that extended region by K iterations
+without seeing anything outside it.  Here the same is done with the oracle's steps on the whole
+image, after replacing every value outside the extended region (state and linearisation) by
+random garbage: inside the output tile the result must equal the undisturbed run bit for bit.  With
+one row or column less on any side (away from the image border) some output value must change, so
+the halo is also the smallest one that works.  The halo sizes are the ones the tile planner and
+kernels use:
+
+  ADMM family (Sec. 3.1.1)        K + 1 above / left,    K below / right
+  pDR with n sweeps (Sec. 3.1.2)  (2n+1) K above / left, (2n+1) K + 1 below / right
+  ALG1 (Sec. 4)                   K on every side
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import schemes
+
+SHAPE = (41, 47)
+LAM, C = 0.05, 0.05
+
+
+def _admm_state(rng, beta):
+    st = {k: rng.normal(scale=2.0, size=SHAPE) for k in ("u", "v")}
+    for k in ("q1x", "q1y", "q2x", "q2y"):
+        st[k] = rng.uniform(-0.5, 0.5, size=SHAPE)
+    st["s"] = rng.uniform(-0.05, 0.05, size=SHAPE)
+    st["w"] = rng.normal(scale=0.5, size=SHAPE) if beta > 0 else np.zeros(SHAPE)
+    for k in ("px", "py"):
+        st[k] = rng.uniform(-0.6, 0.6, size=SHAPE) if beta > 0 else np.zeros(SHAPE)
+    return st
+
+
+def _pd_state(rng, beta):
+    st = {k: rng.normal(scale=1.5, size=SHAPE) for k in ("u", "v", "ub", "vb")}
+    for k in ("qb1x", "qb1y", "qb2x", "qb2y"):
+        st[k] = rng.uniform(-0.6, 0.6, size=SHAPE)
+    for k in ("w", "wb"):
+        st[k] = rng.normal(scale=0.5, size=SHAPE) if beta > 0 else np.zeros(SHAPE)
+    for k in ("pbx", "pby"):
+        st[k] = rng.uniform(-0.6, 0.6, size=SHAPE) if beta > 0 else np.zeros(SHAPE)
+    return st
+
+
+def _lin(rng, beta):
+    L = {k: rng.normal(0, s, size=SHAPE) for k, s in (("Ix", 20), ("Iy", 20), ("It", 15))}
+    L["at"] = float(np.max(beta * beta + L["Ix"] ** 2 + L["Iy"] ** 2))
+    return L
+
+
+def _scheme(name, beta, n):
+    if name == "admm":
+        return _admm_state, lambda st, L: schemes.rpadmm1_step(st, L, beta, LAM, C, 1.0)
+    if name == "rpadmm2":
+        return _admm_state, lambda st, L: schemes.rpadmm2_step(st, L, beta, LAM, C, 1.9)
+    if name == "pdr":
+        return _pd_state, lambda st, L: schemes.pdr_step(st, L, beta, LAM, 2.0, 0.4, n)[0]
+    return _pd_state, lambda st, L: schemes.alg1_step(st, L, beta, LAM, 0.1, 1.25)[0]
+
+
+def _halo(name, K, n):
+    if name in ("admm", "rpadmm2"):
+        return K + 1, K
+    if name == "pdr":
+        return (2 * n + 1) * K, (2 * n + 1) * K + 1
+    return K, K
+
+
+def _tile_result(step, st, L, K, tile, lo, hi, rng):
+    """K steps with everything outside the extended region (lo = (top, left), hi = (bottom,
+    right)) replaced by garbage; returns the output tile of every state field."""
+    y0, x0, th, tw = tile
+    H, W = SHAPE
+    ey0, ex0 = max(y0 - lo[0], 0), max(x0 - lo[1], 0)
+    ey1, ex1 = min(y0 + th + hi[0], H), min(x0 + tw + hi[1], W)
+
+    def cut(a):
+        b = rng.normal(scale=3.0, size=SHAPE)
+        b[ey0:ey1, ex0:ex1] = a[ey0:ey1, ex0:ex1]
+        return b
+
+    s = {k: cut(v) for k, v in st.items()}
+    lin = {k: (cut(v) if np.ndim(v) else v) for k, v in L.items()}
+    for _ in range(K):
+        s = step(s, lin)
+    return {k: v[y0:y0 + th, x0:x0 + tw] for k, v in s.items()}
+
+
+def _setup(name, beta, n, K, seed):
+    rng = np.random.default_rng(seed)
+    make, step = _scheme(name, beta, n)
+    st, L = make(rng, beta), _lin(rng, beta)
+    full = dict(st)
+    for _ in range(K):
+        full = step(full, L)
+    return rng, step, st, L, full
+
+
+CASES = [("admm", 0.0, 1, 1), ("admm", 0.05, 1, 3), ("rpadmm2", 0.05, 1, 2), ("pdr", 0.0, 1, 1),
+         ("pdr", 0.05, 1, 2), ("pdr", 0.0, 2, 1), ("alg1", 0.0, 1, 2), ("alg1", 0.05, 1, 4)]
+
+
+@pytest.mark.parametrize("name,beta,n,K", CASES)
+def test_tile_halo_is_sufficient(name, beta, n, K):
+    rng, step, st, L, full = _setup(name, beta, n, K, seed=zlib.crc32(repr((name, beta, n, K)).encode()))
+    lo, hi = _halo(name, K, n)
+    # interior tiles, tiles on every border and a corner, odd and even offsets
+    for tile in [(15, 17, 7, 9), (16, 18, 6, 5), (0, 0, 8, 8), (SHAPE[0] - 6, SHAPE[1] - 7, 6, 7),
+                 (0, 20, 5, 9), (21, 0, 9, 6)]:
+        got = _tile_result(step, st, L, K, tile, (lo, lo), (hi, hi), rng)
+        y0, x0, th, tw = tile
+        for k, v in got.items():
+            assert np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]), (tile, k)
+
+
+@pytest.mark.parametrize("name,beta,n,K", CASES)
+@pytest.mark.parametrize("side", ["top", "left", "bottom", "right"])
+def test_tile_halo_is_tight(name, beta, n, K, side):
+    rng, step, st, L, full = _setup(name, beta, n, K, seed=zlib.crc32(repr((name, beta, n, K, side)).encode()))
+    lo, hi = _halo(name, K, n)
+    lo2, hi2 = [lo, lo], [hi, hi]
+    {"top": lo2, "left": lo2, "bottom": hi2, "right": hi2}[side][0 if side in ("top", "bottom") else 1] -= 1
+    tile = (16, 17, 8, 9)   # far enough from every border for the largest halo here
+    got = _tile_result(step, st, L, K, tile, tuple(lo2), tuple(hi2), rng)
+    y0, x0, th, tw = tile
+    assert any(not np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]) for k, v in got.items()), side
