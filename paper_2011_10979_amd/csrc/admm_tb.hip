@@ -23,6 +23,8 @@
 // tile indices from device counters.  Tiles of one launch read one state buffer and write the
 // other, so they never depend on each other, and every work-group of the persistent grid exits
 // once its counter passes the end of its run of tiles.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace flowmi {
@@ -41,8 +43,8 @@ struct TileLds {
 // Control flow is wavefront-uniform: a wavefront skips a slot only when none of its lanes holds a
 // pixel of the extended region; otherwise every lane runs it (lanes past the region hold zeros and
 // compute values nobody uses).  Neighbour values are read from LDS at indices clamped into the
-// array and then selected, so no read sits behind a divergent branch and the reads of a phase
-// issue together.
+// array and weighted by the operators' coefficients, so no read sits behind a branch and the reads
+// of a phase issue together.
 template <bool HAS_W, int NT, int PPT>
 __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, const TbLevel& L,
                                              TileLds<HAS_W, NT, PPT>& S) {
@@ -62,29 +64,34 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);   // a~ >= ||M_s||, floored
 
         float du[PPT], dv[PPT], ss[PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], ww[PPT];
-        // per-slot neighbour structure: in-array neighbour indices (clamped into the array) and the
-        // masks of the discrete operators (Sec. 2.2) -- the neighbour lies inside the extended region
-        // (hl, hu, hr, hd), the forward difference / the dual field's own term exists in the image (mx, my)
-        int ei[PPT], ej[PPT];
+        // Per-slot neighbour structure, fixed for the launch: in-array neighbour indices clamped into
+        // the array, and the operators' coefficients of Sec. 2.2 -- the forward difference exists in
+        // the image (fx, fy; folded with 1 / (a c) into cx, cy for the dual step) and the divergence's
+        // left / upper term exists (fl, fu).  Only the image border decides a coefficient: at the edge
+        // of the extended region a neighbour index may land on an unrelated slot, which only changes
+        // halo pixels that are no longer valid (the halo accounts for them).  Every LDS slot holds a
+        // finite value, so a zero coefficient times such a read is exactly zero.
+        int ei[PPT], ej[PPT], iL[PPT], iU[PPT], iR[PPT], iD[PPT];
+        float fx[PPT], fy[PPT], fl[PPT], fu[PPT], cx[PPT], cy[PPT];
         // slot k of this wavefront holds any pixel of the extended region (wave-uniform, scalar branch)
         const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
         auto live = [&](int k) { return wave0 + k * NT < EN; };
-        auto eL = [&](int k) { return max(tid + k * NT - 1, 0); };
-        auto eU = [&](int k) { return max(tid + k * NT - EW, 0); };
-        auto eR = [&](int k) { return min(tid + k * NT + 1, CAP - 1); };
-        auto eD = [&](int k) { return min(tid + k * NT + EW, CAP - 1); };
-        auto hl = [&](int k) { return ej[k] > 0 && ex0 + ej[k] > 0; };
-        auto hu = [&](int k) { return ei[k] > 0 && ey0 + ei[k] > 0; };
-        auto hr = [&](int k) { return ej[k] < EW - 1; };
-        auto hd = [&](int k) { return tid + k * NT + EW < EN; };
-        auto mx = [&](int k) { return ex0 + ej[k] < W - 1 ? 1.f : 0.f; };
-        auto my = [&](int k) { return ey0 + ei[k] < H - 1 ? 1.f : 0.f; };
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int e = tid + k * NT;
             ei[k] = e / EW;
             ej[k] = e - ei[k] * EW;
             const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+            iL[k] = max(e - 1, 0);
+            iU[k] = max(e - EW, 0);
+            iR[k] = min(e + 1, CAP - 1);
+            iD[k] = min(e + EW, CAP - 1);
+            fx[k] = gj < W - 1 ? 1.f : 0.f;
+            fy[k] = gi < H - 1 ? 1.f : 0.f;
+            fl[k] = gj > 0 ? 1.f : 0.f;
+            fu[k] = gi > 0 ? 1.f : 0.f;
+            cx[k] = fx[k] * inv_ac;
+            cy[k] = fy[k] * inv_ac;
             du[k] = dv[k] = ss[k] = Ix[k] = Iy[k] = It[k] = u0[k] = v0[k] = ww[k] = 0.f;
             float q1x = 0.f, q1y = 0.f, q2x = 0.f, q2y = 0.f, px = 0.f, py = 0.f;
             if (e < EN) {
@@ -118,81 +125,138 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         }
         __syncthreads();
 
-        // divergence of a dual field at slot k: [j < W-1] fx(i,j) - [j > 0] fx(i,j-1) + [i < H-1] fy(i,j) - [i > 0] fy(i-1,j)
-        auto divk = [&](const float* fx, const float* fy, int k, int e) {
-            const float l = fx[eL(k)], u = fy[eU(k)];
-            return mx(k) * fx[e] - (hl(k) ? l : 0.f) + my(k) * fy[e] - (hu(k) ? u : 0.f);
+        // divergence of a dual field at slot k from its own, left and upper values:
+        // [j < W-1] ax(i,j) - [j > 0] ax(i,j-1) + [i < H-1] ay(i,j) - [i > 0] ay(i-1,j)
+        auto divv = [&](int k, float ax, float al, float ay, float au) {
+            float d = fmaf(fx[k], ax, -(fl[k] * al));
+            d = fmaf(fy[k], ay, d);
+            return fmaf(-fu[k], au, d);
         };
-
+        auto divk = [&](const float* ax, const float* ay, int k, int e) {
+            return divv(k, ax[e], ax[iL[k]], ay[e], ay[iU[k]]);
+        };
         // phase A (g) for slot k from the divergences of the current dual field
         auto g_out = [&](int k, int e, float dq1, float dq2, float dp) {
             sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
             sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
             if constexpr (HAS_W) sgw[e] = ww[k] + c * (dp - beta * ss[k]);
         };
+        // Each phase reads the operands of a group of GS slots before it writes LDS, so the reads of
+        // the group issue together (the compiler cannot move LDS reads at computed indices past
+        // writes); groups of two keep the larger work-group shapes within their register budget.
+        constexpr int GS = 2;
+        // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own slot)
+        auto phase_b = [&](auto all_live) {
+            constexpr bool AL = decltype(all_live)::value;
+            constexpr int NG = HAS_W ? 3 : 2, NQ = HAS_W ? 6 : 4;
+            float* sg[3] = {sgu, sgv, sgw};
+            float* sq[6] = {sq1x, sq1y, sq2x, sq2y, spx, spy};
+#pragma unroll
+            for (int k0 = 0; k0 < PPT; k0 += GS) {
+                float g0[NG][GS], gr[NG][GS], gd[NG][GS], q[NQ][GS];
+#pragma unroll
+                for (int j = 0; j < GS; ++j) {
+                    const int k = k0 + j;
+                    if (k >= PPT || (!AL && !live(k))) continue;
+                    const int e = tid + k * NT;
+#pragma unroll
+                    for (int f = 0; f < NG; ++f) {
+                        g0[f][j] = sg[f][e];
+                        gr[f][j] = sg[f][iR[k]];
+                        gd[f][j] = sg[f][iD[k]];
+                    }
+#pragma unroll
+                    for (int f = 0; f < NQ; ++f) q[f][j] = sq[f][e];
+                }
+#pragma unroll
+                for (int j = 0; j < GS; ++j) {
+                    const int k = k0 + j;
+                    if (k >= PPT || (!AL && !live(k))) continue;
+                    const int e = tid + k * NT;
+                    const float t1x = fmaf(gr[0][j] - g0[0][j], cx[k], q[0][j]);
+                    const float t1y = fmaf(gd[0][j] - g0[0][j], cy[k], q[1][j]);
+                    const float t2x = fmaf(gr[1][j] - g0[1][j], cx[k], q[2][j]);
+                    const float t2y = fmaf(gd[1][j] - g0[1][j], cy[k], q[3][j]);
+                    const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
+                    const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
+                    sq1x[e] = t1x * sc;
+                    sq1y[e] = t1y * sc;
+                    sq2x[e] = t2x * sc;
+                    sq2y[e] = t2y * sc;
+                    if constexpr (HAS_W) {
+                        const float tpx = fmaf(gr[NG - 1][j] - g0[NG - 1][j], cx[k], q[4][j]);
+                        const float tpy = fmaf(gd[NG - 1][j] - g0[NG - 1][j], cy[k], q[5][j]);
+                        const float np2 = tpx * tpx + tpy * tpy;
+                        const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                        spx[e] = tpx * sp;
+                        spy[e] = tpy * sp;
+                    }
+                }
+            }
+        };
+        // phase C: div y+, s+, multipliers (own slots, registers), then phase A of the next iteration
+        // from the same divergences (C only reads y+, A only writes g: no barrier between them)
+        auto phase_c = [&](auto all_live, bool next) {
+            constexpr bool AL = decltype(all_live)::value;
+            constexpr int ND = HAS_W ? 3 : 2;
+            const float* sx[3] = {sq1x, sq2x, spx};
+            const float* sy[3] = {sq1y, sq2y, spy};
+#pragma unroll
+            for (int k0 = 0; k0 < PPT; k0 += GS) {
+                float dn[ND][GS];
+#pragma unroll
+                for (int j = 0; j < GS; ++j) {
+                    const int k = k0 + j;
+                    if (k >= PPT || (!AL && !live(k))) continue;
+                    const int e = tid + k * NT;
+#pragma unroll
+                    for (int f = 0; f < ND; ++f)
+                        dn[f][j] = divv(k, sx[f][e], sx[f][iL[k]], sy[f][e], sy[f][iU[k]]);
+                }
+#pragma unroll
+                for (int j = 0; j < GS; ++j) {
+                    const int k = k0 + j;
+                    if (k >= PPT || (!AL && !live(k))) continue;
+                    const int e = tid + k * NT;
+                    const float dn1 = dn[0][j], dn2 = dn[1][j];
+                    const float hu_ = du[k] + crs * (dn1 - Ix[k] * ss[k]);
+                    const float hv_ = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
+                    float acc = It[k] + Ix[k] * hu_ + Iy[k] * hv_;
+                    float dnp = 0.f;
+                    if constexpr (HAS_W) {
+                        dnp = dn[ND - 1][j];
+                        acc += beta * (ww[k] + crs * (dnp - beta * ss[k]));
+                    }
+                    float sn = ss[k] + acc * inv_atc;
+                    sn = fminf(fmaxf(sn, -a.lam), a.lam);
+                    const float ms = a.cB * sn - a.cC * ss[k];
+                    du[k] = du[k] + a.cA * dn1 - Ix[k] * ms;
+                    dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;
+                    if constexpr (HAS_W) ww[k] = ww[k] + a.cA * dnp - beta * ms;
+                    ss[k] = sn;
+                    if (next) g_out(k, e, dn1, dn2, dnp);
+                }
+            }
+        };
 
+        // phase A at the start: every slot, so that every g slot in LDS holds a finite value
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
             const int e = tid + k * NT;
             float dp = 0.f;
             if constexpr (HAS_W) dp = divk(spx, spy, k, e);
             g_out(k, e, divk(sq1x, sq1y, k, e), divk(sq2x, sq2y, k, e), dp);
         }
+        // a wavefront whose last slot holds a pixel of the region runs every slot without branches,
+        // so the LDS reads of all its slots issue together
+        const bool all_live = live(PPT - 1);
         for (int it = 0; it < K; ++it) {
             __syncthreads();
-            // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own slot)
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!live(k)) continue;
-                const int e = tid + k * NT;
-                const float gu = sgu[e], gv = sgv[e];
-                const float gur = sgu[eR(k)], gud = sgu[eD(k)], gvr = sgv[eR(k)], gvd = sgv[eD(k)];
-                const float t1x = sq1x[e] + mx(k) * ((hr(k) ? gur : gu) - gu) * inv_ac;
-                const float t1y = sq1y[e] + my(k) * ((hd(k) ? gud : gu) - gu) * inv_ac;
-                const float t2x = sq2x[e] + mx(k) * ((hr(k) ? gvr : gv) - gv) * inv_ac;
-                const float t2y = sq2y[e] + my(k) * ((hd(k) ? gvd : gv) - gv) * inv_ac;
-                const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
-                const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
-                sq1x[e] = t1x * sc;
-                sq1y[e] = t1y * sc;
-                sq2x[e] = t2x * sc;
-                sq2y[e] = t2y * sc;
-                if constexpr (HAS_W) {
-                    const float gw = sgw[e], gwr = sgw[eR(k)], gwd = sgw[eD(k)];
-                    const float tpx = spx[e] + mx(k) * ((hr(k) ? gwr : gw) - gw) * inv_ac;
-                    const float tpy = spy[e] + my(k) * ((hd(k) ? gwd : gw) - gw) * inv_ac;
-                    const float np2 = tpx * tpx + tpy * tpy;
-                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
-                    spx[e] = tpx * sp;
-                    spy[e] = tpy * sp;
-                }
-            }
+            if (all_live) phase_b(std::true_type{});
+            else phase_b(std::false_type{});
             __syncthreads();
-            // phase C: div y+, s+, multipliers (own slots, registers)
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!live(k)) continue;
-                const int e = tid + k * NT;
-                const float dn1 = divk(sq1x, sq1y, k, e);
-                const float dn2 = divk(sq2x, sq2y, k, e);
-                const float hu_ = du[k] + crs * (dn1 - Ix[k] * ss[k]);
-                const float hv_ = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
-                float acc = It[k] + Ix[k] * hu_ + Iy[k] * hv_;
-                float dnp = 0.f;
-                if constexpr (HAS_W) {
-                    dnp = divk(spx, spy, k, e);
-                    acc += beta * (ww[k] + crs * (dnp - beta * ss[k]));
-                }
-                float sn = ss[k] + acc * inv_atc;
-                sn = fminf(fmaxf(sn, -a.lam), a.lam);
-                const float ms = a.cB * sn - a.cC * ss[k];
-                du[k] = du[k] + a.cA * dn1 - Ix[k] * ms;
-                dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;
-                if constexpr (HAS_W) ww[k] = ww[k] + a.cA * dnp - beta * ms;
-                ss[k] = sn;
-                if (it + 1 < K) g_out(k, e, dn1, dn2, dnp);   // phase A of the next iteration
-            }
+            if (all_live) phase_c(std::true_type{}, it + 1 < K);
+            else phase_c(std::false_type{}, it + 1 < K);
         }
 
         // write the output tile
