@@ -11,32 +11,38 @@
 // takes div y bar (left / up) and the dual update grad X+ (right / down), so after K iterations
 // X and X bar depend on the launch's input within (2n + 1) K cells on every side and y bar one
 // more below and to the right.  The tile is loaded with that halo; where it meets the image border
-// there is no halo and the boundary rules of Sec. 2.2 apply exactly.  X and y bar, whose neighbours are read, live in LDS; X bar, b and the
-// linearisation are read at their own cell only and live in registers.  Reads and writes go to
-// different state buffers, so tiles of one launch are independent.  Every neighbour read is an
-// unconditional LDS read at an index clamped into the array followed by a select, in the same
-// summation order as the three-pass kernels.
+// there is no halo and the boundary rules of Sec. 2.2 apply exactly.
+//
+// Layout by colour: thread t owns the t-th red and the t-th black cell of the extended region (in
+// row-major order), and LDS holds X and y bar per colour, indexed by a cell's rank within its
+// colour.  A half sweep then runs one cell per thread with every lane busy, and every neighbour of
+// a cell lies in the other colour's arrays.  X bar, b and the linearisation are read at their own
+// cell only and live in registers.  Neighbour ranks and the operators' coefficients (the
+// neighbour exists in the image, the Gauss-Seidel denominator) are fixed for the launch; a
+// neighbour outside the extended region reads an unrelated finite value with a non-zero
+// coefficient, which only changes halo cells the halo accounts for.  Reads and writes go to
+// different state buffers, so tiles of one launch are independent.
 #include "kernels.hpp"
 
 namespace flowmi {
 
 namespace {
 
-template <bool HAS_W, int NT, int PPT>
+template <bool HAS_W, int NT>
 struct PdrLds {
-    static constexpr int CAP = NT * PPT;
-    static constexpr int NX = HAS_W ? 3 : 2;   // x components held: (u, v) or (w, u, v)
+    static constexpr int NX = HAS_W ? 3 : 2;   // x components held: (u, v) or (u, v, w)
     static constexpr int NY = HAS_W ? 6 : 4;
-    float x[NX][CAP];
-    float y[NY][CAP];
+    // [colour][component][1 + rank]: one spare slot at each end, so that the ranks of a cell's left and
+    // right neighbours (always consecutive within a row of the other colour) both index the array
+    float x[2][NX][NT + 2];
+    float y[2][NY][NT + 2];
 };
 
-template <bool HAS_W, int NT, int PPT>
+template <bool HAS_W, int NT>
 __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int th, int tw,
-                                         PdrLds<HAS_W, NT, PPT>& S) {
-    constexpr int CAP = NT * PPT;
-    constexpr int NX = PdrLds<HAS_W, NT, PPT>::NX;
-    constexpr int NY = PdrLds<HAS_W, NT, PPT>::NY;
+                                         PdrLds<HAS_W, NT>& S) {
+    constexpr int NX = PdrLds<HAS_W, NT>::NX;
+    constexpr int NY = PdrLds<HAS_W, NT>::NY;
     const PdrTbLevel& L = a.lvl;
     const int tid = threadIdx.x;
     const int H = L.H, W = L.W;
@@ -45,162 +51,198 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
     const int hlu = pdr_halo_lo(n, K), hrd = pdr_halo_hi(n, K);
     const int ey0 = max(y0 - hlu, 0), ex0 = max(x0 - hlu, 0);
     const int ey1 = min(y0 + th + hrd, H), ex1 = min(x0 + tw + hrd, W);
-    const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;
+    const int EW = ex1 - ex0, EH = ey1 - ey0;
     const float sigma = a.sigma, tau = a.tau, stt = a.stt, lam = a.lam, beta = a.beta;
     const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
-    auto live = [&](int k) { return wave0 + k * NT < EN; };
 
-    // component c of x / X bar: 0 -> u, 1 -> v, 2 -> w; y planes: q1x q1y q2x q2y (p_x p_y)
-    int ei[PPT], ej[PPT];
-    float xb[NX][PPT], bb[NX][PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], th_s[PPT];
+    // colour c (0 red, 1 black) of local cell (i, j): red iff (p0 + i + j) is even, p0 the parity of
+    // the region's corner in image coordinates.  Row i holds its colour-c cells at columns of parity
+    // (p0 + i + c) & 1; two consecutive rows hold EW cells of each colour.
+    const int p0 = (ey0 + ex0) & 1;
+    auto row_count = [&](int c, int i) { return (EW - ((p0 + i + c) & 1) + 1) >> 1; };
+    auto rank_of = [&](int c, int i, int j) { return (i >> 1) * EW + ((i & 1) ? row_count(c, 0) : 0) + (j >> 1); };
+    int ncol[2];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int e = tid + k * NT;
-        ei[k] = e / EW;
-        ej[k] = e - ei[k] * EW;
-        const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+    for (int c = 0; c < 2; ++c) ncol[c] = rank_of(c, EH, 0);
+    auto live = [&](int c) { return wave0 < ncol[c]; };   // wave-uniform: any lane holds a cell
+
+    // local cell (i, j) of slot c: the tid-th cell of colour c (a cell of the region iff own(c))
+    auto cell = [&](int c, int& i, int& j) {
+        const int m = tid / EW, rem = tid - m * EW, rc0 = row_count(c, 0);
+        i = rem < rc0 ? 2 * m : 2 * m + 1;
+        j = ((p0 + i + c) & 1) + 2 * (rem < rc0 ? rem : rem - rc0);
+    };
+    auto own = [&](int c) { return tid < ncol[c]; };
+    // LDS positions (1 + rank, in the other colour's arrays) of the left, upper and lower neighbours;
+    // the right neighbour sits at nL + 1.  Outside the region: a spare or unrelated finite slot.
+    int nL[2], nU[2], nD[2];
+    float fl[2], fr[2], fu[2], fd[2], rden[2];
+    float xb[NX][2], bb[NX][2], Ix[2], Iy[2], It[2], u0[2], v0[2], th_s[2];
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int f = 0; f < NX; ++f) S.x[c][f][0] = S.x[c][f][NT + 1] = 0.f;
+#pragma unroll
+            for (int f = 0; f < NY; ++f) S.y[c][f][0] = S.y[c][f][NT + 1] = 0.f;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        int i, j;
+        cell(c, i, j);
+        const int gi = ey0 + i, gj = ex0 + j;
+        const int oc = 1 - c;                       // every neighbour has the other colour
+        nL[c] = own(c) ? 1 + rank_of(oc, i, j - 1) : 0;   // j - 1 = -1 gives rank - 1: the spare slot
+        nU[c] = (own(c) && i > 0) ? 1 + rank_of(oc, i - 1, j) : 0;
+        nD[c] = (own(c) && i + 1 < EH) ? 1 + rank_of(oc, i + 1, j) : 0;
+        fl[c] = gj > 0 ? 1.f : 0.f;
+        fr[c] = gj < W - 1 ? 1.f : 0.f;
+        fu[c] = gi > 0 ? 1.f : 0.f;
+        fd[c] = gi < H - 1 ? 1.f : 0.f;
+        rden[c] = 1.f / (1.f + stt * (((fl[c] + fr[c]) + fu[c]) + fd[c]));
         float xv[NX], yv[NY];
 #pragma unroll
-        for (int c = 0; c < NX; ++c) xv[c] = xb[c][k] = bb[c][k] = 0.f;
+        for (int f = 0; f < NX; ++f) xv[f] = xb[f][c] = bb[f][c] = 0.f;
 #pragma unroll
-        for (int c = 0; c < NY; ++c) yv[c] = 0.f;
-        Ix[k] = Iy[k] = It[k] = u0[k] = v0[k] = th_s[k] = 0.f;
-        if (e < EN) {
+        for (int f = 0; f < NY; ++f) yv[f] = 0.f;
+        Ix[c] = Iy[c] = It[c] = u0[c] = v0[c] = th_s[c] = 0.f;
+        if (own(c)) {
             const int64_t o = (int64_t)gi * ld + gj;
 #pragma unroll
-            for (int c = 0; c < NX; ++c) {
-                xv[c] = L.x_in[c][o];
-                xb[c][k] = L.xb_in[c][o];
+            for (int f = 0; f < NX; ++f) {
+                xv[f] = L.x_in[f][o];
+                xb[f][c] = L.xb_in[f][o];
             }
 #pragma unroll
-            for (int c = 0; c < NY; ++c) yv[c] = L.y_in[c][o];
-            Ix[k] = L.Ix[o];
-            Iy[k] = L.Iy[o];
-            It[k] = L.It[o];
-            u0[k] = L.u0[o];
-            v0[k] = L.v0[o];
+            for (int f = 0; f < NY; ++f) yv[f] = L.y_in[f][o];
+            Ix[c] = L.Ix[o];
+            Iy[c] = L.Iy[o];
+            It[c] = L.It[o];
+            u0[c] = L.u0[o];
+            v0[c] = L.v0[o];
         }
 #pragma unroll
-        for (int c = 0; c < NX; ++c) S.x[c][e] = xv[c];
+        for (int f = 0; f < NX; ++f) S.x[c][f][1 + tid] = xv[f];
 #pragma unroll
-        for (int c = 0; c < NY; ++c) S.y[c][e] = yv[c];
+        for (int f = 0; f < NY; ++f) S.y[c][f][1 + tid] = yv[f];
     }
     __syncthreads();
 
-    // red = (i + j) even, in image coordinates
-    auto is_red = [&](int k) { return ((ey0 + ei[k] + ex0 + ej[k]) & 1) == 0; };
-    // x = (b + st sum of in-image neighbours) / (1 + st #neighbours), summed left, right, up, down
-    auto gs = [&](const float* X, float b, int k) {
-        const int e = tid + k * NT;
-        const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-        const float xl = X[max(e - 1, 0)], xr = X[min(e + 1, CAP - 1)];
-        const float xu = X[max(e - EW, 0)], xd = X[min(e + EW, CAP - 1)];
-        float s = 0.f, cnt = 0.f;
-        if (gj > 0) { s += xl; cnt += 1.f; }
-        if (gj < W - 1) { s += xr; cnt += 1.f; }
-        if (gi > 0) { s += xu; cnt += 1.f; }
-        if (gi < H - 1) { s += xd; cnt += 1.f; }
-        return (b + stt * s) / (1.f + stt * cnt);
-    };
-    // [j < W-1] fx(i,j) - [j > 0] fx(i,j-1) + [i < H-1] fy(i,j) - [i > 0] fy(i-1,j)
-    auto dv = [&](const float* fx, const float* fy, int k) {
-        const int e = tid + k * NT;
-        const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-        const float l = fx[max(e - 1, 0)], u = fy[max(e - EW, 0)];
-        float d = 0.f;
-        if (gj < W - 1) d += fx[e];
-        if (gj > 0) d -= l;
-        if (gi < H - 1) d += fy[e];
-        if (gi > 0) d -= u;
-        return d;
-    };
-    auto half_sweep = [&](bool red) {
+    // one half sweep over the cells of colour c: x = (b + st sum of in-image neighbours) / (1 + st #),
+    // summed left, right, up, down
+    auto half_sweep = [&](int c) {
+        if (!live(c)) return;
+        const int oc = 1 - c;
+        float nb[NX][4];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
-            if (is_red(k) != red) continue;
-            const int e = tid + k * NT;
+        for (int f = 0; f < NX; ++f) {
+            nb[f][0] = S.x[oc][f][nL[c]];
+            nb[f][1] = S.x[oc][f][nL[c] + 1];
+            nb[f][2] = S.x[oc][f][nU[c]];
+            nb[f][3] = S.x[oc][f][nD[c]];
+        }
 #pragma unroll
-            for (int c = 0; c < NX; ++c) {
-                const float xn = gs(S.x[c], bb[c][k], k);
-                S.x[c][e] = xn;
-            }
+        for (int f = 0; f < NX; ++f) {
+            float sm = fl[c] * nb[f][0];
+            sm = fmaf(fr[c], nb[f][1], sm);
+            sm = fmaf(fu[c], nb[f][2], sm);
+            sm = fmaf(fd[c], nb[f][3], sm);
+            S.x[c][f][1 + tid] = (bb[f][c] + stt * sm) * rden[c];
         }
     };
 
     for (int it = 0; it < K; ++it) {
-        // [b + R]: b from y bar (left / up neighbours), then the first red half sweep (reads only
-        // black neighbours, writes only red cells)
+        // [b + R]: b from div y bar ([j < W-1] y_x - [j > 0] y_x left + [i < H-1] y_y - [i > 0] y_y up),
+        // then the first red half sweep (reads only black cells, writes only red ones)
+        {
+            float yo[2][NX][2], yn[2][NX][2];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
-            bb[0][k] = xb[0][k] + sigma * dv(S.y[0], S.y[1], k);     // u from q1
-            bb[1][k] = xb[1][k] + sigma * dv(S.y[2], S.y[3], k);     // v from q2
-            if constexpr (HAS_W) bb[2][k] = xb[2][k] + sigma * dv(S.y[4], S.y[5], k);   // w from p
+            for (int c = 0; c < 2; ++c) {
+                if (!live(c)) continue;
+#pragma unroll
+                for (int f = 0; f < NX; ++f) {
+                    yo[c][f][0] = S.y[c][2 * f][1 + tid];
+                    yo[c][f][1] = S.y[c][2 * f + 1][1 + tid];
+                    yn[c][f][0] = S.y[1 - c][2 * f][nL[c]];
+                    yn[c][f][1] = S.y[1 - c][2 * f + 1][nU[c]];
+                }
+#pragma unroll
+                for (int f = 0; f < NX; ++f) {
+                    float d = fr[c] * yo[c][f][0];
+                    d = fmaf(-fl[c], yn[c][f][0], d);
+                    d = fmaf(fd[c], yo[c][f][1], d);
+                    d = fmaf(-fu[c], yn[c][f][1], d);
+                    bb[f][c] = xb[f][c] + sigma * d;
+                }
+            }
         }
-        half_sweep(true);
+        half_sweep(0);
         for (int sw = 0; sw < n; ++sw) {
             __syncthreads();
-            half_sweep(false);
+            half_sweep(1);
             __syncthreads();
-            half_sweep(true);
+            half_sweep(0);
         }
         __syncthreads();
         // [D]: resolvent at X~ = 2 X+ - X bar, dual update from grad X+ (right / down neighbours)
+        {
+            float xo[2][NX], xr[2][NX], xd[2][NX], yo[2][NY];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
-            const int e = tid + k * NT;
-            const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-            const bool hasr = gj < W - 1, hasd = gi < H - 1;
-            const int er = min(e + 1, CAP - 1), ed = min(e + EW, CAP - 1);
-            const float u = S.x[0][e], v = S.x[1][e];
-            const float ur = S.x[0][er], ud = S.x[0][ed], vr = S.x[1][er], vd = S.x[1][ed];
-            const float ux = hasr ? ur - u : 0.f, uy = hasd ? ud - u : 0.f;
-            const float vx = hasr ? vr - v : 0.f, vy = hasd ? vd - v : 0.f;
-            float w = 0.f, wx = 0.f, wy = 0.f;
-            if constexpr (HAS_W) {
-                w = S.x[2][e];
-                const float wr = S.x[2][er], wd = S.x[2][ed];
-                wx = hasr ? wr - w : 0.f;
-                wy = hasd ? wd - w : 0.f;
-            }
-            const float ub = xb[0][k], vbv = xb[1][k];
-            const float ut = 2.f * u - ub, vt = 2.f * v - vbv;
-            float wbv = 0.f, wt = 0.f;
-            if constexpr (HAS_W) { wbv = xb[2][k]; wt = 2.f * w - wbv; }
-            const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
-            const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
-            const float thr = sigma * lam * e2;
-            float step, theta;
-            if (e2 > 0.f) {
-                if (rho < -thr) step = sigma * lam;
-                else if (rho > thr) step = -sigma * lam;
-                else step = -rho / e2;
-                theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
-            } else {
-                step = 0.f;
-                theta = 0.f;
-            }
-            xb[0][k] = ub + (ut + step * Ix[k]) - u;
-            xb[1][k] = vbv + (vt + step * Iy[k]) - v;
-            if constexpr (HAS_W) xb[2][k] = wbv + (wt + step * beta) - w;
-            th_s[k] = theta;
-            const float t2 = 2.f * tau;
-            const float a1x = S.y[0][e] + t2 * ux, a1y = S.y[1][e] + t2 * uy;
-            const float a2x = S.y[2][e] + t2 * vx, a2y = S.y[3][e] + t2 * vy;
-            const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
-            const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
-            S.y[0][e] = a1x * sq - tau * ux;
-            S.y[1][e] = a1y * sq - tau * uy;
-            S.y[2][e] = a2x * sq - tau * vx;
-            S.y[3][e] = a2y * sq - tau * vy;
-            if constexpr (HAS_W) {
-                const float bx = S.y[4][e] + t2 * wx, by = S.y[5][e] + t2 * wy;
-                const float np2 = bx * bx + by * by;
-                const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
-                S.y[4][e] = bx * sp - tau * wx;
-                S.y[5][e] = by * sp - tau * wy;
+            for (int c = 0; c < 2; ++c) {
+                if (!live(c)) continue;
+#pragma unroll
+                for (int f = 0; f < NX; ++f) {
+                    xo[c][f] = S.x[c][f][1 + tid];
+                    xr[c][f] = S.x[1 - c][f][nL[c] + 1];
+                    xd[c][f] = S.x[1 - c][f][nD[c]];
+                }
+#pragma unroll
+                for (int f = 0; f < NY; ++f) yo[c][f] = S.y[c][f][1 + tid];
+                float gx[NX], gy[NX];
+#pragma unroll
+                for (int f = 0; f < NX; ++f) {
+                    gx[f] = fr[c] * (xr[c][f] - xo[c][f]);
+                    gy[f] = fd[c] * (xd[c][f] - xo[c][f]);
+                }
+                const float u = xo[c][0], v = xo[c][1];
+                const float ub = xb[0][c], vbv = xb[1][c];
+                const float ut = 2.f * u - ub, vt = 2.f * v - vbv;
+                float w = 0.f, wbv = 0.f, wt = 0.f;
+                if constexpr (HAS_W) { w = xo[c][2]; wbv = xb[2][c]; wt = 2.f * w - wbv; }
+                const float e2 = beta * beta + Ix[c] * Ix[c] + Iy[c] * Iy[c];
+                const float rho = It[c] + beta * wt + Ix[c] * (ut - u0[c]) + Iy[c] * (vt - v0[c]);
+                const float thr = sigma * lam * e2;
+                float step, theta;
+                if (e2 > 0.f) {
+                    if (rho < -thr) step = sigma * lam;
+                    else if (rho > thr) step = -sigma * lam;
+                    else step = -rho / e2;
+                    theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
+                } else {
+                    step = 0.f;
+                    theta = 0.f;
+                }
+                xb[0][c] = ub + (ut + step * Ix[c]) - u;
+                xb[1][c] = vbv + (vt + step * Iy[c]) - v;
+                if constexpr (HAS_W) xb[2][c] = wbv + (wt + step * beta) - w;
+                th_s[c] = theta;
+                const float t2 = 2.f * tau;
+                const float a1x = yo[c][0] + t2 * gx[0], a1y = yo[c][1] + t2 * gy[0];
+                const float a2x = yo[c][2] + t2 * gx[1], a2y = yo[c][3] + t2 * gy[1];
+                const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
+                const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
+                S.y[c][0][1 + tid] = a1x * sq - tau * gx[0];
+                S.y[c][1][1 + tid] = a1y * sq - tau * gy[0];
+                S.y[c][2][1 + tid] = a2x * sq - tau * gx[1];
+                S.y[c][3][1 + tid] = a2y * sq - tau * gy[1];
+                if constexpr (HAS_W) {
+                    const float bx = yo[c][4] + t2 * gx[2], by = yo[c][5] + t2 * gy[2];
+                    const float np2 = bx * bx + by * by;
+                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                    S.y[c][4][1 + tid] = bx * sp - tau * gx[2];
+                    S.y[c][5][1 + tid] = by * sp - tau * gy[2];
+                }
             }
         }
         __syncthreads();
@@ -208,20 +250,21 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
 
     // write the output tile
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int e = tid + k * NT;
-        if (e >= EN) continue;
-        const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+    for (int c = 0; c < 2; ++c) {
+        if (!own(c)) continue;
+        int i, j;
+        cell(c, i, j);
+        const int gi = ey0 + i, gj = ex0 + j;
         if (gi < y0 || gi >= y0 + th || gj < x0 || gj >= x0 + tw) continue;
         const int64_t o = (int64_t)gi * ld + gj;
 #pragma unroll
-        for (int c = 0; c < NX; ++c) {
-            L.x_out[c][o] = S.x[c][e];
-            L.xb_out[c][o] = xb[c][k];
+        for (int f = 0; f < NX; ++f) {
+            L.x_out[f][o] = S.x[c][f][1 + tid];
+            L.xb_out[f][o] = xb[f][c];
         }
 #pragma unroll
-        for (int c = 0; c < NY; ++c) L.y_out[c][o] = S.y[c][e];
-        L.s_out[o] = th_s[k];
+        for (int f = 0; f < NY; ++f) L.y_out[f][o] = S.y[c][f][1 + tid];
+        L.s_out[o] = th_s[c];
     }
 }
 
@@ -230,28 +273,29 @@ __device__ __forceinline__ int xcd_tile_p(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
-template <bool HAS_W, int NT, int PPT>
+template <bool HAS_W, int NT>
 __global__ __launch_bounds__(NT) void pdr_tb_kernel(PdrTbArgs a) {
-    __shared__ PdrLds<HAS_W, NT, PPT> S;
+    __shared__ PdrLds<HAS_W, NT> S;
     const int t = xcd_tile_p(blockIdx.x, gridDim.x);
     if (t >= a.ntiles) return;
     const int ty = t / a.ntx, tx = t - ty * a.ntx;
     const int y0 = ty * a.th, x0 = tx * a.tw;
-    pdr_tile<HAS_W, NT, PPT>(a, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+    pdr_tile<HAS_W, NT>(a, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
 }
 
 }  // namespace
 
-int pdr_tb_capacity(bool has_w, int nt) { return nt * (has_w ? kPdrPptW : kPdrPpt); }
+// one red and one black cell per thread
+int pdr_tb_capacity(bool, int nt) { return 2 * nt; }
 
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
     if (nt == 512) {
-        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 512, kPdrPptW>), dim3(grid), dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((pdr_tb_kernel<false, 512, kPdrPpt>), dim3(grid), dim3(512), 0, s, a);
+        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 512>), dim3(grid), dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((pdr_tb_kernel<false, 512>), dim3(grid), dim3(512), 0, s, a);
     } else {
-        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 1024, kPdrPptW>), dim3(grid), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((pdr_tb_kernel<false, 1024, kPdrPpt>), dim3(grid), dim3(1024), 0, s, a);
+        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 1024>), dim3(grid), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((pdr_tb_kernel<false, 1024>), dim3(grid), dim3(1024), 0, s, a);
     }
 }
 
