@@ -9,7 +9,9 @@
 // boundary rules of Sec. 2.2 apply exactly).  X bar and y, whose neighbours are read, live in LDS;
 // X and the linearisation live in registers.  Reads and writes go to different state sets, so the
 // tiles of one launch are independent.  Neighbour reads are unconditional LDS reads at indices
-// clamped into the array, followed by selects.
+// clamped into the array, weighted by the operators' coefficients.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace flowmi {
@@ -44,8 +46,15 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
     const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
     auto live = [&](int k) { return wave0 + k * NT < EN; };
 
+    // Per-slot neighbour structure, fixed for the launch: neighbour indices clamped into the array
+    // and the operators' coefficients of Sec. 2.2 (the forward difference exists in the image: fx,
+    // fy, folded with tau into cx, cy; the divergence's left / upper term exists: fl, fu).  Only the
+    // image border decides a coefficient; at the edge of the extended region an index may land on
+    // an unrelated slot, which only changes halo pixels the halo accounts for.  Every LDS slot holds
+    // a finite value, so a zero coefficient times such a read is exactly zero.
     // components: x / x bar (u, v, w); y (q1x, q1y, q2x, q2y, p_x, p_y)
-    int ei[PPT], ej[PPT];
+    int ei[PPT], ej[PPT], iL[PPT], iU[PPT], iR[PPT], iD[PPT];
+    float fx[PPT], fy[PPT], fl[PPT], fu[PPT], cx[PPT], cy[PPT];
     float x[NX][PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], th_s[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -53,6 +62,16 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
         ei[k] = e / EW;
         ej[k] = e - ei[k] * EW;
         const int gi = ey0 + ei[k], gj = ex0 + ej[k];
+        iL[k] = max(e - 1, 0);
+        iU[k] = max(e - EW, 0);
+        iR[k] = min(e + 1, CAP - 1);
+        iD[k] = min(e + EW, CAP - 1);
+        fx[k] = gj < W - 1 ? 1.f : 0.f;
+        fy[k] = gi < H - 1 ? 1.f : 0.f;
+        fl[k] = gj > 0 ? 1.f : 0.f;
+        fu[k] = gi > 0 ? 1.f : 0.f;
+        cx[k] = fx[k] * tau;
+        cy[k] = fy[k] * tau;
         float xbv[NX], yv[NY];
 #pragma unroll
         for (int c = 0; c < NX; ++c) x[c][k] = xbv[c] = 0.f;
@@ -81,92 +100,119 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
     }
     __syncthreads();
 
-    // [j < W-1] fx(i,j) - [j > 0] fx(i,j-1) + [i < H-1] fy(i,j) - [i > 0] fy(i-1,j)
-    auto dv = [&](const float* fx, const float* fy, int k) {
-        const int e = tid + k * NT;
-        const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-        const float l = fx[max(e - 1, 0)], u = fy[max(e - EW, 0)];
-        float d = 0.f;
-        if (gj < W - 1) d += fx[e];
-        if (gj > 0) d -= l;
-        if (gi < H - 1) d += fy[e];
-        if (gi > 0) d -= u;
-        return d;
+    // Each phase reads the operands of a group of GS slots before it writes LDS, so the reads of
+    // the group issue together (the compiler cannot move LDS reads at computed indices past writes).
+    constexpr int GS = 2;
+    // [Y]: dual ascent from the forward differences of X bar, projected (joint q ball, p ball)
+    auto phase_y = [&](auto all_live) {
+        constexpr bool AL = decltype(all_live)::value;
+#pragma unroll
+        for (int k0 = 0; k0 < PPT; k0 += GS) {
+            float xo[NX][GS], xr[NX][GS], xd[NX][GS], yo[NY][GS];
+#pragma unroll
+            for (int j = 0; j < GS; ++j) {
+                const int k = k0 + j;
+                if (k >= PPT || (!AL && !live(k))) continue;
+                const int e = tid + k * NT;
+#pragma unroll
+                for (int c = 0; c < NX; ++c) {
+                    xo[c][j] = S.xb[c][e];
+                    xr[c][j] = S.xb[c][iR[k]];
+                    xd[c][j] = S.xb[c][iD[k]];
+                }
+#pragma unroll
+                for (int c = 0; c < NY; ++c) yo[c][j] = S.y[c][e];
+            }
+#pragma unroll
+            for (int j = 0; j < GS; ++j) {
+                const int k = k0 + j;
+                if (k >= PPT || (!AL && !live(k))) continue;
+                const int e = tid + k * NT;
+                const float a1x = fmaf(cx[k], xr[0][j] - xo[0][j], yo[0][j]);
+                const float a1y = fmaf(cy[k], xd[0][j] - xo[0][j], yo[1][j]);
+                const float a2x = fmaf(cx[k], xr[1][j] - xo[1][j], yo[2][j]);
+                const float a2y = fmaf(cy[k], xd[1][j] - xo[1][j], yo[3][j]);
+                const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
+                const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
+                S.y[0][e] = a1x * sq;
+                S.y[1][e] = a1y * sq;
+                S.y[2][e] = a2x * sq;
+                S.y[3][e] = a2y * sq;
+                if constexpr (HAS_W) {
+                    const float bx = fmaf(cx[k], xr[2][j] - xo[2][j], yo[4][j]);
+                    const float by = fmaf(cy[k], xd[2][j] - xo[2][j], yo[5][j]);
+                    const float np2 = bx * bx + by * by;
+                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                    S.y[4][e] = bx * sp;
+                    S.y[5][e] = by * sp;
+                }
+            }
+        }
+    };
+    // [X]: primal proximal descent X+ = J(X + sigma div y+), extrapolation X bar+ = 2 X+ - X
+    auto phase_x = [&](auto all_live) {
+        constexpr bool AL = decltype(all_live)::value;
+#pragma unroll
+        for (int k0 = 0; k0 < PPT; k0 += GS) {
+            float dvv[NX][GS];
+#pragma unroll
+            for (int j = 0; j < GS; ++j) {
+                const int k = k0 + j;
+                if (k >= PPT || (!AL && !live(k))) continue;
+                const int e = tid + k * NT;
+                // [j < W-1] y_x - [j > 0] y_x(left) + [i < H-1] y_y - [i > 0] y_y(up)
+#pragma unroll
+                for (int c = 0; c < NX; ++c) {
+                    float d = fmaf(fx[k], S.y[2 * c][e], -(fl[k] * S.y[2 * c][iL[k]]));
+                    d = fmaf(fy[k], S.y[2 * c + 1][e], d);
+                    dvv[c][j] = fmaf(-fu[k], S.y[2 * c + 1][iU[k]], d);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < GS; ++j) {
+                const int k = k0 + j;
+                if (k >= PPT || (!AL && !live(k))) continue;
+                const int e = tid + k * NT;
+                const float ut = x[0][k] + sigma * dvv[0][j];
+                const float vt = x[1][k] + sigma * dvv[1][j];
+                float wt = 0.f;
+                if constexpr (HAS_W) wt = x[2][k] + sigma * dvv[NX - 1][j];
+                const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
+                const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
+                const float thr = sigma * lam * e2;
+                float step, theta;
+                if (e2 > 0.f) {
+                    if (rho < -thr) step = sigma * lam;
+                    else if (rho > thr) step = -sigma * lam;
+                    else step = -rho / e2;
+                    theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
+                } else {
+                    step = 0.f;
+                    theta = 0.f;
+                }
+                const float un = ut + step * Ix[k], vn = vt + step * Iy[k];
+                S.xb[0][e] = 2.f * un - x[0][k];
+                S.xb[1][e] = 2.f * vn - x[1][k];
+                x[0][k] = un;
+                x[1][k] = vn;
+                if constexpr (HAS_W) {
+                    const float wn = wt + step * beta;
+                    S.xb[2][e] = 2.f * wn - x[2][k];
+                    x[2][k] = wn;
+                }
+                th_s[k] = theta;
+            }
+        }
     };
 
+    // a wavefront whose last slot holds a pixel of the region runs every slot without branches
+    const bool all_live = live(PPT - 1);
     for (int it = 0; it < K; ++it) {
-        // [Y]: dual ascent from the forward differences of X bar, projected (joint q ball, p ball)
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
-            const int e = tid + k * NT;
-            const int gi = ey0 + ei[k], gj = ex0 + ej[k];
-            const bool hasr = gj < W - 1, hasd = gi < H - 1;
-            const int er = min(e + 1, CAP - 1), ed = min(e + EW, CAP - 1);
-            float g[NX][2];
-#pragma unroll
-            for (int c = 0; c < NX; ++c) {
-                const float xc = S.xb[c][e], xr = S.xb[c][er], xd = S.xb[c][ed];
-                g[c][0] = hasr ? xr - xc : 0.f;
-                g[c][1] = hasd ? xd - xc : 0.f;
-            }
-            const float a1x = S.y[0][e] + tau * g[0][0], a1y = S.y[1][e] + tau * g[0][1];
-            const float a2x = S.y[2][e] + tau * g[1][0], a2y = S.y[3][e] + tau * g[1][1];
-            const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
-            const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
-            float pxn = 0.f, pyn = 0.f;
-            if constexpr (HAS_W) {
-                const float bx = S.y[4][e] + tau * g[2][0], by = S.y[5][e] + tau * g[2][1];
-                const float np2 = bx * bx + by * by;
-                const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
-                pxn = bx * sp;
-                pyn = by * sp;
-            }
-            // every thread has read its neighbours' X bar; y is only read at its own cell here
-            S.y[0][e] = a1x * sq;
-            S.y[1][e] = a1y * sq;
-            S.y[2][e] = a2x * sq;
-            S.y[3][e] = a2y * sq;
-            if constexpr (HAS_W) {
-                S.y[4][e] = pxn;
-                S.y[5][e] = pyn;
-            }
-        }
+        if (all_live) phase_y(std::true_type{});
+        else phase_y(std::false_type{});
         __syncthreads();
-        // [X]: primal proximal descent X+ = J(X + sigma div y+), extrapolation X bar+ = 2 X+ - X
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!live(k)) continue;
-            const int e = tid + k * NT;
-            const float ut = x[0][k] + sigma * dv(S.y[0], S.y[1], k);
-            const float vt = x[1][k] + sigma * dv(S.y[2], S.y[3], k);
-            float wt = 0.f;
-            if constexpr (HAS_W) wt = x[2][k] + sigma * dv(S.y[4], S.y[5], k);
-            const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
-            const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
-            const float thr = sigma * lam * e2;
-            float step, theta;
-            if (e2 > 0.f) {
-                if (rho < -thr) step = sigma * lam;
-                else if (rho > thr) step = -sigma * lam;
-                else step = -rho / e2;
-                theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
-            } else {
-                step = 0.f;
-                theta = 0.f;
-            }
-            const float un = ut + step * Ix[k], vn = vt + step * Iy[k];
-            S.xb[0][e] = 2.f * un - x[0][k];
-            S.xb[1][e] = 2.f * vn - x[1][k];
-            x[0][k] = un;
-            x[1][k] = vn;
-            if constexpr (HAS_W) {
-                const float wn = wt + step * beta;
-                S.xb[2][e] = 2.f * wn - x[2][k];
-                x[2][k] = wn;
-            }
-            th_s[k] = theta;
-        }
+        if (all_live) phase_x(std::true_type{});
+        else phase_x(std::false_type{});
         __syncthreads();
     }
 

@@ -121,6 +121,33 @@ def test_odd_sizes_and_degenerate_levels(ctx):
     conditioned_check(ctx, pair, "odd 35x9", pad=5, levels=3, warps=2, iters=30)
 
 
+@pytest.mark.parametrize("H,W,levels,iters,scheme", [(2, 2, 1, 10, "padmm"), (2, 37, 1, 10, "pdr"),
+                                                      (29, 2, 1, 10, "alg1"), (5, 3, 2, 7, "rpadmm2"),
+                                                      (20, 24, 2, 0, "padmm"), (2, 2, 1, 6, "pdr")])
+def test_smallest_images_and_zero_iterations(ctx, H, W, levels, iters, scheme):
+    """The degenerate cases of the method: 2-pixel sides (every pixel on the image border, where
+    the forward differences vanish), a 3 x 2 coarse level, and zero iterations (the flow stays at
+    its zero start; energy and gap are those of the zero flow)."""
+    print(f"[case] smallest {H}x{W} levels {levels} iters {iters} {scheme}", flush=True)
+    rng = np.random.default_rng(H * 1000 + W * 10 + iters)
+    I0 = rng.uniform(0.0, 1.0, (H, W))
+    pair = type("Pair", (), {})()
+    pair.I0, pair.I1 = I0, np.clip(I0 + rng.normal(0.0, 0.05, (H, W)), 0.0, 1.0)
+    relax = 1.9 if scheme == "rpadmm2" else 1.0
+    u, v, _, _ = conditioned_check(ctx, pair, f"smallest {H}x{W}", scheme=scheme, relax=relax, levels=levels,
+                                   warps=2, iters=iters, use_graph=0)
+    if iters == 0:
+        assert not u.any() and not v.any()
+
+
+def test_single_row_or_column_is_rejected(ctx):
+    for shape in ((1, 16), (16, 1)):
+        I = torch.zeros(shape, dtype=torch.float32, device="cuda")
+        with pytest.raises(fm.FlowError) as e:
+            ctx.solve(I, I.clone(), fm.Params(levels=1, warps=1, iters=1))
+        assert e.value.status == fm.FLOW_E_INVAL
+
+
 def test_vga_bench_workload_full_size(ctx):
     """The 640x480 workload exactly as the benchmark runs it (5 levels x 5 warps x 50, pADMM,
     graph replay), against the full FP64 oracle solve; also p99.9 <= 1e-4 px and mean <= 1e-5 px."""
