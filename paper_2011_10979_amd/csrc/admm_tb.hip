@@ -64,6 +64,16 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);   // a~ >= ||M_s||, floored
 
         float du[PPT], dv[PPT], ss[PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], ww[PPT];
+        // the thread's own dual values (q1x, q1y, q2x, q2y[, p_x, p_y]) and g (u, v[, w]): only the
+        // owner writes them, so with two pixels per thread they stay in registers and LDS serves the
+        // neighbours' reads (larger shapes would spill and read their own values from LDS)
+        constexpr int NQ = HAS_W ? 6 : 4, NG = HAS_W ? 3 : 2;
+        constexpr bool OWN = PPT <= 2;
+        float qo[NQ][PPT], go[NG][PPT];
+        float* const sqa[6] = {sq1x, sq1y, sq2x, sq2y, spx, spy};
+        float* const sga[3] = {sgu, sgv, sgw};
+        auto qown = [&](int f, int k) { return OWN ? qo[f][k] : sqa[f][tid + k * NT]; };
+        auto gown = [&](int f, int k) { return OWN ? go[f][k] : sga[f][tid + k * NT]; };
         // Per-slot neighbour structure, fixed for the launch: in-array neighbour indices clamped into
         // the array, and the operators' coefficients of Sec. 2.2 -- the forward difference exists in
         // the image (fx, fy; folded with 1 / (a c) into cx, cy for the dual step) and the divergence's
@@ -114,13 +124,13 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                     ww[k] = L.in[0][o];
                 }
             }
-            sq1x[e] = q1x;
-            sq1y[e] = q1y;
-            sq2x[e] = q2x;
-            sq2y[e] = q2y;
+            sq1x[e] = qo[0][k] = q1x;
+            sq1y[e] = qo[1][k] = q1y;
+            sq2x[e] = qo[2][k] = q2x;
+            sq2y[e] = qo[3][k] = q2y;
             if constexpr (HAS_W) {
-                spx[e] = px;
-                spy[e] = py;
+                spx[e] = qo[4][k] = px;
+                spy[e] = qo[5][k] = py;
             }
         }
         __syncthreads();
@@ -132,14 +142,17 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
             d = fmaf(fy[k], ay, d);
             return fmaf(-fu[k], au, d);
         };
-        auto divk = [&](const float* ax, const float* ay, int k, int e) {
-            return divv(k, ax[e], ax[iL[k]], ay[e], ay[iU[k]]);
+        // divergence of dual field f (0: q1, 1: q2, 2: p) at slot k, own values from registers
+        auto divf = [&](int f, int k) {
+            const float* sx[3] = {sq1x, sq2x, spx};
+            const float* sy[3] = {sq1y, sq2y, spy};
+            return divv(k, qown(2 * f, k), sx[f][iL[k]], qown(2 * f + 1, k), sy[f][iU[k]]);
         };
         // phase A (g) for slot k from the divergences of the current dual field
         auto g_out = [&](int k, int e, float dq1, float dq2, float dp) {
-            sgu[e] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
-            sgv[e] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
-            if constexpr (HAS_W) sgw[e] = ww[k] + c * (dp - beta * ss[k]);
+            sgu[e] = go[0][k] = u0[k] + (du[k] + c * (dq1 - Ix[k] * ss[k]));
+            sgv[e] = go[1][k] = v0[k] + (dv[k] + c * (dq2 - Iy[k] * ss[k]));
+            if constexpr (HAS_W) sgw[e] = go[2][k] = ww[k] + c * (dp - beta * ss[k]);
         };
         // Each phase reads the operands of a group of GS slots before it writes LDS, so the reads of
         // the group issue together (the compiler cannot move LDS reads at computed indices past
@@ -148,48 +161,42 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         // phase B: y+ = P(y + grad g / (a c)), in place over q (B reads q only at its own slot)
         auto phase_b = [&](auto all_live) {
             constexpr bool AL = decltype(all_live)::value;
-            constexpr int NG = HAS_W ? 3 : 2, NQ = HAS_W ? 6 : 4;
             float* sg[3] = {sgu, sgv, sgw};
-            float* sq[6] = {sq1x, sq1y, sq2x, sq2y, spx, spy};
 #pragma unroll
             for (int k0 = 0; k0 < PPT; k0 += GS) {
-                float g0[NG][GS], gr[NG][GS], gd[NG][GS], q[NQ][GS];
+                float gr[NG][GS], gd[NG][GS];
 #pragma unroll
                 for (int j = 0; j < GS; ++j) {
                     const int k = k0 + j;
                     if (k >= PPT || (!AL && !live(k))) continue;
-                    const int e = tid + k * NT;
 #pragma unroll
                     for (int f = 0; f < NG; ++f) {
-                        g0[f][j] = sg[f][e];
                         gr[f][j] = sg[f][iR[k]];
                         gd[f][j] = sg[f][iD[k]];
                     }
-#pragma unroll
-                    for (int f = 0; f < NQ; ++f) q[f][j] = sq[f][e];
                 }
 #pragma unroll
                 for (int j = 0; j < GS; ++j) {
                     const int k = k0 + j;
                     if (k >= PPT || (!AL && !live(k))) continue;
                     const int e = tid + k * NT;
-                    const float t1x = fmaf(gr[0][j] - g0[0][j], cx[k], q[0][j]);
-                    const float t1y = fmaf(gd[0][j] - g0[0][j], cy[k], q[1][j]);
-                    const float t2x = fmaf(gr[1][j] - g0[1][j], cx[k], q[2][j]);
-                    const float t2y = fmaf(gd[1][j] - g0[1][j], cy[k], q[3][j]);
+                    const float t1x = fmaf(gr[0][j] - gown(0, k), cx[k], qown(0, k));
+                    const float t1y = fmaf(gd[0][j] - gown(0, k), cy[k], qown(1, k));
+                    const float t2x = fmaf(gr[1][j] - gown(1, k), cx[k], qown(2, k));
+                    const float t2y = fmaf(gd[1][j] - gown(1, k), cy[k], qown(3, k));
                     const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
                     const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
-                    sq1x[e] = t1x * sc;
-                    sq1y[e] = t1y * sc;
-                    sq2x[e] = t2x * sc;
-                    sq2y[e] = t2y * sc;
+                    sq1x[e] = qo[0][k] = t1x * sc;
+                    sq1y[e] = qo[1][k] = t1y * sc;
+                    sq2x[e] = qo[2][k] = t2x * sc;
+                    sq2y[e] = qo[3][k] = t2y * sc;
                     if constexpr (HAS_W) {
-                        const float tpx = fmaf(gr[NG - 1][j] - g0[NG - 1][j], cx[k], q[4][j]);
-                        const float tpy = fmaf(gd[NG - 1][j] - g0[NG - 1][j], cy[k], q[5][j]);
+                        const float tpx = fmaf(gr[NG - 1][j] - gown(NG - 1, k), cx[k], qown(4, k));
+                        const float tpy = fmaf(gd[NG - 1][j] - gown(NG - 1, k), cy[k], qown(5, k));
                         const float np2 = tpx * tpx + tpy * tpy;
                         const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
-                        spx[e] = tpx * sp;
-                        spy[e] = tpy * sp;
+                        spx[e] = qo[4][k] = tpx * sp;
+                        spy[e] = qo[5][k] = tpy * sp;
                     }
                 }
             }
@@ -199,8 +206,6 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         auto phase_c = [&](auto all_live, bool next) {
             constexpr bool AL = decltype(all_live)::value;
             constexpr int ND = HAS_W ? 3 : 2;
-            const float* sx[3] = {sq1x, sq2x, spx};
-            const float* sy[3] = {sq1y, sq2y, spy};
 #pragma unroll
             for (int k0 = 0; k0 < PPT; k0 += GS) {
                 float dn[ND][GS];
@@ -208,10 +213,8 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 for (int j = 0; j < GS; ++j) {
                     const int k = k0 + j;
                     if (k >= PPT || (!AL && !live(k))) continue;
-                    const int e = tid + k * NT;
 #pragma unroll
-                    for (int f = 0; f < ND; ++f)
-                        dn[f][j] = divv(k, sx[f][e], sx[f][iL[k]], sy[f][e], sy[f][iU[k]]);
+                    for (int f = 0; f < ND; ++f) dn[f][j] = divf(f, k);
                 }
 #pragma unroll
                 for (int j = 0; j < GS; ++j) {
@@ -244,8 +247,8 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         for (int k = 0; k < PPT; ++k) {
             const int e = tid + k * NT;
             float dp = 0.f;
-            if constexpr (HAS_W) dp = divk(spx, spy, k, e);
-            g_out(k, e, divk(sq1x, sq1y, k, e), divk(sq2x, sq2y, k, e), dp);
+            if constexpr (HAS_W) dp = divf(2, k);
+            g_out(k, e, divf(0, k), divf(1, k), dp);
         }
         // a wavefront whose last slot holds a pixel of the region runs every slot without branches,
         // so the LDS reads of all its slots issue together
@@ -271,14 +274,14 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
             L.out[1][o] = du[k];
             L.out[2][o] = dv[k];
             L.out[9][o] = ss[k];
-            L.out[5][o] = sq1x[e];
-            L.out[6][o] = sq1y[e];
-            L.out[7][o] = sq2x[e];
-            L.out[8][o] = sq2y[e];
+            L.out[5][o] = qown(0, k);
+            L.out[6][o] = qown(1, k);
+            L.out[7][o] = qown(2, k);
+            L.out[8][o] = qown(3, k);
             if constexpr (HAS_W) {
                 L.out[0][o] = ww[k];
-                L.out[3][o] = spx[e];
-                L.out[4][o] = spy[e];
+                L.out[3][o] = qown(4, k);
+                L.out[4][o] = qown(5, k);
             }
         }
     }
