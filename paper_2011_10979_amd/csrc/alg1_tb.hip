@@ -56,6 +56,9 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
     int ei[PPT], ej[PPT], iL[PPT], iU[PPT], iR[PPT], iD[PPT];
     float fx[PPT], fy[PPT], fl[PPT], fu[PPT], cx[PPT], cy[PPT];
     float x[NX][PPT], Ix[PPT], Iy[PPT], It[PPT], u0[PPT], v0[PPT], th_s[PPT];
+    // the thread's own X bar and y: only the owner writes them, so they stay in registers and LDS
+    // serves the neighbours' reads
+    float xbo[NX][PPT], yow[NY][PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int e = tid + k * NT;
@@ -94,9 +97,9 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
             v0[k] = L.v0[o];
         }
 #pragma unroll
-        for (int c = 0; c < NX; ++c) S.xb[c][e] = xbv[c];
+        for (int c = 0; c < NX; ++c) S.xb[c][e] = xbo[c][k] = xbv[c];
 #pragma unroll
-        for (int c = 0; c < NY; ++c) S.y[c][e] = yv[c];
+        for (int c = 0; c < NY; ++c) S.y[c][e] = yow[c][k] = yv[c];
     }
     __syncthreads();
 
@@ -108,43 +111,39 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
         constexpr bool AL = decltype(all_live)::value;
 #pragma unroll
         for (int k0 = 0; k0 < PPT; k0 += GS) {
-            float xo[NX][GS], xr[NX][GS], xd[NX][GS], yo[NY][GS];
+            float xr[NX][GS], xd[NX][GS];
 #pragma unroll
             for (int j = 0; j < GS; ++j) {
                 const int k = k0 + j;
                 if (k >= PPT || (!AL && !live(k))) continue;
-                const int e = tid + k * NT;
 #pragma unroll
                 for (int c = 0; c < NX; ++c) {
-                    xo[c][j] = S.xb[c][e];
                     xr[c][j] = S.xb[c][iR[k]];
                     xd[c][j] = S.xb[c][iD[k]];
                 }
-#pragma unroll
-                for (int c = 0; c < NY; ++c) yo[c][j] = S.y[c][e];
             }
 #pragma unroll
             for (int j = 0; j < GS; ++j) {
                 const int k = k0 + j;
                 if (k >= PPT || (!AL && !live(k))) continue;
                 const int e = tid + k * NT;
-                const float a1x = fmaf(cx[k], xr[0][j] - xo[0][j], yo[0][j]);
-                const float a1y = fmaf(cy[k], xd[0][j] - xo[0][j], yo[1][j]);
-                const float a2x = fmaf(cx[k], xr[1][j] - xo[1][j], yo[2][j]);
-                const float a2y = fmaf(cy[k], xd[1][j] - xo[1][j], yo[3][j]);
+                const float a1x = fmaf(cx[k], xr[0][j] - xbo[0][k], yow[0][k]);
+                const float a1y = fmaf(cy[k], xd[0][j] - xbo[0][k], yow[1][k]);
+                const float a2x = fmaf(cx[k], xr[1][j] - xbo[1][k], yow[2][k]);
+                const float a2y = fmaf(cy[k], xd[1][j] - xbo[1][k], yow[3][k]);
                 const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
                 const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
-                S.y[0][e] = a1x * sq;
-                S.y[1][e] = a1y * sq;
-                S.y[2][e] = a2x * sq;
-                S.y[3][e] = a2y * sq;
+                S.y[0][e] = yow[0][k] = a1x * sq;
+                S.y[1][e] = yow[1][k] = a1y * sq;
+                S.y[2][e] = yow[2][k] = a2x * sq;
+                S.y[3][e] = yow[3][k] = a2y * sq;
                 if constexpr (HAS_W) {
-                    const float bx = fmaf(cx[k], xr[2][j] - xo[2][j], yo[4][j]);
-                    const float by = fmaf(cy[k], xd[2][j] - xo[2][j], yo[5][j]);
+                    const float bx = fmaf(cx[k], xr[2][j] - xbo[2][k], yow[4][k]);
+                    const float by = fmaf(cy[k], xd[2][j] - xbo[2][k], yow[5][k]);
                     const float np2 = bx * bx + by * by;
                     const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
-                    S.y[4][e] = bx * sp;
-                    S.y[5][e] = by * sp;
+                    S.y[4][e] = yow[4][k] = bx * sp;
+                    S.y[5][e] = yow[5][k] = by * sp;
                 }
             }
         }
@@ -159,12 +158,11 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
             for (int j = 0; j < GS; ++j) {
                 const int k = k0 + j;
                 if (k >= PPT || (!AL && !live(k))) continue;
-                const int e = tid + k * NT;
                 // [j < W-1] y_x - [j > 0] y_x(left) + [i < H-1] y_y - [i > 0] y_y(up)
 #pragma unroll
                 for (int c = 0; c < NX; ++c) {
-                    float d = fmaf(fx[k], S.y[2 * c][e], -(fl[k] * S.y[2 * c][iL[k]]));
-                    d = fmaf(fy[k], S.y[2 * c + 1][e], d);
+                    float d = fmaf(fx[k], yow[2 * c][k], -(fl[k] * S.y[2 * c][iL[k]]));
+                    d = fmaf(fy[k], yow[2 * c + 1][k], d);
                     dvv[c][j] = fmaf(-fu[k], S.y[2 * c + 1][iU[k]], d);
                 }
             }
@@ -191,13 +189,13 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
                     theta = 0.f;
                 }
                 const float un = ut + step * Ix[k], vn = vt + step * Iy[k];
-                S.xb[0][e] = 2.f * un - x[0][k];
-                S.xb[1][e] = 2.f * vn - x[1][k];
+                S.xb[0][e] = xbo[0][k] = 2.f * un - x[0][k];
+                S.xb[1][e] = xbo[1][k] = 2.f * vn - x[1][k];
                 x[0][k] = un;
                 x[1][k] = vn;
                 if constexpr (HAS_W) {
                     const float wn = wt + step * beta;
-                    S.xb[2][e] = 2.f * wn - x[2][k];
+                    S.xb[2][e] = xbo[2][k] = 2.f * wn - x[2][k];
                     x[2][k] = wn;
                 }
                 th_s[k] = theta;
@@ -227,10 +225,10 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
 #pragma unroll
         for (int c = 0; c < NX; ++c) {
             L.x_out[c][o] = x[c][k];
-            L.xb_out[c][o] = S.xb[c][e];
+            L.xb_out[c][o] = xbo[c][k];
         }
 #pragma unroll
-        for (int c = 0; c < NY; ++c) L.y_out[c][o] = S.y[c][e];
+        for (int c = 0; c < NY; ++c) L.y_out[c][o] = yow[c][k];
         L.s_out[o] = th_s[k];
     }
 }
