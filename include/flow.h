@@ -247,9 +247,10 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
 
 /* Set the iteration-kernel choice of one level shape (H x W, with or without the w / p block, iters
  * per warp) by hand, as flow_autotune would.  pdr_sweeps = 0: the ADMM family, mode 1 = one-pass
- * kernel with `rows` rows per strip (0 = built-in), 2 / 3 / 4 / 7 / 6 = K-iteration tiles of 256 /
- * 1024 threads / small tiles of 1024 / 512 / 256 threads with K iterations per launch (K = 0: resident if the level fits one
- * tile, else the built-in K).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
+ * kernel with `rows` rows per strip (0 = built-in; 2, 4 or 8), 2 / 3 / 4 / 7 / 6 = K-iteration tiles
+ * of 256 / 1024 threads / small tiles of 1024 / 512 / 256 threads with K iterations per launch (K = 0:
+ * resident if the level fits one tile, else the built-in K) and `rows` the target width of a tile's
+ * extended region (0 = built-in, else 16..512).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
  * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident); pdr_sweeps = -1:
  * ALG1, modes 5 / 6 as for pDR.  Lets a caller reuse a tuning measured in
  * another process.  Drops the context's captured graphs. */

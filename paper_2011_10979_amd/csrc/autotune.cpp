@@ -141,21 +141,27 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             cands.push_back(c);
         }
         for (int mode : {2, 4, 3, 7, 6})
-            for (int K : {2, 4, 8, 16}) {
-                LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K);
-                if (!P.tb) continue;
-                if (P.resident && K != 2) continue;             // one resident candidate per size
-                if (!P.resident && P.K != K) continue;          // capacity lowered K: a duplicate
-                std::vector<TbTile> tiles;
-                append_tiles(P, 0, L.H, L.W, tiles);
-                P.ntiles = (int)tiles.size();
-                Cand c{};
-                c.c.mode = mode;
-                c.c.K = P.resident ? 0 : K;
-                c.P = P;
-                c.tb = true;
-                cands.push_back(c);
-            }
+            for (int K : {2, 4, 8, 16})
+                for (int ew : {0, 32, 48, 64, 96}) {             // extended tile width (0: built-in)
+                    LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K, ew);
+                    if (!P.tb) continue;
+                    if (P.resident && (K != 2 || ew != 0)) continue;   // one resident candidate per size
+                    if (!P.resident && P.K != K) continue;              // capacity lowered K: a duplicate
+                    bool dup = false;                                   // the same tiling under another width
+                    for (const Cand& o : cands)
+                        dup = dup || (o.tb && o.c.mode == mode && o.P.K == P.K && o.P.th == P.th && o.P.tw == P.tw);
+                    if (dup) continue;
+                    std::vector<TbTile> tiles;
+                    append_tiles(P, 0, L.H, L.W, tiles);
+                    P.ntiles = (int)tiles.size();
+                    Cand c{};
+                    c.c.mode = mode;
+                    c.c.K = P.resident ? 0 : K;
+                    c.c.rows = P.resident ? 0 : ew;
+                    c.P = P;
+                    c.tb = true;
+                    cands.push_back(c);
+                }
         double best = 1e30;
         TunedChoice bestc;
         std::ostringstream lv;
@@ -211,7 +217,10 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
     if (mode < 1 || mode > 7) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6, 7 (tiles) or 5 (pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
-    if (rows != 0 && rows != 2 && rows != 4 && rows != 8) return fail(FLOW_E_INVAL, "rows must be 0, 2, 4 or 8");
+    if (mode == 1 && rows != 0 && rows != 2 && rows != 4 && rows != 8)
+        return fail(FLOW_E_INVAL, "rows (one-pass strip height) must be 0, 2, 4 or 8");
+    if (mode != 1 && rows != 0 && (rows < 16 || rows > 512))
+        return fail(FLOW_E_INVAL, "rows (tile modes: extended tile width) must be 0 or in [16, 512]");
     if (pdr_sweeps < -1) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= -1 (-1: ALG1)");
     if (pdr_sweeps == -1 && mode != 5 && mode != 6) return fail(FLOW_E_INVAL, "ALG1 modes: 5 / 6 (tiles of 1024 / 512 threads)");
     if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6)

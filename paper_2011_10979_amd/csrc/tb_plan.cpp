@@ -49,7 +49,7 @@ LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
     return P;
 }
 
-LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
+LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int ew) {
     LevelTbPlan P;
     if (mode == 1 || iters < 2) return P;                    // one-pass kernel
     if (mode == 0) {
@@ -65,7 +65,7 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq) {
         return P;
     }
     const int nt = mode == 3 ? 1024 : mode == 4 ? 1025 : mode == 6 ? 257 : mode == 7 ? 513 : 256;
-    P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, 0);
+    P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, ew);
     if (P.resident) P.K = iters;                             // the whole warp in one launch
     return P;
 }
@@ -105,8 +105,10 @@ LevelTbPlan plan_level_tuned(int H, int W, bool hw, int iters, const std::map<st
     if (g_tb_mode == 0 && tuned) {
         auto it = tuned->find(tune_key(H, W, hw, iters));
         if (it != tuned->end()) {
-            LevelTbPlan P = plan_level(H, W, hw, iters, it->second.mode, it->second.K);
-            P.rows = it->second.rows;
+            // `rows`: the one-pass kernel's strip height, or the tiles' extended width target
+            const TunedChoice& c = it->second;
+            LevelTbPlan P = plan_level(H, W, hw, iters, c.mode, c.K, c.mode == 1 ? 0 : c.rows);
+            P.rows = c.mode == 1 ? c.rows : 0;
             return P;
         }
     }

@@ -235,6 +235,28 @@ def test_autotuned_solve_keeps_parity():
         c.close()
 
 
+@pytest.mark.parametrize("mode,k,ew", [(4, 4, 32), (4, 8, 48), (7, 4, 96), (6, 2, 16), (2, 4, 64)])
+def test_tuned_tile_widths_keep_parity(mode, k, ew):
+    """A tuned choice may also set the width of the tiles' extended region (tuning field `rows` of
+    the tile modes); any width gives the same iteration, so the solve still meets the oracle bar."""
+    print(f"[case] tile width mode {mode} K {k} ew {ew}", flush=True)
+    c = fm.Context(0)
+    try:
+        for key in ("96x128i40", "48x64i40", "24x32i40"):
+            c.set_choice(key, mode, k, ew)
+        pair = synth.vga_pair(seed=5, H=96, W=128)
+        conditioned_check(c, pair, f"tile width {mode}/{k}/{ew}", levels=3, warps=3, iters=40)
+    finally:
+        c.close()
+
+
+def test_tuning_choice_rows_are_checked(ctx):
+    with pytest.raises(fm.FlowError):
+        ctx.set_choice("96x128i40", 1, 0, 16)      # one-pass strip height: 0, 2, 4 or 8
+    with pytest.raises(fm.FlowError):
+        ctx.set_choice("96x128i40", 4, 4, 8)       # tile width: 0 or 16..512
+
+
 @pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8), (7, 4), (6, 2)])
 def test_every_kernel_mode_keeps_parity(ctx, mode, k):
     """Each forced kernel choice (one-pass; tiles of 256 / 1024 / small 1024 threads) meets the bar."""
