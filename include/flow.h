@@ -247,8 +247,9 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
 
 /* Set the iteration-kernel choice of one level shape (H x W, with or without the w / p block, iters
  * per warp) by hand, as flow_autotune would.  pdr_sweeps = 0: the ADMM family, mode 1 = one-pass
- * kernel with `rows` rows per strip (0 = built-in; 2, 4 or 8), 2 / 3 / 4 / 7 / 6 = K-iteration tiles
- * of 256 / 1024 threads / small tiles of 1024 / 512 / 256 threads with K iterations per launch (K = 0:
+ * kernel with `rows` rows per strip (0 = built-in; 2, 4 or 8), 2 / 3 / 4 / 7 / 6 / 8 / 9 = K-iteration
+ * tiles of 256 / 1024 threads / small tiles of 1024 / 512 / 256 threads / one-pixel tiles of 1024 /
+ * 512 threads with K iterations per launch (K = 0:
  * resident if the level fits one tile, else the built-in K) and `rows` the target width of a tile's
  * extended region (0 = built-in, else 16..512).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
  * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident); pdr_sweeps = -1:
@@ -269,7 +270,8 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *   "tb_mode"     iteration kernel per level: 0 built-in choice (levels that fit one 1024-thread tile
  *                 stay resident for a whole warp, larger ones use the one-pass kernel), 1 one-pass
  *                 kernel only, 2 K-iteration tiles of 256 threads, 3 of 1024 threads, 4 / 7 / 6
- *                 small tiles (2 pixels per thread) of 1024 / 512 / 256 threads.
+ *                 small tiles (2 pixels per thread) of 1024 / 512 / 256 threads, 8 / 9 one-pixel
+ *                 tiles of 1024 / 512 threads.
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
  *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
  *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads.
@@ -333,10 +335,12 @@ flow_status flow_op_admm_iter(const flow_admm_state* in, const flow_admm_state* 
 
 /* `iters` iterations in ONE launch of the temporally blocked tile kernel (the solver's path for
  * levels that do not need the one-pass kernel), increment form only (in->u0, in->v0 set).
- * threads: 256 (6 pixels per thread, 4 with beta > 0), 1024 (4, 3 with beta > 0), or the small-tile
- * codes 1025 / 513 / 257 (1024 / 512 / 256 threads, 2 pixels per thread; 513 and 257 with order 0
- * only); tile_h x tile_w: output tile; each tile's extended region
- * min(H, tile_h + 3 iters) x min(W, tile_w + 3 iters) must fit that capacity, else FLOW_E_INVAL.
+ * threads: 256 (6 pixels per thread, 4 with beta > 0), 1024 (4, 3 with beta > 0), the small-tile
+ * codes 1025 / 513 / 257 (1024 / 512 / 256 threads, 2 pixels per thread) or the one-pixel codes
+ * 1026 / 514 (1024 / 512 threads, 1 pixel per thread); codes 513, 257, 1026 and 514 with order 0
+ * only.  tile_h x tile_w: output tile; each tile's extended region (halo iters + 1 above and to the
+ * left, iters below and to the right) min(H, tile_h + 2 iters + 1) x min(W, tile_w + 2 iters + 1)
+ * must fit that capacity, else FLOW_E_INVAL.
  * order: 0 = one work-group per tile (tile from the work-group index), 1 = persistent work-groups
  * pulling tiles from one counter, 2 = the same with 8 per-XCD sub-queues (the batched path's work
  * queue), 3 = one work-group per entry of a tile table in XCD order (the batched path's table

@@ -38,6 +38,8 @@ constexpr int kTbPptW = 4;           // with the w / p block
 constexpr int kTbPptL = 4;           // 1024 threads (at most 128 VGPRs per thread)
 constexpr int kTbPptLW = 3;
 constexpr int kTbPptSmall = 2;       // 1024 threads on small tiles (work-group size code 1025)
+// Work-group size codes 1026 / 514: 1024 / 512 threads with one pixel each, for latency-bound levels
+// (twice the wavefronts of codes 513 / 257 on the same extended region).
 // Halo of a K-iteration tile: per iteration the dual field q reaches one cell further in every
 // direction and the multipliers follow q's divergence (left / above) at the end of the iteration,
 // so after K iterations the iterate of an output pixel depends on the launch's input within K + 1

@@ -360,6 +360,8 @@ int tb_capacity(bool has_w, int nt) {
     if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
     if (nt == 513) return 512 * kTbPptSmall;     // 512 threads, small tiles
     if (nt == 257) return 256 * kTbPptSmall;     // 256 threads, small tiles
+    if (nt == 1026) return 1024;                  // 1024 threads, one pixel each
+    if (nt == 514) return 512;                    // 512 threads, one pixel each
     return 256 * (has_w ? kTbPptW : kTbPpt);
 }
 
@@ -378,6 +380,15 @@ void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s
     } else if (nt == 1025) {
         if (has_w) launch_one<true, 1024, kTbPptSmall>(a, grid, s);
         else launch_one<false, 1024, kTbPptSmall>(a, grid, s);
+    } else if (nt == 1026 || nt == 514) {
+        // one pixel per thread, for latency-bound levels: direct tiling only
+        if (nt == 1026) {
+            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
+            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
+        } else {
+            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 512, 1>), dim3(grid), dim3(512), 0, s, a);
+            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 512, 1>), dim3(grid), dim3(512), 0, s, a);
+        }
     } else if (nt == 513 || nt == 257) {
         // small work-groups for latency-bound levels: direct tiling only
         if (nt == 513) {

@@ -140,7 +140,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             c.tb = false;
             cands.push_back(c);
         }
-        for (int mode : {2, 4, 3, 7, 6})
+        for (int mode : {2, 4, 3, 7, 6, 8, 9})
             for (int K : {2, 4, 8, 16})
                 for (int ew : {0, 32, 48, 64, 96}) {             // extended tile width (0: built-in)
                     LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K, ew);
@@ -215,7 +215,7 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
                                         int32_t pdr_sweeps, int32_t mode, int32_t K, int32_t rows) {
     if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
-    if (mode < 1 || mode > 7) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6, 7 (tiles) or 5 (pDR tiles)");
+    if (mode < 1 || mode > 9) return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6..9 (tiles) or 5 (pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (mode == 1 && rows != 0 && rows != 2 && rows != 4 && rows != 8)
         return fail(FLOW_E_INVAL, "rows (one-pass strip height) must be 0, 2, 4 or 8");
@@ -226,7 +226,7 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6)
         return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads)");
     if (pdr_sweeps == 0 && mode == 5) return fail(FLOW_E_INVAL, "mode 5 is a pDR mode");
-    if (mode > 7) return fail(FLOW_E_INVAL, "unknown mode");
+    if (pdr_sweeps != 0 && mode > 6) return fail(FLOW_E_INVAL, "modes 7, 8, 9 are ADMM modes");
     TunedChoice c;
     c.mode = mode;
     c.K = K;

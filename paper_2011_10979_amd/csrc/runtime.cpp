@@ -621,9 +621,9 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "tb_mode") == 0) {
-        if (value < 0 || value > 7 || value == 5)
+        if (value < 0 || value > 9 || value == 5)
             return fail(FLOW_E_INVAL, "tb_mode: 0 built-in, 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 / 7 / 6 small "
-                                      "tiles of 1024 / 512 / 256 threads");
+                                      "tiles of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads");
         g_tb_mode = (int)value;
         return FLOW_OK;
     }
@@ -834,12 +834,13 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
     if (!in || !out || !Ix || !Iy || !It || !at) return fail(FLOW_E_INVAL, "NULL pointer");
     if (!in->u0 || !in->v0) return fail(FLOW_E_INVAL, "the tile kernel runs the increment form: u0, v0 required");
     if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
-    if (threads != 256 && threads != 1024 && threads != 1025 && threads != 513 && threads != 257)
-        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or a small-tile code 1025 / 513 / 257");
+    if (threads != 256 && threads != 1024 && threads != 1025 && threads != 513 && threads != 257 && threads != 1026 &&
+        threads != 514)
+        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or a small-tile code 1025 / 513 / 257 / 1026 / 514");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     if (order < 0 || order > 3) return fail(FLOW_E_INVAL, "order must be 0, 1, 2 or 3");
-    if ((threads == 513 || threads == 257) && order != 0)
-        return fail(FLOW_E_INVAL, "the 512- and 256-thread small tiles run with direct tiling (order 0) only");
+    if ((threads == 513 || threads == 257 || threads == 1026 || threads == 514) && order != 0)
+        return fail(FLOW_E_INVAL, "work-group codes 513, 257, 1026 and 514 run with direct tiling (order 0) only");
     const bool hw = p->beta > 0;
     const int cap = tb_capacity(hw, threads);
     const int64_t halo = (int64_t)tb_halo_lo(iters) + tb_halo_hi(iters);

@@ -9,7 +9,7 @@
 namespace flowmi {
 
 int g_tb_mode = 0;   // 0 built-in, 1 one-pass only, 2 tiles of 256 threads, 3 of 1024, 4 / 7 / 6 small tiles
-                     // of 1024 / 512 / 256 threads
+                     // of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads
 int g_tb_k = 0;      // iterations per launch of tiled levels (0 = default)
 
 constexpr int kDefaultK = 4;
@@ -38,7 +38,11 @@ LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
         return P;
     }
     if (ew_target <= 0)
-        ew_target = nt == 1024 ? (hw ? 80 : 96) : (nt == 1025 ? 64 : (nt == 513 || nt == 257) ? 32 : (hw ? 32 : 48));
+        ew_target = nt == 1024 ? (hw ? 80 : 96)
+                  : nt == 1025 ? 64
+                  : (nt == 513 || nt == 257 || nt == 1026) ? 32
+                  : nt == 514 ? 24
+                  : (hw ? 32 : 48);
     int th = 0, tw = 0;
     while (K > 0 && !fit_tile(H, W, cap, K, ew_target, th, tw)) --K;
     if (K < 1) return P;
@@ -64,7 +68,8 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int
         }
         return P;
     }
-    const int nt = mode == 3 ? 1024 : mode == 4 ? 1025 : mode == 6 ? 257 : mode == 7 ? 513 : 256;
+    const int nt = mode == 3 ? 1024 : mode == 4 ? 1025 : mode == 6 ? 257 : mode == 7 ? 513
+                 : mode == 8 ? 1026 : mode == 9 ? 514 : 256;
     P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, ew);
     if (P.resident) P.K = iters;                             // the whole warp in one launch
     return P;
@@ -149,7 +154,8 @@ void fill_tb_level(TbLevel* d, const LevelPlanes& L, const float* at2) {
 }
 
 int tb_grid(const LevelTbPlan& P, int ntiles) {
-    const int per_cu = P.nt == 1024 ? 1 : P.nt == 1025 ? 2 : P.nt == 513 ? 4 : P.nt == 257 ? 8 : 4;   // residency
+    const int per_cu = P.nt == 1024 ? 1 : (P.nt == 1025 || P.nt == 1026) ? 2 : (P.nt == 513 || P.nt == 514) ? 4
+                     : P.nt == 257 ? 8 : 4;   // residency
     return std::max(1, std::min(ntiles, 256 * per_cu));
 }
 

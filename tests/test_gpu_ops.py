@@ -280,13 +280,13 @@ def test_admm_iteration_every_strip_height(rows, shape, beta):
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 6), ((37, 130), (8, 30), 3), ((101, 250), (12, 20), 4),
                                           ((60, 80), (60, 80), 9), ((64, 64), (10, 18), 1), ((33, 47), (33, 47), 20)])
 @pytest.mark.parametrize("threads,order", [(256, 0), (1024, 0), (1025, 0), (256, 1), (1024, 1), (1025, 2),
-                                           (1025, 3), (256, 2), (513, 0), (257, 0)])
+                                           (1025, 3), (256, 2), (513, 0), (257, 0), (1026, 0), (514, 0)])
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
 def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme, relax, beta):
     """K iterations of the temporally blocked tile kernel (halo K + 1 / K, ragged tiles, resident
     levels) against K steps of the oracle on the same increment-form state."""
     print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
-    cap = {1025: 2048, 513: 1024, 257: 512}.get(threads) or (1024 * (3 if beta > 0 else 4) if threads == 1024 else
+    cap = {1025: 2048, 513: 1024, 257: 512, 1026: 1024, 514: 512}.get(threads) or (1024 * (3 if beta > 0 else 4) if threads == 1024 else
                                                               256 * (4 if beta > 0 else 6))
     if min(shape[0], tile[0] + 2 * K + 1) * min(shape[1], tile[1] + 2 * K + 1) > cap:
         pytest.skip("tile plus halo exceeds the kernel capacity")

@@ -227,7 +227,7 @@ def test_autotuned_solve_keeps_parity():
         rep = c.autotune(96, 128, fm.Params(levels=3, warps=3, iters=40))
         assert len(rep) == 3
         for key, entry in rep.items():
-            assert entry["choice"]["mode"] in (1, 2, 3, 4, 6, 7) and entry["choice"]["us_per_iter"] > 0
+            assert entry["choice"]["mode"] in (1, 2, 3, 4, 6, 7, 8, 9) and entry["choice"]["us_per_iter"] > 0
             assert len(entry["candidates"]) >= 4
         pair = synth.vga_pair(seed=5, H=96, W=128)
         conditioned_check(c, pair, "autotuned 96x128", levels=3, warps=3, iters=40)
@@ -235,7 +235,8 @@ def test_autotuned_solve_keeps_parity():
         c.close()
 
 
-@pytest.mark.parametrize("mode,k,ew", [(4, 4, 32), (4, 8, 48), (7, 4, 96), (6, 2, 16), (2, 4, 64)])
+@pytest.mark.parametrize("mode,k,ew", [(4, 4, 32), (4, 8, 48), (7, 4, 96), (6, 2, 16), (2, 4, 64), (8, 8, 24),
+                                       (9, 4, 40)])
 def test_tuned_tile_widths_keep_parity(mode, k, ew):
     """A tuned choice may also set the width of the tiles' extended region (tuning field `rows` of
     the tile modes); any width gives the same iteration, so the solve still meets the oracle bar."""
@@ -257,7 +258,7 @@ def test_tuning_choice_rows_are_checked(ctx):
         ctx.set_choice("96x128i40", 4, 4, 8)       # tile width: 0 or 16..512
 
 
-@pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8), (7, 4), (6, 2)])
+@pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8), (7, 4), (6, 2), (8, 4), (9, 2)])
 def test_every_kernel_mode_keeps_parity(ctx, mode, k):
     """Each forced kernel choice (one-pass; tiles of 256 / 1024 / small 1024 threads) meets the bar."""
     print(f"[case] forced mode {mode} K {k}", flush=True)
