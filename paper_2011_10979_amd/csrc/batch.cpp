@@ -322,6 +322,8 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
         }
         S.init = T.launch(init, bl);
         int cur = 0;
+        std::vector<int> lbl;
+        for (int k : S.pairs) lbl.push_back(lin_blocks_of(P->L[k][l].H, P->L[k][l].W));
         for (int w = 0; w < p.warps; ++w) {
             std::vector<LinArgs> lin;
             for (int k : S.pairs) {
@@ -345,7 +347,7 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 la.zero_v = L.st[cur][2];
                 lin.push_back(la);
             }
-            S.lin.push_back(T.launch(lin, bl));
+            S.lin.push_back(T.launch(lin, lbl));
             cur ^= S.lpw & 1;
         }
         final_cur_of_stage[l] = cur;

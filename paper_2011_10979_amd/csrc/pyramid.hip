@@ -93,12 +93,15 @@ __device__ __forceinline__ float wave_max(float x) {
 template <typename T>
 __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by) {
     const int j = bx * 64 + (threadIdx.x & 63);
-    const int i = by * 4 + (threadIdx.x >> 6);
     const T* I0 = (const T*)a.I0;
     const T* I1 = (const T*)a.I1;
     const T* Dx = (const T*)a.Dx;
     const T* Dy = (const T*)a.Dy;
     float ms = 0.f;
+    const int rows = lin_rows(a.H, a.W);
+#pragma unroll 4
+    for (int r = 0; r < rows / 4; ++r) {
+    const int i = by * rows + 4 * r + (threadIdx.x >> 6);
     if (i < a.H && j < a.W) {
         const int64_t off = (int64_t)i * a.ld + j;
         float u0 = a.u0[off], v0 = a.v0[off];
@@ -122,7 +125,8 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
         a.It[off] = a.rel ? Ir : Ir - Ix * u0 - Iy * v0;
         if (a.zero_u) { a.zero_u[off] = 0.f; a.zero_v[off] = 0.f; }
         if (a.keep_u) { a.keep_u[off] = u0; a.keep_v[off] = v0; }
-        ms = a.beta * a.beta + Ix * Ix + Iy * Iy;
+        ms = fmaxf(ms, a.beta * a.beta + Ix * Ix + Iy * Iy);
+    }
     }
     // a~ = max M_s: wave -> block -> one atomic max per block on the float's bit pattern (exact
     // and order-independent for non-negative values); the consumer applies the 1e-12 floor.
@@ -269,8 +273,10 @@ void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int6
 }
 
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s) {
-    if (f16) hipLaunchKernelGGL(linearize_kernel<__half>, grid2d(a.H, a.W), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(linearize_kernel<float>, grid2d(a.H, a.W), dim3(256), 0, s, a);
+    const int rows = lin_rows(a.H, a.W);
+    const dim3 g((a.W + 63) / 64, (a.H + rows - 1) / rows);
+    if (f16) hipLaunchKernelGGL(linearize_kernel<__half>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(linearize_kernel<float>, g, dim3(256), 0, s, a);
 }
 
 void launch_level_init(const LevelInitArgs& a, hipStream_t s) {
@@ -284,6 +290,10 @@ void launch_upsample(const float* coarse, int64_t ldc, float* fine, int Hf, int 
 }
 
 int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
+int lin_blocks_of(int H, int W) {
+    const int rows = lin_rows(H, W);
+    return ((W + 63) / 64) * ((H + rows - 1) / rows);
+}
 
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total, bool f16, hipStream_t s) {
     if (n <= 0 || total <= 0) return;

@@ -365,7 +365,7 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         la.zero_u = L.st[q.cur][1];
         la.zero_v = L.st[q.cur][2];
         lin.push_back(la);
-        bl.push_back(blocks_of(L.H, L.W));
+        bl.push_back(lin_blocks_of(L.H, L.W));
         // descriptors in the pair's own direction: launch direction 0 reads state buffer q.cur
         TbLevel d[2];
         fill_tb_level(d, L, at2 + (q.w & 1));
