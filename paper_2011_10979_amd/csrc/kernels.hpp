@@ -43,10 +43,11 @@ constexpr float kFrameOffsetF16 = 0.5f;
 // Batched launches of one body over many items (one work-group grid per item, prefix offsets).
 enum class BatchOp { Downsample, Derivatives, Copy, Linearize, LevelInit };
 int blocks_of(int H, int W);   // 64 x 4 blocks covering an H x W plane
-// The linearisation's work-groups cover 64 x lin_rows(H, W) pixels: 16 rows (4 pixels per thread)
-// on large levels, so that a work-group issues one atomic max of a~ per 1024 pixels, and 4 rows on
-// small, latency-bound ones.
-constexpr int lin_rows(int H, int W) { return (int64_t)H * W >= (1 << 16) ? 16 : 4; }
+// The linearisation's work-groups have 1024 threads and cover 64 x 16 pixels, one per thread: a~ is
+// one atomic max per work-group on one word, and same-word atomics serialise, so a work-group of
+// 256 threads per 256 pixels spent longer on them than on its memory traffic.
+constexpr int kLinThreads = 1024;
+constexpr int kLinRows = kLinThreads / 64;
 int lin_blocks_of(int H, int W);
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total_blocks, bool f16, hipStream_t s);
 

@@ -98,10 +98,7 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
     const T* Dx = (const T*)a.Dx;
     const T* Dy = (const T*)a.Dy;
     float ms = 0.f;
-    const int rows = lin_rows(a.H, a.W);
-#pragma unroll 4
-    for (int r = 0; r < rows / 4; ++r) {
-    const int i = by * rows + 4 * r + (threadIdx.x >> 6);
+    const int i = by * kLinRows + (threadIdx.x >> 6);
     if (i < a.H && j < a.W) {
         const int64_t off = (int64_t)i * a.ld + j;
         float u0 = a.u0[off], v0 = a.v0[off];
@@ -125,17 +122,18 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
         a.It[off] = a.rel ? Ir : Ir - Ix * u0 - Iy * v0;
         if (a.zero_u) { a.zero_u[off] = 0.f; a.zero_v[off] = 0.f; }
         if (a.keep_u) { a.keep_u[off] = u0; a.keep_v[off] = v0; }
-        ms = fmaxf(ms, a.beta * a.beta + Ix * Ix + Iy * Iy);
-    }
+        ms = a.beta * a.beta + Ix * Ix + Iy * Iy;
     }
     // a~ = max M_s: wave -> block -> one atomic max per block on the float's bit pattern (exact
     // and order-independent for non-negative values); the consumer applies the 1e-12 floor.
-    __shared__ float smax[4];
+    __shared__ float smax[kLinRows];
     ms = wave_max(ms);
     if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = ms;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const float bm = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+        float bm = smax[0];
+#pragma unroll
+        for (int w = 1; w < kLinRows; ++w) bm = fmaxf(bm, smax[w]);
         atomicMax((unsigned int*)a.at, __float_as_uint(bm));
         if (a.at_clear && bx == 0 && by == 0) *a.at_clear = 0.f;
     }
@@ -197,7 +195,7 @@ template <typename T> __global__ __launch_bounds__(256) void derivatives_kernel(
 template <typename T> __global__ __launch_bounds__(256) void copy_kernel(CopyArgs a) {
     copy_body<T>(a, blockIdx.x, blockIdx.y);
 }
-template <typename T> __global__ __launch_bounds__(256) void linearize_kernel(LinArgs a) {
+template <typename T> __global__ __launch_bounds__(kLinThreads) void linearize_kernel(LinArgs a) {
     linearize_body<T>(a, blockIdx.x, blockIdx.y);
 }
 __global__ __launch_bounds__(256) void level_init_kernel(LevelInitArgs a) {
@@ -229,8 +227,8 @@ __device__ __forceinline__ int find_item(const int* __restrict__ off, int n, int
 template <typename A> __device__ __forceinline__ int grid_w(const A& a) { return (a.W + 63) / 64; }
 template <> __device__ __forceinline__ int grid_w<DownArgs>(const DownArgs& a) { return ((a.W + 1) / 2 + 63) / 64; }
 
-template <typename A, void (*BODY)(const A&, int, int)>
-__global__ __launch_bounds__(256) void batched_kernel(const A* __restrict__ items, const int* __restrict__ off, int n) {
+template <typename A, void (*BODY)(const A&, int, int), int NT = 256>
+__global__ __launch_bounds__(NT) void batched_kernel(const A* __restrict__ items, const int* __restrict__ off, int n) {
     const int k = find_item(off, n, blockIdx.x);
     const A a = items[k];
     const int local = blockIdx.x - off[k];
@@ -238,9 +236,9 @@ __global__ __launch_bounds__(256) void batched_kernel(const A* __restrict__ item
     BODY(a, local % gx, local / gx);
 }
 
-template <typename A, void (*BODY)(const A&, int, int)>
+template <typename A, void (*BODY)(const A&, int, int), int NT = 256>
 void launch_b(const void* items, const int* off, int n, int total, hipStream_t s) {
-    hipLaunchKernelGGL((batched_kernel<A, BODY>), dim3(total), dim3(256), 0, s, (const A*)items, off, n);
+    hipLaunchKernelGGL((batched_kernel<A, BODY, NT>), dim3(total), dim3(NT), 0, s, (const A*)items, off, n);
 }
 
 }  // namespace
@@ -273,10 +271,9 @@ void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int6
 }
 
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s) {
-    const int rows = lin_rows(a.H, a.W);
-    const dim3 g((a.W + 63) / 64, (a.H + rows - 1) / rows);
-    if (f16) hipLaunchKernelGGL(linearize_kernel<__half>, g, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(linearize_kernel<float>, g, dim3(256), 0, s, a);
+    const dim3 g((a.W + 63) / 64, (a.H + kLinRows - 1) / kLinRows);
+    if (f16) hipLaunchKernelGGL(linearize_kernel<__half>, g, dim3(kLinThreads), 0, s, a);
+    else hipLaunchKernelGGL(linearize_kernel<float>, g, dim3(kLinThreads), 0, s, a);
 }
 
 void launch_level_init(const LevelInitArgs& a, hipStream_t s) {
@@ -290,10 +287,7 @@ void launch_upsample(const float* coarse, int64_t ldc, float* fine, int Hf, int 
 }
 
 int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
-int lin_blocks_of(int H, int W) {
-    const int rows = lin_rows(H, W);
-    return ((W + 63) / 64) * ((H + rows - 1) / rows);
-}
+int lin_blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + kLinRows - 1) / kLinRows); }
 
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total, bool f16, hipStream_t s) {
     if (n <= 0 || total <= 0) return;
@@ -311,8 +305,8 @@ void launch_batched(BatchOp op, const void* items, const int* off, int n, int to
             else launch_b<CopyArgs, copy_body<float>>(items, off, n, total, s);
             break;
         case BatchOp::Linearize:
-            if (f16) launch_b<LinArgs, linearize_body<__half>>(items, off, n, total, s);
-            else launch_b<LinArgs, linearize_body<float>>(items, off, n, total, s);
+            if (f16) launch_b<LinArgs, linearize_body<__half>, kLinThreads>(items, off, n, total, s);
+            else launch_b<LinArgs, linearize_body<float>, kLinThreads>(items, off, n, total, s);
             break;
         case BatchOp::LevelInit: launch_b<LevelInitArgs, level_init_body>(items, off, n, total, s); break;
     }
