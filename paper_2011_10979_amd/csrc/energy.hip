@@ -28,8 +28,16 @@ __device__ __forceinline__ void energy_body(const EnergyArgs& a, int blk, int nb
     const bool has_w = a.beta != 0.f;
     const int64_t npix = (int64_t)a.H * a.W;
     const float tau = a.pdr_tau;
+    const bool small = npix < ((int64_t)1 << 31);   // 32-bit index arithmetic (64-bit division is slow)
     for (int64_t idx = (int64_t)blk * 256 + threadIdx.x; idx < npix; idx += (int64_t)nblk * 256) {
-        const int i = (int)(idx / a.W), j = (int)(idx % a.W);
+        int i, j;
+        if (small) {
+            i = (int)((uint32_t)idx / (uint32_t)a.W);
+            j = (int)idx - i * a.W;
+        } else {
+            i = (int)(idx / a.W);
+            j = (int)(idx % a.W);
+        }
         const int64_t o = (int64_t)i * a.ld + j;
         const bool hr = j < a.W - 1, hd = i < a.H - 1, hl = j > 0, hu = i > 0;
         // flow value at a cell: u, or u + du when the flow is given as base + increment
@@ -116,19 +124,27 @@ __global__ __launch_bounds__(256) void energy_kernel(EnergyArgs a) { energy_body
 // pairwise tree in LDS combines the 256 sums, so the result is reproducible bit for bit.
 __device__ __forceinline__ void energy_final_body(const double* __restrict__ partial, int nblocks,
                                                   double* __restrict__ out) {
-    __shared__ double sm[256];
-    for (int k = 0; k < kEnergyTerms; ++k) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) t += partial[b * kEnergyTerms + k];
-        sm[threadIdx.x] = t;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-            __syncthreads();
+    // every term at once: thread t adds the partials of blocks t, t + 256, ... in order, then one
+    // fixed pairwise tree over the threads (the same order for every term)
+    __shared__ double sm[kEnergyTerms][256];
+    double t[kEnergyTerms];
+#pragma unroll
+    for (int k = 0; k < kEnergyTerms; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int k = 0; k < kEnergyTerms; ++k) t[k] += partial[b * kEnergyTerms + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kEnergyTerms; ++k) sm[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < kEnergyTerms; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
         }
-        if (threadIdx.x == 0) out[k] = sm[0];
         __syncthreads();
     }
+    if ((int)threadIdx.x < kEnergyTerms) out[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(256) void energy_final_kernel(const double* __restrict__ partial, int nblocks,

@@ -141,7 +141,7 @@ struct EnergyArgs {
     double* out;                     // kEnergyTerms doubles
 };
 constexpr int kEnergyTerms = 8;      // tv, data, dual, residual^2, g_tv, g_data, lam_r, nonfinite
-constexpr int kEnergyBlocks = 512;
+constexpr int kEnergyBlocks = 1024;
 void launch_energy(const EnergyArgs& a, hipStream_t s);
 int energy_blocks(int H, int W);     // work-groups of the first energy kernel for an H x W level
 // items[k] owns work-groups [off[k], off[k+1]) (off[k+1] - off[k] = energy_blocks of its level);
