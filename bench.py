@@ -29,6 +29,7 @@ Other modes:
                     probabilities 0.3, 0.3, 0.2, 0.1, 0.1), 2000 requests after 200 warm-up ones, served
                     by the continuous-batching engine (8 GiB budget); value = completed pairs/s, with
                     p50 / p99 latency; the same trace through a one-at-a-time plain-solve server beside it
+  --mode batch --batch-only [--no-autotune]   the batched solve alone (for profiler runs)
   --mode compare    every scheme of Sec. 4 (pADMM, rpADMMI, rpADMMII, Zach-pADMM, pDR, ALG1) on the
                     same synthetic pair (--pair vga or hd): time per solve, endpoint / angular error
                     against the ground-truth motion, energy and gap at equal iteration counts
@@ -91,24 +92,40 @@ def measured_traffic(workload):
     return e.get("bytes_per_launch")
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count, as the kernel reports them."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model} ({os.cpu_count()} logical CPUs)"
+
+
 def cpu_baseline(pair, args):
     """Time the oracle on a bounded sample of the workload: the full pyramid and warps with
-    `cpu_iters` iterations per warp (default: all of them), solved `cpu_reps` times."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    `cpu_iters` iterations per warp (default: all of them), solved `cpu_reps` times, with every
+    BLAS / OpenMP pool held to one thread."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import Params, solve_pair
     from oracle.pyramid import level_shapes
     I0 = pair.I0.astype(np.float32).astype(np.float64)
     I1 = pair.I1.astype(np.float32).astype(np.float64)
     iters = args.cpu_iters or args.iters
     p = Params(scheme=args.scheme, levels=args.levels, warps=args.warps, iters=iters)
-    t0 = time.perf_counter()
-    for _ in range(args.cpu_reps):
-        solve_pair(I0, I1, p)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_reps):
+            solve_pair(I0, I1, p)
+        dt = time.perf_counter() - t0
     px = sum(h * w for h, w in level_shapes(I0.shape[0], I0.shape[1], args.levels))
     pxi = px * args.warps * iters * args.cpu_reps
-    return {"value": pxi / dt / 1e9, "unit": "Gpixel-iter/s", "cores": 1, "kind": "oracle",
+    return {"value": pxi / dt / 1e9, "unit": "Gpixel-iter/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": f"{args.cpu_reps} x the {I0.shape[1]}x{I0.shape[0]} solve, {args.levels} levels x {args.warps} "
                       f"warps x {iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
 
@@ -182,6 +199,12 @@ def run_batch(args):
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     value = px_iter / (ms_step * 1e-3) / 1e9
     print(f"[bench] batched: {ms_step:.2f} ms per batch, {value:.2f} Gpx-iter/s", file=sys.stderr, flush=True)
+    if args.batch_only:                      # the batched solve alone (for profiler runs)
+        print(json.dumps({"metric": "Gpixel-iter/s (batched solves only)", "value": round(value, 3),
+                          "unit": "Gpixel-iter/s", "ms_per_step": round(ms_step, 3), "steps": args.steps,
+                          "autotuned": not args.no_autotune, "px_iter_per_step": px_iter}), flush=True)
+        ctx.close()
+        return
 
     # per-stage timing (direct launches, events around each stage's iterations)
     ctx.set_stats(True)
@@ -250,7 +273,7 @@ def run_batch(args):
                 pxi += h * w * args.warps * args.iters
                 h, w = (h + 1) // 2, (w + 1) // 2
         cpu = {"value": round(len(jobs) / dt, 3), "unit": "pairs/s", "cores": min(workers, len(jobs)),
-               "kind": "oracle", "Gpx_iter_s": pxi / dt / 1e9,
+               "kind": "oracle", "Gpx_iter_s": pxi / dt / 1e9, "host": host_cpu(),
                "sample": f"the {len(jobs)} smallest pairs of the batch, one process per pair "
                          f"({pxi / 1e6:.0f} M px-iter, {dt:.1f} s, FP64 NumPy)"}
     line = {
@@ -547,6 +570,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batch mode: time the batched solve only (no plain solves, per-stage timing or oracle check)")
     ap.add_argument("--save-tuning", default=None)
     ap.add_argument("--load-tuning", default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
