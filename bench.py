@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="set a library tuning knob (flow_tune_set) before the run, e.g. serve_graph=0")
     ap.add_argument("--batch-only", action="store_true",
                     help="batch mode: time the batched solve only (no plain solves, per-stage timing or oracle check)")
     ap.add_argument("--save-tuning", default=None)
@@ -598,6 +600,9 @@ def main():
     import synth
     import paper_2011_10979_amd as fm
 
+    for kv in args.tune:
+        key, _, val = kv.partition("=")
+        fm.set_tuning(key, int(val))
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, args.steps)
         return

@@ -182,6 +182,8 @@ typedef struct flow_server_stats {
     int32_t peak_active;
     uint64_t arena_bytes;           /* the serving budget (pairs' working sets) */
     uint64_t bytes_in_use, peak_bytes_in_use;
+    int64_t graphs_captured;        /* graphs of an epoch's tile launches captured so far (one per
+                                       buffer set and stage choice; every other epoch replays one) */
 } flow_server_stats;
 
 /* Device bytes of one pair's working set (pyramids, linearisation, scheme state of every level) for
@@ -281,6 +283,8 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *   "batch_k"     iterations per batched tile launch (0 = tuned / built-in; lowered where a level's
  *                 tiles cannot hold the halo).
  *   "batch_ew"    extended tile width target of batched tiles (0 = tuned / built-in, else 16..512).
+ *   "serve_graph" serving epochs: 1 (default) replay their tile launches from captured graphs, 0
+ *                 launch them directly (the same kernels and results).
  * FLOW_E_INVAL for an unknown key or value.  Not thread-safe against concurrent solves. */
 flow_status flow_tune_set(const char* key, int64_t value);
 

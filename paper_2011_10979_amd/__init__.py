@@ -62,7 +62,7 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("epochs", ctypes.c_int64), ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
                 ("peak_active", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
-                ("peak_bytes_in_use", ctypes.c_uint64)]
+                ("peak_bytes_in_use", ctypes.c_uint64), ("graphs_captured", ctypes.c_int64)]
 
 
 class _Pair(ctypes.Structure):

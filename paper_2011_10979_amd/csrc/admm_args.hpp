@@ -61,6 +61,8 @@ struct TbLevel {
 struct TbArgs {
     const TbTile* tiles;
     int ntiles;
+    const int* ntiles_dev;           // table / queue order: if set, the tile count is read from device
+                                     // memory (a launch replayed from a graph over tables that change)
     const TbLevel* levels;           // two descriptors per (pair, level): [2 * id + dir]
     int dir;                         // which ping-pong direction this launch uses
     int K;                           // iterations of this launch (halo K + 1 top/left, K bottom/right)

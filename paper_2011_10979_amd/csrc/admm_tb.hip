@@ -311,13 +311,19 @@ __global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
     process_tile<HAS_W, NT, PPT>(a, T, a.lvl, S);
 }
 
-// Many levels (batched pairs), table order: work-group b takes tile xcd_tile(b) of the table, so
-// each XCD works through a contiguous run of tiles (neighbours share its L2).
+// Many levels (batched pairs), table order: one tile per work-group.  The n tiles are split into 8
+// contiguous runs, one per XCD (work-groups are dealt to the XCDs round-robin, so XCD x holds
+// work-groups b = x (mod 8)): neighbouring tiles, which re-read each other's halo, share its L2,
+// and a grid larger than the table (a launch replayed from a graph over changing tables) still
+// spreads a small table over every XCD.  The grid is a multiple of 8 of at least n.
 template <bool HAS_W, int NT, int PPT>
 __global__ __launch_bounds__(NT) void admm_tb_table_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    if (t >= a.ntiles) return;
+    const int n = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
+    const int per = (n + 7) >> 3;                      // tiles per XCD
+    const int x = blockIdx.x & 7, y = blockIdx.x >> 3;
+    const int t = x * per + y;
+    if (y >= per || t >= n) return;
     const TbTile T = a.tiles[t];
     process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
 }
@@ -329,9 +335,10 @@ template <bool HAS_W, int NT, int PPT>
 __global__ __launch_bounds__(NT) void admm_tb_queue_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
     __shared__ int s_tile;
+    const int n = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
     const int x = blockIdx.x % a.nq;
-    const int lo = (int)((int64_t)a.ntiles * x / a.nq);
-    const int hi = (int)((int64_t)a.ntiles * (x + 1) / a.nq);
+    const int lo = (int)((int64_t)n * x / a.nq);
+    const int hi = (int)((int64_t)n * (x + 1) / a.nq);
     for (;;) {
         if (threadIdx.x == 0) s_tile = lo + (int)(atomicAdd(a.queue + x, 1u) - a.queue_base);
         __syncthreads();

@@ -93,13 +93,15 @@ int tile_grid(const StageChoice& ch, int ntiles) {
 }
 
 int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* descs, const StageChoice& ch,
-                      const flow_params& p, int at_slot, int dir0, unsigned* counters, hipStream_t s) {
+                      const flow_params& p, int at_slot, int dir0, unsigned* counters, hipStream_t s,
+                      const int* ntiles_dev) {
     const bool hw = p.beta > 0;
     AdmmIterArgs co{};
     fill_admm_coeffs(co, p);
     TbArgs a{};
     a.tiles = tiles;
     a.ntiles = ntiles;
+    a.ntiles_dev = ntiles_dev;
     a.levels = descs;
     a.at_slot = at_slot;
     a.c = co.c; a.lam = co.lam; a.beta = co.beta; a.inv_ac = co.inv_ac; a.c_rho_s = co.c_rho_s;
@@ -117,7 +119,7 @@ int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* 
             a.queue = nullptr;
             a.nq = 1;
         }
-        if (ntiles > 0) launch_admm_tb(a, hw, kBatchNt, grid, s);
+        if (ntiles > 0 || ntiles_dev) launch_admm_tb(a, hw, kBatchNt, grid, s);
         dir ^= 1;
         k += kk;
         ++li;

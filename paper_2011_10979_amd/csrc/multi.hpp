@@ -86,9 +86,12 @@ StageChoice fit_stage_choice(StageChoice c, const Shapes& s, bool hw);
 void level_tiles(int H, int W, bool hw, const StageChoice& ch, int desc, std::vector<TbTile>& out);
 // The K-iteration launches of one warp over `ntiles` tiles (table at `tiles`, descriptors at
 // `descs`, launch direction 0, 1, 0, ... starting from `dir0`); queue order uses kNq counters per
-// launch from `counters` (zeroed by the caller).  Returns the direction after the launches.
+// launch from `counters` (zeroed by the caller).  With `ntiles_dev` the kernels read the tile count
+// there instead (launches that a graph replays over changing tables).  Returns the direction after
+// the launches.
 int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* descs, const StageChoice& ch,
-                      const flow_params& p, int at_slot, int dir0, unsigned* counters, hipStream_t s);
+                      const flow_params& p, int at_slot, int dir0, unsigned* counters, hipStream_t s,
+                      const int* ntiles_dev = nullptr);
 int tile_grid(const StageChoice& ch, int ntiles);
 // Checks of one caller pair (shape, pitches, device extents); `who` prefixes messages.
 flow_status validate_pair(const flow_pair& q, const flow_params& p, const std::string& who);

@@ -653,6 +653,11 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         g_batch_k = (int)value;
         return FLOW_OK;
     }
+    if (std::strcmp(key, "serve_graph") == 0) {
+        if (value != 0 && value != 1) return fail(FLOW_E_INVAL, "serve_graph: 0 direct launches, 1 graph replay");
+        g_serve_graph = (int)value;
+        return FLOW_OK;
+    }
     if (std::strcmp(key, "batch_ew") == 0) {
         if (value != 0 && (value < 16 || value > 512)) return fail(FLOW_E_INVAL, "batch_ew: 0 (tuned / built-in) or 16 .. 512");
         g_batch_ew = (int)value;

@@ -14,7 +14,12 @@
 // a served result is bitwise the same alone or in any mix.
 //
 // Epochs are double-buffered: the host builds epoch e + 1's tables while the device runs epoch e,
-// and blocks only when it needs epoch e - 1's buffers again.
+// and blocks only when it needs epoch e - 1's buffers again.  An epoch's K-iteration tile launches
+// (about iters / K of them, the bulk of its launches) are replayed from a captured graph: the tile
+// count, the level descriptors and the tiles sit at fixed offsets of the buffer set's table, the
+// kernels read the tile count there, and the launches use a fixed persistent grid, so one graph
+// per buffer set and stage choice (K, order, width) serves every epoch; the few elementwise
+// launches, whose grids follow the epoch's item tables, stay direct.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,6 +34,8 @@
 #include "runtime.hpp"
 
 namespace flowmi {
+
+int g_serve_graph = 1;
 
 #define HIP_TRY(expr)                                           \
     do {                                                        \
@@ -114,6 +121,20 @@ struct flow_server {
     size_t at_off = 0, epart_off = 0, eout_off = 0, cnt_off = 0;
     DevBuf tab[2];
     PinnedBuf htab[2], he[2];
+    // fixed offsets in an epoch's table: the tile count at 0, the level descriptors at kDescsAt
+    // (room for two per pair in flight), the tiles at tiles_at()
+    static constexpr size_t kDescsAt = 256;
+    size_t tiles_at() const {
+        return (kDescsAt + sizeof(TbLevel) * 2 * (size_t)max_active + 255) & ~(size_t)255;
+    }
+    hipStream_t cs = nullptr;      // capture stream (default priority)
+    struct TileGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<std::tuple<int, int, int, int, int>, TileGraph> graphs[2];   // (K, order, ew, launches, grid)
+    void drop_graphs(int b);
+    flow_status tile_launches(int b, const StageChoice& ch, int ntiles, int lpw, unsigned* d_cnt);
     Epoch ep[2];
     std::deque<uint64_t> queue;
     std::map<uint64_t, Req> reqs;
@@ -153,12 +174,65 @@ flow_status flow_server::init(const flow_params& prm, size_t budget, int maxa, h
         if (r != FLOW_OK) return r;
     }
     for (int k = maxa - 1; k >= 0; --k) free_slots.push_back(k);
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     st.arena_bytes = budget;
+    return FLOW_OK;
+}
+
+void flow_server::drop_graphs(int b) {
+    for (auto& kv : graphs[b]) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+    }
+    graphs[b].clear();
+}
+
+// The epoch's tile launches over the tables of buffer set b (already uploaded on s): replayed from
+// the graph of this stage choice, captured on first use, or launched directly.
+flow_status flow_server::tile_launches(int b, const StageChoice& ch, int ntiles, int lpw, unsigned* d_cnt) {
+    const TbTile* tiles = (const TbTile*)(tab[b].d + tiles_at());
+    const TbLevel* descs = (const TbLevel*)(tab[b].d + kDescsAt);
+    if (!g_serve_graph) {
+        if (ch.order == ORDER_QUEUE) launch_reset_u32(d_cnt, lpw * kNq, s);
+        enqueue_tile_warp(tiles, ntiles, tile_grid(ch, ntiles), descs, ch, p, 0, 0, d_cnt, s);
+        return FLOW_OK;
+    }
+    // the grid: 512 work-groups (two of 1024 threads per CU) pulling from the queues, or for table
+    // order one work-group per tile, rounded up to a power of two (at least 64) so that a few
+    // graphs cover every table size and at most half of a launch's work-groups exit at once
+    int grid = 512;
+    if (ch.order != ORDER_QUEUE) {
+        grid = 64;
+        while (grid < ntiles) grid *= 2;
+    }
+    const auto key = std::make_tuple(ch.K, ch.order, ch.ew, lpw, grid);
+    auto it = graphs[b].find(key);
+    if (it == graphs[b].end()) {
+        TileGraph g;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (ch.order == ORDER_QUEUE) launch_reset_u32(d_cnt, lpw * kNq, cs);
+        enqueue_tile_warp(tiles, 0, grid, descs, ch, p, 0, 0, d_cnt, cs, (const int*)tab[b].d);
+        hipError_t e = hipStreamEndCapture(cs, &g.graph);
+        if (e != hipSuccess) {
+            if (g.graph) hipGraphDestroy(g.graph);
+            return hip_fail(e, "hipStreamEndCapture(serving tile launches)");
+        }
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g.graph);
+            return hip_fail(e, "hipGraphInstantiate(serving tile launches)");
+        }
+        it = graphs[b].emplace(key, g).first;
+        st.graphs_captured++;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, s));
     return FLOW_OK;
 }
 
 flow_server::~flow_server() {
     if (s) hipStreamSynchronize(s);
+    for (int b = 0; b < 2; ++b) drop_graphs(b);
+    if (cs) hipStreamDestroy(cs);
     for (auto& x : ep)
         if (x.ev) hipEventDestroy(x.ev);
     if (arena.base) hipFree(arena.base);
@@ -255,7 +329,6 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
     unsigned* d_cnt = (unsigned*)(dyn.d + cnt_off) + (size_t)b * std::max(1, p.iters) * kNq;
 
     // ---- tables of this epoch
-    TableBuilder T;
     std::vector<CopyArgs> imp;
     std::vector<int> imp_bl;
     std::vector<DerivArgs> der;
@@ -276,24 +349,20 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             der_bl.push_back(blocks_of(L.H, L.W));
         }
     }
-    const BLaunch l_imp = T.launch(imp, imp_bl);
-    std::vector<BLaunch> l_down(std::max(1, lmax_new));
+    std::vector<std::vector<DownArgs>> down(std::max(1, lmax_new));
+    std::vector<std::vector<int>> down_bl(std::max(1, lmax_new));
     for (int l = 1; l < lmax_new; ++l) {
-        std::vector<DownArgs> it;
-        std::vector<int> bl;
         for (uint64_t t : active) {
             Req& q = reqs[t];
             if (q.imported || q.levels <= l) continue;
             const LevelPlanes& F = q.L[l - 1];
             const LevelPlanes& C = q.L[l];
-            it.push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
-            it.push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
-            bl.push_back(blocks_of(C.H, C.W));
-            bl.push_back(blocks_of(C.H, C.W));
+            down[l].push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
+            down[l].push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
+            down_bl[l].push_back(blocks_of(C.H, C.W));
+            down_bl[l].push_back(blocks_of(C.H, C.W));
         }
-        l_down[l] = T.launch(it, bl);
     }
-    const BLaunch l_der = T.launch(der, der_bl);
 
     Shapes shapes;
     for (uint64_t t : active) {
@@ -386,32 +455,47 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             finishing.push_back(active[i]);
         }
     }
+    // The epoch's table, one upload: [tile count | level descriptors (room for max_active pairs) |
+    // tiles | item tables].  The first three sit at the same offsets in every epoch, which the
+    // graphs of the tile launches rely on; a table buffer that has to grow moves, and the graphs
+    // recorded over the old one are dropped.
+    const int ntiles = (int)tiles.size();
+    TableBuilder T;
+    T.h.assign(tiles_at(), 0);
+    std::memcpy(T.h.data(), &ntiles, sizeof(int));
+    std::memcpy(T.h.data() + kDescsAt, descs.data(), sizeof(TbLevel) * descs.size());
+    const size_t tiles_off = T.put(tiles);
+    const BLaunch l_imp = T.launch(imp, imp_bl);
+    std::vector<BLaunch> l_down(std::max(1, lmax_new));
+    for (int l = 1; l < lmax_new; ++l) l_down[l] = T.launch(down[l], down_bl[l]);
+    const BLaunch l_der = T.launch(der, der_bl);
     const BLaunch l_init = T.launch(init, init_bl);
     const BLaunch l_lin = T.launch(lin, bl);
     const BLaunch l_en = T.launch(en, en_bl);
     const BLaunch l_exp = T.launch(exp, exp_bl);
-    const size_t descs_off = T.put(descs);
-    const size_t tiles_off = T.put(tiles);
 
     r = htab[b].ensure(T.h.size());
     if (r != FLOW_OK) return r;
-    r = tab[b].ensure(T.h.size(), "serving tables");
-    if (r != FLOW_OK) return r;
+    {
+        const char* old = tab[b].d;
+        r = tab[b].ensure(T.h.size(), "serving tables");
+        if (r != FLOW_OK) return r;
+        if (tab[b].d != old) drop_graphs(b);
+    }
     std::memcpy(htab[b].h, T.h.data(), T.h.size());
     HIP_TRY(hipSetDevice(device));
     HIP_TRY(hipMemcpyAsync(tab[b].d, htab[b].h, T.h.size(), hipMemcpyHostToDevice, s));
+    (void)tiles_off;   // == tiles_at(): T.h held exactly the aligned prefix before the put
 
     // ---- launches
     const char* tb = tab[b].d;
-    if (ch.order == ORDER_QUEUE) launch_reset_u32(d_cnt, lpw * kNq, s);
     run_items(BatchOp::Copy, tb, l_imp, f16, s);
     for (int l = 1; l < lmax_new; ++l) run_items(BatchOp::Downsample, tb, l_down[l], f16, s);
     run_items(BatchOp::Derivatives, tb, l_der, f16, s);
     run_items(BatchOp::LevelInit, tb, l_init, false, s);
     run_items(BatchOp::Linearize, tb, l_lin, f16, s);
-    const int ntiles = (int)tiles.size();
-    enqueue_tile_warp((const TbTile*)(tb + tiles_off), ntiles, tile_grid(ch, ntiles), (const TbLevel*)(tb + descs_off),
-                      ch, p, 0, 0, d_cnt, s);
+    r = tile_launches(b, ch, ntiles, lpw, d_cnt);
+    if (r != FLOW_OK) return r;
     if (l_en.n > 0)
         launch_energy_batched((const EnergyArgs*)(tb + l_en.items), (const int*)(tb + l_en.off), l_en.n, l_en.total, s);
     run_items(BatchOp::Copy, tb, l_exp, false, s);

@@ -85,6 +85,34 @@ def test_served_results_are_the_same_alone_in_a_mix_and_batched(ctx, frames):
         assert same(out[k], batched[k]), k
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_graph_replayed_epochs_equal_direct_launches(ctx, frames, order):
+    """An epoch's tile launches replayed from a captured graph (fixed tables, device tile count,
+    persistent grid) give bitwise the same served results as direct launches, in both tile orders,
+    and few graphs serve many epochs."""
+    print(f"[case] serve graph replay order {order}", flush=True)
+    fm.set_tuning("batch_order", order)
+    try:
+        out = {}
+        stats = {}
+        for g in (0, 1):
+            fm.set_tuning("serve_graph", g)
+            srv = fm.Server(ctx, fm.Params(**KW), budget_bytes=64 << 20, max_active=8)
+            tick = {k: srv.submit(f[3], f[4], f[2]) for k, f in enumerate(frames[:4])}
+            srv.step()
+            tick.update({k + 4: srv.submit(f[3], f[4], f[2]) for k, f in enumerate(frames[4:])})
+            out[g] = serve_all(srv, tick)
+            stats[g] = srv.stats()
+            srv.close()
+    finally:
+        fm.set_tuning("serve_graph", 1)
+        fm.set_tuning("batch_order", -1)
+    for k in range(len(SPEC)):
+        assert same(out[0][k], out[1][k]), k
+    assert stats[0]["graphs_captured"] == 0
+    assert 1 <= stats[1]["graphs_captured"] < stats[1]["epochs"]
+
+
 def test_budget_and_slots_bound_what_is_in_flight(ctx, frames):
     print("[case] serve admission", flush=True)
     p = fm.Params(**KW)
