@@ -185,7 +185,9 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                     const float t2x = fmaf(gr[1][j] - gown(1, k), cx[k], qown(2, k));
                     const float t2y = fmaf(gd[1][j] - gown(1, k), cy[k], qown(3, k));
                     const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
-                    const float sc = nq > 1.f ? rsqrtf(nq) : 1.f;
+                    // projection scale min(1, 1/|t|): the hardware reciprocal square root is at
+                    // least 1 (or infinite) wherever |t| <= 1, so the min alone selects
+                    const float sc = fminf(1.f, __builtin_amdgcn_rsqf(nq));
                     sq1x[e] = qo[0][k] = t1x * sc;
                     sq1y[e] = qo[1][k] = t1y * sc;
                     sq2x[e] = qo[2][k] = t2x * sc;
@@ -194,7 +196,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                         const float tpx = fmaf(gr[NG - 1][j] - gown(NG - 1, k), cx[k], qown(4, k));
                         const float tpy = fmaf(gd[NG - 1][j] - gown(NG - 1, k), cy[k], qown(5, k));
                         const float np2 = tpx * tpx + tpy * tpy;
-                        const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                        const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
                         spx[e] = qo[4][k] = tpx * sp;
                         spy[e] = qo[5][k] = tpy * sp;
                     }
@@ -231,7 +233,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                         acc += beta * (ww[k] + crs * (dnp - beta * ss[k]));
                     }
                     float sn = ss[k] + acc * inv_atc;
-                    sn = fminf(fmaxf(sn, -a.lam), a.lam);
+                    sn = __builtin_amdgcn_fmed3f(sn, -a.lam, a.lam);
                     const float ms = a.cB * sn - a.cC * ss[k];
                     du[k] = du[k] + a.cA * dn1 - Ix[k] * ms;
                     dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;

@@ -132,7 +132,7 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
                 const float a2x = fmaf(cx[k], xr[1][j] - xbo[1][k], yow[2][k]);
                 const float a2y = fmaf(cy[k], xd[1][j] - xbo[1][k], yow[3][k]);
                 const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
-                const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
+                const float sq = fminf(1.f, __builtin_amdgcn_rsqf(nq));
                 S.y[0][e] = yow[0][k] = a1x * sq;
                 S.y[1][e] = yow[1][k] = a1y * sq;
                 S.y[2][e] = yow[2][k] = a2x * sq;
@@ -141,7 +141,7 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
                     const float bx = fmaf(cx[k], xr[2][j] - xbo[2][k], yow[4][k]);
                     const float by = fmaf(cy[k], xd[2][j] - xbo[2][k], yow[5][k]);
                     const float np2 = bx * bx + by * by;
-                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                    const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
                     S.y[4][e] = yow[4][k] = bx * sp;
                     S.y[5][e] = yow[5][k] = by * sp;
                 }
@@ -183,7 +183,7 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
                     if (rho < -thr) step = sigma * lam;
                     else if (rho > thr) step = -sigma * lam;
                     else step = -rho / e2;
-                    theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
+                    theta = __builtin_amdgcn_fmed3f(rho / (sigma * e2), -lam, lam);
                 } else {
                     step = 0.f;
                     theta = 0.f;

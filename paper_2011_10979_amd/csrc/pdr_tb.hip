@@ -218,7 +218,7 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
                     if (rho < -thr) step = sigma * lam;
                     else if (rho > thr) step = -sigma * lam;
                     else step = -rho / e2;
-                    theta = fminf(fmaxf(rho / (sigma * e2), -lam), lam);
+                    theta = __builtin_amdgcn_fmed3f(rho / (sigma * e2), -lam, lam);
                 } else {
                     step = 0.f;
                     theta = 0.f;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
                 const float a1x = yo[c][0] + t2 * gx[0], a1y = yo[c][1] + t2 * gy[0];
                 const float a2x = yo[c][2] + t2 * gx[1], a2y = yo[c][3] + t2 * gy[1];
                 const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
-                const float sq = nq > 1.f ? rsqrtf(nq) : 1.f;
+                const float sq = fminf(1.f, __builtin_amdgcn_rsqf(nq));
                 S.y[c][0][1 + tid] = a1x * sq - tau * gx[0];
                 S.y[c][1][1 + tid] = a1y * sq - tau * gy[0];
                 S.y[c][2][1 + tid] = a2x * sq - tau * gx[1];
@@ -239,7 +239,7 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
                 if constexpr (HAS_W) {
                     const float bx = yo[c][4] + t2 * gx[2], by = yo[c][5] + t2 * gy[2];
                     const float np2 = bx * bx + by * by;
-                    const float sp = np2 > 1.f ? rsqrtf(np2) : 1.f;
+                    const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
                     S.y[c][4][1 + tid] = bx * sp - tau * gx[2];
                     S.y[c][5][1 + tid] = by * sp - tau * gy[2];
                 }
