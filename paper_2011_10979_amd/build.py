@@ -1,4 +1,5 @@
-"""Build libflowmi.so (HIP kernels + C ABI runtime) for gfx950 with hipcc, in-tree.
+"""Build libflowmi.so (HIP kernels + C ABI runtime) for gfx950 with hipcc, in-tree, and the plain C
+client of its C ABI (tests/c_client/solve_pair) with gcc.
 
 Usage: python -m paper_2011_10979_amd.build [--jobs N]
 """
@@ -21,6 +22,8 @@ SOURCES = ["admm.hip", "admm_tb.hip", "pyramid.hip", "pdr.hip", "pdr_tb.hip", "a
            "runtime.cpp", "context.cpp", "tb_plan.cpp", "autotune.cpp", "batch.cpp", "multi.cpp", "serve.cpp"]
 
 ARCH = os.environ.get("FLOWMI_ARCH", "gfx950")
+C_CLIENT_SRC = os.path.join(os.path.dirname(HERE), "tests", "c_client", "solve_pair.c")
+C_CLIENT = os.path.splitext(C_CLIENT_SRC)[0]
 
 
 def hipcc() -> str:
@@ -58,7 +61,28 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_c_client(verbose)
     return LIB
+
+
+def build_c_client(verbose: bool = False) -> str:
+    """Compile the C client as C11 with gcc against include/flow.h, libflowmi.so and the HIP runtime
+    (found at run time through an rpath relative to the binary, so the tree can move)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler (gcc) found")
+    tmp = C_CLIENT + ".tmp"
+    cmd = [cc, "-std=c11", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", INCLUDE, C_CLIENT_SRC, "-o", tmp, "-L", HERE, "-lflowmi", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN/" + os.path.relpath(HERE, os.path.dirname(C_CLIENT)), f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C client build failed\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, C_CLIENT)
+    if verbose:
+        print(f"built {C_CLIENT}")
+    return C_CLIENT
 
 
 def main(argv=None):
