@@ -45,7 +45,7 @@ struct TileLds {
 // compute values nobody uses).  Neighbour values are read from LDS at indices clamped into the
 // array and weighted by the operators' coefficients, so no read sits behind a branch and the reads
 // of a phase issue together.
-template <bool HAS_W, int NT, int PPT>
+template <bool HAS_W, int NT, int PPT, bool BAND>
 __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, const TbLevel& L,
                                              TileLds<HAS_W, NT, PPT>& S) {
     constexpr int CAP = NT * PPT;
@@ -72,8 +72,24 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         float qo[NQ][PPT], go[NG][PPT];
         float* const sqa[6] = {sq1x, sq1y, sq2x, sq2y, spx, spy};
         float* const sga[3] = {sgu, sgv, sgw};
-        auto qown = [&](int f, int k) { return OWN ? qo[f][k] : sqa[f][tid + k * NT]; };
-        auto gown = [&](int f, int k) { return OWN ? go[f][k] : sga[f][tid + k * NT]; };
+        // Shrinking band: after iteration m only the region shrunk by m rows on each side with a
+        // halo (a side that is not the image border) can still reach the output tile, so a
+        // wavefront all of whose rows lie outside it skips the iteration.  Its stale values are as
+        // harmless as any other value outside the valid region.  With several pixels per thread a
+        // tile that shrinks lays its slots out so that a wavefront covers consecutive rows (its PPT
+        // slots are PPT consecutive runs of 64 in the extended region's row-major order); any other
+        // tile strides them by the work-group size, which spreads a partly filled region evenly over
+        // the wavefronts.  With one pixel per thread both layouts coincide, and the skip costs more
+        // than it saves (the iteration is bound by the LDS round trips and barriers, not by issue).
+        const int EH = ey1 - ey0;
+        const int shr_top = ey0 > 0, shr_bot = ey1 < H;
+        const bool band = BAND && PPT > 1 && (shr_top || shr_bot);
+        const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+        const int wbase = band ? wave0 * PPT : wave0, stride = band ? 64 : NT;
+        const int sbase = wbase + (tid & 63);
+        auto slot = [&](int k) { return sbase + k * stride; };
+        auto qown = [&](int f, int k) { return OWN ? qo[f][k] : sqa[f][slot(k)]; };
+        auto gown = [&](int f, int k) { return OWN ? go[f][k] : sga[f][slot(k)]; };
         // Per-slot neighbour structure, fixed for the launch: in-array neighbour indices clamped into
         // the array, and the operators' coefficients of Sec. 2.2 -- the forward difference exists in
         // the image (fx, fy; folded with 1 / (a c) into cx, cy for the dual step) and the divergence's
@@ -84,11 +100,13 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         int ei[PPT], ej[PPT], iL[PPT], iU[PPT], iR[PPT], iD[PPT];
         float fx[PPT], fy[PPT], fl[PPT], fu[PPT], cx[PPT], cy[PPT];
         // slot k of this wavefront holds any pixel of the extended region (wave-uniform, scalar branch)
-        const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
-        auto live = [&](int k) { return wave0 + k * NT < EN; };
+        auto live = [&](int k) { return wbase + k * stride < EN; };
+        // first and last row of the wavefront's pixels in the band layout (wave-uniform)
+        const int wr0 = __builtin_amdgcn_readfirstlane(min(wbase, EN - 1) / EW);
+        const int wr1 = __builtin_amdgcn_readfirstlane(min(wbase + 64 * PPT - 1, EN - 1) / EW);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int e = tid + k * NT;
+            const int e = slot(k);
             ei[k] = e / EW;
             ej[k] = e - ei[k] * EW;
             const int gi = ey0 + ei[k], gj = ex0 + ej[k];
@@ -179,7 +197,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 for (int j = 0; j < GS; ++j) {
                     const int k = k0 + j;
                     if (k >= PPT || (!AL && !live(k))) continue;
-                    const int e = tid + k * NT;
+                    const int e = slot(k);
                     const float t1x = fmaf(gr[0][j] - gown(0, k), cx[k], qown(0, k));
                     const float t1y = fmaf(gd[0][j] - gown(0, k), cy[k], qown(1, k));
                     const float t2x = fmaf(gr[1][j] - gown(1, k), cx[k], qown(2, k));
@@ -222,7 +240,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                 for (int j = 0; j < GS; ++j) {
                     const int k = k0 + j;
                     if (k >= PPT || (!AL && !live(k))) continue;
-                    const int e = tid + k * NT;
+                    const int e = slot(k);
                     const float dn1 = dn[0][j], dn2 = dn[1][j];
                     const float hu_ = du[k] + crs * (dn1 - Ix[k] * ss[k]);
                     const float hv_ = dv[k] + crs * (dn2 - Iy[k] * ss[k]);
@@ -247,7 +265,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         // phase A at the start: every slot, so that every g slot in LDS holds a finite value
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int e = tid + k * NT;
+            const int e = slot(k);
             float dp = 0.f;
             if constexpr (HAS_W) dp = divf(2, k);
             g_out(k, e, divf(0, k), divf(1, k), dp);
@@ -256,18 +274,24 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
         // so the LDS reads of all its slots issue together
         const bool all_live = live(PPT - 1);
         for (int it = 0; it < K; ++it) {
+            const int band_lo = shr_top * (it + 1), band_hi = EH - shr_bot * (it + 1);
+            const bool run = !band || __builtin_amdgcn_readfirstlane(live(0) && wr1 >= band_lo && wr0 < band_hi);
             __syncthreads();
-            if (all_live) phase_b(std::true_type{});
-            else phase_b(std::false_type{});
+            if (run) {
+                if (all_live) phase_b(std::true_type{});
+                else phase_b(std::false_type{});
+            }
             __syncthreads();
-            if (all_live) phase_c(std::true_type{}, it + 1 < K);
-            else phase_c(std::false_type{}, it + 1 < K);
+            if (run) {
+                if (all_live) phase_c(std::true_type{}, it + 1 < K);
+                else phase_c(std::false_type{}, it + 1 < K);
+            }
         }
 
         // write the output tile
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int e = tid + k * NT;
+            const int e = slot(k);
             if (e >= EN) continue;
             const int ei = e / EW, ej = e - ei * EW;
             const int gi = ey0 + ei, gj = ex0 + ej;
@@ -289,6 +313,14 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
     }
 }
 
+// Minimum wavefronts per SIMD each kernel shape asks the register allocator to allow: with two
+// pixels per thread, no w and the shrinking band, 64 VGPRs give 8 wavefronts per SIMD (two
+// 1024-thread work-groups, or four of 512, per CU), which hide each other's barriers and loads;
+// other shapes leave the allocator free.  BAND = false: the kernel is only launched on a level
+// that one tile covers (nothing shrinks), without the band's per-iteration test.
+template <bool HAS_W, int NT, int PPT, bool BAND>
+constexpr int tb_waves_per_simd() { return (!HAS_W && PPT == 2 && BAND) ? 8 : 1; }
+
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     // work-groups are dealt round-robin to the 8 XCDs; neighbouring tiles (which re-read each
     // other's halo) go to the same XCD's L2
@@ -298,8 +330,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // One level, regular tiling: the tile comes from the work-group index, the level descriptor from
 // the kernel arguments (no table reads, no counter).
-template <bool HAS_W, int NT, int PPT>
-__global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
+template <bool HAS_W, int NT, int PPT, bool BAND>
+__global__ __launch_bounds__(NT, (tb_waves_per_simd<HAS_W, NT, PPT, BAND>())) void admm_tb_direct_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= a.ntiles) return;
@@ -310,7 +342,7 @@ __global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
     T.x0 = tx * a.tw;
     T.th = min(a.th, a.lvl.H - T.y0);
     T.tw = min(a.tw, a.lvl.W - T.x0);
-    process_tile<HAS_W, NT, PPT>(a, T, a.lvl, S);
+    process_tile<HAS_W, NT, PPT, BAND>(a, T, a.lvl, S);
 }
 
 // Many levels (batched pairs), table order: one tile per work-group.  The n tiles are split into 8
@@ -319,7 +351,7 @@ __global__ __launch_bounds__(NT) void admm_tb_direct_kernel(TbArgs a) {
 // and a grid larger than the table (a launch replayed from a graph over changing tables) still
 // spreads a small table over every XCD.  The grid is a multiple of 8 of at least n.
 template <bool HAS_W, int NT, int PPT>
-__global__ __launch_bounds__(NT) void admm_tb_table_kernel(TbArgs a) {
+__global__ __launch_bounds__(NT, (tb_waves_per_simd<HAS_W, NT, PPT, true>())) void admm_tb_table_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
     const int n = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
     const int per = (n + 7) >> 3;                      // tiles per XCD
@@ -327,14 +359,14 @@ __global__ __launch_bounds__(NT) void admm_tb_table_kernel(TbArgs a) {
     const int t = x * per + y;
     if (y >= per || t >= n) return;
     const TbTile T = a.tiles[t];
-    process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
+    process_tile<HAS_W, NT, PPT, true>(a, T, a.levels[2 * T.level + a.dir], S);
 }
 
 // Many levels (batched pairs), work queue: a persistent grid pulls (level, tile) items from nq
 // counters; sub-queue x owns a contiguous run of the table and is drained by the work-groups
 // b = x (mod nq), which the dispatcher places on one XCD when nq = 8.
 template <bool HAS_W, int NT, int PPT>
-__global__ __launch_bounds__(NT) void admm_tb_queue_kernel(TbArgs a) {
+__global__ __launch_bounds__(NT, (tb_waves_per_simd<HAS_W, NT, PPT, true>())) void admm_tb_queue_kernel(TbArgs a) {
     __shared__ TileLds<HAS_W, NT, PPT> S;
     __shared__ int s_tile;
     const int n = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
@@ -348,7 +380,7 @@ __global__ __launch_bounds__(NT) void admm_tb_queue_kernel(TbArgs a) {
         __syncthreads();                  // everyone has read s_tile before it is overwritten
         if (t >= hi) break;               // uniform: the whole work-group leaves together
         const TbTile T = a.tiles[t];
-        process_tile<HAS_W, NT, PPT>(a, T, a.levels[2 * T.level + a.dir], S);
+        process_tile<HAS_W, NT, PPT, true>(a, T, a.levels[2 * T.level + a.dir], S);
         __syncthreads();                  // LDS is reused by the next tile
     }
 }
@@ -374,11 +406,24 @@ int tb_capacity(bool has_w, int nt) {
     return 256 * (has_w ? kTbPptW : kTbPpt);
 }
 
+// direct tiling; a level that one tile covers runs the instance without the shrinking band
+template <bool HAS_W, int NT, int PPT>
+static void launch_direct(const TbArgs& a, int grid, hipStream_t s) {
+    if constexpr (PPT > 1) {
+        const bool whole = a.ntiles == 1 && a.th >= a.lvl.H && a.tw >= a.lvl.W;
+        if (!whole) {
+            hipLaunchKernelGGL((admm_tb_direct_kernel<HAS_W, NT, PPT, true>), dim3(grid), dim3(NT), 0, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((admm_tb_direct_kernel<HAS_W, NT, PPT, false>), dim3(grid), dim3(NT), 0, s, a);
+}
+
 template <bool HAS_W, int NT, int PPT>
 static void launch_one(const TbArgs& a, int grid, hipStream_t s) {
     if (a.queue) hipLaunchKernelGGL((admm_tb_queue_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
     else if (a.tiles) hipLaunchKernelGGL((admm_tb_table_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((admm_tb_direct_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+    else launch_direct<HAS_W, NT, PPT>(a, grid, s);
 }
 
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s) {
@@ -392,20 +437,20 @@ void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s
     } else if (nt == 1026 || nt == 514) {
         // one pixel per thread, for latency-bound levels: direct tiling only
         if (nt == 1026) {
-            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
-            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
+            if (has_w) launch_direct<true, 1024, 1>(a, grid, s);
+            else launch_direct<false, 1024, 1>(a, grid, s);
         } else {
-            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 512, 1>), dim3(grid), dim3(512), 0, s, a);
-            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 512, 1>), dim3(grid), dim3(512), 0, s, a);
+            if (has_w) launch_direct<true, 512, 1>(a, grid, s);
+            else launch_direct<false, 512, 1>(a, grid, s);
         }
     } else if (nt == 513 || nt == 257) {
         // small work-groups for latency-bound levels: direct tiling only
         if (nt == 513) {
-            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 512, kTbPptSmall>), dim3(grid), dim3(512), 0, s, a);
-            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 512, kTbPptSmall>), dim3(grid), dim3(512), 0, s, a);
+            if (has_w) launch_direct<true, 512, kTbPptSmall>(a, grid, s);
+            else launch_direct<false, 512, kTbPptSmall>(a, grid, s);
         } else {
-            if (has_w) hipLaunchKernelGGL((admm_tb_direct_kernel<true, 256, kTbPptSmall>), dim3(grid), dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((admm_tb_direct_kernel<false, 256, kTbPptSmall>), dim3(grid), dim3(256), 0, s, a);
+            if (has_w) launch_direct<true, 256, kTbPptSmall>(a, grid, s);
+            else launch_direct<false, 256, kTbPptSmall>(a, grid, s);
         }
     } else {
         if (has_w) launch_one<true, 256, kTbPptW>(a, grid, s);
