@@ -380,9 +380,17 @@ class Server:
         return a.value, q.value
 
     def poll(self, ticket):
-        """None while running; (u, v, result) once done."""
+        """None while running; (u, v, result) once done.  A pair that finished with a non-finite
+        energy or gap raises FlowError (FLOW_E_NONFINITE) once, with its outputs in .result; the
+        ticket is collected either way."""
         d = ctypes.c_int32()
-        _check(lib().flow_server_poll(self._h, ticket, ctypes.byref(d)))
+        st = lib().flow_server_poll(self._h, ticket, ctypes.byref(d))
+        if st == FLOW_E_NONFINITE:
+            err = FlowError(st, lib().flow_last_error().decode())
+            _, _, u, v, res = self._live.pop(ticket)
+            err.result = (u, v, _result_dict(res))
+            raise err
+        _check(st)
         if not d.value:
             return None
         _, _, u, v, res = self._live.pop(ticket)

@@ -68,9 +68,12 @@ __device__ __forceinline__ void copy_body(const CopyArgs& a, int bx, int by) {
 }
 
 // Integer / fraction split of the sample position p + d clamped into [0, n-1]; keeps the
-// fraction exact where p + d in FP32 would lose bits (|p| up to 2^11, ulp 1e-4 px).
+// fraction exact where p + d in FP32 would lose bits (|p| up to 2^11, ulp 1e-4 px).  The whole
+// part is clamped to [-n, n] before the conversion, so a displacement that is NaN (max of NaN and
+// -n is -n) or beyond the level converts to a defined integer and samples the border.  A NaN flow
+// still reaches I_t (through -I_x u0 - I_y v0) and the state, and the energy check reports it.
 __device__ __forceinline__ void split_pos(int p, float d, int n, int& i0, float& t) {
-    const float fl = floorf(d);
+    const float fl = fminf(fmaxf(floorf(d), -(float)n), (float)n);
     t = d - fl;
     int ii = p + (int)fl;
     if (ii < 0) { ii = 0; t = 0.f; }

@@ -3,7 +3,8 @@ admitted pair advanced one warp per epoch in shared launches.
 
 Checks: a served pair's results are bitwise the same alone, in a mix that changes while it runs, and
 as a batched solve; the budget and slot limits hold; served flows match the FP64 oracle; bad
-requests are refused.
+requests are refused; a pair with a non-finite frame is reported once and leaves the others
+untouched.
 """
 import multiprocessing as mp
 
@@ -178,3 +179,29 @@ def test_bad_requests_are_refused(ctx, frames):
     srv.close()
     with pytest.raises(fm.FlowError):
         fm.Server(ctx, fm.Params(**dict(KW, scheme="pdr")))
+
+
+def test_non_finite_pair_is_reported_and_leaves_the_others_untouched(ctx, frames):
+    """A frame holding a NaN gives that pair a non-finite energy: its poll raises FLOW_E_NONFINITE
+    once (outputs attached) and collects the ticket; a pair served beside it is bitwise the same as
+    served alone."""
+    print("[case] serve non-finite pair", flush=True)
+    srv = fm.Server(ctx, fm.Params(**KW), budget_bytes=64 << 20, max_active=8)
+    alone = serve_all(srv, {0: srv.submit(frames[0][3], frames[0][4], frames[0][2])})[0]
+    bad = frames[1][3].contiguous().clone()
+    bad[5, 7] = float("nan")
+    tick = {"bad": srv.submit(bad, frames[1][4].contiguous(), frames[1][2]),
+            "good": srv.submit(frames[0][3], frames[0][4], frames[0][2])}
+    srv.drain()
+    with pytest.raises(fm.FlowError) as e:
+        srv.poll(tick["bad"])
+    assert e.value.status == fm.FLOW_E_NONFINITE
+    u, v, res = e.value.result
+    assert u.shape == bad.shape and not np.isfinite(res["energy"])
+    with pytest.raises(fm.FlowError) as e:
+        srv.poll(tick["bad"])                                               # collected
+    assert e.value.status == fm.FLOW_E_NOTFOUND
+    assert same(srv.poll(tick["good"]), alone)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 3 and st["bytes_in_use"] == 0
