@@ -617,7 +617,13 @@ def main():
         return
 
     dev = torch.device("cuda:0")
-    pair = synth.vga_pair(seed=1, H=args.H, W=args.W)
+    if args.pair == "hd":
+        # the 1920x1080 plain-vs-precision-form workload: rotation plus zoom with occlusions, 6 levels
+        pair = synth.hd_pair(seed=2)
+        args.H, args.W = pair.I0.shape
+        args.levels = 6
+    else:
+        pair = synth.vga_pair(seed=1, H=args.H, W=args.W)
     I0 = torch.from_numpy(pair.I0.astype(np.float32)).to(dev)
     I1 = torch.from_numpy(pair.I1.astype(np.float32)).to(dev)
     ctx = fm.Context(0)
@@ -728,8 +734,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.storage == "f32" else "f32 (f16-stored pyramids)",
         "data": "synthetic",
-        "config": {"workload": f"{args.W}x{args.H} pair, {args.levels}-level pyramid x {args.warps} warps x "
-                               f"{args.iters} iterations, {args.scheme}",
+        "config": {"workload": f"{args.W}x{args.H} pair{' (rotation + zoom, occluding rectangles)' if args.pair == 'hd' else ''}, "
+                               f"{args.levels}-level pyramid x {args.warps} warps x {args.iters} iterations, {args.scheme}",
                    "H": args.H, "W": args.W, "levels": args.levels, "warps": args.warps, "iters": args.iters,
                    "scheme": args.scheme, "storage": args.storage, "px_iter_per_step": px_iter,
                    "graph": True, "autotuned": tuning},

@@ -53,9 +53,11 @@ def test_hd_1080p_fp32_and_fp16_against_the_oracle(ctx):
     assert_conditioned("1080p fp32", to_np(u), to_np(v), res, ref, perts)
     d = np.maximum(np.abs(to_np(u) - ref[0]), np.abs(to_np(v) - ref[1]))
     assert np.quantile(d, 0.999) <= 1e-4 and d.mean() <= 1e-5
+    epe32 = np.hypot(to_np(u) - ref[0], to_np(v) - ref[1])
     epe16 = np.hypot(to_np(u16) - ref[0], to_np(v16) - ref[1])
-    print(f"[parity] 1080p fp16 storage: EPE vs oracle mean {epe16.mean():.3e} p99.9 {np.quantile(epe16, 0.999):.3e} "
-          f"max {epe16.max():.3e}", flush=True)
+    for name, e in (("fp32", epe32), ("fp16 storage", epe16)):
+        print(f"[parity] 1080p {name}: EPE vs oracle mean {e.mean():.3e} p99.9 {np.quantile(e, 0.999):.3e} "
+              f"max {e.max():.3e}", flush=True)
     assert epe16.mean() <= 1e-2
 
 
