@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="single mode: launch every kernel directly instead "
+                    "of replaying the solve's captured graph")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="set a library tuning knob (flow_tune_set) before the run, e.g. serve_graph=0")
     ap.add_argument("--batch-only", action="store_true",
@@ -628,7 +630,7 @@ def main():
     I1 = torch.from_numpy(pair.I1.astype(np.float32)).to(dev)
     ctx = fm.Context(0)
     params = fm.Params(scheme=args.scheme, storage=args.storage, levels=args.levels, warps=args.warps,
-                       iters=args.iters, use_graph=1)
+                       iters=args.iters, use_graph=0 if args.no_graph else 1)
     u = torch.empty_like(I0)
     v = torch.empty_like(I0)
     tuning = None
@@ -738,7 +740,7 @@ def main():
                                f"{args.levels}-level pyramid x {args.warps} warps x {args.iters} iterations, {args.scheme}",
                    "H": args.H, "W": args.W, "levels": args.levels, "warps": args.warps, "iters": args.iters,
                    "scheme": args.scheme, "storage": args.storage, "px_iter_per_step": px_iter,
-                   "graph": True, "autotuned": tuning},
+                   "graph": not args.no_graph, "autotuned": tuning},
         "energy": res["energy"], "gap": res["gap"],
         "per_level": per_level,
         "roofline": roof,
