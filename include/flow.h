@@ -12,7 +12,9 @@
  * warping pyramid (Sec. 4).
  *
  * Conventions shared by every entry point
- *   - Images and flow fields are row-major FP32 planes of H rows by W columns.  `ld` / `ld_*` is the
+ *   - Images and flow fields are row-major FP32 planes of H rows by W columns, each side at most
+ *     FLOW_MAX_SIDE (larger sides are refused with FLOW_E_INVAL; device memory bounds the area
+ *     long before: a pair's working set is about 100 B per pixel).  `ld` / `ld_*` is the
  *     row pitch in ELEMENTS (>= W).  Pointers tagged "device" must be device memory of the
  *     context's GPU (e.g. torch.cuda tensors); nothing is ever copied from host memory unless a
  *     pointer is tagged "host".
@@ -32,6 +34,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#define FLOW_MAX_SIDE 131072   /* largest H or W of any plane */
 
 #ifdef __cplusplus
 extern "C" {

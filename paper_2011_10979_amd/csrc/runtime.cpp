@@ -43,6 +43,8 @@ int64_t pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
 // write outside the caller's memory, so it is rejected before anything is launched.
 flow_status check_extent(const void* ptr, int H, int W, int64_t ld, size_t elem, const char* name) {
     if (!ptr) return fail(FLOW_E_INVAL, std::string(name) + " is NULL");
+    if (H > FLOW_MAX_SIDE || W > FLOW_MAX_SIDE)
+        return fail(FLOW_E_INVAL, std::string(name) + ": a side above FLOW_MAX_SIDE pixels");
     hipDeviceptr_t base = nullptr;
     size_t size = 0;
     hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
@@ -91,6 +93,8 @@ flow_status validate(const flow_params* p) {
 
 flow_status validate_shape(int H, int W, int64_t ld, int levels) {
     if (H < 2 || W < 2) return fail(FLOW_E_INVAL, "H and W must be >= 2");
+    // 2-D launch grids put H / 4 in the grid's y dimension (limit 65535 work-groups)
+    if (H > FLOW_MAX_SIDE || W > FLOW_MAX_SIDE) return fail(FLOW_E_INVAL, "H and W must be at most FLOW_MAX_SIDE");
     if (ld < W) return fail(FLOW_E_INVAL, "pitch smaller than W");
     auto s = level_shapes(H, W, levels).back();
     if (s.first < 2 || s.second < 2) return fail(FLOW_E_INVAL, "coarsest level has a side < 2");

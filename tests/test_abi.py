@@ -132,6 +132,8 @@ def test_working_set_bytes_is_host_only_and_checked(flowlib):
     assert fm.working_set_bytes(480, 640, levels=3) < vga
     assert fm.working_set_bytes(480, 640, storage="f16") < vga
     assert fm.working_set_bytes(480, 640, beta=0.05) > vga
-    for bad in ((1, 64, {}), (480, 640, {"levels": 17}), (40, 40, {"levels": 7})):
+    assert fm.working_set_bytes(131072, 64, levels=1) > 0                   # FLOW_MAX_SIDE rows
+    for bad in ((1, 64, {}), (480, 640, {"levels": 17}), (40, 40, {"levels": 7}), (131073, 64, {"levels": 1}),
+                (64, 131073, {"levels": 1})):
         with pytest.raises(fm.FlowError):
             fm.working_set_bytes(bad[0], bad[1], **bad[2])
