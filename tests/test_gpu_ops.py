@@ -160,20 +160,27 @@ def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
     against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
     print_case("pdr_tb", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta)
     halo = (4 * sweeps + 2) * K + 1
-    if min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > 2048:
-        pytest.skip("tile plus halo exceeds the kernel capacity")
+    oversized = min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > 2048
     rng = np.random.default_rng(zlib.crc32(repr(("pdrtb", shape, tile, K, sweeps, beta)).encode()))
     st = random_pdr_state(rng, shape, beta)
     Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
     u0 = f32(rng.normal(scale=3.0, size=shape))
     v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+
+    def call():
+        return fm.pdr_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
+                         fm.Params(scheme="pdr", gs_sweeps=sweeps, beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    if oversized:                                    # refused before any launch
+        with pytest.raises(fm.FlowError, match="capacity") as e:
+            call()
+        assert e.value.status == fm.FLOW_E_INVAL
+        return
     L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0)
     ref = dict(st)
     for _ in range(K):
         ref, duals = schemes.pdr_step(ref, L, beta, 0.05, 2.0, 0.4, sweeps)
-    g = {k: to_dev(v, pad=3) for k, v in st.items()}
-    out, s_out = fm.pdr_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
-                           fm.Params(scheme="pdr", gs_sweeps=sweeps, beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    out, s_out = call()
     keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
     tol = 1e-4 * max(1, K)
     for k in keys:
@@ -190,20 +197,27 @@ def test_alg1_tiles_match_k_oracle_steps(shape, tile, K, beta):
     """K ALG1 iterations of its tile kernel (halo K on each side, ragged tiles, a resident level)
     against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
     print_case("alg1_tb", shape=shape, tile=tile, K=K, beta=beta)
-    if min(shape[0], tile[0] + 2 * K) * min(shape[1], tile[1] + 2 * K) > 2048:
-        pytest.skip("tile plus halo exceeds the kernel capacity")
+    oversized = min(shape[0], tile[0] + 2 * K) * min(shape[1], tile[1] + 2 * K) > 2048
     rng = np.random.default_rng(zlib.crc32(repr(("alg1tb", shape, tile, K, beta)).encode()))
     st = random_pdr_state(rng, shape, beta)
     Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
     u0 = f32(rng.normal(scale=3.0, size=shape))
     v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+
+    def call():
+        return fm.alg1_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
+                          fm.Params(scheme="alg1", beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    if oversized:                                    # refused before any launch
+        with pytest.raises(fm.FlowError, match="capacity") as e:
+            call()
+        assert e.value.status == fm.FLOW_E_INVAL
+        return
     L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0)
     ref = dict(st)
     for _ in range(K):
         ref, duals = schemes.alg1_step(ref, L, beta, 0.05, 0.1, 1.25)
-    g = {k: to_dev(v, pad=3) for k, v in st.items()}
-    out, s_out = fm.alg1_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
-                            fm.Params(scheme="alg1", beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+    out, s_out = call()
     keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
     tol = 1e-4 * max(1, K)
     for k in keys:
@@ -284,12 +298,12 @@ def test_admm_iteration_every_strip_height(rows, shape, beta):
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
 def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme, relax, beta):
     """K iterations of the temporally blocked tile kernel (halo K + 1 / K, ragged tiles, resident
-    levels) against K steps of the oracle on the same increment-form state."""
+    levels) against K steps of the oracle on the same increment-form state; a tile whose extended
+    region exceeds the kernel's capacity is refused before any launch."""
     print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
     cap = {1025: 2048, 513: 1024, 257: 512, 1026: 1024, 514: 512}.get(threads) or (1024 * (3 if beta > 0 else 4) if threads == 1024 else
                                                               256 * (4 if beta > 0 else 6))
-    if min(shape[0], tile[0] + 2 * K + 1) * min(shape[1], tile[1] + 2 * K + 1) > cap:
-        pytest.skip("tile plus halo exceeds the kernel capacity")
+    oversized = min(shape[0], tile[0] + 2 * K + 1) * min(shape[1], tile[1] + 2 * K + 1) > cap
     rng = np.random.default_rng(zlib.crc32(repr(("tb", shape, tile, K, threads, scheme)).encode()))
     st = random_admm_state(rng, shape, beta)
     Ix, Iy, Itr, at = random_lin(rng, shape, beta)
@@ -297,16 +311,24 @@ def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme,
     v0 = f32(rng.normal(scale=4.0, size=shape))
     du = f32(rng.normal(scale=0.3, size=shape))
     dv = f32(rng.normal(scale=0.3, size=shape))
+    g = _dev_state(dict(st, u=du, v=dv, u0=u0, v0=v0), pad=2)
+    at_t = torch.tensor([at, 0.0], dtype=torch.float32, device="cuda")
+
+    def call():
+        return fm.admm_tb(g, to_dev(Ix, 2), to_dev(Iy, 2), to_dev(Itr, 2), at_t,
+                          fm.Params(scheme=scheme, relax=relax, beta=beta), iters=K, threads=threads,
+                          tile_h=tile[0], tile_w=tile[1], order=order)
+    if oversized:                                    # refused before any launch
+        with pytest.raises(fm.FlowError, match="capacity") as e:
+            call()
+        assert e.value.status == fm.FLOW_E_INVAL
+        return
     full = dict(st, u=u0 + du, v=v0 + dv)
     L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0, at=at)
     for _ in range(K):
         full = (schemes.rpadmm1_step(full, L, beta, 0.05, 0.05, relax) if scheme == "padmm"
                 else schemes.rpadmm2_step(full, L, beta, 0.05, 0.05, relax))
-    g = _dev_state(dict(st, u=du, v=dv, u0=u0, v0=v0), pad=2)
-    at_t = torch.tensor([at, 0.0], dtype=torch.float32, device="cuda")
-    out = fm.admm_tb(g, to_dev(Ix, 2), to_dev(Iy, 2), to_dev(Itr, 2), at_t,
-                     fm.Params(scheme=scheme, relax=relax, beta=beta), iters=K, threads=threads,
-                     tile_h=tile[0], tile_w=tile[1], order=order)
+    out = call()
     tol = 1e-4 * max(1, K)
     assert max_abs(to_np(out["u"]), full["u"] - u0) < tol
     assert max_abs(to_np(out["v"]), full["v"] - v0) < tol
