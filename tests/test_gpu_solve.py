@@ -148,15 +148,27 @@ def test_single_row_or_column_is_rejected(ctx):
         assert e.value.status == fm.FLOW_E_INVAL
 
 
-def test_vga_bench_workload_full_size(ctx):
-    """The 640x480 workload exactly as the benchmark runs it (5 levels x 5 warps x 50, pADMM,
-    graph replay), against the full FP64 oracle solve; also p99.9 <= 1e-4 px and mean <= 1e-5 px."""
-    print("[case] vga 640x480 5x5x50", flush=True)
+@pytest.mark.parametrize("plan", ["builtin", "autotuned"])
+def test_vga_bench_workload_full_size(ctx, plan):
+    """The 640x480 workload (5 levels x 5 warps x 50, pADMM, graph replay) against the full FP64
+    oracle solve, with the built-in kernel plan and with the plan the benchmark times (the
+    autotuner's per-level choice, K-iteration tiles); also p99.9 <= 1e-4 px and mean <= 1e-5 px."""
+    print(f"[case] vga 640x480 5x5x50 plan {plan}", flush=True)
     pair = synth.vga_pair(seed=1)
-    u, v, ru, rv = conditioned_check(ctx, pair, "vga 640x480", global_bars=True, levels=5, warps=5, iters=50)
+    kw = dict(levels=5, warps=5, iters=50)
+    c = ctx
+    if plan == "autotuned":
+        c = fm.Context(0)
+        rep = c.autotune(480, 640, fm.Params(**kw))
+        print(f"[parity] vga autotuned plan: { {k: e['choice'] for k, e in rep.items()} }", flush=True)
+    try:
+        u, v, ru, rv = conditioned_check(c, pair, f"vga 640x480 {plan}", global_bars=True, **kw)
+    finally:
+        if c is not ctx:
+            c.close()
     epe_gpu = np.hypot(u - pair.u, v - pair.v).mean()
     epe_ora = np.hypot(ru - pair.u, rv - pair.v).mean()
-    print(f"[parity] vga EPE vs truth gpu {epe_gpu:.4f} oracle {epe_ora:.4f}", flush=True)
+    print(f"[parity] vga {plan} EPE vs truth gpu {epe_gpu:.4f} oracle {epe_ora:.4f}", flush=True)
 
 
 def test_graph_replay_equals_direct_launches(ctx):
