@@ -68,6 +68,16 @@ def test_batch_of_64_uneven_pairs(ctx):
     frames = [(to_dev(a), to_dev(b), synth.levels_by_size(*a.shape)) for a, b in host]
     kw = dict(warps=5, iters=50)
     out = ctx.solve_batched(frames, fm.Params(**kw, use_graph=1))
+    # the stage choice the benchmark times (autotuned) gives the same results bit for bit
+    tuned = fm.Context(0)
+    try:
+        tuned.autotune_batched(frames, fm.Params(**kw))
+        out_t = tuned.solve_batched(frames, fm.Params(**kw, use_graph=1))
+    finally:
+        tuned.close()
+    for k in range(64):
+        assert torch.equal(out_t[k][0], out[k][0]) and torch.equal(out_t[k][1], out[k][1]), k
+        assert out_t[k][2]["energy"] == out[k][2]["energy"], k
     fm.set_tuning("tb_mode", 4)
     for k, (I0, I1, lv) in enumerate(frames):
         u, v, res = ctx.solve(I0, I1, fm.Params(**kw, levels=lv))
