@@ -71,16 +71,19 @@ def pdr_bytes_per_px_iter(has_w, sweeps):
 
 
 def kernel_sha():
+    """Hash of the iteration kernels' sources and of the tile planner (which sets the tiles a launch
+    loads, and so its traffic)."""
     h = hashlib.sha256()
-    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp"):
+    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp", "tb_plan.cpp"):
         with open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the iteration kernel from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (else None)."""
+def measured_traffic(workload, choice):
+    """HBM bytes per launch of the level-0 iteration kernel from committed rocprofv3 counter runs,
+    if they were taken on the current kernel and planner source with the same per-level choice
+    (mode, K, tile width) as this run (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
@@ -88,6 +91,9 @@ def measured_traffic(workload):
         return None
     e = d.get(workload)
     if not e or e.get("kernel_sha") != kernel_sha():
+        return None
+    keys = ("mode", "K", "rows")
+    if not choice or not e.get("choice") or any(e["choice"].get(k) != choice.get(k) for k in keys):
         return None
     return e.get("bytes_per_launch")
 
@@ -701,7 +707,8 @@ def main():
         roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
                         f"ADMM iteration kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice "
                         f"{(tuning or {}).get(f'{shapes[0][0]}x{shapes[0][1]}i{args.iters}')}",
-                        measured_traffic(f"{args.W}x{args.H}"), reps)
+                        measured_traffic(f"{args.W}x{args.H}",
+                                         (tuning or {}).get(f"{shapes[0][0]}x{shapes[0][1]}i{args.iters}")), reps)
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
     elif args.scheme in ("pdr", "alg1"):
         suffix = "a" if args.scheme == "alg1" else f"p{params.gs_sweeps}"

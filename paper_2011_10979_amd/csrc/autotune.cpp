@@ -1,11 +1,10 @@
 // Autotuner: for every level shape of a pair, time each iteration-kernel choice (one-pass kernel
 // with strip heights 2 / 4 / 8; K-iteration tiles of 256, 1024 and small 1024-thread work-groups
-// with K = 2, 4, 8, 16; a resident tile where the level fits) over one warp's worth of iterations
-// with HIP events, and keep the fastest.  Every choice computes the same iteration, so the choice
+// with K = 2, 4, 6, 8, 10, 12, 16; a resident tile where the level fits) over one warp's worth of
+// iterations with HIP events, and keep the fastest.  Every choice computes the same iteration, so the choice
 // changes speed only (results agree to rounding); later solves of the context use the table.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <sstream>
@@ -140,8 +139,10 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             c.tb = false;
             cands.push_back(c);
         }
+        // iterations per launch: every launch pays a fixed cost (loads, stores, dispatch), so the
+        // steps between 2 and 16 matter as well (50 iterations: 5 launches at K = 10, 7 at K = 8)
         for (int mode : {2, 4, 3, 7, 6, 8, 9})
-            for (int K : {2, 4, 8, 16})
+            for (int K : {2, 4, 6, 8, 10, 12, 16})
                 for (int ew : {0, 32, 48, 64, 96}) {             // extended tile width (0: built-in)
                     LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K, ew);
                     if (!P.tb) continue;

@@ -53,6 +53,37 @@ LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
     return P;
 }
 
+// Work-groups of a tile shape that one CU holds at once, set by each kernel's registers (64 VGPRs
+// or fewer allow 8 wavefronts per SIMD) and the 8-wavefront limit per SIMD.
+static int tb_wgs_per_cu(int nt, bool hw) {
+    switch (nt) {
+    case 1025: return hw ? 1 : 2;    // 1024 threads, 64 / 81 VGPRs
+    case 1026: return 2;             // 1024 threads, one pixel
+    case 513: return hw ? 3 : 4;
+    case 514: return 4;
+    case 257: return hw ? 6 : 8;
+    case 1024: return 1;             // 1024 threads, 3-4 pixels
+    default: return 3;               // 256 threads, 4-6 pixels
+    }
+}
+
+// A level whose full-height tiles fit in one round of work-groups (one per CU, else as many per CU as
+// fit) gets tiles just short enough to fill that round: the launch takes as long as its busiest CU,
+// so shorter tiles spread the same level over more CUs, or even it out, with less work each.
+static void balance_tiles(LevelTbPlan& P, int H, int W, bool hw) {
+    constexpr int kCUs = 256;
+    if (!P.tb || P.resident) return;
+    const int ntx = (W + P.tw - 1) / P.tw;
+    const int n = ntx * ((H + P.th - 1) / P.th);
+    for (const int per : {1, tb_wgs_per_cu(P.nt, hw)}) {
+        const int slots = kCUs * per;
+        if (n > slots) continue;
+        const int rows = slots / ntx;                // tile rows that one round holds
+        if (rows >= 1) P.th = std::min(P.th, std::max(2, (H + rows - 1) / rows));
+        return;
+    }
+}
+
 LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int ew) {
     LevelTbPlan P;
     if (mode == 1 || iters < 2) return P;                    // one-pass kernel
@@ -72,6 +103,7 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int
                  : mode == 8 ? 1026 : mode == 9 ? 514 : 256;
     P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, ew);
     if (P.resident) P.K = iters;                             // the whole warp in one launch
+    balance_tiles(P, H, W, hw);
     return P;
 }
 
