@@ -608,7 +608,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
                 c.K = p->iters;
                 cands.push_back(c);
             }
-            for (int K : {2, 4, 8})
+            for (int K : {2, 4, 6, 8, 10})
                 for (int ew : {64, 128})
                     if (stage_fits(P, S, hw, K, ew)) {
                         StageChoice c;

@@ -77,8 +77,9 @@ using Shapes = std::vector<std::pair<int, int>>;
 // Every shape takes tiles for exactly K iterations with width target ew (or fits one tile).
 bool shapes_fit(const Shapes& s, bool hw, int K, int ew);
 bool shapes_all_resident(const Shapes& s, bool hw);
-// Built-in choice: the whole warp in one launch where every level fits one tile; else 4 iterations
-// per launch when the levels hold enough pixels to fill the chip with tiles, 8 otherwise.
+// Built-in choice: the whole warp in one launch where every level fits one tile; else 6 iterations
+// per launch when the levels hold enough pixels to fill the chip with tiles (many rounds of
+// work-groups, where the recomputed halo costs throughput), 8 otherwise.
 StageChoice default_stage_choice(const Shapes& s, bool hw, int iters);
 // Lower K (and fall back to width 64) until every shape fits.
 StageChoice fit_stage_choice(StageChoice c, const Shapes& s, bool hw);
