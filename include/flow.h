@@ -243,8 +243,9 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
  * shape for this context's later solves.  ADMM family: one-pass kernel with 2 / 4 / 8-row strips;
  * K-iteration tiles of 256, 1024 and small 1024-thread work-groups for K = 2, 4, 6, 8, 10, 12, 16
  * (tiles shortened to fill one round of work-groups where a level needs less); a resident tile
- * where the level fits.  pDR: the three-pass iteration, K-iteration tiles for K = 1, 2, 3, a
- * resident tile.  Every choice computes the same iteration (results agree to rounding).  Blocking;
+ * where the level fits.  pDR: the three-pass iteration, K-iteration tiles for K = 1, 2, 3, 4, a
+ * resident tile; ALG1: tiles for K = 1, 2, 3, 4, 6, 8, 10, a resident tile (both with balanced
+ * tiles).  Every choice computes the same iteration (results agree to rounding).  Blocking;
  * uses the context's arena (contents are overwritten). */
 flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
 

@@ -69,8 +69,8 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
         st = clear_level(L, s);
         if (st != FLOW_OK) break;
         if (pd_state(*p)) {
-            // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, or a resident level;
-            // ALG1: tiles with K = 1, 2, 4, 8, or a resident level
+            // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, 4, or a resident level;
+            // ALG1: tiles with K = 1, 2, 3, 4, 6, 8, 10, or a resident level
             const bool alg1 = p->scheme == FLOW_ALG1;
             struct PCand { TunedChoice c; PdrTbPlan T; };
             std::vector<PCand> cands;
@@ -80,7 +80,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
                 cands.push_back(three);
             }
             bool resident_done = false;
-            const std::vector<int> ks = alg1 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 3};
+            const std::vector<int> ks = alg1 ? std::vector<int>{1, 2, 3, 4, 6, 8, 10} : std::vector<int>{1, 2, 3, 4};
             for (int nt : {1024, 512})
             for (int K : ks) {
                 PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(*p, K), K, 0, nt);

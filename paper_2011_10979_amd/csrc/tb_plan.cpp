@@ -70,18 +70,22 @@ static int tb_wgs_per_cu(int nt, bool hw) {
 // A level whose full-height tiles fit in one round of work-groups (one per CU, else as many per CU as
 // fit) gets tiles just short enough to fill that round: the launch takes as long as its busiest CU,
 // so shorter tiles spread the same level over more CUs, or even it out, with less work each.
-static void balance_tiles(LevelTbPlan& P, int H, int W, bool hw) {
+// Returns the balanced tile height.
+static int balanced_height(int H, int W, int th, int tw, int wgs_per_cu) {
     constexpr int kCUs = 256;
-    if (!P.tb || P.resident) return;
-    const int ntx = (W + P.tw - 1) / P.tw;
-    const int n = ntx * ((H + P.th - 1) / P.th);
-    for (const int per : {1, tb_wgs_per_cu(P.nt, hw)}) {
+    const int ntx = (W + tw - 1) / tw;
+    const int n = ntx * ((H + th - 1) / th);
+    for (const int per : {1, wgs_per_cu}) {
         const int slots = kCUs * per;
         if (n > slots) continue;
         const int rows = slots / ntx;                // tile rows that one round holds
-        if (rows >= 1) P.th = std::min(P.th, std::max(2, (H + rows - 1) / rows));
-        return;
+        return rows >= 1 ? std::min(th, std::max(2, (H + rows - 1) / rows)) : th;
     }
+    return th;
+}
+
+static void balance_tiles(LevelTbPlan& P, int H, int W, bool hw) {
+    if (P.tb && !P.resident) P.th = balanced_height(H, W, P.th, P.tw, tb_wgs_per_cu(P.nt, hw));
 }
 
 LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int ew) {
@@ -129,7 +133,9 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, i
     if (tw < 8 || th < 2 || (int64_t)ext_w * std::min(H, th + halo) > cap) return P;
     P.tb = true;
     P.K = K;
-    P.th = th;
+    // pDR and ALG1 tiles (74 / 67 VGPRs, 86 / 82 with w): one 1024-thread work-group per CU, two or
+    // three of 512 threads
+    P.th = balanced_height(H, W, th, tw, nt == 512 ? (hw ? 2 : 3) : 1);
     P.tw = tw;
     return P;
 }
