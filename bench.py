@@ -599,7 +599,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; pairs would be sharded across GPUs with no "
+        print("bench.py: the library runs on one GPU; pairs would be sharded across GPUs with no "
               "communication, and no multi-GPU figure is produced.", file=sys.stderr)
         sys.exit(2)
 
