@@ -58,6 +58,8 @@ void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void*
 void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64_t ldd, bool f16, hipStream_t s);
 void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s,
                    const float* add = nullptr);
+// Deterministic pseudo-random plane in [-scale, scale) (timing runs).
+void launch_fill_noise(float* p, int H, int W, int64_t ld, uint32_t seed, float scale, hipStream_t s);
 
 // Level start: upsample (or zero) the flow and clear / set the scheme's auxiliary planes.
 struct LevelInitArgs {

@@ -198,6 +198,21 @@ template <typename T> __global__ __launch_bounds__(256) void derivatives_kernel(
 template <typename T> __global__ __launch_bounds__(256) void copy_kernel(CopyArgs a) {
     copy_body<T>(a, blockIdx.x, blockIdx.y);
 }
+// Deterministic noise in [-scale, scale) from the "lowbias32" integer mixer of C. Wellons' hash
+// prospector, applied to seed ^ (row * 0x9E3779B9 + column): operands for timing runs that vary
+// from pixel to pixel as those of real images do.
+__global__ __launch_bounds__(256) void noise_kernel(float* p, int H, int W, int64_t ld, uint32_t seed, float scale) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= H || j >= W) return;
+    uint32_t x = seed ^ ((uint32_t)i * 0x9E3779B9u + (uint32_t)j);
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    p[(int64_t)i * ld + j] = scale * fmaf((float)(x >> 8), 2.f / 16777216.f, -1.f);
+}
 template <typename T> __global__ __launch_bounds__(kLinThreads) void linearize_kernel(LinArgs a) {
     linearize_body<T>(a, blockIdx.x, blockIdx.y);
 }
@@ -271,6 +286,10 @@ void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int6
                    const float* add) {
     const CopyArgs a{src, H, W, lds, dst, ldd, 0.f, add};
     hipLaunchKernelGGL(copy_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
+}
+
+void launch_fill_noise(float* p, int H, int W, int64_t ld, uint32_t seed, float scale, hipStream_t s) {
+    hipLaunchKernelGGL(noise_kernel, grid2d(H, W), dim3(256), 0, s, p, H, W, ld, seed, scale);
 }
 
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s) {
