@@ -241,11 +241,12 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
 /* Autotuner: for every pyramid level of an H x W pair under params p, time each iteration-kernel
  * choice over one warp's iterations with HIP events on `stream`, and keep the fastest per level
  * shape for this context's later solves.  ADMM family: one-pass kernel with 2 / 4 / 8-row strips;
- * K-iteration tiles of 256, 1024 and small 1024-thread work-groups for K = 2, 4, 6, 8, 10, 12, 16
- * (tiles shortened to fill one round of work-groups where a level needs less); a resident tile
- * where the level fits.  pDR: the three-pass iteration, K-iteration tiles for K = 1, 2, 3, 4, a
- * resident tile; ALG1: tiles for K = 1, 2, 3, 4, 6, 8, 10, a resident tile (both with balanced
- * tiles).  Every choice computes the same iteration (results agree to rounding).  Blocking;
+ * K-iteration tiles of 256, 1024 and small 1024-thread work-groups for every K in [2, 16] that is
+ * the smallest giving its number of launches per warp, ceil(iters / n) (50 iterations: K = 2, 3,
+ * 4, 5, 6, 7, 8, 9, 10, 13; tiles shortened to fill one round of work-groups where a level needs
+ * less); a resident tile where the level fits.  pDR: the three-pass iteration, K-iteration tiles
+ * for K = 1, 2, 3, 4, a resident tile; ALG1: tiles for the same launch-count K values in [1, 10],
+ * a resident tile (both with balanced tiles).  Every choice computes the same iteration (results agree to rounding).  Blocking;
  * uses the context's arena (contents are overwritten). */
 flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
 

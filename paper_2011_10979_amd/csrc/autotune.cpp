@@ -1,7 +1,7 @@
 // Autotuner: for every level shape of a pair, time each iteration-kernel choice (one-pass kernel
 // with strip heights 2 / 4 / 8; K-iteration tiles of 256, 1024 and small 1024-thread work-groups
-// with K = 2, 4, 6, 8, 10, 12, 16; a resident tile where the level fits) over one warp's worth of
-// iterations with HIP events, and keep the fastest.  Every choice computes the same iteration, so the choice
+// with every K up to 16 that is the smallest for its number of launches per warp; a resident tile
+// where the level fits) over one warp's worth of iterations with HIP events, and keep the fastest.  Every choice computes the same iteration, so the choice
 // changes speed only (results agree to rounding); later solves of the context use the table.
 #include <hip/hip_runtime.h>
 
@@ -23,6 +23,20 @@ namespace flowmi {
 // deterministic noise at the scale of image gradients and flows.  Timed on zeros, where no operand
 // changes, the ranking of launch shapes differed from the one in solves of images (at 1920 x 1080,
 // level 0, a choice 0.3% faster on zeros was 10% slower in the solve); on noise the two agree.
+// Iterations per launch worth timing for `iters` iterations per warp: for each launch count n the
+// smallest K that covers the warp in n launches, ceil(iters / n), within [kmin, kmax] (ascending).
+// A larger K with the same launch count only widens the halo (50 iterations: K = 12 and 10 both
+// take five launches).
+static std::vector<int> launch_ks(int iters, int kmin, int kmax) {
+    std::vector<int> ks;
+    for (int n = iters; n >= 1; --n) {
+        const int K = (iters + n - 1) / n;
+        if (K >= kmin && K <= kmax && (ks.empty() || ks.back() != K)) ks.push_back(K);
+    }
+    if (ks.empty()) ks.push_back(kmin);
+    return ks;
+}
+
 static flow_status prepare_level(const LevelPlanes& L, hipStream_t s) {
     const size_t plane = (size_t)L.H * L.ld * sizeof(float);
     for (int b = 0; b < 2; ++b) {
@@ -77,7 +91,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
         if (st != FLOW_OK) break;
         if (pd_state(*p)) {
             // pDR: the three-pass iteration, or tiles with K = 1, 2, 3, 4, or a resident level;
-            // ALG1: tiles with K = 1, 2, 3, 4, 6, 8, 10, or a resident level
+            // ALG1: tiles with the launch-count K values up to 10, or a resident level
             const bool alg1 = p->scheme == FLOW_ALG1;
             struct PCand { TunedChoice c; PdrTbPlan T; };
             std::vector<PCand> cands;
@@ -87,7 +101,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
                 cands.push_back(three);
             }
             bool resident_done = false;
-            const std::vector<int> ks = alg1 ? std::vector<int>{1, 2, 3, 4, 6, 8, 10} : std::vector<int>{1, 2, 3, 4};
+            const std::vector<int> ks = alg1 ? launch_ks(p->iters, 1, 10) : std::vector<int>{1, 2, 3, 4};
             for (int nt : {1024, 512})
             for (int K : ks) {
                 PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(*p, K), K, 0, nt);
@@ -146,14 +160,15 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             c.tb = false;
             cands.push_back(c);
         }
-        // iterations per launch: every launch pays a fixed cost (loads, stores, dispatch), so the
-        // steps between 2 and 16 matter as well (50 iterations: 5 launches at K = 10, 7 at K = 8)
+        // iterations per launch: every launch pays a fixed cost (loads, stores, dispatch), so each
+        // launch count matters (50 iterations: 7 launches at K = 8, 6 at K = 9, 5 at K = 10)
+        const std::vector<int> ks = launch_ks(p->iters, 2, 16);
         for (int mode : {2, 4, 3, 7, 6, 8, 9})
-            for (int K : {2, 4, 6, 8, 10, 12, 16})
+            for (int K : ks)
                 for (int ew : {0, 32, 48, 64, 96}) {             // extended tile width (0: built-in)
                     LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K, ew);
                     if (!P.tb) continue;
-                    if (P.resident && (K != 2 || ew != 0)) continue;   // one resident candidate per size
+                    if (P.resident && (K != ks.front() || ew != 0)) continue;   // one resident candidate per size
                     if (!P.resident && P.K != K) continue;              // capacity lowered K: a duplicate
                     bool dup = false;                                   // the same tiling under another width
                     for (const Cand& o : cands)
