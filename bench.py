@@ -35,6 +35,7 @@ Other modes:
                     against the ground-truth motion, energy and gap at equal iteration counts
   --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
                                       them from F instead of tuning (for profiler runs)
+  --choice KEY=MODE,K,ROWS            then pin one level shape's choice (counters of another choice)
   --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
                                       kernel for the HBM counter calibration) and exit
 """
@@ -82,20 +83,23 @@ def kernel_sha():
 
 def measured_traffic(workload, choice):
     """HBM bytes per launch of the level-0 iteration kernel from committed rocprofv3 counter runs,
-    if they were taken on the current kernel and planner source with the same per-level choice
-    (mode, K, tile width) as this run (else None)."""
+    if they were taken on the current kernel and planner source with the same level-0 choice
+    (mode, K, tile width) as this run (else None).  The record holds one entry per measured choice:
+    the autotuner's pick among candidates within a percent of each other varies between runs."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     e = d.get(workload)
-    if not e or e.get("kernel_sha") != kernel_sha():
+    if not e or e.get("kernel_sha") != kernel_sha() or not choice:
         return None
     keys = ("mode", "K", "rows")
-    if not choice or not e.get("choice") or any(e["choice"].get(k) != choice.get(k) for k in keys):
-        return None
-    return e.get("bytes_per_launch")
+    for m in e.get("entries", []):
+        c = m.get("choice") or {}
+        if all(c.get(k) == choice.get(k) for k in keys):
+            return m.get("bytes_per_launch")
+    return None
 
 
 def host_cpu():
@@ -584,6 +588,8 @@ def main():
                     help="batch mode: time the batched solve only (no plain solves, per-stage timing or oracle check)")
     ap.add_argument("--save-tuning", default=None)
     ap.add_argument("--load-tuning", default=None)
+    ap.add_argument("--choice", action="append", default=[], metavar="KEY=MODE,K,ROWS",
+                    help="after tuning, pin one level shape's kernel choice, e.g. 480x640i50=4,9,48")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
     ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "compare"])
     ap.add_argument("--pair", default="vga", choices=["vga", "hd"])
@@ -650,6 +656,12 @@ def main():
         # one-time choice of the iteration kernel per level shape (outside the timed region)
         tuning = {k: v_["choice"] for k, v_ in ctx.autotune(args.H, args.W, params).items()}
         print(f"[bench] autotuned: {tuning}", file=sys.stderr, flush=True)
+    for kv in args.choice:
+        key, _, val = kv.partition("=")
+        mode, K, rows = (int(x) for x in val.split(","))
+        ctx.set_choice(key, mode, K, rows)
+        tuning = dict(tuning or {}, **{key: {"mode": mode, "K": K, "rows": rows}})
+        print(f"[bench] pinned {key}: mode {mode}, K {K}, rows {rows}", file=sys.stderr, flush=True)
     if args.save_tuning and tuning is not None:
         with open(args.save_tuning, "w") as fh:
             json.dump(tuning, fh)

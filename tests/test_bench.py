@@ -20,12 +20,20 @@ def _entry():
 
 def test_traffic_is_reported_only_for_the_source_and_choice_it_was_measured_with(monkeypatch):
     e = _entry()
-    choice = dict(e["choice"], us_per_iter=1.0)
     if e["kernel_sha"] != bench.kernel_sha():
         pytest.skip("traffic.json predates the current kernel or planner source (re-measured on the GPU)")
-    assert bench.measured_traffic("640x480", choice) == e["bytes_per_launch"]
-    for k, v in (("mode", 8), ("K", e["choice"]["K"] + 2), ("rows", 48)):
-        assert bench.measured_traffic("640x480", dict(choice, **{k: v})) is None, k
+    measured = {(m["choice"]["mode"], m["choice"]["K"], m["choice"]["rows"]): m["bytes_per_launch"]
+                for m in e["entries"]}
+    assert measured
+    for (mode, K, rows), b in measured.items():
+        choice = {"mode": mode, "K": K, "rows": rows, "us_per_iter": 1.0}
+        assert bench.measured_traffic("640x480", choice) == b
+        # one field away from a measured choice, unless that is measured as well
+        for other in ((8, K, rows), (mode, K + 7, rows), (mode, K, rows + 16)):
+            if other not in measured:
+                c = dict(zip(("mode", "K", "rows"), other))
+                assert bench.measured_traffic("640x480", c) is None, other
+    choice = dict(e["entries"][0]["choice"])
     assert bench.measured_traffic("640x480", None) is None
     assert bench.measured_traffic("1920x1080", choice) is None
     monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
