@@ -230,8 +230,9 @@ flow_status flow_server_drain(flow_server* srv);
 flow_status flow_server_get_stats(const flow_server* srv, flow_server_stats* out);
 
 /* Batched autotuner: for each stage of this batch, time every tile-launch choice (table order or
- * per-XCD work queues; K = 2, 4, 6, 8, 10 iterations per launch, or the whole warp where every
- * level of the stage fits one tile; extended tile width 64 or 128) over one warp's iterations, and keep the
+ * per-XCD work queues; every K in [2, 10] that is the smallest for its number of launches per
+ * warp, ceil(iters / n), or the whole warp where every level of the stage fits one tile; extended
+ * tile width 64 or 128) over one warp's iterations, and keep the
  * fastest for later flow_solve_batched calls on batches whose stage has the same level shapes.
  * The choice changes speed only (results are bitwise the same).  Runs the pipeline on the pairs'
  * frames; blocking. */

@@ -23,11 +23,7 @@ namespace flowmi {
 // deterministic noise at the scale of image gradients and flows.  Timed on zeros, where no operand
 // changes, the ranking of launch shapes differed from the one in solves of images (at 1920 x 1080,
 // level 0, a choice 0.3% faster on zeros was 10% slower in the solve); on noise the two agree.
-// Iterations per launch worth timing for `iters` iterations per warp: for each launch count n the
-// smallest K that covers the warp in n launches, ceil(iters / n), within [kmin, kmax] (ascending).
-// A larger K with the same launch count only widens the halo (50 iterations: K = 12 and 10 both
-// take five launches).
-static std::vector<int> launch_ks(int iters, int kmin, int kmax) {
+std::vector<int> launch_ks(int iters, int kmin, int kmax) {
     std::vector<int> ks;
     for (int n = iters; n >= 1; --n) {
         const int K = (iters + n - 1) / n;

@@ -601,6 +601,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
         run_b(BatchOp::Linearize, tab, S.lin[0], f16, s);
         std::vector<StageChoice> cands;
         const bool all_res = shapes_all_resident(stage_shapes(P, S), hw);
+        const std::vector<int> ks = launch_ks(p->iters, 2, 10);
         for (int order : {ORDER_TABLE, ORDER_QUEUE}) {
             if (all_res) {
                 StageChoice c;
@@ -608,7 +609,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
                 c.K = p->iters;
                 cands.push_back(c);
             }
-            for (int K : {2, 4, 6, 8, 10})
+            for (int K : ks)
                 for (int ew : {64, 128})
                     if (stage_fits(P, S, hw, K, ew)) {
                         StageChoice c;

@@ -129,6 +129,11 @@ struct TunedChoice {
     double us_per_iter = 0;
 };
 std::string tune_key(int H, int W, bool hw, int iters);
+// Iterations per launch worth timing for `iters` iterations per warp: for each launch count n the
+// smallest K that covers the warp in n launches, ceil(iters / n), within [kmin, kmax] (ascending).
+// A larger K with the same launch count only widens the halo (50 iterations: K = 12 and 10 both
+// take five launches).
+std::vector<int> launch_ks(int iters, int kmin, int kmax);
 extern int g_tb_mode;
 extern int g_tb_k;
 extern int g_batch_order;   // batched tile launches: -1 tuned / built-in, 0 table order, 1 work queue
