@@ -78,7 +78,7 @@ StageChoice default_stage_choice(const Shapes& s, bool hw, int iters) {
     }
     int64_t px = 0;
     for (auto& x : s) px += (int64_t)x.first * x.second;
-    c.K = px >= 300000 ? 6 : 8;
+    c.K = px >= 300000 ? 5 : 8;
     return fit_stage_choice(c, s, hw);
 }
 

@@ -77,7 +77,7 @@ using Shapes = std::vector<std::pair<int, int>>;
 // Every shape takes tiles for exactly K iterations with width target ew (or fits one tile).
 bool shapes_fit(const Shapes& s, bool hw, int K, int ew);
 bool shapes_all_resident(const Shapes& s, bool hw);
-// Built-in choice: the whole warp in one launch where every level fits one tile; else 6 iterations
+// Built-in choice: the whole warp in one launch where every level fits one tile; else 5 iterations
 // per launch when the levels hold enough pixels to fill the chip with tiles (many rounds of
 // work-groups, where the recomputed halo costs throughput), 8 otherwise.
 StageChoice default_stage_choice(const Shapes& s, bool hw, int iters);
