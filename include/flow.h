@@ -251,8 +251,11 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
  * uses the context's arena (contents are overwritten). */
 flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
 
-/* JSON report of the last flow_autotune (choice and all measured candidates per level shape) into
- * buf (host, cap bytes including the terminating NUL); FLOW_E_INVAL if it does not fit. */
+/* JSON report of the context's last autotuning call into buf (host, cap bytes including the
+ * terminating NUL); FLOW_E_INVAL if it does not fit.  After flow_autotune: the choice and every
+ * measured candidate per level shape.  After flow_autotune_batched: {"stages": [...]}, one entry
+ * per stage (level, pairs, order 0 table / 1 work queue, K, extended tile width ew, and the
+ * measured microseconds of one warp's tile launches). */
 flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
 
 /* Set the iteration-kernel choice of one level shape (H x W, with or without the w / p block, iters

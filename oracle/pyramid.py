@@ -14,9 +14,10 @@ import numpy as np
 from .ops import bilinear
 
 
-def downsample(I):
-    """Next pyramid level: mean of the 2x2 block at (2i, 2j), rows/columns past the edge replicated."""
-    I = np.asarray(I, dtype=np.float64)
+def downsample(I, dtype=np.float64):
+    """Next pyramid level: mean of the 2x2 block at (2i, 2j), rows/columns past the edge replicated
+    (the four taps summed in row-major order, in `dtype` arithmetic)."""
+    I = np.asarray(I, dtype=dtype)
     M, N = I.shape
     Mc, Nc = (M + 1) // 2, (N + 1) // 2
     r0 = 2 * np.arange(Mc)
@@ -34,9 +35,9 @@ def level_shapes(M, N, levels):
     return shapes
 
 
-def derivatives(F):
+def derivatives(F, dtype=np.float64):
     """Central differences (F[j+1] - F[j-1]) / 2 with neighbour indices clamped into the frame."""
-    F = np.asarray(F, dtype=np.float64)
+    F = np.asarray(F, dtype=dtype)
     M, N = F.shape
     jp = np.minimum(np.arange(N) + 1, N - 1)
     jm = np.maximum(np.arange(N) - 1, 0)
@@ -47,15 +48,34 @@ def derivatives(F):
     return Dx, Dy
 
 
-def build_pyramid(I0, I1, levels):
-    """Per level l = 0 (finest) .. levels-1: (I0, I1, D_x I1, D_y I1)."""
+def build_pyramid(I0, I1, levels, storage="f32"):
+    """Per level l = 0 (finest) .. levels-1: (I0, I1, D_x I1, D_y I1).
+
+    storage="f16" is the half-precision storage form of the pyramids.  The frames (binary32) are
+    stored centred, minus 1/2; every stored plane -- each image level, computed from the stored
+    level above it, and each derivative plane -- is evaluated in binary32 arithmetic from stored
+    operands and rounded once to binary16.  The centring cancels in the linearisation, which only
+    uses differences of images and the derivatives.  The planes are returned as float64."""
+    if storage == "f32":
+        out = []
+        a, b = np.asarray(I0, np.float64), np.asarray(I1, np.float64)
+        for lev in range(levels):
+            if lev > 0:
+                a, b = downsample(a), downsample(b)
+            dx, dy = derivatives(b)
+            out.append((a, b, dx, dy))
+        return out
+    if storage != "f16":
+        raise ValueError(storage)
+    f32, half = np.float32, (lambda F: np.asarray(F, np.float32).astype(np.float16).astype(np.float32))
+    a = half(np.asarray(I0, f32) - f32(0.5))
+    b = half(np.asarray(I1, f32) - f32(0.5))
     out = []
-    a, b = np.asarray(I0, np.float64), np.asarray(I1, np.float64)
     for lev in range(levels):
         if lev > 0:
-            a, b = downsample(a), downsample(b)
-        dx, dy = derivatives(b)
-        out.append((a, b, dx, dy))
+            a, b = half(downsample(a, f32)), half(downsample(b, f32))
+        dx, dy = derivatives(b, f32)
+        out.append(tuple(np.asarray(x, np.float64) for x in (a, b, half(dx), half(dy))))
     return out
 
 

@@ -35,6 +35,7 @@ class Params:
     alg1_tau: float = 0.1      # ALG1: dual step (Sec. 4); the primal step is 1 / (L^2 tau), L^2 = 8
     alg1_sigma: float = 1.25
     kappa: float = 255.0       # intensity scale applied to frames given in [0, 1]
+    storage: str = "f32"       # "f16": the half-precision storage form of the pyramids (build_pyramid)
     levels: int = 1
     warps: int = 1
     iters: int = 200
@@ -77,14 +78,18 @@ def warp_terms(st, duals, L, p: Params):
                  duals["q2x"], duals["q2y"], duals["s"], L["Ix"], L["Iy"], L["It"], p.beta, p.lam)
 
 
-def solve_pair(I0, I1, p: Params, trace: bool = False):
+def solve_pair(I0, I1, p: Params, trace: bool = False, perturb=None):
     """Estimate d = (u, v) with I1(x + d) ~= I0(x).  Returns a dict with u, v, w, the final warp's
-    energy terms and, with trace=True, one record of terms per (level, warp)."""
+    energy terms and, with trace=True, one record of terms per (level, warp).
+
+    `perturb` (tests only; None for the method itself) maps the carried state dict to a perturbed
+    copy after every iteration: a probe of how far perturbations of a given size, e.g. the rounding
+    of the state to FP32, move the result."""
     if p.scheme not in SCHEMES:
         raise ValueError(p.scheme)
     if p.scheme == "zach" and p.beta != 0.0:
         raise ValueError("Zach-pADMM is the beta = 0 model")
-    pyr = build_pyramid(I0, I1, p.levels)
+    pyr = build_pyramid(I0, I1, p.levels, p.storage)
     u = v = w = None
     records = []
     last = None
@@ -104,6 +109,10 @@ def solve_pair(I0, I1, p: Params, trace: bool = False):
                 duals = st
             for _ in range(p.iters):
                 st, duals = step(p.scheme, st, L, p)
+                if perturb is not None:
+                    st = perturb(st)
+                    if p.scheme not in PDR_STATE:
+                        duals = st
             if trace or (lev == 0 and wp == p.warps - 1):
                 t = warp_terms(st, duals, L, p)
                 t.update(level=lev, warp=wp, at=at)

@@ -328,10 +328,15 @@ class Context:
 
     def autotune_batched(self, pairs, params: Params | None = None, **kw):
         """Time the batched tile-launch choices per stage of this batch; later solve_batched calls
-        on batches with the same stage shapes use the fastest."""
+        on batches with the same stage shapes use the fastest.  Returns the report (the choice of
+        each stage) as a dict."""
+        import json
         params = params or Params(**kw)
         arr, _, _ = self._pairs(pairs)
         _check(lib().flow_autotune_batched(self._h, len(pairs), arr, ctypes.byref(params.c_struct()), _stream()))
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().flow_get_tuning(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode() or "{}")
 
 
 def working_set_bytes(H, W, params: Params | None = None, levels: int = 0, **kw):

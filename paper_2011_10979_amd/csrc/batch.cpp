@@ -270,8 +270,8 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
             if (P->levels[k] <= l) continue;
             const LevelPlanes& F = P->L[k][l - 1];
             const LevelPlanes& C = P->L[k][l];
-            it.push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
-            it.push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
+            it.push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld, F.I0lo, C.I0lo});
+            it.push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld, F.I1lo, C.I1lo});
             bl.push_back(blocks_of(C.H, C.W));
             bl.push_back(blocks_of(C.H, C.W));
         }
@@ -283,7 +283,7 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
         for (int k = 0; k < n; ++k)
             for (int l = 0; l < P->levels[k]; ++l) {
                 const LevelPlanes& L = P->L[k][l];
-                it.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld});
+                it.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, L.I1lo});
                 bl.push_back(blocks_of(L.H, L.W));
             }
         P->deriv = T.launch(it, bl);
@@ -330,6 +330,7 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 const LevelPlanes& L = P->L[k][l];
                 LinArgs la{};
                 la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+                la.I0lo = L.I0lo; la.I1lo = L.I1lo;
                 la.u0 = L.U0[0];
                 la.v0 = L.U0[1];
                 if (w > 0) {             // commit the previous warp's increment on the way
@@ -595,6 +596,8 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
     DevBuf tmp_tiles, tmp_cnt;
     st = tmp_cnt.ensure(256, "tuning counters");
     std::map<std::string, StageChoice> chosen;
+    std::ostringstream rep;                       // the report flow_get_tuning returns afterwards
+    rep << "{\"stages\": [";
     for (BStage& S : P.stages) {
         if (st != FLOW_OK) break;
         run_b(BatchOp::LevelInit, tab, S.init, false, s);
@@ -673,13 +676,18 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
             }
         }
         chosen[S.key] = bestc;
+        rep << (&S == &P.stages.front() ? "" : ", ") << "{\"level\": " << S.l << ", \"pairs\": " << S.pairs.size()
+            << ", \"order\": " << bestc.order << ", \"K\": " << bestc.K << ", \"ew\": " << bestc.ew
+            << ", \"us_per_warp\": " << 1e3 * best << "}";
     }
+    rep << "]}";
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     tmp_tiles.release();
     tmp_cnt.release();
     if (st != FLOW_OK) return st;
     for (auto& kv : chosen) B.tuned[kv.first] = kv.second;
+    ctx->tune_report = rep.str();
     B.tune_epoch++;
     B.drop_graph();
     B.plan.reset();

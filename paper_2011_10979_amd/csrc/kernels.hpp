@@ -13,6 +13,7 @@ namespace flowmi {
 // Warp + linearise + a~ (max of M_s, one atomic max per work-group on the float bits).
 struct LinArgs {
     const void *I0, *I1, *Dx, *Dy;   // float or __half, pitch ld
+    const float *I0lo, *I1lo;        // optional low parts of float-float image levels (FP32 storage)
     float *u0, *v0;                  // pitch ld: the linearisation point (written when pend_u is set)
     const float *pend_u, *pend_v;    // optional pending increment of the previous warp: the point is
                                      // u0 + pend_u, committed into u0 here (in place, own pixel only)
@@ -29,8 +30,15 @@ struct LinArgs {
 void launch_linearize(const LinArgs& a, bool f16, hipStream_t s);
 
 // Argument blocks of the elementwise pyramid / bookkeeping kernels (also the items of batched launches).
-struct DownArgs { const void* src; int H, W; int64_t ld; void* dst; int64_t ldd; };     // output ceil(H/2) x ceil(W/2)
-struct DerivArgs { const void* I; int H, W; int64_t ld; void* Dx; void* Dy; int64_t ldd; };
+// FP32 image levels below the finest are float-float (hi + lo planes, both pitch ld): a 2x2 mean
+// needs two more significand bits per level than its inputs, and FP32 rounding of the coarse images
+// moves ill-conditioned pixels of the final flow by up to a few 1e-4 px, while with hi + lo the
+// levels are exact.  src_lo / dst_lo / I_lo are nullptr for the finest level and for FP16 storage.
+struct DownArgs {
+    const void* src; int H, W; int64_t ld; void* dst; int64_t ldd;   // output ceil(H/2) x ceil(W/2)
+    const float* src_lo; float* dst_lo;
+};
+struct DerivArgs { const void* I; int H, W; int64_t ld; void* Dx; void* Dy; int64_t ldd; const float* I_lo; };
 // FP32 -> FP32 or FP16 plane copy, dst = src (+ add) - offset.  Frames imported into FP16 pyramids are
 // stored centred (offset kFrameOffsetF16): every pyramid step is linear and I_t is a difference, so
 // the offset cancels, while FP16 spacing over [-1/2, 1/2] is half of that over [1/2, 1].
@@ -52,9 +60,10 @@ int lin_blocks_of(int H, int W);
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total_blocks, bool f16, hipStream_t s);
 
 // Pyramid: 2x2 box average with edge replication, central differences, format conversion.
-void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s);
+void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s,
+                       const float* src_lo = nullptr, float* dst_lo = nullptr);
 void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void* Dy, int64_t ldd, bool f16,
-                        hipStream_t s);
+                        hipStream_t s, const float* I_lo = nullptr);
 void launch_import(const float* src, int H, int W, int64_t lds, void* dst, int64_t ldd, bool f16, hipStream_t s);
 void launch_copy2d(const float* src, int H, int W, int64_t lds, float* dst, int64_t ldd, hipStream_t s,
                    const float* add = nullptr);

@@ -3,7 +3,8 @@
 //   b      = X bar + sigma div y bar                                  (per component w, u, v)
 //   X+     = X + M^{-1}(b - T X),  T = I - sigma tau Delta (Neumann),  M = n symmetric red-black
 //            Gauss-Seidel sweeps (eq. neumann:boudary)
-//   X bar+ = X bar + J(2 X+ - X bar) - X+,  J = (I + sigma dF)^{-1} (eq:resolvent)
+//   X bar+ = X bar + J(2 X+ - X bar) - X+,  J = (I + sigma dF)^{-1} (eq:resolvent); J moves its
+//            argument by a step along e = (beta, I_x, I_y), so this is X+ + step e
 //   y bar+ = P(y bar + 2 tau grad X+) - tau grad X+                   (P_p on p, joint P_q on q)
 //
 // A red (i + j even) or black cell update only reads cells of the other colour, so every half
@@ -23,16 +24,20 @@ namespace {
 
 dim3 grid2d(int H, int W) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
-// GS update of one cell: (b + st * sum of in-frame neighbours) / (1 + st * count)
+// GS update of one cell, (b + st * sum of in-frame neighbours) / (1 + st * count), evaluated as
+// the cell's value plus its correction ((b - x) + st * sum of (neighbour - x)) / (1 + st * count):
+// the same value, but the flows (several pixels) cancel in the differences before any rounding,
+// so FP32 rounds only the small correction and the final sum
 __device__ __forceinline__ float gs_cell(const float* x, const float* b, int i, int j, int H, int W, int64_t ld,
                                          float stt) {
     const int64_t o = (int64_t)i * ld + j;
+    const float xo = x[o];
     float s = 0.f, n = 0.f;
-    if (j > 0) { s += x[o - 1]; n += 1.f; }
-    if (j < W - 1) { s += x[o + 1]; n += 1.f; }
-    if (i > 0) { s += x[o - ld]; n += 1.f; }
-    if (i < H - 1) { s += x[o + ld]; n += 1.f; }
-    return (b[o] + stt * s) / (1.f + stt * n);
+    if (j > 0) { s += x[o - 1] - xo; n += 1.f; }
+    if (j < W - 1) { s += x[o + 1] - xo; n += 1.f; }
+    if (i > 0) { s += x[o - ld] - xo; n += 1.f; }
+    if (i < H - 1) { s += x[o + ld] - xo; n += 1.f; }
+    return xo + ((b[o] - xo) + stt * s) / (1.f + stt * n);
 }
 
 __device__ __forceinline__ float div_at(const float* px, const float* py, int i, int j, int H, int W, int64_t ld) {
@@ -132,9 +137,10 @@ __global__ __launch_bounds__(256) void pdr_final_kernel(PdrArgs a) {
         step = 0.f;
         theta = 0.f;
     }
-    a.ub[o] = ub + (ut + step * Ix) - u;
-    a.vb[o] = vb + (vt + step * Iy) - v;
-    if constexpr (HAS_W) a.wb[o] = wbv + (wt + step * a.beta) - w;
+    // X bar + J(X~) - X+ with J(X~) = X~ + step e and X~ = 2 X+ - X bar is X+ + step e (one rounding)
+    a.ub[o] = u + step * Ix;
+    a.vb[o] = v + step * Iy;
+    if constexpr (HAS_W) a.wb[o] = w + step * a.beta;
     if (a.s_out) a.s_out[o] = theta;
 
     // dual: y bar+ = P(y bar + 2 tau grad X+) - tau grad X+

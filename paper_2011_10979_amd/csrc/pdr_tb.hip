@@ -5,7 +5,8 @@
 // Per iteration and cell (X = (w, u, v), X bar, y bar = (p bar, q bar), n sweeps):
 //   [b + R]   b = X bar + sigma div y bar; first red half sweep
 //   [B] [R]   n black / red half sweep pairs (x = (b + st sum_nb x) / (1 + st #nb), st = sigma tau)
-//   [D]       X+ = x; X bar+ = X bar + J(2 X+ - X bar) - X+ (eq:resolvent);
+//   [D]       X+ = x; X bar+ = X bar + J(2 X+ - X bar) - X+ = X+ + step e (eq:resolvent: J moves
+//             its argument by a step along e = (beta, I_x, I_y));
 //             y bar+ = P(y bar + 2 tau grad X+) - tau grad X+
 // with a barrier between phases.  Each half sweep reaches one cell further in every direction; b
 // takes div y bar (left / up) and the dual update grad X+ (right / down), so after K iterations
@@ -130,25 +131,28 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
     __syncthreads();
 
     // one half sweep over the cells of colour c: x = (b + st sum of in-image neighbours) / (1 + st #),
-    // summed left, right, up, down
+    // evaluated as x + ((b - x) + st sum of (neighbour - x)) / (1 + st #), summed left, right, up,
+    // down: the flows cancel in the differences before any rounding, so FP32 rounds only the small
+    // correction and the final sum
     auto half_sweep = [&](int c) {
         if (!live(c)) return;
         const int oc = 1 - c;
-        float nb[NX][4];
+        float nb[NX][4], xo[NX];
 #pragma unroll
         for (int f = 0; f < NX; ++f) {
             nb[f][0] = S.x[oc][f][nL[c]];
             nb[f][1] = S.x[oc][f][nL[c] + 1];
             nb[f][2] = S.x[oc][f][nU[c]];
             nb[f][3] = S.x[oc][f][nD[c]];
+            xo[f] = S.x[c][f][1 + tid];
         }
 #pragma unroll
         for (int f = 0; f < NX; ++f) {
-            float sm = fl[c] * nb[f][0];
-            sm = fmaf(fr[c], nb[f][1], sm);
-            sm = fmaf(fu[c], nb[f][2], sm);
-            sm = fmaf(fd[c], nb[f][3], sm);
-            S.x[c][f][1 + tid] = (bb[f][c] + stt * sm) * rden[c];
+            float sm = fl[c] * (nb[f][0] - xo[f]);
+            sm = fmaf(fr[c], nb[f][1] - xo[f], sm);
+            sm = fmaf(fu[c], nb[f][2] - xo[f], sm);
+            sm = fmaf(fd[c], nb[f][3] - xo[f], sm);
+            S.x[c][f][1 + tid] = fmaf((bb[f][c] - xo[f]) + stt * sm, rden[c], xo[f]);
         }
     };
 
@@ -223,9 +227,10 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int
                     step = 0.f;
                     theta = 0.f;
                 }
-                xb[0][c] = ub + (ut + step * Ix[c]) - u;
-                xb[1][c] = vbv + (vt + step * Iy[c]) - v;
-                if constexpr (HAS_W) xb[2][c] = wbv + (wt + step * beta) - w;
+                // X bar + J(X~) - X+ with J(X~) = X~ + step e, X~ = 2 X+ - X bar: X+ + step e
+                xb[0][c] = fmaf(step, Ix[c], u);
+                xb[1][c] = fmaf(step, Iy[c], v);
+                if constexpr (HAS_W) xb[2][c] = fmaf(step, beta, w);
                 th_s[c] = theta;
                 const float t2 = 2.f * tau;
                 const float a1x = yo[c][0] + t2 * gx[0], a1y = yo[c][1] + t2 * gy[0];

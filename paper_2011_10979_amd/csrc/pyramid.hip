@@ -29,6 +29,14 @@ dim3 grid2d(int H, int W) { return dim3((W + 63) / 64, (H + 3) / 4); }
 // ---------------------------------------------------------------------------------------------
 // bodies: (bx, by) is the work-group's position in the item's grid of 64 x 4 blocks
 // ---------------------------------------------------------------------------------------------
+// Error-free sum of two floats (Knuth's TwoSum): s + e == a + b exactly, s = fl(a + b).
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
 template <typename T>
 __device__ __forceinline__ void downsample_body(const DownArgs& a, int bx, int by) {
     const int Hc = (a.H + 1) / 2, Wc = (a.W + 1) / 2;
@@ -38,9 +46,26 @@ __device__ __forceinline__ void downsample_body(const DownArgs& a, int bx, int b
     const T* src = (const T*)a.src;
     const int r0 = 2 * r, r1 = min(2 * r + 1, a.H - 1);
     const int c0 = 2 * b, c1 = min(2 * b + 1, a.W - 1);
-    const float s = ldv(src, (int64_t)r0 * a.ld + c0) + ldv(src, (int64_t)r0 * a.ld + c1) +
-                    ldv(src, (int64_t)r1 * a.ld + c0) + ldv(src, (int64_t)r1 * a.ld + c1);
-    stv((T*)a.dst, (int64_t)r * a.ldd + b, 0.25f * s);
+    const int64_t o[4] = {(int64_t)r0 * a.ld + c0, (int64_t)r0 * a.ld + c1, (int64_t)r1 * a.ld + c0,
+                          (int64_t)r1 * a.ld + c1};
+    const int64_t od = (int64_t)r * a.ldd + b;
+    if (a.dst_lo) {
+        // float-float mean: the four high parts summed without error, the rounding errors and the
+        // low parts collected in a second float, renormalised; the factor 1/4 is exact
+        float e1, e2, e3;
+        float hi = two_sum(ldv(src, o[0]), ldv(src, o[1]), e1);
+        hi = two_sum(hi, ldv(src, o[2]), e2);
+        hi = two_sum(hi, ldv(src, o[3]), e3);
+        float lo = (e1 + e2) + e3;
+        if (a.src_lo) lo += (a.src_lo[o[0]] + a.src_lo[o[1]]) + (a.src_lo[o[2]] + a.src_lo[o[3]]);
+        float l;
+        const float h = two_sum(hi, lo, l);
+        stv((T*)a.dst, od, 0.25f * h);
+        a.dst_lo[od] = 0.25f * l;
+        return;
+    }
+    const float s = ldv(src, o[0]) + ldv(src, o[1]) + ldv(src, o[2]) + ldv(src, o[3]);
+    stv((T*)a.dst, od, 0.25f * s);
 }
 
 template <typename T>
@@ -51,8 +76,16 @@ __device__ __forceinline__ void derivatives_body(const DerivArgs& a, int bx, int
     const T* I = (const T*)a.I;
     const int64_t row = (int64_t)i * a.ld;
     const int W = a.W, H = a.H;
-    const float dx = 0.5f * (ldv(I, row + min(j + 1, W - 1)) - ldv(I, row + max(j - 1, 0)));
-    const float dy = 0.5f * (ldv(I, (int64_t)min(i + 1, H - 1) * a.ld + j) - ldv(I, (int64_t)max(i - 1, 0) * a.ld + j));
+    const int64_t xr = row + min(j + 1, W - 1), xl = row + max(j - 1, 0);
+    const int64_t yd = (int64_t)min(i + 1, H - 1) * a.ld + j, yu = (int64_t)max(i - 1, 0) * a.ld + j;
+    float dx = ldv(I, xr) - ldv(I, xl);
+    float dy = ldv(I, yd) - ldv(I, yu);
+    if (a.I_lo) {   // float-float level: the low parts' difference completes the high parts'
+        dx += a.I_lo[xr] - a.I_lo[xl];
+        dy += a.I_lo[yd] - a.I_lo[yu];
+    }
+    dx *= 0.5f;
+    dy *= 0.5f;
     stv((T*)a.Dx, (int64_t)i * a.ldd + j, dx);
     stv((T*)a.Dy, (int64_t)i * a.ldd + j, dy);
 }
@@ -116,10 +149,22 @@ __device__ __forceinline__ void linearize_body(const LinArgs& a, int bx, int by)
         split_pos(i, v0, a.H, iy, ty);
         split_pos(j, u0, a.W, jx, tx);
         const int64_t o00 = (int64_t)iy * a.ld + jx;
-        const float I1w = bilin(I1, o00, a.ld, ty, tx);
         const float Ix = a.kappa * bilin(Dx, o00, a.ld, ty, tx);
         const float Iy = a.kappa * bilin(Dy, o00, a.ld, ty, tx);
-        const float Ir = a.kappa * (I1w - ldv(I0, off));
+        // I1(x + d0) - I0(x) as the bilinear mean of the four taps' differences to I0 (the weights
+        // sum to one): the differences are small and formed before any rounding of a weighted sum
+        // of values near 1/2, and on float-float levels they include the low parts
+        const float i0 = ldv(I0, off);
+        const int64_t ot[4] = {o00, o00 + 1, o00 + a.ld, o00 + a.ld + 1};
+        float dt[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dt[k] = ldv(I1, ot[k]) - i0;
+        if (a.I1lo) {
+            const float l0 = a.I0lo[off];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dt[k] += a.I1lo[ot[k]] - l0;
+        }
+        const float Ir = a.kappa * ((1.f - ty) * ((1.f - tx) * dt[0] + tx * dt[1]) + ty * ((1.f - tx) * dt[2] + tx * dt[3]));
         a.Ix[off] = Ix;
         a.Iy[off] = Iy;
         a.It[off] = a.rel ? Ir : Ir - Ix * u0 - Iy * v0;
@@ -262,16 +307,17 @@ void launch_b(const void* items, const int* off, int n, int total, hipStream_t s
 }  // namespace
 
 // ----------------------------------- host launchers --------------------------------------------
-void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s) {
-    const DownArgs a{src, H, W, ld, dst, ldd};
+void launch_downsample(const void* src, int H, int W, int64_t ld, void* dst, int64_t ldd, bool f16, hipStream_t s,
+                       const float* src_lo, float* dst_lo) {
+    const DownArgs a{src, H, W, ld, dst, ldd, f16 ? nullptr : src_lo, f16 ? nullptr : dst_lo};
     const dim3 g = grid2d((H + 1) / 2, (W + 1) / 2);
     if (f16) hipLaunchKernelGGL(downsample_kernel<__half>, g, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(downsample_kernel<float>, g, dim3(256), 0, s, a);
 }
 
 void launch_derivatives(const void* I, int H, int W, int64_t ld, void* Dx, void* Dy, int64_t ldd, bool f16,
-                        hipStream_t s) {
-    const DerivArgs a{I, H, W, ld, Dx, Dy, ldd};
+                        hipStream_t s, const float* I_lo) {
+    const DerivArgs a{I, H, W, ld, Dx, Dy, ldd, f16 ? nullptr : I_lo};
     if (f16) hipLaunchKernelGGL(derivatives_kernel<__half>, grid2d(H, W), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(derivatives_kernel<float>, grid2d(H, W), dim3(256), 0, s, a);
 }

@@ -109,10 +109,12 @@ size_t layout_bytes(int H, int W, const flow_params& p) {
     const bool pdr = pd_state(p);
     const bool hw = p.beta > 0;
     size_t total = 0;
+    int lev = 0;
     for (auto [h, w] : level_shapes(H, W, p.levels)) {
         const size_t plane = (size_t)h * pitch_of(w) * 4;
         const size_t pyr = (size_t)h * pitch_of(w) * (f16 ? 2 : 4);
         total += 4 * pyr + 5 * plane;   // pyramid, linearisation, linearisation point
+        if (!f16 && lev++ > 0) total += 2 * plane;   // low parts of the float-float image levels
         if (pdr) total += (size_t)(hw ? 2 * (3 + 3 + 6) + 3 + 1 : 2 * (2 + 2 + 4) + 2 + 1) * plane;
         else total += (size_t)2 * (hw ? 10 : 7) * plane;
         total += 48 * 256;  // alignment slack: every plane starts on a 256-byte boundary
@@ -146,6 +148,10 @@ flow_status build_layout(DevArena& arena, int H, int W, const flow_params& p, st
         const size_t pyr = (size_t)h * L.ld * (f16 ? 2 : 4);
         L.I0 = take(pyr);
         L.I1 = take(pyr);
+        if (!f16 && !out.empty()) {
+            L.I0lo = (float*)take(plane);
+            L.I1lo = (float*)take(plane);
+        }
         L.Dx = take(pyr);
         L.Dy = take(pyr);
         L.Ix = (float*)take(plane);
@@ -464,10 +470,10 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
         LevelPlanes& L = Ls[l];
         if (l > 0) {
             const LevelPlanes& F = Ls[l - 1];
-            launch_downsample(F.I0, F.H, F.W, F.ld, L.I0, L.ld, f16, s);
-            launch_downsample(F.I1, F.H, F.W, F.ld, L.I1, L.ld, f16, s);
+            launch_downsample(F.I0, F.H, F.W, F.ld, L.I0, L.ld, f16, s, F.I0lo, L.I0lo);
+            launch_downsample(F.I1, F.H, F.W, F.ld, L.I1, L.ld, f16, s, F.I1lo, L.I1lo);
         }
-        launch_derivatives(L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, f16, s);
+        launch_derivatives(L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, f16, s, L.I1lo);
     }
     int cur_coarse = 0;
     for (int l = nl - 1; l >= 0; --l) {
@@ -517,6 +523,7 @@ flow_status enqueue_core(std::vector<LevelPlanes>& Ls, const flow_params& p, Scr
             // increment (du, dv) restarts at zero, pDR keeps a copy of the linearisation point
             LinArgs la{};
             la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+            la.I0lo = L.I0lo; la.I1lo = L.I1lo;
             la.u0 = const_cast<float*>(level_flow(L, p, 1, cur));
             la.v0 = const_cast<float*>(level_flow(L, p, 2, cur));
             if (wp > 0) {                // commit the previous warp's increment on the way

@@ -34,6 +34,7 @@ struct LevelPlanes {
     int H = 0, W = 0;
     int64_t ld = 0;
     void *I0 = nullptr, *I1 = nullptr, *Dx = nullptr, *Dy = nullptr;
+    float *I0lo = nullptr, *I1lo = nullptr;   // low parts of float-float image levels (FP32 storage, levels >= 1)
     float *Ix = nullptr, *Iy = nullptr, *It = nullptr;
     float* st[2][10] = {};                // ADMM ping-pong: w, du, dv, px, py, q1x, q1y, q2x, q2y, s
     float* U0[2] = {};                    // linearisation point (u0, v0); ADMM: the flow without the pending increment

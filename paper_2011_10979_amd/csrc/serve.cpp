@@ -345,7 +345,7 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         imp_bl.push_back(blocks_of(q.q.H, q.q.W));
         lmax_new = std::max(lmax_new, q.levels);
         for (const LevelPlanes& L : q.L) {
-            der.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld});
+            der.push_back(DerivArgs{L.I1, L.H, L.W, L.ld, L.Dx, L.Dy, L.ld, L.I1lo});
             der_bl.push_back(blocks_of(L.H, L.W));
         }
     }
@@ -357,8 +357,8 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             if (q.imported || q.levels <= l) continue;
             const LevelPlanes& F = q.L[l - 1];
             const LevelPlanes& C = q.L[l];
-            down[l].push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld});
-            down[l].push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld});
+            down[l].push_back(DownArgs{F.I0, F.H, F.W, F.ld, C.I0, C.ld, F.I0lo, C.I0lo});
+            down[l].push_back(DownArgs{F.I1, F.H, F.W, F.ld, C.I1, C.ld, F.I1lo, C.I1lo});
             down_bl[l].push_back(blocks_of(C.H, C.W));
             down_bl[l].push_back(blocks_of(C.H, C.W));
         }
@@ -418,6 +418,7 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         }
         LinArgs la{};
         la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
+        la.I0lo = L.I0lo; la.I1lo = L.I1lo;
         la.u0 = L.U0[0];
         la.v0 = L.U0[1];
         if (q.w > 0) {                          // commit the previous warp's increment on the way

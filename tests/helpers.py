@@ -58,54 +58,71 @@ def max_abs(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(a) else 0.0
 
 
+TOL_F32 = 1e-4     # max |du|, |dv| against the FP64 oracle at a fixed iteration count (px)
+N_PROBES = 8       # FP32-rounding probes of the oracle, for pixels above TOL_F32
+F_PROBE = 6.0      # a pixel may sit F_PROBE x the probes' largest departure from the oracle away
+
+
 def _oracle_job(args):
     from oracle import Params as OParams, solve_pair
-    I0, I1, kw = args
-    r = solve_pair(I0, I1, OParams(**kw))
-    return r["u"], r["v"], (r["energy"], r["gap"])
+    I0, I1, kw = args[:3]
+    perturb = None
+    if len(args) > 3:
+        # the state rounded to FP32 after every iteration, each value first nudged by a uniform
+        # relative amount within one FP32 half-ulp (seeded): a model of FP32 storage of the iterate
+        rng = np.random.default_rng(args[3])
+
+        def perturb(st):
+            return {k: (np.asarray(x * (1.0 + rng.uniform(-2.0 ** -24, 2.0 ** -24, x.shape)), np.float32)
+                        .astype(np.float64) if isinstance(x, np.ndarray) else x) for k, x in st.items()}
+    r = solve_pair(I0, I1, OParams(**kw), perturb=perturb)
+    return {k: r[k] for k in ("u", "v", "energy", "gap")}
 
 
-def oracle_with_sensitivity(jobs, pool, probes=1):
-    """Start the FP64 oracle on every (I0, I1, kwargs) job and on `probes` copies of its frames
-    perturbed by independent 1e-7 relative noise (seeded), in `pool`.  Returns a callable
-    get(timeout) -> [[ref, pert_1, ..., pert_probes] per job]."""
-    rng = np.random.default_rng(123)
-    work = []
-    for I0, I1, kw in jobs:
-        work.append((I0, I1, kw))
-        for _ in range(probes):
-            P0 = I0 * (1 + 1e-7 * rng.standard_normal(I0.shape))
-            P1 = I1 * (1 + 1e-7 * rng.standard_normal(I1.shape))
-            work.append((P0, P1, kw))
-    fut = pool.map_async(_oracle_job, work)
-
-    def get(timeout):
-        r = fut.get(timeout=timeout)
-        g = probes + 1
-        return [r[g * k:g * (k + 1)] for k in range(len(jobs))]
-    return get
+def oracle_refs(jobs, pool):
+    """Start the FP64 oracle on every (I0, I1, kwargs) job in `pool` (so that it runs while the GPU
+    works).  Returns a callable get(timeout) -> [dict(u, v, energy, gap) per job]."""
+    fut = pool.map_async(_oracle_job, list(jobs))
+    return lambda timeout: fut.get(timeout=timeout)
 
 
-def assert_conditioned(name, u, v, res, ref, perts):
-    """Per-pixel bar 1e-4 px + 10 x the oracle's own response to perturbations of its input frames
-    of the size of FP32 rounding (largest over the probes and over a 5 x 5 neighbourhood); energy /
-    gap within 1e-6 / 1e-5 of the energy, widened likewise."""
-    import scipy.ndimage
-    ru, rv, (re, rgap) = ref
-    resp = np.zeros_like(ru)
-    de = dg = 0.0
-    for pu, pv, (pe, pgap) in perts:
-        resp = np.maximum(resp, np.maximum(np.abs(pu - ru), np.abs(pv - rv)))
-        de = max(de, abs(pe - re))
-        dg = max(dg, abs(pgap - rgap))
+def assert_parity(name, u, v, res, ref, mean_tol=None, job=None):
+    """The FP32 contract against the FP64 oracle: every pixel within max |du|, |dv| <= 1e-4 px, the
+    energy within 1e-6 relative and the dual gap within 1e-5 of the energy.  Prints the maximum,
+    p99.9, mean and the count of pixels above 1e-4; `mean_tol` also bounds the mean difference
+    (full-size workloads).
+
+    Where some pixels sit above 1e-4 and `job` (the oracle's (I0, I1, kwargs)) is given, the oracle
+    is run N_PROBES more times with its state rounded to FP32 after every iteration (random
+    sub-ulp nudges, seeds 0..N_PROBES-1), and a pixel passes if it is within F_PROBE x the largest
+    departure of those probes from the oracle there: such a pixel moves that far under FP32
+    rounding of the oracle's own state, which no FP32 arithmetic avoids."""
+    ru, rv = ref["u"], ref["v"]
     d = np.maximum(np.abs(u - ru), np.abs(v - rv))
-    sens = scipy.ndimage.maximum_filter(resp, size=5, mode="nearest")
-    print(f"[parity] {name}: max {d.max():.3e} p99.9 {np.quantile(d, 0.999):.3e} mean {d.mean():.3e}; "
-          f"sensitivity max {sens.max():.2e} ({len(perts)} probes); energy {res['energy']:.4f} vs {re:.4f}", flush=True)
-    bad = d > 1e-4
-    for i, j in list(zip(*np.where(bad)))[:20]:
-        print(f"[parity] {name}: pixel ({i},{j}) |d| {d[i, j]:.2e} sensitivity {sens[i, j]:.2e} "
-              f"oracle u,v {ru[i, j]:.4f},{rv[i, j]:.4f}", flush=True)
-    assert np.all(d <= 1e-4 + 10.0 * sens), float((d - 1e-4 - 10.0 * sens).max())
-    assert abs(res["energy"] - re) <= 1e-6 * re + 10.0 * de, (res["energy"], re, de)
-    assert abs(res["gap"] - rgap) <= 1e-5 * re + 10.0 * dg, (res["gap"], rgap, dg)
+    bad = d > TOL_F32
+    i, j = np.unravel_index(int(np.argmax(d)), d.shape)
+    print(f"[parity] {name}: max {d.max():.3e} at ({i},{j}) p99.9 {np.quantile(d, 0.999):.3e} mean {d.mean():.3e} "
+          f"pixels > 1e-4: {int(bad.sum())} of {d.size}; energy {res['energy']:.6f} vs {ref['energy']:.6f}, "
+          f"gap {res['gap']:.6f} vs {ref['gap']:.6f}", flush=True)
+    if bad.any() and job is not None:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(N_PROBES) as pool:
+            probes = pool.map(_oracle_job, [tuple(job) + (k,) for k in range(N_PROBES)])
+        spread = np.zeros_like(d)
+        for pr in probes:
+            spread = np.maximum(spread, np.maximum(np.abs(pr["u"] - ru), np.abs(pr["v"] - rv)))
+        bar = np.maximum(TOL_F32, F_PROBE * spread)
+        for a, b in list(zip(*np.where(bad)))[:10]:
+            print(f"[parity] {name}: pixel ({a},{b}) |d| {d[a, b]:.2e}, FP32-rounding probes of the oracle "
+                  f"depart {spread[a, b]:.2e} there (bar {bar[a, b]:.2e})", flush=True)
+        bad = d > bar
+    else:
+        for a, b in list(zip(*np.where(bad)))[:10]:
+            print(f"[parity] {name}: pixel ({a},{b}) |d| {d[a, b]:.2e} oracle u,v {ru[a, b]:.4f},{rv[a, b]:.4f}",
+                  flush=True)
+    assert int(bad.sum()) == 0, (name, float(d.max()), int(bad.sum()))
+    if mean_tol is not None:
+        assert d.mean() <= mean_tol, (name, float(d.mean()))
+    re = ref["energy"]
+    assert abs(res["energy"] - re) <= 1e-6 * abs(re) + 1e-6, (name, res["energy"], re)
+    assert abs(res["gap"] - ref["gap"]) <= 1e-5 * abs(re) + 1e-6, (name, res["gap"], ref["gap"])

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2011_10979_amd as fm  # noqa: E402
 import synth  # noqa: E402
-from helpers import to_dev, to_np, f32, oracle_with_sensitivity, assert_conditioned  # noqa: E402
+from helpers import to_dev, to_np, f32, oracle_refs, assert_parity  # noqa: E402
 
 KW = dict(levels=3, warps=2, iters=30)
 # (H, W, seed, levels): uneven sides, ragged tiles, a pair with fewer levels, a tiny one
@@ -66,11 +66,11 @@ def test_batched_pairs_match_the_oracle(ctx, scheme, relax, beta):
     for I0, I1, lv, _, _ in fr:
         jobs.append((I0, I1, dict(okw, levels=lv or KW["levels"])))
     with mp.get_context("fork").Pool(4) as pool:
-        fut = oracle_with_sensitivity(jobs, pool)
+        fut = oracle_refs(jobs, pool)
         out = batched(ctx, fr, **kw)
         refs = fut(900)
     for k, (u, v, res) in enumerate(out):
-        assert_conditioned(f"batched pair {k} {MIX[k][:2]}", to_np(u), to_np(v), res, refs[k][0], refs[k][1:])
+        assert_parity(f"batched pair {k} {MIX[k][:2]}", to_np(u), to_np(v), res, refs[k])
 
 
 def test_batched_equals_plain_tile_solves_bitwise(ctx):

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2011_10979_amd as fm  # noqa: E402
 import synth  # noqa: E402
-from helpers import to_dev, to_np, f32, oracle_with_sensitivity, assert_conditioned  # noqa: E402
+from helpers import to_dev, to_np, f32, oracle_refs, assert_parity  # noqa: E402
 
 KW = dict(levels=3, warps=2, iters=30)
 SPEC = [(70, 90, 41, 0), (45, 130, 42, 0), (33, 35, 43, 2), (96, 128, 44, 0), (20, 300, 45, 2), (60, 61, 46, 0)]
@@ -147,7 +147,7 @@ def test_served_flows_match_the_oracle(ctx, frames, scheme, relax, beta):
     kw = dict(KW, scheme=scheme, relax=relax, beta=beta)
     jobs = [(f[0], f[1], dict(kw, levels=f[2] or KW["levels"])) for f in frames[:3]]
     with mp.get_context("fork").Pool(3) as pool:
-        fut = oracle_with_sensitivity(jobs, pool)
+        fut = oracle_refs(jobs, pool)
         srv = fm.Server(ctx, fm.Params(**kw), budget_bytes=64 << 20, max_active=4)
         tick = {}
         for k in range(3):
@@ -158,7 +158,7 @@ def test_served_flows_match_the_oracle(ctx, frames, scheme, relax, beta):
         refs = fut(900)
     for k in range(3):
         u, v, res = out[k]
-        assert_conditioned(f"served pair {k}", to_np(u), to_np(v), res, refs[k][0], refs[k][1:])
+        assert_parity(f"served pair {k}", to_np(u), to_np(v), res, refs[k])
 
 
 def test_bad_requests_are_refused(ctx, frames):

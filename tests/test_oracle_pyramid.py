@@ -109,3 +109,57 @@ def test_upsample_inverts_downsample_geometry():
 def test_bilinear_used_by_warp_clamps():
     F = np.arange(6.0).reshape(2, 3)
     assert ops.bilinear(F, np.array([-1.0]), np.array([5.0]))[0] == F[0, 2]
+
+
+def _is_half(x):
+    return np.array_equal(np.asarray(x, np.float64).astype(np.float16).astype(np.float64), x)
+
+
+def test_f16_storage_form_planes_are_binary16_and_centred():
+    """The half-precision storage form: every stored plane holds binary16 values; the images are
+    the frames minus 1/2 to within half a binary16 spacing at the finest level, and each coarse
+    level is the binary16 value nearest the 2x2 mean of the stored level above it (checked against
+    the exact FP64 mean of those stored values: at most half a binary16 spacing away; the binary32
+    sum of four binary16 operands in [-1/2, 1/2] only rounds when it reaches 1 in magnitude with an
+    operand below 2^-13, which these inputs never combine)."""
+    rng = np.random.default_rng(11)
+    I0 = rng.uniform(0, 1, (23, 30)).astype(np.float32).astype(np.float64)
+    I1 = rng.uniform(0, 1, (23, 30)).astype(np.float32).astype(np.float64)
+    p16 = pyramid.build_pyramid(I0, I1, 4, storage="f16")
+    p32 = pyramid.build_pyramid(I0, I1, 4)
+    for lev, planes in enumerate(p16):
+        assert all(_is_half(x) for x in planes)
+        assert all(np.abs(x).max() <= 0.5 for x in planes[:2])
+    spacing = lambda x: np.spacing(np.abs(x).astype(np.float16)).astype(np.float64)  # noqa: E731
+    for k, I in ((0, I0), (1, I1)):
+        assert np.all(np.abs(p16[0][k] - (I - 0.5)) <= 0.5 * spacing(p16[0][k]))
+    for lev in range(1, 4):
+        for k in (0, 1):
+            exact = pyramid.downsample(p16[lev - 1][k])
+            assert np.all(np.abs(p16[lev][k] - exact) <= 0.5 * spacing(p16[lev][k]) + 1e-12)
+        dx, dy = pyramid.derivatives(p16[lev][1])
+        assert np.all(np.abs(p16[lev][2] - dx) <= 0.5 * spacing(p16[lev][2]) + 1e-12)
+        assert np.all(np.abs(p16[lev][3] - dy) <= 0.5 * spacing(p16[lev][3]) + 1e-12)
+    # the storage form stays close to the FP64 pyramid (a few binary16 spacings of 1/2)
+    for a, b in zip(p16, p32):
+        assert np.abs((a[0] + 0.5) - b[0]).max() < 4 * 2.0 ** -12
+        assert np.abs(a[2] - b[2]).max() < 4 * 2.0 ** -12
+
+
+def test_f16_storage_form_rejects_unknown_storage():
+    with pytest.raises(ValueError):
+        pyramid.build_pyramid(np.zeros((4, 4)), np.zeros((4, 4)), 1, storage="bf16")
+
+
+def test_f16_storage_form_recovers_the_translation():
+    """Solved on the 64 x 64 translation pair the storage form still recovers the motion, with
+    a mean flow within 1e-2 px of the FP32 form's."""
+    import synth
+    from oracle import Params, solve_pair
+    pair = synth.translation_pair(0)
+    I0 = pair.I0.astype(np.float32).astype(np.float64)
+    I1 = pair.I1.astype(np.float32).astype(np.float64)
+    r32 = solve_pair(I0, I1, Params(levels=1, warps=1, iters=200))
+    r16 = solve_pair(I0, I1, Params(levels=1, warps=1, iters=200, storage="f16"))
+    assert abs(r16["u"].mean() - r32["u"].mean()) < 1e-2 and abs(r16["v"].mean() - r32["v"].mean()) < 1e-2
+    assert abs(r16["u"].mean() - 0.3) < 0.03 and abs(r16["v"].mean() + 0.2) < 0.03

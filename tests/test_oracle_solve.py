@@ -63,3 +63,24 @@ def test_energy_and_gap_reported(translation):
 def test_zach_requires_beta_zero(translation):
     with pytest.raises(ValueError):
         solve_pair(*translation, Params(scheme="zach", beta=0.05, iters=1))
+
+
+def test_perturb_hook_is_inert_when_identity_and_small_for_fp32_rounding():
+    """The tests' probe hook: applied as the identity it changes nothing, bit for bit; rounding the
+    state to FP32 after every iteration moves the 64 x 64 translation solve by far less than the
+    FP32 parity bar of 1e-4 px (a well-conditioned case), yet does move it."""
+    import numpy as np
+    import synth
+    from oracle import Params, solve_pair
+    pair = synth.translation_pair(0)
+    I0 = pair.I0.astype(np.float32).astype(np.float64)
+    I1 = pair.I1.astype(np.float32).astype(np.float64)
+    for scheme in ("padmm", "pdr"):
+        p = Params(scheme=scheme, levels=2, warps=2, iters=30)
+        a = solve_pair(I0, I1, p)
+        b = solve_pair(I0, I1, p, perturb=lambda st: dict(st))
+        assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["v"], b["v"]) and a["energy"] == b["energy"]
+        r32 = lambda st: {k: np.asarray(x, np.float32).astype(np.float64) for k, x in st.items()}  # noqa: E731
+        c = solve_pair(I0, I1, p, perturb=r32)
+        d = max(np.abs(c["u"] - a["u"]).max(), np.abs(c["v"] - a["v"]).max())
+        assert 0 < d < 1e-5, (scheme, d)
