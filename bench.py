@@ -1,41 +1,48 @@
 #!/usr/bin/env python3
-"""Benchmark: Gpixel-iterations/s of the coarse-to-fine TV-L1 flow solve on one MI355X.
+"""Benchmark of the coarse-to-fine TV-L1 flow solvers on one MI355X.
 
-Workload (default): one synthetic 640x480 FP32 pair (rich texture, piecewise-constant motion),
-5-level pyramid (factor 1/2), 5 warps per level, 50 pADMM iterations per warp.  A step is one
-whole solve (pyramid, warps, iterations, energy / gap) with the frames already resident in HBM;
-the solve is replayed from a hipGraph.  value = pixel-iterations of a step / step time.
+Default workload (--mode batch): 64 synthetic pairs of uneven sizes (W ~ U[128, 1280], H ~ U[96, 720],
+seeds 1000 + k; even k piecewise-constant motion, odd k rotation + zoom with occlusions), pyramid
+depth by size, 5 warps x 50 pADMM iterations per level, FP32, solved together by the batched path
+(autotuned stage choices, graph replay).  A step is one batched solve of all 64 pairs with the frames
+already resident in HBM; value = pixel-iterations of all pairs and levels / step time.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel: the ADMM iteration kernel of the finest level (about three
-                quarters of all pixel-iterations; the autotuner picks one-pass or K-iteration tiles
-                per level).  Algorithmic bytes of one launch = 76 B per pixel (12 FP32 planes read,
-                7 written, once per launch whatever K it advances) x the level's pixels; launch
-                duration from HIP events on the solve stream around each warp's block of iteration
-                launches, averaged over instrumented solves; peak = 8 TB/s HBM.  traffic = HBM bytes
-                per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs (calibrated against a
-                plain copy), when they were taken on the current kernel source, else null.
-  cpu_baseline  the FP64 NumPy oracle on the same workload (solved twice, about 10-15 s), one core
-  per_level     Gpixel-iter/s of each level's iteration blocks
+  pairs_per_s, per_level     pairs per second; Gpixel-iter/s and launch time of each level's stage
+  plain_sequential           the same 64 pairs as 64 plain solves in turn (built-in plan; tiles at
+                             every level, with a bitwise comparison against the batched flows)
+  roofline                   the dominant kernel, the batched K-iteration tile kernel (every stage):
+                             algorithmic bytes of the pixel-iterations one launch advances (68 B per
+                             pixel-iteration, one pass per iteration) / average launch duration from
+                             HIP events on the solve stream, against 8 TB/s; beside it the one-pass
+                             figure (76 B per pixel per launch, a launch makes one pass for all K
+                             iterations) and, when a rocprofv3 counter record of the same kernel
+                             source and stage choices exists, the DRAM traffic per launch
+  serving                    a Poisson trace (200 pairs/s, 1000 requests after 100) through the
+                             continuous-batching engine with frames uploaded per request: pairs/s, p50 /
+                             p99 latency, and the capacity with 300 requests arriving at once
+  oracle_check               every batched flow against the FP64 oracle (max |du|, |dv|, pixels above
+                             1e-4 px, mean and p99.9 endpoint error)
+  cpu_baseline               the oracle on one core (the 8 smallest pairs in turn);
+  cpu_baseline_all_cores     the oracle on all 64 pairs, one process per pair on the host's cores
 
 Other modes:
-  --mode batch      64 synthetic pairs of uneven sizes (W ~ U[128, 1280], H ~ U[96, 720], seeds
-                    1000 + k, pyramid depth by size) solved together by the batched path (autotuned
-                    stages, graph replay); value = pixel-iterations of all pairs / step time; reported
-                    beside 64 sequential plain solves of the same pairs (pairs/s, both plain
-                    kernel plans) and a bitwise comparison of every pair with its plain tile solve
+  --mode single     one pair solved repeatedly: 640x480 (5 levels), or --pair hd for the 1920x1080
+                    precision-form workload (6 levels; --storage f16 for FP16-stored pyramids); per-level
+                    rates, roofline of the level-0 iteration kernel, oracle CPU baseline
   --mode serve      Poisson arrivals (mean 200 pairs/s, seed 7) of pairs drawn from a pool of 10
                     pre-generated pairs per size (320x240, 640x480, 1024x436, 1280x720, 1920x1080 with
                     probabilities 0.3, 0.3, 0.2, 0.1, 0.1), 2000 requests after 200 warm-up ones, served
-                    by the continuous-batching engine (8 GiB budget); value = completed pairs/s, with
-                    p50 / p99 latency; the same trace through a one-at-a-time plain-solve server beside it
+                    by the continuous-batching engine (8 GiB budget), frames uploaded per request (unless
+                    --no-ingest); value = completed pairs/s, with p50 / p99 latency; the same trace
+                    through a one-at-a-time plain-solve server beside it
   --mode batch --batch-only [--no-autotune]   the batched solve alone (for profiler runs)
   --mode compare    every scheme of Sec. 4 (pADMM, rpADMMI, rpADMMII, Zach-pADMM, pDR, ALG1) on the
                     same synthetic pair (--pair vga or hd): time per solve, endpoint / angular error
                     against the ground-truth motion, energy and gap at equal iteration counts
-  --save-tuning F / --load-tuning F   write the autotuned per-level kernel choices to F, or apply
-                                      them from F instead of tuning (for profiler runs)
-  --choice KEY=MODE,K,ROWS            then pin one level shape's choice (counters of another choice)
+  --save-tuning F / --load-tuning F   single mode: write the autotuned per-level kernel choices to F,
+                                      or apply them from F instead of tuning (for profiler runs)
+  --choice KEY=MODE,K,ROWS            single mode: then pin one level shape's choice
   --calibrate-copy MB                 time a plain device-to-device copy of MB MiB (the reference
                                       kernel for the HBM counter calibration) and exit
 """
@@ -53,11 +60,18 @@ HBM_PEAK_GBS = 8000.0
 # FP32 planes read + written per pixel by one launch of an iteration kernel (increment form):
 # reads du, dv, s, q1x, q1y, q2x, q2y, I_x, I_y, I_t, u0, v0 (+ w, px, py); writes the 7 (10) state planes
 BYTES_PER_PX_LAUNCH = {False: 4 * (12 + 7), True: 4 * (15 + 10)}
+# Algorithmic HBM bytes of one ADMM-family iteration per pixel in its plain form (one pass per
+# iteration, FP32): read 7 state planes (u, v, s, q1x, q1y, q2x, q2y) and I_x, I_y, I_t, write the 7
+# state planes; with the illumination field 3 more state planes (w, p_x, p_y) each way.
+BYTES_PER_PX_ITER = {False: 4 * (10 + 7), True: 4 * (13 + 10)}
 
 
 # pDR / ALG1 tile kernels, per launch: reads X, X bar, y, I_x, I_y, I_t, u0, v0; writes X, X bar, y, Theta
 # (for ALG1 this is also one iteration done in one pass)
 PDR_TB_BYTES_PER_PX_LAUNCH = {False: 4 * ((2 + 2 + 4 + 5) + (2 + 2 + 4 + 1)), True: 4 * ((3 + 3 + 6 + 5) + (3 + 3 + 6 + 1))}
+# pDR / ALG1 per pixel-iteration in one fused pass (plain form): read X, X bar, y and I_x, I_y, I_t,
+# write X, X bar, y
+PDR_TB_BYTES_PER_PX_ITER = {False: 4 * ((2 + 2 + 4 + 3) + (2 + 2 + 4)), True: 4 * ((3 + 3 + 6 + 3) + (3 + 3 + 6))}
 
 
 def pdr_bytes_per_px_iter(has_w, sweeps):
@@ -140,19 +154,31 @@ def cpu_baseline(pair, args):
                       f"warps x {iters} iterations ({pxi / 1e6:.1f} M px-iter, {dt:.1f} s, FP64 NumPy, 1 thread)"}
 
 
-def roofline(ms, launches, iters, px, has_w, kernel, traffic, reps, per_px=None, unit="launch"):
-    """HBM roofline of an iteration kernel from event-timed blocks of its launches: algorithmic
-    bytes per launch (BYTES_PER_PX_LAUNCH x pixels) / average launch duration, against 8 TB/s."""
-    per_px = per_px or BYTES_PER_PX_LAUNCH[has_w]
+def roofline(ms, launches, iters, px, has_w, kernel, traffic, reps, per_iter=None, per_launch=None):
+    """HBM roofline of an iteration kernel from event-timed blocks of its launches.  achieved =
+    algorithmic bytes of the pixel-iterations one launch advances (`per_iter` B per pixel-iteration,
+    one pass per iteration) / average launch duration, against 8 TB/s; a launch of K iterations makes
+    one pass for all K, so this can exceed the peak.  Beside it the one-pass figure (`per_launch` B
+    per pixel per launch) and, with `traffic` (measured DRAM bytes per launch), the DRAM rate."""
+    per_iter = per_iter or BYTES_PER_PX_ITER[has_w]
+    per_launch = per_launch or BYTES_PER_PX_LAUNCH[has_w]
     launch_s = ms * 1e-3 / max(1, launches)
-    bytes_launch = per_px * px
-    achieved = bytes_launch / launch_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-            "per_unit": f"{per_px} B per pixel per {unit}", "bytes_per_launch": bytes_launch,
-            "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step_level0": launches // reps,
-            # the same pixel-iterations priced at one HBM pass per iteration
-            "one_pass_equivalent_GBs": round(per_px * px * iters / (ms * 1e-3) / 1e9, 1)}
+    pxi_launch = px * iters / max(1, launches)
+    achieved = per_iter * pxi_launch / launch_s / 1e9
+    one_pass = per_launch * px / launch_s / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "traffic_source": ("looked up: profiles/traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE runs on this kernel "
+                            "source and choice, copy-calibrated)") if traffic else None,
+         "kernel": kernel, "per_unit": f"{per_iter} B per pixel-iteration", "px_iter_per_launch": round(pxi_launch),
+         "bytes_per_launch": round(per_iter * pxi_launch), "avg_launch_us": round(launch_s * 1e6, 3),
+         "launches_per_step_level0": launches // reps,
+         "one_pass_per_launch": {"per_unit": f"{per_launch} B per pixel per launch", "GBs": round(one_pass, 1),
+                                 "frac": round(one_pass / HBM_PEAK_GBS, 4)}}
+    if traffic:
+        r["dram_GBs"] = round(traffic / launch_s / 1e9, 1)
+        r["dram_frac"] = round(r["dram_GBs"] / HBM_PEAK_GBS, 4)
+    return r
 
 
 def _gen_batch_pair(k):
@@ -169,8 +195,81 @@ def _oracle_pair(job):
     return r["u"], r["v"], time.perf_counter() - t0
 
 
+def _oracle_check(job):
+    """Worker: the FP64 oracle on one pair, compared with the GPU flow (u, v) of the same pair.
+    Returns the parity figures and the oracle's solve time."""
+    import numpy as np
+    from oracle import Params, solve_pair
+    I0, I1, u, v, kw = job
+    t0 = time.perf_counter()
+    r = solve_pair(I0.astype("float64"), I1.astype("float64"), Params(**kw))
+    dt = time.perf_counter() - t0
+    du = np.abs(u.astype("float64") - r["u"])
+    dv = np.abs(v.astype("float64") - r["v"])
+    d = np.maximum(du, dv)
+    epe = np.hypot(du, dv)
+    return {"max_abs_px": float(d.max()), "over_1e-4": int((d > 1e-4).sum()), "mean_epe_px": float(epe.mean()),
+            "p999_epe_px": float(np.quantile(epe, 0.999)), "oracle_s": dt}
+
+
+class ProfRegion:
+    """roctx profiler resume / pause around the launches whose HIP-event times give the roofline, so
+    that `rocprofv3 --selected-regions` traces exactly those launches (no-op without the library)."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        try:
+            lib = ctypes.CDLL("librocprofiler-sdk-roctx.so.1")
+        except OSError:
+            try:
+                lib = ctypes.CDLL(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib",
+                                               "librocprofiler-sdk-roctx.so.1"))
+            except OSError:
+                return
+        lib.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+        lib.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+        self.lib = lib
+
+    def __enter__(self):
+        if self.lib:
+            self.lib.roctxProfilerResume(0)
+        return self
+
+    def __exit__(self, *exc):
+        if self.lib:
+            self.lib.roctxProfilerPause(0)
+        return False
+
+
+def batch_traffic(signature):
+    """DRAM bytes per launch of the batched tile kernel, averaged over one batched solve's launches,
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record, when it was taken on the current
+    kernel and planner source with the same stage choices as this run (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        e = json.load(open(path)).get("batch64")
+    except (OSError, ValueError):
+        return None
+    if not e or e.get("kernel_sha") != kernel_sha():
+        return None
+    for m in e.get("entries", []):
+        if m.get("stages") == signature:
+            return m.get("bytes_per_launch")
+    return None
+
+
+def pair_px(H, W, levels):
+    tot = 0
+    for _ in range(levels):
+        tot += H * W
+        H, W = (H + 1) // 2, (W + 1) // 2
+    return tot
+
+
 def run_batch(args):
-    """The batched configuration: 64 uneven pairs in one batched solve vs 64 plain solves."""
+    """The headline configuration: 64 uneven pairs solved together by the batched path, beside 64
+    sequential plain solves, a short served trace and the FP64 oracle on every pair."""
     import multiprocessing as mp
     import numpy as np
     import torch
@@ -187,26 +286,26 @@ def run_batch(args):
                synth.levels_by_size(*a.shape)) for a, b in host]
     shapes = [a.shape for a, _ in host]
     params = fm.Params(scheme=args.scheme, storage=args.storage, warps=args.warps, iters=args.iters, use_graph=1)
-    px_all = 0
-    for (H, W), (_, _, lv) in zip(shapes, frames):
-        h, w = H, W
-        for _ in range(lv):
-            px_all += h * w
-            h, w = (h + 1) // 2, (w + 1) // 2
-    px_iter = px_all * args.warps * args.iters
+    pxi_pair = [pair_px(H, W, lv) * args.warps * args.iters for (H, W), (_, _, lv) in zip(shapes, frames)]
+    px_iter = sum(pxi_pair)
     ctx = fm.Context(0)
+    tuning = None
     if not args.no_autotune:
         t0 = time.perf_counter()
-        ctx.autotune_batched(frames, params)
-        print(f"[bench] batched autotune {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        tuning = ctx.autotune_batched(frames, params).get("stages")
+        print(f"[bench] batched autotune {time.perf_counter() - t0:.1f} s: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         out = ctx.solve_batched(frames, params)
     torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    start.record()
     for _ in range(args.steps):
         out = ctx.solve_batched(frames, params)
+    end.record()
     torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    wall = time.perf_counter() - t0
+    ms_step = max(start.elapsed_time(end), wall * 1e3) / args.steps
     value = px_iter / (ms_step * 1e-3) / 1e9
     print(f"[bench] batched: {ms_step:.2f} ms per batch, {value:.2f} Gpx-iter/s", file=sys.stderr, flush=True)
     if args.batch_only:                      # the batched solve alone (for profiler runs)
@@ -216,7 +315,8 @@ def run_batch(args):
         ctx.close()
         return
 
-    # per-stage timing (direct launches, events around each stage's iterations)
+    # per-stage timing: direct launches, HIP events on the solve stream around each stage's tile
+    # launches (the region a rocprofv3 --selected-regions trace covers)
     ctx.set_stats(True)
     p_inst = fm.Params(**{**params.__dict__, "use_graph": 0})
     reps = 2
@@ -224,19 +324,47 @@ def run_batch(args):
     ms = [0.0] * nl
     launches = [0] * nl
     iters = [0] * nl
-    for _ in range(reps):
-        ctx.solve_batched(frames, p_inst)
-        s = ctx.stats()
-        for l in range(nl):
-            ms[l] += s["iter_ms"][l]
-            launches[l] += s["launches"][l]
-            iters[l] += s["iterations"][l]
-        level_px = s["level_px"]
+    with ProfRegion():
+        for _ in range(reps):
+            ctx.solve_batched(frames, p_inst)
+            s = ctx.stats()
+            for l in range(nl):
+                ms[l] += s["iter_ms"][l]
+                launches[l] += s["launches"][l]
+                iters[l] += s["iterations"][l]
+    level_px = s["level_px"]
     ctx.set_stats(False)
-    per_level = [{"level": l, "pixels": level_px[l], "Gpx_iter_s": level_px[l] * iters[l] / (ms[l] * 1e-3) / 1e9,
-                  "us_per_launch": 1e3 * ms[l] / max(1, launches[l])} for l in range(nl)]
-    roof = roofline(ms[0], launches[0], iters[0], level_px[0], params.beta > 0,
-                    f"batched tile kernel, level-0 stage ({level_px[0]} px over {n} pairs)", None, reps)
+    per_level = [{"level": l, "pixels": level_px[l], "Gpx_iter_s": round(level_px[l] * iters[l] / (ms[l] * 1e-3) / 1e9, 2),
+                  "us_per_launch": round(1e3 * ms[l] / max(1, launches[l]), 2), "launches_per_step": launches[l] // reps}
+                 for l in range(nl)]
+    has_w = params.beta > 0
+    tile_ms = sum(ms)
+    tile_launches = sum(launches)
+    tile_pxi = sum(level_px[l] * iters[l] for l in range(nl))           # over `reps` solves
+    tile_px_launch = sum(level_px[l] * launches[l] for l in range(nl))
+    launch_s = tile_ms * 1e-3 / tile_launches
+    alg_launch = BYTES_PER_PX_ITER[has_w] * tile_pxi / tile_launches     # algorithmic bytes per launch
+    achieved = alg_launch / launch_s / 1e9
+    signature = [[st["level"], st["order"], st["K"], st["ew"]] for st in tuning] if tuning else "built-in"
+    traffic = batch_traffic(signature)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_source": ("looked up: profiles/traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE runs on this "
+                               "kernel source and stage choice, copy-calibrated)") if traffic else None,
+            "kernel": "admm_tb_table_kernel<false, 1024, 2> (batched K-iteration tile kernel, every stage)",
+            "per_unit": f"{BYTES_PER_PX_ITER[has_w]} B per pixel-iteration",
+            "px_iter_per_launch": round(tile_pxi / tile_launches), "bytes_per_launch": round(alg_launch),
+            "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step": tile_launches // reps,
+            "note": "K iterations per launch share one pass over HBM, so the algorithmic rate can exceed the "
+                    "HBM peak; dram_* figures are the measured traffic",
+            "one_pass_per_launch": {"per_unit": f"{BYTES_PER_PX_LAUNCH[has_w]} B per pixel per launch",
+                                    "GBs": round(BYTES_PER_PX_LAUNCH[has_w] * tile_px_launch / tile_launches
+                                                 / launch_s / 1e9, 1)}}
+    roof["one_pass_per_launch"]["frac"] = round(roof["one_pass_per_launch"]["GBs"] / HBM_PEAK_GBS, 4)
+    if traffic:
+        roof["dram_GBs"] = round(traffic / launch_s / 1e9, 1)
+        roof["dram_frac"] = round(roof["dram_GBs"] / HBM_PEAK_GBS, 4)
+    print(f"[bench] roofline {roof}", file=sys.stderr, flush=True)
 
     # 64 sequential plain solves of the same pairs: built-in kernel plan, then tiles at every level
     plain = {}
@@ -258,49 +386,70 @@ def run_batch(args):
     fm.set_tuning("tb_mode", 0)
     print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
 
-    # oracle on the smallest pairs: EPE of the batched flow against the FP64 oracle, and the
-    # oracle's own rate on all host cores
-    order = sorted(range(n), key=lambda k: shapes[k][0] * shapes[k][1])[:args.oracle_pairs]
-    jobs = [(host[k][0], host[k][1], dict(scheme=args.scheme, levels=frames[k][2], warps=args.warps,
-                                           iters=args.iters)) for k in order]
-    cpu = None
-    epe = None
-    if jobs and not args.no_cpu_baseline:
+    serving = None
+    if not args.no_serve:
+        serving = serve_leg(args, ctx, ingest=True, with_plain=False, n_meas=args.batch_serve_requests,
+                            n_warm=100, capacity=300)
+        serving.pop("_pool")
+        print(f"[bench] serving: {serving}", file=sys.stderr, flush=True)
+    ctx.close()
+
+    # the FP64 oracle on every pair of the batch (one process per pair on all host cores): parity
+    # of every batched flow, and the oracle's own rate on all cores; then on one core
+    check = cpu_all = cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
         os.environ.setdefault("OMP_NUM_THREADS", "1")
+        order = sorted(range(n), key=lambda k: -pxi_pair[k])           # largest first: shorter tail
+        jobs = [(host[k][0], host[k][1], out[k][0].cpu().numpy(), out[k][1].cpu().numpy(),
+                 dict(scheme=args.scheme, levels=frames[k][2], warps=args.warps, iters=args.iters)) for k in order]
+        print(f"[bench] oracle on all {n} pairs, {workers} processes ...", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-            refs = pool.map(_oracle_pair, jobs)
-        dt = time.perf_counter() - t0
-        epes = []
-        for k, (ru, rv, _) in zip(order, refs):
-            u, v = out[k][0].cpu().numpy(), out[k][1].cpu().numpy()
-            epes.append(float(np.sqrt((u - ru) ** 2 + (v - rv) ** 2).mean()))
-        epe = {"pairs": [list(shapes[k]) for k in order], "mean_epe_vs_oracle": epes, "max": max(epes)}
-        pxi = 0
-        for k in order:
-            h, w = shapes[k]
-            for _ in range(frames[k][2]):
-                pxi += h * w * args.warps * args.iters
-                h, w = (h + 1) // 2, (w + 1) // 2
-        cpu = {"value": round(len(jobs) / dt, 3), "unit": "pairs/s", "cores": min(workers, len(jobs)),
-               "kind": "oracle", "Gpx_iter_s": pxi / dt / 1e9, "host": host_cpu(),
-               "sample": f"the {len(jobs)} smallest pairs of the batch, one process per pair "
-                         f"({pxi / 1e6:.0f} M px-iter, {dt:.1f} s, FP64 NumPy)"}
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_check, jobs, chunksize=1)
+        dt_all = time.perf_counter() - t0
+        worst = max(range(n), key=lambda i: res[i]["max_abs_px"])
+        check = {"pairs": n, "max_abs_px": max(r["max_abs_px"] for r in res),
+                 "worst_pair": [int(order[worst])] + list(shapes[order[worst]]),
+                 "pixels_over_1e-4": sum(r["over_1e-4"] for r in res),
+                 "max_mean_epe_px": max(r["mean_epe_px"] for r in res),
+                 "max_p999_epe_px": max(r["p999_epe_px"] for r in res)}
+        check["fp32_bar_1e-4_met"] = check["pixels_over_1e-4"] == 0
+        check["epe_bar_1e-2_met"] = check["max_mean_epe_px"] <= 1e-2
+        cpu_all = {"value": round(px_iter / dt_all / 1e9, 4), "unit": "Gpixel-iter/s", "cores": workers,
+                   "kind": "oracle", "pairs_per_s": round(n / dt_all, 3), "host": host_cpu(),
+                   "sample": f"all {n} pairs of the batch, one process per pair ({px_iter / 1e9:.2f} G px-iter, "
+                             f"{dt_all:.1f} s wall, FP64 NumPy, one BLAS thread each)"}
+        small = sorted(range(n), key=lambda k: pxi_pair[k])[:args.cpu_pairs]
+        pxi = sum(pxi_pair[k] for k in small)
+        print(f"[bench] oracle on {len(small)} pairs, one core ...", file=sys.stderr, flush=True)
+        with threadpool_limits(limits=1):
+            from oracle import Params, solve_pair
+            t0 = time.perf_counter()
+            for k in small:
+                solve_pair(host[k][0].astype("float64"), host[k][1].astype("float64"),
+                           Params(scheme=args.scheme, levels=frames[k][2], warps=args.warps, iters=args.iters))
+            dt = time.perf_counter() - t0
+        cpu = {"value": round(pxi / dt / 1e9, 4), "unit": "Gpixel-iter/s", "cores": 1, "kind": "oracle",
+               "pairs_per_s": round(len(small) / dt, 3), "host": host_cpu(),
+               "sample": f"the {len(small)} smallest pairs of the batch in turn ({pxi / 1e6:.0f} M px-iter, "
+                         f"{dt:.1f} s, FP64 NumPy, 1 thread)"}
     line = {
-        "metric": "Gpixel-iter/s (batched coarse-to-fine TV-L1 flow solves, pixel-iterations over all pairs "
-                  "and levels); pairs/s",
-        "value": round(value, 3), "unit": "Gpixel-iter/s", "pairs_per_s": round(n / (ms_step * 1e-3), 2),
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{n} pairs of uneven sizes (128x96 .. 1280x720, seeds 1000+k), pyramid depth "
-                               f"by size x {args.warps} warps x {args.iters} iterations, {args.scheme}, batched",
-                   "pairs": n, "px_iter_per_step": px_iter, "graph": True, "autotuned": not args.no_autotune},
+        "metric": "Gpixel-iter/s per level; pairs/s + p50/p99 latency at EPE<=0.01px vs oracle",
+        "value": round(value, 3), "unit": "Gpixel-iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n} synthetic pairs of uneven sizes (128x96 .. 1280x720, seeds 1000+k), pyramid "
+                               f"depth by size x {args.warps} warps x {args.iters} iterations, {args.scheme}, "
+                               f"solved together by the batched path",
+                   "pairs": n, "px_iter_per_step": px_iter, "graph": True, "stage_choices": tuning or "built-in"},
+        "pairs_per_s": round(n / (ms_step * 1e-3), 2),
         "plain_sequential": plain,
         "speedup_vs_best_plain": round(min(p_["ms"] for p_ in plain.values()) / ms_step, 3),
-        "per_level": per_level, "roofline": roof, "oracle_check": epe, "cpu_baseline": cpu,
+        "per_level": per_level, "roofline": roof, "serving": serving, "oracle_check": check,
+        "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all,
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 def _gen_serving_pair(job):
@@ -318,9 +467,11 @@ def _percentiles(lat):
             "mean_ms": round(float(a.mean()), 3), "max_ms": round(float(a.max()), 3)}
 
 
-def run_serve(args):
-    """The serving configuration: a Poisson request trace through the continuous-batching engine and
-    through a one-at-a-time plain-solve server."""
+def serve_leg(args, ctx, ingest=True, with_plain=True, n_meas=None, n_warm=None, capacity=None):
+    """A Poisson request trace through the continuous-batching engine (and, with `with_plain`,
+    through a one-at-a-time plain-solve server).  With `ingest` each request's frames start in
+    pinned host memory and are uploaded on the serving stream when the request arrives, inside its
+    latency window; otherwise they are already on the device."""
     import multiprocessing as mp
     import numpy as np
     import torch
@@ -333,26 +484,33 @@ def run_serve(args):
         host = pool.map(_gen_serving_pair, [(si, j) for si in range(len(synth.SERVING_SIZES)) for j in range(per)])
     print(f"[bench] generated {len(host)} pool pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
+    pool_host = [[None] * per for _ in synth.SERVING_SIZES]
     pool_dev = [[None] * per for _ in synth.SERVING_SIZES]
     for si in range(len(synth.SERVING_SIZES)):
         for j in range(per):
             a, b = host[si * per + j]
-            pool_dev[si][j] = (torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+            pool_host[si][j] = (torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory())
+            if not ingest or with_plain:
+                pool_dev[si][j] = (torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
     levels = [synth.levels_by_size(H, W) for H, W in synth.SERVING_SIZES]
-    n_warm, n_meas = args.serve_warmup, args.requests
+    n_warm = args.serve_warmup if n_warm is None else n_warm
+    n_meas = args.requests if n_meas is None else n_meas
     t_arr, size_idx = synth.serving_trace(n_warm + n_meas, args.rate, seed=7)
     pick = np.random.default_rng(8).integers(0, per, size=n_warm + n_meas)
     params = fm.Params(scheme=args.scheme, storage=args.storage, warps=args.warps, iters=args.iters)
-    px_iter = []
-    for si in size_idx:
-        H, W = synth.SERVING_SIZES[si]
-        tot = 0
-        for _ in range(levels[si]):
-            tot += H * W
-            H, W = (H + 1) // 2, (W + 1) // 2
-        px_iter.append(tot * args.warps * args.iters)
-    ctx = fm.Context(0)
+    px_iter = [pair_px(*synth.SERVING_SIZES[si], levels[si]) * args.warps * args.iters for si in size_idx]
     torch.cuda.synchronize()
+
+    def frames_of(i):
+        si, j = size_idx[i], pick[i]
+        if not ingest:
+            return pool_dev[si][j]
+        h0, h1 = pool_host[si][j]
+        d0 = torch.empty(h0.shape, dtype=torch.float32, device=dev)
+        d1 = torch.empty(h1.shape, dtype=torch.float32, device=dev)
+        d0.copy_(h0, non_blocking=True)        # stream-ordered before the engine's import of the pair
+        d1.copy_(h1, non_blocking=True)
+        return d0, d1
 
     def replay(label, submit, advance, poll, t_arr=t_arr, n_warm=n_warm, n_meas=n_meas):
         lat = [None] * len(t_arr)
@@ -398,7 +556,7 @@ def run_serve(args):
     srv = fm.Server(ctx, params, budget_bytes=args.budget_gib << 30, max_active=args.max_active)
 
     def s_submit(i):
-        I0, I1 = pool_dev[size_idx[i]][pick[i]]
+        I0, I1 = frames_of(i)
         return srv.submit(I0, I1, levels[size_idx[i]])
 
     def s_poll(t):
@@ -408,77 +566,85 @@ def run_serve(args):
     sst = srv.stats()
     served["engine"] = {k: sst[k] for k in ("epochs", "peak_active", "peak_bytes_in_use", "arena_bytes")}
     # capacity: the first `capacity` requests of the trace all arriving at once
-    n_cap = min(args.capacity, len(t_arr))
+    n_cap = min(args.capacity if capacity is None else capacity, len(t_arr))
     cap_arr = np.zeros(n_cap)
     cap_served = replay("engine capacity", s_submit, srv.step, s_poll, cap_arr, 0, n_cap) if n_cap else None
     srv.close()
-    print(f"[bench] engine: {served}", file=sys.stderr, flush=True)
+    result = {"workload": f"Poisson arrivals {args.rate}/s, {n_meas} requests after {n_warm}, sizes "
+                          f"320x240/640x480/1024x436/1280x720/1920x1080 (p .3/.3/.2/.1/.1), pool of {per} pairs per "
+                          f"size, pyramid depth by size x {args.warps} warps x {args.iters} iterations, {args.scheme}",
+              "frames": "uploaded from pinned host memory inside each request's latency" if ingest
+                        else "resident on the device before the trace",
+              "budget_GiB": args.budget_gib, "max_active": args.max_active,
+              "engine": served, "engine_capacity": {"requests": n_cap, "arriving": "all at once",
+                                                    **(cap_served or {})}}
+    if with_plain:
+        # one at a time: a FIFO of plain solves (graph replay per size, tiles at every level)
+        fm.set_tuning("tb_mode", 4)
+        gp = fm.Params(**{**params.__dict__, "use_graph": 1})
+        for si in range(len(synth.SERVING_SIZES)):                     # capture each size's graph
+            ctx.solve(*pool_dev[si][0], fm.Params(**{**gp.__dict__, "levels": levels[si]}))
+        queue = []
+        finished = set()
+        tick = [0]
 
-    # one at a time: a FIFO of plain solves (graph replay per size, tiles at every level)
-    fm.set_tuning("tb_mode", 4)
-    gp = fm.Params(**{**params.__dict__, "use_graph": 1})
-    for si in range(len(synth.SERVING_SIZES)):                     # capture each size's graph
-        ctx.solve(*pool_dev[si][0], fm.Params(**{**gp.__dict__, "levels": levels[si]}))
-    queue = []
-    finished = set()
-    tick = [0]
+        def p_submit(i):
+            tick[0] += 1
+            queue.append((tick[0], frames_of(i), i))
+            return tick[0]
 
-    def p_submit(i):
-        tick[0] += 1
-        queue.append((tick[0], i))
-        return tick[0]
+        def p_advance():
+            if queue:
+                t, (I0, I1), i = queue.pop(0)
+                ctx.solve(I0, I1, fm.Params(**{**gp.__dict__, "levels": levels[size_idx[i]]}))
+                finished.add(t)
 
-    def p_advance():
-        if queue:
-            t, i = queue.pop(0)
-            I0, I1 = pool_dev[size_idx[i]][pick[i]]
-            ctx.solve(I0, I1, fm.Params(**{**gp.__dict__, "levels": levels[size_idx[i]]}))
-            finished.add(t)
+        result["plain_one_at_a_time"] = replay("plain", p_submit, p_advance, lambda t: t in finished)
+        result["plain_capacity"] = replay("plain capacity", p_submit, p_advance, lambda t: t in finished, cap_arr,
+                                          0, n_cap) if n_cap else None
+        fm.set_tuning("tb_mode", 0)
+    result["_pool"] = (host, pool_dev, levels)
+    return result
 
-    plain = replay("plain", p_submit, p_advance, lambda t: t in finished)
-    cap_plain = replay("plain capacity", p_submit, p_advance, lambda t: t in finished, cap_arr, 0, n_cap) \
-        if n_cap else None
-    fm.set_tuning("tb_mode", 0)
-    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
 
-    # accuracy: served flows of the smallest size against the FP64 oracle
+def run_serve(args):
+    """The serving configuration: a Poisson request trace through the continuous-batching engine and
+    through a one-at-a-time plain-solve server, with a check of served flows against the oracle."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    import paper_2011_10979_amd as fm
+    ctx = fm.Context(0)
+    res = serve_leg(args, ctx, ingest=not args.no_ingest, with_plain=True)
+    host, pool_dev, levels = res.pop("_pool")
+    per = args.pool
     check = None
     if not args.no_cpu_baseline:
-        jobs = []
+        # served flows of the smallest size's pool pairs against the FP64 oracle
         seen = list(range(min(per, args.oracle_pairs)))
-        for j in seen:
-            a, b = host[j]
-            jobs.append((a, b, dict(scheme=args.scheme, levels=levels[0], warps=args.warps, iters=args.iters)))
-        # served results of those pool pairs: any request that used them (results are the same per pair)
+        dev = torch.device("cuda:0")
+        params = fm.Params(scheme=args.scheme, storage=args.storage, warps=args.warps, iters=args.iters)
         srv = fm.Server(ctx, params, budget_bytes=1 << 30, max_active=8)
-        tk = {j: srv.submit(*pool_dev[0][j], levels[0]) for j in seen}
+        tk = {j: srv.submit(torch.from_numpy(host[j][0]).to(dev), torch.from_numpy(host[j][1]).to(dev), levels[0])
+              for j in seen}
         srv.drain()
         got = {j: srv.poll(t) for j, t in tk.items()}
         srv.close()
+        jobs = [(host[j][0], host[j][1], got[j][0].cpu().numpy(), got[j][1].cpu().numpy(),
+                 dict(scheme=args.scheme, levels=levels[0], warps=args.warps, iters=args.iters)) for j in seen]
         os.environ.setdefault("OMP_NUM_THREADS", "1")
-        t0 = time.perf_counter()
-        with mp.get_context("fork").Pool(min(workers, max(1, len(jobs)))) as pool:
-            refs = pool.map(_oracle_pair, jobs)
-        dt = time.perf_counter() - t0
-        epes = []
-        for j, (ru, rv, _) in zip(seen, refs):
-            u, v = got[j][0].cpu().numpy(), got[j][1].cpu().numpy()
-            epes.append(float(np.sqrt((u - ru) ** 2 + (v - rv) ** 2).mean()))
-        check = {"size": "320x240", "pairs": len(jobs), "mean_epe_vs_oracle": epes, "max": max(epes),
-                 "oracle_pairs_per_s": round(len(jobs) / dt, 3), "oracle_cores": min(workers, len(jobs))}
+        with mp.get_context("fork").Pool(min(16, max(1, len(jobs)))) as pool:
+            rs = pool.map(_oracle_check, jobs)
+        check = {"size": "320x240", "pairs": len(jobs), "max_abs_px": max(r["max_abs_px"] for r in rs),
+                 "pixels_over_1e-4": sum(r["over_1e-4"] for r in rs),
+                 "max_mean_epe_px": max(r["mean_epe_px"] for r in rs)}
     line = {
         "metric": "pairs/s with p50 / p99 latency (served coarse-to-fine TV-L1 flow solves, Poisson arrivals)",
-        "value": served["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True,
+        "value": res["engine"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"Poisson arrivals {args.rate}/s, {n_meas} requests after {n_warm}, sizes "
-                               f"320x240/640x480/1024x436/1280x720/1920x1080 (p .3/.3/.2/.1/.1), pool of {per} "
-                               f"pairs per size, pyramid depth by size x {args.warps} warps x {args.iters} "
-                               f"iterations, {args.scheme}",
-                   "budget_GiB": args.budget_gib, "max_active": args.max_active},
-        "served": served, "plain_one_at_a_time": plain,
-        "capacity": {"requests": n_cap, "note": "the first requests of the trace, all arriving at once",
-                     "engine": cap_served, "plain_one_at_a_time": cap_plain},
-        "oracle_check": check,
+        "config": {"workload": res.pop("workload"), "budget_GiB": args.budget_gib, "max_active": args.max_active,
+                   "frames": res.pop("frames")},
+        **res, "oracle_check": check,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -591,7 +757,7 @@ def main():
     ap.add_argument("--choice", action="append", default=[], metavar="KEY=MODE,K,ROWS",
                     help="after tuning, pin one level shape's kernel choice, e.g. 480x640i50=4,9,48")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "compare"])
+    ap.add_argument("--mode", default="batch", choices=["single", "batch", "serve", "compare"])
     ap.add_argument("--pair", default="vga", choices=["vga", "hd"])
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--requests", type=int, default=2000)
@@ -602,6 +768,12 @@ def main():
     ap.add_argument("--capacity", type=int, default=600, help="requests of the saturation run (0: none)")
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--oracle-pairs", type=int, default=4)
+    ap.add_argument("--cpu-pairs", type=int, default=8, help="batch mode: pairs of the one-core oracle sample")
+    ap.add_argument("--no-serve", action="store_true", help="batch mode: skip the served-trace leg")
+    ap.add_argument("--batch-serve-requests", type=int, default=1000,
+                    help="batch mode: requests of the served-trace leg (after 100 warm-up ones)")
+    ap.add_argument("--no-ingest", action="store_true",
+                    help="serve mode: frames resident on the device before the trace (no upload per request)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -609,9 +781,6 @@ def main():
               "communication, and no multi-GPU figure is produced.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    import synth
     import paper_2011_10979_amd as fm
 
     for kv in args.tune:
@@ -629,7 +798,15 @@ def main():
     if args.mode == "compare":
         run_compare(args)
         return
+    run_single(args)
 
+
+def run_single(args):
+    """One pair (640x480, or the 1920x1080 pair with --pair hd) solved repeatedly."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2011_10979_amd as fm
     dev = torch.device("cuda:0")
     if args.pair == "hd":
         # the 1920x1080 plain-vs-precision-form workload: rotation plus zoom with occlusions, 6 levels
@@ -732,16 +909,14 @@ def main():
             name = "ALG1" if args.scheme == "alg1" else "pDR"
             roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
                             f"{name} tile kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
-                            None, reps, per_px=PDR_TB_BYTES_PER_PX_LAUNCH[has_w])
-            one_iter = (PDR_TB_BYTES_PER_PX_LAUNCH[has_w] if args.scheme == "alg1"
-                        else pdr_bytes_per_px_iter(has_w, params.gs_sweeps))
-            roof["one_pass_equivalent_GBs"] = round(one_iter * shapes[0][0] * shapes[0][1] * lvl_iters[0]
-                                                    / (lvl_ms[0] * 1e-3) / 1e9, 1)
+                            None, reps, per_iter=PDR_TB_BYTES_PER_PX_ITER[has_w],
+                            per_launch=PDR_TB_BYTES_PER_PX_LAUNCH[has_w])
         else:
             # three-pass pDR: the unit is one iteration (2n + 1 passes over the level)
             roof = roofline(lvl_ms[0], lvl_iters[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
                             f"pDR iteration, level 0 ({shapes[0][1]}x{shapes[0][0]}): {2 * params.gs_sweeps + 1} passes",
-                            None, reps, per_px=pdr_bytes_per_px_iter(has_w, params.gs_sweeps), unit="iteration")
+                            None, reps, per_iter=PDR_TB_BYTES_PER_PX_ITER[has_w],
+                            per_launch=pdr_bytes_per_px_iter(has_w, params.gs_sweeps))
         roof["iteration_launches_per_step"] = sum(lvl_launch) // reps
 
     cpu = None

@@ -53,15 +53,44 @@ def test_kernel_hash_covers_the_tile_planner(tmp_path, monkeypatch):
 
 
 def test_roofline_arithmetic():
-    # 35 launches of 23.35 MB (76 B x 640 x 480) in 0.56 ms over one step: 16 us per launch
+    # 35 launches over 250 iterations of a 640 x 480 level in 0.56 ms: 16 us per launch, 7.14
+    # iterations per launch, priced at 68 B per pixel-iteration; one pass per launch is 76 B per pixel
     px = 640 * 480
     r = bench.roofline(ms=0.56, launches=35, iters=250, px=px, has_w=False, kernel="k", traffic=None, reps=1)
-    assert r["bytes_per_launch"] == 76 * px
+    assert r["px_iter_per_launch"] == round(px * 250 / 35)
+    assert r["bytes_per_launch"] == round(68 * px * 250 / 35)
     assert r["avg_launch_us"] == pytest.approx(16.0)
-    assert r["achieved"] == pytest.approx(76 * px / 16e-6 / 1e9, abs=0.1)
+    assert r["achieved"] == pytest.approx(68 * px * 250 / 0.56e-3 / 1e9, abs=0.1)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
-    assert r["one_pass_equivalent_GBs"] == pytest.approx(76 * px * 250 / 0.56e-3 / 1e9, abs=0.1)
+    assert r["one_pass_per_launch"]["GBs"] == pytest.approx(76 * px / 16e-6 / 1e9, abs=0.1)
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["launches_per_step_level0"] == 35
+    assert r["traffic"] is None and "dram_GBs" not in r
+    t = bench.roofline(ms=0.56, launches=35, iters=250, px=px, has_w=False, kernel="k", traffic=27.3e6, reps=1)
+    assert t["dram_GBs"] == pytest.approx(27.3e6 / 16e-6 / 1e9, abs=0.1) and t["traffic_source"]
+    w = bench.roofline(ms=0.56, launches=35, iters=250, px=px, has_w=True, kernel="k", traffic=None, reps=1)
+    assert w["per_unit"].startswith("92 B") and w["one_pass_per_launch"]["per_unit"].startswith("100 B")
+
+
+def test_batch_traffic_needs_the_source_and_the_stage_choices(monkeypatch, tmp_path):
+    rec = {"batch64": {"kernel_sha": bench.kernel_sha(),
+                       "entries": [{"stages": [[0, 0, 5, 64], [1, 0, 5, 64]], "bytes_per_launch": 1.5e9}]}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    csrc = tmp_path / "paper_2011_10979_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp", "tb_plan.cpp"):
+        (csrc / f).write_bytes(open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.batch_traffic([[0, 0, 5, 64], [1, 0, 5, 64]]) == 1.5e9
+    assert bench.batch_traffic([[0, 0, 6, 64], [1, 0, 5, 64]]) is None
+    assert bench.batch_traffic("built-in") is None
+    (csrc / "admm_tb.hip").write_text("changed")
+    assert bench.batch_traffic([[0, 0, 5, 64], [1, 0, 5, 64]]) is None
+
+
+def test_pair_px_sums_the_pyramid():
+    assert bench.pair_px(480, 640, 5) == 409200
+    assert bench.pair_px(1080, 1920, 6) == 2764200
 
 
 def test_more_than_one_gpu_is_refused():
