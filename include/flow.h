@@ -195,6 +195,33 @@ typedef struct flow_server_stats {
  * serving budget hold per pair.  Host-only. */
 flow_status flow_working_set_bytes(int32_t H, int32_t W, const flow_params* p, int32_t levels, uint64_t* bytes);
 
+/* Allocation-free variant of flow_solve, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: serving loops with a fixed footprint, harnesses that forbid
+ * allocation).  No context: the whole working set of the solve -- pyramids, linearisation, scheme
+ * state, reduction partials -- lives in one static device workspace of FLOW_STATIC_BYTES per GPU,
+ * which the library holds from the first call on that GPU until the process ends.  The call makes
+ * no device allocation and calls no allocating routine; it runs on the current device with the
+ * built-in kernel plan (no autotuning, no graph), so its flow and energy are bitwise those of
+ * flow_solve on a context without autotuning.
+ *   I0, I1, u, v, ld, ld_uv, p, stream   as for flow_solve (p->use_graph is ignored; p->tol must
+ *                                         be 0: a fixed iteration count)
+ *   res      host, may be NULL.  Non-NULL: the call blocks until the results are written and
+ *            reports FLOW_E_NONFINITE as flow_solve does; NULL: the call only enqueues the work on
+ *            `stream` and returns (no host synchronisation, no finiteness check).
+ * Every call on one GPU uses that GPU's single workspace, which keeps the last call's contents:
+ * calls that overlap on one GPU (concurrent streams or host threads) race and must be serialised
+ * by the caller.  Errors: as flow_solve, plus FLOW_E_INVAL for tol != 0 and FLOW_E_NOMEM (before
+ * any device work) when the pair's working set exceeds the workspace -- a 1920 x 1080 pADMM pair
+ * at beta = 0 with 6 levels fits, see flow_static_bytes. */
+#define FLOW_STATIC_BYTES (256ull << 20)
+flow_status flow_solve_static(const float* I0, const float* I1, int32_t H, int32_t W, int64_t ld,
+                              const flow_params* p, float* u, float* v, int64_t ld_uv, flow_result* res,
+                              void* stream);
+
+/* Workspace bytes flow_solve_static needs for an H x W pair under p (*need) and the workspace size
+ * (*limit, = FLOW_STATIC_BYTES); either pointer may be NULL.  Host-only. */
+flow_status flow_static_bytes(int32_t H, int32_t W, const flow_params* p, uint64_t* need, uint64_t* limit);
+
 /* Create a serving engine on ctx's GPU for solves with parameters p (ADMM family, tol = 0; per-pair
  * pyramid depth from flow_pair.levels, else p->levels).  hbm_budget: bytes of device memory for
  * the working sets of the pairs in flight (0: 8 GiB), allocated once here; a few MB of tables come

@@ -79,7 +79,8 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_op_energy", "flow_tune_set", "flow_op_admm_tb", "flow_autotune", "flow_get_tuning",
            "flow_tune_choice", "flow_autotune_batched", "flow_server_create", "flow_server_destroy",
            "flow_server_submit", "flow_server_step", "flow_server_poll", "flow_server_drain",
-           "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb", "flow_op_alg1_tb"]
+           "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb", "flow_op_alg1_tb",
+           "flow_solve_static", "flow_static_bytes"]
 
 
 def lib():
@@ -96,6 +97,10 @@ def lib():
             "flow_destroy": [vp],
             "flow_solve": [vp, vp, vp, i32, i32, i64, ctypes.POINTER(_Params), vp, vp, i64, ctypes.POINTER(_Result), vp],
             "flow_solve_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
+            "flow_solve_static": [vp, vp, i32, i32, i64, ctypes.POINTER(_Params), vp, vp, i64, ctypes.POINTER(_Result),
+                                  vp],
+            "flow_static_bytes": [i32, i32, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64)],
             "flow_autotune_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
             "flow_server_create": [vp, ctypes.POINTER(_Params), ctypes.c_size_t, i32, vp, ctypes.POINTER(vp)],
             "flow_server_destroy": [vp],
@@ -345,6 +350,38 @@ def working_set_bytes(H, W, params: Params | None = None, levels: int = 0, **kw)
     b = ctypes.c_uint64()
     _check(lib().flow_working_set_bytes(int(H), int(W), ctypes.byref(params.c_struct()), int(levels), ctypes.byref(b)))
     return b.value
+
+
+def solve_static(I0, I1, params: Params | None = None, u=None, v=None, **kw):
+    """flow_solve_static: the plain solve on the current device's static workspace (no context, no
+    device allocation by the library; built-in kernel plan).  Returns (u, v, result)."""
+    params = params or Params(**kw)
+    _plane(I0, "I0")
+    _plane(I1, "I1")
+    if I0.shape != I1.shape or I0.stride() != I1.stride():
+        raise ValueError("I0 and I1 must have the same shape and strides")
+    H, W = I0.shape
+    if u is None:
+        u = torch.empty((H, W), device=I0.device, dtype=torch.float32)
+    if v is None:
+        v = torch.empty((H, W), device=I0.device, dtype=torch.float32)
+    _plane(u, "u")
+    _plane(v, "v")
+    if u.stride() != v.stride():
+        raise ValueError("u and v must share strides")
+    res = _Result()
+    _check(lib().flow_solve_static(_ptr(I0), _ptr(I1), H, W, I0.stride(0), ctypes.byref(params.c_struct()), _ptr(u),
+                                   _ptr(v), u.stride(0), ctypes.byref(res), _stream()))
+    return u, v, _result_dict(res)
+
+
+def static_bytes(H, W, params: Params | None = None, **kw):
+    """(bytes flow_solve_static needs for an H x W pair, the static workspace size)."""
+    params = params or Params(**kw)
+    need, limit = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().flow_static_bytes(int(H), int(W), ctypes.byref(params.c_struct()), ctypes.byref(need),
+                                   ctypes.byref(limit)))
+    return need.value, limit.value
 
 
 class Server:

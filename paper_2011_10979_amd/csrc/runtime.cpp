@@ -300,7 +300,7 @@ EnergyArgs energy_args(const LevelPlanes& L, const flow_params& p, int cur, Scra
 
 // Tile plan of every level plus the device tables the tile kernel reads (ADMM family only).
 flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
-                      const std::map<std::string, TunedChoice>* tuned) {
+                      const std::map<std::string, TunedChoice>* tuned, bool upload) {
     out.levels.clear();
     out.pdr.clear();
     if (pd_state(p)) {
@@ -320,6 +320,7 @@ flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratc
         fill_tb_level(&descs[2 * l], Ls[l], sc.at);
         out.levels.push_back(P);
     }
+    if (!upload) return FLOW_OK;
     out.tables.reset(new TbTables());
     return out.tables->upload(tiles, descs);
 }

@@ -166,8 +166,9 @@ struct SolvePlan {
     std::unique_ptr<TbTables> tables;
 };
 
+// upload = false: the level plans only (direct tiling reads no device table), nothing allocated
 flow_status make_plan(std::vector<LevelPlanes>& Ls, const flow_params& p, Scratch& sc, SolvePlan& out,
-                      const std::map<std::string, TunedChoice>* tuned);
+                      const std::map<std::string, TunedChoice>* tuned, bool upload = true);
 PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std::string, TunedChoice>* tuned);
 int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int64_t n,
                       hipStream_t s, int64_t* launches);
