@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libflowmi.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["admm.hip", "admm_tb.hip", "pyramid.hip", "pdr.hip", "pdr_tb.hip", "alg1_tb.hip", "energy.hip", "noalloc.hip",
-           "runtime.cpp", "context.cpp", "tb_plan.cpp", "autotune.cpp", "batch.cpp", "multi.cpp", "serve.cpp"]
+           "runtime.cpp", "geometry.cpp", "context.cpp", "tb_plan.cpp", "autotune.cpp", "batch.cpp", "multi.cpp", "serve.cpp"]
 
 ARCH = os.environ.get("FLOWMI_ARCH", "gfx950")
 C_CLIENT_SRC = os.path.join(os.path.dirname(HERE), "tests", "c_client", "solve_pair.c")

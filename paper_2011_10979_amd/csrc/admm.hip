@@ -206,27 +206,7 @@ __global__ __launch_bounds__(256) void admm_iter_kernel(AdmmIterArgs a) {
 
 }  // namespace
 
-int g_admm_rows_override = 0;
 
-AdmmGeometry admm_geometry(int H, int W, int rows_hint) {
-    AdmmGeometry g;
-    g.strips = (W + kStrip - 1) / kStrip;
-    auto waves = [&](int r) { return (long long)g.strips * ((H + r - 1) / r); };
-    // Tall strips amortise the 3-row halo; short ones give more wavefronts to hide latency.
-    int rows = 2;
-    if (waves(8) >= 4096) rows = 8;
-    else if (waves(4) >= 1024) rows = 4;
-    if (g_admm_rows_override == 2 || g_admm_rows_override == 4 || g_admm_rows_override == 8)
-        rows = g_admm_rows_override;
-    else if (rows_hint == 2 || rows_hint == 4 || rows_hint == 8)
-        rows = rows_hint;
-    g.rows = rows;
-    g.segs = (H + g.rows - 1) / g.rows;
-    long long blocks = (waves(rows) + 3) / 4;
-    blocks = (blocks + 7) / 8 * 8;
-    g.blocks = (int)blocks;
-    return g;
-}
 
 template <int R>
 static void launch_rows(const AdmmIterArgs& b, const AdmmGeometry& g, bool has_w, bool rel, hipStream_t s) {

@@ -396,15 +396,6 @@ void launch_reset_u32(unsigned* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(reset_u32_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
 }
 
-int tb_capacity(bool has_w, int nt) {
-    if (nt == 1024) return 1024 * (has_w ? kTbPptLW : kTbPptL);
-    if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
-    if (nt == 513) return 512 * kTbPptSmall;     // 512 threads, small tiles
-    if (nt == 257) return 256 * kTbPptSmall;     // 256 threads, small tiles
-    if (nt == 1026) return 1024;                  // 1024 threads, one pixel each
-    if (nt == 514) return 512;                    // 512 threads, one pixel each
-    return 256 * (has_w ? kTbPptW : kTbPpt);
-}
 
 // direct tiling; a level that one tile covers runs the instance without the shrinking band
 template <bool HAS_W, int NT, int PPT>

@@ -180,13 +180,6 @@ __global__ __launch_bounds__(256) void energy_final_batched_kernel(const EnergyA
 
 }  // namespace
 
-int energy_blocks(int H, int W) {
-    const int64_t npix = (int64_t)H * W;
-    int blocks = (int)((npix + 255) / 256);
-    if (blocks > kEnergyBlocks) blocks = kEnergyBlocks;
-    if (blocks < 1) blocks = 1;
-    return blocks;
-}
 
 void launch_energy(const EnergyArgs& a, hipStream_t s) {
     const int blocks = energy_blocks(a.H, a.W);

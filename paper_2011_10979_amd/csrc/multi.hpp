@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -68,6 +70,44 @@ struct PinnedBuf {
     size_t bytes = 0;
     flow_status ensure(size_t need);
     void release();
+};
+
+// First-fit allocator over offsets [0, cap) (the serving arena; callers round sizes up to 256 bytes):
+// the free ranges sorted by offset, adjacent free ranges merged on release.
+struct RangeAlloc {
+    size_t cap = 0;
+    std::map<size_t, size_t> free_;   // offset -> size
+    void reset(size_t c) {
+        cap = c;
+        free_.clear();
+        if (c) free_[0] = c;
+    }
+    bool alloc(size_t n, size_t& off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            off = it->first;
+            const size_t rest = it->second - n;
+            free_.erase(it);
+            if (rest) free_[off + n] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
 };
 
 inline int launches_per_warp(int iters, int K) { return iters <= 0 ? 0 : (iters + K - 1) / K; }

@@ -290,8 +290,6 @@ __global__ __launch_bounds__(NT) void pdr_tb_kernel(PdrTbArgs a) {
 
 }  // namespace
 
-// one red and one black cell per thread
-int pdr_tb_capacity(bool, int nt) { return 2 * nt; }
 
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;

@@ -354,8 +354,6 @@ void launch_upsample(const float* coarse, int64_t ldc, float* fine, int Hf, int 
                        fine, Hf, Wf, ldf, scale);
 }
 
-int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
-int lin_blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + kLinRows - 1) / kLinRows); }
 
 void launch_batched(BatchOp op, const void* items, const int* off, int n, int total, bool f16, hipStream_t s) {
     if (n <= 0 || total <= 0) return;

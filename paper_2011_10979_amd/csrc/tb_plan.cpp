@@ -22,7 +22,8 @@ static bool fit_tile(int H, int W, int cap, int K, int ew_target, int& th, int& 
     const int ext_w = std::min(W, tw + halo);
     int eh = cap / ext_w;
     th = (eh >= H) ? H : eh - halo;
-    return tw >= 8 && th >= 2 && (int64_t)std::min(W, tw + halo) * std::min(H, th + halo) <= cap;
+    // tiles at least 8 wide, or as wide as a level narrower than that (no side halo then)
+    return (tw >= 8 || tw == W) && th >= 2 && (int64_t)std::min(W, tw + halo) * std::min(H, th + halo) <= cap;
 }
 
 LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
@@ -130,7 +131,7 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, i
     const int ext_w = std::min(W, tw + halo);
     const int eh = cap / ext_w;
     const int th = (eh >= H) ? H : eh - halo;
-    if (tw < 8 || th < 2 || (int64_t)ext_w * std::min(H, th + halo) > cap) return P;
+    if ((tw < 8 && tw != W) || th < 2 || (int64_t)ext_w * std::min(H, th + halo) > cap) return P;
     P.tb = true;
     P.K = K;
     // pDR and ALG1 tiles (74 / 67 VGPRs, 86 / 82 with w): one 1024-thread work-group per CU, two or
@@ -159,6 +160,7 @@ LevelTbPlan plan_level_tuned(int H, int W, bool hw, int iters, const std::map<st
 }
 
 void append_tiles(const LevelTbPlan& P, int level_id, int H, int W, std::vector<TbTile>& out) {
+    if (!P.tb || P.th < 1 || P.tw < 1) return;      // no tile plan: no tiles (callers check the plan)
     for (int y = 0; y < H; y += P.th)
         for (int x = 0; x < W; x += P.tw) {
             TbTile t;

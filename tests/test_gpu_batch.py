@@ -152,3 +152,28 @@ def test_invalid_pairs_are_rejected_before_anything_runs(ctx):
     # the context still works afterwards
     out = batched(ctx, fr, **KW)
     assert all(np.isfinite(r["energy"]) for _, _, r in out)
+
+
+def test_levels_narrower_than_a_tile_width(ctx):
+    """Pairs whose coarse levels are narrower than 8 pixels (75 x 5, 5 x 100, 88 x 5): batched and
+    served, their tiles span the level's width; bitwise equal to the plain solve on the same tile
+    kernel, and within the FP32 bar of the oracle."""
+    print("[case] narrow coarse levels", flush=True)
+    spec = [(150, 10, 41, 2), (9, 200, 42, 2), (700, 40, 43, 4)]
+    fr = frames(spec)
+    jobs = [(I0, I1, dict(KW, levels=lv)) for I0, I1, lv, _, _ in fr]
+    with mp.get_context("fork").Pool(3) as pool:
+        get = oracle_refs(jobs, pool)
+        out = batched(ctx, fr, **KW)
+        srv = fm.Server(ctx, fm.Params(**KW), budget_bytes=64 << 20, max_active=3)
+        tick = [srv.submit(d0, d1, lv) for _, _, lv, d0, d1 in fr]
+        srv.drain()
+        served = [srv.poll(t) for t in tick]
+        srv.close()
+        fm.set_tuning("tb_mode", 4)
+        for k, (_, _, lv, d0, d1) in enumerate(fr):
+            plain = ctx.solve(d0, d1, fm.Params(**dict(KW, levels=lv)))
+            assert same(out[k], plain) and same(served[k], plain), spec[k]
+        refs = get(600)
+    for k, (u, v, res) in enumerate(out):
+        assert_parity(f"narrow pair {spec[k][:2]}", to_np(u), to_np(v), res, refs[k], job=jobs[k])
