@@ -266,6 +266,15 @@ flow_status flow_server_get_stats(const flow_server* srv, flow_server_stats* out
 flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
                                   void* stream);
 
+/* Set the stage choice of `level` for batches with this batch's stage shapes, as
+ * flow_autotune_batched would (for reuse of a measured choice, e.g. the "stages" entries of its
+ * report): order 0 tile table / 1 work queue, K iterations per tile launch (>= iters: the whole
+ * warp in one launch), extended tile width ew in [16, 512].  The choice changes speed only.
+ * FLOW_E_INVAL if no pair has the level or one of its levels takes no tiles of that K and width.
+ * Host-only. */
+flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                                    int32_t level, int32_t order, int32_t K, int32_t ew);
+
 /* Autotuner: for every pyramid level of an H x W pair under params p, time each iteration-kernel
  * choice over one warp's iterations with HIP events on `stream`, and keep the fastest per level
  * shape for this context's later solves.  ADMM family: one-pass kernel with 2 / 4 / 8-row strips;

@@ -80,7 +80,7 @@ EXPORTS = ["flow_params_default", "flow_create", "flow_destroy", "flow_solve", "
            "flow_tune_choice", "flow_autotune_batched", "flow_server_create", "flow_server_destroy",
            "flow_server_submit", "flow_server_step", "flow_server_poll", "flow_server_drain",
            "flow_server_get_stats", "flow_working_set_bytes", "flow_op_pdr_tb", "flow_op_alg1_tb",
-           "flow_solve_static", "flow_static_bytes"]
+           "flow_solve_static", "flow_static_bytes", "flow_tune_batched_stage"]
 
 
 def lib():
@@ -102,6 +102,7 @@ def lib():
             "flow_static_bytes": [i32, i32, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_uint64),
                                   ctypes.POINTER(ctypes.c_uint64)],
             "flow_autotune_batched": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), vp],
+            "flow_tune_batched_stage": [vp, i32, ctypes.POINTER(_Pair), ctypes.POINTER(_Params), i32, i32, i32, i32],
             "flow_server_create": [vp, ctypes.POINTER(_Params), ctypes.c_size_t, i32, vp, ctypes.POINTER(vp)],
             "flow_server_destroy": [vp],
             "flow_working_set_bytes": [i32, i32, ctypes.POINTER(_Params), i32, ctypes.POINTER(ctypes.c_uint64)],
@@ -267,6 +268,11 @@ class Context:
         _check(lib().flow_get_tuning(self._h, buf, len(buf)))
         return json.loads(buf.value.decode() or "{}")
 
+    def set_batched_stage(self, pairs, level, order, K, ew, params: Params | None = None, **kw):
+        """Pin the stage choice of `level` for batches with these pairs' stage shapes (see
+        flow_tune_batched_stage)."""
+        _set_batched_stage(self, pairs, level, order, K, ew, params or Params(**kw))
+
     def set_choice(self, key: str, mode: int, K: int = 0, rows: int = 0):
         """Apply one level-shape choice of an autotune report (key "<H>x<W>[w]i<iters>[p<sweeps>]") by hand."""
         import re
@@ -342,6 +348,12 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().flow_get_tuning(self._h, buf, len(buf)))
         return json.loads(buf.value.decode() or "{}")
+
+
+def _set_batched_stage(ctx, pairs, level, order, K, ew, params):
+    arr, _, _ = ctx._pairs(pairs)
+    _check(lib().flow_tune_batched_stage(ctx._h, len(pairs), arr, ctypes.byref(params.c_struct()), int(level),
+                                         int(order), int(K), int(ew)))
 
 
 def working_set_bytes(H, W, params: Params | None = None, levels: int = 0, **kw):

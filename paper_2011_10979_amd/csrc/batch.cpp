@@ -438,15 +438,16 @@ void enqueue_batch(const BatchState& B, const flow_params& p, hipStream_t s, hip
     for (const BStage& S : P.stages) {
         run_b(BatchOp::LevelInit, tab, S.init, false, s);
         int cur = 0;
-        if (ev) hipEventRecord(ev[2 * si], s);
         for (int w = 0; w < p.warps; ++w) {
             run_b(BatchOp::Linearize, tab, S.lin[w], f16, s);
+            // instrumented solves time the iteration launches alone, warp by warp
+            if (ev) hipEventRecord(ev[2 * (si * p.warps + w)], s);
             cur = enqueue_stage_iters(B, S, p, w, cur, s);
+            if (ev) hipEventRecord(ev[2 * (si * p.warps + w) + 1], s);
             if (S.l == 0 && w == p.warps - 1)
                 launch_energy_batched((const EnergyArgs*)(tab + P.energy.items), (const int*)(tab + P.energy.off),
                                       P.energy.n, P.energy.total, s);
         }
-        if (ev) hipEventRecord(ev[2 * si + 1], s);
         ++si;
     }
     run_b(BatchOp::Copy, B.io.d, P.exp, false, s);                       // export
@@ -513,7 +514,7 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
         }
         HIP_TRY(hipGraphLaunch(B.exec, s));
     } else {
-        while (B.ev.size() < 2 * P.stages.size()) {
+        while (B.ev.size() < 2 * P.stages.size() * (size_t)p->warps) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             B.ev.push_back(e);
@@ -540,7 +541,11 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
             S.iterations[G.l] = (int64_t)p->warps * p->iters;
             S.launches[G.l] = (int64_t)p->warps * G.lpw;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, B.ev[2 * si], B.ev[2 * si + 1]);
+            for (int w = 0; w < p->warps; ++w) {
+                float wms = 0.f;
+                hipEventElapsedTime(&wms, B.ev[2 * (si * p->warps + w)], B.ev[2 * (si * p->warps + w) + 1]);
+                ms += wms;
+            }
             S.iter_ms[G.l] = ms;
             pxi += px * S.iterations[G.l];
         }
@@ -559,6 +564,38 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
         if (!std::isfinite(e[0] + e[1]) || !std::isfinite(e[2]) || e[7] != 0.0) finite = false;
     }
     if (!finite) return fail(FLOW_E_NONFINITE, "non-finite energy or gap in a batched pair");
+    return FLOW_OK;
+}
+
+extern "C" flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
+                                               int32_t level, int32_t order, int32_t K, int32_t ew) {
+    if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
+    if (n < 1 || !pairs) return fail(FLOW_E_INVAL, "bad batch arguments");
+    flow_status st = validate(p);
+    if (st != FLOW_OK) return st;
+    st = validate_pairs(n, pairs, *p);
+    if (st != FLOW_OK) return st;
+    if (level < 0 || level >= FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "level out of range");
+    if (order != ORDER_TABLE && order != ORDER_QUEUE) return fail(FLOW_E_INVAL, "order: 0 table, 1 work queue");
+    if (K < 1 || ew < 16 || ew > 512) return fail(FLOW_E_INVAL, "K must be >= 1 and ew in [16, 512]");
+    const bool hw = p->beta > 0;
+    Shapes shapes;
+    for (int32_t k = 0; k < n; ++k) {
+        const int lv = pairs[k].levels > 0 ? pairs[k].levels : p->levels;
+        if (lv > level) shapes.push_back(level_shapes(pairs[k].H, pairs[k].W, lv)[level]);
+    }
+    if (shapes.empty()) return fail(FLOW_E_INVAL, "no pair of the batch has that level");
+    if (!shapes_fit(shapes, hw, K, ew))
+        return fail(FLOW_E_INVAL, "a level of the stage takes no tiles of that K and width");
+    BatchState& B = batch_of(ctx);
+    StageChoice c;
+    c.order = order;
+    c.K = K;
+    c.ew = ew;
+    B.tuned[stage_key(shapes, hw, p->iters)] = c;
+    B.tune_epoch++;
+    B.drop_graph();
+    B.plan.reset();
     return FLOW_OK;
 }
 

@@ -107,6 +107,24 @@ def test_autotuned_batch_keeps_results(ctx):
         assert same(a, b)
 
 
+def test_pinned_stage_choices_keep_results(ctx):
+    """Stage choices set by hand (the entries an autotune report lists) change speed only: the
+    batch's results stay bitwise the same; a level no pair has, or an order outside 0 / 1, is refused."""
+    print("[case] batched pinned stage choices", flush=True)
+    fr = frames(MIX)
+    pairs = [(d0, d1, lv) for _, _, lv, d0, d1 in fr]
+    before = batched(ctx, fr, **KW)
+    for level, order, K, ew in ((0, 1, 3, 48), (1, 0, 7, 96), (2, 0, 30, 64)):
+        ctx.set_batched_stage(pairs, level, order, K, ew, fm.Params(**KW))
+    after = batched(ctx, fr, **KW)
+    for a, b in zip(before, after):
+        assert same(a, b)
+    with pytest.raises(fm.FlowError):
+        ctx.set_batched_stage(pairs, 7, 0, 4, 64, fm.Params(**KW))
+    with pytest.raises(fm.FlowError):
+        ctx.set_batched_stage(pairs, 0, 2, 4, 64, fm.Params(**KW))
+
+
 def test_graph_replay_reads_new_frames(ctx):
     print("[case] batched graph replay", flush=True)
     fa = frames(MIX[:3])
