@@ -922,7 +922,7 @@ def run_single(args):
         suffix = "a" if args.scheme == "alg1" else f"p{params.gs_sweeps}"
         key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}{suffix}"
         ch0 = (tuning or {}).get(key0, {"mode": 5})
-        if ch0["mode"] in (5, 6):
+        if ch0["mode"] in (5, 6, 10):
             # K-iteration pDR / ALG1 tiles: per launch the kernel reads X, X bar, y and the
             # linearisation once and writes X, X bar, y and Theta once
             name = "ALG1" if args.scheme == "alg1" else "pDR"

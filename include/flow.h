@@ -301,7 +301,8 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
  * 512 threads with K iterations per launch (K = 0:
  * resident if the level fits one tile, else the built-in K) and `rows` the target width of a tile's
  * extended region (0 = built-in, else 16..512).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
- * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident); pdr_sweeps = -1:
+ * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident), 10 = large tiles
+ * (1024 threads with two cells of each colour, 4096-cell regions; beta = 0 only); pdr_sweeps = -1:
  * ALG1, modes 5 / 6 as for pDR.  Lets a caller reuse a tuning measured in
  * another process.  Drops the context's captured graphs. */
 flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t pdr_sweeps,
@@ -323,7 +324,8 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 tiles of 1024 / 512 threads.
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
  *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
- *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads.
+ *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads, 10 large
+ *                 tiles (1024 threads, two cells of each colour per thread; with beta > 0: 5).
  *   "pdr_k"       iterations per pDR tile launch (0 = built-in 2).
  *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
  *                 work queues.
@@ -417,8 +419,10 @@ flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work
  * for pDR levels), from `in` to `out` (distinct planes; in is not modified), with I_t relative to
  * the linearisation point (u0, v0) as in the solver: rho = I_t + beta w + I_x (u - u0) + I_y (v - v0).
  * tile_h x tile_w: output tile; each tile's extended region
- * min(H, tile_h + (4 gs_sweeps + 3) iters) x min(W, tile_w + (4 gs_sweeps + 3) iters) must hold at
- * most 2048 pixels, else FLOW_E_INVAL.  s_out receives Theta of the last iteration.  Blocking. */
+ * min(H, tile_h + (4 gs_sweeps + 2) iters + 1) x min(W, tile_w + (4 gs_sweeps + 2) iters + 1) must hold
+ * at most 2048 pixels, or 4096 with beta = 0 (regions above 2048 run the large tiles: 1024 threads
+ * with two cells of each colour), else FLOW_E_INVAL.  s_out receives Theta of the last iteration.
+ * Blocking. */
 flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
                            int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,

@@ -43,6 +43,7 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
     const int ey1 = min(y0 + th + hk, H), ex1 = min(x0 + tw + hk, W);
     const int EW = ex1 - ex0, EN = (ey1 - ey0) * EW;
     const float sigma = a.sigma, tau = a.tau, lam = a.lam, beta = a.beta;
+    const float sl = sigma * lam, inv_sigma = 1.f / sigma;
     const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
     auto live = [&](int k) { return wave0 + k * NT < EN; };
 
@@ -177,16 +178,12 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, in
                 if constexpr (HAS_W) wt = x[2][k] + sigma * dvv[NX - 1][j];
                 const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
                 const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
-                const float thr = sigma * lam * e2;
-                float step, theta;
+                // eq:resolvent with step sigma: -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
+                // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
+                float step = 0.f, theta = 0.f;
                 if (e2 > 0.f) {
-                    if (rho < -thr) step = sigma * lam;
-                    else if (rho > thr) step = -sigma * lam;
-                    else step = -rho / e2;
-                    theta = __builtin_amdgcn_fmed3f(rho / (sigma * e2), -lam, lam);
-                } else {
-                    step = 0.f;
-                    theta = 0.f;
+                    step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+                    theta = -step * inv_sigma;
                 }
                 const float un = ut + step * Ix[k], vn = vt + step * Iy[k];
                 S.xb[0][e] = xbo[0][k] = 2.f * un - x[0][k];

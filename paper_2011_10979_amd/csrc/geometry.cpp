@@ -37,8 +37,9 @@ int tb_capacity(bool has_w, int nt) {
     return 256 * (has_w ? kTbPptW : kTbPpt);
 }
 
-// pDR / ALG1 tiles: one red and one black cell per thread
-int pdr_tb_capacity(bool, int nt) { return 2 * nt; }
+// pDR / ALG1 tiles: work-group codes 512 / 1024 (one red and one black cell per thread), 2048 (1024
+// threads with two cells of each colour) and 513 (512 threads with two of each)
+int pdr_tb_capacity(bool, int nt) { return nt == 513 ? 2048 : 2 * nt; }
 
 int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
 int lin_blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + kLinRows - 1) / kLinRows); }

@@ -129,7 +129,9 @@ struct PdrTbArgs {
     int th, tw, ntx, ntiles;         // output tiling
     float sigma, tau, stt, lam, beta;
 };
-int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads
+int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads; 2048 / 513: 1024 /
+                                                          // 512 threads with two cells of each colour
+                                                          // (pDR, beta = 0)
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 // ALG1 (primal-dual) tiles on the same argument block: sigma / tau are its primal / dual steps
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);

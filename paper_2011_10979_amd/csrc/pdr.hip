@@ -126,16 +126,13 @@ __global__ __launch_bounds__(256) void pdr_final_kernel(PdrArgs a) {
     const float du0 = a.u0 ? ut - a.u0[o] : ut;
     const float dv0 = a.v0 ? vt - a.v0[o] : vt;
     const float rho = It + a.beta * wt + Ix * du0 + Iy * dv0;
-    const float thr = a.sigma * a.lam * e2;
-    float step, theta;
+    // eq:resolvent: the step along e is -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
+    // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
+    const float sl = a.sigma * a.lam;
+    float step = 0.f, theta = 0.f;
     if (e2 > 0.f) {
-        if (rho < -thr) step = a.sigma * a.lam;
-        else if (rho > thr) step = -a.sigma * a.lam;
-        else step = -rho / e2;
-        theta = fminf(fmaxf(rho / (a.sigma * e2), -a.lam), a.lam);
-    } else {
-        step = 0.f;
-        theta = 0.f;
+        step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+        theta = -step * (1.f / a.sigma);
     }
     // X bar + J(X~) - X+ with J(X~) = X~ + step e and X~ = 2 X+ - X bar is X+ + step e (one rounding)
     a.ub[o] = u + step * Ix;

@@ -370,7 +370,8 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
     return cur;
 }
 
-int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512
+int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512,
+                      // 10 / 11 tiles of 1024 / 512 threads with two cells of each colour per thread (beta = 0)
 int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
 constexpr int kPdrDefaultK = 2;
 constexpr int kAlg1DefaultK = 4;
@@ -397,8 +398,9 @@ PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std:
         }
     }
     if (alg1 && mode == 1) mode = 5;                 // ALG1 has no three-pass form
+    if ((mode == 10 || mode == 11) && (alg1 || hw)) mode -= 5;   // two cells per colour: pDR without w only
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
-    const int nt = mode == 6 ? 512 : 1024;
+    const int nt = mode == 6 ? 512 : mode == 10 ? 2048 : mode == 11 ? 513 : 1024;
     const int kdef = alg1 ? kAlg1DefaultK : kPdrDefaultK;
     const int k0 = K > 0 ? K : kdef;
     PdrTbPlan T = plan_pd_tiles(H, W, hw, pd_halo(p, k0), k0, 0, nt);
@@ -645,8 +647,10 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "pdr_mode") == 0) {
-        if (value != 0 && value != 1 && value != 5 && value != 6)
-            return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles of 1024 threads, 6 of 512");
+        if (value != 0 && value != 1 && value != 5 && value != 6 && value != 10 && value != 11)
+            return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles of 1024 threads, 6 of 512, "
+                                      "10 / 11 tiles of 1024 / 512 threads with two cells of each colour per "
+                                      "thread (beta = 0; 5 / 6 otherwise)");
         g_pdr_mode = (int)value;
         return FLOW_OK;
     }
@@ -969,7 +973,11 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     const bool hw = p->beta > 0;
     const int64_t halo = pd_halo(*p, iters);
-    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > pdr_tb_capacity(hw, 1024))
+    const int64_t region = std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo);
+    // regions above the 1024-thread kernel's capacity run the large pDR tiles (beta = 0)
+    const bool large = p->scheme == FLOW_PDR && !hw && region > pdr_tb_capacity(hw, 1024);
+    const int nt = large ? 2048 : 1024;
+    if (region > pdr_tb_capacity(hw, nt))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,
                             in->qb1x, in->qb1y, in->qb2x, in->qb2y};
@@ -1007,7 +1015,7 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     hipStream_t s = (hipStream_t)stream;
     // reads set 0 (in), writes set 1 (out)
     if (p->scheme == FLOW_ALG1) launch_alg1_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);
-    else launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);
+    else launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, nt, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return FLOW_OK;

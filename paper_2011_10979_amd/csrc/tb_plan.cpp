@@ -125,7 +125,7 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, i
         P.tw = W;
         return P;
     }
-    if (ew_target <= 0) ew_target = nt == 512 ? 32 : 64;
+    if (ew_target <= 0) ew_target = nt == 512 ? 32 : 64;      // 32 x 32, 64 x 32 or 64 x 64 regions
     const int ew = std::min(W, std::max(ew_target, halo + 8));
     const int tw = (ew >= W) ? W : ew - halo;
     const int ext_w = std::min(W, tw + halo);
@@ -134,9 +134,9 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, i
     if ((tw < 8 && tw != W) || th < 2 || (int64_t)ext_w * std::min(H, th + halo) > cap) return P;
     P.tb = true;
     P.K = K;
-    // pDR and ALG1 tiles (74 / 67 VGPRs, 86 / 82 with w): one 1024-thread work-group per CU, two or
-    // three of 512 threads
-    P.th = balanced_height(H, W, th, tw, nt == 512 ? (hw ? 2 : 3) : 1);
+    // pDR and ALG1 tiles (70 / 67 VGPRs, 80 / 82 with w; two cells of each colour per thread: 128):
+    // one 1024-thread work-group per CU, two or three of 512 threads
+    P.th = balanced_height(H, W, th, tw, nt == 512 ? (hw ? 2 : 3) : nt == 513 ? 2 : 1);
     P.tw = tw;
     return P;
 }

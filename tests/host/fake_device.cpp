@@ -454,7 +454,16 @@ void launch_admm_tb(const TbArgs& a, bool, int nt, int grid, hipStream_t s) {
         }
     });
 }
-void launch_pdr_tb(const PdrTbArgs& a, bool, int, hipStream_t s) {
+// every tile's extended region fits the work-group shape it is launched with (the real kernels
+// index LDS by the region's cells), and the large pDR tiles run without the w block only
+static void check_pd_tiles(const PdrTbArgs& a, bool has_w, int nt, int halo) {
+    check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513, "pDR / ALG1 tile launch: work-group code");
+    check((nt != 2048 && nt != 513) || !has_w, "pDR tiles with two cells of each colour launched with w");
+    const int64_t eh = std::min<int64_t>(a.lvl.H, (int64_t)a.th + halo);
+    const int64_t ew = std::min<int64_t>(a.lvl.W, (int64_t)a.tw + halo);
+    check(eh * ew <= pdr_tb_capacity(has_w, nt), "pDR / ALG1 tile region above the kernel's capacity");
+}
+static void toy_pd_tiles(const PdrTbArgs& a, hipStream_t s) {
     ++g_launches;
     enqueue(s, [=] {
         const PdrTbLevel& L = a.lvl;
@@ -472,7 +481,15 @@ void launch_pdr_tb(const PdrTbArgs& a, bool, int, hipStream_t s) {
             }
     });
 }
-void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) { launch_pdr_tb(a, has_w, nt, s); }
+void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
+    check_pd_tiles(a, has_w, nt, pdr_halo_lo(a.sweeps, a.K) + pdr_halo_hi(a.sweeps, a.K));
+    toy_pd_tiles(a, s);
+}
+void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
+    check(nt != 2048 && nt != 513, "pDR-only tiles launched for ALG1");
+    check_pd_tiles(a, has_w, nt, 2 * alg1_halo(a.K));
+    toy_pd_tiles(a, s);
+}
 static void pdr_pass(const PdrArgs& a, bool final_pass) {
     float* x[3] = {a.w, a.u, a.v};
     for (int i = 0; i < a.H; ++i)

@@ -146,8 +146,9 @@ static void test_planners(std::mt19937& rng) {
         }
         // pDR / ALG1 tiles
         const int halo = 3 * (1 + rng() % 4);
+        const int pnt[] = {512, 1024, 2048, 513};
         const PdrTbPlan R = plan_pd_tiles(H, W, hw, halo, 1 + rng() % 4, rng() % 2 ? 0 : 32 + rng() % 64,
-                                          rng() % 2 ? 512 : 1024);
+                                          pnt[rng() % 4]);
         if (R.tb && !R.resident) {
             CHECK(R.th >= 2 && (R.tw >= 8 || R.tw == W), "pDR tile %dx%d of a level %d wide", R.th, R.tw, W);
             const int ext_w = std::min(W, R.tw + halo), ext_h = std::min(H, R.th + halo);
@@ -390,6 +391,44 @@ static void test_solves(std::mt19937& rng) {
     CHECK(fake_device_live_allocations() == 0, "%zu device allocations leaked", fake_device_live_allocations());
 }
 
+// pDR and ALG1 solves under every kernel choice and K: each tile launch is checked by the fake
+// device against its kernel's capacity (the large pDR tiles only without the w block)
+static void test_pd_solves(std::mt19937& rng) {
+    flow_ctx* ctx = nullptr;
+    OK(flow_create(&ctx, 0, 0));
+    for (int k = 0; k < 6; ++k) {
+        const int H = 12 + rng() % 140, W = 12 + rng() % 160;
+        int lv = 1;
+        while (lv < 4 && std::min(H, W) >> lv >= 4) ++lv;
+        Frame f = make_frame(rng, H, W, lv);
+        float *u, *v;
+        hipMalloc(&u, sizeof(float) * H * W);
+        hipMalloc(&v, sizeof(float) * H * W);
+        for (int mode : {0, 1, 5, 6, 10, 11})
+            for (int K : {0, 1, 2, 3}) {
+                OK(flow_tune_set("pdr_mode", mode));
+                OK(flow_tune_set("pdr_k", K));
+                for (int scheme : {FLOW_PDR, FLOW_ALG1})
+                    for (double beta : {0.0, 0.05}) {
+                        flow_params p = params(lv);
+                        p.scheme = scheme;
+                        p.beta = beta;
+                        p.use_graph = (int)(rng() % 2);
+                        flow_result r{};
+                        OK(flow_solve(ctx, f.I0, f.I1, H, W, W, &p, u, v, W, &r, nullptr));
+                        read_out(f, u, v, r);
+                    }
+            }
+        hipFree(u);
+        hipFree(v);
+        hipFree(f.I0);
+        hipFree(f.I1);
+    }
+    OK(flow_tune_set("pdr_mode", 0));
+    OK(flow_tune_set("pdr_k", 0));
+    flow_destroy(ctx);
+}
+
 int main(int argc, char** argv) {
     const unsigned seed = argc > 1 ? (unsigned)std::strtoul(argv[1], nullptr, 10) : 1u;
     std::mt19937 rng(seed);
@@ -399,6 +438,8 @@ int main(int argc, char** argv) {
     std::printf("planners: %d failed checks\n", g_fail);
     test_solves(rng);
     std::printf("solves: %d failed checks (%ld toy launches)\n", g_fail, fake_device_launches());
+    test_pd_solves(rng);
+    std::printf("pDR / ALG1 solves: %d failed checks (%ld toy launches)\n", g_fail, fake_device_launches());
     if (g_fail) {
         std::printf("FAILED (%d checks)\n", g_fail);
         return 1;

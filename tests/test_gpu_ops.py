@@ -153,14 +153,17 @@ def test_pdr_iteration(shape, sweeps, beta):
 
 
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 6), ((37, 130), (8, 30), 2), ((101, 250), (12, 20), 1),
-                                          ((40, 45), (40, 45), 9), ((64, 64), (10, 18), 2), ((33, 47), (5, 9), 3)])
+                                          ((40, 45), (40, 45), 9), ((64, 64), (10, 18), 2), ((33, 47), (5, 9), 3),
+                                          ((101, 250), (40, 40), 2), ((64, 64), (51, 51), 2), ((130, 140), (30, 50), 3),
+                                          ((60, 61), (60, 61), 4)])
 @pytest.mark.parametrize("sweeps,beta", [(1, 0.0), (1, 0.05), (2, 0.0)])
 def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
-    """K pDR iterations of the tile kernel (halo (2n+1)K / (2n+1)K + 1, ragged tiles, a resident level)
-    against K steps of the oracle on the same state, I_t relative to (u0, v0)."""
+    """K pDR iterations of the tile kernel (halo (2n+1)K / (2n+1)K + 1, ragged tiles, resident levels;
+    extended regions above 2048 cells run the large tiles, beta = 0) against K steps of the oracle on
+    the same state, I_t relative to (u0, v0)."""
     print_case("pdr_tb", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta)
     halo = (4 * sweeps + 2) * K + 1
-    oversized = min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > 2048
+    oversized = min(shape[0], tile[0] + halo) * min(shape[1], tile[1] + halo) > (4096 if beta == 0 else 2048)
     rng = np.random.default_rng(zlib.crc32(repr(("pdrtb", shape, tile, K, sweeps, beta)).encode()))
     st = random_pdr_state(rng, shape, beta)
     Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
@@ -188,6 +191,26 @@ def test_pdr_tiles_match_k_oracle_steps(shape, tile, K, sweeps, beta):
     assert max_abs(to_np(s_out), duals["s"]) < tol
     for k in keys:                                   # the input state is left as it was
         assert np.array_equal(to_np(g[k]), f32(st[k]))
+
+
+@pytest.mark.parametrize("shape,tile,K,small", [((101, 250), (40, 40), 2, (12, 20)), ((64, 64), (51, 51), 2, (10, 18)),
+                                                ((60, 61), (60, 61), 4, (5, 9)), ((130, 140), (30, 50), 3, (7, 11))])
+def test_large_pdr_tiles_equal_the_1024_thread_tiles(shape, tile, K, small):
+    """A large tile (1024 threads, two cells of each colour per thread) computes each cell with the
+    same expression on the same operands as the 1024-thread tiles: K iterations of both tilings of
+    the same state agree bit for bit."""
+    print_case("pdr_tb large vs small", shape=shape, tile=tile, K=K, small=small)
+    rng = np.random.default_rng(zlib.crc32(repr(("pdrtb2", shape, tile, K)).encode()))
+    st = random_pdr_state(rng, shape, 0.0)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, 0.0)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    outs = [fm.pdr_tb(g, to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3),
+                      fm.Params(scheme="pdr"), iters=K, tile_h=t[0], tile_w=t[1]) for t in (tile, small)]
+    for k in ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"]:
+        assert torch.equal(outs[0][0][k], outs[1][0][k]), k
+    assert torch.equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 9), ((37, 130), (8, 30), 4), ((101, 250), (12, 20), 1),
