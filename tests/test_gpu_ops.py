@@ -293,6 +293,54 @@ def test_admm_iteration_increment_form(shape, scheme, relax, beta):
         assert max_abs(to_np(out[k]), ref[k]) < 1e-4, k
 
 
+def _ulps(a, b):
+    """Distance in units in the last place between float32 arrays (the order-preserving integer
+    image of each value's bits)."""
+    def key(x):
+        i = np.ascontiguousarray(x, dtype=np.float32).view(np.int32).astype(np.int64)
+        return np.where(i < 0, -(i & 0x7FFFFFFF), i)
+    return np.abs(key(a) - key(b))
+
+
+@pytest.mark.parametrize("threads", [1025, 1026, 256])
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_tiles_and_one_pass_iterations_agree_to_the_ulp(threads, beta):
+    """K = 6 iterations of a tile kernel against 6 one-pass iterations from the same increment-form
+    state: the two kernels evaluate the same expressions in their own order, so they may differ by
+    rounding only.  Per field, the largest difference is measured in units of the FP32 spacing at the
+    field's magnitude (its largest value) and bounded by 16 (measured: at most 7.5, in p_x with beta >
+    0); the ulps of the values above a tenth of that magnitude are printed beside it (at most 34)."""
+    shape, K = (70, 90), 6
+    print_case("tile vs one-pass", threads=threads, beta=beta)
+    rng = np.random.default_rng(zlib.crc32(repr(("ulp", threads, beta)).encode()))
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, Itr, at = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=4.0, size=shape))
+    v0 = f32(rng.normal(scale=4.0, size=shape))
+    du = f32(rng.normal(scale=0.3, size=shape))
+    dv = f32(rng.normal(scale=0.3, size=shape))
+    init = dict(st, u=du, v=dv, u0=u0, v0=v0)
+    at_t = torch.tensor([at, 0.0], dtype=torch.float32, device="cuda")
+    p = fm.Params(beta=beta)
+    lin = (to_dev(Ix, 2), to_dev(Iy, 2), to_dev(Itr, 2))
+    tile = fm.admm_tb(_dev_state(init, pad=2), *lin, at_t, p, iters=K, threads=threads, tile_h=12, tile_w=20, order=0)
+    g = _dev_state(init, pad=2)
+    for _ in range(K):
+        out = fm.admm_iter(g, *lin, at_t[:1], p)
+        g = dict(g, **{k: v for k, v in out.items() if v is not None})
+    keys = ["u", "v", "q1x", "q1y", "q2x", "q2y", "s"] + (["w", "px", "py"] if beta > 0 else [])
+    spacings, ulps = {}, {}
+    for k in keys:
+        a, b = to_np(tile[k]), to_np(g[k])
+        scale = float(np.abs(b).max())
+        spacings[k] = round(float(np.abs(a - b).max() / np.spacing(np.float32(scale))), 2)
+        large = np.abs(b) >= 0.1 * scale
+        ulps[k] = int(_ulps(a, b)[large].max())
+    print(f"[ulps] threads {threads} beta {beta}: max difference in spacings at each field's magnitude "
+          f"{spacings}; ulps of values above a tenth of it {ulps}", flush=True)
+    assert max(spacings.values()) <= 16, spacings
+
+
 @pytest.mark.parametrize("rows", [2, 4, 8])
 @pytest.mark.parametrize("shape", [(7, 5), (37, 130), (101, 250)])
 @pytest.mark.parametrize("beta", [0.0, 0.05])
