@@ -351,23 +351,30 @@ def run_batch(args):
     tile_pxi = sum(level_px[l] * iters[l] for l in range(nl))           # over `reps` solves
     tile_px_launch = sum(level_px[l] * launches[l] for l in range(nl))
     launch_s = tile_ms * 1e-3 / tile_launches
-    alg_launch = BYTES_PER_PX_ITER[has_w] * tile_pxi / tile_launches     # algorithmic bytes per launch
+    pd = args.scheme in ("pdr", "alg1")
+    per_iter = (PDR_TB_BYTES_PER_PX_ITER if pd else BYTES_PER_PX_ITER)[has_w]
+    per_launch = (PDR_TB_BYTES_PER_PX_LAUNCH if pd else BYTES_PER_PX_LAUNCH)[has_w]
+    alg_launch = per_iter * tile_pxi / tile_launches                     # algorithmic bytes per launch
     achieved = alg_launch / launch_s / 1e9
-    signature = [[st["level"], st["order"], st["K"], st["ew"]] for st in tuning] if tuning else "built-in"
-    traffic = batch_traffic(signature, args.iters)
+    if pd:                                                  # the DRAM record covers the ADMM batch only
+        signature, traffic = "pDR / ALG1 stages", None
+    else:
+        signature = [[st["level"], st["order"], st["K"], st["ew"]] for st in tuning] if tuning else "built-in"
+        traffic = batch_traffic(signature, args.iters)
+    kernel = {"padmm": "admm_tb_table_kernel<false, 1024, 2>", "rpadmm2": "admm_tb_table_kernel<false, 1024, 2>",
+              "pdr": "pdr_tb_table_kernel", "alg1": "alg1_tb_table_kernel"}.get(args.scheme, "tile table kernel")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_source": ("looked up: profiles/traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE runs on this "
                                "kernel source and stage choice, copy-calibrated)") if traffic else None,
-            "kernel": "admm_tb_table_kernel<false, 1024, 2> (batched K-iteration tile kernel, every stage)",
-            "per_unit": f"{BYTES_PER_PX_ITER[has_w]} B per pixel-iteration",
+            "kernel": f"{kernel} (batched K-iteration tile kernel, every stage)",
+            "per_unit": f"{per_iter} B per pixel-iteration",
             "px_iter_per_launch": round(tile_pxi / tile_launches), "bytes_per_launch": round(alg_launch),
             "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step": tile_launches // reps,
             "note": "K iterations per launch share one pass over HBM, so the algorithmic rate can exceed the "
                     "HBM peak; dram_* figures are the measured traffic",
-            "one_pass_per_launch": {"per_unit": f"{BYTES_PER_PX_LAUNCH[has_w]} B per pixel per launch",
-                                    "GBs": round(BYTES_PER_PX_LAUNCH[has_w] * tile_px_launch / tile_launches
-                                                 / launch_s / 1e9, 1)}}
+            "one_pass_per_launch": {"per_unit": f"{per_launch} B per pixel per launch",
+                                    "GBs": round(per_launch * tile_px_launch / tile_launches / launch_s / 1e9, 1)}}
     roof["one_pass_per_launch"]["frac"] = round(roof["one_pass_per_launch"]["GBs"] / HBM_PEAK_GBS, 4)
     if traffic:
         roof["dram_GBs"] = round(traffic / launch_s / 1e9, 1)

@@ -163,10 +163,13 @@ typedef struct flow_pair {
  * the last stage); each step of a stage (level start, linearisation, K iterations, energy) is ONE
  * launch over all pairs, the iterations a launch of the K-iteration tile kernel over the tiles of
  * every pair's level, in XCD order or from per-XCD work queues (choice, K and tile width per stage
- * from flow_autotune_batched, else built in).  ADMM family only with tol = 0 (pDR pairs and
- * stopping tests run as plain solves in turn).  Every pair's arithmetic is independent of the rest
- * of the batch and of the stage choices, so a pair's results are bitwise the same alone or in any
- * batch, and equal to a plain solve that uses small 1024-thread tiles (tb_mode 4) at every level.
+ * from flow_autotune_batched, else built in).  pDR and ALG1 (Sec. 3.1.2, Sec. 4) take the same
+ * stages with their own tile kernels in table order (1024 threads, the built-in K per launch, or
+ * the whole warp per launch where every level of a stage fits one tile).  With tol > 0, or a pDR
+ * halo that no tile holds (many sweeps), the pairs run as plain solves in turn.  Every pair's
+ * arithmetic is independent of the rest of the batch and of the stage choices, so a pair's results
+ * are bitwise the same alone or in any batch, and equal to a plain solve that uses small
+ * 1024-thread tiles (tb_mode 4) at every level (pDR and ALG1: to the plain tile solve).
  * The context keeps the working set of the last batch (arena, tables, captured graph) for reuse.
  * Errors: FLOW_E_INVAL (any pair invalid: nothing runs), FLOW_E_NOMEM (working set of all pairs
  * above the budget), FLOW_E_NONFINITE (outputs written, some pair's energy not finite).  Blocks

@@ -28,12 +28,11 @@ struct Alg1Lds {
 };
 
 template <bool HAS_W, int NT, int PPT>
-__device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, int y0, int x0, int th, int tw,
+__device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, const PdrTbLevel& L, int y0, int x0, int th, int tw,
                                           Alg1Lds<HAS_W, NT, PPT>& S) {
     constexpr int CAP = NT * PPT;
     constexpr int NX = Alg1Lds<HAS_W, NT, PPT>::NX;
     constexpr int NY = Alg1Lds<HAS_W, NT, PPT>::NY;
-    const PdrTbLevel& L = a.lvl;
     const int tid = threadIdx.x;
     const int H = L.H, W = L.W;
     const int64_t ld = L.ld;
@@ -242,19 +241,38 @@ __global__ __launch_bounds__(NT) void alg1_tb_kernel(PdrTbArgs a) {
     if (t >= a.ntiles) return;
     const int ty = t / a.ntx, tx = t - ty * a.ntx;
     const int y0 = ty * a.th, x0 = tx * a.tw;
-    alg1_tile<HAS_W, NT, PPT>(a, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+    alg1_tile<HAS_W, NT, PPT>(a, a.lvl, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+}
+
+// Many levels (batched pairs): tile entries of a table in XCD order (as the pDR table kernel).
+template <bool HAS_W, int NT, int PPT>
+__global__ __launch_bounds__(NT) void alg1_tb_table_kernel(PdrTbArgs a) {
+    __shared__ Alg1Lds<HAS_W, NT, PPT> S;
+    const int per = (a.ntiles + 7) >> 3;
+    const int x = blockIdx.x & 7, y = blockIdx.x >> 3;
+    const int t = x * per + y;
+    if (y >= per || t >= a.ntiles) return;
+    const TbTile T = a.tiles[t];
+    alg1_tile<HAS_W, NT, PPT>(a, a.levels[2 * T.level + a.dir], T.y0, T.x0, T.th, T.tw, S);
 }
 
 }  // namespace
 
+template <bool HAS_W, int NT, int PPT>
+static void launch_alg1_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
+    if (a.tiles) hipLaunchKernelGGL((alg1_tb_table_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((alg1_tb_kernel<HAS_W, NT, PPT>), dim3(grid), dim3(NT), 0, s, a);
+}
+
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
+    if (a.ntiles < 1) return;
     if (nt == 512) {
-        if (has_w) hipLaunchKernelGGL((alg1_tb_kernel<true, 512, kPdrPptW>), dim3(grid), dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((alg1_tb_kernel<false, 512, kPdrPpt>), dim3(grid), dim3(512), 0, s, a);
+        if (has_w) launch_alg1_shape<true, 512, kPdrPptW>(a, grid, s);
+        else launch_alg1_shape<false, 512, kPdrPpt>(a, grid, s);
     } else {
-        if (has_w) hipLaunchKernelGGL((alg1_tb_kernel<true, 1024, kPdrPptW>), dim3(grid), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((alg1_tb_kernel<false, 1024, kPdrPpt>), dim3(grid), dim3(1024), 0, s, a);
+        if (has_w) launch_alg1_shape<true, 1024, kPdrPptW>(a, grid, s);
+        else launch_alg1_shape<false, 1024, kPdrPpt>(a, grid, s);
     }
 }
 

@@ -10,6 +10,12 @@
 // its own a~ slots and energy partials, every tile is computed by the same kernel instantiation, and
 // the K of a launch only decides how far a tile's halo is recomputed), so a pair's results are
 // bitwise the same alone or in any batch, for any stage choice.
+//
+// pDR and ALG1 (state X, X bar, y bar) take the same stages with their own tile kernels in table
+// order: 1024-thread tiles with one red and one black cell per thread (ALG1: its own tiles), the
+// plain path's built-in K per launch, or the whole warp in one launch where every level of the
+// stage fits one tile.  Every pDR tile shape and K computes each cell with the same expressions, so
+// a batched pDR pair is bitwise the plain pDR tile solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +47,8 @@ struct BStage {
     int lpw = 0;                        // tile launches per warp
     int tile_off = 0, ntiles = 0, grid = 0;
     int counter_off = 0;                // first counter of the stage's queue launches
+    bool pd = false;                    // pDR / ALG1 stage: tile kernels of that scheme, work-group code pd_nt
+    int pd_nt = 1024;
     BLaunch init;
     std::vector<BLaunch> lin;           // per warp
 };
@@ -59,6 +67,7 @@ struct BatchPlan {
     // device scalars (in BatchState::dyn): a~ slots, energy partials and sums, queue counters
     size_t at_off = 0, epart_off = 0, eout_off = 0, cnt_off = 0, dyn_bytes = 0;
     size_t descs_off = 0, tiles_off = 0;       // tile-kernel tables in BatchState::tab
+    size_t pdescs_off = 0;                     // pDR / ALG1 level descriptors in BatchState::tab
     BLaunch imp, exp;                          // import / export launches in BatchState::io
     size_t io_bytes = 0;
 };
@@ -150,14 +159,116 @@ std::string batch_key(int n, const flow_pair* pairs, const flow_params& p) {
     std::ostringstream o;
     o.precision(17);
     o << n << ";bo" << g_batch_order << ",bk" << g_batch_k << ",be" << g_batch_ew << ';' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
-      << p.intensity_scale << ',' << p.levels << ',' << p.warps << ',' << p.iters << ',' << p.storage << ';';
+      << p.intensity_scale << ',' << p.levels << ',' << p.warps << ',' << p.iters << ',' << p.storage << ','
+      << p.sigma << ',' << p.tau << ',' << p.gs_sweeps << ',' << p.alg1_tau << ',' << p.alg1_sigma << ';';
     for (int k = 0; k < n; ++k) o << pairs[k].H << 'x' << pairs[k].W << 'l' << pairs[k].levels << ',';
     return o.str();
+}
+
+// Tiles of pDR / ALG1 stage S for work-group code nt and K iterations per launch (levels that fit
+// one tile take one); false if some level takes no tiles.
+bool pd_stage_tiles(const BatchPlan& P, const BStage& S, const flow_params& p, int nt, int K,
+                    const std::vector<int>& desc_id, std::vector<TbTile>& out) {
+    const bool hw = p.beta > 0;
+    std::vector<PdrTbPlan> plans;
+    for (int k : S.pairs) {
+        const LevelPlanes& L = P.L[k][S.l];
+        plans.push_back(plan_pd_tiles(L.H, L.W, hw, pd_halo(p, std::min(K, 64)), K, 0, nt));
+        if (!plans.back().tb) return false;
+    }
+    for (size_t i = 0; i < S.pairs.size(); ++i) {
+        const int k = S.pairs[i];
+        const LevelPlanes& L = P.L[k][S.l];
+        const int th = plans[i].th, tw = plans[i].tw;
+        for (int y = 0; y < L.H; y += th)
+            for (int x = 0; x < L.W; x += tw) {
+                TbTile t;
+                t.level = desc_id[k * FLOW_MAX_LEVELS + S.l];
+                t.y0 = y;
+                t.x0 = x;
+                t.th = std::min(th, L.H - y);
+                t.tw = std::min(tw, L.W - x);
+                out.push_back(t);
+            }
+    }
+    return true;
+}
+
+// Every level of pDR / ALG1 stage S fits one tile of work-group code nt.
+bool pd_stage_resident(const BatchPlan& P, const BStage& S, bool hw, int nt) {
+    for (int k : S.pairs)
+        if ((int64_t)P.L[k][S.l].H * P.L[k][S.l].W > pdr_tb_capacity(hw, nt)) return false;
+    return true;
+}
+
+// Work-group codes a pDR / ALG1 stage may take: 1024 and 512 threads with one cell of each colour
+// per thread; pDR without the w block also 1024 and 512 threads with two.
+std::vector<int> pd_codes(const flow_params& p) {
+    if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513};
+    return {1024, 512};
+}
+
+// pDR / ALG1 stage: the tuned choice (work-group code and K) where one is recorded for the stage's
+// shapes and still fits, else 1024-thread tiles with the plain path's built-in K, lowered until
+// every level takes tiles (the whole warp in one launch where every level fits one tile).
+// Appends the stage's tiles; false if some level takes no tiles even at K = 1 (callers check
+// beforehand with pd_batch_tileable).
+bool plan_pd_stage(const BatchPlan& P, BStage& S, const flow_params& p, const std::vector<int>& desc_id,
+                   const std::map<std::string, StageChoice>& tuned, std::vector<TbTile>& tiles) {
+    const bool hw = p.beta > 0;
+    S.pd = true;
+    S.ch = StageChoice();
+    S.tile_off = (int)tiles.size();
+    auto it = tuned.find(S.key);
+    bool ok = false;
+    if (it != tuned.end()) {
+        const std::vector<int> codes = pd_codes(p);
+        if (std::find(codes.begin(), codes.end(), it->second.nt) != codes.end() &&
+            pd_stage_tiles(P, S, p, it->second.nt, it->second.K, desc_id, tiles)) {
+            S.ch = it->second;
+            ok = true;
+        } else {
+            tiles.resize(S.tile_off);
+        }
+    }
+    if (!ok) {
+        S.ch.nt = 1024;
+        S.ch.K = pd_stage_resident(P, S, hw, 1024) ? std::max(1, p.iters)
+                                                   : (p.scheme == FLOW_ALG1 ? kAlg1DefaultK : kPdrDefaultK);
+        for (;; --S.ch.K) {
+            if (pd_stage_tiles(P, S, p, 1024, S.ch.K, desc_id, tiles)) {
+                ok = true;
+                break;
+            }
+            tiles.resize(S.tile_off);
+            if (S.ch.K <= 1) break;
+        }
+        if (!ok) return false;
+    }
+    S.ch.order = ORDER_TABLE;
+    S.pd_nt = S.ch.nt;
+    S.lpw = launches_per_warp(p.iters, S.ch.K);
+    S.ntiles = (int)tiles.size() - S.tile_off;
+    S.grid = S.ntiles;
+    return true;
+}
+
+// Every level of every pair takes pDR / ALG1 tiles at one iteration per launch (with many sweeps
+// the pDR halo can outgrow a tile; such batches are solved as plain solves in turn).
+bool pd_batch_tileable(int n, const flow_pair* pairs, const flow_params& p) {
+    const bool hw = p.beta > 0;
+    for (int k = 0; k < n; ++k) {
+        const int lv = pairs[k].levels > 0 ? pairs[k].levels : p.levels;
+        for (auto& x : level_shapes(pairs[k].H, pairs[k].W, lv))
+            if (!plan_pd_tiles(x.first, x.second, hw, pd_halo(p, 1), 1, 0, 1024).tb) return false;
+    }
+    return true;
 }
 
 // Lays the pairs out in the batch arena and builds every table of the launch sequence.
 flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pairs, const flow_params& p) {
     const bool hw = p.beta > 0;
+    const bool pd = pd_state(p);
     const bool f16 = p.storage == FLOW_STORE_F16;
     std::unique_ptr<BatchPlan> P(new BatchPlan());
     P->key = batch_key(n, pairs, p);
@@ -216,6 +327,13 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 shapes.emplace_back(P->L[k][l].H, P->L[k][l].W);
             }
         S.key = stage_key(shapes, hw, p.iters);
+        if (pd) {
+            S.key = (p.scheme == FLOW_ALG1 ? std::string("a:") : "p" + std::to_string(p.gs_sweeps) + ":") + S.key;
+            if (!plan_pd_stage(*P, S, p, desc_id, B.tuned, tiles))
+                return fail(FLOW_E_INVAL, "a level of the batch takes no pDR / ALG1 tiles");
+            P->stages.push_back(S);
+            continue;
+        }
         auto it = B.tuned.find(S.key);
         S.ch = (it != B.tuned.end() && shapes_fit(shapes, hw, it->second.K, it->second.ew))
                    ? it->second : default_stage_choice(shapes, hw, p.iters);
@@ -255,11 +373,23 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
 
     // tables
     TableBuilder T;
-    std::vector<TbLevel> descs(2 * std::max(1, ndesc));
-    for (int k = 0; k < n; ++k)
-        for (int l = 0; l < P->levels[k]; ++l)
-            fill_tb_level(&descs[2 * desc_id[k * FLOW_MAX_LEVELS + l]], P->L[k][l], d_at + 2 * k);
-    P->descs_off = T.put(descs);
+    if (!pd) {
+        std::vector<TbLevel> descs(2 * std::max(1, ndesc));
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < P->levels[k]; ++l)
+                fill_tb_level(&descs[2 * desc_id[k * FLOW_MAX_LEVELS + l]], P->L[k][l], d_at + 2 * k);
+        P->descs_off = T.put(descs);
+    } else {
+        // direction d reads state set d and writes the other
+        std::vector<PdrTbLevel> descs(2 * std::max(1, ndesc));
+        PdrTbPlan one;
+        one.th = one.tw = 1;
+        for (int k = 0; k < n; ++k)
+            for (int l = 0; l < P->levels[k]; ++l)
+                for (int d = 0; d < 2; ++d)
+                    descs[2 * desc_id[k * FLOW_MAX_LEVELS + l] + d] = pdr_tb_args(P->L[k][l], p, one, d, 1).lvl;
+        P->pdescs_off = T.put(descs);
+    }
     P->tiles_off = T.put(tiles);
     // pyramid
     P->down.resize(P->lmax);
@@ -309,12 +439,24 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 ia.wc = hw ? level_flow(C, p, 0, cc) : nullptr;
                 ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
             }
-            ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
-            ia.set_flow[1] = L.U0[0];
-            ia.set_flow[2] = L.U0[1];
             int nz = 0;
-            for (int q = 3; q < 10; ++q)
-                if (L.st[0][q]) ia.zero[nz++] = L.st[0][q];
+            if (!pd) {
+                ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
+                ia.set_flow[1] = L.U0[0];
+                ia.set_flow[2] = L.U0[1];
+                for (int q = 3; q < 10; ++q)
+                    if (L.st[0][q]) ia.zero[nz++] = L.st[0][q];
+            } else {                     // X = X bar = the upsampled flow, y bar = 0, Theta = 0
+                ia.set_flow[0] = hw ? L.Xs[0][0] : nullptr;
+                ia.set_flow[1] = L.Xs[0][1];
+                ia.set_flow[2] = L.Xs[0][2];
+                ia.copy_flow[0] = hw ? L.Xbs[0][0] : nullptr;
+                ia.copy_flow[1] = L.Xbs[0][1];
+                ia.copy_flow[2] = L.Xbs[0][2];
+                for (int q = 0; q < 6; ++q)
+                    if (L.ybs[0][q]) ia.zero[nz++] = L.ybs[0][q];
+                ia.zero[nz++] = L.s_out;
+            }
             ia.nzero = nz;
             ia.clear_scalar = d_at + 2 * k;
             init.push_back(ia);
@@ -331,11 +473,20 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 LinArgs la{};
                 la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
                 la.I0lo = L.I0lo; la.I1lo = L.I1lo;
-                la.u0 = L.U0[0];
-                la.v0 = L.U0[1];
-                if (w > 0) {             // commit the previous warp's increment on the way
-                    la.pend_u = L.st[cur][1];
-                    la.pend_v = L.st[cur][2];
+                if (!pd) {
+                    la.u0 = L.U0[0];
+                    la.v0 = L.U0[1];
+                    if (w > 0) {         // commit the previous warp's increment on the way
+                        la.pend_u = L.st[cur][1];
+                        la.pend_v = L.st[cur][2];
+                    }
+                    la.zero_u = L.st[cur][1];
+                    la.zero_v = L.st[cur][2];
+                } else {                 // linearise around X; keep a copy of the point for I_t
+                    la.u0 = L.Xs[cur][1];
+                    la.v0 = L.Xs[cur][2];
+                    la.keep_u = L.U0[0];
+                    la.keep_v = L.U0[1];
                 }
                 la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
                 la.at = d_at + 2 * k + (w & 1);
@@ -344,8 +495,6 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
                 la.kappa = (float)p.intensity_scale;
                 la.beta = (float)p.beta;
                 la.rel = 1;
-                la.zero_u = L.st[cur][1];
-                la.zero_v = L.st[cur][2];
                 lin.push_back(la);
             }
             S.lin.push_back(T.launch(lin, lbl));
@@ -408,9 +557,11 @@ void fill_io(BatchState& B, int n, const flow_pair* pairs, const flow_params& p)
         const float off = p.storage == FLOW_STORE_F16 ? kFrameOffsetF16 : 0.f;
         ci[2 * k] = CopyArgs{q.I0, q.H, q.W, q.ld, L.I0, L.ld, off};
         ci[2 * k + 1] = CopyArgs{q.I1, q.H, q.W, q.ld, L.I1, L.ld, off};
-        // the flow is U0 plus the last warp's pending increment
-        ce[2 * k] = CopyArgs{L.U0[0], q.H, q.W, L.ld, q.u, q.ld_uv, 0.f, L.st[P.final_cur][1]};
-        ce[2 * k + 1] = CopyArgs{L.U0[1], q.H, q.W, L.ld, q.v, q.ld_uv, 0.f, L.st[P.final_cur][2]};
+        // the flow is U0 plus the last warp's pending increment (pDR / ALG1: X)
+        ce[2 * k] = CopyArgs{level_flow(L, p, 1, P.final_cur), q.H, q.W, L.ld, q.u, q.ld_uv, 0.f,
+                             level_inc(L, p, 1, P.final_cur)};
+        ce[2 * k + 1] = CopyArgs{level_flow(L, p, 2, P.final_cur), q.H, q.W, L.ld, q.v, q.ld_uv, 0.f,
+                                 level_inc(L, p, 2, P.final_cur)};
     }
 }
 
@@ -421,6 +572,23 @@ void run_b(BatchOp op, const char* base, const BLaunch& L, bool f16, hipStream_t
 // The tile launches of one warp of stage S (returns the state buffer after them).
 int enqueue_stage_iters(const BatchState& B, const BStage& S, const flow_params& p, int w, int cur, hipStream_t s) {
     const BatchPlan& P = *B.plan;
+    if (S.pd) {
+        PdrTbArgs a{};
+        pd_tile_scalars(a, p);
+        a.tiles = (const TbTile*)(B.tab.d + P.tiles_off) + S.tile_off;
+        a.ntiles = S.ntiles;
+        a.levels = (const PdrTbLevel*)(B.tab.d + P.pdescs_off);
+        int dir = cur;
+        for (int k = 0; k < p.iters;) {
+            a.K = std::min(S.ch.K, p.iters - k);
+            a.dir = dir;
+            if (p.scheme == FLOW_ALG1) launch_alg1_tb(a, p.beta > 0, S.pd_nt, s);
+            else launch_pdr_tb(a, p.beta > 0, S.pd_nt, s);
+            dir ^= 1;
+            k += a.K;
+        }
+        return dir;
+    }
     unsigned* counters = (unsigned*)(B.dyn.d + P.cnt_off) + S.counter_off + w * S.lpw * kNq;
     return enqueue_tile_warp((const TbTile*)(B.tab.d + P.tiles_off) + S.tile_off, S.ntiles, S.grid,
                              (const TbLevel*)(B.tab.d + P.descs_off), S.ch, p, w & 1, cur, counters, s);
@@ -483,8 +651,8 @@ extern "C" flow_status flow_solve_batched(flow_ctx* ctx, int32_t n, const flow_p
     if (n == 0) return FLOW_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    if (pd_state(*p) || p->tol > 0) {
-        // pDR, ALG1 and stopping tests: plain solves in turn
+    if (p->tol > 0 || (pd_state(*p) && !pd_batch_tileable(n, pairs, *p))) {
+        // stopping tests, and pDR with a halo no tile holds: plain solves in turn
         for (int32_t k = 0; k < n; ++k) {
             flow_params pk = *p;
             if (pairs[k].levels > 0) pk.levels = pairs[k].levels;
@@ -575,6 +743,7 @@ extern "C" flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const f
     if (st != FLOW_OK) return st;
     st = validate_pairs(n, pairs, *p);
     if (st != FLOW_OK) return st;
+    if (pd_state(*p)) return fail(FLOW_E_INVAL, "batched pDR and ALG1 stages take the built-in choice");
     if (level < 0 || level >= FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "level out of range");
     if (order != ORDER_TABLE && order != ORDER_QUEUE) return fail(FLOW_E_INVAL, "order: 0 table, 1 work queue");
     if (K < 1 || ew < 16 || ew > 512) return fail(FLOW_E_INVAL, "K must be >= 1 and ew in [16, 512]");
@@ -607,7 +776,8 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
     if (st != FLOW_OK) return st;
     st = validate_pairs(n, pairs, *p);
     if (st != FLOW_OK) return st;
-    if (n == 0 || pd_state(*p) || p->iters < 1) return FLOW_OK;
+    if (n == 0 || p->iters < 1) return FLOW_OK;
+    if (pd_state(*p) && !pd_batch_tileable(n, pairs, *p)) return FLOW_OK;   // plain solves in turn
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     st = prepare(ctx, n, pairs, *p);
@@ -639,6 +809,63 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
         if (st != FLOW_OK) break;
         run_b(BatchOp::LevelInit, tab, S.init, false, s);
         run_b(BatchOp::Linearize, tab, S.lin[0], f16, s);
+        if (S.pd) {
+            // pDR / ALG1: work-group code x K (pDR 1 .. 4, ALG1 the launch-count values up to 10),
+            // and the whole warp per launch where every level fits one tile of that code
+            std::vector<StageChoice> pc;
+            const std::vector<int> pks = p->scheme == FLOW_ALG1 ? launch_ks(p->iters, 1, 10) : std::vector<int>{1, 2, 3, 4};
+            for (int nt : pd_codes(*p)) {
+                std::vector<int> kk = pks;
+                if (pd_stage_resident(P, S, hw, nt)) kk.push_back(p->iters);
+                for (int K : kk) {
+                    StageChoice c;
+                    c.nt = nt;
+                    c.K = K;
+                    pc.push_back(c);
+                }
+            }
+            double pbest = 1e30;
+            StageChoice pbestc = S.ch;
+            for (const StageChoice& c : pc) {
+                std::vector<TbTile> tl;
+                if (!pd_stage_tiles(P, S, *p, c.nt, c.K, desc_id, tl)) continue;
+                st = tmp_tiles.ensure(sizeof(TbTile) * tl.size(), "tuning tiles");
+                if (st != FLOW_OK) break;
+                HIP_TRY(hipMemcpy(tmp_tiles.d, tl.data(), sizeof(TbTile) * tl.size(), hipMemcpyHostToDevice));
+                PdrTbArgs a{};
+                pd_tile_scalars(a, *p);
+                a.tiles = (const TbTile*)tmp_tiles.d;
+                a.ntiles = (int)tl.size();
+                a.levels = (const PdrTbLevel*)(tab + P.pdescs_off);
+                float best_ms = 1e30f;
+                for (int rep_i = 0; rep_i < 4; ++rep_i) {         // the first run is a warm-up
+                    HIP_TRY(hipEventRecord(e0, s));
+                    int dir = 0;
+                    for (int k = 0; k < p->iters;) {
+                        a.K = std::min(c.K, p->iters - k);
+                        a.dir = dir;
+                        if (p->scheme == FLOW_ALG1) launch_alg1_tb(a, hw, c.nt, s);
+                        else launch_pdr_tb(a, hw, c.nt, s);
+                        dir ^= 1;
+                        k += a.K;
+                    }
+                    HIP_TRY(hipEventRecord(e1, s));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep_i > 0) best_ms = std::min(best_ms, ms);
+                }
+                HIP_TRY(hipGetLastError());
+                if (best_ms < pbest) {
+                    pbest = best_ms;
+                    pbestc = c;
+                }
+            }
+            chosen[S.key] = pbestc;
+            rep << (&S == &P.stages.front() ? "" : ", ") << "{\"level\": " << S.l << ", \"pairs\": " << S.pairs.size()
+                << ", \"nt\": " << pbestc.nt << ", \"K\": " << pbestc.K << ", \"us_per_warp\": " << 1e3 * pbest << "}";
+            continue;
+        }
         std::vector<StageChoice> cands;
         const bool all_res = shapes_all_resident(stage_shapes(P, S), hw);
         const std::vector<int> ks = launch_ks(p->iters, 2, 10);

@@ -128,6 +128,12 @@ struct PdrTbArgs {
     int K, sweeps;                   // iterations of this launch; symmetric sweeps per iteration
     int th, tw, ntx, ntiles;         // output tiling
     float sigma, tau, stt, lam, beta;
+    // table order (batched pairs): with tiles set, work-groups take the ntiles entries of the tile
+    // table in XCD order (8 contiguous runs, one per XCD) and each entry names its level descriptor
+    // levels[2 * tile.level + dir]; lvl, th, tw and ntx are then unused
+    const TbTile* tiles;
+    const PdrTbLevel* levels;
+    int dir;
 };
 int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads; 2048 / 513: 1024 /
                                                           // 512 threads with two cells of each colour

@@ -26,6 +26,7 @@ struct StageChoice {
     int K = 0;                   // iterations per tile launch (>= iters: the whole warp in one launch)
     int ew = 64;                 // extended tile width target
     int order = ORDER_TABLE;
+    int nt = 1024;               // pDR / ALG1 stages: tile work-group code (see pdr_tb_capacity)
 };
 
 // One multi-item launch of an elementwise body: items and block offsets at byte offsets of a table.

@@ -42,12 +42,11 @@ struct PdrLds {
 // NT threads, CPC cells of each colour per thread (ranks tid, tid + NT, ...): NC = NT * CPC cells of
 // each colour per tile.
 template <bool HAS_W, int NT, int CPC>
-__device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, int y0, int x0, int th, int tw,
+__device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, const PdrTbLevel& L, int y0, int x0, int th, int tw,
                                          PdrLds<HAS_W, NT * CPC>& S) {
     constexpr int NC = NT * CPC;
     constexpr int NX = PdrLds<HAS_W, NC>::NX;
     constexpr int NY = PdrLds<HAS_W, NC>::NY;
-    const PdrTbLevel& L = a.lvl;
     const int tid = threadIdx.x;
     const int H = L.H, W = L.W;
     const int64_t ld = L.ld;
@@ -302,28 +301,49 @@ __global__ __launch_bounds__(NT) void pdr_tb_kernel(PdrTbArgs a) {
     if (t >= a.ntiles) return;
     const int ty = t / a.ntx, tx = t - ty * a.ntx;
     const int y0 = ty * a.th, x0 = tx * a.tw;
-    pdr_tile<HAS_W, NT, CPC>(a, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+    pdr_tile<HAS_W, NT, CPC>(a, a.lvl, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+}
+
+// Many levels (batched pairs): tile entries of a table in XCD order; neighbouring tiles of a level,
+// which re-read each other's halo, share one XCD's L2.  The grid is a multiple of 8 of at least
+// ntiles.
+template <bool HAS_W, int NT, int CPC>
+__global__ __launch_bounds__(NT) void pdr_tb_table_kernel(PdrTbArgs a) {
+    __shared__ PdrLds<HAS_W, NT * CPC> S;
+    const int per = (a.ntiles + 7) >> 3;             // tiles per XCD
+    const int x = blockIdx.x & 7, y = blockIdx.x >> 3;
+    const int t = x * per + y;
+    if (y >= per || t >= a.ntiles) return;
+    const TbTile T = a.tiles[t];
+    pdr_tile<HAS_W, NT, CPC>(a, a.levels[2 * T.level + a.dir], T.y0, T.x0, T.th, T.tw, S);
 }
 
 }  // namespace
 
 
+template <bool HAS_W, int NT, int CPC>
+static void launch_pdr_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
+    if (a.tiles) hipLaunchKernelGGL((pdr_tb_table_kernel<HAS_W, NT, CPC>), dim3(grid), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((pdr_tb_kernel<HAS_W, NT, CPC>), dim3(grid), dim3(NT), 0, s, a);
+}
+
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
+    if (a.ntiles < 1) return;
     // two cells of each colour per thread exist for beta = 0 only (with the w block they would need
     // more than 128 VGPRs); the planners never pair them with w, and a tile sized for them must not
     // reach the other kernels' LDS
     if ((nt == 2048 || nt == 513) && has_w) return;
     if (nt == 512) {
-        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 512, 1>), dim3(grid), dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((pdr_tb_kernel<false, 512, 1>), dim3(grid), dim3(512), 0, s, a);
+        if (has_w) launch_pdr_shape<true, 512, 1>(a, grid, s);
+        else launch_pdr_shape<false, 512, 1>(a, grid, s);
     } else if (nt == 2048) {                 // 1024 threads, two cells of each colour per thread
-        hipLaunchKernelGGL((pdr_tb_kernel<false, 1024, 2>), dim3(grid), dim3(1024), 0, s, a);
+        launch_pdr_shape<false, 1024, 2>(a, grid, s);
     } else if (nt == 513) {                  // 512 threads, two cells of each colour per thread
-        hipLaunchKernelGGL((pdr_tb_kernel<false, 512, 2>), dim3(grid), dim3(512), 0, s, a);
+        launch_pdr_shape<false, 512, 2>(a, grid, s);
     } else {
-        if (has_w) hipLaunchKernelGGL((pdr_tb_kernel<true, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((pdr_tb_kernel<false, 1024, 1>), dim3(grid), dim3(1024), 0, s, a);
+        if (has_w) launch_pdr_shape<true, 1024, 1>(a, grid, s);
+        else launch_pdr_shape<false, 1024, 1>(a, grid, s);
     }
 }
 

@@ -373,8 +373,6 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
 int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512,
                       // 10 / 11 tiles of 1024 / 512 threads with two cells of each colour per thread (beta = 0)
 int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
-constexpr int kPdrDefaultK = 2;
-constexpr int kAlg1DefaultK = 4;
 
 std::string pd_tune_key(int H, int W, const flow_params& p) {
     const std::string k = tune_key(H, W, p.beta > 0, p.iters);
@@ -430,10 +428,15 @@ PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPla
     a.lvl.s_out = L.s_out;
     a.lvl.H = L.H; a.lvl.W = L.W; a.lvl.ld = L.ld;
     a.K = K;
-    a.sweeps = p.gs_sweeps;
     a.th = T.th; a.tw = T.tw;
     a.ntx = (L.W + T.tw - 1) / T.tw;
     a.ntiles = a.ntx * ((L.H + T.th - 1) / T.th);
+    pd_tile_scalars(a, p);
+    return a;
+}
+
+void pd_tile_scalars(PdrTbArgs& a, const flow_params& p) {
+    a.sweeps = p.gs_sweeps;
     if (p.scheme == FLOW_ALG1) {
         a.sigma = (float)p.alg1_sigma;
         a.tau = (float)p.alg1_tau;
@@ -442,7 +445,6 @@ PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPla
         a.sigma = (float)p.sigma; a.tau = (float)p.tau; a.stt = (float)(p.sigma * p.tau);
     }
     a.lam = (float)p.lambda; a.beta = (float)p.beta;
-    return a;
 }
 
 // `n` pDR or ALG1 iterations of level L on K-iteration tiles starting from state set `cur`; returns

@@ -174,6 +174,11 @@ int enqueue_pdr_tiles(const LevelPlanes& L, const flow_params& p, const PdrTbPla
                       hipStream_t s, int64_t* launches);
 PdrArgs pdr_args(const LevelPlanes& L, const flow_params& p, int cur);
 PdrTbArgs pdr_tb_args(const LevelPlanes& L, const flow_params& p, const PdrTbPlan& T, int cur, int K);
+// The scheme's scalars of a pDR / ALG1 tile launch (sweeps, steps, lambda, beta).
+void pd_tile_scalars(PdrTbArgs& a, const flow_params& p);
+// Built-in iterations per pDR / ALG1 tile launch.
+constexpr int kPdrDefaultK = 2;
+constexpr int kAlg1DefaultK = 4;
 void enqueue_pdr_iter(const PdrArgs& a, int sweeps, bool hw, hipStream_t s);
 int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTbPlan* P, int rows_hint, int cur,
                        int64_t n, int at_slot, const float* at2, hipStream_t s, int64_t* launches = nullptr);

@@ -455,40 +455,60 @@ void launch_admm_tb(const TbArgs& a, bool, int nt, int grid, hipStream_t s) {
     });
 }
 // every tile's extended region fits the work-group shape it is launched with (the real kernels
-// index LDS by the region's cells), and the large pDR tiles run without the w block only
-static void check_pd_tiles(const PdrTbArgs& a, bool has_w, int nt, int halo) {
+// index LDS by the region's cells), and the tiles with two cells of each colour run without the w
+// block only
+static void check_pd_codes(bool has_w, int nt) {
     check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513, "pDR / ALG1 tile launch: work-group code");
     check((nt != 2048 && nt != 513) || !has_w, "pDR tiles with two cells of each colour launched with w");
-    const int64_t eh = std::min<int64_t>(a.lvl.H, (int64_t)a.th + halo);
-    const int64_t ew = std::min<int64_t>(a.lvl.W, (int64_t)a.tw + halo);
+}
+static void check_pd_region(const PdrTbLevel& L, int th, int tw, bool has_w, int nt, int halo) {
+    const int64_t eh = std::min<int64_t>(L.H, (int64_t)th + halo);
+    const int64_t ew = std::min<int64_t>(L.W, (int64_t)tw + halo);
     check(eh * ew <= pdr_tb_capacity(has_w, nt), "pDR / ALG1 tile region above the kernel's capacity");
 }
-static void toy_pd_tiles(const PdrTbArgs& a, hipStream_t s) {
+// toy iteration: X += K on the tile's output cells, X bar and y bar copied, Theta = I_t
+static void toy_pd_region(const PdrTbLevel& L, int K, int y0, int x0, int th, int tw) {
+    for (int i = y0; i < y0 + th; ++i)
+        for (int j = x0; j < x0 + tw; ++j) {
+            const int64_t o = (int64_t)i * L.ld + j;
+            for (int f = 0; f < 3; ++f)
+                if (L.x_in[f]) {
+                    stf(L.x_out[f], o, ldf(L.x_in[f], o) + (float)K);
+                    stf(L.xb_out[f], o, ldf(L.xb_in[f], o));
+                }
+            for (int f = 0; f < 6; ++f)
+                if (L.y_in[f]) stf(L.y_out[f], o, ldf(L.y_in[f], o));
+            stf(L.s_out, o, ldf(L.It, o));
+        }
+}
+static void launch_pd(const PdrTbArgs& a, bool has_w, int nt, int halo, hipStream_t s) {
+    check_pd_codes(has_w, nt);
+    check(a.K > 0 && a.ntiles > 0, "pDR / ALG1 tile launch without tiles or iterations");
     ++g_launches;
-    enqueue(s, [=] {
-        const PdrTbLevel& L = a.lvl;
-        for (int i = 0; i < L.H; ++i)
-            for (int j = 0; j < L.W; ++j) {
-                const int64_t o = (int64_t)i * L.ld + j;
-                for (int f = 0; f < 3; ++f)
-                    if (L.x_in[f]) {
-                        stf(L.x_out[f], o, ldf(L.x_in[f], o) + (float)a.K);
-                        stf(L.xb_out[f], o, ldf(L.xb_in[f], o));
-                    }
-                for (int f = 0; f < 6; ++f)
-                    if (L.y_in[f]) stf(L.y_out[f], o, ldf(L.y_in[f], o));
-                stf(L.s_out, o, ldf(L.It, o));
-            }
+    if (!a.tiles) {                                      // direct: regular tiles of one level
+        check_pd_region(a.lvl, a.th, a.tw, has_w, nt, halo);
+        enqueue(s, [=] { toy_pd_region(a.lvl, a.K, 0, 0, a.lvl.H, a.lvl.W); });
+        return;
+    }
+    enqueue(s, [=] {                                     // table order: tile entries name their level
+        check(tracked(a.tiles, sizeof(TbTile) * a.ntiles), "pDR tile table outside device memory");
+        for (int t = 0; t < a.ntiles; ++t) {
+            const TbTile& T = a.tiles[t];
+            const PdrTbLevel* L = a.levels + 2 * T.level + a.dir;
+            check(tracked(L, sizeof(PdrTbLevel)), "pDR level descriptor outside device memory");
+            check(T.y0 >= 0 && T.x0 >= 0 && T.th >= 1 && T.tw >= 1 && T.y0 + T.th <= L->H && T.x0 + T.tw <= L->W,
+                  "pDR tile outside its level");
+            check_pd_region(*L, T.th, T.tw, has_w, nt, halo);
+            toy_pd_region(*L, a.K, T.y0, T.x0, T.th, T.tw);
+        }
     });
 }
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
-    check_pd_tiles(a, has_w, nt, pdr_halo_lo(a.sweeps, a.K) + pdr_halo_hi(a.sweeps, a.K));
-    toy_pd_tiles(a, s);
+    launch_pd(a, has_w, nt, pdr_halo_lo(a.sweeps, a.K) + pdr_halo_hi(a.sweeps, a.K), s);
 }
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     check(nt != 2048 && nt != 513, "pDR-only tiles launched for ALG1");
-    check_pd_tiles(a, has_w, nt, 2 * alg1_halo(a.K));
-    toy_pd_tiles(a, s);
+    launch_pd(a, has_w, nt, 2 * alg1_halo(a.K), s);
 }
 static void pdr_pass(const PdrArgs& a, bool final_pass) {
     float* x[3] = {a.w, a.u, a.v};

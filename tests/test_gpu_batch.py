@@ -148,13 +148,43 @@ def test_f16_storage_batch_matches_plain(ctx):
         assert same(out[k], (u, v, res)), f"pair {k}"
 
 
-def test_pdr_batch_runs_plain_solves(ctx):
-    print("[case] batched pdr", flush=True)
-    fr = frames(MIX[:2])
-    out = batched(ctx, fr, **KW, scheme="pdr")
+@pytest.mark.parametrize("scheme,beta", [("pdr", 0.0), ("pdr", 0.05), ("alg1", 0.0), ("alg1", 0.05)])
+def test_pd_batch_equals_plain_tile_solves(ctx, scheme, beta):
+    """Batched pDR and ALG1: stages of table-order tile launches over all pairs; every pair is
+    bitwise its plain tile solve (every tile shape and K computes a cell the same way), alone and in
+    a mix, direct and replayed from a graph."""
+    print(f"[case] batched {scheme} beta {beta}", flush=True)
+    fr = frames(MIX)
+    kw = dict(KW, scheme=scheme, beta=beta)
+    out = batched(ctx, fr, **kw)
+    rep = batched(ctx, fr, **dict(kw, use_graph=1))
     for k, (I0, I1, lv, d0, d1) in enumerate(fr):
-        u, v, res = ctx.solve(d0, d1, fm.Params(**dict(KW, levels=lv or KW["levels"], scheme="pdr")))
-        assert same(out[k], (u, v, res))
+        u, v, res = ctx.solve(d0, d1, fm.Params(**dict(kw, levels=lv or KW["levels"])))
+        assert same(out[k], (u, v, res)), f"pair {k}"
+        assert same(rep[k], (u, v, res)), f"pair {k} (graph)"
+    alone = batched(ctx, fr[3:4], **kw)
+    assert same(alone[0], out[3])
+    # stage choices measured by the batched autotuner (work-group shape and K per stage) change
+    # speed only
+    rep = ctx.autotune_batched([(d0, d1, lv) for _, _, lv, d0, d1 in fr], fm.Params(**kw))
+    assert len(rep["stages"]) == 3 and all(st["K"] >= 1 for st in rep["stages"])
+    tuned = batched(ctx, fr, **kw)
+    for a, b in zip(out, tuned):
+        assert same(a, b)
+
+
+def test_pd_batch_matches_the_oracle(ctx):
+    """Batched pDR pairs against the FP64 oracle under the parity bar."""
+    print("[case] batched pdr vs oracle", flush=True)
+    fr = frames(MIX[:3])
+    kw = dict(KW, scheme="pdr")
+    out = batched(ctx, fr, **kw)
+    jobs = [(I0, I1, dict(scheme="pdr", levels=lv or KW["levels"], warps=KW["warps"], iters=KW["iters"]))
+            for I0, I1, lv, _, _ in fr]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        refs = oracle_refs(jobs, pool)(900)
+    for k, ((u, v, res), ref) in enumerate(zip(out, refs)):
+        assert_parity(f"batched pdr pair {k}", to_np(u), to_np(v), res, ref, job=jobs[k])
 
 
 def test_invalid_pairs_are_rejected_before_anything_runs(ctx):
