@@ -225,8 +225,10 @@ flow_status flow_solve_static(const float* I0, const float* I1, int32_t H, int32
  * (*limit, = FLOW_STATIC_BYTES); either pointer may be NULL.  Host-only. */
 flow_status flow_static_bytes(int32_t H, int32_t W, const flow_params* p, uint64_t* need, uint64_t* limit);
 
-/* Create a serving engine on ctx's GPU for solves with parameters p (ADMM family, tol = 0; per-pair
- * pyramid depth from flow_pair.levels, else p->levels).  hbm_budget: bytes of device memory for
+/* Create a serving engine on ctx's GPU for solves with parameters p (any scheme, tol = 0, else
+ * FLOW_E_INVAL; per-pair pyramid depth from flow_pair.levels, else p->levels).  pDR and ALG1 epochs
+ * launch their tile kernels in table order directly; flow_server_submit refuses (FLOW_E_INVAL) a
+ * pDR pair with so many sweeps that its halo outgrows a tile at some level.  hbm_budget: bytes of device memory for
  * the working sets of the pairs in flight (0: 8 GiB), allocated once here; a few MB of tables come
  * on top.  max_active: most pairs in flight at once.  Every epoch runs on `stream` (hipStream_t).
  * ctx must outlive the engine.  FLOW_E_NOMEM if the budget cannot be allocated. */

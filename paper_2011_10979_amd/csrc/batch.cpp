@@ -256,12 +256,8 @@ bool plan_pd_stage(const BatchPlan& P, BStage& S, const flow_params& p, const st
 // Every level of every pair takes pDR / ALG1 tiles at one iteration per launch (with many sweeps
 // the pDR halo can outgrow a tile; such batches are solved as plain solves in turn).
 bool pd_batch_tileable(int n, const flow_pair* pairs, const flow_params& p) {
-    const bool hw = p.beta > 0;
-    for (int k = 0; k < n; ++k) {
-        const int lv = pairs[k].levels > 0 ? pairs[k].levels : p.levels;
-        for (auto& x : level_shapes(pairs[k].H, pairs[k].W, lv))
-            if (!plan_pd_tiles(x.first, x.second, hw, pd_halo(p, 1), 1, 0, 1024).tb) return false;
-    }
+    for (int k = 0; k < n; ++k)
+        if (!pd_pair_tileable(pairs[k].H, pairs[k].W, pairs[k].levels > 0 ? pairs[k].levels : p.levels, p)) return false;
     return true;
 }
 

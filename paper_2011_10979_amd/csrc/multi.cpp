@@ -127,6 +127,25 @@ int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* 
     return dir;
 }
 
+bool pd_pair_tileable(int H, int W, int levels, const flow_params& p) {
+    for (auto& x : level_shapes(H, W, levels))
+        if (!plan_pd_tiles(x.first, x.second, p.beta > 0, pd_halo(p, 1), 1, 0, 1024).tb) return false;
+    return true;
+}
+
+int pd_shared_k(const Shapes& s, const flow_params& p) {
+    const bool hw = p.beta > 0;
+    bool resident = true;
+    for (auto& x : s) resident = resident && (int64_t)x.first * x.second <= pdr_tb_capacity(hw, 1024);
+    if (resident) return std::max(1, p.iters);
+    for (int K = p.scheme == FLOW_ALG1 ? kAlg1DefaultK : kPdrDefaultK; K >= 1; --K) {
+        bool fits = true;
+        for (auto& x : s) fits = fits && plan_pd_tiles(x.first, x.second, hw, pd_halo(p, K), K, 0, 1024).tb;
+        if (fits) return K;
+    }
+    return 0;
+}
+
 flow_status validate_pair(const flow_pair& q, const flow_params& p, const std::string& who) {
     if (q.levels < 0 || q.levels > FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, who + "levels out of range");
     const int lv = q.levels > 0 ? q.levels : p.levels;

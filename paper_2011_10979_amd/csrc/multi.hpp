@@ -135,6 +135,13 @@ int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* 
                       const flow_params& p, int at_slot, int dir0, unsigned* counters, hipStream_t s,
                       const int* ntiles_dev = nullptr);
 int tile_grid(const StageChoice& ch, int ntiles);
+// pDR / ALG1: every level of an H x W pair with `levels` levels takes 1024-thread tiles at one
+// iteration per launch (with many sweeps the pDR halo can outgrow a tile).
+bool pd_pair_tileable(int H, int W, int levels, const flow_params& p);
+// pDR / ALG1 choice over levels of several pairs sharing K-iteration launches: 1024-thread tiles,
+// the whole warp per launch where every level fits one tile, else the plain path's built-in K
+// lowered until every level takes tiles (0 if none does).
+int pd_shared_k(const Shapes& s, const flow_params& p);
 // Checks of one caller pair (shape, pitches, device extents); `who` prefixes messages.
 flow_status validate_pair(const flow_pair& q, const flow_params& p, const std::string& who);
 

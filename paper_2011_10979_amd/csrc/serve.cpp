@@ -87,8 +87,9 @@ struct flow_server {
     // fixed offsets in an epoch's table: the tile count at 0, the level descriptors at kDescsAt
     // (room for two per pair in flight), the tiles at tiles_at()
     static constexpr size_t kDescsAt = 256;
+    static constexpr size_t kDescBytes = sizeof(TbLevel) > sizeof(PdrTbLevel) ? sizeof(TbLevel) : sizeof(PdrTbLevel);
     size_t tiles_at() const {
-        return (kDescsAt + sizeof(TbLevel) * 2 * (size_t)max_active + 255) & ~(size_t)255;
+        return (kDescsAt + kDescBytes * 2 * (size_t)max_active + 255) & ~(size_t)255;
     }
     hipStream_t cs = nullptr;      // capture stream (default priority)
     struct TileGraph {
@@ -332,18 +333,29 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         const LevelPlanes& L = reqs[t].L[reqs[t].l];
         shapes.emplace_back(L.H, L.W);
     }
-    StageChoice ch = default_stage_choice(shapes, hw, p.iters);
-    if (g_batch_order >= 0) ch.order = g_batch_order;
-    if (g_batch_ew > 0) ch.ew = g_batch_ew;
-    if (g_batch_k > 0) ch.K = g_batch_k;
-    ch = fit_stage_choice(ch, shapes, hw);
+    const bool pd = pd_state(p);
+    StageChoice ch;
+    if (!pd) {
+        ch = default_stage_choice(shapes, hw, p.iters);
+        if (g_batch_order >= 0) ch.order = g_batch_order;
+        if (g_batch_ew > 0) ch.ew = g_batch_ew;
+        if (g_batch_k > 0) ch.K = g_batch_k;
+        ch = fit_stage_choice(ch, shapes, hw);
+    } else {
+        // pDR / ALG1: 1024-thread tiles; every admitted pair's levels take tiles at K = 1 (submit
+        // checks it), so a K >= 1 exists
+        ch.K = pd_shared_k(shapes, p);
+        ch.nt = 1024;
+        if (ch.K < 1) return fail(FLOW_E_INVAL, "a served level takes no pDR / ALG1 tiles");
+    }
     const int lpw = launches_per_warp(p.iters, ch.K);
 
     std::vector<LevelInitArgs> init;
     std::vector<int> init_bl;
     std::vector<LinArgs> lin;
     std::vector<int> bl;
-    std::vector<TbLevel> descs(2 * active.size());
+    std::vector<TbLevel> descs(pd ? 0 : 2 * active.size());
+    std::vector<PdrTbLevel> pdescs(pd ? 2 * active.size() : 0);
     std::vector<TbTile> tiles;
     std::vector<EnergyArgs> en;
     std::vector<int> en_bl;
@@ -368,12 +380,24 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
                 ia.wc = hw ? level_flow(C, p, 0, q.cur_coarse) : nullptr;
                 ia.Hc = C.H; ia.Wc = C.W; ia.ldc = C.ld;
             }
-            ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
-            ia.set_flow[1] = L.U0[0];
-            ia.set_flow[2] = L.U0[1];
             int nz = 0;
-            for (int k = 3; k < 10; ++k)
-                if (L.st[0][k]) ia.zero[nz++] = L.st[0][k];
+            if (!pd) {
+                ia.set_flow[0] = hw ? L.st[0][0] : nullptr;
+                ia.set_flow[1] = L.U0[0];
+                ia.set_flow[2] = L.U0[1];
+                for (int k = 3; k < 10; ++k)
+                    if (L.st[0][k]) ia.zero[nz++] = L.st[0][k];
+            } else {                            // X = X bar = the upsampled flow, y bar = 0, Theta = 0
+                ia.set_flow[0] = hw ? L.Xs[0][0] : nullptr;
+                ia.set_flow[1] = L.Xs[0][1];
+                ia.set_flow[2] = L.Xs[0][2];
+                ia.copy_flow[0] = hw ? L.Xbs[0][0] : nullptr;
+                ia.copy_flow[1] = L.Xbs[0][1];
+                ia.copy_flow[2] = L.Xbs[0][2];
+                for (int k = 0; k < 6; ++k)
+                    if (L.ybs[0][k]) ia.zero[nz++] = L.ybs[0][k];
+                ia.zero[nz++] = L.s_out;
+            }
             ia.nzero = nz;
             ia.clear_scalar = at2;
             init.push_back(ia);
@@ -382,11 +406,20 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         LinArgs la{};
         la.I0 = L.I0; la.I1 = L.I1; la.Dx = L.Dx; la.Dy = L.Dy;
         la.I0lo = L.I0lo; la.I1lo = L.I1lo;
-        la.u0 = L.U0[0];
-        la.v0 = L.U0[1];
-        if (q.w > 0) {                          // commit the previous warp's increment on the way
-            la.pend_u = L.st[q.cur][1];
-            la.pend_v = L.st[q.cur][2];
+        if (!pd) {
+            la.u0 = L.U0[0];
+            la.v0 = L.U0[1];
+            if (q.w > 0) {                      // commit the previous warp's increment on the way
+                la.pend_u = L.st[q.cur][1];
+                la.pend_v = L.st[q.cur][2];
+            }
+            la.zero_u = L.st[q.cur][1];
+            la.zero_v = L.st[q.cur][2];
+        } else {                                // linearise around X; keep a copy of the point for I_t
+            la.u0 = L.Xs[q.cur][1];
+            la.v0 = L.Xs[q.cur][2];
+            la.keep_u = L.U0[0];
+            la.keep_v = L.U0[1];
         }
         la.Ix = L.Ix; la.Iy = L.Iy; la.It = L.It;
         la.at = at2 + (q.w & 1);
@@ -395,16 +428,26 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         la.kappa = (float)p.intensity_scale;
         la.beta = (float)p.beta;
         la.rel = 1;
-        la.zero_u = L.st[q.cur][1];
-        la.zero_v = L.st[q.cur][2];
         lin.push_back(la);
         bl.push_back(lin_blocks_of(L.H, L.W));
         // descriptors in the pair's own direction: launch direction 0 reads state buffer q.cur
-        TbLevel d[2];
-        fill_tb_level(d, L, at2 + (q.w & 1));
-        descs[2 * i] = d[q.cur];
-        descs[2 * i + 1] = d[q.cur ^ 1];
-        level_tiles(L.H, L.W, hw, ch, (int)i, tiles);
+        if (!pd) {
+            TbLevel d[2];
+            fill_tb_level(d, L, at2 + (q.w & 1));
+            descs[2 * i] = d[q.cur];
+            descs[2 * i + 1] = d[q.cur ^ 1];
+            level_tiles(L.H, L.W, hw, ch, (int)i, tiles);
+        } else {
+            PdrTbPlan one;
+            one.th = one.tw = 1;
+            pdescs[2 * i] = pdr_tb_args(L, p, one, q.cur, 1).lvl;
+            pdescs[2 * i + 1] = pdr_tb_args(L, p, one, q.cur ^ 1, 1).lvl;
+            const PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(p, std::min(ch.K, 64)), ch.K, 0, 1024);
+            if (!T.tb) return fail(FLOW_E_INVAL, "a served level takes no pDR / ALG1 tiles");
+            for (int y = 0; y < L.H; y += T.th)
+                for (int x = 0; x < L.W; x += T.tw)
+                    tiles.push_back(TbTile{(int)i, y, x, std::min(T.th, L.H - y), std::min(T.tw, L.W - x)});
+        }
         const int after = q.cur ^ (lpw & 1);
         if (l == 0 && q.w == p.warps - 1) {
             EnergyArgs e = energy_args(L, p, after, none);
@@ -412,8 +455,10 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
             e.out = d_eout + (size_t)q.slot * kEnergyTerms;
             en.push_back(e);
             en_bl.push_back(energy_blocks(L.H, L.W));
-            exp.push_back(CopyArgs{L.U0[0], L.H, L.W, L.ld, q.q.u, q.q.ld_uv, 0.f, L.st[after][1]});
-            exp.push_back(CopyArgs{L.U0[1], L.H, L.W, L.ld, q.q.v, q.q.ld_uv, 0.f, L.st[after][2]});
+            exp.push_back(CopyArgs{level_flow(L, p, 1, after), L.H, L.W, L.ld, q.q.u, q.q.ld_uv, 0.f,
+                                   level_inc(L, p, 1, after)});
+            exp.push_back(CopyArgs{level_flow(L, p, 2, after), L.H, L.W, L.ld, q.q.v, q.q.ld_uv, 0.f,
+                                   level_inc(L, p, 2, after)});
             exp_bl.push_back(blocks_of(L.H, L.W));
             exp_bl.push_back(blocks_of(L.H, L.W));
             finishing.push_back(active[i]);
@@ -427,7 +472,8 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
     TableBuilder T;
     T.h.assign(tiles_at(), 0);
     std::memcpy(T.h.data(), &ntiles, sizeof(int));
-    std::memcpy(T.h.data() + kDescsAt, descs.data(), sizeof(TbLevel) * descs.size());
+    if (!pd) std::memcpy(T.h.data() + kDescsAt, descs.data(), sizeof(TbLevel) * descs.size());
+    else std::memcpy(T.h.data() + kDescsAt, pdescs.data(), sizeof(PdrTbLevel) * pdescs.size());
     const size_t tiles_off = T.put(tiles);
     const BLaunch l_imp = T.launch(imp, imp_bl);
     std::vector<BLaunch> l_down(std::max(1, lmax_new));
@@ -458,8 +504,26 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
     run_items(BatchOp::Derivatives, tb, l_der, f16, s);
     run_items(BatchOp::LevelInit, tb, l_init, false, s);
     run_items(BatchOp::Linearize, tb, l_lin, f16, s);
-    r = tile_launches(b, ch, ntiles, lpw, d_cnt);
-    if (r != FLOW_OK) return r;
+    if (!pd) {
+        r = tile_launches(b, ch, ntiles, lpw, d_cnt);
+        if (r != FLOW_OK) return r;
+    } else if (ntiles > 0) {
+        // pDR / ALG1 tile launches, direct: direction 0 reads each pair's current state buffer
+        PdrTbArgs a{};
+        pd_tile_scalars(a, p);
+        a.tiles = (const TbTile*)(tb + tiles_at());
+        a.ntiles = ntiles;
+        a.levels = (const PdrTbLevel*)(tb + kDescsAt);
+        int dir = 0;
+        for (int k = 0; k < p.iters;) {
+            a.K = std::min(ch.K, p.iters - k);
+            a.dir = dir;
+            if (p.scheme == FLOW_ALG1) launch_alg1_tb(a, hw, ch.nt, s);
+            else launch_pdr_tb(a, hw, ch.nt, s);
+            dir ^= 1;
+            k += a.K;
+        }
+    }
     if (l_en.n > 0)
         launch_energy_batched((const EnergyArgs*)(tb + l_en.items), (const int*)(tb + l_en.off), l_en.n, l_en.total, s);
     run_items(BatchOp::Copy, tb, l_exp, false, s);
@@ -500,7 +564,6 @@ flow_status flow_server_create(flow_ctx* ctx, const flow_params* p, size_t hbm_b
     *out = nullptr;
     flow_status r = validate(p);
     if (r != FLOW_OK) return r;
-    if (pd_state(*p)) return fail(FLOW_E_INVAL, "the serving engine runs the ADMM family (pADMM, rpADMMII)");
     if (p->tol > 0) return fail(FLOW_E_INVAL, "the serving engine runs a fixed iteration count (tol = 0)");
     if (max_active < 1 || max_active > 4096) return fail(FLOW_E_INVAL, "max_active must be in [1, 4096]");
     if (hbm_budget == 0) hbm_budget = (size_t)8 << 30;
@@ -543,6 +606,8 @@ flow_status flow_server_submit(flow_server* srv, const flow_pair* pair, uint64_t
     q.levels = pair->levels > 0 ? pair->levels : srv->p.levels;
     flow_params pk = srv->p;
     pk.levels = q.levels;
+    if (pd_state(pk) && !pd_pair_tileable(pair->H, pair->W, q.levels, pk))
+        return fail(FLOW_E_INVAL, "the pDR halo of this many sweeps outgrows a tile at some level of the pair");
     q.bytes = (layout_bytes(pair->H, pair->W, pk) + 255) & ~(size_t)255;
     if (q.bytes > srv->arena.bytes)
         return fail(FLOW_E_NOMEM, "pair working set of " + std::to_string(q.bytes) + " bytes exceeds the serving budget");

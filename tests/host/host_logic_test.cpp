@@ -429,7 +429,8 @@ static void test_pd_solves(std::mt19937& rng) {
     flow_destroy(ctx);
 }
 
-// Batched pDR and ALG1: every pair of random subsets equals its plain tile solve, bit for bit
+// Batched and served pDR and ALG1: every pair of random subsets, and every served pair, equals its
+// plain tile solve, bit for bit
 static void test_pd_batches(std::mt19937& rng) {
     flow_ctx* ctx = nullptr;
     OK(flow_create(&ctx, 0, 0));
@@ -488,6 +489,30 @@ static void test_pd_batches(std::mt19937& rng) {
                           scheme == FLOW_PDR ? "pDR" : "ALG1", idx[i], beta, round);
                 for (float* b : bufs) hipFree(b);
             }
+            // served: submit, step and poll in a random order; every result equals the plain solve
+            flow_server* srv = nullptr;
+            OK(flow_server_create(ctx, &p, (size_t)64 << 20, 1 + (int)(rng() % 3), nullptr, &srv));
+            std::vector<uint64_t> tk(fs.size());
+            std::vector<flow_result> rs(fs.size());
+            std::vector<float*> us(fs.size()), vs(fs.size());
+            for (size_t k = 0; k < fs.size(); ++k) {
+                hipMalloc(&us[k], sizeof(float) * fs[k].H * fs[k].W);
+                hipMalloc(&vs[k], sizeof(float) * fs[k].H * fs[k].W);
+                flow_pair q{fs[k].I0, fs[k].I1, fs[k].H, fs[k].W, fs[k].W, us[k], vs[k], fs[k].W, &rs[k], fs[k].levels};
+                OK(flow_server_submit(srv, &q, &tk[k]));
+                for (int st = (int)(rng() % 3); st > 0; --st) OK(flow_server_step(srv, nullptr, nullptr));
+            }
+            OK(flow_server_drain(srv));
+            for (size_t k = 0; k < fs.size(); ++k) {
+                int32_t done = 0;
+                OK(flow_server_poll(srv, tk[k], &done));
+                CHECK(done == 1 && read_out(fs[k], us[k], vs[k], rs[k]) == ref[k],
+                      "served %s pair %zu (beta %g) differs from its plain solve", scheme == FLOW_PDR ? "pDR" : "ALG1",
+                      k, beta);
+                hipFree(us[k]);
+                hipFree(vs[k]);
+            }
+            OK(flow_server_destroy(srv));
         }
     for (auto& f : fs) {
         hipFree(f.I0);

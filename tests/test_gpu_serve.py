@@ -2,8 +2,8 @@
 admitted pair advanced one warp per epoch in shared launches.
 
 Checks: a served pair's results are bitwise the same alone, in a mix that changes while it runs, and
-as a batched solve; the budget and slot limits hold; served flows match the FP64 oracle; bad
-requests are refused; a pair with a non-finite frame is reported once and leaves the others
+as a batched solve (pDR and ALG1: as the plain tile solve); the budget and slot limits hold; served
+flows match the FP64 oracle; bad requests are refused; a pair with a non-finite frame is reported once and leaves the others
 untouched.
 """
 import multiprocessing as mp
@@ -178,7 +178,45 @@ def test_bad_requests_are_refused(ctx, frames):
     assert np.isfinite(out[0][2]["energy"])
     srv.close()
     with pytest.raises(fm.FlowError):
-        fm.Server(ctx, fm.Params(**dict(KW, scheme="pdr")))
+        fm.Server(ctx, fm.Params(**dict(KW, tol=1e-3)))                  # fixed iteration counts only
+    srv = fm.Server(ctx, fm.Params(**dict(KW, scheme="pdr", gs_sweeps=40)), budget_bytes=64 << 20)
+    with pytest.raises(fm.FlowError, match="halo"):                        # no tile holds this halo
+        srv.submit(frames[3][3], frames[3][4], frames[3][2])
+    srv.close()
+
+
+@pytest.mark.parametrize("scheme,beta", [("pdr", 0.0), ("pdr", 0.05), ("alg1", 0.0), ("alg1", 0.05)])
+def test_served_pd_pairs_equal_their_plain_solves(ctx, frames, scheme, beta):
+    """pDR and ALG1 served in a mix that changes while they run (pairs at different levels share the
+    table-order tile launches): every result is bitwise the plain tile solve of the pair."""
+    print(f"[case] serve {scheme} beta {beta}", flush=True)
+    kw = dict(KW, scheme=scheme, beta=beta)
+    srv = fm.Server(ctx, fm.Params(**kw), budget_bytes=64 << 20, max_active=4)
+    tick = {}
+    for k in range(len(frames)):
+        tick[k] = srv.submit(frames[k][3], frames[k][4], frames[k][2])
+        srv.step()
+    out = serve_all(srv, tick)
+    srv.close()
+    for k, (I0, I1, lv, d0, d1) in enumerate(frames):
+        ref = ctx.solve(d0, d1, fm.Params(**dict(kw, levels=lv or KW["levels"])))
+        assert same(out[k], ref), f"pair {k}"
+
+
+def test_served_pdr_flows_match_the_oracle(ctx, frames):
+    print("[case] serve pdr vs oracle", flush=True)
+    kw = dict(KW, scheme="pdr")
+    srv = fm.Server(ctx, fm.Params(**kw), budget_bytes=64 << 20, max_active=8)
+    tick = {k: srv.submit(frames[k][3], frames[k][4], frames[k][2]) for k in (0, 2, 5)}
+    out = serve_all(srv, tick)
+    srv.close()
+    jobs = {k: (frames[k][0], frames[k][1], dict(scheme="pdr", levels=frames[k][2] or KW["levels"], warps=KW["warps"],
+                                                 iters=KW["iters"])) for k in tick}
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        refs = oracle_refs(list(jobs.values()), pool)(900)
+    for (k, job), ref in zip(jobs.items(), refs):
+        u, v, res = out[k]
+        assert_parity(f"served pdr pair {k}", to_np(u), to_np(v), res, ref, job=job)
 
 
 def test_non_finite_pair_is_reported_and_leaves_the_others_untouched(ctx, frames):
