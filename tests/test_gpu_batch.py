@@ -148,14 +148,15 @@ def test_f16_storage_batch_matches_plain(ctx):
         assert same(out[k], (u, v, res)), f"pair {k}"
 
 
-@pytest.mark.parametrize("scheme,beta", [("pdr", 0.0), ("pdr", 0.05), ("alg1", 0.0), ("alg1", 0.05)])
-def test_pd_batch_equals_plain_tile_solves(ctx, scheme, beta):
+@pytest.mark.parametrize("scheme,beta,storage", [("pdr", 0.0, "f32"), ("pdr", 0.05, "f32"), ("alg1", 0.0, "f32"),
+                                                 ("alg1", 0.05, "f32"), ("pdr", 0.0, "f16")])
+def test_pd_batch_equals_plain_tile_solves(ctx, scheme, beta, storage):
     """Batched pDR and ALG1: stages of table-order tile launches over all pairs; every pair is
     bitwise its plain tile solve (every tile shape and K computes a cell the same way), alone and in
     a mix, direct and replayed from a graph."""
-    print(f"[case] batched {scheme} beta {beta}", flush=True)
+    print(f"[case] batched {scheme} beta {beta} {storage}", flush=True)
     fr = frames(MIX)
-    kw = dict(KW, scheme=scheme, beta=beta)
+    kw = dict(KW, scheme=scheme, beta=beta, storage=storage)
     out = batched(ctx, fr, **kw)
     rep = batched(ctx, fr, **dict(kw, use_graph=1))
     for k, (I0, I1, lv, d0, d1) in enumerate(fr):
