@@ -216,17 +216,17 @@ def _oracle_check(job):
 def batch_sha():
     """Hash of the batched path's tile kernel and of the sources that plan its tiles."""
     h = hashlib.sha256()
-    for f in ("admm_tb.hip", "admm_args.hpp", "tb_plan.cpp", "multi.cpp", "geometry.cpp"):
+    for f in ("admm_tb.hip", "admm_rows.hip", "admm_args.hpp", "tb_plan.cpp", "multi.cpp", "geometry.cpp"):
         with open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def batch_traffic(signature, iters):
-    """DRAM bytes per launch of the batched tile kernel, averaged over one batched solve's launches,
-    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record of each stage (level, order, K,
-    width), when every stage of this run was measured on the current kernel and planner source
-    (else None).  A stage makes ceil(iters / K) launches per warp."""
+    """DRAM bytes per launch of a batched tile kernel, averaged over its launches in one batched
+    solve, from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE record of each of its stages (level,
+    order, tile code, K, width), when every such stage was measured on the current kernel and
+    planner source (else None).  A stage makes ceil(iters / K) launches per warp."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         e = json.load(open(path)).get("batch64")
@@ -234,10 +234,11 @@ def batch_traffic(signature, iters):
         return None
     if not e or e.get("kernel_sha") != batch_sha() or not isinstance(signature, list):
         return None
-    rec = {(m["level"], m["order"], m["K"], m["ew"]): m["bytes_per_launch"] for m in e.get("stages", [])}
+    rec = {(m["level"], m["order"], m.get("nt", 1025), m["K"], m["ew"]): m["bytes_per_launch"]
+           for m in e.get("stages", [])}
     tot = n = 0
-    for level, order, K, ew in signature:
-        b = rec.get((level, order, K, ew))
+    for level, order, nt, K, ew in signature:
+        b = rec.get((level, order, nt, K, ew))
         if b is None:
             return None
         launches = -(-iters // K)
@@ -294,7 +295,8 @@ def run_batch(args):
         with open(args.load_batch_tuning) as fh:
             tuning = json.load(fh)
         for st in tuning:
-            ctx.set_batched_stage(frames, st["level"], st["order"], st["K"], st["ew"], params)
+            order = st["nt"] if st.get("nt", 1025) != 1025 else st["order"]     # wave-row tiles: their code
+            ctx.set_batched_stage(frames, st["level"], order, st["K"], st["ew"], params)
         print(f"[bench] loaded batched stage choices: {tuning}", file=sys.stderr, flush=True)
     elif not args.no_autotune:
         t0 = time.perf_counter()
@@ -346,12 +348,31 @@ def run_batch(args):
                   "us_per_launch": round(1e3 * ms[l] / max(1, launches[l]), 2), "launches_per_step": launches[l] // reps}
                  for l in range(nl)]
     has_w = params.beta > 0
-    tile_ms = sum(ms)
-    tile_launches = sum(launches)
-    tile_pxi = sum(level_px[l] * iters[l] for l in range(nl))           # over `reps` solves
-    tile_px_launch = sum(level_px[l] * launches[l] for l in range(nl))
-    launch_s = tile_ms * 1e-3 / tile_launches
     pd = args.scheme in ("pdr", "alg1")
+    # the dominant kernel: the ADMM stages' tile kernel (general tiles from the table or from work
+    # queues, or wave-row tiles) that takes the most time, over the levels that run it
+    wt = "true" if has_w else "false"
+    by_level = {st["level"]: st for st in tuning} if (tuning and not pd) else {}
+
+    def kname(st):
+        nt = st.get("nt", 1025)
+        if nt in (2049, 3073, 4097):
+            return f"admm_rows_table_kernel<{wt}, 16, {(nt - 1) // 1024}>"
+        return f"admm_tb_{'queue' if st['order'] == 1 else 'table'}_kernel<{wt}, 1024, 2>"
+    if by_level:
+        groups = {}
+        for l in range(nl):
+            groups.setdefault(kname(by_level[l]), []).append(l)
+        kernel, sel = max(groups.items(), key=lambda kv: sum(ms[l] for l in kv[1]))
+    else:
+        sel = list(range(nl))
+        kernel = {"pdr": "pdr_tb_table_kernel", "alg1": "alg1_tb_table_kernel"}.get(
+            args.scheme, "batched ADMM tile kernels (built-in stage choices)")
+    tile_ms = sum(ms[l] for l in sel)
+    tile_launches = sum(launches[l] for l in sel)
+    tile_pxi = sum(level_px[l] * iters[l] for l in sel)                  # over `reps` solves
+    tile_px_launch = sum(level_px[l] * launches[l] for l in sel)
+    launch_s = tile_ms * 1e-3 / tile_launches
     per_iter = (PDR_TB_BYTES_PER_PX_ITER if pd else BYTES_PER_PX_ITER)[has_w]
     per_launch = (PDR_TB_BYTES_PER_PX_LAUNCH if pd else BYTES_PER_PX_LAUNCH)[has_w]
     alg_launch = per_iter * tile_pxi / tile_launches                     # algorithmic bytes per launch
@@ -359,15 +380,14 @@ def run_batch(args):
     if pd:                                                  # the DRAM record covers the ADMM batch only
         signature, traffic = "pDR / ALG1 stages", None
     else:
-        signature = [[st["level"], st["order"], st["K"], st["ew"]] for st in tuning] if tuning else "built-in"
+        signature = ([[l, by_level[l]["order"], by_level[l].get("nt", 1025), by_level[l]["K"], by_level[l]["ew"]]
+                      for l in sel] if by_level else "built-in")
         traffic = batch_traffic(signature, args.iters)
-    kernel = {"padmm": "admm_tb_table_kernel<false, 1024, 2>", "rpadmm2": "admm_tb_table_kernel<false, 1024, 2>",
-              "pdr": "pdr_tb_table_kernel", "alg1": "alg1_tb_table_kernel"}.get(args.scheme, "tile table kernel")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_source": ("looked up: profiles/traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE runs on this "
                                "kernel source and stage choice, copy-calibrated)") if traffic else None,
-            "kernel": f"{kernel} (batched K-iteration tile kernel, every stage)",
+            "kernel": f"{kernel} (batched K-iteration tile kernel, levels {sel})",
             "per_unit": f"{per_iter} B per pixel-iteration",
             "px_iter_per_launch": round(tile_pxi / tile_launches), "bytes_per_launch": round(alg_launch),
             "avg_launch_us": round(launch_s * 1e6, 3), "launches_per_step": tile_launches // reps,

@@ -261,10 +261,11 @@ flow_status flow_server_poll(flow_server* srv, uint64_t ticket, int32_t* done);
 flow_status flow_server_drain(flow_server* srv);
 flow_status flow_server_get_stats(const flow_server* srv, flow_server_stats* out);
 
-/* Batched autotuner: for each stage of this batch, time every tile-launch choice (table order or
- * per-XCD work queues; every K in [2, 10] that is the smallest for its number of launches per
- * warp, ceil(iters / n), or the whole warp where every level of the stage fits one tile; extended
- * tile width 64 or 128) over one warp's iterations, and keep the
+/* Batched autotuner: for each stage of this batch, time every tile-launch choice (the general tiles
+ * in table order or per-XCD work queues, and the wave-row tiles of 32 / 48 / 64 rows in table order;
+ * every K in [2, 10] that is the smallest for its number of launches per warp, ceil(iters / n), or
+ * the whole warp where every level of the stage fits one tile; extended tile width 64 or 128, 64 for
+ * the wave-row tiles) over one warp's iterations, and keep the
  * fastest for later flow_solve_batched calls on batches whose stage has the same level shapes.
  * The choice changes speed only (results are bitwise the same).  Runs the pipeline on the pairs'
  * frames; blocking. */
@@ -273,8 +274,11 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
 
 /* Set the stage choice of `level` for batches with this batch's stage shapes, as
  * flow_autotune_batched would (for reuse of a measured choice, e.g. the "stages" entries of its
- * report): order 0 tile table / 1 work queue, K iterations per tile launch (>= iters: the whole
- * warp in one launch), extended tile width ew in [16, 512].  The choice changes speed only.
+ * report): order 0 general tiles from the tile table / 1 general tiles from work queues / 2049,
+ * 3073 or 4097 wave-row tiles of 32 / 48 / 64 rows from the tile table (the report's "nt" where it
+ * is one of these), K iterations per tile launch (>= iters: the whole warp in one launch),
+ * extended tile width ew in [16, 512] (at most 64 for the wave-row tiles).  The choice changes
+ * speed only.
  * FLOW_E_INVAL if no pair has the level or one of its levels takes no tiles of that K and width.
  * Host-only. */
 flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
@@ -326,7 +330,8 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 stay resident for a whole warp, larger ones use the one-pass kernel), 1 one-pass
  *                 kernel only, 2 K-iteration tiles of 256 threads, 3 of 1024 threads, 4 / 7 / 6
  *                 small tiles (2 pixels per thread) of 1024 / 512 / 256 threads, 8 / 9 one-pixel
- *                 tiles of 1024 / 512 threads.
+ *                 tiles of 1024 / 512 threads, 12 / 13 / 14 wave-row tiles of 1024 threads (extended
+ *                 regions of at most 64 columns and 32 / 48 / 64 rows, every field in registers).
  *   "tb_k"        iterations per tile launch on levels that do not fit one tile (0 = 4).
  *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
  *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads, 10 large
@@ -337,6 +342,9 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *   "batch_k"     iterations per batched tile launch (0 = tuned / built-in; lowered where a level's
  *                 tiles cannot hold the halo).
  *   "batch_ew"    extended tile width target of batched tiles (0 = tuned / built-in, else 16..512).
+ *   "batch_nt"    ADMM tile kernel of every batched and served stage: 0 tuned / built-in, 1025 the
+ *                 general small tiles, 2049 / 3073 / 4097 the wave-row tiles (table order; a stage
+ *                 whose levels take none of them keeps the general tiles).
  *   "serve_graph" serving epochs: 1 (default) replay their tile launches from captured graphs, 0
  *                 launch them directly (the same kernels and results).
  * FLOW_E_INVAL for an unknown key or value.  Not thread-safe against concurrent solves. */

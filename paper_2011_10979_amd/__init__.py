@@ -270,7 +270,7 @@ class Context:
 
     def set_batched_stage(self, pairs, level, order, K, ew, params: Params | None = None, **kw):
         """Pin the stage choice of `level` for batches with these pairs' stage shapes (see
-        flow_tune_batched_stage)."""
+        flow_tune_batched_stage; `order` 0 table, 1 work queue, or a wave-row code 2049 / 3073 / 4097)."""
         _set_batched_stage(self, pairs, level, order, K, ew, params or Params(**kw))
 
     def set_choice(self, key: str, mode: int, K: int = 0, rows: int = 0):

@@ -78,9 +78,15 @@ struct TbArgs {
     int th, tw, ntx;
 };
 // nt: 256, 1024, or the small-tile codes 1025 / 513 / 257 (1024 / 512 / 256 threads, 2 pixels each;
-// 513 and 257 only with direct tiling)
+// 513 and 257 only with direct tiling), or the wave-row codes 2049 / 3073 / 4097 (1024 threads; an
+// extended region of at most 64 columns and 32 / 48 / 64 rows, held in registers one wavefront-wide
+// row per thread and row; direct or table order)
 int tb_capacity(bool has_w, int nt);
+bool is_rows_code(int nt);
+// an extended region of eh x ew pixels fits the tile kernel of work-group code nt
+bool tb_fits(bool has_w, int nt, int64_t eh, int64_t ew);
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s);
+void launch_admm_rows(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s);
 void launch_reset_u32(unsigned* p, int n, hipStream_t s);
 
 }  // namespace flowmi

@@ -202,7 +202,8 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                     const float t1y = fmaf(gd[0][j] - gown(0, k), cy[k], qown(1, k));
                     const float t2x = fmaf(gr[1][j] - gown(1, k), cx[k], qown(2, k));
                     const float t2y = fmaf(gd[1][j] - gown(1, k), cy[k], qown(3, k));
-                    const float nq = t1x * t1x + t1y * t1y + t2x * t2x + t2y * t2y;
+                    // sums of products as explicit FMA chains: every tile kernel rounds them alike
+                    const float nq = fmaf(t2y, t2y, fmaf(t2x, t2x, fmaf(t1y, t1y, t1x * t1x)));
                     // projection scale min(1, 1/|t|): the hardware reciprocal square root is at
                     // least 1 (or infinite) wherever |t| <= 1, so the min alone selects
                     const float sc = fminf(1.f, __builtin_amdgcn_rsqf(nq));
@@ -213,7 +214,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                     if constexpr (HAS_W) {
                         const float tpx = fmaf(gr[NG - 1][j] - gown(NG - 1, k), cx[k], qown(4, k));
                         const float tpy = fmaf(gd[NG - 1][j] - gown(NG - 1, k), cy[k], qown(5, k));
-                        const float np2 = tpx * tpx + tpy * tpy;
+                        const float np2 = fmaf(tpy, tpy, tpx * tpx);
                         const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
                         spx[e] = qo[4][k] = tpx * sp;
                         spy[e] = qo[5][k] = tpy * sp;
@@ -252,7 +253,7 @@ __device__ __forceinline__ void process_tile(const TbArgs& a, const TbTile& T, c
                     }
                     float sn = ss[k] + acc * inv_atc;
                     sn = __builtin_amdgcn_fmed3f(sn, -a.lam, a.lam);
-                    const float ms = a.cB * sn - a.cC * ss[k];
+                    const float ms = fmaf(a.cB, sn, -(a.cC * ss[k]));
                     du[k] = du[k] + a.cA * dn1 - Ix[k] * ms;
                     dv[k] = dv[k] + a.cA * dn2 - Iy[k] * ms;
                     if constexpr (HAS_W) ww[k] = ww[k] + a.cA * dnp - beta * ms;
@@ -418,6 +419,10 @@ static void launch_one(const TbArgs& a, int grid, hipStream_t s) {
 }
 
 void launch_admm_tb(const TbArgs& a, bool has_w, int nt, int grid, hipStream_t s) {
+    if (is_rows_code(nt)) {                     // direct or table order (callers never pass a queue)
+        if (!a.queue) launch_admm_rows(a, has_w, nt, grid, s);
+        return;
+    }
     if (!a.queue) grid = (grid + 7) / 8 * 8;     // direct / table order: the XCD remap wants a multiple of 8
     if (nt == 1024) {
         if (has_w) launch_one<true, 1024, kTbPptLW>(a, grid, s);

@@ -160,7 +160,7 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
         // iterations per launch: every launch pays a fixed cost (loads, stores, dispatch), so each
         // launch count matters (50 iterations: 7 launches at K = 8, 6 at K = 9, 5 at K = 10)
         const std::vector<int> ks = launch_ks(p->iters, 2, 16);
-        for (int mode : {2, 4, 3, 7, 6, 8, 9})
+        for (int mode : {2, 4, 3, 7, 6, 8, 9, 12, 13, 14})
             for (int K : ks)
                 for (int ew : {0, 32, 48, 64, 96}) {             // extended tile width (0: built-in)
                     LevelTbPlan P = plan_level(L.H, L.W, hw, p->iters, mode, K, ew);
@@ -235,8 +235,9 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
                                         int32_t pdr_sweeps, int32_t mode, int32_t K, int32_t rows) {
     if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
-    if (mode < 1 || mode > 11)
-        return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6..9 (tiles) or 5 / 10 / 11 (pDR tiles)");
+    if (mode < 1 || mode > 14)
+        return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6..9, 12..14 (tiles) or 5 / 10 / 11 "
+                                  "(pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
     if (mode == 1 && rows != 0 && rows != 2 && rows != 4 && rows != 8)
         return fail(FLOW_E_INVAL, "rows (one-pass strip height) must be 0, 2, 4 or 8");
@@ -248,8 +249,10 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
         return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads), 10 / 11 (the same "
                                   "with two cells of each colour per thread)");
     if (pdr_sweeps > 0 && mode >= 10 && has_w) return fail(FLOW_E_INVAL, "pDR modes 10 and 11 need beta = 0");
-    if (pdr_sweeps == 0 && (mode == 5 || mode >= 10)) return fail(FLOW_E_INVAL, "modes 5, 10 and 11 are pDR modes");
-    if (pdr_sweeps != 0 && mode > 6 && mode < 10) return fail(FLOW_E_INVAL, "modes 7, 8, 9 are ADMM modes");
+    if (pdr_sweeps == 0 && (mode == 5 || mode == 10 || mode == 11))
+        return fail(FLOW_E_INVAL, "modes 5, 10 and 11 are pDR modes");
+    if (pdr_sweeps != 0 && ((mode > 6 && mode < 10) || mode >= 12))
+        return fail(FLOW_E_INVAL, "modes 7, 8, 9, 12, 13 and 14 are ADMM modes");
     TunedChoice c;
     c.mode = mode;
     c.K = K;

@@ -111,6 +111,7 @@ size_t batch_bytes(const BatchState* b) { return b ? b->bytes() : 0; }
 int g_batch_order = -1;
 int g_batch_k = 0;
 int g_batch_ew = 0;
+int g_batch_nt = 0;
 
 namespace {
 
@@ -129,8 +130,8 @@ Shapes stage_shapes(const BatchPlan& P, const BStage& S) {
     return s;
 }
 
-bool stage_fits(const BatchPlan& P, const BStage& S, bool hw, int K, int ew) {
-    return shapes_fit(stage_shapes(P, S), hw, K, ew);
+bool stage_fits(const BatchPlan& P, const BStage& S, bool hw, int K, int ew, int nt) {
+    return shapes_fit(stage_shapes(P, S), hw, K, ew, nt);
 }
 
 void stage_tiles(const BatchPlan& P, const BStage& S, bool hw, const StageChoice& ch,
@@ -158,7 +159,7 @@ flow_status validate_pairs(int n, const flow_pair* pairs, const flow_params& p) 
 std::string batch_key(int n, const flow_pair* pairs, const flow_params& p) {
     std::ostringstream o;
     o.precision(17);
-    o << n << ";bo" << g_batch_order << ",bk" << g_batch_k << ",be" << g_batch_ew << ';' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
+    o << n << ";bo" << g_batch_order << ",bk" << g_batch_k << ",be" << g_batch_ew << ",bn" << g_batch_nt << ';' << p.scheme << ',' << p.lambda << ',' << p.beta << ',' << p.c << ',' << p.relax << ','
       << p.intensity_scale << ',' << p.levels << ',' << p.warps << ',' << p.iters << ',' << p.storage << ','
       << p.sigma << ',' << p.tau << ',' << p.gs_sweeps << ',' << p.alg1_tau << ',' << p.alg1_sigma << ';';
     for (int k = 0; k < n; ++k) o << pairs[k].H << 'x' << pairs[k].W << 'l' << pairs[k].levels << ',';
@@ -331,12 +332,13 @@ flow_status build_plan(flow_ctx* ctx, BatchState& B, int n, const flow_pair* pai
             continue;
         }
         auto it = B.tuned.find(S.key);
-        S.ch = (it != B.tuned.end() && shapes_fit(shapes, hw, it->second.K, it->second.ew))
+        S.ch = (it != B.tuned.end() && shapes_fit(shapes, hw, it->second.K, it->second.ew, it->second.tnt))
                    ? it->second : default_stage_choice(shapes, hw, p.iters);
         // process-wide overrides (tests and experiments); K is lowered until every level fits
         if (g_batch_order >= 0) S.ch.order = g_batch_order;
         if (g_batch_ew > 0) S.ch.ew = g_batch_ew;
         if (g_batch_k > 0) S.ch.K = g_batch_k;
+        if (g_batch_nt > 0) S.ch.tnt = g_batch_nt;
         S.ch = fit_stage_choice(S.ch, shapes, hw);
         S.lpw = launches_per_warp(p.iters, S.ch.K);
         S.tile_off = (int)tiles.size();
@@ -741,8 +743,11 @@ extern "C" flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const f
     if (st != FLOW_OK) return st;
     if (pd_state(*p)) return fail(FLOW_E_INVAL, "batched pDR and ALG1 stages take the built-in choice");
     if (level < 0 || level >= FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "level out of range");
-    if (order != ORDER_TABLE && order != ORDER_QUEUE) return fail(FLOW_E_INVAL, "order: 0 table, 1 work queue");
+    if (order != ORDER_TABLE && order != ORDER_QUEUE && !is_rows_code(order))
+        return fail(FLOW_E_INVAL, "order: 0 table, 1 work queue, or a wave-row code 2049 / 3073 / 4097 (table order)");
     if (K < 1 || ew < 16 || ew > 512) return fail(FLOW_E_INVAL, "K must be >= 1 and ew in [16, 512]");
+    const int nt = is_rows_code(order) ? order : kBatchNt;
+    if (is_rows_code(nt) && ew > kWave) return fail(FLOW_E_INVAL, "the wave-row tiles take ew <= 64");
     const bool hw = p->beta > 0;
     Shapes shapes;
     for (int32_t k = 0; k < n; ++k) {
@@ -750,13 +755,14 @@ extern "C" flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const f
         if (lv > level) shapes.push_back(level_shapes(pairs[k].H, pairs[k].W, lv)[level]);
     }
     if (shapes.empty()) return fail(FLOW_E_INVAL, "no pair of the batch has that level");
-    if (!shapes_fit(shapes, hw, K, ew))
+    if (!shapes_fit(shapes, hw, K, ew, nt))
         return fail(FLOW_E_INVAL, "a level of the stage takes no tiles of that K and width");
     BatchState& B = batch_of(ctx);
     StageChoice c;
-    c.order = order;
+    c.order = is_rows_code(order) ? ORDER_TABLE : order;
     c.K = K;
     c.ew = ew;
+    c.tnt = nt;
     B.tuned[stage_key(shapes, hw, p->iters)] = c;
     B.tune_epoch++;
     B.drop_graph();
@@ -862,26 +868,32 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
                 << ", \"nt\": " << pbestc.nt << ", \"K\": " << pbestc.K << ", \"us_per_warp\": " << 1e3 * pbest << "}";
             continue;
         }
+        // the general tiles in table and queue order, and the wave-row tiles (table order only)
         std::vector<StageChoice> cands;
-        const bool all_res = shapes_all_resident(stage_shapes(P, S), hw);
         const std::vector<int> ks = launch_ks(p->iters, 2, 10);
-        for (int order : {ORDER_TABLE, ORDER_QUEUE}) {
-            if (all_res) {
-                StageChoice c;
-                c.order = order;
-                c.K = p->iters;
-                cands.push_back(c);
-            }
-            for (int K : ks)
-                for (int ew : {64, 128})
-                    if (stage_fits(P, S, hw, K, ew)) {
-                        StageChoice c;
-                        c.order = order;
-                        c.K = K;
-                        c.ew = ew;
-                        cands.push_back(c);
+        for (int nt : {kBatchNt, 2049, 3073, 4097})
+            for (int order : {ORDER_TABLE, ORDER_QUEUE}) {
+                if (is_rows_code(nt) && order != ORDER_TABLE) continue;
+                if (shapes_all_resident(stage_shapes(P, S), hw, nt)) {
+                    StageChoice c;
+                    c.order = order;
+                    c.K = p->iters;
+                    c.tnt = nt;
+                    cands.push_back(c);
+                }
+                for (int K : ks)
+                    for (int ew : {64, 128}) {
+                        if (is_rows_code(nt) && ew > kWave) continue;
+                        if (stage_fits(P, S, hw, K, ew, nt)) {
+                            StageChoice c;
+                            c.order = order;
+                            c.K = K;
+                            c.ew = ew;
+                            c.tnt = nt;
+                            cands.push_back(c);
+                        }
                     }
-        }
+            }
         double best = 1e30;
         StageChoice bestc = S.ch;
         for (const StageChoice& c : cands) {
@@ -919,7 +931,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
                     } else {
                         a.nq = 1;
                     }
-                    launch_admm_tb(a, hw, kBatchNt, T.grid, s);
+                    launch_admm_tb(a, hw, c.tnt, T.grid, s);
                     cur ^= 1;
                     k += kk;
                 }
@@ -937,7 +949,7 @@ extern "C" flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flo
         }
         chosen[S.key] = bestc;
         rep << (&S == &P.stages.front() ? "" : ", ") << "{\"level\": " << S.l << ", \"pairs\": " << S.pairs.size()
-            << ", \"order\": " << bestc.order << ", \"K\": " << bestc.K << ", \"ew\": " << bestc.ew
+            << ", \"order\": " << bestc.order << ", \"nt\": " << bestc.tnt << ", \"K\": " << bestc.K << ", \"ew\": " << bestc.ew
             << ", \"us_per_warp\": " << 1e3 * best << "}";
     }
     rep << "]}";

@@ -27,7 +27,10 @@ AdmmGeometry admm_geometry(int H, int W, int rows_hint) {
     return g;
 }
 
+bool is_rows_code(int nt) { return nt == 2049 || nt == 3073 || nt == 4097; }
+
 int tb_capacity(bool has_w, int nt) {
+    if (is_rows_code(nt)) return nt - 1;          // 64 columns x 32, 48 or 64 rows
     if (nt == 1024) return 1024 * (has_w ? kTbPptLW : kTbPptL);
     if (nt == 1025) return 1024 * kTbPptSmall;   // 1024 threads, small tiles
     if (nt == 513) return 512 * kTbPptSmall;     // 512 threads, small tiles
@@ -35,6 +38,11 @@ int tb_capacity(bool has_w, int nt) {
     if (nt == 1026) return 1024;                  // 1024 threads, one pixel each
     if (nt == 514) return 512;                    // 512 threads, one pixel each
     return 256 * (has_w ? kTbPptW : kTbPpt);
+}
+
+bool tb_fits(bool has_w, int nt, int64_t eh, int64_t ew) {
+    if (is_rows_code(nt)) return ew <= kWave && eh * kWave <= nt - 1;
+    return eh * ew <= tb_capacity(has_w, nt);
 }
 
 // pDR / ALG1 tiles: work-group codes 512 / 1024 (one red and one black cell per thread), 2048 (1024

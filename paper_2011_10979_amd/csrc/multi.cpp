@@ -43,27 +43,32 @@ void PinnedBuf::release() {
     bytes = 0;
 }
 
-bool shapes_fit(const Shapes& s, bool hw, int K, int ew) {
+bool shapes_fit(const Shapes& s, bool hw, int K, int ew, int nt) {
     for (auto& x : s) {
-        const LevelTbPlan T = plan_tiles(x.first, x.second, hw, kBatchNt, std::min(K, 64), ew);
+        const LevelTbPlan T = plan_tiles(x.first, x.second, hw, nt, std::min(K, 64), ew);
         if (!T.tb) return false;
         if (!T.resident && T.K != K) return false;
     }
     return true;
 }
 
-bool shapes_all_resident(const Shapes& s, bool hw) {
+bool shapes_all_resident(const Shapes& s, bool hw, int nt) {
     for (auto& x : s)
-        if ((int64_t)x.first * x.second > tb_capacity(hw, kBatchNt)) return false;
+        if (!tb_fits(hw, nt, x.first, x.second)) return false;
     return true;
 }
 
 StageChoice fit_stage_choice(StageChoice c, const Shapes& s, bool hw) {
     if (c.K < 1) c.K = 1;
-    while (c.K > 1 && !shapes_fit(s, hw, c.K, c.ew)) --c.K;
-    if (!shapes_fit(s, hw, c.K, c.ew)) {
+    if (is_rows_code(c.tnt)) {
+        c.order = ORDER_TABLE;
+        if (c.ew > kWave) c.ew = kWave;
+        if (!shapes_fit(s, hw, 1, c.ew, c.tnt)) c.tnt = kBatchNt;
+    }
+    while (c.K > 1 && !shapes_fit(s, hw, c.K, c.ew, c.tnt)) --c.K;
+    if (!shapes_fit(s, hw, c.K, c.ew, c.tnt)) {
         c.ew = 64;
-        while (c.K > 1 && !shapes_fit(s, hw, c.K, c.ew)) --c.K;
+        while (c.K > 1 && !shapes_fit(s, hw, c.K, c.ew, c.tnt)) --c.K;
     }
     return c;
 }
@@ -72,18 +77,19 @@ StageChoice default_stage_choice(const Shapes& s, bool hw, int iters) {
     StageChoice c;
     c.order = ORDER_TABLE;
     c.ew = 64;
-    if (shapes_all_resident(s, hw)) {
+    if (shapes_all_resident(s, hw, c.tnt)) {
         c.K = std::max(1, iters);
         return c;
     }
     int64_t px = 0;
     for (auto& x : s) px += (int64_t)x.first * x.second;
-    c.K = px >= 300000 ? 5 : 8;
+    c.tnt = px >= 1000000 ? 3073 : 2049;
+    c.K = px >= 1000000 ? 9 : 8;
     return fit_stage_choice(c, s, hw);
 }
 
 void level_tiles(int H, int W, bool hw, const StageChoice& ch, int desc, std::vector<TbTile>& out) {
-    const LevelTbPlan T = plan_tiles(H, W, hw, kBatchNt, std::min(ch.K, 64), ch.ew);
+    const LevelTbPlan T = plan_tiles(H, W, hw, ch.tnt, std::min(ch.K, 64), ch.ew);
     append_tiles(T, desc, H, W, out);
 }
 
@@ -119,7 +125,7 @@ int enqueue_tile_warp(const TbTile* tiles, int ntiles, int grid, const TbLevel* 
             a.queue = nullptr;
             a.nq = 1;
         }
-        if (ntiles > 0 || ntiles_dev) launch_admm_tb(a, hw, kBatchNt, grid, s);
+        if (ntiles > 0 || ntiles_dev) launch_admm_tb(a, hw, ch.tnt, grid, s);
         dir ^= 1;
         k += kk;
         ++li;

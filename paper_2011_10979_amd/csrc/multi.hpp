@@ -17,7 +17,7 @@
 
 namespace flowmi {
 
-constexpr int kBatchNt = 1025;   // tile kernel instantiation of every multi-pair level (1024 threads, small tiles)
+constexpr int kBatchNt = 1025;   // general tile kernel of the multi-pair levels (1024 threads, small tiles)
 constexpr int kNq = 8;           // per-XCD sub-queues of the work-queue order
 
 enum { ORDER_TABLE = 0, ORDER_QUEUE = 1 };
@@ -27,6 +27,7 @@ struct StageChoice {
     int ew = 64;                 // extended tile width target
     int order = ORDER_TABLE;
     int nt = 1024;               // pDR / ALG1 stages: tile work-group code (see pdr_tb_capacity)
+    int tnt = kBatchNt;          // ADMM stages: tile work-group code (kBatchNt or a wave-row code, table order)
 };
 
 // One multi-item launch of an elementwise body: items and block offsets at byte offsets of a table.
@@ -115,14 +116,16 @@ inline int launches_per_warp(int iters, int K) { return iters <= 0 ? 0 : (iters 
 
 // Level shapes (H, W) that one tile launch covers.
 using Shapes = std::vector<std::pair<int, int>>;
-// Every shape takes tiles for exactly K iterations with width target ew (or fits one tile).
-bool shapes_fit(const Shapes& s, bool hw, int K, int ew);
-bool shapes_all_resident(const Shapes& s, bool hw);
-// Built-in choice: the whole warp in one launch where every level fits one tile; else 5 iterations
-// per launch when the levels hold enough pixels to fill the chip with tiles (many rounds of
-// work-groups, where the recomputed halo costs throughput), 8 otherwise.
+// Every shape takes tiles of ADMM tile code nt for exactly K iterations with width target ew (or
+// fits one tile).
+bool shapes_fit(const Shapes& s, bool hw, int K, int ew, int nt = kBatchNt);
+bool shapes_all_resident(const Shapes& s, bool hw, int nt = kBatchNt);
+// Built-in choice: the whole warp in one launch where every level fits one general tile; else
+// wave-row tiles, of 48 rows and 9 iterations per launch when the levels hold a million pixels or
+// more (many rounds of work-groups), of 32 rows and 8 iterations otherwise (more, shorter tiles).
 StageChoice default_stage_choice(const Shapes& s, bool hw, int iters);
-// Lower K (and fall back to width 64) until every shape fits.
+// Lower K (and fall back to width 64) until every shape fits; a wave-row code runs in table order,
+// and falls back to kBatchNt where a shape takes none of its tiles.
 StageChoice fit_stage_choice(StageChoice c, const Shapes& s, bool hw);
 // Tiles of one level for a choice, naming descriptor `desc`.
 void level_tiles(int H, int W, bool hw, const StageChoice& ch, int desc, std::vector<TbTile>& out);

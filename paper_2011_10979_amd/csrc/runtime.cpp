@@ -637,9 +637,10 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "tb_mode") == 0) {
-        if (value < 0 || value > 9 || value == 5)
+        if (value < 0 || value > 14 || value == 5 || value == 10 || value == 11)
             return fail(FLOW_E_INVAL, "tb_mode: 0 built-in, 1 one-pass, 2 tiles/256, 3 tiles/1024, 4 / 7 / 6 small "
-                                      "tiles of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads");
+                                      "tiles of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads, "
+                                      "12 / 13 / 14 wave-row tiles of 32 / 48 / 64 rows");
         g_tb_mode = (int)value;
         return FLOW_OK;
     }
@@ -674,6 +675,13 @@ flow_status flow_tune_set(const char* key, int64_t value) {
     if (std::strcmp(key, "serve_graph") == 0) {
         if (value != 0 && value != 1) return fail(FLOW_E_INVAL, "serve_graph: 0 direct launches, 1 graph replay");
         g_serve_graph = (int)value;
+        return FLOW_OK;
+    }
+    if (std::strcmp(key, "batch_nt") == 0) {
+        if (value != 0 && value != 1025 && !is_rows_code((int)value))
+            return fail(FLOW_E_INVAL, "batch_nt: 0 (tuned / built-in), 1025 (general tiles) or a wave-row code "
+                                      "2049 / 3073 / 4097");
+        g_batch_nt = (int)value;
         return FLOW_OK;
     }
     if (std::strcmp(key, "batch_ew") == 0) {
@@ -858,16 +866,18 @@ flow_status flow_op_admm_tb(const flow_admm_state* in, const flow_admm_state* ou
     if (!in->u0 || !in->v0) return fail(FLOW_E_INVAL, "the tile kernel runs the increment form: u0, v0 required");
     if (H < 2 || W < 2 || ld < W) return fail(FLOW_E_INVAL, "bad shape");
     if (threads != 256 && threads != 1024 && threads != 1025 && threads != 513 && threads != 257 && threads != 1026 &&
-        threads != 514)
-        return fail(FLOW_E_INVAL, "threads must be 256, 1024 or a small-tile code 1025 / 513 / 257 / 1026 / 514");
+        threads != 514 && !is_rows_code(threads))
+        return fail(FLOW_E_INVAL, "threads must be 256, 1024, a small-tile code 1025 / 513 / 257 / 1026 / 514 or a "
+                                  "wave-row code 2049 / 3073 / 4097");
     if (iters < 1 || tile_h < 1 || tile_w < 1) return fail(FLOW_E_INVAL, "iters, tile_h, tile_w must be >= 1");
     if (order < 0 || order > 3) return fail(FLOW_E_INVAL, "order must be 0, 1, 2 or 3");
     if ((threads == 513 || threads == 257 || threads == 1026 || threads == 514) && order != 0)
         return fail(FLOW_E_INVAL, "work-group codes 513, 257, 1026 and 514 run with direct tiling (order 0) only");
+    if (is_rows_code(threads) && order != 0 && order != 3)
+        return fail(FLOW_E_INVAL, "wave-row codes run with direct tiling or table order (0 or 3) only");
     const bool hw = p->beta > 0;
-    const int cap = tb_capacity(hw, threads);
     const int64_t halo = (int64_t)tb_halo_lo(iters) + tb_halo_hi(iters);
-    if (std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo) > cap)
+    if (!tb_fits(hw, threads, std::min<int64_t>(H, tile_h + halo), std::min<int64_t>(W, tile_w + halo)))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[10] = {in->w, in->u, in->v, in->px, in->py, in->q1x, in->q1y, in->q2x, in->q2y, in->s};
     float* outs[10] = {out->w, out->u, out->v, out->px, out->py, out->q1x, out->q1y, out->q2x, out->q2y, out->s};

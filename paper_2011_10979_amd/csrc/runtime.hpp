@@ -140,6 +140,7 @@ extern int g_tb_k;
 extern int g_batch_order;   // batched tile launches: -1 tuned / built-in, 0 table order, 1 work queue
 extern int g_batch_k;       // 0 tuned / built-in, else iterations per batched tile launch
 extern int g_batch_ew;      // 0 tuned / built-in, else extended tile width target
+extern int g_batch_nt;      // 0 tuned / built-in, else the ADMM tile code of every batched / served stage
 extern int g_serve_graph;   // 1 (default): serving epochs replay their tile launches from graphs
 LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int ew = 0);
 // Tiles of work-group size nt (256, 1024, 1025) for K iterations per launch with extended tiles about

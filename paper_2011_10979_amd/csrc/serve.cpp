@@ -96,7 +96,7 @@ struct flow_server {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
-    std::map<std::tuple<int, int, int, int, int>, TileGraph> graphs[2];   // (K, order, ew, launches, grid)
+    std::map<std::tuple<int, int, int, int, int, int>, TileGraph> graphs[2];   // (K, order, ew, code, launches, grid)
     void drop_graphs(int b);
     flow_status tile_launches(int b, const StageChoice& ch, int ntiles, int lpw, unsigned* d_cnt);
     Epoch ep[2];
@@ -169,7 +169,7 @@ flow_status flow_server::tile_launches(int b, const StageChoice& ch, int ntiles,
         grid = 64;
         while (grid < ntiles) grid *= 2;
     }
-    const auto key = std::make_tuple(ch.K, ch.order, ch.ew, lpw, grid);
+    const auto key = std::make_tuple(ch.K, ch.order, ch.ew, ch.tnt, lpw, grid);
     auto it = graphs[b].find(key);
     if (it == graphs[b].end()) {
         TileGraph g;
@@ -340,6 +340,7 @@ flow_status flow_server::step(int32_t* n_active, int32_t* n_queued) {
         if (g_batch_order >= 0) ch.order = g_batch_order;
         if (g_batch_ew > 0) ch.ew = g_batch_ew;
         if (g_batch_k > 0) ch.K = g_batch_k;
+        if (g_batch_nt > 0) ch.tnt = g_batch_nt;
         ch = fit_stage_choice(ch, shapes, hw);
     } else {
         // pDR / ALG1: 1024-thread tiles; every admitted pair's levels take tiles at K = 1 (submit

@@ -9,28 +9,30 @@
 namespace flowmi {
 
 int g_tb_mode = 0;   // 0 built-in, 1 one-pass only, 2 tiles of 256 threads, 3 of 1024, 4 / 7 / 6 small tiles
-                     // of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads
+                     // of 1024 / 512 / 256 threads, 8 / 9 one-pixel tiles of 1024 / 512 threads, 12 / 13 / 14
+                     // wave-row tiles of 32 / 48 / 64 rows
 int g_tb_k = 0;      // iterations per launch of tiled levels (0 = default)
 
 constexpr int kDefaultK = 4;
 
-static bool fit_tile(int H, int W, int cap, int K, int ew_target, int& th, int& tw) {
+static bool fit_tile(int H, int W, bool hw, int nt, int K, int ew_target, int& th, int& tw) {
     // output tile th x tw whose extended region (halo K + 1 and K per axis, clipped to the image) fits
     const int halo = tb_halo_lo(K) + tb_halo_hi(K);
+    const int cap = tb_capacity(hw, nt);
     const int ew = std::min(W, ew_target);
     tw = (ew >= W) ? W : ew - halo;
     const int ext_w = std::min(W, tw + halo);
     int eh = cap / ext_w;
+    if (is_rows_code(nt)) eh = std::min(eh, cap / kWave);  // wave-row tiles: rows of one wavefront
     th = (eh >= H) ? H : eh - halo;
     // tiles at least 8 wide, or as wide as a level narrower than that (no side halo then)
-    return (tw >= 8 || tw == W) && th >= 2 && (int64_t)std::min(W, tw + halo) * std::min(H, th + halo) <= cap;
+    return (tw >= 8 || tw == W) && th >= 2 && tb_fits(hw, nt, std::min(H, th + halo), std::min(W, tw + halo));
 }
 
 LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
     LevelTbPlan P;
-    const int cap = tb_capacity(hw, nt);
     P.nt = nt;
-    if ((int64_t)H * W <= cap) {                             // one tile covers the level, no halo
+    if (tb_fits(hw, nt, H, W)) {                             // one tile covers the level, no halo
         P.tb = true;
         P.resident = true;
         P.K = K;
@@ -38,14 +40,15 @@ LevelTbPlan plan_tiles(int H, int W, bool hw, int nt, int K, int ew_target) {
         P.tw = W;
         return P;
     }
-    if (ew_target <= 0)
-        ew_target = nt == 1024 ? (hw ? 80 : 96)
+    if (ew_target <= 0 || (is_rows_code(nt) && ew_target > kWave))
+        ew_target = is_rows_code(nt) ? kWave
+                  : nt == 1024 ? (hw ? 80 : 96)
                   : nt == 1025 ? 64
                   : (nt == 513 || nt == 257 || nt == 1026) ? 32
                   : nt == 514 ? 24
                   : (hw ? 32 : 48);
     int th = 0, tw = 0;
-    while (K > 0 && !fit_tile(H, W, cap, K, ew_target, th, tw)) --K;
+    while (K > 0 && !fit_tile(H, W, hw, nt, K, ew_target, th, tw)) --K;
     if (K < 1) return P;
     P.tb = true;
     P.K = K;
@@ -64,6 +67,9 @@ static int tb_wgs_per_cu(int nt, bool hw) {
     case 514: return 4;
     case 257: return hw ? 6 : 8;
     case 1024: return 1;             // 1024 threads, 3-4 pixels
+    case 2049: return 2;             // wave-row tiles of 1024 threads: 46 / 54 VGPRs
+    case 3073: return hw ? 1 : 2;    // 62 / 74
+    case 4097: return 1;             // 78 / 94
     default: return 3;               // 256 threads, 4-6 pixels
     }
 }
@@ -94,18 +100,25 @@ LevelTbPlan plan_level(int H, int W, bool hw, int iters, int mode, int kreq, int
     if (mode == 1 || iters < 2) return P;                    // one-pass kernel
     if (mode == 0) {
         // built-in choice: a level that fits one 1024-thread tile stays resident for a whole warp
-        // (one launch instead of `iters`); larger levels use the one-pass kernel
+        // (one launch instead of `iters`); larger levels take wave-row tiles, 48 rows high and 8
+        // iterations per launch from a million pixels on, else 32 rows and 10 iterations (more and
+        // shorter tiles for a level that fills fewer CUs); the one-pass kernel where neither fits
         if ((int64_t)H * W <= tb_capacity(hw, 1024)) {
             P.tb = P.resident = true;
             P.nt = 1024;
             P.K = iters;
             P.th = H;
             P.tw = W;
+            return P;
         }
+        const bool big = (int64_t)H * W >= 1000000;
+        P = plan_tiles(H, W, hw, big ? 3073 : 2049, big ? 8 : 10, 0);
+        balance_tiles(P, H, W, hw);
         return P;
     }
     const int nt = mode == 3 ? 1024 : mode == 4 ? 1025 : mode == 6 ? 257 : mode == 7 ? 513
-                 : mode == 8 ? 1026 : mode == 9 ? 514 : 256;
+                 : mode == 8 ? 1026 : mode == 9 ? 514 : mode == 12 ? 2049 : mode == 13 ? 3073 : mode == 14 ? 4097
+                 : 256;
     P = plan_tiles(H, W, hw, nt, kreq > 0 ? kreq : kDefaultK, ew);
     if (P.resident) P.K = iters;                             // the whole warp in one launch
     balance_tiles(P, H, W, hw);
@@ -194,8 +207,8 @@ void fill_tb_level(TbLevel* d, const LevelPlanes& L, const float* at2) {
 }
 
 int tb_grid(const LevelTbPlan& P, int ntiles) {
-    const int per_cu = P.nt == 1024 ? 1 : (P.nt == 1025 || P.nt == 1026) ? 2 : (P.nt == 513 || P.nt == 514) ? 4
-                     : P.nt == 257 ? 8 : 4;   // residency
+    const int per_cu = (P.nt == 1024 || P.nt == 4097) ? 1 : (P.nt == 1025 || P.nt == 1026 || P.nt == 2049 || P.nt == 3073) ? 2
+                     : (P.nt == 513 || P.nt == 514) ? 4 : P.nt == 257 ? 8 : 4;   // residency
     return std::max(1, std::min(ntiles, 256 * per_cu));
 }
 

@@ -415,15 +415,24 @@ void launch_admm_iter(const AdmmIterArgs& a, bool, hipStream_t s) {
             }
     });
 }
-void launch_admm_tb(const TbArgs& a, bool, int nt, int grid, hipStream_t s) {
+// the extended region of an ADMM tile (halo K + 1 above / left, K below / right, clipped) fits the
+// work-group shape it is launched with: the real kernels index LDS or registers by its cells
+static void check_admm_region(const TbLevel& L, const TbTile& T, int K, bool hw, int nt) {
+    const int64_t eh = std::min(T.y0 + T.th + K, L.H) - std::max(T.y0 - (K + 1), 0);
+    const int64_t ew = std::min(T.x0 + T.tw + K, L.W) - std::max(T.x0 - (K + 1), 0);
+    check(tb_fits(hw, nt, eh, ew), "ADMM tile region beyond the kernel's shape");
+}
+void launch_admm_tb(const TbArgs& a, bool hw, int nt, int grid, hipStream_t s) {
     check(grid > 0 && a.K > 0, "tile launch without work-groups or iterations");
     check(tb_capacity(false, nt) > 0, "tile launch of an unknown work-group shape");
+    check(!(is_rows_code(nt) && a.queue), "wave-row tiles launched from work queues");
     ++g_launches;
     enqueue(s, [=] {
         if (!a.tiles) {                                  // direct: regular tiles of one level
             for (int t = 0; t < a.ntiles; ++t) {
                 const int ty = t / a.ntx, tx = t - ty * a.ntx;
                 TbTile T{0, ty * a.th, tx * a.tw, std::min(a.th, a.lvl.H - ty * a.th), std::min(a.tw, a.lvl.W - tx * a.tw)};
+                check_admm_region(a.lvl, T, a.K, hw, nt);
                 tile_body(a.lvl, T, a.K, a.at_slot);
             }
             return;
@@ -434,6 +443,7 @@ void launch_admm_tb(const TbArgs& a, bool, int nt, int grid, hipStream_t s) {
             const TbTile& T = a.tiles[t];
             const TbLevel* L = a.levels + 2 * T.level + a.dir;
             check(tracked(L, sizeof(TbLevel)), "level descriptor outside device memory");
+            check_admm_region(*L, T, a.K, hw, nt);
             tile_body(*L, T, a.K, a.at_slot);
         };
         if (!a.queue) {

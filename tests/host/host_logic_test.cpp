@@ -116,11 +116,11 @@ static void check_cover(const std::vector<TbTile>& tiles, int H, int W, const ch
 }
 
 static void test_planners(std::mt19937& rng) {
-    const int nts[] = {256, 1024, 1025, 513, 257, 1026, 514};
+    const int nts[] = {256, 1024, 1025, 513, 257, 1026, 514, 2049, 3073, 4097};
     for (int c = 0; c < 1500; ++c) {
         const int H = 2 + rng() % (rng() % 8 ? 300 : 2500), W = 2 + rng() % (rng() % 8 ? 300 : 2500);
         const bool hw = rng() % 2;
-        const int nt = nts[rng() % 7], K = 1 + rng() % 16;
+        const int nt = nts[rng() % 10], K = 1 + rng() % 16;
         const int ew = rng() % 3 ? 0 : 16 + rng() % 300;
         const LevelTbPlan P = plan_tiles(H, W, hw, nt, K, ew);
         if (!P.tb) continue;
@@ -129,16 +129,15 @@ static void test_planners(std::mt19937& rng) {
         CHECK(!tiles.empty() && tiles[0].level == 7, "tiles name their level");
         check_cover(tiles, H, W, "plan_tiles");
         CHECK(P.K >= 1 && P.K <= K, "K %d of %d", P.K, K);
-        const int cap = tb_capacity(hw, nt);
         for (const TbTile& t : tiles) {
             const int ey0 = std::max(t.y0 - tb_halo_lo(P.K), 0), ex0 = std::max(t.x0 - tb_halo_lo(P.K), 0);
             const int ey1 = std::min(t.y0 + t.th + tb_halo_hi(P.K), H), ex1 = std::min(t.x0 + t.tw + tb_halo_hi(P.K), W);
-            CHECK((int64_t)(ey1 - ey0) * (ex1 - ex0) <= cap || P.resident,
-                  "extended tile %dx%d over capacity %d (H %d W %d nt %d K %d)", ey1 - ey0, ex1 - ex0, cap, H, W, nt, P.K);
+            CHECK(tb_fits(hw, nt, ey1 - ey0, ex1 - ex0), "extended tile %dx%d beyond the shape of code %d (H %d W %d K %d)",
+                  ey1 - ey0, ex1 - ex0, nt, H, W, P.K);
         }
         // the full plan of a mode (with the balancing of tile heights) covers the level as well
-        const int modes[] = {2, 3, 4, 6, 7, 8, 9};
-        const LevelTbPlan Q = plan_level(H, W, hw, 50, modes[rng() % 7], K, ew);
+        const int modes[] = {2, 3, 4, 6, 7, 8, 9, 12, 13, 14};
+        const LevelTbPlan Q = plan_level(H, W, hw, 50, modes[rng() % 10], K, ew);
         if (Q.tb) {
             std::vector<TbTile> tq;
             append_tiles(Q, 0, H, W, tq);
@@ -291,18 +290,22 @@ static void test_solves(std::mt19937& rng) {
         for (size_t k = 0; k < fs.size(); ++k)
             if (rng() % 2) { sub.push_back(fs[k]); idx.push_back((int)k); }
         if (sub.empty()) continue;
+        const int bnt[] = {0, 1025, 2049, 3073, 4097};
         OK(flow_tune_set("batch_order", (int)(rng() % 2)));
         OK(flow_tune_set("batch_k", (int)(rng() % 4 == 0 ? 0 : 1 + rng() % 13)));
+        OK(flow_tune_set("batch_nt", bnt[rng() % 5]));
         const std::vector<Out> got = solve_batch(ctx, sub, (int)(rng() % 2));
         for (size_t i = 0; i < sub.size(); ++i)
             CHECK(got[i] == ref[idx[i]], "batched pair %d (round %d) differs from alone", idx[i], round);
     }
     OK(flow_tune_set("batch_order", -1));
     OK(flow_tune_set("batch_k", 0));
+    OK(flow_tune_set("batch_nt", 0));
 
     // serving: randomised submit / step / poll orders under a budget that holds two or three pairs
     for (int round = 0; round < 10; ++round) {
         OK(flow_tune_set("serve_graph", (int)(rng() % 2)));
+        OK(flow_tune_set("batch_nt", rng() % 2 ? 0 : 3073));
         uint64_t big = 0;
         for (auto& f : fs) {
             uint64_t b = 0;
@@ -372,6 +375,7 @@ static void test_solves(std::mt19937& rng) {
         OK(flow_server_destroy(srv));
     }
     OK(flow_tune_set("serve_graph", 1));
+    OK(flow_tune_set("batch_nt", 0));
 
     // a pair that can never fit the budget is refused at submit
     {

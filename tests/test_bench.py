@@ -73,27 +73,31 @@ def test_roofline_arithmetic():
 
 def test_batch_traffic_needs_the_source_and_every_stage_choice(monkeypatch, tmp_path):
     """Per-stage DRAM records combine into bytes per launch weighted by each stage's launches
-    (ceil(iters / K) per warp), and only when every stage of the run was measured on this source."""
+    (ceil(iters / K) per warp), and only when every stage of the run was measured on this source
+    with the same choice (order, tile code, K, width); records without a code are general tiles."""
     csrc = tmp_path / "paper_2011_10979_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("admm_tb.hip", "admm_args.hpp", "tb_plan.cpp", "multi.cpp", "geometry.cpp"):
+    for f in ("admm_tb.hip", "admm_rows.hip", "admm_args.hpp", "tb_plan.cpp", "multi.cpp", "geometry.cpp"):
         (csrc / f).write_bytes(open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     rec = {"batch64": {"kernel_sha": bench.batch_sha(),
                        "stages": [{"level": 0, "order": 0, "K": 5, "ew": 64, "bytes_per_launch": 1.5e9},
+                                  {"level": 0, "order": 0, "nt": 3073, "K": 8, "ew": 64, "bytes_per_launch": 1.2e9},
                                   {"level": 1, "order": 0, "K": 10, "ew": 64, "bytes_per_launch": 0.3e9},
                                   {"level": 1, "order": 0, "K": 5, "ew": 128, "bytes_per_launch": 0.4e9}]}}
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     # 50 iterations: 10 launches of level 0 per warp, 5 of level 1 at K = 10
-    assert bench.batch_traffic([[0, 0, 5, 64], [1, 0, 10, 64]], 50) == round((10 * 1.5e9 + 5 * 0.3e9) / 15)
-    assert bench.batch_traffic([[0, 0, 5, 64], [1, 0, 5, 128]], 50) == round((1.5e9 + 0.4e9) / 2)
-    assert bench.batch_traffic([[0, 0, 5, 64]], 50) == 1.5e9
-    assert bench.batch_traffic([[0, 0, 6, 64], [1, 0, 10, 64]], 50) is None
-    assert bench.batch_traffic([[0, 1, 5, 64]], 50) is None
+    assert bench.batch_traffic([[0, 0, 1025, 5, 64], [1, 0, 1025, 10, 64]], 50) == round((10 * 1.5e9 + 5 * 0.3e9) / 15)
+    assert bench.batch_traffic([[0, 0, 1025, 5, 64], [1, 0, 1025, 5, 128]], 50) == round((1.5e9 + 0.4e9) / 2)
+    assert bench.batch_traffic([[0, 0, 1025, 5, 64]], 50) == 1.5e9
+    assert bench.batch_traffic([[0, 0, 3073, 8, 64]], 50) == 1.2e9
+    assert bench.batch_traffic([[0, 0, 2049, 8, 64]], 50) is None
+    assert bench.batch_traffic([[0, 0, 1025, 6, 64], [1, 0, 1025, 10, 64]], 50) is None
+    assert bench.batch_traffic([[0, 1, 1025, 5, 64]], 50) is None
     assert bench.batch_traffic("built-in", 50) is None
     (csrc / "multi.cpp").write_text("changed")
-    assert bench.batch_traffic([[0, 0, 5, 64]], 50) is None
+    assert bench.batch_traffic([[0, 0, 1025, 5, 64]], 50) is None
 
 
 def test_pair_px_sums_the_pyramid():

@@ -35,7 +35,7 @@ def ctx():
 @pytest.fixture(autouse=True)
 def reset_knobs():
     yield
-    for k, v in (("tb_mode", 0), ("tb_k", 0), ("batch_order", -1), ("batch_k", 0), ("batch_ew", 0)):
+    for k, v in (("tb_mode", 0), ("tb_k", 0), ("batch_order", -1), ("batch_k", 0), ("batch_ew", 0), ("batch_nt", 0)):
         fm.set_tuning(k, v)
 
 
@@ -83,14 +83,16 @@ def test_batched_equals_plain_tile_solves_bitwise(ctx):
         assert same(out[k], (u, v, res)), f"pair {k}"
 
 
-@pytest.mark.parametrize("order,K,ew", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 8, 128), (0, 5, 96), (1, 3, 64)])
-def test_pair_alone_equals_pair_in_mix_under_every_choice(ctx, order, K, ew):
-    print(f"[case] alone vs mix order={order} K={K} ew={ew}", flush=True)
+@pytest.mark.parametrize("order,K,ew,nt", [(0, 0, 0, 0), (1, 0, 0, 0), (0, 2, 0, 0), (1, 8, 128, 0), (0, 5, 96, 0),
+                                           (1, 3, 64, 0), (0, 8, 64, 3073), (0, 4, 0, 2049), (0, 10, 48, 4097)])
+def test_pair_alone_equals_pair_in_mix_under_every_choice(ctx, order, K, ew, nt):
+    print(f"[case] alone vs mix order={order} K={K} ew={ew} nt={nt}", flush=True)
     fr = frames(MIX)
     alone = batched(ctx, [fr[3]], **KW)[0]
     fm.set_tuning("batch_order", order)
     fm.set_tuning("batch_k", K)
     fm.set_tuning("batch_ew", ew)
+    fm.set_tuning("batch_nt", nt)
     mix = batched(ctx, [fr[1], fr[3], fr[0], fr[4]], **KW)
     assert same(alone, mix[1])
     mix2 = batched(ctx, fr, **KW)
@@ -109,20 +111,26 @@ def test_autotuned_batch_keeps_results(ctx):
 
 def test_pinned_stage_choices_keep_results(ctx):
     """Stage choices set by hand (the entries an autotune report lists) change speed only: the
-    batch's results stay bitwise the same; a level no pair has, or an order outside 0 / 1, is refused."""
+    batch's results stay bitwise the same, with the general tiles from the table or from work
+    queues and with the wave-row tiles; a level no pair has, an order that is neither 0 / 1 nor a
+    wave-row code, or a wave-row width above 64 is refused."""
     print("[case] batched pinned stage choices", flush=True)
     fr = frames(MIX)
     pairs = [(d0, d1, lv) for _, _, lv, d0, d1 in fr]
     before = batched(ctx, fr, **KW)
-    for level, order, K, ew in ((0, 1, 3, 48), (1, 0, 7, 96), (2, 0, 30, 64)):
-        ctx.set_batched_stage(pairs, level, order, K, ew, fm.Params(**KW))
-    after = batched(ctx, fr, **KW)
-    for a, b in zip(before, after):
-        assert same(a, b)
+    for pins in (((0, 1, 3, 48), (1, 0, 7, 96), (2, 0, 30, 64)),
+                 ((0, 3073, 8, 64), (1, 2049, 5, 64), (2, 4097, 10, 48))):
+        for level, order, K, ew in pins:
+            ctx.set_batched_stage(pairs, level, order, K, ew, fm.Params(**KW))
+        after = batched(ctx, fr, **KW)
+        for a, b in zip(before, after):
+            assert same(a, b)
     with pytest.raises(fm.FlowError):
         ctx.set_batched_stage(pairs, 7, 0, 4, 64, fm.Params(**KW))
     with pytest.raises(fm.FlowError):
         ctx.set_batched_stage(pairs, 0, 2, 4, 64, fm.Params(**KW))
+    with pytest.raises(fm.FlowError):
+        ctx.set_batched_stage(pairs, 0, 3073, 4, 96, fm.Params(**KW))
 
 
 def test_graph_replay_reads_new_frames(ctx):

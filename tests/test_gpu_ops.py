@@ -15,6 +15,8 @@ import paper_2011_10979_amd as fm  # noqa: E402
 from oracle import ops, pyramid, schemes, energy  # noqa: E402
 from helpers import to_dev, to_np, f32, random_admm_state, random_lin, max_abs  # noqa: E402
 
+ROW_CODES = (2049, 3073, 4097)   # wave-row tile codes: 64 columns x 32 / 48 / 64 rows
+
 SHAPES = [(2, 2), (2, 67), (67, 2), (3, 5), (17, 61), (70, 130), (129, 200), (240, 320)]
 
 
@@ -302,7 +304,7 @@ def _ulps(a, b):
     return np.abs(key(a) - key(b))
 
 
-@pytest.mark.parametrize("threads", [1025, 1026, 256])
+@pytest.mark.parametrize("threads", [1025, 1026, 256, 3073])
 @pytest.mark.parametrize("beta", [0.0, 0.05])
 def test_tiles_and_one_pass_iterations_agree_to_the_ulp(threads, beta):
     """K = 6 iterations of a tile kernel against 6 one-pass iterations from the same increment-form
@@ -365,16 +367,21 @@ def test_admm_iteration_every_strip_height(rows, shape, beta):
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 6), ((37, 130), (8, 30), 3), ((101, 250), (12, 20), 4),
                                           ((60, 80), (60, 80), 9), ((64, 64), (10, 18), 1), ((33, 47), (33, 47), 20)])
 @pytest.mark.parametrize("threads,order", [(256, 0), (1024, 0), (1025, 0), (256, 1), (1024, 1), (1025, 2),
-                                           (1025, 3), (256, 2), (513, 0), (257, 0), (1026, 0), (514, 0)])
+                                           (1025, 3), (256, 2), (513, 0), (257, 0), (1026, 0), (514, 0),
+                                           (2049, 0), (3073, 0), (3073, 3), (4097, 0)])
 @pytest.mark.parametrize("scheme,relax,beta", [("padmm", 1.0, 0.0), ("rpadmm2", 1.9, 0.05)])
 def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme, relax, beta):
     """K iterations of the temporally blocked tile kernel (halo K + 1 / K, ragged tiles, resident
     levels) against K steps of the oracle on the same increment-form state; a tile whose extended
     region exceeds the kernel's capacity is refused before any launch."""
     print_case("admm_tb", shape=shape, tile=tile, K=K, threads=threads, order=order, scheme=scheme, beta=beta)
-    cap = {1025: 2048, 513: 1024, 257: 512, 1026: 1024, 514: 512}.get(threads) or (1024 * (3 if beta > 0 else 4) if threads == 1024 else
-                                                              256 * (4 if beta > 0 else 6))
-    oversized = min(shape[0], tile[0] + 2 * K + 1) * min(shape[1], tile[1] + 2 * K + 1) > cap
+    eh, ew = min(shape[0], tile[0] + 2 * K + 1), min(shape[1], tile[1] + 2 * K + 1)
+    if threads in ROW_CODES:                         # wave-row tiles: at most 64 columns, (code - 1) / 64 rows
+        oversized = ew > 64 or eh * 64 > threads - 1
+    else:
+        cap = {1025: 2048, 513: 1024, 257: 512, 1026: 1024, 514: 512}.get(threads) or (
+            1024 * (3 if beta > 0 else 4) if threads == 1024 else 256 * (4 if beta > 0 else 6))
+        oversized = eh * ew > cap
     rng = np.random.default_rng(zlib.crc32(repr(("tb", shape, tile, K, threads, scheme)).encode()))
     st = random_admm_state(rng, shape, beta)
     Ix, Iy, Itr, at = random_lin(rng, shape, beta)
@@ -405,3 +412,39 @@ def test_admm_tiles_match_k_oracle_steps(shape, tile, K, threads, order, scheme,
     assert max_abs(to_np(out["v"]), full["v"] - v0) < tol
     for k in ["q1x", "q1y", "q2x", "q2y", "s"] + (["w", "px", "py"] if beta > 0 else []):
         assert max_abs(to_np(out[k]), full[k]) < tol, k
+
+
+def _row_cases():
+    """(shape, tile, K, code) with the tile's extended region within the wave-row shape."""
+    cases = []
+    for shape, tile, K in [((101, 250), (12, 20), 4), ((300, 200), (27, 53), 5), ((96, 130), (17, 43), 10),
+                           ((45, 64), (45, 64), 7), ((70, 33), (20, 33), 3)]:
+        eh, ew = min(shape[0], tile[0] + 2 * K + 1), min(shape[1], tile[1] + 2 * K + 1)
+        cases += [(shape, tile, K, nt) for nt in ROW_CODES if ew <= 64 and eh * 64 <= nt - 1]
+    return cases
+
+
+@pytest.mark.parametrize("shape,tile,K,threads", _row_cases())
+@pytest.mark.parametrize("beta", [0.0, 0.05])
+def test_row_tiles_equal_the_general_tiles(shape, tile, K, threads, beta):
+    """The wave-row tiles (registers per row, DPP neighbours) evaluate the general tile kernel's
+    operations in the same order: the same tiles give bitwise the same iterates, in direct and in
+    table order."""
+    print_case("rows vs general tiles", shape=shape, tile=tile, K=K, threads=threads, beta=beta)
+    eh, ew = min(shape[0], tile[0] + 2 * K + 1), min(shape[1], tile[1] + 2 * K + 1)
+    rng = np.random.default_rng(zlib.crc32(repr(("rows", shape, tile, K, threads, beta)).encode()))
+    st = random_admm_state(rng, shape, beta)
+    Ix, Iy, Itr, at = random_lin(rng, shape, beta)
+    init = dict(st, u=f32(rng.normal(scale=0.3, size=shape)), v=f32(rng.normal(scale=0.3, size=shape)),
+                u0=f32(rng.normal(scale=4.0, size=shape)), v0=f32(rng.normal(scale=4.0, size=shape)))
+    at_t = torch.tensor([at, 0.0], dtype=torch.float32, device="cuda")
+    lin = (to_dev(Ix, 2), to_dev(Iy, 2), to_dev(Itr, 2))
+    p = fm.Params(beta=beta)
+    ref = fm.admm_tb(_dev_state(init, pad=2), *lin, at_t, p, iters=K, threads=1025 if eh * ew <= 2048 else 1024,
+                     tile_h=tile[0], tile_w=tile[1], order=0)
+    keys = ["u", "v", "q1x", "q1y", "q2x", "q2y", "s"] + (["w", "px", "py"] if beta > 0 else [])
+    for order in (0, 3):
+        out = fm.admm_tb(_dev_state(init, pad=2), *lin, at_t, p, iters=K, threads=threads, tile_h=tile[0],
+                         tile_w=tile[1], order=order)
+        for k in keys:
+            assert np.array_equal(to_np(out[k]), to_np(ref[k])), (order, k)

@@ -248,9 +248,11 @@ def test_tuning_choice_rows_are_checked(ctx):
         ctx.set_choice("96x128i40", 4, 4, 8)       # tile width: 0 or 16..512
 
 
-@pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8), (7, 4), (6, 2), (8, 4), (9, 2)])
+@pytest.mark.parametrize("mode,k", [(1, 0), (2, 2), (3, 4), (4, 8), (7, 4), (6, 2), (8, 4), (9, 2), (12, 6), (13, 5),
+                                    (14, 10)])
 def test_every_kernel_mode_keeps_parity(ctx, mode, k):
-    """Each forced kernel choice (one-pass; tiles of 256 / 1024 / small 1024 threads) meets the bar."""
+    """Each forced kernel choice (one-pass; tiles of 256 / 1024 / small 1024 threads; wave-row tiles)
+    meets the bar."""
     print(f"[case] forced mode {mode} K {k}", flush=True)
     fm.set_tuning("tb_mode", mode)
     fm.set_tuning("tb_k", k)
