@@ -90,7 +90,7 @@ def kernel_sha():
     """Hash of the iteration kernels' sources and of the tile planner (which sets the tiles a launch
     loads, and so its traffic)."""
     h = hashlib.sha256()
-    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp", "tb_plan.cpp"):
+    for f in ("admm.hip", "admm_tb.hip", "admm_rows.hip", "admm_args.hpp", "tb_plan.cpp", "geometry.cpp"):
         with open(os.path.join(ROOT, "paper_2011_10979_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

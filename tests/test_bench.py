@@ -41,15 +41,18 @@ def test_traffic_is_reported_only_for_the_source_and_choice_it_was_measured_with
 
 
 def test_kernel_hash_covers_the_tile_planner(tmp_path, monkeypatch):
-    """The hash reads the iteration kernels and the planner: a planner change alone changes it."""
+    """The hash reads the iteration kernels, the planner and the tile geometry: a change to any one
+    of them alone changes it."""
     csrc = tmp_path / "paper_2011_10979_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("admm.hip", "admm_tb.hip", "admm_args.hpp", "tb_plan.cpp"):
+    files = ("admm.hip", "admm_tb.hip", "admm_rows.hip", "admm_args.hpp", "tb_plan.cpp", "geometry.cpp")
+    for f in files:
         (csrc / f).write_text(f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    h0 = bench.kernel_sha()
-    (csrc / "tb_plan.cpp").write_text("changed")
-    assert bench.kernel_sha() != h0
+    for f in files:
+        h0 = bench.kernel_sha()
+        (csrc / f).write_text(f + " changed")
+        assert bench.kernel_sha() != h0, f
 
 
 def test_roofline_arithmetic():
