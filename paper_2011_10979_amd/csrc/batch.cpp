@@ -198,14 +198,16 @@ bool pd_stage_tiles(const BatchPlan& P, const BStage& S, const flow_params& p, i
 // Every level of pDR / ALG1 stage S fits one tile of work-group code nt.
 bool pd_stage_resident(const BatchPlan& P, const BStage& S, bool hw, int nt) {
     for (int k : S.pairs)
-        if ((int64_t)P.L[k][S.l].H * P.L[k][S.l].W > pdr_tb_capacity(hw, nt)) return false;
+        if (!pd_fits(hw, nt, P.L[k][S.l].H, P.L[k][S.l].W)) return false;
     return true;
 }
 
 // Work-group codes a pDR / ALG1 stage may take: 1024 and 512 threads with one cell of each colour
-// per thread; pDR without the w block also 1024 and 512 threads with two.
+// per thread; pDR also the wave-row tiles of 128 x 32 cells, and without the w block 1024 and 512
+// threads with two cells of each colour and the wave-row tiles of 128 x 48.
 std::vector<int> pd_codes(const flow_params& p) {
-    if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513};
+    if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513, 4098, 6145};
+    if (p.scheme == FLOW_PDR) return {1024, 512, 4098};
     return {1024, 512};
 }
 

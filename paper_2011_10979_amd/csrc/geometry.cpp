@@ -46,8 +46,20 @@ bool tb_fits(bool has_w, int nt, int64_t eh, int64_t ew) {
 }
 
 // pDR / ALG1 tiles: work-group codes 512 / 1024 (one red and one black cell per thread), 2048 (1024
-// threads with two cells of each colour) and 513 (512 threads with two of each)
-int pdr_tb_capacity(bool, int nt) { return nt == 513 ? 2048 : 2 * nt; }
+// threads with two cells of each colour), 513 (512 threads with two of each), and the pDR wave-row
+// codes 4098 / 6145 (1024 threads; regions of at most 128 columns and 32 / 48 rows)
+bool is_pd_rows_code(int nt) { return nt == 4098 || nt == 6145; }
+
+int pdr_tb_capacity(bool, int nt) {
+    if (nt == 4098) return 4096;
+    if (nt == 6145) return 6144;
+    return nt == 513 ? 2048 : 2 * nt;
+}
+
+bool pd_fits(bool has_w, int nt, int64_t eh, int64_t ew) {
+    if (is_pd_rows_code(nt)) return ew <= 2 * kWave && eh * 2 * kWave <= pdr_tb_capacity(has_w, nt);
+    return eh * ew <= pdr_tb_capacity(has_w, nt);
+}
 
 int blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + 3) / 4); }
 int lin_blocks_of(int H, int W) { return ((W + 63) / 64) * ((H + kLinRows - 1) / kLinRows); }

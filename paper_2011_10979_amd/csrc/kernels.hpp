@@ -137,8 +137,14 @@ struct PdrTbArgs {
 };
 int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 threads; 2048 / 513: 1024 /
                                                           // 512 threads with two cells of each colour
-                                                          // (pDR, beta = 0)
+                                                          // (pDR, beta = 0); 4098 / 6145: pDR wave-row
+                                                          // tiles of 128 x 32 / 128 x 48 cells (6145:
+                                                          // beta = 0)
+bool is_pd_rows_code(int nt);
+// an extended region of eh x ew cells fits the pDR / ALG1 tile kernel of work-group code nt
+bool pd_fits(bool has_w, int nt, int64_t eh, int64_t ew);
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
+void launch_pdr_rows(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 // ALG1 (primal-dual) tiles on the same argument block: sigma / tau are its primal / dual steps
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 

@@ -232,8 +232,9 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, const PdrTbLevel& L
             float w = 0.f, wbv = 0.f, wt = 0.f;
             if constexpr (HAS_W) { w = xo[2]; wbv = xb[2][c][k]; wt = 2.f * w - wbv; }
             const float ix = Ix[c][k], iy = Iy[c][k];
-            const float e2 = beta * beta + ix * ix + iy * iy;
-            const float rho = It[c][k] + beta * wt + ix * (ut - u0[c][k]) + iy * (vt - v0[c][k]);
+            // sums of products as explicit FMA chains: every pDR tile kernel rounds them alike
+            const float e2 = fmaf(iy, iy, fmaf(ix, ix, beta * beta));
+            const float rho = fmaf(iy, vt - v0[c][k], fmaf(ix, ut - u0[c][k], fmaf(beta, wt, It[c][k])));
             // eq:resolvent: the step along e is -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
             // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
             float step = 0.f, theta = 0.f;
@@ -249,18 +250,18 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, const PdrTbLevel& L
             const float t2 = 2.f * tau;
             const float a1x = yo[0] + t2 * gx[0], a1y = yo[1] + t2 * gy[0];
             const float a2x = yo[2] + t2 * gx[1], a2y = yo[3] + t2 * gy[1];
-            const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
+            const float nq = fmaf(a2y, a2y, fmaf(a2x, a2x, fmaf(a1y, a1y, a1x * a1x)));
             const float sq = fminf(1.f, __builtin_amdgcn_rsqf(nq));
-            S.y[c][0][e] = a1x * sq - tau * gx[0];
-            S.y[c][1][e] = a1y * sq - tau * gy[0];
-            S.y[c][2][e] = a2x * sq - tau * gx[1];
-            S.y[c][3][e] = a2y * sq - tau * gy[1];
+            S.y[c][0][e] = fmaf(a1x, sq, -(tau * gx[0]));
+            S.y[c][1][e] = fmaf(a1y, sq, -(tau * gy[0]));
+            S.y[c][2][e] = fmaf(a2x, sq, -(tau * gx[1]));
+            S.y[c][3][e] = fmaf(a2y, sq, -(tau * gy[1]));
             if constexpr (HAS_W) {
                 const float bx = yo[4] + t2 * gx[2], by = yo[5] + t2 * gy[2];
-                const float np2 = bx * bx + by * by;
+                const float np2 = fmaf(by, by, bx * bx);
                 const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
-                S.y[c][4][e] = bx * sp - tau * gx[2];
-                S.y[c][5][e] = by * sp - tau * gy[2];
+                S.y[c][4][e] = fmaf(bx, sp, -(tau * gx[2]));
+                S.y[c][5][e] = fmaf(by, sp, -(tau * gy[2]));
             }
         }
         __syncthreads();
@@ -330,6 +331,10 @@ static void launch_pdr_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
     if (a.ntiles < 1) return;
+    if (is_pd_rows_code(nt)) {               // wave-row tiles (6145 without the w block only)
+        launch_pdr_rows(a, has_w, nt, s);
+        return;
+    }
     // two cells of each colour per thread exist for beta = 0 only (with the w block they would need
     // more than 128 VGPRs); the planners never pair them with w, and a tile sized for them must not
     // reach the other kernels' LDS

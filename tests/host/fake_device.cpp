@@ -468,13 +468,14 @@ void launch_admm_tb(const TbArgs& a, bool hw, int nt, int grid, hipStream_t s) {
 // index LDS by the region's cells), and the tiles with two cells of each colour run without the w
 // block only
 static void check_pd_codes(bool has_w, int nt) {
-    check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513, "pDR / ALG1 tile launch: work-group code");
-    check((nt != 2048 && nt != 513) || !has_w, "pDR tiles with two cells of each colour launched with w");
+    check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513 || nt == 4098 || nt == 6145,
+          "pDR / ALG1 tile launch: work-group code");
+    check((nt != 2048 && nt != 513 && nt != 6145) || !has_w, "pDR tiles for beta = 0 launched with w");
 }
 static void check_pd_region(const PdrTbLevel& L, int th, int tw, bool has_w, int nt, int halo) {
     const int64_t eh = std::min<int64_t>(L.H, (int64_t)th + halo);
     const int64_t ew = std::min<int64_t>(L.W, (int64_t)tw + halo);
-    check(eh * ew <= pdr_tb_capacity(has_w, nt), "pDR / ALG1 tile region above the kernel's capacity");
+    check(pd_fits(has_w, nt, eh, ew), "pDR / ALG1 tile region beyond the kernel's shape");
 }
 // toy iteration: X += K on the tile's output cells, X bar and y bar copied, Theta = I_t
 static void toy_pd_region(const PdrTbLevel& L, int K, int y0, int x0, int th, int tw) {
@@ -517,7 +518,7 @@ void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     launch_pd(a, has_w, nt, pdr_halo_lo(a.sweeps, a.K) + pdr_halo_hi(a.sweeps, a.K), s);
 }
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
-    check(nt != 2048 && nt != 513, "pDR-only tiles launched for ALG1");
+    check(nt != 2048 && nt != 513 && !is_pd_rows_code(nt), "pDR-only tiles launched for ALG1");
     launch_pd(a, has_w, nt, 2 * alg1_halo(a.K), s);
 }
 static void pdr_pass(const PdrArgs& a, bool final_pass) {

@@ -215,6 +215,48 @@ def test_large_pdr_tiles_equal_the_1024_thread_tiles(shape, tile, K, small):
     assert torch.equal(outs[0][1], outs[1][1])
 
 
+def _pdr_row_cases():
+    """(shape, tile, K, sweeps, beta, mode): wave-row pDR tiles (mode 12: 128 x 32 cells, 13: 128 x 48)
+    whose extended region also fits the general tiles used as reference (4096 cells, 2048 with w)."""
+    cases = []
+    for shape, tile, K, n in [((101, 250), (19, 50), 2, 1), ((130, 140), (17, 80), 3, 1), ((60, 61), (60, 61), 4, 1),
+                              ((45, 200), (20, 115), 1, 1), ((90, 170), (10, 90), 1, 2), ((33, 128), (33, 128), 6, 1),
+                              ((28, 100), (28, 100), 5, 1), ((40, 60), (10, 30), 1, 1), ((70, 300), (15, 40), 2, 1)]:
+        halo = (2 * n + 1) * K * 2 + 1
+        eh, ew = min(shape[0], tile[0] + halo), min(shape[1], tile[1] + halo)
+        for beta in (0.0, 0.05):
+            for mode, rows in ((12, 32), (13, 48)):
+                if ew <= 128 and eh <= rows and eh * ew <= (2048 if beta > 0 else 4096):
+                    cases.append((shape, tile, K, n, beta, mode))
+    return cases
+
+
+@pytest.mark.parametrize("shape,tile,K,sweeps,beta,mode", _pdr_row_cases())
+def test_pdr_row_tiles_equal_the_general_tiles(shape, tile, K, sweeps, beta, mode):
+    """The wave-row pDR tiles (cell pairs per lane, registers per row, DPP neighbours) evaluate the
+    general pDR tiles' operations in the same order: K iterations of the same tiles of the same state
+    agree bit for bit (with w, mode 13 runs the 128 x 32 shape)."""
+    print_case("pdr rows vs general tiles", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta, mode=mode)
+    rng = np.random.default_rng(zlib.crc32(repr(("pdrrows", shape, tile, K, sweeps, beta)).encode()))
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    lin = (to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3))
+    p = fm.Params(scheme="pdr", beta=beta, gs_sweeps=sweeps)
+    ref = fm.pdr_tb(g, *lin, p, iters=K, tile_h=tile[0], tile_w=tile[1])
+    fm.set_tuning("pdr_mode", mode)
+    try:
+        out = fm.pdr_tb(g, *lin, p, iters=K, tile_h=tile[0], tile_w=tile[1])
+    finally:
+        fm.set_tuning("pdr_mode", 0)
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    for k in keys:
+        assert torch.equal(out[0][k], ref[0][k]), k
+    assert torch.equal(out[1], ref[1])
+
+
 @pytest.mark.parametrize("shape,tile,K", [((7, 5), (7, 5), 9), ((37, 130), (8, 30), 4), ((101, 250), (12, 20), 1),
                                           ((40, 45), (40, 45), 20), ((64, 64), (10, 18), 6), ((33, 47), (5, 9), 3)])
 @pytest.mark.parametrize("beta", [0.0, 0.05])
