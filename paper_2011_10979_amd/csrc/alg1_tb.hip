@@ -178,10 +178,11 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, const PdrTbLevel& 
                 const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
                 const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
                 // eq:resolvent with step sigma: -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
-                // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
+                // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0);
+                // 1 / |e|^2 is the hardware reciprocal (within 1 ulp)
                 float step = 0.f, theta = 0.f;
                 if (e2 > 0.f) {
-                    step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+                    step = __builtin_amdgcn_fmed3f(-rho * __builtin_amdgcn_rcpf(e2), -sl, sl);
                     theta = -step * inv_sigma;
                 }
                 const float un = ut + step * Ix[k], vn = vt + step * Iy[k];

@@ -98,10 +98,10 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             }
             bool resident_done = false;
             const std::vector<int> ks = alg1 ? launch_ks(p->iters, 1, 10) : std::vector<int>{1, 2, 3, 4};
-            for (int nt : {1024, 512, 2048, 513, 4098, 6145})
+            for (int nt : {1024, 512, 2048, 513, 4098, 6145, 3074, 2050})
             for (int K : ks) {
-                if ((nt == 2048 || nt == 513 || nt == 6145) && (alg1 || hw)) continue;   // pDR without the w block
-                if (nt == 4098 && alg1) continue;                                         // wave-row tiles: pDR
+                if ((nt == 2048 || nt == 513 || nt == 6145 || nt == 3074) && (alg1 || hw)) continue;   // pDR, no w
+                if ((nt == 4098 || nt == 2050) && alg1) continue;                                       // pDR
                 PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(*p, K), K, 0, nt);
                 if (!T.tb) continue;
                 if (T.resident) {
@@ -110,7 +110,8 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
                     T.K = p->iters;
                 }
                 PCand c{};
-                c.c.mode = nt == 512 ? 6 : nt == 2048 ? 10 : nt == 513 ? 11 : nt == 4098 ? 12 : nt == 6145 ? 13 : 5;
+                c.c.mode = nt == 512 ? 6 : nt == 2048 ? 10 : nt == 513 ? 11 : nt == 4098 ? 12 : nt == 6145 ? 13
+                         : nt == 3074 ? 14 : nt == 2050 ? 15 : 5;
                 c.c.K = T.resident ? 0 : K;
                 c.T = T;
                 cands.push_back(c);
@@ -236,7 +237,7 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
                                         int32_t pdr_sweeps, int32_t mode, int32_t K, int32_t rows) {
     if (!ctx) return fail(FLOW_E_INVAL, "ctx is NULL");
     if (H < 2 || W < 2 || iters < 1) return fail(FLOW_E_INVAL, "H, W must be >= 2 and iters >= 1");
-    if (mode < 1 || mode > 14)
+    if (mode < 1 || mode > 15)
         return fail(FLOW_E_INVAL, "mode must be 1 (one-pass / three-pass), 2..4, 6..9, 12..14 (tiles) or 5 / 10 / 11 "
                                   "(pDR tiles)");
     if (K < 0 || K > 64) return fail(FLOW_E_INVAL, "K must be in [0, 64] (0 = resident or built-in)");
@@ -246,16 +247,15 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
         return fail(FLOW_E_INVAL, "rows (tile modes: extended tile width) must be 0 or in [16, 512]");
     if (pdr_sweeps < -1) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= -1 (-1: ALG1)");
     if (pdr_sweeps == -1 && mode != 5 && mode != 6) return fail(FLOW_E_INVAL, "ALG1 modes: 5 / 6 (tiles of 1024 / 512 threads)");
-    if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6 && mode != 10 && mode != 11 && mode != 12 && mode != 13)
+    if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6 && mode < 10)
         return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads), 10 / 11 (the same "
                                   "with two cells of each colour per thread), 12 / 13 (wave-row tiles of 128 x 32 / "
-                                  "128 x 48 cells)");
-    if (pdr_sweeps > 0 && (mode == 10 || mode == 11 || mode == 13) && has_w)
-        return fail(FLOW_E_INVAL, "pDR modes 10, 11 and 13 need beta = 0");
-    if (pdr_sweeps == 0 && (mode == 5 || mode == 10 || mode == 11))
-        return fail(FLOW_E_INVAL, "modes 5, 10 and 11 are pDR modes");
-    if (pdr_sweeps != 0 && ((mode > 6 && mode < 10) || mode == 14 || (pdr_sweeps < 0 && mode >= 12)))
-        return fail(FLOW_E_INVAL, "modes 7, 8, 9 and 14 are ADMM modes (12 and 13: ADMM or pDR)");
+                                  "128 x 48 cells), 14 / 15 (wave-row tiles of 64 x 48 / 64 x 32 cells)");
+    if (pdr_sweeps > 0 && (mode == 10 || mode == 11 || mode == 13 || mode == 14) && has_w)
+        return fail(FLOW_E_INVAL, "pDR modes 10, 11, 13 and 14 need beta = 0");
+    if (pdr_sweeps == 0 && (mode == 5 || mode == 10 || mode == 11 || mode == 15))
+        return fail(FLOW_E_INVAL, "modes 5, 10, 11 and 15 are pDR modes");
+    if (pdr_sweeps != 0 && mode > 6 && mode < 10) return fail(FLOW_E_INVAL, "modes 7, 8 and 9 are ADMM modes");
     TunedChoice c;
     c.mode = mode;
     c.K = K;

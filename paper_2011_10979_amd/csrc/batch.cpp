@@ -203,11 +203,11 @@ bool pd_stage_resident(const BatchPlan& P, const BStage& S, bool hw, int nt) {
 }
 
 // Work-group codes a pDR / ALG1 stage may take: 1024 and 512 threads with one cell of each colour
-// per thread; pDR also the wave-row tiles of 128 x 32 cells, and without the w block 1024 and 512
-// threads with two cells of each colour and the wave-row tiles of 128 x 48.
+// per thread; pDR also the wave-row tiles of 128 x 32 and 64 x 32 cells, and without the w block
+// 1024 and 512 threads with two cells of each colour and the wave-row tiles of 128 x 48 and 64 x 48.
 std::vector<int> pd_codes(const flow_params& p) {
-    if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513, 4098, 6145};
-    if (p.scheme == FLOW_PDR) return {1024, 512, 4098};
+    if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513, 4098, 6145, 3074, 2050};
+    if (p.scheme == FLOW_PDR) return {1024, 512, 4098, 2050};
     return {1024, 512};
 }
 

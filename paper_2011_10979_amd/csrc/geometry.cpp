@@ -47,17 +47,18 @@ bool tb_fits(bool has_w, int nt, int64_t eh, int64_t ew) {
 
 // pDR / ALG1 tiles: work-group codes 512 / 1024 (one red and one black cell per thread), 2048 (1024
 // threads with two cells of each colour), 513 (512 threads with two of each), and the pDR wave-row
-// codes 4098 / 6145 (1024 threads; regions of at most 128 columns and 32 / 48 rows)
-bool is_pd_rows_code(int nt) { return nt == 4098 || nt == 6145; }
+// codes (1024 threads): 4098 / 6145 with a cell pair per lane (regions of at most 128 columns and
+// 32 / 48 rows) and 2050 / 3074 with one cell per lane (at most 64 columns and 32 / 48 rows)
+bool is_pd_rows_code(int nt) { return nt == 4098 || nt == 6145 || nt == 2050 || nt == 3074; }
+int pd_rows_width(int nt) { return (nt == 2050 || nt == 3074) ? kWave : 2 * kWave; }
 
 int pdr_tb_capacity(bool, int nt) {
-    if (nt == 4098) return 4096;
-    if (nt == 6145) return 6144;
+    if (is_pd_rows_code(nt)) return nt - (nt & 3);   // 4096, 6144, 2048, 3072
     return nt == 513 ? 2048 : 2 * nt;
 }
 
 bool pd_fits(bool has_w, int nt, int64_t eh, int64_t ew) {
-    if (is_pd_rows_code(nt)) return ew <= 2 * kWave && eh * 2 * kWave <= pdr_tb_capacity(has_w, nt);
+    if (is_pd_rows_code(nt)) return ew <= pd_rows_width(nt) && eh * pd_rows_width(nt) <= pdr_tb_capacity(has_w, nt);
     return eh * ew <= pdr_tb_capacity(has_w, nt);
 }
 

@@ -141,6 +141,7 @@ int pdr_tb_capacity(bool has_w, int nt);                  // nt: 1024 or 512 thr
                                                           // tiles of 128 x 32 / 128 x 48 cells (6145:
                                                           // beta = 0)
 bool is_pd_rows_code(int nt);
+int pd_rows_width(int nt);                                // widest region of a pDR wave-row code
 // an extended region of eh x ew cells fits the pDR / ALG1 tile kernel of work-group code nt
 bool pd_fits(bool has_w, int nt, int64_t eh, int64_t ew);
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);

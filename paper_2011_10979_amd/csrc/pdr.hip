@@ -127,11 +127,12 @@ __global__ __launch_bounds__(256) void pdr_final_kernel(PdrArgs a) {
     const float dv0 = a.v0 ? vt - a.v0[o] : vt;
     const float rho = It + a.beta * wt + Ix * du0 + Iy * dv0;
     // eq:resolvent: the step along e is -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
-    // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
+    // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0);
+    // 1 / |e|^2 is the hardware reciprocal (within 1 ulp): the same in every pDR kernel
     const float sl = a.sigma * a.lam;
     float step = 0.f, theta = 0.f;
     if (e2 > 0.f) {
-        step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+        step = __builtin_amdgcn_fmed3f(-rho * __builtin_amdgcn_rcpf(e2), -sl, sl);
         theta = -step * (1.f / a.sigma);
     }
     // X bar + J(X~) - X+ with J(X~) = X~ + step e and X~ = 2 X+ - X bar is X+ + step e (one rounding)

@@ -182,10 +182,10 @@ __device__ __forceinline__ void pdr_rows(const PdrTbArgs& a, const PdrTbLevel& L
         }
     };
     // half sweep over colour col (0 red, 1 black): in row k that is cell par[k] ^ col of each pair
-    auto half_sweep = [&](int col) {
+    auto half_sweep = [&](int col, int lo, int hi) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if (wv * R + k >= EH) continue;
+            if (wv * R + k < lo || wv * R + k >= hi) continue;
             if ((par[k] ^ col) == 0) update(k, cell_t<0>{});
             else update(k, cell_t<1>{});
         }
@@ -227,10 +227,11 @@ __device__ __forceinline__ void pdr_rows(const PdrTbArgs& a, const PdrTbLevel& L
         const float rho = fmaf(iy, vt - S.lin[2][r][c][lane], fmaf(ix, ut - S.lin[1][r][c][lane],
                                                                   fmaf(beta, wt, S.lin[0][r][c][lane])));
         // eq:resolvent: the step along e is -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
-        // Theta = -step / sigma (both 0 where e = 0)
+        // Theta = -step / sigma (both 0 where e = 0); 1 / |e|^2 is the hardware reciprocal (within
+        // 1 ulp), as in every pDR kernel
         float step = 0.f, theta = 0.f;
         if (e2 > 0.f) {
-            step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+            step = __builtin_amdgcn_fmed3f(-rho * __builtin_amdgcn_rcpf(e2), -sl, sl);
             theta = -step * inv_sigma;
         }
         xb[0][k][c] = fmaf(step, ix, u);
@@ -263,26 +264,31 @@ __device__ __forceinline__ void pdr_rows(const PdrTbArgs& a, const PdrTbLevel& L
         }
     };
 
+    // Shrinking band: at iteration it only the rows of the region shrunk by (2n + 1) it + 1 rows on
+    // each side with a halo can still reach the output tile; the others skip every phase and keep
+    // their state (the halo accounts for what their neighbours then read)
+    const int shr_top = ey0 > 0, shr_bot = ey1 < H;
     for (int it = 0; it < K; ++it) {
+        const int lo = shr_top * ((2 * n + 1) * it + 1), hi = EH - shr_bot * ((2 * n + 1) * it + 1);
         // [b + R]
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if (wv * R + k >= EH) continue;
+            if (wv * R + k < lo || wv * R + k >= hi) continue;
             rhs(k, cell_t<0>{});
             rhs(k, cell_t<1>{});
         }
-        half_sweep(0);
+        half_sweep(0, lo, hi);
         for (int sw = 0; sw < n; ++sw) {
             __syncthreads();
-            half_sweep(1);
+            half_sweep(1, lo, hi);
             __syncthreads();
-            half_sweep(0);
+            half_sweep(0, lo, hi);
         }
         __syncthreads();
         // [D]
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            if (wv * R + k >= EH) continue;
+            if (wv * R + k < lo || wv * R + k >= hi) continue;
             dual(k, cell_t<0>{}, it + 1 == K);
             dual(k, cell_t<1>{}, it + 1 == K);
         }
@@ -343,6 +349,256 @@ void launch_rows_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
     else hipLaunchKernelGGL((pdr_rows_kernel<HAS_W, NW, R>), dim3(grid), dim3(NW * 64), 0, s, a);
 }
 
+// The same iteration on regions of at most 64 columns, one cell per lane and row: lanes alternate
+// in colour, so a half sweep computes every lane and keeps the update only in the lanes of its
+// colour.  Half the lanes idle in the sweeps, but 12 values per cell in registers (I_t, u0, v0 and
+// I_x in LDS, read once per iteration) let three rows per lane fit 64 VGPRs, two 1024-thread
+// work-groups per CU.
+template <bool HAS_W, int NW, int R>
+struct PdrRow1Lds {
+    static constexpr int NX = HAS_W ? 3 : 2;
+    float lin[4][NW * R][64];                           // I_t, u0, v0, I_x
+    float xtop[NX][NW + 2][64];                         // [w + 1]: wavefront w's top / bottom row of X
+    float xbot[NX][NW + 2][64];
+    float ybot[NX][NW + 2][64];                         // y components of wavefront w's bottom row
+};
+
+template <bool HAS_W, int NW, int R>
+__device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& L, int y0, int x0, int th, int tw,
+                                          PdrRow1Lds<HAS_W, NW, R>& S) {
+    constexpr int NX = HAS_W ? 3 : 2, NY = 2 * NX;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int H = L.H, W = L.W;
+    const int64_t ld = L.ld;
+    const int K = a.K, n = a.sweeps;
+    const int hlu = pdr_halo_lo(n, K), hrd = pdr_halo_hi(n, K);
+    const int ey0 = max(y0 - hlu, 0), ex0 = max(x0 - hlu, 0);
+    const int ey1 = min(y0 + th + hrd, H), ex1 = min(x0 + tw + hrd, W);
+    const int EW = ex1 - ex0, EH = ey1 - ey0;          // at most 64 and NW R (the planners' bound)
+    const float sigma = a.sigma, tau = a.tau, stt = a.stt, lam = a.lam, beta = a.beta;
+    const float sl = sigma * lam, inv_sigma = 1.f / sigma;
+    const int gj = ex0 + lane;
+    const float fl = gj > 0 ? 1.f : 0.f, fr = gj < W - 1 ? 1.f : 0.f;
+
+    float x[NX][R], xb[NX][R], y[NY][R], bb[NX][R], Iy[R], rden[R];
+    float fu[R], fd[R];                                 // wavefront-uniform
+    int par[R];                                         // colour of lane 0 of the row (0 red)
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = wv * R + k, gi = ey0 + r;
+        fu[k] = gi > 0 ? 1.f : 0.f;
+        fd[k] = gi < H - 1 ? 1.f : 0.f;
+        par[k] = (gi + ex0) & 1;
+        rden[k] = 1.f / (1.f + stt * (((fl + fr) + fu[k]) + fd[k]));
+#pragma unroll
+        for (int f = 0; f < NX; ++f) x[f][k] = xb[f][k] = bb[f][k] = 0.f;
+#pragma unroll
+        for (int f = 0; f < NY; ++f) y[f][k] = 0.f;
+        Iy[k] = 0.f;
+        float lt = 0.f, lu = 0.f, lv = 0.f, lx = 0.f;
+        if (r < EH && lane < EW) {
+            const int64_t o = (int64_t)gi * ld + gj;
+#pragma unroll
+            for (int f = 0; f < NX; ++f) {
+                x[f][k] = gload(L.x_in[f], o);
+                xb[f][k] = gload(L.xb_in[f], o);
+            }
+#pragma unroll
+            for (int f = 0; f < NY; ++f) y[f][k] = gload(L.y_in[f], o);
+            lx = gload(L.Ix, o);
+            Iy[k] = gload(L.Iy, o);
+            lt = gload(L.It, o);
+            lu = gload(L.u0, o);
+            lv = gload(L.v0, o);
+        }
+        S.lin[0][r][lane] = lt;
+        S.lin[1][r][lane] = lu;
+        S.lin[2][r][lane] = lv;
+        S.lin[3][r][lane] = lx;
+    }
+#pragma unroll
+    for (int f = 0; f < NX; ++f) {
+        S.xtop[f][wv + 1][lane] = x[f][0];
+        S.xbot[f][wv + 1][lane] = x[f][R - 1];
+        S.ybot[f][wv + 1][lane] = y[2 * f + 1][R - 1];
+        if (wv == 0) {
+            S.xtop[f][0][lane] = S.xtop[f][NW + 1][lane] = 0.f;
+            S.xbot[f][0][lane] = S.xbot[f][NW + 1][lane] = 0.f;
+            S.ybot[f][0][lane] = S.ybot[f][NW + 1][lane] = 0.f;
+        }
+    }
+    __syncthreads();
+
+    auto xu = [&](int f, int k) { return k > 0 ? x[f][k > 0 ? k - 1 : 0] : S.xbot[f][wv][lane]; };
+    auto xd = [&](int f, int k) { return k + 1 < R ? x[f][k + 1 < R ? k + 1 : k] : S.xtop[f][wv + 2][lane]; };
+    // half sweep over colour col (0 red, 1 black): every lane computes the update of its cell, the
+    // lanes of that colour keep it
+    auto half_sweep = [&](int col, int lo, int hi) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (wv * R + k < lo || wv * R + k >= hi) continue;
+            const bool mine = ((par[k] + lane) & 1) == col;
+            float nl[NX], nr[NX], nu[NX], nd[NX];
+#pragma unroll
+            for (int f = 0; f < NX; ++f) {
+                nl[f] = from_left(x[f][k]);
+                nr[f] = from_right(x[f][k]);
+                nu[f] = xu(f, k);
+                nd[f] = xd(f, k);
+            }
+#pragma unroll
+            for (int f = 0; f < NX; ++f) {
+                const float xo = x[f][k];
+                float sm = fl * (nl[f] - xo);
+                sm = fmaf(fr, nr[f] - xo, sm);
+                sm = fmaf(fu[k], nu[f] - xo, sm);
+                sm = fmaf(fd[k], nd[f] - xo, sm);
+                const float upd = fmaf(fmaf(stt, sm, bb[f][k] - xo), rden[k], xo);
+                x[f][k] = mine ? upd : xo;
+            }
+            if (k == 0) {
+#pragma unroll
+                for (int f = 0; f < NX; ++f) S.xtop[f][wv + 1][lane] = x[f][0];
+            }
+            if (k == R - 1) {
+#pragma unroll
+                for (int f = 0; f < NX; ++f) S.xbot[f][wv + 1][lane] = x[f][R - 1];
+            }
+        }
+    };
+
+    // Shrinking band: at iteration it only the rows of the region shrunk by (2n + 1) it + 1 rows on
+    // each side with a halo can still reach the output tile; the others skip every phase and keep
+    // their state (the halo accounts for what their neighbours then read)
+    const int shr_top = ey0 > 0, shr_bot = ey1 < H;
+    for (int it = 0; it < K; ++it) {
+        const int lo = shr_top * ((2 * n + 1) * it + 1), hi = EH - shr_bot * ((2 * n + 1) * it + 1);
+        // [b + R]: b = X bar + sigma div y bar
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (wv * R + k < lo || wv * R + k >= hi) continue;
+#pragma unroll
+            for (int f = 0; f < NX; ++f) {
+                const float yox = y[2 * f][k], yoy = y[2 * f + 1][k];
+                const float ynx = from_left(yox);
+                const float yny = k > 0 ? y[2 * f + 1][k > 0 ? k - 1 : 0] : S.ybot[f][wv][lane];
+                float d = fr * yox;
+                d = fmaf(-fl, ynx, d);
+                d = fmaf(fd[k], yoy, d);
+                d = fmaf(-fu[k], yny, d);
+                bb[f][k] = fmaf(sigma, d, xb[f][k]);
+            }
+        }
+        half_sweep(0, lo, hi);
+        for (int sw = 0; sw < n; ++sw) {
+            __syncthreads();
+            half_sweep(1, lo, hi);
+            __syncthreads();
+            half_sweep(0, lo, hi);
+        }
+        __syncthreads();
+        // [D]: resolvent at X~ = 2 X+ - X bar, dual update from grad X+ (right / down neighbours)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = wv * R + k;
+            if (r < lo || r >= hi) continue;
+            float xo[NX], gx[NX], gy[NX];
+#pragma unroll
+            for (int f = 0; f < NX; ++f) {
+                xo[f] = x[f][k];
+                gx[f] = fr * (from_right(xo[f]) - xo[f]);
+                gy[f] = fd[k] * (xd(f, k) - xo[f]);
+            }
+            const float u = xo[0], v = xo[1];
+            const float ut = 2.f * u - xb[0][k], vt = 2.f * v - xb[1][k];
+            float w = 0.f, wt = 0.f;
+            if constexpr (HAS_W) { w = xo[2]; wt = 2.f * w - xb[2][k]; }
+            const float ix = S.lin[3][r][lane], iy = Iy[k];
+            const float e2 = fmaf(iy, iy, fmaf(ix, ix, beta * beta));
+            const float rho = fmaf(iy, vt - S.lin[2][r][lane], fmaf(ix, ut - S.lin[1][r][lane],
+                                                                    fmaf(beta, wt, S.lin[0][r][lane])));
+            float step = 0.f, theta = 0.f;
+            if (e2 > 0.f) {
+                step = __builtin_amdgcn_fmed3f(-rho * __builtin_amdgcn_rcpf(e2), -sl, sl);
+                theta = -step * inv_sigma;
+            }
+            xb[0][k] = fmaf(step, ix, u);
+            xb[1][k] = fmaf(step, iy, v);
+            if constexpr (HAS_W) xb[2][k] = fmaf(step, beta, w);
+            if (it + 1 == K) {                          // Theta of an output cell: the data dual for the gap
+                const int gi = ey0 + r;
+                if (gi >= y0 && gi < y0 + th && lane < EW && gj >= x0 && gj < x0 + tw)
+                    gstore(L.s_out, (int64_t)gi * ld + gj, theta);
+            }
+            const float t2 = 2.f * tau;
+            const float a1x = fmaf(t2, gx[0], y[0][k]), a1y = fmaf(t2, gy[0], y[1][k]);
+            const float a2x = fmaf(t2, gx[1], y[2][k]), a2y = fmaf(t2, gy[1], y[3][k]);
+            const float nq = fmaf(a2y, a2y, fmaf(a2x, a2x, fmaf(a1y, a1y, a1x * a1x)));
+            const float sq = fminf(1.f, __builtin_amdgcn_rsqf(nq));
+            y[0][k] = fmaf(a1x, sq, -(tau * gx[0]));
+            y[1][k] = fmaf(a1y, sq, -(tau * gy[0]));
+            y[2][k] = fmaf(a2x, sq, -(tau * gx[1]));
+            y[3][k] = fmaf(a2y, sq, -(tau * gy[1]));
+            if constexpr (HAS_W) {
+                const float bx = fmaf(t2, gx[2], y[4][k]), by = fmaf(t2, gy[2], y[5][k]);
+                const float np2 = fmaf(by, by, bx * bx);
+                const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
+                y[4][k] = fmaf(bx, sp, -(tau * gx[2]));
+                y[5][k] = fmaf(by, sp, -(tau * gy[2]));
+            }
+            if (k == R - 1) {
+#pragma unroll
+                for (int f = 0; f < NX; ++f) S.ybot[f][wv + 1][lane] = y[2 * f + 1][R - 1];
+            }
+        }
+        __syncthreads();
+    }
+
+    // write the output tile
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = wv * R + k, gi = ey0 + r;
+        if (r >= EH || gi < y0 || gi >= y0 + th) continue;
+        if (lane >= EW || gj < x0 || gj >= x0 + tw) continue;
+        const int64_t o = (int64_t)gi * ld + gj;
+#pragma unroll
+        for (int f = 0; f < NX; ++f) {
+            gstore(L.x_out[f], o, x[f][k]);
+            gstore(L.xb_out[f], o, xb[f][k]);
+        }
+#pragma unroll
+        for (int f = 0; f < NY; ++f) gstore(L.y_out[f], o, y[f][k]);
+    }
+}
+
+template <bool HAS_W, int NW, int R>
+__global__ __launch_bounds__(NW * 64, 8) void pdr_rows1_kernel(PdrTbArgs a) {
+    __shared__ PdrRow1Lds<HAS_W, NW, R> S;
+    const int t = xcd_tile_pr(blockIdx.x, gridDim.x);
+    if (t >= a.ntiles) return;
+    const int ty = t / a.ntx, tx = t - ty * a.ntx;
+    const int y0 = ty * a.th, x0 = tx * a.tw;
+    pdr_rows1<HAS_W, NW, R>(a, a.lvl, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+}
+
+template <bool HAS_W, int NW, int R>
+__global__ __launch_bounds__(NW * 64, 8) void pdr_rows1_table_kernel(PdrTbArgs a) {
+    __shared__ PdrRow1Lds<HAS_W, NW, R> S;
+    const int per = (a.ntiles + 7) >> 3;
+    const int x = blockIdx.x & 7, y = blockIdx.x >> 3;
+    const int t = x * per + y;
+    if (y >= per || t >= a.ntiles) return;
+    const TbTile T = a.tiles[t];
+    pdr_rows1<HAS_W, NW, R>(a, a.levels[2 * T.level + a.dir], T.y0, T.x0, T.th, T.tw, S);
+}
+
+template <bool HAS_W, int NW, int R>
+void launch_rows1_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
+    if (a.tiles) hipLaunchKernelGGL((pdr_rows1_table_kernel<HAS_W, NW, R>), dim3(grid), dim3(NW * 64), 0, s, a);
+    else hipLaunchKernelGGL((pdr_rows1_kernel<HAS_W, NW, R>), dim3(grid), dim3(NW * 64), 0, s, a);
+}
+
 }  // namespace
 
 void launch_pdr_rows(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
@@ -353,6 +609,11 @@ void launch_pdr_rows(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     } else if (nt == 4098) {                 // 128 x 32 cells
         if (has_w) launch_rows_shape<true, 16, 2>(a, grid, s);
         else launch_rows_shape<false, 16, 2>(a, grid, s);
+    } else if (nt == 3074) {                 // 64 x 48 cells, one per lane and row, beta = 0 only
+        if (!has_w) launch_rows1_shape<false, 16, 3>(a, grid, s);
+    } else if (nt == 2050) {                 // 64 x 32 cells, one per lane and row
+        if (has_w) launch_rows1_shape<true, 16, 2>(a, grid, s);
+        else launch_rows1_shape<false, 16, 2>(a, grid, s);
     }
 }
 

@@ -236,10 +236,11 @@ __device__ __forceinline__ void pdr_tile(const PdrTbArgs& a, const PdrTbLevel& L
             const float e2 = fmaf(iy, iy, fmaf(ix, ix, beta * beta));
             const float rho = fmaf(iy, vt - v0[c][k], fmaf(ix, ut - u0[c][k], fmaf(beta, wt, It[c][k])));
             // eq:resolvent: the step along e is -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
-            // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0)
+            // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0);
+            // 1 / |e|^2 is the hardware reciprocal (within 1 ulp): the same in every pDR kernel
             float step = 0.f, theta = 0.f;
             if (e2 > 0.f) {
-                step = __builtin_amdgcn_fmed3f(-rho / e2, -sl, sl);
+                step = __builtin_amdgcn_fmed3f(-rho * __builtin_amdgcn_rcpf(e2), -sl, sl);
                 theta = -step * inv_sigma;
             }
             // X bar + J(X~) - X+ with J(X~) = X~ + step e, X~ = 2 X+ - X bar: X+ + step e

@@ -372,7 +372,8 @@ int enqueue_admm_iters(const LevelPlanes& L, const flow_params& p, const LevelTb
 
 int g_pdr_mode = 0;   // pDR iteration kernel: 0 built-in (tiles), 1 three-pass, 5 tiles of 1024 threads, 6 of 512,
                       // 10 / 11 tiles of 1024 / 512 threads with two cells of each colour per thread (beta = 0),
-                      // 12 / 13 wave-row tiles of 128 x 32 / 128 x 48 cells (13: beta = 0)
+                      // 12 / 13 wave-row tiles of 128 x 32 / 128 x 48 cells (13: beta = 0), 14 / 15 of
+                      // 64 x 48 / 64 x 32 cells, one per lane (14: beta = 0)
 int g_pdr_k = 0;      // iterations per pDR tile launch (0 = built-in)
 
 std::string pd_tune_key(int H, int W, const flow_params& p) {
@@ -398,11 +399,12 @@ PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std:
     }
     if (alg1 && mode == 1) mode = 5;                 // ALG1 has no three-pass form
     if ((mode == 10 || mode == 11) && (alg1 || hw)) mode -= 5;   // two cells per colour: pDR without w only
-    if ((mode == 12 || mode == 13) && alg1) mode = 5;            // wave-row tiles: pDR only
+    if (mode >= 12 && alg1) mode = 5;                            // wave-row tiles: pDR only
     if (mode == 13 && hw) mode = 12;                             // 128 x 48 cells without the w block only
+    if (mode == 14 && hw) mode = 15;                             // 64 x 48 cells without the w block only
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
     const int nt = mode == 6 ? 512 : mode == 10 ? 2048 : mode == 11 ? 513 : mode == 12 ? 4098 : mode == 13 ? 6145
-                 : 1024;
+                 : mode == 14 ? 3074 : mode == 15 ? 2050 : 1024;
     const int kdef = alg1 ? kAlg1DefaultK : kPdrDefaultK;
     const int k0 = K > 0 ? K : kdef;
     PdrTbPlan T = plan_pd_tiles(H, W, hw, pd_halo(p, k0), k0, 0, nt);
@@ -654,12 +656,12 @@ flow_status flow_tune_set(const char* key, int64_t value) {
         return FLOW_OK;
     }
     if (std::strcmp(key, "pdr_mode") == 0) {
-        if (value != 0 && value != 1 && value != 5 && value != 6 && value != 10 && value != 11 && value != 12 &&
-            value != 13)
+        if (value != 0 && value != 1 && value != 5 && value != 6 && (value < 10 || value > 15))
             return fail(FLOW_E_INVAL, "pdr_mode: 0 built-in, 1 three-pass, 5 tiles of 1024 threads, 6 of 512, "
                                       "10 / 11 tiles of 1024 / 512 threads with two cells of each colour per "
                                       "thread (beta = 0; 5 / 6 otherwise), 12 / 13 wave-row tiles of 128 x 32 / "
-                                      "128 x 48 cells (13: beta = 0; 12 otherwise)");
+                                      "128 x 48 cells (13: beta = 0; 12 otherwise), 14 / 15 wave-row tiles of "
+                                      "64 x 48 / 64 x 32 cells (14: beta = 0; 15 otherwise)");
         g_pdr_mode = (int)value;
         return FLOW_OK;
     }
@@ -993,10 +995,12 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     const int64_t halo = pd_halo(*p, iters);
     const int64_t region = std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo);
     // regions above the 1024-thread kernel's capacity run the large pDR tiles (beta = 0); with the
-    // pdr_mode knob at 12 / 13, pDR runs the wave-row tiles of 128 x 32 / 128 x 48 cells
+    // pdr_mode knob at 12 / 13 / 14 / 15, pDR runs the wave-row tiles of 128 x 32 / 128 x 48 / 64 x 48
+    // / 64 x 32 cells
     const bool large = p->scheme == FLOW_PDR && !hw && region > pdr_tb_capacity(hw, 1024);
     int nt = large ? 2048 : 1024;
     if (p->scheme == FLOW_PDR && (g_pdr_mode == 12 || g_pdr_mode == 13)) nt = g_pdr_mode == 13 && !hw ? 6145 : 4098;
+    if (p->scheme == FLOW_PDR && (g_pdr_mode == 14 || g_pdr_mode == 15)) nt = g_pdr_mode == 14 && !hw ? 3074 : 2050;
     if (!pd_fits(hw, nt, std::min<int64_t>(H, tile_h + halo), std::min<int64_t>(W, tile_w + halo)))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,

@@ -139,19 +139,20 @@ PdrTbPlan plan_pd_tiles(int H, int W, bool hw, int halo, int K, int ew_target, i
         P.tw = W;
         return P;
     }
-    // 32 x 32, 64 x 32 or 64 x 64 regions; the wave-row tiles 128 columns wide
-    if (ew_target <= 0 || (rows && ew_target > 2 * kWave)) ew_target = rows ? 2 * kWave : nt == 512 ? 32 : 64;
+    // 32 x 32, 64 x 32 or 64 x 64 regions; the wave-row tiles 128 or 64 columns wide
+    if (ew_target <= 0 || (rows && ew_target > pd_rows_width(nt))) ew_target = rows ? pd_rows_width(nt) : nt == 512 ? 32 : 64;
     const int ew = std::min(W, std::max(ew_target, halo + 8));
     const int tw = (ew >= W) ? W : ew - halo;
     const int ext_w = std::min(W, tw + halo);
-    const int eh = rows ? std::min(cap / ext_w, cap / (2 * kWave)) : cap / ext_w;
+    const int eh = rows ? std::min(cap / ext_w, cap / pd_rows_width(nt)) : cap / ext_w;
     const int th = (eh >= H) ? H : eh - halo;
     if ((tw < 8 && tw != W) || th < 2 || !pd_fits(hw, nt, std::min(H, th + halo), ext_w)) return P;
     P.tb = true;
     P.K = K;
     // pDR and ALG1 tiles (70 / 67 VGPRs, 80 / 82 with w; two cells of each colour per thread: 128;
-    // wave-row tiles: 104 / 128): one 1024-thread work-group per CU, two or three of 512 threads
-    P.th = balanced_height(H, W, th, tw, nt == 512 ? (hw ? 2 : 3) : nt == 513 ? 2 : 1);
+    // wave-row tiles with a cell pair per lane: 104 / 128, with one cell per lane: 51 / 64): one
+    // 1024-thread work-group per CU (two of the one-cell wave-row tiles), two or three of 512 threads
+    P.th = balanced_height(H, W, th, tw, nt == 512 ? (hw ? 2 : 3) : (nt == 513 || nt == 2050 || nt == 3074) ? 2 : 1);
     P.tw = tw;
     return P;
 }

@@ -468,9 +468,9 @@ void launch_admm_tb(const TbArgs& a, bool hw, int nt, int grid, hipStream_t s) {
 // index LDS by the region's cells), and the tiles with two cells of each colour run without the w
 // block only
 static void check_pd_codes(bool has_w, int nt) {
-    check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513 || nt == 4098 || nt == 6145,
+    check(nt == 512 || nt == 1024 || nt == 2048 || nt == 513 || is_pd_rows_code(nt),
           "pDR / ALG1 tile launch: work-group code");
-    check((nt != 2048 && nt != 513 && nt != 6145) || !has_w, "pDR tiles for beta = 0 launched with w");
+    check((nt != 2048 && nt != 513 && nt != 6145 && nt != 3074) || !has_w, "pDR tiles for beta = 0 launched with w");
 }
 static void check_pd_region(const PdrTbLevel& L, int th, int tw, bool has_w, int nt, int halo) {
     const int64_t eh = std::min<int64_t>(L.H, (int64_t)th + halo);

@@ -145,9 +145,9 @@ static void test_planners(std::mt19937& rng) {
         }
         // pDR / ALG1 tiles
         const int halo = 3 * (1 + rng() % 4);
-        const int pnt[] = {512, 1024, 2048, 513, 4098, 6145};
+        const int pnt[] = {512, 1024, 2048, 513, 4098, 6145, 3074, 2050};
         const PdrTbPlan R = plan_pd_tiles(H, W, hw, halo, 1 + rng() % 4, rng() % 2 ? 0 : 32 + rng() % 64,
-                                          pnt[rng() % 6]);
+                                          pnt[rng() % 8]);
         if (R.tb && !R.resident) {
             CHECK(R.th >= 2 && (R.tw >= 8 || R.tw == W), "pDR tile %dx%d of a level %d wide", R.th, R.tw, W);
             const int ext_w = std::min(W, R.tw + halo), ext_h = std::min(H, R.th + halo);
@@ -408,7 +408,7 @@ static void test_pd_solves(std::mt19937& rng) {
         float *u, *v;
         hipMalloc(&u, sizeof(float) * H * W);
         hipMalloc(&v, sizeof(float) * H * W);
-        for (int mode : {0, 1, 5, 6, 10, 11, 12, 13})
+        for (int mode : {0, 1, 5, 6, 10, 11, 12, 13, 14, 15})
             for (int K : {0, 1, 3}) {
                 OK(flow_tune_set("pdr_mode", mode));
                 OK(flow_tune_set("pdr_k", K));

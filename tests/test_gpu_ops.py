@@ -216,8 +216,9 @@ def test_large_pdr_tiles_equal_the_1024_thread_tiles(shape, tile, K, small):
 
 
 def _pdr_row_cases():
-    """(shape, tile, K, sweeps, beta, mode): wave-row pDR tiles (mode 12: 128 x 32 cells, 13: 128 x 48)
-    whose extended region also fits the general tiles used as reference (4096 cells, 2048 with w)."""
+    """(shape, tile, K, sweeps, beta, mode): wave-row pDR tiles (mode 12: 128 x 32 cells, 13: 128 x 48,
+    14: 64 x 48 with one cell per lane, 15: 64 x 32) whose extended region also fits the general
+    tiles used as reference (4096 cells, 2048 with w)."""
     cases = []
     for shape, tile, K, n in [((101, 250), (19, 50), 2, 1), ((130, 140), (17, 80), 3, 1), ((60, 61), (60, 61), 4, 1),
                               ((45, 200), (20, 115), 1, 1), ((90, 170), (10, 90), 1, 2), ((33, 128), (33, 128), 6, 1),
@@ -225,8 +226,8 @@ def _pdr_row_cases():
         halo = (2 * n + 1) * K * 2 + 1
         eh, ew = min(shape[0], tile[0] + halo), min(shape[1], tile[1] + halo)
         for beta in (0.0, 0.05):
-            for mode, rows in ((12, 32), (13, 48)):
-                if ew <= 128 and eh <= rows and eh * ew <= (2048 if beta > 0 else 4096):
+            for mode, rows, cols in ((12, 32, 128), (13, 48, 128), (14, 48, 64), (15, 32, 64)):
+                if ew <= cols and eh <= rows and eh * ew <= (2048 if beta > 0 else 4096):
                     cases.append((shape, tile, K, n, beta, mode))
     return cases
 
@@ -235,7 +236,7 @@ def _pdr_row_cases():
 def test_pdr_row_tiles_equal_the_general_tiles(shape, tile, K, sweeps, beta, mode):
     """The wave-row pDR tiles (cell pairs per lane, registers per row, DPP neighbours) evaluate the
     general pDR tiles' operations in the same order: K iterations of the same tiles of the same state
-    agree bit for bit (with w, mode 13 runs the 128 x 32 shape)."""
+    agree bit for bit (with w, modes 13 and 14 run the 128 x 32 and 64 x 32 shapes)."""
     print_case("pdr rows vs general tiles", shape=shape, tile=tile, K=K, sweeps=sweeps, beta=beta, mode=mode)
     rng = np.random.default_rng(zlib.crc32(repr(("pdrrows", shape, tile, K, sweeps, beta)).encode()))
     st = random_pdr_state(rng, shape, beta)

@@ -267,7 +267,8 @@ def test_every_kernel_mode_keeps_parity(ctx, mode, k):
 @pytest.mark.parametrize("mode,k,beta", [(1, 0, 0.0), (5, 1, 0.0), (5, 2, 0.0), (5, 3, 0.05), (5, 2, 0.05),
                                          (6, 1, 0.0), (6, 2, 0.05), (10, 1, 0.0), (10, 2, 0.0), (10, 3, 0.0),
                                          (10, 2, 0.05), (11, 2, 0.0), (11, 4, 0.0), (11, 2, 0.05), (12, 2, 0.0),
-                                         (12, 1, 0.05), (13, 2, 0.0), (13, 3, 0.0), (13, 2, 0.05)])
+                                         (12, 1, 0.05), (13, 2, 0.0), (13, 3, 0.0), (13, 2, 0.05), (14, 2, 0.0),
+                                         (14, 3, 0.0), (14, 2, 0.05), (15, 1, 0.0), (15, 2, 0.05)])
 def test_every_pdr_kernel_mode_keeps_parity(ctx, mode, k, beta):
     """pDR with the three-pass iteration and with K-iteration tiles of 1024 and 512 threads, one or
     two cells of each colour per thread (K = 1 .. 4; the coarsest levels resident; two cells per
@@ -286,7 +287,7 @@ def test_every_pdr_kernel_mode_keeps_parity(ctx, mode, k, beta):
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_pdr_tile_shapes_give_bitwise_the_same_solve(ctx, k):
     """Every pDR tile shape (1024 or 512 threads, one or two cells of each colour per thread, wave-row
-    tiles of 128 x 32 and 128 x 48 cells) forms
+    tiles of 128 x 32, 128 x 48, 64 x 48 and 64 x 32 cells) forms
     each cell's update with the same expressions on the same operands, and tiling never changes
     them: with the same K per launch the solves agree bit for bit."""
     print(f"[case] pDR tile shapes K {k}", flush=True)
@@ -294,14 +295,14 @@ def test_pdr_tile_shapes_give_bitwise_the_same_solve(ctx, k):
     I0, I1 = to_dev(f32(pair.I0)), to_dev(f32(pair.I1))
     out = {}
     try:
-        for mode in (5, 6, 10, 11, 12, 13):
+        for mode in (5, 6, 10, 11, 12, 13, 14, 15):
             fm.set_tuning("pdr_mode", mode)
             fm.set_tuning("pdr_k", k)
             out[mode] = ctx.solve(I0, I1, fm.Params(scheme="pdr", levels=3, warps=2, iters=20))
     finally:
         fm.set_tuning("pdr_mode", 0)
         fm.set_tuning("pdr_k", 0)
-    for mode in (6, 10, 11, 12, 13):
+    for mode in (6, 10, 11, 12, 13, 14, 15):
         assert torch.equal(out[mode][0], out[5][0]) and torch.equal(out[mode][1], out[5][1]), mode
         assert out[mode][2]["energy"] == out[5][2]["energy"], mode
 

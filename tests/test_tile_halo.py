@@ -130,12 +130,13 @@ def test_tile_halo_is_tight(name, beta, n, K, side):
 
 
 # The kernels go further than the halo: after iteration m of a launch only the extended region
-# shrunk by m rows on every side that has a halo can still reach the output, so a wavefront whose
-# rows all lie outside that band skips the iteration and its rows keep stale values.  Stale values
-# are one kind of garbage; here the rows outside the band are replaced by random values after
-# every iteration, and the output tile must still equal the undisturbed run bit for bit.  With a
-# band one row narrower on either side some output value changes (for K >= 2: with one iteration
-# the row above the output tile can no longer reach it), so the band is the narrowest that works.
+# shrunk by m rows on every side that has a halo can still reach the output, so rows outside that
+# band skip the iteration and keep stale values (a whole wavefront's rows in the general ADMM
+# tiles, single rows in the wave-row tiles).  Stale values are one kind of garbage; here the rows
+# outside the band are replaced by random values after every iteration, and the output tile must
+# still equal the undisturbed run bit for bit.  With a band one row narrower on either side some
+# output value changes (for K >= 2: with one iteration the row above the output tile can no longer
+# reach it), so the band is the narrowest that works.
 
 def _band_result(step, st, L, K, tile, lo, hi, rng, extra=(0, 0)):
     """Like _tile_result, and after iteration m (1-based) every row outside the extended region
@@ -184,5 +185,101 @@ def test_shrinking_band_is_tight(name, beta, n, K, extra):
     lo, hi = _halo(name, K, n)
     tile = (16, 17, 8, 9)
     got = _band_result(step, st, L, K, tile, (lo, lo), (hi, hi), rng, extra)
+    y0, x0, th, tw = tile
+    assert any(not np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]) for k, v in got.items())
+
+
+# The pDR wave-row tiles skip rows in every phase of an iteration (b, the half sweeps, the resolvent
+# and dual step): a skipped row keeps its state and its neighbours in the band read that state.
+# Modelled here phase by phase with the oracle's operators: at iteration m (0-based) only the rows
+# of the extended region shrunk by (2n + 1) m + 1 rows on every side with a halo are computed, and
+# the output tile still equals the undisturbed run bit for bit; one row more on either side changes
+# it.
+
+def _pdr_step_rows(st, L, beta, n, rows):
+    """schemes.pdr_step where only the rows flagged in `rows` are computed, phase by phase."""
+    sigma, tau = 2.0, 0.4
+    Ix, Iy, It = L["Ix"], L["Iy"], L["It"]
+    stt = sigma * tau
+    has_w = beta != 0.0
+    M = rows[:, None]
+    red = schemes.red_mask(SHAPE)
+    black = ~red
+
+    def sweep(x, b):
+        for _ in range(n):
+            for col in (red, black, black, red):
+                x = np.where(M, schemes.gs_colour_update(x, b, stt, col), x)
+        return x
+
+    w = sweep(st["w"], st["wb"] + sigma * schemes.div(st["pbx"], st["pby"])) if has_w else st["w"]
+    u = sweep(st["u"], st["ub"] + sigma * schemes.div(st["qb1x"], st["qb1y"]))
+    v = sweep(st["v"], st["vb"] + sigma * schemes.div(st["qb2x"], st["qb2y"]))
+    Jw, Ju, Jv, _ = schemes.resolvent(2 * w - st["wb"], 2 * u - st["ub"], 2 * v - st["vb"], Ix, Iy, It, beta, LAM,
+                                      sigma)
+
+    def keep(new, old):
+        return np.where(M, new, old)
+    gwx, gwy = schemes.grad(w)
+    gux, guy = schemes.grad(u)
+    gvx, gvy = schemes.grad(v)
+    ppx, ppy = (schemes.proj_p(st["pbx"] + 2 * tau * gwx, st["pby"] + 2 * tau * gwy) if has_w
+                else (st["pbx"], st["pby"]))
+    q1x, q1y, q2x, q2y = schemes.proj_q(st["qb1x"] + 2 * tau * gux, st["qb1y"] + 2 * tau * guy,
+                                        st["qb2x"] + 2 * tau * gvx, st["qb2y"] + 2 * tau * gvy)
+    return dict(w=w, u=u, v=v, wb=keep(st["wb"] + Jw - w, st["wb"]) if has_w else st["wb"],
+                ub=keep(st["ub"] + Ju - u, st["ub"]), vb=keep(st["vb"] + Jv - v, st["vb"]),
+                pbx=keep(ppx - tau * gwx, st["pbx"]) if has_w else st["pbx"],
+                pby=keep(ppy - tau * gwy, st["pby"]) if has_w else st["pby"],
+                qb1x=keep(q1x - tau * gux, st["qb1x"]), qb1y=keep(q1y - tau * guy, st["qb1y"]),
+                qb2x=keep(q2x - tau * gvx, st["qb2x"]), qb2y=keep(q2y - tau * gvy, st["qb2y"]))
+
+
+def _pdr_row_band_result(st, L, beta, n, K, tile, rng, extra=(0, 0)):
+    lo, hi = _halo("pdr", K, n)
+    y0, x0, th, tw = tile
+    H, W = SHAPE
+    ey0, ex0 = max(y0 - lo, 0), max(x0 - lo, 0)
+    ey1, ex1 = min(y0 + th + hi, H), min(x0 + tw + hi, W)
+
+    def cut(a):
+        b = rng.normal(scale=3.0, size=SHAPE)
+        b[ey0:ey1, ex0:ex1] = a[ey0:ey1, ex0:ex1]
+        return b
+
+    s = {k: cut(v) for k, v in st.items()}
+    lin = {k: (cut(v) if np.ndim(v) else v) for k, v in L.items()}
+    for m in range(K):
+        d = (2 * n + 1) * m + 1
+        rows = np.zeros(H, bool)
+        rows[ey0 + d + extra[0] if ey0 > 0 else 0:ey1 - d - extra[1] if ey1 < H else H] = True
+        s = _pdr_step_rows(s, lin, beta, n, rows)
+    return {k: v[y0:y0 + th, x0:x0 + tw] for k, v in s.items()}
+
+
+PDR_ROW_CASES = [(0.0, 1, 1), (0.0, 1, 2), (0.05, 1, 3), (0.0, 2, 2), (0.0, 1, 3)]
+
+
+@pytest.mark.parametrize("beta,n,K", PDR_ROW_CASES)
+def test_pdr_rows_outside_the_band_may_skip_every_phase(beta, n, K):
+    rng, step, st, L, full = _setup("pdr", beta, n, K, seed=zlib.crc32(repr(("pdr-rows", beta, n, K)).encode()))
+    if K == 1:                                       # with every row computed the model is pdr_step itself
+        one = _pdr_step_rows(st, L, beta, n, np.ones(SHAPE[0], bool))
+        assert all(np.array_equal(v, full[k]) for k, v in one.items())
+    for tile in [(15, 17, 7, 9), (16, 18, 6, 5), (0, 0, 8, 8), (SHAPE[0] - 6, SHAPE[1] - 7, 6, 7),
+                 (0, 20, 5, 9), (21, 0, 9, 6)]:
+        got = _pdr_row_band_result(st, L, beta, n, K, tile, rng)
+        y0, x0, th, tw = tile
+        for k, v in got.items():
+            assert np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]), (tile, k)
+
+
+@pytest.mark.parametrize("beta,n,K", PDR_ROW_CASES)
+@pytest.mark.parametrize("extra", [(1, 0), (0, 1)], ids=["top", "bottom"])
+def test_pdr_row_band_is_tight(beta, n, K, extra):
+    rng, step, st, L, full = _setup("pdr", beta, n, K,
+                                    seed=zlib.crc32(repr(("pdr-rows-tight", beta, n, K, extra)).encode()))
+    tile = (16, 17, 8, 9)
+    got = _pdr_row_band_result(st, L, beta, n, K, tile, rng, extra)
     y0, x0, th, tw = tile
     assert any(not np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]) for k, v in got.items())
