@@ -949,9 +949,10 @@ def run_single(args):
         suffix = "a" if args.scheme == "alg1" else f"p{params.gs_sweeps}"
         key0 = f"{shapes[0][0]}x{shapes[0][1]}{'w' if has_w else ''}i{args.iters}{suffix}"
         ch0 = (tuning or {}).get(key0, {"mode": 5})
-        if ch0["mode"] in (5, 6, 10):
-            # K-iteration pDR / ALG1 tiles: per launch the kernel reads X, X bar, y and the
-            # linearisation once and writes X, X bar, y and Theta once
+        if ch0["mode"] != 1:
+            # K-iteration pDR / ALG1 tiles (every mode but the three-pass iteration's): per launch
+            # the kernel reads X, X bar, y and the linearisation once and writes X, X bar, y and
+            # Theta once
             name = "ALG1" if args.scheme == "alg1" else "pDR"
             roof = roofline(lvl_ms[0], lvl_launch[0], lvl_iters[0], shapes[0][0] * shapes[0][1], has_w,
                             f"{name} tile kernel, level 0 ({shapes[0][1]}x{shapes[0][0]}), choice {ch0}",
