@@ -38,6 +38,30 @@ using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ float gload(const float* p, int64_t o) { return ((const gfloat*)p)[o]; }
 __device__ __forceinline__ void gstore(float* p, int64_t o, float v) { ((gfloat*)p)[o] = v; }
 
+// a level descriptor of the tile table, read through the constant address space: the table does
+// not change while a launch runs, so its pointers load into scalar registers (read as ordinary
+// global memory they would be vector loads, their values held in vector registers)
+__device__ __forceinline__ TbLevel level_scalar(const TbLevel* p) {
+    using CL = const __attribute__((address_space(4))) TbLevel;
+    CL* q = (CL*)p;
+    TbLevel L;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        L.in[i] = q->in[i];
+        L.out[i] = q->out[i];
+    }
+    L.Ix = q->Ix;
+    L.Iy = q->Iy;
+    L.It = q->It;
+    L.u0 = q->u0;
+    L.v0 = q->v0;
+    L.at = q->at;
+    L.H = q->H;
+    L.W = q->W;
+    L.ld = q->ld;
+    return L;
+}
+
 template <bool HAS_W, int NW>
 struct RowLds {
     static constexpr int NG = HAS_W ? 3 : 2;
@@ -47,7 +71,10 @@ struct RowLds {
     float ybot[NG][NW + 2][64];
 };
 
-template <bool HAS_W, int NW, int R, bool BAND>
+// IN: the extended region lies inside the image's interior (no image edge in it), so every
+// neighbour-exists coefficient of the discrete operators is 1 and their products drop out (the same
+// arithmetic: a product by 1 is exact)
+template <bool HAS_W, int NW, int R, bool BAND, bool IN>
 __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, const TbLevel& L, RowLds<HAS_W, NW>& S) {
     constexpr int NG = HAS_W ? 3 : 2, NQ = HAS_W ? 6 : 4;
     const int lane = threadIdx.x & 63;
@@ -59,10 +86,10 @@ __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, c
     const int ey0 = max(T.y0 - tb_halo_lo(K), 0), ex0 = max(T.x0 - tb_halo_lo(K), 0);
     const int ey1 = min(T.y0 + T.th + K, H), ex1 = min(T.x0 + T.tw + K, W);
     const int EW = ex1 - ex0, EH = ey1 - ey0;          // at most 64 and NW R (the planners' bound)
-    const float inv_atc = 1.f / (fmaxf(L.at[a.at_slot], 1e-12f) * c);
+    const float inv_atc = 1.f / (fmaxf(gload(L.at, a.at_slot), 1e-12f) * c);
     const int gj = ex0 + lane;
-    const float fx = gj < W - 1 ? 1.f : 0.f, fl = gj > 0 ? 1.f : 0.f;
-    const float cx = fx * inv_ac;
+    const float fx = IN || gj < W - 1 ? 1.f : 0.f, fl = IN || gj > 0 ? 1.f : 0.f;
+    const float cx = IN ? inv_ac : fx * inv_ac;
     const int shr_top = ey0 > 0, shr_bot = ey1 < H;
     const bool band = BAND && (shr_top || shr_bot);
 
@@ -72,9 +99,9 @@ __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, c
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int r = wv * R + k, gi = ey0 + r;
-        fy[k] = gi < H - 1 ? 1.f : 0.f;
-        fu[k] = gi > 0 ? 1.f : 0.f;
-        cy[k] = fy[k] * inv_ac;
+        fy[k] = IN || gi < H - 1 ? 1.f : 0.f;
+        fu[k] = IN || gi > 0 ? 1.f : 0.f;
+        cy[k] = IN ? inv_ac : fy[k] * inv_ac;
         du[k] = dv[k] = ss[k] = Ix[k] = Iy[k] = It[k] = u0[k] = v0[k] = ww[k] = 0.f;
 #pragma unroll
         for (int f = 0; f < NQ; ++f) qo[f][k] = 0.f;
@@ -193,7 +220,9 @@ __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, c
         if constexpr (HAS_W) dp = divf(2, k);
         g_out(k, divf(0, k), divf(1, k), dp);
     }
-    for (int it = 0; it < K; ++it) {
+    // one iteration; the last one (NEXT false) is its own copy, so that no select on "is there a next
+    // iteration" runs per row in the others
+    auto iteration = [&](int it, auto next) {
         // rows that can still reach the output tile (all rows of the region without the band)
         const int lo = band ? shr_top * (it + 1) : 0, hi = band ? EH - shr_bot * (it + 1) : EH;
         __syncthreads();
@@ -203,12 +232,17 @@ __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, c
             if (r >= lo && r < hi) phase_b(k);
         }
         __syncthreads();
+        // the same rows, from bounds re-read as scalars: a row condition kept across the barrier
+        // would live as a lane mask and cost vector instructions per row
+        const int lo_c = __builtin_amdgcn_readfirstlane(lo), hi_c = __builtin_amdgcn_readfirstlane(hi);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int r = wv * R + k;
-            if (r >= lo && r < hi) phase_c(k, it + 1 < K);
+            if (r >= lo_c && r < hi_c) phase_c(k, decltype(next)::value);
         }
-    }
+    };
+    for (int it = 0; it + 1 < K; ++it) iteration(it, std::true_type{});
+    if (K > 0) iteration(K - 1, std::false_type{});
 
     // write the output tile
 #pragma unroll
@@ -230,6 +264,17 @@ __device__ __forceinline__ void process_rows(const TbArgs& a, const TbTile& T, c
             gstore(L.out[4], o, qo[5][k]);
         }
     }
+}
+
+// the tile's extended region, as process_rows clips it, holds no image edge
+__device__ __forceinline__ bool region_interior(const TbArgs& a, const TbTile& T, const TbLevel& L) {
+    return T.y0 - tb_halo_lo(a.K) > 0 && T.x0 - tb_halo_lo(a.K) > 0 && T.y0 + T.th + a.K < L.H && T.x0 + T.tw + a.K < L.W;
+}
+
+template <bool HAS_W, int NW, int R>
+__device__ __forceinline__ void process_rows_banded(const TbArgs& a, const TbTile& T, const TbLevel& L, RowLds<HAS_W, NW>& S) {
+    if (region_interior(a, T, L)) process_rows<HAS_W, NW, R, true, true>(a, T, L, S);
+    else process_rows<HAS_W, NW, R, true, false>(a, T, L, S);
 }
 
 // Wavefronts per SIMD each shape asks the register allocator to allow: 8 (64 VGPRs, two 1024-thread
@@ -254,7 +299,8 @@ __global__ __launch_bounds__(NW * 64, (rows_waves_per_simd<HAS_W, R>())) void ad
     T.x0 = tx * a.tw;
     T.th = min(a.th, a.lvl.H - T.y0);
     T.tw = min(a.tw, a.lvl.W - T.x0);
-    process_rows<HAS_W, NW, R, BAND>(a, T, a.lvl, S);
+    if constexpr (BAND) process_rows_banded<HAS_W, NW, R>(a, T, a.lvl, S);
+    else process_rows<HAS_W, NW, R, false, false>(a, T, a.lvl, S);
 }
 
 // Many levels (batched pairs), table order: tile entries split into 8 contiguous runs, one per XCD.
@@ -267,7 +313,8 @@ __global__ __launch_bounds__(NW * 64, (rows_waves_per_simd<HAS_W, R>())) void ad
     const int t = x * per + y;
     if (y >= per || t >= n) return;
     const TbTile T = a.tiles[t];
-    process_rows<HAS_W, NW, R, true>(a, T, a.levels[2 * T.level + a.dir], S);
+    const TbLevel L = level_scalar(a.levels + (2 * T.level + a.dir));
+    process_rows_banded<HAS_W, NW, R>(a, T, L, S);
 }
 
 template <bool HAS_W, int NW, int R>
