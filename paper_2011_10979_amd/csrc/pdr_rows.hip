@@ -363,7 +363,9 @@ struct PdrRow1Lds {
     float ybot[NX][NW + 2][64];                         // y components of wavefront w's bottom row
 };
 
-template <bool HAS_W, int NW, int R>
+// IN: the extended region holds no image edge, so every neighbour-exists coefficient is 1 and its
+// products drop out (the same arithmetic: a product by 1 is exact)
+template <bool HAS_W, int NW, int R, bool IN>
 __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& L, int y0, int x0, int th, int tw,
                                           PdrRow1Lds<HAS_W, NW, R>& S) {
     constexpr int NX = HAS_W ? 3 : 2, NY = 2 * NX;
@@ -379,7 +381,7 @@ __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& 
     const float sigma = a.sigma, tau = a.tau, stt = a.stt, lam = a.lam, beta = a.beta;
     const float sl = sigma * lam, inv_sigma = 1.f / sigma;
     const int gj = ex0 + lane;
-    const float fl = gj > 0 ? 1.f : 0.f, fr = gj < W - 1 ? 1.f : 0.f;
+    const float fl = IN || gj > 0 ? 1.f : 0.f, fr = IN || gj < W - 1 ? 1.f : 0.f;
 
     float x[NX][R], xb[NX][R], y[NY][R], bb[NX][R], Iy[R], rden[R];
     float fu[R], fd[R];                                 // wavefront-uniform
@@ -387,8 +389,8 @@ __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& 
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int r = wv * R + k, gi = ey0 + r;
-        fu[k] = gi > 0 ? 1.f : 0.f;
-        fd[k] = gi < H - 1 ? 1.f : 0.f;
+        fu[k] = IN || gi > 0 ? 1.f : 0.f;
+        fd[k] = IN || gi < H - 1 ? 1.f : 0.f;
         par[k] = (gi + ex0) & 1;
         rden[k] = 1.f / (1.f + stt * (((fl + fr) + fu[k]) + fd[k]));
 #pragma unroll
@@ -434,7 +436,10 @@ __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& 
     auto xd = [&](int f, int k) { return k + 1 < R ? x[f][k + 1 < R ? k + 1 : k] : S.xtop[f][wv + 2][lane]; };
     // half sweep over colour col (0 red, 1 black): every lane computes the update of its cell, the
     // lanes of that colour keep it
-    auto half_sweep = [&](int col, int lo, int hi) {
+    auto half_sweep = [&](int col, int lo_, int hi_) {
+        // bounds re-read as scalars: a row condition kept across a barrier would live as a lane
+        // mask and cost vector instructions per row
+        const int lo = __builtin_amdgcn_readfirstlane(lo_), hi = __builtin_amdgcn_readfirstlane(hi_);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             if (wv * R + k < lo || wv * R + k >= hi) continue;
@@ -499,10 +504,11 @@ __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& 
         }
         __syncthreads();
         // [D]: resolvent at X~ = 2 X+ - X bar, dual update from grad X+ (right / down neighbours)
+        const int lo_d = __builtin_amdgcn_readfirstlane(lo), hi_d = __builtin_amdgcn_readfirstlane(hi);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int r = wv * R + k;
-            if (r < lo || r >= hi) continue;
+            if (r < lo_d || r >= hi_d) continue;
             float xo[NX], gx[NX], gy[NX];
 #pragma unroll
             for (int f = 0; f < NX; ++f) {
@@ -572,6 +578,47 @@ __device__ __forceinline__ void pdr_rows1(const PdrTbArgs& a, const PdrTbLevel& 
     }
 }
 
+// the tile's extended region, as pdr_rows1 clips it, holds no image edge
+template <bool HAS_W, int NW, int R>
+__device__ __forceinline__ void pdr_rows1_any(const PdrTbArgs& a, const PdrTbLevel& L, int y0, int x0, int th, int tw,
+                                              PdrRow1Lds<HAS_W, NW, R>& S) {
+    const int hlu = pdr_halo_lo(a.sweeps, a.K), hrd = pdr_halo_hi(a.sweeps, a.K);
+    if (y0 - hlu > 0 && x0 - hlu > 0 && y0 + th + hrd < L.H && x0 + tw + hrd < L.W)
+        pdr_rows1<HAS_W, NW, R, true>(a, L, y0, x0, th, tw, S);
+    else
+        pdr_rows1<HAS_W, NW, R, false>(a, L, y0, x0, th, tw, S);
+}
+
+// a level descriptor of the tile table, read through the constant address space: the table does
+// not change while a launch runs, so its pointers load into scalar registers
+__device__ __forceinline__ PdrTbLevel pdr_level_scalar(const PdrTbLevel* p) {
+    using CL = const __attribute__((address_space(4))) PdrTbLevel;
+    CL* q = (CL*)p;
+    PdrTbLevel L;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        L.x_in[i] = q->x_in[i];
+        L.xb_in[i] = q->xb_in[i];
+        L.x_out[i] = q->x_out[i];
+        L.xb_out[i] = q->xb_out[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        L.y_in[i] = q->y_in[i];
+        L.y_out[i] = q->y_out[i];
+    }
+    L.Ix = q->Ix;
+    L.Iy = q->Iy;
+    L.It = q->It;
+    L.u0 = q->u0;
+    L.v0 = q->v0;
+    L.s_out = q->s_out;
+    L.H = q->H;
+    L.W = q->W;
+    L.ld = q->ld;
+    return L;
+}
+
 template <bool HAS_W, int NW, int R>
 __global__ __launch_bounds__(NW * 64, 8) void pdr_rows1_kernel(PdrTbArgs a) {
     __shared__ PdrRow1Lds<HAS_W, NW, R> S;
@@ -579,7 +626,7 @@ __global__ __launch_bounds__(NW * 64, 8) void pdr_rows1_kernel(PdrTbArgs a) {
     if (t >= a.ntiles) return;
     const int ty = t / a.ntx, tx = t - ty * a.ntx;
     const int y0 = ty * a.th, x0 = tx * a.tw;
-    pdr_rows1<HAS_W, NW, R>(a, a.lvl, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
+    pdr_rows1_any<HAS_W, NW, R>(a, a.lvl, y0, x0, min(a.th, a.lvl.H - y0), min(a.tw, a.lvl.W - x0), S);
 }
 
 template <bool HAS_W, int NW, int R>
@@ -590,7 +637,8 @@ __global__ __launch_bounds__(NW * 64, 8) void pdr_rows1_table_kernel(PdrTbArgs a
     const int t = x * per + y;
     if (y >= per || t >= a.ntiles) return;
     const TbTile T = a.tiles[t];
-    pdr_rows1<HAS_W, NW, R>(a, a.levels[2 * T.level + a.dir], T.y0, T.x0, T.th, T.tw, S);
+    const PdrTbLevel L = pdr_level_scalar(a.levels + (2 * T.level + a.dir));
+    pdr_rows1_any<HAS_W, NW, R>(a, L, T.y0, T.x0, T.th, T.tw, S);
 }
 
 template <bool HAS_W, int NW, int R>

@@ -283,3 +283,40 @@ def test_pdr_row_band_is_tight(beta, n, K, extra):
     got = _pdr_row_band_result(st, L, beta, n, K, tile, rng, extra)
     y0, x0, th, tw = tile
     assert any(not np.array_equal(v, full[k][y0:y0 + th, x0:x0 + tw]) for k, v in got.items())
+
+
+def _tile_regions(shape, tile, lo, hi):
+    """Extended regions (clipped) of every tile of a regular tiling: (ey0, ex0, ey1, ex1)."""
+    H, W = shape
+    for y0 in range(0, H, tile[0]):
+        for x0 in range(0, W, tile[1]):
+            th, tw = min(tile[0], H - y0), min(tile[1], W - x0)
+            yield y0 - lo, x0 - lo, y0 + th + hi, x0 + tw + hi
+
+
+def _kinds(shape, regions):
+    """Which kinds of tile occur: an interior region (no image edge inside it), and regions that
+    reach each of the four image edges."""
+    H, W = shape
+    kinds = set()
+    for ey0, ex0, ey1, ex1 in regions:
+        edges = {"top": ey0 <= 0, "left": ex0 <= 0, "bottom": ey1 >= H, "right": ex1 >= W}
+        kinds |= {k for k, v in edges.items() if v}
+        if not any(edges.values()):
+            kinds.add("interior")
+    return kinds
+
+
+def test_wave_row_parity_cases_cover_interior_and_edge_tiles():
+    """The wave-row tiles take a branch of their own where the extended region holds no image edge
+    (every neighbour coefficient 1); the GPU cases that compare them bitwise with the general tiles
+    run both branches: tiles inside the image and tiles at each of its edges."""
+    import test_gpu_ops as g
+    admm, pdr = set(), set()
+    for shape, tile, K, _ in g._row_cases():
+        admm |= _kinds(shape, _tile_regions(shape, tile, K + 1, K))
+    for shape, tile, K, n, _, _ in g._pdr_row_cases():
+        pdr |= _kinds(shape, _tile_regions(shape, tile, (2 * n + 1) * K, (2 * n + 1) * K + 1))
+    want = {"interior", "top", "left", "bottom", "right"}
+    assert admm >= want, admm
+    assert pdr >= want, pdr
