@@ -349,25 +349,34 @@ def run_batch(args):
                  for l in range(nl)]
     has_w = params.beta > 0
     pd = args.scheme in ("pdr", "alg1")
-    # the dominant kernel: the ADMM stages' tile kernel (general tiles from the table or from work
-    # queues, or wave-row tiles) that takes the most time, over the levels that run it
+    # the dominant kernel: the stages' tile kernel (ADMM: general tiles from the table or from work
+    # queues, or wave-row tiles; pDR: general, two-cell or one-cell wave-row tiles) that takes the
+    # most time, over the levels that run it
     wt = "true" if has_w else "false"
-    by_level = {st["level"]: st for st in tuning} if (tuning and not pd) else {}
+    by_level = {st["level"]: st for st in tuning} if tuning else {}
 
     def kname(st):
         nt = st.get("nt", 1025)
+        if args.scheme == "pdr":
+            if nt in (2050, 3074):
+                return f"pdr_rows1_table_kernel<{wt}, 16, {3 if nt == 3074 else 2}>"
+            if nt in (4098, 6145):
+                return f"pdr_rows_table_kernel<{wt}, 16, {3 if nt == 6145 else 2}>"
+            return f"pdr_tb_table_kernel (general tiles, code {nt})"
+        if args.scheme == "alg1":
+            return f"alg1_tb_table_kernel (code {nt})"
         if nt in (2049, 3073, 4097):
             return f"admm_rows_table_kernel<{wt}, 16, {(nt - 1) // 1024}>"
         return f"admm_tb_{'queue' if st['order'] == 1 else 'table'}_kernel<{wt}, 1024, 2>"
-    if by_level:
+    if by_level and all(l in by_level for l in range(nl)):
         groups = {}
         for l in range(nl):
             groups.setdefault(kname(by_level[l]), []).append(l)
         kernel, sel = max(groups.items(), key=lambda kv: sum(ms[l] for l in kv[1]))
     else:
         sel = list(range(nl))
-        kernel = {"pdr": "pdr_tb_table_kernel", "alg1": "alg1_tb_table_kernel"}.get(
-            args.scheme, "batched ADMM tile kernels (built-in stage choices)")
+        kernel = {"pdr": "pDR tile kernels", "alg1": "ALG1 tile kernels"}.get(
+            args.scheme, "batched ADMM tile kernels") + " (built-in stage choices)"
     tile_ms = sum(ms[l] for l in sel)
     tile_launches = sum(launches[l] for l in sel)
     tile_pxi = sum(level_px[l] * iters[l] for l in sel)                  # over `reps` solves
