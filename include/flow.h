@@ -336,8 +336,10 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *   "pdr_mode"    pDR iteration kernel: 0 built-in (tiles; a level that fits one tile keeps the whole
  *                 warp resident), 1 three-pass iteration, 5 / 6 tiles of 1024 / 512 threads, 10 / 11
  *                 large tiles (1024 / 512 threads, two cells of each colour per thread; with
- *                 beta > 0: 5 / 6), 12 / 13 wave-row tiles of 128 x 32 / 128 x 48 cells (with
- *                 beta > 0: 12).  12 and 13 also select the wave-row tiles in flow_op_pdr_tb.
+ *                 beta > 0: 5 / 6), 12 / 13 wave-row tiles of 128 x 32 / 128 x 48 cells with a cell
+ *                 pair per lane (with beta > 0: 12), 14 / 15 wave-row tiles of 64 x 48 / 64 x 32
+ *                 cells with one cell per lane (with beta > 0: 15).  12 to 15 also select the
+ *                 wave-row tiles in flow_op_pdr_tb.
  *   "pdr_k"       iterations per pDR tile launch (0 = built-in 2).
  *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
  *                 work queues.
@@ -436,9 +438,10 @@ flow_status flow_op_pdr_iter(const flow_pdr_state* st, float* work0, float* work
  * tile_h x tile_w: output tile; each tile's extended region
  * min(H, tile_h + (4 gs_sweeps + 2) iters + 1) x min(W, tile_w + (4 gs_sweeps + 2) iters + 1) must hold
  * at most 2048 pixels, or 4096 with beta = 0 (regions above 2048 run the large tiles: 1024 threads
- * with two cells of each colour), else FLOW_E_INVAL.  With the "pdr_mode" knob at 12 or 13 the
- * wave-row tiles run instead: the region must then be at most 128 columns wide and 32 rows high
- * (48 with beta = 0 and knob 13).  Every tile kernel gives bitwise the same iterates.  s_out
+ * with two cells of each colour), else FLOW_E_INVAL.  With the "pdr_mode" knob at 12 to 15 the
+ * wave-row tiles run instead: the region must then be at most 128 columns wide (knobs 12, 13) or
+ * 64 (knobs 14, 15) and 32 rows high (48 with beta = 0 and knob 13 or 14), else FLOW_E_INVAL.
+ * Every tile kernel gives bitwise the same iterates.  s_out
  * receives Theta of the last iteration.  Blocking. */
 flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
                            const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
