@@ -364,7 +364,9 @@ def run_batch(args):
                 return f"pdr_rows_table_kernel<{wt}, 16, {3 if nt == 6145 else 2}>"
             return f"pdr_tb_table_kernel (general tiles, code {nt})"
         if args.scheme == "alg1":
-            return f"alg1_tb_table_kernel (code {nt})"
+            if nt in (2050, 3074):
+                return f"alg1_rows_table_kernel<{wt}, 16, {3 if nt == 3074 else 2}>"
+            return f"alg1_tb_table_kernel (general tiles, code {nt})"
         if nt in (2049, 3073, 4097):
             return f"admm_rows_table_kernel<{wt}, 16, {(nt - 1) // 1024}>"
         return f"admm_tb_{'queue' if st['order'] == 1 else 'table'}_kernel<{wt}, 1024, 2>"

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflowmi.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["admm.hip", "admm_tb.hip", "admm_rows.hip", "pyramid.hip", "pdr.hip", "pdr_tb.hip", "pdr_rows.hip", "alg1_tb.hip", "energy.hip", "noalloc.hip",
+SOURCES = ["admm.hip", "admm_tb.hip", "admm_rows.hip", "pyramid.hip", "pdr.hip", "pdr_tb.hip", "pdr_rows.hip", "alg1_tb.hip", "alg1_rows.hip", "energy.hip", "noalloc.hip",
            "runtime.cpp", "geometry.cpp", "context.cpp", "tb_plan.cpp", "autotune.cpp", "batch.cpp", "multi.cpp", "serve.cpp"]
 
 ARCH = os.environ.get("FLOWMI_ARCH", "gfx950")

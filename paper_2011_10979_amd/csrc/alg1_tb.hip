@@ -131,7 +131,8 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, const PdrTbLevel& 
                 const float a1y = fmaf(cy[k], xd[0][j] - xbo[0][k], yow[1][k]);
                 const float a2x = fmaf(cx[k], xr[1][j] - xbo[1][k], yow[2][k]);
                 const float a2y = fmaf(cy[k], xd[1][j] - xbo[1][k], yow[3][k]);
-                const float nq = a1x * a1x + a1y * a1y + a2x * a2x + a2y * a2y;
+                // sums of products as explicit FMA chains: every ALG1 tile kernel rounds them alike
+                const float nq = fmaf(a2y, a2y, fmaf(a2x, a2x, fmaf(a1y, a1y, a1x * a1x)));
                 const float sq = fminf(1.f, __builtin_amdgcn_rsqf(nq));
                 S.y[0][e] = yow[0][k] = a1x * sq;
                 S.y[1][e] = yow[1][k] = a1y * sq;
@@ -140,7 +141,7 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, const PdrTbLevel& 
                 if constexpr (HAS_W) {
                     const float bx = fmaf(cx[k], xr[2][j] - xbo[2][k], yow[4][k]);
                     const float by = fmaf(cy[k], xd[2][j] - xbo[2][k], yow[5][k]);
-                    const float np2 = bx * bx + by * by;
+                    const float np2 = fmaf(by, by, bx * bx);
                     const float sp = fminf(1.f, __builtin_amdgcn_rsqf(np2));
                     S.y[4][e] = yow[4][k] = bx * sp;
                     S.y[5][e] = yow[5][k] = by * sp;
@@ -175,8 +176,8 @@ __device__ __forceinline__ void alg1_tile(const PdrTbArgs& a, const PdrTbLevel& 
                 const float vt = x[1][k] + sigma * dvv[1][j];
                 float wt = 0.f;
                 if constexpr (HAS_W) wt = x[2][k] + sigma * dvv[NX - 1][j];
-                const float e2 = beta * beta + Ix[k] * Ix[k] + Iy[k] * Iy[k];
-                const float rho = It[k] + beta * wt + Ix[k] * (ut - u0[k]) + Iy[k] * (vt - v0[k]);
+                const float e2 = fmaf(Iy[k], Iy[k], fmaf(Ix[k], Ix[k], beta * beta));
+                const float rho = fmaf(Iy[k], vt - v0[k], fmaf(Ix[k], ut - u0[k], fmaf(beta, wt, It[k])));
                 // eq:resolvent with step sigma: -rho / |e|^2 clamped to [-sigma lam, sigma lam], and
                 // Theta = clamp(rho / (sigma |e|^2), -lam, lam) = -step / sigma (both 0 where e = 0);
                 // 1 / |e|^2 is the hardware reciprocal (within 1 ulp)
@@ -268,6 +269,10 @@ static void launch_alg1_shape(const PdrTbArgs& a, int grid, hipStream_t s) {
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     const int grid = (a.ntiles + 7) / 8 * 8;
     if (a.ntiles < 1) return;
+    if (nt == 3074 || nt == 2050) {            // wave-row tiles, one cell per lane (3074 without w only)
+        launch_alg1_rows(a, has_w, nt, s);
+        return;
+    }
     if (nt == 512) {
         if (has_w) launch_alg1_shape<true, 512, kPdrPptW>(a, grid, s);
         else launch_alg1_shape<false, 512, kPdrPpt>(a, grid, s);

@@ -100,8 +100,9 @@ extern "C" flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const 
             const std::vector<int> ks = alg1 ? launch_ks(p->iters, 1, 10) : std::vector<int>{1, 2, 3, 4};
             for (int nt : {1024, 512, 2048, 513, 4098, 6145, 3074, 2050})
             for (int K : ks) {
-                if ((nt == 2048 || nt == 513 || nt == 6145 || nt == 3074) && (alg1 || hw)) continue;   // pDR, no w
-                if ((nt == 4098 || nt == 2050) && alg1) continue;                                       // pDR
+                if ((nt == 2048 || nt == 513 || nt == 6145) && (alg1 || hw)) continue;   // pDR, no w
+                if (nt == 3074 && hw) continue;                                          // no w
+                if (nt == 4098 && alg1) continue;                                        // pDR
                 PdrTbPlan T = plan_pd_tiles(L.H, L.W, hw, pd_halo(*p, K), K, 0, nt);
                 if (!T.tb) continue;
                 if (T.resident) {
@@ -246,7 +247,10 @@ extern "C" flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int
     if (mode != 1 && rows != 0 && (rows < 16 || rows > 512))
         return fail(FLOW_E_INVAL, "rows (tile modes: extended tile width) must be 0 or in [16, 512]");
     if (pdr_sweeps < -1) return fail(FLOW_E_INVAL, "pdr_sweeps must be >= -1 (-1: ALG1)");
-    if (pdr_sweeps == -1 && mode != 5 && mode != 6) return fail(FLOW_E_INVAL, "ALG1 modes: 5 / 6 (tiles of 1024 / 512 threads)");
+    if (pdr_sweeps == -1 && mode != 5 && mode != 6 && mode != 14 && mode != 15)
+        return fail(FLOW_E_INVAL, "ALG1 modes: 5 / 6 (tiles of 1024 / 512 threads), 14 / 15 (wave-row tiles of 64 x 48 "
+                                  "/ 64 x 32 cells)");
+    if (pdr_sweeps == -1 && mode == 14 && has_w) return fail(FLOW_E_INVAL, "ALG1 mode 14 needs beta = 0");
     if (pdr_sweeps > 0 && mode != 1 && mode != 5 && mode != 6 && mode < 10)
         return fail(FLOW_E_INVAL, "pDR modes: 1 (three-pass), 5 / 6 (tiles of 1024 / 512 threads), 10 / 11 (the same "
                                   "with two cells of each colour per thread), 12 / 13 (wave-row tiles of 128 x 32 / "

@@ -208,7 +208,8 @@ bool pd_stage_resident(const BatchPlan& P, const BStage& S, bool hw, int nt) {
 std::vector<int> pd_codes(const flow_params& p) {
     if (p.scheme == FLOW_PDR && !(p.beta > 0)) return {1024, 512, 2048, 513, 4098, 6145, 3074, 2050};
     if (p.scheme == FLOW_PDR) return {1024, 512, 4098, 2050};
-    return {1024, 512};
+    if (!(p.beta > 0)) return {1024, 512, 3074, 2050};              // ALG1
+    return {1024, 512, 2050};
 }
 
 // pDR / ALG1 stage: the tuned choice (work-group code and K) where one is recorded for the stage's

@@ -146,6 +146,8 @@ int pd_rows_width(int nt);                                // widest region of a 
 bool pd_fits(bool has_w, int nt, int64_t eh, int64_t ew);
 void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 void launch_pdr_rows(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
+// ALG1 on the one-cell wave-row tiles: 3074 (64 x 48 cells, beta = 0) or 2050 (64 x 32)
+void launch_alg1_rows(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 // ALG1 (primal-dual) tiles on the same argument block: sigma / tau are its primal / dual steps
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s);
 

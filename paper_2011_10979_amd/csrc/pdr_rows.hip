@@ -20,23 +20,11 @@
 // which only changes halo cells the halo accounts for.
 #include <type_traits>
 
-#include "kernels.hpp"
+#include "rows_dev.hpp"
 
 namespace flowmi {
 
 namespace {
-
-// lane l receives lane l + 1's value (lane 63: 0), and lane l - 1's (lane 0: 0)
-__device__ __forceinline__ float from_right(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_left(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
-}
-
-using gfloat = __attribute__((address_space(1))) float;
-__device__ __forceinline__ float gload(const float* p, int64_t o) { return ((const gfloat*)p)[o]; }
-__device__ __forceinline__ void gstore(float* p, int64_t o, float v) { ((gfloat*)p)[o] = v; }
 
 template <bool HAS_W, int NW, int R>
 struct PdrRowLds {
@@ -587,36 +575,6 @@ __device__ __forceinline__ void pdr_rows1_any(const PdrTbArgs& a, const PdrTbLev
         pdr_rows1<HAS_W, NW, R, true>(a, L, y0, x0, th, tw, S);
     else
         pdr_rows1<HAS_W, NW, R, false>(a, L, y0, x0, th, tw, S);
-}
-
-// a level descriptor of the tile table, read through the constant address space: the table does
-// not change while a launch runs, so its pointers load into scalar registers
-__device__ __forceinline__ PdrTbLevel pdr_level_scalar(const PdrTbLevel* p) {
-    using CL = const __attribute__((address_space(4))) PdrTbLevel;
-    CL* q = (CL*)p;
-    PdrTbLevel L;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        L.x_in[i] = q->x_in[i];
-        L.xb_in[i] = q->xb_in[i];
-        L.x_out[i] = q->x_out[i];
-        L.xb_out[i] = q->xb_out[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        L.y_in[i] = q->y_in[i];
-        L.y_out[i] = q->y_out[i];
-    }
-    L.Ix = q->Ix;
-    L.Iy = q->Iy;
-    L.It = q->It;
-    L.u0 = q->u0;
-    L.v0 = q->v0;
-    L.s_out = q->s_out;
-    L.H = q->H;
-    L.W = q->W;
-    L.ld = q->ld;
-    return L;
 }
 
 template <bool HAS_W, int NW, int R>

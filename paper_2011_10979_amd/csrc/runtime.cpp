@@ -399,7 +399,7 @@ PdrTbPlan plan_pdr_level(int H, int W, const flow_params& p, const std::map<std:
     }
     if (alg1 && mode == 1) mode = 5;                 // ALG1 has no three-pass form
     if ((mode == 10 || mode == 11) && (alg1 || hw)) mode -= 5;   // two cells per colour: pDR without w only
-    if (mode >= 12 && alg1) mode = 5;                            // wave-row tiles: pDR only
+    if ((mode == 12 || mode == 13) && alg1) mode = 5;            // cell-pair wave-row tiles: pDR only
     if (mode == 13 && hw) mode = 12;                             // 128 x 48 cells without the w block only
     if (mode == 14 && hw) mode = 15;                             // 64 x 48 cells without the w block only
     if (mode == 1 || p.iters < 1) return PdrTbPlan();
@@ -996,11 +996,11 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     const int64_t region = std::min<int64_t>(H, tile_h + halo) * std::min<int64_t>(W, tile_w + halo);
     // regions above the 1024-thread kernel's capacity run the large pDR tiles (beta = 0); with the
     // pdr_mode knob at 12 / 13 / 14 / 15, pDR runs the wave-row tiles of 128 x 32 / 128 x 48 / 64 x 48
-    // / 64 x 32 cells
+    // / 64 x 32 cells, and at 14 / 15 ALG1 its wave-row tiles of 64 x 48 / 64 x 32 cells
     const bool large = p->scheme == FLOW_PDR && !hw && region > pdr_tb_capacity(hw, 1024);
     int nt = large ? 2048 : 1024;
     if (p->scheme == FLOW_PDR && (g_pdr_mode == 12 || g_pdr_mode == 13)) nt = g_pdr_mode == 13 && !hw ? 6145 : 4098;
-    if (p->scheme == FLOW_PDR && (g_pdr_mode == 14 || g_pdr_mode == 15)) nt = g_pdr_mode == 14 && !hw ? 3074 : 2050;
+    if (g_pdr_mode == 14 || g_pdr_mode == 15) nt = g_pdr_mode == 14 && !hw ? 3074 : 2050;   // pDR and ALG1
     if (!pd_fits(hw, nt, std::min<int64_t>(H, tile_h + halo), std::min<int64_t>(W, tile_w + halo)))
         return fail(FLOW_E_INVAL, "tile plus halo exceeds the tile kernel's capacity");
     const float* ins[12] = {in->w, in->u, in->v, in->wb, in->ub, in->vb, in->pbx, in->pby,
@@ -1038,7 +1038,7 @@ static flow_status op_pd_tb(const flow_pdr_state* in, const flow_pdr_state* out,
     T.tw = tile_w;
     hipStream_t s = (hipStream_t)stream;
     // reads set 0 (in), writes set 1 (out)
-    if (p->scheme == FLOW_ALG1) launch_alg1_tb(pdr_tb_args(L, *p, T, 0, iters), hw, 1024, s);
+    if (p->scheme == FLOW_ALG1) launch_alg1_tb(pdr_tb_args(L, *p, T, 0, iters), hw, nt, s);
     else launch_pdr_tb(pdr_tb_args(L, *p, T, 0, iters), hw, nt, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));

@@ -518,7 +518,8 @@ void launch_pdr_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
     launch_pd(a, has_w, nt, pdr_halo_lo(a.sweeps, a.K) + pdr_halo_hi(a.sweeps, a.K), s);
 }
 void launch_alg1_tb(const PdrTbArgs& a, bool has_w, int nt, hipStream_t s) {
-    check(nt != 2048 && nt != 513 && !is_pd_rows_code(nt), "pDR-only tiles launched for ALG1");
+    check(nt != 2048 && nt != 513 && nt != 4098 && nt != 6145, "pDR-only tiles launched for ALG1");
+    check(nt != 3074 || !has_w, "ALG1 64 x 48 wave-row tiles launched with w");
     launch_pd(a, has_w, nt, 2 * alg1_halo(a.K), s);
 }
 static void pdr_pass(const PdrArgs& a, bool final_pass) {

@@ -423,6 +423,21 @@ static void test_pd_solves(std::mt19937& rng) {
                         read_out(f, u, v, r);
                     }
             }
+        // ALG1 takes its kernel from per-level choices: every tile shape (wave-row 64 x 48 without w)
+        for (int mode : {5, 6, 14, 15})
+            for (int K : {0, 2, 5})
+                for (double beta : {0.0, 0.05}) {
+                    if (mode == 14 && beta > 0) continue;
+                    flow_params p = params(lv);
+                    p.scheme = FLOW_ALG1;
+                    p.beta = beta;
+                    int h = H, w = W;
+                    for (int l = 0; l < lv; ++l, h = (h + 1) / 2, w = (w + 1) / 2)
+                        OK(flow_tune_choice(ctx, h, w, beta > 0, p.iters, -1, mode, K, 0));
+                    flow_result r{};
+                    OK(flow_solve(ctx, f.I0, f.I1, H, W, W, &p, u, v, W, &r, nullptr));
+                    read_out(f, u, v, r);
+                }
         hipFree(u);
         hipFree(v);
         hipFree(f.I0);

@@ -232,6 +232,81 @@ def _pdr_row_cases():
     return cases
 
 
+def _alg1_row_cases():
+    """(shape, tile, K, beta, mode): ALG1 wave-row tiles (mode 14: 64 x 48 cells, beta = 0; 15: 64 x 32)
+    whose extended region (halo K on every side) also fits the general ALG1 tiles (2048 cells)."""
+    cases = []
+    for shape, tile, K in [((101, 250), (12, 44), 4), ((130, 140), (10, 40), 10), ((30, 61), (30, 61), 3),
+                           ((45, 200), (20, 50), 1), ((70, 300), (15, 40), 2), ((32, 64), (32, 64), 6),
+                           ((2, 67), (2, 40), 2), ((67, 2), (20, 2), 2)]:
+        eh, ew = min(shape[0], tile[0] + 2 * K), min(shape[1], tile[1] + 2 * K)
+        for beta in (0.0, 0.05):
+            for mode, rows in ((14, 48), (15, 32)):
+                if mode == 14 and beta > 0:
+                    continue
+                if ew <= 64 and eh <= rows and eh * ew <= 2048:
+                    cases.append((shape, tile, K, beta, mode))
+    return cases
+
+
+def _alg1_call(g, lin, beta, K, tile):
+    return fm.alg1_tb(g, *lin, fm.Params(scheme="alg1", beta=beta), iters=K, tile_h=tile[0], tile_w=tile[1])
+
+
+@pytest.mark.parametrize("shape,tile,K,beta,mode", _alg1_row_cases())
+def test_alg1_row_tiles_equal_the_general_tiles(shape, tile, K, beta, mode):
+    """The ALG1 wave-row tiles (one cell per lane and row, registers per row, DPP neighbours, the
+    shrinking band) evaluate the general ALG1 tiles' operations in the same order: K iterations of
+    the same tiles of the same state agree bit for bit, Theta included."""
+    print_case("alg1 rows vs general tiles", shape=shape, tile=tile, K=K, beta=beta, mode=mode)
+    rng = np.random.default_rng(zlib.crc32(repr(("alg1rows", shape, tile, K, beta)).encode()))
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    lin = (to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3))
+    ref, ref_s = _alg1_call(g, lin, beta, K, tile)
+    fm.set_tuning("pdr_mode", mode)
+    try:
+        out, out_s = _alg1_call(g, lin, beta, K, tile)
+    finally:
+        fm.set_tuning("pdr_mode", 0)
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    for k in keys:
+        assert torch.equal(out[k], ref[k]), k
+    assert torch.equal(out_s, ref_s)
+
+
+@pytest.mark.parametrize("shape,tile,K,beta,mode", [((120, 130), (28, 40), 10, 0.0, 14), ((140, 200), (30, 44), 9, 0.0, 14),
+                                                    ((90, 150), (12, 40), 10, 0.05, 15), ((48, 64), (48, 64), 7, 0.0, 14)])
+def test_alg1_row_tiles_match_k_oracle_steps(shape, tile, K, beta, mode):
+    """ALG1 wave-row tiles whose extended regions fill every row of the shape (64 x 48 with beta = 0,
+    64 x 32 with w), beyond the general tiles' capacity, against K steps of the oracle."""
+    print_case("alg1 rows vs oracle", shape=shape, tile=tile, K=K, beta=beta, mode=mode)
+    rng = np.random.default_rng(zlib.crc32(repr(("alg1rowsor", shape, tile, K, beta)).encode()))
+    st = random_pdr_state(rng, shape, beta)
+    Ix, Iy, Itr, _ = random_lin(rng, shape, beta)
+    u0 = f32(rng.normal(scale=3.0, size=shape))
+    v0 = f32(rng.normal(scale=3.0, size=shape))
+    g = {k: to_dev(v, pad=3) for k, v in st.items()}
+    lin = (to_dev(Ix, 3), to_dev(Iy, 3), to_dev(Itr, 3), to_dev(u0, 3), to_dev(v0, 3))
+    fm.set_tuning("pdr_mode", mode)
+    try:
+        out, s_out = _alg1_call(g, lin, beta, K, tile)
+    finally:
+        fm.set_tuning("pdr_mode", 0)
+    L = dict(Ix=Ix, Iy=Iy, It=Itr - Ix * u0 - Iy * v0)
+    ref = dict(st)
+    for _ in range(K):
+        ref, duals = schemes.alg1_step(ref, L, beta, 0.05, 0.1, 1.25)
+    keys = ["u", "v", "ub", "vb", "qb1x", "qb1y", "qb2x", "qb2y"] + (["w", "wb", "pbx", "pby"] if beta > 0 else [])
+    tol = 1e-4 * max(1, K)
+    for k in keys:
+        assert max_abs(to_np(out[k]), ref[k]) < tol, (k, max_abs(to_np(out[k]), ref[k]))
+    assert max_abs(to_np(s_out), duals["s"]) < tol
+
+
 @pytest.mark.parametrize("shape,tile,K,sweeps,beta,mode", _pdr_row_cases())
 def test_pdr_row_tiles_equal_the_general_tiles(shape, tile, K, sweeps, beta, mode):
     """The wave-row pDR tiles (cell pairs per lane, registers per row, DPP neighbours) evaluate the

@@ -307,9 +307,34 @@ def test_pdr_tile_shapes_give_bitwise_the_same_solve(ctx, k):
         assert out[mode][2]["energy"] == out[5][2]["energy"], mode
 
 
-@pytest.mark.parametrize("mode,k,beta", [(5, 1, 0.0), (5, 4, 0.0), (6, 2, 0.05), (6, 8, 0.0)])
+@pytest.mark.parametrize("k,beta", [(2, 0.0), (5, 0.0), (3, 0.05)])
+def test_alg1_tile_shapes_give_bitwise_the_same_solve(k, beta):
+    """Every ALG1 tile shape (1024 or 512 threads, wave-row tiles of 64 x 48 and 64 x 32 cells) forms
+    each cell's update with the same expressions on the same operands: with the same K per launch
+    the solves agree bit for bit."""
+    print(f"[case] ALG1 tile shapes K {k} beta {beta}", flush=True)
+    pair = synth.vga_pair(seed=8, H=150, W=190)
+    I0, I1 = to_dev(f32(pair.I0)), to_dev(f32(pair.I1))
+    modes = (5, 6, 14, 15) if beta == 0 else (5, 6, 15)
+    out = {}
+    for mode in modes:
+        c = fm.Context(0)
+        try:
+            for H, W in [(150, 190), (75, 95), (38, 48)]:
+                c.set_choice(f"{H}x{W}{'w' if beta > 0 else ''}i20a", mode, k)
+            out[mode] = c.solve(I0, I1, fm.Params(scheme="alg1", beta=beta, levels=3, warps=2, iters=20))
+        finally:
+            c.close()
+    for mode in modes[1:]:
+        assert torch.equal(out[mode][0], out[5][0]) and torch.equal(out[mode][1], out[5][1]), mode
+        assert out[mode][2]["energy"] == out[5][2]["energy"], mode
+
+
+@pytest.mark.parametrize("mode,k,beta", [(5, 1, 0.0), (5, 4, 0.0), (6, 2, 0.05), (6, 8, 0.0), (14, 3, 0.0),
+                                         (14, 10, 0.0), (15, 4, 0.05), (15, 10, 0.0)])
 def test_every_alg1_kernel_mode_keeps_parity(ctx, mode, k, beta):
-    """ALG1 with tiles of 1024 and 512 threads and several K (coarse levels resident) meets the bar."""
+    """ALG1 with tiles of 1024 and 512 threads and wave-row tiles of 64 x 48 / 64 x 32 cells, several K
+    (coarse levels resident), meets the bar."""
     print(f"[case] forced ALG1 mode {mode} K {k} beta {beta}", flush=True)
     c = fm.Context(0)
     try:

@@ -132,7 +132,8 @@ def test_tile_halo_is_tight(name, beta, n, K, side):
 # The kernels go further than the halo: after iteration m of a launch only the extended region
 # shrunk by m rows on every side that has a halo can still reach the output, so rows outside that
 # band skip the iteration and keep stale values (a whole wavefront's rows in the general ADMM
-# tiles, single rows in the wave-row tiles).  Stale values are one kind of garbage; here the rows
+# tiles, single rows in the ADMM and ALG1 wave-row tiles).  Stale values are one kind of garbage;
+# here the rows
 # outside the band are replaced by random values after every iteration, and the output tile must
 # still equal the undisturbed run bit for bit.  With a band one row narrower on either side some
 # output value changes (for K >= 2: with one iteration the row above the output tile can no longer
@@ -162,7 +163,8 @@ def _band_result(step, st, L, K, tile, lo, hi, rng, extra=(0, 0)):
     return {k: v[y0:y0 + th, x0:x0 + tw] for k, v in s.items()}
 
 
-BAND_CASES = [c for c in CASES if c[0] in ("admm", "rpadmm2")] + [("admm", 0.0, 1, 5), ("admm", 0.05, 1, 6)]
+BAND_CASES = [c for c in CASES if c[0] in ("admm", "rpadmm2", "alg1")] + [("admm", 0.0, 1, 5), ("admm", 0.05, 1, 6),
+                                                                            ("alg1", 0.0, 1, 5)]
 
 
 @pytest.mark.parametrize("name,beta,n,K", BAND_CASES)
