@@ -290,9 +290,11 @@ flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const flow_pair* p
  * K-iteration tiles of 256, 1024 and small 1024-thread work-groups for every K in [2, 16] that is
  * the smallest giving its number of launches per warp, ceil(iters / n) (50 iterations: K = 2, 3,
  * 4, 5, 6, 7, 8, 9, 10, 13; tiles shortened to fill one round of work-groups where a level needs
- * less); a resident tile where the level fits.  pDR: the three-pass iteration, K-iteration tiles
- * for K = 1, 2, 3, 4, a resident tile; ALG1: tiles for the same launch-count K values in [1, 10],
- * a resident tile (both with balanced tiles).  Every choice computes the same iteration (results agree to rounding).  Blocking;
+ * less); the wave-row tiles of 64 x 32 / 48 / 64 cells for the same K; a resident tile where the
+ * level fits.  pDR: the three-pass iteration, K-iteration tiles (1024 / 512 threads, one or two
+ * cells of each colour, wave-row tiles with a cell pair or one cell per lane) for K = 1, 2, 3, 4, a
+ * resident tile; ALG1: tiles of 1024 / 512 threads and wave-row tiles of 64 x 48 / 64 x 32 cells for
+ * the same launch-count K values in [1, 10], a resident tile (all with balanced tiles).  Every choice computes the same iteration (results agree to rounding).  Blocking;
  * uses the context's arena (contents are overwritten). */
 flow_status flow_autotune(flow_ctx* ctx, int32_t H, int32_t W, const flow_params* p, void* stream);
 
@@ -309,11 +311,15 @@ flow_status flow_get_tuning(const flow_ctx* ctx, char* buf, size_t cap);
  * tiles of 256 / 1024 threads / small tiles of 1024 / 512 / 256 threads / one-pixel tiles of 1024 /
  * 512 threads with K iterations per launch (K = 0:
  * resident if the level fits one tile, else the built-in K) and `rows` the target width of a tile's
- * extended region (0 = built-in, else 16..512).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 = three-pass
- * iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident), 10 = large tiles
- * (1024 threads with two cells of each colour, 4096-cell regions; beta = 0 only); pdr_sweeps = -1:
- * ALG1, modes 5 / 6 as for pDR.  Lets a caller reuse a tuning measured in
- * another process.  Drops the context's captured graphs. */
+ * extended region (0 = built-in, else 16..512); 12 / 13 / 14 = wave-row tiles of 64 x 32 / 64 x 48 /
+ * 64 x 64 cells (a `rows` above 64 acts as 64).  pdr_sweeps = n >= 1: pDR with n sweeps, mode 1 =
+ * three-pass iteration, 5 / 6 = K-iteration tiles of 1024 / 512 threads (K = 0: resident), 10 / 11 =
+ * the same with two cells of each colour per thread (beta = 0 only), 12 / 13 = wave-row tiles of
+ * 128 x 32 / 128 x 48 cells with a cell pair per lane (13: beta = 0 only), 14 / 15 = wave-row tiles
+ * of 64 x 48 / 64 x 32 cells with one cell per lane (14: beta = 0 only); pdr_sweeps = -1: ALG1,
+ * modes 5 / 6 as for pDR and 14 / 15 = its wave-row tiles of 64 x 48 (beta = 0 only) / 64 x 32
+ * cells.  Other modes: FLOW_E_INVAL.  Lets a caller reuse a tuning measured in another process.
+ * Drops the context's captured graphs. */
 flow_status flow_tune_choice(flow_ctx* ctx, int32_t H, int32_t W, int32_t has_w, int32_t iters, int32_t pdr_sweeps,
                              int32_t mode, int32_t K, int32_t rows);
 
@@ -339,7 +345,8 @@ flow_status flow_memory_in_use(const flow_ctx* ctx, size_t* bytes);
  *                 beta > 0: 5 / 6), 12 / 13 wave-row tiles of 128 x 32 / 128 x 48 cells with a cell
  *                 pair per lane (with beta > 0: 12), 14 / 15 wave-row tiles of 64 x 48 / 64 x 32
  *                 cells with one cell per lane (with beta > 0: 15).  12 to 15 also select the
- *                 wave-row tiles in flow_op_pdr_tb.
+ *                 wave-row tiles in flow_op_pdr_tb, 14 and 15 those of ALG1 in flow_op_alg1_tb
+ *                 (ALG1 solves take their kernels from flow_autotune or flow_tune_choice).
  *   "pdr_k"       iterations per pDR tile launch (0 = built-in 2).
  *   "batch_order" batched tile launches: -1 tuned / built-in, 0 tile table in XCD order, 1 per-XCD
  *                 work queues.
@@ -451,7 +458,9 @@ flow_status flow_op_pdr_tb(const flow_pdr_state* in, const flow_pdr_state* out, 
 /* `iters` ALG1 iterations in ONE launch of its tile kernel, as flow_op_pdr_tb (same state planes:
  * X, X bar = the extrapolated point, y in the y bar slots; steps p->alg1_tau, p->alg1_sigma); each
  * tile's extended region min(H, tile_h + 2 iters) x min(W, tile_w + 2 iters) must hold at most 2048
- * pixels.  Blocking. */
+ * pixels, else FLOW_E_INVAL.  With the "pdr_mode" knob at 14 or 15 the ALG1 wave-row tiles run
+ * instead: the region must then be at most 64 columns wide and 48 (knob 14, beta = 0) or 32 rows
+ * high.  Every tile kernel gives bitwise the same iterates.  Blocking. */
 flow_status flow_op_alg1_tb(const flow_pdr_state* in, const flow_pdr_state* out, float* s_out, const float* Ix,
                             const float* Iy, const float* It, const float* u0, const float* v0, int32_t H, int32_t W,
                             int64_t ld, const flow_params* p, int32_t iters, int32_t tile_h, int32_t tile_w,
