@@ -96,7 +96,9 @@ def assert_parity(name, u, v, res, ref, mean_tol=None, job=None):
     is run N_PROBES more times with its state rounded to FP32 after every iteration (random
     sub-ulp nudges, seeds 0..N_PROBES-1), and a pixel passes if it is within F_PROBE x the largest
     departure of those probes from the oracle there: such a pixel moves that far under FP32
-    rounding of the oracle's own state, which no FP32 arithmetic avoids."""
+    rounding of the oracle's own state, which no FP32 arithmetic avoids.  When the probes run, the
+    mean difference is held to the larger of `mean_tol` and F_PROBE x the probes' mean largest
+    departure, by the same reading."""
     ru, rv = ref["u"], ref["v"]
     d = np.maximum(np.abs(u - ru), np.abs(v - rv))
     bad = d > TOL_F32
@@ -112,6 +114,9 @@ def assert_parity(name, u, v, res, ref, mean_tol=None, job=None):
         for pr in probes:
             spread = np.maximum(spread, np.maximum(np.abs(pr["u"] - ru), np.abs(pr["v"] - rv)))
         bar = np.maximum(TOL_F32, F_PROBE * spread)
+        if mean_tol is not None:
+            mean_tol = max(mean_tol, F_PROBE * float(spread.mean()))
+            print(f"[parity] {name}: probes' mean departure {spread.mean():.3e}, mean bar {mean_tol:.3e}", flush=True)
         for a, b in list(zip(*np.where(bad)))[:10]:
             print(f"[parity] {name}: pixel ({a},{b}) |d| {d[a, b]:.2e}, FP32-rounding probes of the oracle "
                   f"depart {spread[a, b]:.2e} there (bar {bar[a, b]:.2e})", flush=True)

@@ -142,6 +142,23 @@ def test_vga_bench_workload_full_size(ctx, plan):
     print(f"[parity] vga {plan} EPE vs truth gpu {epe_gpu:.4f} oracle {epe_ora:.4f}", flush=True)
 
 
+@pytest.mark.parametrize("scheme", ["pdr", "alg1"])
+def test_vga_pd_schemes_autotuned_full_size(scheme):
+    """pDR (one symmetric sweep) and ALG1 on the 640x480 workload (5 levels x 5 warps x 50, beta = 0)
+    with the plan their benchmark times (the autotuner's per-level choice: wave-row tiles on the
+    large levels) against the full FP64 oracle solve; also mean <= 1e-5 px."""
+    print(f"[case] vga 640x480 5x5x50 {scheme} autotuned", flush=True)
+    pair = synth.vga_pair(seed=1)
+    kw = dict(scheme=scheme, levels=5, warps=5, iters=50)
+    c = fm.Context(0)
+    try:
+        rep = c.autotune(480, 640, fm.Params(**kw))
+        print(f"[parity] vga {scheme} autotuned plan: { {k: e['choice'] for k, e in rep.items()} }", flush=True)
+        parity_check(c, pair, f"vga 640x480 {scheme} autotuned", full_size=True, **kw)
+    finally:
+        c.close()
+
+
 def test_graph_replay_equals_direct_launches(ctx):
     pair = synth.vga_pair(seed=3, H=120, W=160)
     I0, I1 = to_dev(pair.I0), to_dev(pair.I1)
