@@ -295,6 +295,9 @@ def run_batch(args):
         with open(args.load_batch_tuning) as fh:
             tuning = json.load(fh)
         for st in tuning:
+            if args.scheme in ("pdr", "alg1"):                                 # pDR / ALG1: the tile code
+                ctx.set_batched_stage(frames, st["level"], st["nt"], st["K"], 64, params)
+                continue
             order = st["nt"] if st.get("nt", 1025) != 1025 else st["order"]     # wave-row tiles: their code
             ctx.set_batched_stage(frames, st["level"], order, st["K"], st["ew"], params)
         print(f"[bench] loaded batched stage choices: {tuning}", file=sys.stderr, flush=True)

@@ -277,9 +277,12 @@ flow_status flow_autotune_batched(flow_ctx* ctx, int32_t n, const flow_pair* pai
  * report): order 0 general tiles from the tile table / 1 general tiles from work queues / 2049,
  * 3073 or 4097 wave-row tiles of 32 / 48 / 64 rows from the tile table (the report's "nt" where it
  * is one of these), K iterations per tile launch (>= iters: the whole warp in one launch),
- * extended tile width ew in [16, 512] (at most 64 for the wave-row tiles).  The choice changes
- * speed only.
- * FLOW_E_INVAL if no pair has the level or one of its levels takes no tiles of that K and width.
+ * extended tile width ew in [16, 512] (at most 64 for the wave-row tiles).  For pDR and ALG1 batches
+ * `order` is the stage's work-group code (the report's "nt": 1024 / 512 threads, pDR 2048 / 513 with
+ * two cells of each colour, the wave-row codes 4098 / 6145 / 3074 / 2050 of pDR and 3074 / 2050 of
+ * ALG1, as the scheme and beta allow) and `ew` is not used.  The choice changes speed only.
+ * FLOW_E_INVAL if no pair has the level or one of its levels takes no tiles of that K and width
+ * (that code and K).
  * Host-only. */
 flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const flow_pair* pairs, const flow_params* p,
                                     int32_t level, int32_t order, int32_t K, int32_t ew);

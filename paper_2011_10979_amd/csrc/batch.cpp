@@ -744,8 +744,35 @@ extern "C" flow_status flow_tune_batched_stage(flow_ctx* ctx, int32_t n, const f
     if (st != FLOW_OK) return st;
     st = validate_pairs(n, pairs, *p);
     if (st != FLOW_OK) return st;
-    if (pd_state(*p)) return fail(FLOW_E_INVAL, "batched pDR and ALG1 stages take the built-in choice");
     if (level < 0 || level >= FLOW_MAX_LEVELS) return fail(FLOW_E_INVAL, "level out of range");
+    if (pd_state(*p)) {
+        // pDR / ALG1 stage: order is the work-group code (the report's "nt"), ew is not used
+        const std::vector<int> codes = pd_codes(*p);
+        if (std::find(codes.begin(), codes.end(), order) == codes.end())
+            return fail(FLOW_E_INVAL, "pDR / ALG1 stage: order must be one of the scheme's tile codes (the report's nt)");
+        if (K < 1) return fail(FLOW_E_INVAL, "K must be >= 1");
+        const bool hw = p->beta > 0;
+        Shapes shapes;
+        for (int32_t k = 0; k < n; ++k) {
+            const int lv = pairs[k].levels > 0 ? pairs[k].levels : p->levels;
+            if (lv > level) shapes.push_back(level_shapes(pairs[k].H, pairs[k].W, lv)[level]);
+        }
+        if (shapes.empty()) return fail(FLOW_E_INVAL, "no pair of the batch has that level");
+        const int kk = std::min<int>(K, std::max(1, p->iters));
+        for (const auto& sh : shapes)
+            if (!plan_pd_tiles(sh.first, sh.second, hw, pd_halo(*p, kk), kk, 0, order).tb)
+                return fail(FLOW_E_INVAL, "a level of the stage takes no tiles of that code and K");
+        BatchState& B = batch_of(ctx);
+        StageChoice c;
+        c.nt = order;
+        c.K = kk;
+        const std::string pre = p->scheme == FLOW_ALG1 ? std::string("a:") : "p" + std::to_string(p->gs_sweeps) + ":";
+        B.tuned[pre + stage_key(shapes, hw, p->iters)] = c;
+        B.tune_epoch++;
+        B.drop_graph();
+        B.plan.reset();
+        return FLOW_OK;
+    }
     if (order != ORDER_TABLE && order != ORDER_QUEUE && !is_rows_code(order))
         return fail(FLOW_E_INVAL, "order: 0 table, 1 work queue, or a wave-row code 2049 / 3073 / 4097 (table order)");
     if (K < 1 || ew < 16 || ew > 512) return fail(FLOW_E_INVAL, "K must be >= 1 and ew in [16, 512]");

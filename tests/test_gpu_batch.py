@@ -182,6 +182,38 @@ def test_pd_batch_equals_plain_tile_solves(ctx, scheme, beta, storage):
         assert same(a, b)
 
 
+@pytest.mark.parametrize("scheme,beta,pins", [
+    ("pdr", 0.0, ((0, 3074, 3), (1, 2050, 2), (2, 512, 30))),
+    ("pdr", 0.0, ((0, 4098, 1), (1, 6145, 2), (2, 2048, 4))),
+    ("pdr", 0.05, ((0, 2050, 2), (1, 4098, 1), (2, 1024, 3))),
+    ("alg1", 0.0, ((0, 3074, 5), (1, 2050, 10), (2, 512, 30))),
+    ("alg1", 0.05, ((0, 2050, 6), (1, 1024, 3), (2, 2050, 30)))])
+def test_pinned_pd_stage_choices_keep_results(ctx, scheme, beta, pins):
+    """pDR / ALG1 stage choices set by hand (the work-group code and K the batched autotuner's
+    report lists) change speed only: the batch stays bitwise the same; a code the scheme does not
+    run, or one whose region the level cannot hold, is refused."""
+    print(f"[case] batched {scheme} beta {beta} pinned {pins}", flush=True)
+    fr = frames(MIX)
+    kw = dict(KW, scheme=scheme, beta=beta)
+    pairs = [(d0, d1, lv) for _, _, lv, d0, d1 in fr]
+    c = fm.Context(0)
+    try:
+        before = batched(c, fr, **kw)
+        for level, nt, K in pins:
+            c.set_batched_stage(pairs, level, nt, K, 64, fm.Params(**kw))
+        after = batched(c, fr, **kw)
+        for a, b in zip(before, after):
+            assert same(a, b)
+        bad = 4098 if scheme == "alg1" else 1025           # a code of another scheme
+        with pytest.raises(fm.FlowError):
+            c.set_batched_stage(pairs, 0, bad, 2, 64, fm.Params(**kw))
+        if beta > 0:                                      # the 48-row one-cell tiles need beta = 0
+            with pytest.raises(fm.FlowError):
+                c.set_batched_stage(pairs, 0, 3074, 2, 64, fm.Params(**kw))
+    finally:
+        c.close()
+
+
 def test_pd_batch_matches_the_oracle(ctx):
     """Batched pDR pairs against the FP64 oracle under the parity bar."""
     print("[case] batched pdr vs oracle", flush=True)
